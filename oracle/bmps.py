@@ -1,0 +1,222 @@
+"""Boundary-MPS contraction of the Boltzmann PEPS (oracle; test infrastructure only).
+
+What is computed (Sec. 2 and Fig. 1(c)-(d) of the paper; the paper defers the
+mechanics to its references, so the steps below are the adopted reading):
+
+* Row factors.  F_r(X) = prod_c w_{r,c}(x_c) prod_c W^H_{r,c}(x_c, x_{c+1}) and
+  G_r(X, Y) = prod_c W^V_{r,c}(x_c, y_c) W^D_{r,c}(x_c, y_{c+1}) W^A_{r,c}(x_{c+1}, y_c),
+  with w, W the Boltzmann factors of the min-shifted energy tables of Eq. (1).
+* Boundary functions.  E~_{rows} = 1 and E~_r(X) = F_r(X) sum_Y G_r(X, Y) E~_{r+1}(Y)
+  (for r = rows-1 the couplings G are absent).  Then Z = exp(-beta*shift) sum_X E~_0(X).
+* Boundary MPS.  E~_r(X) ~ exp(lam_r) A_{r,0}[x_0] ... A_{r,cols-1}[x_{cols-1}], each
+  A_{r,c} a (chi_c x d x chi_{c+1}) tensor, right-canonical (A_{r,0} normalised).
+* One row step (the paper's "SVDTruncate" with "num_sweeps" and
+  "graduate_truncation", read as two-site variational fitting):
+    1. target T = W_r psi, with psi = the normalised previous boundary MPS and W_r
+       the row MPO whose site tensor at column c is
+       W_c[(a, e), x, y] = w_c(x) V_c(x, y) H_{c-1}(a, x) D_{c-1}(a, y) A_{c-1}(x, e),
+       left bond (a, e) = (x_{c-1}, y_{c-1}), right bond (x_c, y_c);
+    2. initial guess phi_c[x] = w_c(x) sum_y V_c(x, y) psi_c[y] (previous row's bond
+       dimensions), brought to right-canonical form by LQ factorisations;
+    3. ``num_sweeps`` sweeps; each is a left-to-right then a right-to-left pass of
+       two-site updates.  An update at columns (c, c+1) forms the exact projection of
+       T onto the orthonormal left/right environment bases,
+       B = <env_L| T |env_R>, and splits it with the truncated SVD protocol of
+       ``linalg`` at rank min(chi, rows(B), cols(B));
+    4. normalise: lam_r = lam_{r+1} + log of the norm of the final centre.
+
+Parity status: the exact regime (chi >= every exact Schmidt rank) is pinned
+against brute force and the exact row transfer; the truncated regime is pinned
+only by invariants (normalisation, monotone error in chi) - "parity unpinned"
+beyond those, as any truncated contraction is defined by its own protocol.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .energy import Weights
+from .linalg import tsvd_left, tsvd_right
+
+
+def row_weights(W: Weights, r: int):
+    """Per-column factor arrays of row r: w_c, V_c, and the left couplings
+    (H_{c-1}, D_{c-1}, A_{c-1}) as (a-dim x d) arrays, ones for c = 0.
+    For the bottom row the vertical couplings are all ones."""
+    inst = W.inst
+    R, C, d = inst.rows, inst.cols, inst.d
+    w = [W.loc[r, c] for c in range(C)]
+    if r < R - 1:
+        V = [W.v[r, c] for c in range(C)]
+    else:
+        V = [np.ones((d, d)) for _ in range(C)]
+    Hl, Dl, Al = [np.ones((1, d))], [np.ones((1, d))], [np.ones((d, 1))]
+    for c in range(1, C):
+        Hl.append(W.h[r, c - 1])                              # [x_{c-1}][x_c]
+        if r < R - 1:
+            Dl.append(W.dg[r, c - 1])                         # [x_{c-1}][y_c]
+            Al.append(W.an[r, c - 1])                         # [x_c][y_{c-1}]
+        else:
+            Dl.append(np.ones((d, d)))
+            Al.append(np.ones((d, d)))
+    return w, V, Hl, Dl, Al
+
+
+def _left_part(EL, psi, w, V, Hl, Dl, Al):
+    """P[p, x, y, Q] = sum_{a, e, q} E^L[p, a, e, q] W_c[(a, e), x, y] psi_c[q, y, Q]
+    (the left environment pushed through column c, before phi_c is applied)."""
+    T1 = np.einsum("paeq,xe->paxq", EL, Al)              # A_{c-1}(x, e), sum e
+    T2 = np.einsum("paxq,ax,ay->pxyq", T1, Hl, Dl)       # H_{c-1}(a, x) D_{c-1}(a, y), sum a
+    T3 = np.einsum("pxyq,qyQ->pxyQ", T2, psi)            # psi_c, sum q
+    return T3 * (w[:, None] * V)[None, :, :, None]       # w_c(x) V_c(x, y)
+
+
+def _right_part(ER, psi, w, V):
+    """Q[q, x, y, P] = w_c(x) V_c(x, y) sum_{Q} psi_c[q, y, Q] E^R_{c+1}[P, x, y, Q]."""
+    T = np.einsum("qyQ,PxyQ->qxyP", psi, ER)
+    return T * (w[:, None] * V)[None, :, :, None]
+
+
+def env_left(EL, phi, psi, w, V, Hl, Dl, Al):
+    """E^L_{c+1}[P, x, y, Q] = sum E^L_c[p, a, e, q] phi_c[p, x, P] W_c[(a, e), x, y] psi_c[q, y, Q]."""
+    P = _left_part(EL, psi, w, V, Hl, Dl, Al)
+    return np.einsum("pxP,pxyQ->PxyQ", phi, P)
+
+
+def env_right(ER, phi, psi, w, V, Hl, Dl, Al):
+    """E^R_c[p, a, e, q] = sum phi_c[p, x, P] W_c[(a, e), x, y] psi_c[q, y, Q] E^R_{c+1}[P, x, y, Q]."""
+    G1 = np.einsum("pxP,PxyQ->pxyQ", phi, ER)            # phi_c, sum P
+    G2 = np.einsum("pxyQ,qyQ->pxyq", G1, psi)            # psi_c, sum Q
+    G2 = G2 * (w[:, None] * V)[None, :, :, None]         # w_c(x) V_c(x, y)
+    G3 = np.einsum("pxyq,ay->pxaq", G2, Dl)              # D_{c-1}(a, y), sum y
+    return np.einsum("pxaq,ax,xe->paeq", G3, Hl, Al)     # H_{c-1}(a, x) A_{c-1}(x, e), sum x
+
+
+def two_site_block(EL, ER, psi0, psi1, f0, f1):
+    """B[p, x, z, P] = <env_L| W_c psi_c W_{c+1} psi_{c+1} |env_R> at columns (c, c+1),
+    x = x_c, z = x_{c+1}."""
+    w0, V0, H0, D0, A0 = f0
+    w1, V1, H1, D1, A1 = f1
+    P = _left_part(EL, psi0, w0, V0, H0, D0, A0)         # [p, x, y, Q]
+    Q = _right_part(ER, psi1, w1, V1)                    # [Q, z, v, P]
+    P2 = np.einsum("pxyQ,zy->pxzQ", P, A1)               # A_c(x_{c+1}, y_c), sum y
+    Q2 = np.einsum("QzvP,xv->QxzP", Q, D1)               # D_c(x_c, y_{c+1}), sum v
+    B = np.einsum("pxzQ,QxzP->pxzP", P2, Q2)             # sum Q
+    return B * H1[None, :, :, None]                      # H_c(x_c, x_{c+1})
+
+
+def _norm(T):
+    s = float(np.linalg.norm(T))
+    return (T / s, np.log(s)) if s > 0 else (T, 0.0)
+
+
+def right_canonicalize(phi):
+    """LQ sweep from the right: phi_c (c >= 1) become right isometries."""
+    phi = [t.copy() for t in phi]
+    for c in range(len(phi) - 1, 0, -1):
+        bl, d, br = phi[c].shape
+        Q, Rr = np.linalg.qr(phi[c].reshape(bl, d * br).T, mode="reduced")
+        k = Q.shape[1]
+        phi[c] = Q.T.reshape(k, d, br)
+        phi[c - 1] = np.einsum("pxq,kq->pxk", phi[c - 1], Rr)
+    return phi
+
+
+def row_step(psi, fac, chi, num_sweeps, p, q):
+    """One boundary-MPS row update: returns (phi, log_scale) with phi
+    right-canonical, phi_0 normalised, and T ~ exp(log_scale) phi."""
+    C = len(psi)
+    w, V, Hl, Dl, Al = fac
+    f = [(w[c], V[c], Hl[c], Dl[c], Al[c]) for c in range(C)]
+    phi = [np.einsum("x,xy,pyP->pxP", w[c], V[c], psi[c]) for c in range(C)]
+    phi = right_canonicalize(phi)
+    d = psi[0].shape[1]
+    EL = [None] * (C + 1)
+    ER = [None] * (C + 1)
+    EL[0] = (np.ones((1, 1, 1, 1)), 0.0)
+    ER[C] = (np.ones((1, d, d, 1)), 0.0)
+
+    def build_ER(c):
+        T, s = ER[c + 1]
+        T2, s2 = _norm(env_right(T, phi[c], psi[c], *f[c]))
+        ER[c] = (T2, s + s2)
+
+    def build_EL(c):
+        T, s = EL[c]
+        T2, s2 = _norm(env_left(T, phi[c], psi[c], *f[c]))
+        EL[c + 1] = (T2, s + s2)
+
+    def block(c):
+        B = two_site_block(EL[c][0], ER[c + 2][0], psi[c], psi[c + 1], f[c], f[c + 1])
+        return B, EL[c][1] + ER[c + 2][1]
+
+    lam = 0.0
+    for _ in range(num_sweeps):
+        for c in range(C - 1, 1, -1):
+            build_ER(c)
+        # left-to-right pass
+        for c in range(C - 1):
+            B, s = block(c)
+            pl, _, _, pr = B.shape
+            Bm = B.reshape(pl * d, d * pr)
+            k = min(chi, Bm.shape[0], Bm.shape[1])
+            if c < C - 2:
+                U, Rm = tsvd_left(Bm, k, p, q)
+                phi[c] = U.reshape(pl, d, -1)
+                phi[c + 1] = Rm.reshape(-1, d, pr)
+                build_EL(c)
+            else:
+                Lm, Vt = tsvd_right(Bm, k, p, q)
+                phi[c] = Lm.reshape(pl, d, -1)
+                phi[c + 1] = Vt.reshape(-1, d, pr)
+                lam = s
+                if C > 2:
+                    build_ER(c + 1)
+        # right-to-left pass
+        for c in range(C - 3, -1, -1):
+            B, s = block(c)
+            pl, _, _, pr = B.shape
+            Bm = B.reshape(pl * d, d * pr)
+            k = min(chi, Bm.shape[0], Bm.shape[1])
+            Lm, Vt = tsvd_right(Bm, k, p, q)
+            phi[c] = Lm.reshape(pl, d, -1)
+            phi[c + 1] = Vt.reshape(-1, d, pr)
+            lam = s
+            if c > 0:
+                build_ER(c + 1)
+    phi[0], s0 = _norm(phi[0])
+    return phi, lam + s0
+
+
+def boundary_mps(inst, chi: int, num_sweeps: int = 1, p: int = 16, q: int = 1):
+    """All boundary MPSs, bottom row first.  Returns dict with
+    'A' [rows][cols] tensors, 'lam' [rows] log-scales and 'logZ'."""
+    if inst.cols < 2:
+        raise ValueError("cols >= 2 required")
+    W = Weights(inst)
+    R, C, d = inst.rows, inst.cols, inst.d
+    A = [None] * R
+    lam = [0.0] * R
+    e0 = np.zeros((1, d, 1))
+    e0[0, 0, 0] = 1.0
+    psi = [e0.copy() for _ in range(C)]          # E~_rows = 1 through y = 0 (couplings are ones)
+    prev = 0.0
+    for r in range(R - 1, -1, -1):
+        phi, s = row_step(psi, row_weights(W, r), chi, num_sweeps, p, q)
+        A[r] = phi
+        lam[r] = prev + s
+        prev = lam[r]
+        psi = phi
+    # log Z = lam_0 + log sum_X A_0[x_0]..A_{C-1}[x_{C-1}] - beta * shift
+    v = np.ones(1)
+    for c in range(C):
+        v = v @ A[0][c].sum(axis=1)
+    logZ = lam[0] + float(np.log(v[0])) - inst.beta * W.shift
+    return {"A": A, "lam": lam, "logZ": logZ}
+
+
+def mps_full(A_row) -> np.ndarray:
+    """Dense function of a row MPS (small cases only)."""
+    T = A_row[0][0]                                     # (d, chi_1)
+    for c in range(1, len(A_row)):
+        T = np.tensordot(T, A_row[c], axes=([T.ndim - 1], [0]))
+    return T[..., 0]

@@ -1,0 +1,168 @@
+"""Branch-and-bound (beam) search over conditional marginals (oracle; test
+infrastructure only).
+
+The paper's search (Sec. 2, Fig. 1(d)-(e)) adds one Potts variable at a time in
+a fixed order and keeps a fixed number of the most probable partial
+configurations.  Adopted reading:
+
+* order: row-major, rows top to bottom, columns left to right;
+* each partial configuration b carries score(b) = sum of log p(x_k | x_<k), its
+  FP64 energy of the fixed variables, and the left environment vector L^b;
+* conditional at site (r, c):  q(b, s) = g^b_c(s) * L^b A_{r,c}[:, s, :] R^{a(b)}_{c+1},
+  p(s | b) = q(b, s) / sum_s' q(b, s'), where g^b_c(s) are the couplings of s to the
+  fixed row r-1, R^a_{c+1} the right environment of the row-start ancestor a
+  (R^a_cols = 1, R^a_c = sum_s g^a_c(s) A_{r,c}[:, s, :] R^a_{c+1}); negative q
+  (truncation error) counts as zero probability;
+* keep the M best children by (score desc, parent position asc, s asc);
+  with ``cut_off_prob`` > 0, children below cut_off_prob times the best child
+  of the step get score -inf (they sort last and count as discarded);
+* output: the final beam, energies recomputed by Eq. (1), sorted by energy
+  ascending (ties keep beam order).
+
+The vectors L and R only need a positive scale (it cancels in p(s | b)), so
+they are kept max-normalised without log-scales.
+
+Parity status: with exact boundary functions the scores equal brute-force
+log P(x_<=k) and the beam equals a brute-force beam search
+(tests/test_oracle_search.py); with truncated boundary MPSs the search is
+pinned through the invariants only.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .energy import Weights, potts_energy
+
+
+def _fields(W: Weights, r: int, above: np.ndarray) -> np.ndarray:
+    """g[b, c, s] for a batch of fixed rows r-1 (``above`` is [B][cols])."""
+    B = above.shape[0] if above is not None else 1
+    C, d = W.inst.cols, W.inst.d
+    g = np.ones((B, C, d))
+    if r == 0:
+        return g
+    for c in range(C):
+        g[:, c] *= W.v[r - 1, c][above[:, c], :]
+        if c > 0:
+            g[:, c] *= W.dg[r - 1, c - 1][above[:, c - 1], :]
+        if c < C - 1:
+            g[:, c] *= W.an[r - 1, c][above[:, c + 1], :]
+    return g
+
+
+def delta_energy(inst, cfg: np.ndarray, r: int, c: int) -> np.ndarray:
+    """[B][d] energy added by setting x_{r,c} = s (Eq. (1) terms that close)."""
+    C = inst.cols
+    dE = np.repeat(inst.local_E[r, c][None, :], cfg.shape[0], axis=0).copy()
+    if c > 0:
+        dE += inst.pair_h[r, c - 1][cfg[:, r * C + c - 1], :]
+    if r > 0:
+        up = (r - 1) * C
+        dE += inst.pair_v[r - 1, c][cfg[:, up + c], :]
+        if inst.kings:
+            if c > 0:
+                dE += inst.pair_d[r - 1, c - 1][cfg[:, up + c - 1], :]
+            if c < C - 1:
+                dE += inst.pair_a[r - 1, c][cfg[:, up + c + 1], :]
+    return dE
+
+
+def select_top(scores: np.ndarray, M: int) -> np.ndarray:
+    """Flat indices (b*d + s) of the M best candidates, ordered by score
+    descending then flat index ascending (= parent position, then s)."""
+    flat = scores.reshape(-1)
+    order = np.lexsort((np.arange(flat.size), -flat))
+    return order[:M]
+
+
+def marginals(A_rc, g_c, L, R_next):
+    """q[b, s] = g_c[b, s] * sum_{alpha, alpha'} L[b, alpha] A[alpha, s, alpha'] R[b, alpha']."""
+    return g_c * np.einsum("ba,asz,bz->bs", L, A_rc, R_next)
+
+
+def log_conditionals(q: np.ndarray) -> np.ndarray:
+    q = np.where(q > 0, q, 0.0)
+    tot = q.sum(axis=1, keepdims=True)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lp = np.log(q) - np.log(tot)
+    return np.where(np.isfinite(lp), lp, -np.inf)
+
+
+def right_envs(A_row, g):
+    """R[a, c] for c = cols..0 (list index c), max-normalised vectors."""
+    B = g.shape[0]
+    C = len(A_row)
+    R = [None] * (C + 1)
+    R[C] = np.ones((B, 1))
+    for c in range(C - 1, -1, -1):
+        S = np.einsum("asz,bz->bas", A_row[c], R[c + 1])         # [B][chi_c][d]
+        v = np.einsum("bas,bs->ba", S, g[:, c])
+        m = np.abs(v).max(axis=1, keepdims=True)
+        R[c] = v / np.where(m > 0, m, 1.0)
+    return R
+
+
+def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None):
+    """Run the search with boundary MPS tensors A[r][c].  Returns dict with
+    'states' [n][N], 'energies', 'scores' (sorted by energy) and 'beam_energies'
+    (the final beam in beam order).  ``trace`` (optional list) receives per-site
+    dicts with the parents' log-conditionals for teacher-forced comparisons."""
+    W = Weights(inst)
+    Rr, C, d = inst.rows, inst.cols, inst.d
+    N = Rr * C
+    cfg = np.zeros((1, N), dtype=np.int64)
+    score = np.zeros(1)
+    energy = np.zeros(1)
+    for r in range(Rr):
+        above = cfg[:, (r - 1) * C: r * C] if r > 0 else None
+        g_anc = _fields(W, r, above)                                  # [n_anc][C][d]
+        R = right_envs(A[r], g_anc)
+        anc = np.arange(cfg.shape[0])
+        L = np.ones((cfg.shape[0], 1))
+        for c in range(C):
+            q = marginals(A[r][c], g_anc[anc, c], L, R[c + 1][anc])
+            lp = log_conditionals(q)
+            cand = score[:, None] + lp
+            if cut_off_prob > 0:
+                best = cand.max()
+                cand = np.where(cand >= best + np.log(cut_off_prob), cand, -np.inf)
+            if trace is not None:
+                trace.append({"site": r * C + c, "cfg": cfg.copy(), "logp": lp.copy()})
+            dE = delta_energy(inst, cfg, r, c)
+            keep = select_top(cand, M)
+            b, s = np.divmod(keep, d)
+            cfg = cfg[b].copy()
+            cfg[:, r * C + c] = s
+            score = cand.reshape(-1)[keep]
+            energy = energy[b] + dE[b, s]
+            # L^child = g^b_c(s) * L^b A_{r,c}[:, s, :]
+            Lb = np.einsum("ba,baz->bz", L[b], np.transpose(A[r][c][:, s, :], (1, 0, 2)))
+            Lb = Lb * g_anc[anc[b], c, s][:, None]
+            m = np.abs(Lb).max(axis=1, keepdims=True)
+            L = Lb / np.where(m > 0, m, 1.0)
+            anc = anc[b]
+    E = potts_energy(inst, cfg)
+    order = np.lexsort((np.arange(len(E)), E))
+    return {"states": cfg[order], "energies": E[order], "scores": score[order],
+            "beam_states": cfg, "beam_scores": score, "beam_energies": energy,
+            "n_valid": int(np.isfinite(score).sum())}
+
+
+def teacher_forced_logp(inst, A, r: int, c: int, cfg: np.ndarray) -> np.ndarray:
+    """log p(s | b) at site (r, c) for given partial configurations ``cfg``
+    ([B][N], first r*cols+c entries valid), with the row-start ancestor of b
+    taken as b's own rows 0..r-1."""
+    W = Weights(inst)
+    C = inst.cols
+    above = cfg[:, (r - 1) * C: r * C] if r > 0 else None
+    g = _fields(W, r, above) if r > 0 else np.ones((cfg.shape[0], C, inst.d))
+    R = right_envs(A[r], g)
+    L = np.ones((cfg.shape[0], 1))
+    for cc in range(c):
+        s = cfg[:, r * C + cc]
+        Lb = np.einsum("ba,baz->bz", L, np.transpose(A[r][cc][:, s, :], (1, 0, 2)))
+        Lb = Lb * g[np.arange(cfg.shape[0]), cc, s][:, None]
+        m = np.abs(Lb).max(axis=1, keepdims=True)
+        L = Lb / np.where(m > 0, m, 1.0)
+    q = marginals(A[r][c], g[:, c], L, R[c + 1])
+    return log_conditionals(q)
