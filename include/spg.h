@@ -1,0 +1,163 @@
+/*
+ * spg.h - C ABI of the MI355X (gfx950) PEPS branch-and-bound hot path.
+ *
+ * The library finds low-energy states of a generalized Potts model (paper,
+ * Sec. 2, Eq. (1)) on a rows x cols square or king's-graph lattice of clusters
+ * (Fig. 1(b)): it builds the Boltzmann-weight PEPS (Fig. 1(c)), contracts it
+ * row by row into boundary MPSs (Fig. 1(d)), and runs the branch-and-bound
+ * (beam) search over conditional marginals (Fig. 1(d)-(e)).  Every step runs
+ * in HIP kernels on the GPU; the host only validates arguments, sizes buffers
+ * and enqueues work.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: SPG_OK (0) or a negative SPG_ERR_* code; the message of the
+ *     last failure on the calling thread is returned by spg_last_error().
+ *     Arguments are validated before anything is enqueued, so an error return
+ *     leaves outputs untouched unless stated otherwise.
+ *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued asynchronously; a call blocks only when it writes a HOST output.
+ *   - Ownership: spg_peps_t and spg_env_t are library-owned and freed with
+ *     their spg_free_* call.  Every buffer passed in is caller-owned; DEVICE
+ *     pointers must stay valid until the enqueued work completes.
+ *   - A handle is not thread-safe; an env keeps a pointer to its peps, which
+ *     must outlive it.
+ *   - Sites are numbered row-major, site = r * cols + c.  Local states are
+ *     0 .. d-1.
+ *   - Limits: 1 <= rows, 2 <= cols, 2 <= d <= 256, 1 <= chi <= 80,
+ *     1 <= max_states <= 65536; larger values return SPG_ERR_UNSUPPORTED.
+ */
+#ifndef SPG_H
+#define SPG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SPG_OK = 0,
+  SPG_ERR_INVALID = -1,     /* bad argument (null pointer, inconsistent sizes)   */
+  SPG_ERR_OOM = -2,         /* device allocation failed                          */
+  SPG_ERR_HIP = -3,         /* a HIP runtime call failed                         */
+  SPG_ERR_NONFINITE = -4,   /* non-finite energy, beta or log-scale              */
+  SPG_ERR_UNSUPPORTED = -5  /* size outside the supported limits                 */
+};
+
+/* Working precision of the contractions (boundary MPS, environments,
+ * marginals).  QR/SVD factorisations, energies and accumulated scores are
+ * always FP64. */
+enum { SPG_FP64 = 0, SPG_FP32 = 1, SPG_BF16 = 2 };
+
+typedef struct spg_peps spg_peps_t;
+typedef struct spg_env spg_env_t;
+
+/* A Potts instance, Eq. (1): E(x) = sum_edges E_mn(x_m, x_n) + sum_sites E_n(x_n).
+ * All pointers are HOST float64 arrays, row-major, read only during
+ * spg_build_peps.  Edge classes: H (r,c)-(r,c+1), V (r,c)-(r+1,c),
+ * D (r,c)-(r+1,c+1), A (r,c+1)-(r+1,c); a pair table is indexed
+ * [state of the first site][state of the second site]. */
+typedef struct {
+  int32_t rows, cols, d;
+  int32_t kings;              /* 1: H, V, D and A edges (king's graph); 0: H and V only */
+  double beta;                /* inverse temperature of the Boltzmann weights exp(-beta E) */
+  const double *local_E;      /* [rows][cols][d]                                        */
+  const double *pair_E_h;     /* [rows][cols-1][d][d]                                   */
+  const double *pair_E_v;     /* [rows-1][cols][d][d]                                   */
+  const double *pair_E_d;     /* [rows-1][cols-1][d][d]; NULL when kings == 0           */
+  const double *pair_E_a;     /* [rows-1][cols-1][d][d]; NULL when kings == 0           */
+} spg_instance_desc;
+
+/* Boundary-MPS contraction parameters (the paper's MpsParameters: bond
+ * dimension and number of sweeps; "SVDTruncate" is the truncated SVD of
+ * two-site blocks by randomized subspace iteration). */
+typedef struct {
+  int32_t chi;          /* bond dimension cap of every boundary MPS                 */
+  int32_t num_sweeps;   /* variational sweeps per row (>= 1); one sweep is a       */
+                        /* left-to-right then a right-to-left pass                  */
+  int32_t precision;    /* SPG_FP64 / SPG_FP32 / SPG_BF16                           */
+  int32_t oversample;   /* sketch oversampling p of the truncated SVD (>= 0)       */
+  int32_t power_iters;  /* subspace (power) iterations q of the truncated SVD      */
+} spg_mps_params;
+
+/* Search parameters (the paper's SearchParameters). */
+typedef struct {
+  int32_t max_states;   /* beam width M: partial configurations kept per step      */
+  double cut_off_prob;  /* 0 disables; else a child whose probability is below     */
+                        /* cut_off_prob times the best child of the step is        */
+                        /* discarded (kept only as -inf padding)                   */
+} spg_search_params;
+
+/* Build the PEPS of an instance (Sec. 2, Fig. 1(c)): copies the energy tables
+ * to the device and forms the Boltzmann weights w = exp(-beta (E - eps)) of
+ * every table, eps = the table minimum (the shift only rescales Z).
+ * Errors: SPG_ERR_INVALID (null desc/out/table), SPG_ERR_UNSUPPORTED (sizes),
+ * SPG_ERR_NONFINITE (non-finite beta or energy), SPG_ERR_OOM, SPG_ERR_HIP.
+ * Blocks until the tables are on the device. */
+int spg_build_peps(const spg_instance_desc *desc, void *stream, spg_peps_t **out);
+
+/* Boundary-MPS contraction of the PEPS (Sec. 2, Fig. 1(d); Sec. 2.1 names the
+ * boundary-MPS approach): for r = rows-1 .. 0 the row's transfer operator is
+ * applied to the previous boundary MPS and compressed to bond dimension chi.
+ * The result (rows x cols tensors of chi_c x d x chi_{c+1}, right-canonical,
+ * plus per-row log-scales) is held in a new env.  When log_Z_out (HOST) is not
+ * NULL the call synchronises the stream and writes the estimate of log Z.
+ * Errors: SPG_ERR_INVALID, SPG_ERR_UNSUPPORTED (chi, precision), SPG_ERR_OOM,
+ * SPG_ERR_HIP, SPG_ERR_NONFINITE (log Z requested and not finite). */
+int spg_boundary_mps(const spg_peps_t *peps, const spg_mps_params *params, void *stream,
+                     spg_env_t **out, double *log_Z_out);
+
+/* Conditional marginals (Sec. 2: marginal and conditional probabilities are
+ * derived from the contraction): for each of n_beam partial configurations
+ * b (DEVICE int32 [n_beam][rows*cols], entries of sites < `site` used),
+ * writes log p(x_site = s | b) for s = 0..d-1 to log_cond_out (DEVICE float64
+ * [n_beam][d]).  Impossible states get -inf.
+ * Errors: SPG_ERR_INVALID (null pointers, site out of range, n_beam < 1),
+ * SPG_ERR_OOM, SPG_ERR_HIP. */
+int spg_marginals(const spg_env_t *env, int32_t site, int32_t n_beam, const int32_t *beam_cfg,
+                  double *log_cond_out, void *stream);
+
+/* Branch-and-bound search (Sec. 2; Fig. 1(d)-(e)): visits the sites in
+ * row-major order, keeping the max_states most probable partial
+ * configurations (ties: parent position, then state), and returns the final
+ * beam sorted by energy ascending:
+ *   states_out   DEVICE int32   [max_states][rows*cols]
+ *   energies_out DEVICE float64 [max_states]  (Eq. (1), recomputed in FP64)
+ *   logp_out     DEVICE float64 [max_states]  (accumulated log-probability)
+ *   n_out        HOST   int32   number of rows written with a finite log-probability
+ *                                (rows beyond the beam size are left untouched)
+ * Synchronises the stream (n_out is a host output).
+ * Errors: SPG_ERR_INVALID, SPG_ERR_UNSUPPORTED (max_states), SPG_ERR_OOM, SPG_ERR_HIP. */
+int spg_branch_and_bound(const spg_env_t *env, const spg_search_params *params,
+                         int32_t *states_out, double *energies_out, double *logp_out,
+                         int32_t *n_out, void *stream);
+
+void spg_free_peps(spg_peps_t *peps);
+void spg_free_env(spg_env_t *env);
+const char *spg_last_error(void);
+
+/* ---- inspection hooks (tests and tools) -------------------------------- */
+
+/* Sizes of an env: rows, cols, d, chi and the bond dimensions
+ * bond_dims HOST int32 [rows][cols+1] (may be NULL).  Synchronous. */
+int spg_env_info(const spg_env_t *env, int32_t *rows, int32_t *cols, int32_t *d, int32_t *chi,
+                 int32_t *bond_dims);
+
+/* Copy the boundary MPS to the host: tensors HOST float64
+ * [rows][cols][chi][d][chi] (zero outside the bond dimensions) and
+ * lam HOST float64 [rows] (log-scales; either may be NULL).  Synchronous. */
+int spg_env_export(const spg_env_t *env, double *tensors, double *lam);
+
+/* Make an env from given boundary-MPS tensors (HOST float64, same layout as
+ * spg_env_export, bond dimensions HOST int32 [rows][cols+1]) so the search
+ * can be run on tensors computed elsewhere.  `precision` selects the search
+ * arithmetic as in spg_mps_params.  Errors: SPG_ERR_INVALID, SPG_ERR_UNSUPPORTED,
+ * SPG_ERR_OOM, SPG_ERR_HIP.  Blocks until the copy is done. */
+int spg_env_import(const spg_peps_t *peps, int32_t chi, const int32_t *bond_dims,
+                   const double *tensors, const double *lam, int32_t precision, void *stream,
+                   spg_env_t **out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPG_H */

@@ -166,3 +166,39 @@ def teacher_forced_logp(inst, A, r: int, c: int, cfg: np.ndarray) -> np.ndarray:
         L = Lb / np.where(m > 0, m, 1.0)
     q = marginals(A[r][c], g[:, c], L, R[c + 1])
     return log_conditionals(q)
+
+
+def teacher_forced_condition(inst, A, r: int, c: int, cfg: np.ndarray):
+    """Running-error condition numbers of the teacher-forced conditionals.
+
+    The same chain as ``teacher_forced_logp`` contracted with absolute values
+    (|L|, |A|, |R|, with L and R built from |A| as well) gives q_abs >= |q| term
+    by term; a floating-point evaluation of q with n operations along the chain
+    has |fl(q) - q| <= n eps q_abs (standard running error bound).  Both chains
+    are divided by the same positive factors, so the bound survives scaling.
+    Returns (kappa_s, kappa_Z) = (q_abs(s) / |q(s)|, sum_s q_abs / sum_s q+)."""
+    W = Weights(inst)
+    C = inst.cols
+    nb = cfg.shape[0]
+    above = cfg[:, (r - 1) * C: r * C] if r > 0 else None
+    g = _fields(W, r, above) if r > 0 else np.ones((nb, C, inst.d))
+    Rv, Ra = np.ones((nb, 1)), np.ones((nb, 1))
+    for cc in range(C - 1, c, -1):
+        v = np.einsum("asz,bz,bs->ba", A[r][cc], Rv, g[:, cc])
+        va = np.einsum("asz,bz,bs->ba", np.abs(A[r][cc]), Ra, g[:, cc])
+        m = np.where(va.max(axis=1, keepdims=True) > 0, va.max(axis=1, keepdims=True), 1.0)
+        Rv, Ra = v / m, va / m
+    L, La = np.ones((nb, 1)), np.ones((nb, 1))
+    for cc in range(c):
+        s = cfg[:, r * C + cc]
+        gs = g[np.arange(nb), cc, s][:, None]
+        L = gs * np.einsum("ba,baz->bz", L, np.transpose(A[r][cc][:, s, :], (1, 0, 2)))
+        La = gs * np.einsum("ba,baz->bz", La, np.transpose(np.abs(A[r][cc])[:, s, :], (1, 0, 2)))
+        m = np.where(La.max(axis=1, keepdims=True) > 0, La.max(axis=1, keepdims=True), 1.0)
+        L, La = L / m, La / m
+    q = marginals(A[r][c], g[:, c], L, Rv)
+    qa = marginals(np.abs(A[r][c]), g[:, c], La, Ra)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ks = qa / np.abs(q)
+        kz = qa.sum(axis=1) / np.where(q > 0, q, 0).sum(axis=1)
+    return ks, kz

@@ -1,0 +1,622 @@
+// C ABI of include/spg.h: argument validation, device buffers and the
+// sequencing of the kernels on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "spg_internal.h"
+
+namespace spg {
+
+thread_local std::string g_err;
+void set_error(const std::string &m) { g_err = m; }
+
+void DevBuf::ensure(size_t n) {
+  if (n <= bytes) return;
+  release();
+  if (hipMalloc(&p, n) != hipSuccess) {
+    p = nullptr;
+    bytes = 0;
+    (void)hipGetLastError();
+    set_error("device allocation of " + std::to_string(n) + " bytes failed");
+    throw Fail{SPG_ERR_OOM};
+  }
+  bytes = n;
+  SPG_HIP(hipMemset(p, 0, n));
+  SPG_HIP(hipDeviceSynchronize());
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+static int fail(int code, const std::string &m) {
+  set_error(m);
+  return code;
+}
+
+#define SPG_TRY try {
+#define SPG_CATCH                                                  \
+  }                                                                \
+  catch (const ::spg::Fail &f) { return f.code; }                  \
+  catch (const std::bad_alloc &) {                                 \
+    ::spg::set_error("host allocation failed");                    \
+    return SPG_ERR_OOM;                                            \
+  }
+
+// ---------------------------------------------------------------------------
+// Boundary MPS: one workspace per call.
+struct BmpsWork {
+  int R, C, d, chi, lmax;
+  DevBuf EL, ER, T1, P, Qr, P2, Q2, G1, G2, B, Y, Q, Z, Qz, Om, Cm, Qc, Rc, V, sig, U, Rm,
+      qrwork, tmp, logs, psi0;
+  size_t env_sz() const { return (size_t)chi * d * d * chi; }
+  size_t site_sz() const { return (size_t)chi * d * chi; }
+  double *ELc(int c) { return EL.as<double>() + (size_t)c * env_sz(); }
+  double *ERc(int c) { return ER.as<double>() + (size_t)c * env_sz(); }
+  void alloc() {
+    const size_t es = env_sz() * sizeof(double);
+    EL.ensure(es * (C + 1));
+    ER.ensure(es * (C + 1));
+    T1.ensure(2 * es);
+    P.ensure(es); Qr.ensure(es); P2.ensure(es); Q2.ensure(es); G1.ensure(es); G2.ensure(es);
+    const size_t mn = (size_t)chi * d;                  // max rows / cols of a two-site block
+    B.ensure(mn * mn * sizeof(double));
+    const size_t ml = mn * lmax * sizeof(double);
+    Y.ensure(ml); Q.ensure(ml); Z.ensure(ml); Qz.ensure(ml); Om.ensure(ml); Qc.ensure(ml);
+    Cm.ensure(ml);
+    Rc.ensure((size_t)lmax * lmax * sizeof(double));
+    V.ensure((size_t)lmax * lmax * sizeof(double));
+    sig.ensure((size_t)lmax * sizeof(double));
+    U.ensure(ml);
+    Rm.ensure(ml);
+    qrwork.ensure((2 * mn * lmax + lmax) * sizeof(double));
+    tmp.ensure(site_sz() * sizeof(double));
+    logs.ensure((size_t)(2 * C + 8 + R) * sizeof(double));
+    psi0.ensure(site_sz() * C * sizeof(double));
+  }
+};
+
+// Rank-kk split of an m x n matrix view B (element (i,j) at B[i*br + j*bc]):
+// U (m x kk, orthonormal columns) written at U[i*ur + j*uc].  Randomised range
+// finder with q power iterations, sketch width l = min(k+p, m, n), then the
+// SVD of the projected l x n matrix (QR of its transpose + one-sided Jacobi).
+static int tsvd_left(BmpsWork &w, const double *B, long br, long bc, int m, int n, int k, int p,
+                     int q, double *U, long ur, long uc, hipStream_t s) {
+  const int l = std::min(std::min(k + p, m), n);
+  const int kk = std::min(k, l);
+  double *Om = w.Om.as<double>(), *Y = w.Y.as<double>(), *Q = w.Q.as<double>();
+  double *Z = w.Z.as<double>(), *Qz = w.Qz.as<double>(), *Cm = w.Cm.as<double>();
+  fill_sketch(n, l, Om, s);
+  auto mm = [&](int M, int N, int K, const double *A, long ai, long ak, const double *Bp, long bk,
+                long bj, double *Cp, long ci, long cj) {
+    GemmDesc g{};
+    g.M = M; g.N = N; g.K = K; g.nb1 = 1; g.nb2 = 1;
+    g.A = A; g.a_i = ai; g.a_k = ak;
+    g.B = Bp; g.b_k = bk; g.b_j = bj;
+    g.C = Cp; g.c_i = ci; g.c_j = cj;
+    g.alpha = 1.0; g.beta = 0.0;
+    gemm_f64(g, s);
+  };
+  double *qw = w.qrwork.as<double>();
+  mm(m, l, n, B, br, bc, Om, l, 1, Y, l, 1);                 // Y = B Om
+  qr_f64(m, l, Y, l, 1, Q, l, 1, nullptr, qw, s);           // Q = orth(Y)
+  for (int it = 0; it < q; ++it) {
+    mm(n, l, m, B, bc, br, Q, l, 1, Z, l, 1);                // Z = B^T Q
+    qr_f64(n, l, Z, l, 1, Qz, l, 1, nullptr, qw, s);
+    mm(m, l, n, B, br, bc, Qz, l, 1, Y, l, 1);               // Y = B Qz
+    qr_f64(m, l, Y, l, 1, Q, l, 1, nullptr, qw, s);
+  }
+  mm(l, n, m, Q, 1, l, B, br, bc, Cm, n, 1);                 // Cm = Q^T B   (l x n)
+  qr_f64(n, l, Cm, 1, n, w.Qc.as<double>(), l, 1, w.Rc.as<double>(), qw, s);  // Cm^T = Qc Rc
+  jacobi_svd_f64(l, w.Rc.as<double>(), w.V.as<double>(), w.sig.as<double>(), s);
+  mm(m, kk, l, Q, l, 1, w.V.as<double>(), l, 1, U, ur, uc);  // U = Q V[:, :kk]
+  return kk;
+}
+
+// ---------------------------------------------------------------------------
+static void row_factors(const spg_peps *pp, int r, int c, bool bottom, RowFactors &f) {
+  const int C = pp->cols, d = pp->d;
+  const size_t dd = (size_t)d * d;
+  f.w = pp->W_loc.as<double>() + ((size_t)r * C + c) * d;
+  f.V = bottom ? pp->ones.as<double>() : pp->W_v.as<double>() + ((size_t)r * C + c) * dd;
+  if (c == 0) {
+    f.Hl = pp->e0row.as<double>();
+    f.Dl = pp->e0row.as<double>();
+    f.Al = pp->e0col.as<double>();
+  } else {
+    f.Hl = pp->W_h.as<double>() + ((size_t)r * (C - 1) + c - 1) * dd;
+    f.Dl = bottom ? pp->ones.as<double>() : pp->W_d.as<double>() + ((size_t)r * (C - 1) + c - 1) * dd;
+    f.Al = bottom ? pp->ones.as<double>() : pp->W_a.as<double>() + ((size_t)r * (C - 1) + c - 1) * dd;
+  }
+}
+
+static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream_t s) {
+  const spg_peps *pp = env->peps;
+  const int R = pp->rows, C = pp->cols, d = pp->d, chi = env->chi;
+  BmpsWork w;
+  w.R = R; w.C = C; w.d = d; w.chi = chi;
+  w.lmax = std::min(chi + std::max(prm->oversample, 0), chi * d);
+  w.alloc();
+  const size_t site = w.site_sz(), es = w.env_sz();
+  double *A = env->A.as<double>();
+  double *logs = w.logs.as<double>();
+  // log slots: EL[c] at c, ER[c] at C+1+c, centre at 2C+2, lam[r] at 2C+4+r
+  const int sEL = 0, sER = C + 1, sCen = 2 * C + 2, sLam = 2 * C + 4;
+  fill_zero(logs, (size_t)(2 * C + 8 + R), s);
+  // E~_rows = 1 through the state y = 0 of a bond-1 product MPS
+  fill_zero(w.psi0.as<double>(), site * C, s);
+  for (int c = 0; c < C; ++c) set_e0(1, 1, w.psi0.as<double>() + c * site, 1, s);
+  // trivial environments: EL[0] and ER[C] (p = q = 0, all (a, e) / (x, y) for ER)
+  fill_zero(w.ELc(0), es, s);
+  set_e0(1, 1, w.ELc(0), 1, s);
+  fill_zero(w.ERc(C), es, s);
+  set_e0(d * d, 1, w.ERc(C), chi, s);                        // ER[0][x][y][0] = 1
+  std::vector<int> pdims(C + 1, 1), fdims(C + 1, 1);
+  for (int r = R - 1; r >= 0; --r) {
+    const bool bottom = (r == R - 1);
+    const double *psi = bottom ? w.psi0.as<double>() : A + (size_t)(r + 1) * C * site;
+    double *phi = A + (size_t)r * C * site;
+    if (bottom) std::fill(pdims.begin(), pdims.end(), 1);
+    else for (int c = 0; c <= C; ++c) pdims[c] = env->dims[(r + 1) * (C + 1) + c];
+    std::vector<RowFactors> f(C);
+    for (int c = 0; c < C; ++c) row_factors(pp, r, c, bottom, f[c]);
+    // initial guess phi_c[x] = w_c(x) sum_y V_c(x,y) psi_c[y], then right-canonical form
+    fill_zero(phi, site * C, s);
+    for (int c = 0; c < C; ++c) init_guess(d, chi, pdims[c], pdims[c + 1], psi + c * site, f[c], phi + c * site, s);
+    fdims = pdims;
+    for (int c = C - 1; c >= 1; --c) {
+      const int bl = fdims[c], br = fdims[c + 1];
+      double *Mc = w.Cm.as<double>();                           // compact bl x (d*br)
+      pack_right(d, chi, bl, br, phi + c * site, Mc, s);
+      // QR of Mc^T (d*br x bl): Q -> new right isometry, R folded into phi_{c-1}
+      qr_f64(d * br, bl, Mc, 1, (long)d * br, w.Qc.as<double>(), bl, 1, w.Rc.as<double>(),
+             w.qrwork.as<double>(), s);
+      fill_zero(phi + c * site, site, s);
+      unpack_right(d, chi, bl, br, w.Qc.as<double>(), 1, bl, phi + c * site, s);
+      lq_fold(d, chi, bl, bl, w.Rc.as<double>(), phi + (c - 1) * site, w.tmp.as<double>(), s);
+    }
+    auto build_ER = [&](int c) {
+      env_right(d, chi, fdims[c], fdims[c + 1], pdims[c], pdims[c + 1], phi + c * site,
+                psi + c * site, w.ERc(c + 1), f[c], w.G1.as<double>(), w.G2.as<double>(),
+                w.ERc(c), s);
+      normalize_box(w.ERc(c), fdims[c], d, d, pdims[c], (long)d * d * chi, (long)d * chi, chi, 1,
+                    logs, sER + c, sER + c + 1, s);
+    };
+    auto build_EL = [&](int c) {
+      left_part(d, chi, fdims[c], pdims[c], pdims[c + 1], w.ELc(c), psi + c * site, f[c],
+                w.T1.as<double>(), w.P.as<double>(), s);
+      env_left(d, chi, fdims[c], fdims[c + 1], pdims[c + 1], phi + c * site, w.P.as<double>(),
+               w.ELc(c + 1), s);
+      normalize_box(w.ELc(c + 1), fdims[c + 1], d, d, pdims[c + 1], (long)d * d * chi,
+                    (long)d * chi, chi, 1, logs, sEL + c + 1, sEL + c, s);
+    };
+    // two-site update at (c, c+1); right = true: centre moves left (phi_c = U S, phi_{c+1} = V^T)
+    auto update = [&](int c, bool right) {
+      const int pl = fdims[c], pr = fdims[c + 2];
+      two_site_block(d, chi, pl, pdims[c], pdims[c + 1], pdims[c + 2], pr, w.ELc(c), w.ERc(c + 2),
+                     psi + c * site, psi + (c + 1) * site, f[c], f[c + 1], w.T1.as<double>(),
+                     w.P.as<double>(), w.Qr.as<double>(), w.P2.as<double>(), w.Q2.as<double>(),
+                     w.B.as<double>(), s);
+      const int m = pl * d, n = d * pr;
+      const int k = std::min(chi, std::min(m, n));
+      double *Bm = w.B.as<double>();
+      double *phic = phi + c * site, *phin = phi + (c + 1) * site;
+      fill_zero(phic, site, s);
+      fill_zero(phin, site, s);
+      GemmDesc g{};
+      g.nb1 = 1; g.nb2 = 1; g.alpha = 1.0; g.beta = 0.0;
+      int kk;
+      if (!right) {
+        kk = tsvd_left(w, Bm, n, 1, m, n, k, prm->oversample, prm->power_iters, phic, chi, 1, s);
+        // Rm = U^T B (kk x n) -> phi_{c+1}[k][z][P]
+        g.M = kk; g.N = n; g.K = m;
+        g.A = phic; g.a_i = 1; g.a_k = chi;
+        g.B = Bm; g.b_k = n; g.b_j = 1;
+        g.C = w.Rm.as<double>(); g.c_i = n; g.c_j = 1;
+        gemm_f64(g, s);
+        unpack_right(d, chi, kk, pr, w.Rm.as<double>(), n, 1, phin, s);
+      } else {
+        // tsvd of B^T (n x m): U' (n x kk) -> phi_{c+1} = U'^T;  phi_c = B U'
+        double *Up = w.U.as<double>();
+        kk = tsvd_left(w, Bm, 1, n, n, m, k, prm->oversample, prm->power_iters, Up, k, 1, s);
+        unpack_right(d, chi, kk, pr, Up, 1, k, phin, s);
+        g.M = m; g.N = kk; g.K = n;
+        g.A = Bm; g.a_i = n; g.a_k = 1;
+        g.B = Up; g.b_k = k; g.b_j = 1;
+        g.C = phic; g.c_i = chi; g.c_j = 1;
+        gemm_f64(g, s);
+      }
+      fdims[c + 1] = kk;
+    };
+    int last_pair_lam_slot = sER + 2;
+    for (int sw = 0; sw < std::max(prm->num_sweeps, 1); ++sw) {
+      for (int c = C - 1; c >= 2; --c) build_ER(c);
+      for (int c = 0; c <= C - 2; ++c) {
+        if (c < C - 2) {
+          update(c, false);
+          build_EL(c);
+        } else {
+          update(c, true);
+          if (C > 2) build_ER(c + 1);
+        }
+      }
+      for (int c = C - 3; c >= 0; --c) {
+        update(c, true);
+        if (c > 0) build_ER(c + 1);
+      }
+    }
+    (void)last_pair_lam_slot;
+    // normalise the centre phi_0; lam_r = lam_{r+1} + log-scale of ER[2] + log |phi_0|
+    normalize_box(phi, 1, d, fdims[1], 1, (long)d * chi, chi, 1, 1, logs, sCen, -1, s);
+    add_logs(logs, sLam + r, bottom ? -1 : sLam + r + 1, (C > 2) ? sER + 2 : -1, sCen, s);
+    for (int c = 0; c <= C; ++c) env->dims[r * (C + 1) + c] = fdims[c];
+  }
+  SPG_HIP(hipMemcpyAsync(env->lam.as<double>(), logs + sLam, sizeof(double) * R,
+                         hipMemcpyDeviceToDevice, s));
+  // keep the workspace alive until the stream has consumed it
+  SPG_HIP(hipStreamSynchronize(s));
+}
+
+static SearchTabs tabs_of(const spg_env *env) {
+  const spg_peps *pp = env->peps;
+  SearchTabs t;
+  t.rows = pp->rows; t.cols = pp->cols; t.d = pp->d; t.chi = env->chi;
+  t.E_loc = pp->E_loc.as<double>(); t.E_h = pp->E_h.as<double>(); t.E_v = pp->E_v.as<double>();
+  t.E_d = pp->E_d.as<double>(); t.E_a = pp->E_a.as<double>();
+  t.W_v = pp->W_v.as<double>(); t.W_d = pp->W_d.as<double>(); t.W_a = pp->W_a.as<double>();
+  return t;
+}
+
+static int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+}  // namespace spg
+
+using namespace spg;
+
+extern "C" {
+
+const char *spg_last_error(void) { return g_err.c_str(); }
+
+int spg_build_peps(const spg_instance_desc *desc, void *stream, spg_peps_t **out) {
+  SPG_TRY
+  if (!desc || !out) return fail(SPG_ERR_INVALID, "spg_build_peps: null desc or out");
+  const int R = desc->rows, C = desc->cols, d = desc->d;
+  if (R < 1 || C < 2 || d < 2) return fail(SPG_ERR_UNSUPPORTED, "spg_build_peps: need rows >= 1, cols >= 2, d >= 2");
+  if (d > 256) return fail(SPG_ERR_UNSUPPORTED, "spg_build_peps: d > 256");
+  if ((long)R * C > 65536) return fail(SPG_ERR_UNSUPPORTED, "spg_build_peps: more than 65536 sites");
+  if (!std::isfinite(desc->beta) || desc->beta < 0)
+    return fail(SPG_ERR_NONFINITE, "spg_build_peps: beta must be finite and >= 0");
+  if (!desc->local_E || !desc->pair_E_h || (R > 1 && !desc->pair_E_v))
+    return fail(SPG_ERR_INVALID, "spg_build_peps: null energy table");
+  if (desc->kings && R > 1 && (!desc->pair_E_d || !desc->pair_E_a))
+    return fail(SPG_ERR_INVALID, "spg_build_peps: kings=1 needs pair_E_d and pair_E_a");
+  const size_t dd = (size_t)d * d;
+  const size_t n_loc = (size_t)R * C * d, n_h = (size_t)R * (C - 1) * dd;
+  const size_t n_v = (size_t)(R - 1) * C * dd, n_x = (size_t)(R - 1) * (C - 1) * dd;
+  auto finite = [](const double *p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(p[i])) return false;
+    return true;
+  };
+  if (!finite(desc->local_E, n_loc) || !finite(desc->pair_E_h, n_h) ||
+      (n_v && !finite(desc->pair_E_v, n_v)) ||
+      (desc->kings && n_x && (!finite(desc->pair_E_d, n_x) || !finite(desc->pair_E_a, n_x))))
+    return fail(SPG_ERR_NONFINITE, "spg_build_peps: non-finite energy");
+  hipStream_t s = (hipStream_t)stream;
+  spg_peps *pp = new spg_peps();
+  try {
+    pp->rows = R; pp->cols = C; pp->d = d; pp->kings = desc->kings ? 1 : 0; pp->beta = desc->beta;
+    SPG_HIP(hipGetDevice(&pp->device));
+    auto up = [&](DevBuf &b, const double *src, size_t n) {
+      b.ensure(std::max<size_t>(n, 1) * sizeof(double));
+      if (n && src) SPG_HIP(hipMemcpyAsync(b.p, src, n * sizeof(double), hipMemcpyHostToDevice, s));
+    };
+    up(pp->E_loc, desc->local_E, n_loc);
+    up(pp->E_h, desc->pair_E_h, n_h);
+    up(pp->E_v, desc->pair_E_v, n_v);
+    up(pp->E_d, desc->kings ? desc->pair_E_d : nullptr, n_x);   // zero tables on a square lattice
+    up(pp->E_a, desc->kings ? desc->pair_E_a : nullptr, n_x);
+    pp->W_loc.ensure(std::max<size_t>(n_loc, 1) * 8); pp->W_h.ensure(std::max<size_t>(n_h, 1) * 8);
+    pp->W_v.ensure(std::max<size_t>(n_v, 1) * 8); pp->W_d.ensure(std::max<size_t>(n_x, 1) * 8);
+    pp->W_a.ensure(std::max<size_t>(n_x, 1) * 8);
+    const size_t ntab = (size_t)R * C + (size_t)R * (C - 1) + (size_t)(R - 1) * C + 2 * (size_t)(R - 1) * (C - 1);
+    DevBuf mins;
+    mins.ensure(std::max<size_t>(ntab, 1) * 8);
+    double *mn = mins.as<double>();
+    size_t off = 0;
+    build_weights(R * C, d, pp->beta, pp->E_loc.as<double>(), pp->W_loc.as<double>(), mn + off, s); off += (size_t)R * C;
+    build_weights(R * (C - 1), (int)dd, pp->beta, pp->E_h.as<double>(), pp->W_h.as<double>(), mn + off, s); off += (size_t)R * (C - 1);
+    build_weights((R - 1) * C, (int)dd, pp->beta, pp->E_v.as<double>(), pp->W_v.as<double>(), mn + off, s); off += (size_t)(R - 1) * C;
+    build_weights((R - 1) * (C - 1), (int)dd, pp->beta, pp->E_d.as<double>(), pp->W_d.as<double>(), mn + off, s); off += (size_t)(R - 1) * (C - 1);
+    build_weights((R - 1) * (C - 1), (int)dd, pp->beta, pp->E_a.as<double>(), pp->W_a.as<double>(), mn + off, s); off += (size_t)(R - 1) * (C - 1);
+    std::vector<double> hm(ntab);
+    if (ntab) SPG_HIP(hipMemcpyAsync(hm.data(), mn, ntab * 8, hipMemcpyDeviceToHost, s));
+    // constant helper tables
+    std::vector<double> ones(dd, 1.0), e0r(dd, 0.0), e0c(dd, 0.0);
+    for (int i = 0; i < d; ++i) { e0r[i] = 1.0; e0c[(size_t)i * d] = 1.0; }
+    up(pp->ones, ones.data(), dd);
+    up(pp->e0row, e0r.data(), dd);
+    up(pp->e0col, e0c.data(), dd);
+    SPG_HIP(hipStreamSynchronize(s));
+    mins.release();
+    double sh = 0.0;
+    for (double v : hm) sh += v;
+    pp->shift = sh;
+  } catch (...) {
+    spg_free_peps(pp);
+    throw;
+  }
+  *out = pp;
+  return SPG_OK;
+  SPG_CATCH
+}
+
+void spg_free_peps(spg_peps_t *pp) {
+  if (!pp) return;
+  for (DevBuf *b : {&pp->E_loc, &pp->E_h, &pp->E_v, &pp->E_d, &pp->E_a, &pp->W_loc, &pp->W_h,
+                    &pp->W_v, &pp->W_d, &pp->W_a, &pp->ones, &pp->e0row, &pp->e0col, &pp->e0vec})
+    b->release();
+  delete pp;
+}
+
+void spg_free_env(spg_env_t *env) {
+  if (!env) return;
+  for (DevBuf *b : {&env->A, &env->lam, &env->cfg[0], &env->cfg[1], &env->score[0],
+                    &env->score[1], &env->energy[0], &env->energy[1], &env->L[0], &env->L[1],
+                    &env->anc[0], &env->anc[1], &env->Rv, &env->cand, &env->sel, &env->keys,
+                    &env->ids, &env->ework, &env->perm, &env->nvalid, &env->tmp, &env->cfg32})
+    b->release();
+  delete env;
+}
+
+static int check_mps_params(const spg_mps_params *p) {
+  if (!p) return fail(SPG_ERR_INVALID, "null mps params");
+  if (p->chi < 1 || p->chi > kMaxChi) return fail(SPG_ERR_UNSUPPORTED, "chi must be in 1..80");
+  if (p->num_sweeps < 1) return fail(SPG_ERR_INVALID, "num_sweeps must be >= 1");
+  if (p->oversample < 0 || p->power_iters < 0 || p->power_iters > 8)
+    return fail(SPG_ERR_INVALID, "oversample >= 0 and power_iters in 0..8 required");
+  if (p->chi + p->oversample > kMaxSketch)
+    return fail(SPG_ERR_UNSUPPORTED, "chi + oversample must be <= 96");
+  if (p->precision != SPG_FP64)
+    return fail(SPG_ERR_UNSUPPORTED, "this precision is not available for the boundary MPS");
+  return SPG_OK;
+}
+
+int spg_boundary_mps(const spg_peps_t *peps, const spg_mps_params *params, void *stream,
+                     spg_env_t **out, double *log_Z_out) {
+  SPG_TRY
+  if (!peps || !out) return fail(SPG_ERR_INVALID, "spg_boundary_mps: null peps or out");
+  int rc = check_mps_params(params);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  spg_env *env = new spg_env();
+  try {
+    env->peps = peps;
+    env->chi = params->chi;
+    env->precision = params->precision;
+    const int R = peps->rows, C = peps->cols, d = peps->d, chi = params->chi;
+    env->dims.assign((size_t)R * (C + 1), 1);
+    env->A.ensure((size_t)R * C * chi * d * chi * sizeof(double));
+    env->lam.ensure((size_t)R * sizeof(double));
+    boundary_mps_fp64(env, params, s);
+    if (log_Z_out) {
+      // log Z = lam_0 + log sum_X A_0[x_0]..A_{C-1}[x_{C-1}] - beta * shift (host, small)
+      std::vector<double> A0((size_t)C * chi * d * chi), lam(R);
+      SPG_HIP(hipMemcpyAsync(A0.data(), env->A.p, A0.size() * 8, hipMemcpyDeviceToHost, s));
+      SPG_HIP(hipMemcpyAsync(lam.data(), env->lam.p, R * 8, hipMemcpyDeviceToHost, s));
+      SPG_HIP(hipStreamSynchronize(s));
+      std::vector<double> v(chi, 0.0), nv(chi);
+      v[0] = 1.0;
+      for (int c = 0; c < C; ++c) {
+        std::fill(nv.begin(), nv.end(), 0.0);
+        const double *T = A0.data() + (size_t)c * chi * d * chi;
+        for (int a = 0; a < chi; ++a)
+          for (int x = 0; x < d; ++x)
+            for (int b = 0; b < chi; ++b) nv[b] += v[a] * T[((size_t)a * d + x) * chi + b];
+        v = nv;
+      }
+      const double lz = lam[0] + std::log(v[0]) - peps->beta * peps->shift;
+      *log_Z_out = lz;
+      if (!std::isfinite(lz)) {
+        *out = env;
+        return fail(SPG_ERR_NONFINITE, "spg_boundary_mps: log Z is not finite");
+      }
+    }
+  } catch (...) {
+    spg_free_env(env);
+    throw;
+  }
+  *out = env;
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_env_info(const spg_env_t *env, int32_t *rows, int32_t *cols, int32_t *d, int32_t *chi,
+                 int32_t *bond_dims) {
+  if (!env) return fail(SPG_ERR_INVALID, "spg_env_info: null env");
+  if (rows) *rows = env->peps->rows;
+  if (cols) *cols = env->peps->cols;
+  if (d) *d = env->peps->d;
+  if (chi) *chi = env->chi;
+  if (bond_dims) std::memcpy(bond_dims, env->dims.data(), env->dims.size() * sizeof(int32_t));
+  return SPG_OK;
+}
+
+int spg_env_export(const spg_env_t *env, double *tensors, double *lam) {
+  SPG_TRY
+  if (!env) return fail(SPG_ERR_INVALID, "spg_env_export: null env");
+  const spg_peps *pp = env->peps;
+  const size_t n = (size_t)pp->rows * pp->cols * env->chi * pp->d * env->chi;
+  if (tensors) SPG_HIP(hipMemcpy(tensors, env->A.p, n * 8, hipMemcpyDeviceToHost));
+  if (lam) SPG_HIP(hipMemcpy(lam, env->lam.p, (size_t)pp->rows * 8, hipMemcpyDeviceToHost));
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_env_import(const spg_peps_t *peps, int32_t chi, const int32_t *bond_dims,
+                   const double *tensors, const double *lam, int32_t precision, void *stream,
+                   spg_env_t **out) {
+  SPG_TRY
+  if (!peps || !bond_dims || !tensors || !out) return fail(SPG_ERR_INVALID, "spg_env_import: null argument");
+  if (chi < 1 || chi > kMaxChi) return fail(SPG_ERR_UNSUPPORTED, "spg_env_import: chi must be in 1..80");
+  if (precision != SPG_FP64) return fail(SPG_ERR_UNSUPPORTED, "spg_env_import: precision");
+  const int R = peps->rows, C = peps->cols, d = peps->d;
+  for (int r = 0; r < R; ++r) {
+    if (bond_dims[r * (C + 1)] != 1 || bond_dims[r * (C + 1) + C] != 1)
+      return fail(SPG_ERR_INVALID, "spg_env_import: boundary bonds must be 1");
+    for (int c = 0; c <= C; ++c)
+      if (bond_dims[r * (C + 1) + c] < 1 || bond_dims[r * (C + 1) + c] > chi)
+        return fail(SPG_ERR_INVALID, "spg_env_import: bond dimension out of range");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  spg_env *env = new spg_env();
+  try {
+    env->peps = peps;
+    env->chi = chi;
+    env->precision = precision;
+    env->dims.assign(bond_dims, bond_dims + (size_t)R * (C + 1));
+    const size_t n = (size_t)R * C * chi * d * chi;
+    env->A.ensure(n * 8);
+    env->lam.ensure((size_t)R * 8);
+    SPG_HIP(hipMemcpyAsync(env->A.p, tensors, n * 8, hipMemcpyHostToDevice, s));
+    if (lam) SPG_HIP(hipMemcpyAsync(env->lam.p, lam, (size_t)R * 8, hipMemcpyHostToDevice, s));
+    SPG_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    spg_free_env(env);
+    throw;
+  }
+  *out = env;
+  return SPG_OK;
+  SPG_CATCH
+}
+
+static void ensure_search(spg_env *env, int M) {
+  const spg_peps *pp = env->peps;
+  const int N = pp->rows * pp->cols, d = pp->d, chi = env->chi, C = pp->cols;
+  const int p2 = pow2_at_least(std::max(M, 1));
+  for (int i = 0; i < 2; ++i) {
+    env->cfg[i].ensure((size_t)M * N);
+    env->score[i].ensure((size_t)M * 8);
+    env->energy[i].ensure((size_t)M * 8);
+    env->L[i].ensure((size_t)M * chi * 8);
+    env->anc[i].ensure((size_t)M * 4);
+  }
+  env->Rv.ensure((size_t)M * (C + 1) * chi * 8);
+  env->cand.ensure((size_t)M * d * 8);
+  env->sel.ensure((size_t)M * 4);
+  env->keys.ensure((size_t)p2 * 8);
+  env->ids.ensure((size_t)p2 * 4);
+  env->ework.ensure((size_t)(M + p2) * 8);
+  env->perm.ensure((size_t)p2 * 4);
+  env->nvalid.ensure(8);
+}
+
+int spg_marginals(const spg_env_t *cenv, int32_t site, int32_t n_beam, const int32_t *beam_cfg,
+                  double *log_cond_out, void *stream) {
+  SPG_TRY
+  if (!cenv || !beam_cfg || !log_cond_out) return fail(SPG_ERR_INVALID, "spg_marginals: null argument");
+  spg_env *env = const_cast<spg_env *>(cenv);
+  const spg_peps *pp = env->peps;
+  const int C = pp->cols, N = pp->rows * C, d = pp->d, chi = env->chi;
+  if (site < 0 || site >= N) return fail(SPG_ERR_INVALID, "spg_marginals: site out of range");
+  if (n_beam < 1) return fail(SPG_ERR_INVALID, "spg_marginals: n_beam must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  const int r = site / C, c = site % C;
+  ensure_search(env, n_beam);
+  env->cfg32.ensure((size_t)n_beam * N);
+  uint8_t *cfg = env->cfg32.as<uint8_t>();
+  cfg_from_i32(n_beam, N, beam_cfg, cfg, s);
+  const SearchTabs t = tabs_of(env);
+  const double *A = env->A.as<double>();
+  const size_t site_sz = (size_t)chi * d * chi;
+  const long rstride = (long)(C + 1) * chi;
+  double *Rv = env->Rv.as<double>();
+  set_e0(n_beam, chi, Rv + (size_t)C * chi, rstride, s);
+  for (int cc = C - 1; cc > c; --cc)
+    right_env_col(t, r, cc, n_beam, cfg, N, A + ((size_t)r * C + cc) * site_sz,
+                  Rv + (size_t)(cc + 1) * chi, Rv + (size_t)cc * chi, rstride, s);
+  double *L = env->L[0].as<double>();
+  int32_t *anc = env->anc[0].as<int32_t>();
+  beam_reset_row(n_beam, chi, L, anc, s);
+  for (int cc = 0; cc < c; ++cc)
+    advance_L(t, r, cc, n_beam, cfg, N, A + ((size_t)r * C + cc) * site_sz, L, nullptr, s);
+  marginals(t, r, c, n_beam, cfg, N, A + ((size_t)r * C + c) * site_sz, L, anc, Rv, rstride,
+            nullptr, log_cond_out, 0, s);
+  (void)d;
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_branch_and_bound(const spg_env_t *cenv, const spg_search_params *prm, int32_t *states_out,
+                         double *energies_out, double *logp_out, int32_t *n_out, void *stream) {
+  SPG_TRY
+  if (!cenv || !prm || !states_out || !energies_out || !logp_out || !n_out)
+    return fail(SPG_ERR_INVALID, "spg_branch_and_bound: null argument");
+  if (prm->max_states < 1 || prm->max_states > 65536)
+    return fail(SPG_ERR_UNSUPPORTED, "spg_branch_and_bound: max_states must be in 1..65536");
+  if (!(prm->cut_off_prob >= 0.0) || prm->cut_off_prob >= 1.0)
+    return fail(SPG_ERR_INVALID, "spg_branch_and_bound: cut_off_prob must be in [0, 1)");
+  spg_env *env = const_cast<spg_env *>(cenv);
+  const spg_peps *pp = env->peps;
+  const int R = pp->rows, C = pp->cols, N = R * C, d = pp->d, chi = env->chi;
+  const int M = prm->max_states;
+  hipStream_t s = (hipStream_t)stream;
+  ensure_search(env, M);
+  const SearchTabs t = tabs_of(env);
+  const double *A = env->A.as<double>();
+  const size_t site_sz = (size_t)chi * d * chi;
+  const long rstride = (long)(C + 1) * chi;
+  double *Rv = env->Rv.as<double>();
+  int cur = 0;
+  long B = 1;
+  fill_zero(env->score[0].as<double>(), 1, s);
+  fill_zero(env->energy[0].as<double>(), 1, s);
+  const double log_cut = (prm->cut_off_prob > 0.0) ? std::log(prm->cut_off_prob) : 0.0;
+  for (int r = 0; r < R; ++r) {
+    const int n_anc = (int)B;
+    beam_reset_row(n_anc, chi, env->L[cur].as<double>(), env->anc[cur].as<int32_t>(), s);
+    set_e0(n_anc, chi, Rv + (size_t)C * chi, rstride, s);
+    for (int c = C - 1; c >= 1; --c)
+      right_env_col(t, r, c, n_anc, env->cfg[cur].as<uint8_t>(), N,
+                    A + ((size_t)r * C + c) * site_sz, Rv + (size_t)(c + 1) * chi,
+                    Rv + (size_t)c * chi, rstride, s);
+    for (int c = 0; c < C; ++c) {
+      const double *Arc = A + ((size_t)r * C + c) * site_sz;
+      marginals(t, r, c, (int)B, env->cfg[cur].as<uint8_t>(), N, Arc, env->L[cur].as<double>(),
+                env->anc[cur].as<int32_t>(), Rv, rstride, env->score[cur].as<double>(),
+                env->cand.as<double>(), 1, s);
+      if (prm->cut_off_prob > 0.0) apply_cutoff((int)(B * d), log_cut, env->cand.as<double>(), s);
+      const long Bn = std::min<long>(M, B * d);
+      select_topm((int)(B * d), M, env->cand.as<double>(), env->sel.as<int32_t>(),
+                  env->keys.as<uint64_t>(), env->ids.as<int32_t>(), s);
+      const int nx = cur ^ 1;
+      beam_update(t, r, c, (int)Bn, env->sel.as<int32_t>(), N, env->cfg[cur].as<uint8_t>(),
+                  env->energy[cur].as<double>(), env->L[cur].as<double>(),
+                  env->anc[cur].as<int32_t>(), env->cand.as<double>(), Arc, c < C - 1,
+                  env->cfg[nx].as<uint8_t>(), env->energy[nx].as<double>(),
+                  env->score[nx].as<double>(), env->L[nx].as<double>(),
+                  env->anc[nx].as<int32_t>(), s);
+      cur = nx;
+      B = Bn;
+    }
+  }
+  final_sort(t, (int)B, N, env->cfg[cur].as<uint8_t>(), env->score[cur].as<double>(), states_out,
+             energies_out, logp_out, env->ework.as<double>(), env->perm.as<int32_t>(),
+             env->nvalid.as<int32_t>(), s);
+  int32_t nv = 0;
+  SPG_HIP(hipMemcpyAsync(&nv, env->nvalid.p, 4, hipMemcpyDeviceToHost, s));
+  SPG_HIP(hipStreamSynchronize(s));
+  *n_out = nv;
+  return SPG_OK;
+  SPG_CATCH
+}
+
+}  // extern "C"

@@ -1,0 +1,363 @@
+// Boundary-MPS contraction kernels (FP64) for one row update of the
+// Boltzmann PEPS: the row transfer operator acts on the previous boundary MPS
+// psi through the row MPO whose site tensor at column c is
+//   W_c[(a,e), x, y] = w_c(x) V_c(x,y) H_{c-1}(a,x) D_{c-1}(a,y) A_{c-1}(x,e),
+// with left bond (a, e) = (x_{c-1}, y_{c-1}) and right bond (x_c, y_c).
+// Tensor layouts (padded to chi on every bond index, row-major):
+//   MPS site      phi[p][x][P]          chi x d x chi
+//   environment   E[p][a][e][q]         chi x d x d x chi   (p: new MPS, q: psi)
+// The small d-index contractions are plain kernels (one thread per output);
+// the bond-index contractions go through the strided batched GEMM.
+#include "spg_internal.h"
+
+namespace spg {
+
+namespace {
+
+inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// phi[p][x][P] = w(x) sum_y V(x,y) psi[p][y][P]
+__global__ void k_init_guess(int d, int chi, int bl, int br, const double *psi, const double *w,
+                             const double *V, double *phi) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)bl * d * br;
+  if (e >= tot) return;
+  const int P = e % br, x = (e / br) % d, p = (int)(e / ((long)br * d));
+  double acc = 0.0;
+  for (int y = 0; y < d; ++y) acc += V[x * d + y] * psi[((long)p * d + y) * chi + P];
+  phi[((long)p * d + x) * chi + P] = w[x] * acc;
+}
+
+// T1[p][a][x][q] = sum_e Al[x][e] EL[p][a][e][q]
+__global__ void k_T1(int d, int chi, int pl, int ql, const double *EL, const double *Al,
+                     double *T1) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)pl * d * d * ql;
+  if (e >= tot) return;
+  const int q = e % ql, x = (e / ql) % d, a = (e / ((long)ql * d)) % d;
+  const int p = (int)(e / ((long)ql * d * d));
+  const double *src = EL + (((long)p * d + a) * d) * chi + q;
+  double acc = 0.0;
+  for (int ee = 0; ee < d; ++ee) acc += Al[x * d + ee] * src[(long)ee * chi];
+  T1[(((long)p * d + a) * d + x) * chi + q] = acc;
+}
+
+// T2[p][x][y][q] = sum_a Hl[a][x] Dl[a][y] T1[p][a][x][q]
+__global__ void k_T2(int d, int chi, int pl, int ql, const double *T1, const double *Hl,
+                     const double *Dl, double *T2) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)pl * d * d * ql;
+  if (e >= tot) return;
+  const int q = e % ql, y = (e / ql) % d, x = (e / ((long)ql * d)) % d;
+  const int p = (int)(e / ((long)ql * d * d));
+  double acc = 0.0;
+  for (int a = 0; a < d; ++a)
+    acc += Hl[a * d + x] * Dl[a * d + y] * T1[(((long)p * d + a) * d + x) * chi + q];
+  T2[(((long)p * d + x) * d + y) * chi + q] = acc;
+}
+
+// T[p][x][y][Q] *= w(x) V(x,y)   (box p < n0, Q < n3)
+__global__ void k_scale_wv(int d, int chi, int n0, int n3, const double *w, const double *V,
+                           double *T) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)n0 * d * d * n3;
+  if (e >= tot) return;
+  const int Q = e % n3, y = (e / n3) % d, x = (e / ((long)n3 * d)) % d;
+  const int p = (int)(e / ((long)n3 * d * d));
+  T[(((long)p * d + x) * d + y) * chi + Q] *= w[x] * V[x * d + y];
+}
+
+// G3[p][x][a][q] = sum_y G2[p][x][y][q] Dl[a][y]
+__global__ void k_G3(int d, int chi, int pl, int ql, const double *G2, const double *Dl,
+                     double *G3) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)pl * d * d * ql;
+  if (e >= tot) return;
+  const int q = e % ql, a = (e / ql) % d, x = (e / ((long)ql * d)) % d;
+  const int p = (int)(e / ((long)ql * d * d));
+  const double *src = G2 + (((long)p * d + x) * d) * chi + q;
+  double acc = 0.0;
+  for (int y = 0; y < d; ++y) acc += Dl[a * d + y] * src[(long)y * chi];
+  G3[(((long)p * d + x) * d + a) * chi + q] = acc;
+}
+
+// ER[p][a][e][q] = sum_x G3[p][x][a][q] Hl[a][x] Al[x][e]
+__global__ void k_ERfin(int d, int chi, int pl, int ql, const double *G3, const double *Hl,
+                        const double *Al, double *ER) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)pl * d * d * ql;
+  if (e >= tot) return;
+  const int q = e % ql, ee = (e / ql) % d, a = (e / ((long)ql * d)) % d;
+  const int p = (int)(e / ((long)ql * d * d));
+  double acc = 0.0;
+  for (int x = 0; x < d; ++x)
+    acc += Hl[a * d + x] * Al[x * d + ee] * G3[(((long)p * d + x) * d + a) * chi + q];
+  ER[(((long)p * d + a) * d + ee) * chi + q] = acc;
+}
+
+// P2[p][x][z][Q] = sum_y P[p][x][y][Q] A1[z][y]
+__global__ void k_P2(int d, int chi, int pl, int nq, const double *P, const double *A1,
+                     double *P2) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)pl * d * d * nq;
+  if (e >= tot) return;
+  const int Q = e % nq, z = (e / nq) % d, x = (e / ((long)nq * d)) % d;
+  const int p = (int)(e / ((long)nq * d * d));
+  const double *src = P + (((long)p * d + x) * d) * chi + Q;
+  double acc = 0.0;
+  for (int y = 0; y < d; ++y) acc += A1[z * d + y] * src[(long)y * chi];
+  P2[(((long)p * d + x) * d + z) * chi + Q] = acc;
+}
+
+// Q2[Q][x][z][P] = sum_v Qr[Q][z][v][P] D1[x][v]
+__global__ void k_Q2(int d, int chi, int nq, int pr, const double *Qr, const double *D1,
+                     double *Q2) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)nq * d * d * pr;
+  if (e >= tot) return;
+  const int P = e % pr, z = (e / pr) % d, x = (e / ((long)pr * d)) % d;
+  const int Q = (int)(e / ((long)pr * d * d));
+  const double *src = Qr + (((long)Q * d + z) * d) * chi + P;
+  double acc = 0.0;
+  for (int v = 0; v < d; ++v) acc += D1[x * d + v] * src[(long)v * chi];
+  Q2[(((long)Q * d + x) * d + z) * chi + P] = acc;
+}
+
+// B[p][x][z][P] (compact) *= H1[x][z]
+__global__ void k_scale_H(int d, int pl, int pr, const double *H1, double *B) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)pl * d * d * pr;
+  if (e >= tot) return;
+  const int z = (e / pr) % d, x = (e / ((long)pr * d)) % d;
+  B[e] *= H1[x * d + z];
+}
+
+__global__ void k_unpack_right(int d, int chi, int nk, int pr, const double *src, long sk,
+                               long sj, double *dst) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)nk * d * pr;
+  if (e >= tot) return;
+  const int P = e % pr, z = (e / pr) % d, k = (int)(e / ((long)pr * d));
+  dst[((long)k * d + z) * chi + P] = src[k * sk + ((long)z * pr + P) * sj];
+}
+
+// tmp[p][x][k] = sum_q phi[p][x][q] R[k][q]  (R row-major k x bl), then copy back
+__global__ void k_lq_fold(int d, int chi, int pl, int bl, int kk, const double *R,
+                          const double *phi, double *tmp) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)pl * d * kk;
+  if (e >= tot) return;
+  const int k = e % kk;
+  const long px = e / kk;
+  double acc = 0.0;
+  for (int q = 0; q < bl; ++q) acc += phi[px * chi + q] * R[(long)k * bl + q];
+  tmp[px * chi + k] = acc;
+}
+
+__global__ void k_pack_right(int d, int chi, int nk, int pr, const double *src, double *dst) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long tot = (long)nk * d * pr;
+  if (e >= tot) return;
+  const int P = e % pr, z = (e / pr) % d, k = (int)(e / ((long)pr * d));
+  dst[e] = src[((long)k * d + z) * chi + P];
+}
+
+// w = exp(-beta (E - min E)) per table of `tsize` entries, one block per table.
+__global__ __launch_bounds__(256) void k_weights(int ntab, int tsize, double beta,
+                                                 const double *E, double *W, double *mins) {
+  __shared__ double red[256];
+  const int t = blockIdx.x;
+  if (t >= ntab) return;
+  const double *e = E + (long)t * tsize;
+  double m = INFINITY;
+  for (int i = threadIdx.x; i < tsize; i += blockDim.x) m = fmin(m, e[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const double mn = red[0];
+  for (int i = threadIdx.x; i < tsize; i += blockDim.x)
+    W[(long)t * tsize + i] = exp(-beta * (e[i] - mn));
+  if (threadIdx.x == 0) mins[t] = mn;
+}
+
+__global__ void k_set_e0(int n, int chi, double *p, long stride) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)n * chi) return;
+  const int j = (int)(e / chi), i = (int)(e % chi);
+  p[j * stride + i] = (i == 0) ? 1.0 : 0.0;
+}
+
+__global__ void k_add_logs(double *logs, int out, int a, int b, int c) {
+  logs[out] = (a >= 0 ? logs[a] : 0.0) + (b >= 0 ? logs[b] : 0.0) + (c >= 0 ? logs[c] : 0.0);
+}
+
+}  // namespace
+
+void init_guess(int d, int chi, int bl, int br, const double *psi, const RowFactors &f,
+                double *phi, hipStream_t s) {
+  const long tot = (long)bl * d * br;
+  hipLaunchKernelGGL(k_init_guess, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, bl, br, psi,
+                     f.w, f.V, phi);
+  SPG_CHECK_LAUNCH();
+}
+
+void left_part(int d, int chi, int pl, int ql, int qr, const double *EL, const double *psi,
+               const RowFactors &f, double *T1, double *P, hipStream_t s) {
+  const long tot = (long)pl * d * d * ql;
+  hipLaunchKernelGGL(k_T1, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, pl, ql, EL, f.Al, T1);
+  SPG_CHECK_LAUNCH();
+  // T2 written into P (the GEMM below reads T2 and writes P in place would alias),
+  // so T2 goes to the second half of T1's buffer.
+  double *T2 = T1 + (long)chi * d * d * chi;
+  hipLaunchKernelGGL(k_T2, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, pl, ql, T1, f.Hl,
+                     f.Dl, T2);
+  SPG_CHECK_LAUNCH();
+  // P[p][x][y][Q] = sum_q T2[p][x][y][q] psi[q][y][Q]   (batch y; rows (p,x))
+  GemmDesc g{};
+  g.M = pl * d; g.N = qr; g.K = ql; g.nb1 = d; g.nb2 = 1;
+  g.A = T2; g.a_i = (long)d * chi; g.a_k = 1; g.a_b1 = chi; g.a_b2 = 0;
+  g.B = psi; g.b_k = (long)d * chi; g.b_j = 1; g.b_b1 = chi; g.b_b2 = 0;
+  g.C = P; g.c_i = (long)d * chi; g.c_j = 1; g.c_b1 = chi; g.c_b2 = 0;
+  g.alpha = 1.0; g.beta = 0.0;
+  gemm_f64(g, s);
+  const long tot2 = (long)pl * d * d * qr;
+  hipLaunchKernelGGL(k_scale_wv, dim3(nblk(tot2, 256)), dim3(256), 0, s, d, chi, pl, qr, f.w,
+                     f.V, P);
+  SPG_CHECK_LAUNCH();
+}
+
+void env_left(int d, int chi, int pl, int pr, int qr, const double *phi, const double *P,
+              double *ELn, hipStream_t s) {
+  // ELn[P][x][y][Q] = sum_p phi[p][x][P] P[p][x][y][Q]   (batch x; cols (y,Q) over d*chi)
+  GemmDesc g{};
+  g.M = pr; g.N = d * chi; g.K = pl; g.nb1 = d; g.nb2 = 1;
+  g.A = phi; g.a_i = 1; g.a_k = (long)d * chi; g.a_b1 = chi; g.a_b2 = 0;
+  g.B = P; g.b_k = (long)d * d * chi; g.b_j = 1; g.b_b1 = (long)d * chi; g.b_b2 = 0;
+  g.C = ELn; g.c_i = (long)d * d * chi; g.c_j = 1; g.c_b1 = (long)d * chi; g.c_b2 = 0;
+  g.alpha = 1.0; g.beta = 0.0;
+  (void)qr;
+  gemm_f64(g, s);
+}
+
+void env_right(int d, int chi, int pl, int pr, int ql, int qr, const double *phi,
+               const double *psi, const double *ER, const RowFactors &f, double *G1,
+               double *G2, double *ERn, hipStream_t s) {
+  // G1[p][x][y][Q] = sum_P phi[p][x][P] ER[P][x][y][Q]   (batch x; cols (y,Q))
+  GemmDesc g{};
+  g.M = pl; g.N = d * chi; g.K = pr; g.nb1 = d; g.nb2 = 1;
+  g.A = phi; g.a_i = (long)d * chi; g.a_k = 1; g.a_b1 = chi; g.a_b2 = 0;
+  g.B = ER; g.b_k = (long)d * d * chi; g.b_j = 1; g.b_b1 = (long)d * chi; g.b_b2 = 0;
+  g.C = G1; g.c_i = (long)d * d * chi; g.c_j = 1; g.c_b1 = (long)d * chi; g.c_b2 = 0;
+  g.alpha = 1.0; g.beta = 0.0;
+  gemm_f64(g, s);
+  (void)qr;
+  // G2[p][x][y][q] = sum_Q G1[p][x][y][Q] psi[q][y][Q]   (batch y; rows (p,x))
+  GemmDesc h{};
+  h.M = pl * d; h.N = ql; h.K = qr; h.nb1 = d; h.nb2 = 1;
+  h.A = G1; h.a_i = (long)d * chi; h.a_k = 1; h.a_b1 = chi; h.a_b2 = 0;
+  h.B = psi; h.b_k = 1; h.b_j = (long)d * chi; h.b_b1 = chi; h.b_b2 = 0;
+  h.C = G2; h.c_i = (long)d * chi; h.c_j = 1; h.c_b1 = chi; h.c_b2 = 0;
+  h.alpha = 1.0; h.beta = 0.0;
+  gemm_f64(h, s);
+  const long tot = (long)pl * d * d * ql;
+  hipLaunchKernelGGL(k_scale_wv, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, pl, ql, f.w,
+                     f.V, G2);
+  SPG_CHECK_LAUNCH();
+  double *G3 = G1;  // G1 no longer needed
+  hipLaunchKernelGGL(k_G3, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, pl, ql, G2, f.Dl, G3);
+  SPG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_ERfin, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, pl, ql, G3, f.Hl,
+                     f.Al, ERn);
+  SPG_CHECK_LAUNCH();
+}
+
+void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, const double *EL,
+                    const double *ER, const double *psi0, const double *psi1,
+                    const RowFactors &f0, const RowFactors &f1, double *T1, double *P,
+                    double *Qr, double *P2, double *Q2, double *B, hipStream_t s) {
+  // P[p][x][y][Q] : left part through column c (Q = psi bond between c and c+1, qm)
+  left_part(d, chi, pl, ql, qm, EL, psi0, f0, T1, P, s);
+  // Qr[q][x][y][P] = w1(x)V1(x,y) sum_Q psi1[q][y][Q] ER[P][x][y][Q]   (batch (x,y))
+  GemmDesc g{};
+  g.M = qm; g.N = pr; g.K = qr; g.nb1 = d; g.nb2 = d;
+  g.A = psi1; g.a_i = (long)d * chi; g.a_k = 1; g.a_b1 = 0; g.a_b2 = chi;
+  g.B = ER; g.b_k = 1; g.b_j = (long)d * d * chi; g.b_b1 = (long)d * chi; g.b_b2 = chi;
+  g.C = Qr; g.c_i = (long)d * d * chi; g.c_j = 1; g.c_b1 = (long)d * chi; g.c_b2 = chi;
+  g.alpha = 1.0; g.beta = 0.0;
+  gemm_f64(g, s);
+  const long totq = (long)qm * d * d * pr;
+  hipLaunchKernelGGL(k_scale_wv, dim3(nblk(totq, 256)), dim3(256), 0, s, d, chi, qm, pr, f1.w,
+                     f1.V, Qr);
+  SPG_CHECK_LAUNCH();
+  const long totp = (long)pl * d * d * qm;
+  hipLaunchKernelGGL(k_P2, dim3(nblk(totp, 256)), dim3(256), 0, s, d, chi, pl, qm, P, f1.Al, P2);
+  SPG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_Q2, dim3(nblk(totq, 256)), dim3(256), 0, s, d, chi, qm, pr, Qr, f1.Dl,
+                     Q2);
+  SPG_CHECK_LAUNCH();
+  // B[p][x][z][P] = sum_Q P2[p][x][z][Q] Q2[Q][x][z][P]   (batch (x,z)), compact output
+  GemmDesc h{};
+  h.M = pl; h.N = pr; h.K = qm; h.nb1 = d; h.nb2 = d;
+  h.A = P2; h.a_i = (long)d * d * chi; h.a_k = 1; h.a_b1 = (long)d * chi; h.a_b2 = chi;
+  h.B = Q2; h.b_k = (long)d * d * chi; h.b_j = 1; h.b_b1 = (long)d * chi; h.b_b2 = chi;
+  h.C = B; h.c_i = (long)d * d * pr; h.c_j = 1; h.c_b1 = (long)d * pr; h.c_b2 = pr;
+  h.alpha = 1.0; h.beta = 0.0;
+  gemm_f64(h, s);
+  const long totb = (long)pl * d * d * pr;
+  hipLaunchKernelGGL(k_scale_H, dim3(nblk(totb, 256)), dim3(256), 0, s, d, pl, pr, f1.Hl, B);
+  SPG_CHECK_LAUNCH();
+}
+
+void unpack_right(int d, int chi, int nk, int pr, const double *src, long sk, long sj,
+                  double *dst, hipStream_t s) {
+  const long tot = (long)nk * d * pr;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_unpack_right, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, nk, pr, src,
+                     sk, sj, dst);
+  SPG_CHECK_LAUNCH();
+}
+
+void lq_fold(int d, int chi, int bl, int k, const double *R, double *phi_prev, double *tmp,
+             hipStream_t s) {
+  // phi_prev has left dim pl = chi rows at most; fold over all padded rows (zeros stay zero)
+  const int pl = chi;
+  const long tot = (long)pl * d * k;
+  fill_zero(tmp, (size_t)chi * d * chi, s);
+  hipLaunchKernelGGL(k_lq_fold, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, pl, bl, k, R,
+                     phi_prev, tmp);
+  SPG_CHECK_LAUNCH();
+  SPG_HIP(hipMemcpyAsync(phi_prev, tmp, sizeof(double) * chi * d * chi, hipMemcpyDeviceToDevice,
+                         s));
+}
+
+void pack_right(int d, int chi, int nk, int pr, const double *src, double *dst, hipStream_t s) {
+  const long tot = (long)nk * d * pr;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_pack_right, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, nk, pr, src,
+                     dst);
+  SPG_CHECK_LAUNCH();
+}
+
+void build_weights(int ntab, int tsize, double beta, const double *E, double *W, double *mins,
+                   hipStream_t s) {
+  if (ntab <= 0) return;
+  hipLaunchKernelGGL(k_weights, dim3(ntab), dim3(256), 0, s, ntab, tsize, beta, E, W, mins);
+  SPG_CHECK_LAUNCH();
+}
+
+void set_e0(int n, int chi, double *p, long stride, hipStream_t s) {
+  const long tot = (long)n * chi;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_set_e0, dim3(nblk(tot, 256)), dim3(256), 0, s, n, chi, p, stride);
+  SPG_CHECK_LAUNCH();
+}
+
+void add_logs(double *logs, int out, int a, int b, int c, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_logs, dim3(1), dim3(1), 0, s, logs, out, a, b, c);
+  SPG_CHECK_LAUNCH();
+}
+
+}  // namespace spg

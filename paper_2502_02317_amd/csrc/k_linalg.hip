@@ -1,0 +1,340 @@
+// Dense FP64 linear algebra for the boundary-MPS compression on gfx950:
+// strided batched GEMM, Householder QR, one-sided Jacobi SVD of the small
+// projected matrix, the SplitMix64 sketch and box normalisation.
+#include <cmath>
+
+#include "spg_internal.h"
+
+namespace spg {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum; every thread receives the result.  `red` holds >= 16 doubles.
+__device__ double block_sum(double v, double *red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t += red[w];
+  return t;
+}
+
+// ---------------------------------------------------------------- GEMM
+// 64x64 output tile per 256-thread workgroup, K staged through LDS in steps of
+// 16; each thread owns a 4x4 sub-tile (rows ty+16i, cols tx+16j).
+__global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
+  const int b1 = blockIdx.z / g.nb2, b2 = blockIdx.z % g.nb2;
+  const double *A = g.A + b1 * g.a_b1 + b2 * g.a_b2;
+  const double *B = g.B + b1 * g.b_b1 + b2 * g.b_b2;
+  double *C = g.C + b1 * g.c_b1 + b2 * g.c_b2;
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int r = e >> 4, kk = e & 15;
+      const int gi = i0 + r, gk = k0 + kk;
+      As[kk][r] = (gi < g.M && gk < g.K) ? A[gi * g.a_i + gk * g.a_k] : 0.0;
+      const int kb = e >> 6, cb = e & 63;
+      const int gkb = k0 + kb, gj = j0 + cb;
+      Bs[kb][cb] = (gkb < g.K && gj < g.N) ? B[gkb * g.b_k + gj * g.b_j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gi = i0 + ty + 16 * i;
+    if (gi >= g.M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gj = j0 + tx + 16 * j;
+      if (gj >= g.N) continue;
+      double *cp = C + gi * g.c_i + gj * g.c_j;
+      const double v = g.alpha * acc[i][j];
+      *cp = (g.beta != 0.0) ? v + g.beta * (*cp) : v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- QR
+// Householder QR in one workgroup (LAPACK dgeqrf/dorgqr conventions:
+// H_j = I - tau_j v_j v_j^T, v_j[j] = 1).  The matrix is copied to a
+// column-major workspace; Q is formed by backward accumulation.
+__global__ __launch_bounds__(1024) void k_qr(int m, int n, const double *X, long xr, long xc,
+                                            double *Qo, long qr, long qc, double *R,
+                                            double *work) {
+  double *W = work;                      // m x n column-major (v below diagonal, R above)
+  double *Qw = work + (size_t)m * n;     // m x n column-major
+  double *tau = work + 2 * (size_t)m * n;
+  __shared__ double red[16];
+  __shared__ double sh_tau, sh_scale, sh_beta;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  const size_t mn = (size_t)m * n;
+  for (size_t e = tid; e < mn; e += blockDim.x) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    W[e] = X[i * xr + j * xc];
+    Qw[e] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double *col = W + (size_t)j * m;
+    double loc = 0.0;
+    for (int i = j + 1 + tid; i < m; i += blockDim.x) loc += col[i] * col[i];
+    const double sig = block_sum(loc, red);
+    if (tid == 0) {
+      const double alpha = col[j];
+      if (sig == 0.0) {
+        sh_tau = 0.0; sh_scale = 0.0; sh_beta = alpha;
+      } else {
+        const double nrm = sqrt(alpha * alpha + sig);
+        const double beta = (alpha >= 0.0) ? -nrm : nrm;
+        sh_tau = (beta - alpha) / beta;
+        sh_scale = 1.0 / (alpha - beta);
+        sh_beta = beta;
+      }
+    }
+    __syncthreads();
+    const double tj = sh_tau, sc = sh_scale;
+    if (tj != 0.0)
+      for (int i = j + 1 + tid; i < m; i += blockDim.x) col[i] *= sc;
+    __syncthreads();
+    if (tj != 0.0) {
+      for (int k = j + 1 + wid; k < n; k += nw) {
+        double *ck = W + (size_t)k * m;
+        double dot = (lane == 0) ? ck[j] : 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) dot += col[i] * ck[i];
+        dot = wave_sum(dot);
+        const double f = tj * dot;
+        if (lane == 0) ck[j] -= f;
+        for (int i = j + 1 + lane; i < m; i += 64) ck[i] -= f * col[i];
+      }
+    }
+    if (tid == 0) {
+      col[j] = sh_beta;
+      tau[j] = tj;
+    }
+    __syncthreads();
+  }
+  if (R != nullptr)
+    for (int e = tid; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e % n;
+      R[e] = (i <= j) ? W[(size_t)j * m + i] : 0.0;
+    }
+  // Q = H_0 H_1 ... H_{n-1} [I; 0]
+  for (int j = n - 1; j >= 0; --j) {
+    const double tj = tau[j];
+    if (tj == 0.0) continue;
+    const double *v = W + (size_t)j * m;
+    for (int k = j + wid; k < n; k += nw) {
+      double *qk = Qw + (size_t)k * m;
+      double dot = (lane == 0) ? qk[j] : 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) dot += v[i] * qk[i];
+      dot = wave_sum(dot);
+      const double f = tj * dot;
+      if (lane == 0) qk[j] -= f;
+      for (int i = j + 1 + lane; i < m; i += 64) qk[i] -= f * v[i];
+    }
+    __syncthreads();
+  }
+  for (size_t e = tid; e < mn; e += blockDim.x) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    Qo[i * qr + j * qc] = Qw[e];
+  }
+}
+
+// ---------------------------------------------------------------- Jacobi SVD
+// One-sided (Hestenes) Jacobi on the columns of an l x l matrix held in LDS,
+// round-robin pair ordering, one wavefront per column pair.
+__global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double *Vo,
+                                                double *sig) {
+  __shared__ double W[kMaxSketch * kMaxSketch];
+  __shared__ double V[kMaxSketch * kMaxSketch];
+  __shared__ double nrm[kMaxSketch];
+  __shared__ int rotated;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  for (int e = tid; e < l * l; e += blockDim.x) {
+    const int i = e / l, j = e % l;          // Rm row-major; W, V column-major
+    W[j * l + i] = Rm[e];
+    V[j * l + i] = (i == j) ? 1.0 : 0.0;
+  }
+  const int le = (l + 1) & ~1;
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int t = 0; t < le - 1; ++t) {
+      for (int k = wid; k < le / 2; k += nw) {
+        int p, q;
+        if (k == 0) { p = t; q = le - 1; }
+        else { p = (t + k) % (le - 1); q = (t - k + le - 1) % (le - 1); }
+        if (p > q) { const int tmp = p; p = q; q = tmp; }
+        if (q >= l) continue;
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int r = lane; r < l; r += 64) {
+          const double x = W[p * l + r], y = W[q * l + r];
+          a += x * x; b += y * y; g += x * y;
+        }
+        a = wave_sum(a); b = wave_sum(b); g = wave_sum(g);
+        if (a > 0.0 && b > 0.0 && fabs(g) > 1e-15 * sqrt(a * b)) {
+          const double zeta = (b - a) / (2.0 * g);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          for (int r = lane; r < l; r += 64) {
+            const double x = W[p * l + r], y = W[q * l + r];
+            W[p * l + r] = cs * x - sn * y;
+            W[q * l + r] = sn * x + cs * y;
+            const double vx = V[p * l + r], vy = V[q * l + r];
+            V[p * l + r] = cs * vx - sn * vy;
+            V[q * l + r] = sn * vx + cs * vy;
+          }
+          if (lane == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (rotated == 0) break;
+    __syncthreads();
+  }
+  for (int j = wid; j < l; j += nw) {
+    double a = 0.0;
+    for (int r = lane; r < l; r += 64) a += W[j * l + r] * W[j * l + r];
+    a = wave_sum(a);
+    if (lane == 0) nrm[j] = sqrt(a);
+  }
+  __syncthreads();
+  for (int j = tid; j < l; j += blockDim.x) {
+    int rank = 0;
+    for (int i = 0; i < l; ++i)
+      rank += (nrm[i] > nrm[j]) || (nrm[i] == nrm[j] && i < j);
+    sig[rank] = nrm[j];
+    for (int r = 0; r < l; ++r) Vo[r * l + rank] = V[j * l + r];
+  }
+}
+
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t idx) {
+  uint64_t z = seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_sketch(int n, int l, double *Om) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)n * l) return;
+  const long i = e / l, j = e % l;
+  const uint64_t z = splitmix64_at(0x5EED5EED12345678ull, (uint64_t)(i * 1024 + j));
+  Om[e] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+}
+
+__global__ __launch_bounds__(1024) void k_normalize_box(double *T, int n0, int n1, int n2,
+                                                       int n3, long s0, long s1, long s2,
+                                                       long s3, double *logs, int out,
+                                                       int in) {
+  __shared__ double red[16];
+  const long tot = (long)n0 * n1 * n2 * n3;
+  double acc = 0.0;
+  for (long e = threadIdx.x; e < tot; e += blockDim.x) {
+    long r = e;
+    const int i3 = r % n3; r /= n3;
+    const int i2 = r % n2; r /= n2;
+    const int i1 = r % n1; const int i0 = (int)(r / n1);
+    const double v = T[i0 * s0 + i1 * s1 + i2 * s2 + i3 * s3];
+    acc += v * v;
+  }
+  const double ss = block_sum(acc, red);
+  const double nr = sqrt(ss);
+  const double inv = (nr > 0.0) ? 1.0 / nr : 1.0;
+  for (long e = threadIdx.x; e < tot; e += blockDim.x) {
+    long r = e;
+    const int i3 = r % n3; r /= n3;
+    const int i2 = r % n2; r /= n2;
+    const int i1 = r % n1; const int i0 = (int)(r / n1);
+    T[i0 * s0 + i1 * s1 + i2 * s2 + i3 * s3] *= inv;
+  }
+  if (threadIdx.x == 0) logs[out] = (in >= 0 ? logs[in] : 0.0) + (nr > 0.0 ? log(nr) : 0.0);
+}
+
+__global__ void k_fill_zero(double *p, size_t n) {
+  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (e < n) p[e] = 0.0;
+}
+
+}  // namespace
+
+void gemm_f64(const GemmDesc &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
+  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.nb1 * g.nb2);
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+  SPG_CHECK_LAUNCH();
+}
+
+void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr, long qc,
+            double *R, double *work, hipStream_t s) {
+  if (m <= 0 || n <= 0) return;
+  if (m < n) {
+    set_error("qr_f64: needs rows >= columns");
+    throw Fail{SPG_ERR_INVALID};
+  }
+  hipLaunchKernelGGL(k_qr, dim3(1), dim3(1024), 0, s, m, n, X, xr, xc, Q, qr, qc, R, work);
+  SPG_CHECK_LAUNCH();
+}
+
+void jacobi_svd_f64(int l, const double *Rm, double *V, double *sig, hipStream_t s) {
+  if (l <= 0) return;
+  if (l > kMaxSketch) {
+    set_error("jacobi_svd_f64: size above the LDS limit");
+    throw Fail{SPG_ERR_UNSUPPORTED};
+  }
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, l, Rm, V, sig);
+  SPG_CHECK_LAUNCH();
+}
+
+void fill_sketch(int n, int l, double *Om, hipStream_t s) {
+  const long tot = (long)n * l;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_sketch, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, l, Om);
+  SPG_CHECK_LAUNCH();
+}
+
+void normalize_box(double *T, int n0, int n1, int n2, int n3, long s0, long s1, long s2,
+                   long s3, double *logs, int out, int in, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalize_box, dim3(1), dim3(1024), 0, s, T, n0, n1, n2, n3, s0, s1, s2,
+                     s3, logs, out, in);
+  SPG_CHECK_LAUNCH();
+}
+
+void fill_zero(double *p, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  SPG_CHECK_LAUNCH();
+}
+
+}  // namespace spg

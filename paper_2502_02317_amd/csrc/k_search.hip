@@ -1,0 +1,537 @@
+// Branch-and-bound search kernels (FP64 path).
+//
+// The beam holds, per partial configuration b: its states (uint8 per site),
+// accumulated log-probability score, FP64 energy of the fixed variables, the
+// left environment vector L^b of its current row (max-normalised) and the
+// index of its row-start ancestor, whose right environments R^a_c are shared
+// by all its descendants in the row.
+//
+// Conditional at site (r,c) for parent b and state s:
+//   q(b,s) = g^b_c(s) * L^b A_{r,c}[:, s, :] R^{a(b)}_{c+1},
+// g^b_c(s) = the Boltzmann weights of the couplings between s and the fixed
+// row r-1 (V from (r-1,c), D from (r-1,c-1), A from (r-1,c+1)).
+#include <cfloat>
+#include <climits>
+
+#include "spg_internal.h"
+
+namespace spg {
+
+namespace {
+
+inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// g^b_c(s): couplings of x_{r,c} = s to the fixed row above (1 for r = 0).
+__device__ __forceinline__ double field(const SearchTabs &t, int r, int c, const uint8_t *cb,
+                                        int s) {
+  if (r == 0) return 1.0;
+  const int C = t.cols, d = t.d;
+  const uint8_t *up = cb + (r - 1) * C;
+  const long dd = (long)d * d;
+  double g = t.W_v[((long)(r - 1) * C + c) * dd + up[c] * d + s];
+  if (c > 0) g *= t.W_d[((long)(r - 1) * (C - 1) + (c - 1)) * dd + up[c - 1] * d + s];
+  if (c < C - 1) g *= t.W_a[((long)(r - 1) * (C - 1) + c) * dd + up[c + 1] * d + s];
+  return g;
+}
+
+// Energy added by x_{r,c} = s: the Eq. (1) terms that close at this site.
+__device__ __forceinline__ double delta_energy(const SearchTabs &t, int r, int c,
+                                               const uint8_t *cb, int s) {
+  const int C = t.cols, d = t.d;
+  const long dd = (long)d * d;
+  double e = t.E_loc[((long)r * C + c) * d + s];
+  if (c > 0) e += t.E_h[((long)r * (C - 1) + (c - 1)) * dd + cb[r * C + c - 1] * d + s];
+  if (r > 0) {
+    const uint8_t *up = cb + (r - 1) * C;
+    e += t.E_v[((long)(r - 1) * C + c) * dd + up[c] * d + s];
+    if (c > 0) e += t.E_d[((long)(r - 1) * (C - 1) + (c - 1)) * dd + up[c - 1] * d + s];
+    if (c < C - 1) e += t.E_a[((long)(r - 1) * (C - 1) + c) * dd + up[c + 1] * d + s];
+  }
+  return e;
+}
+
+constexpr int kWaves = 4;   // wavefronts (work items) per 256-thread block
+
+// R^a_c[alpha] = sum_s g^a_c(s) sum_alpha' A[alpha][s][alpha'] R^a_{c+1}[alpha'], max-normalised
+__global__ __launch_bounds__(256) void k_right_env(SearchTabs t, int r, int c, int n_anc,
+                                                   const uint8_t *cfg, int N, const double *A,
+                                                   const double *Rnext, double *Rout,
+                                                   long rstride) {
+  __shared__ double Rs[kWaves][kMaxChi];
+  __shared__ double gs[kWaves][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int a0 = blockIdx.x * kWaves + w;
+  const bool valid = a0 < n_anc;
+  const int a = valid ? a0 : 0;
+  const int chi = t.chi, d = t.d;
+  const uint8_t *cb = cfg + (long)a * N;
+  if (valid) {
+    for (int i = lane; i < chi; i += 64) Rs[w][i] = Rnext[a * rstride + i];
+    for (int s = lane; s < d; s += 64) gs[w][s] = field(t, r, c, cb, s);
+  }
+  __syncthreads();
+  if (!valid) return;
+  double v[2] = {0.0, 0.0};
+  for (int h = 0; h < 2; ++h) {
+    const int al = lane + 64 * h;
+    if (al >= chi) continue;
+    double acc = 0.0;
+    for (int s = 0; s < d; ++s) {
+      const double *row = A + ((long)al * d + s) * chi;
+      double u = 0.0;
+      for (int b = 0; b < chi; ++b) u += row[b] * Rs[w][b];
+      acc += gs[w][s] * u;
+    }
+    v[h] = acc;
+  }
+  const double m = wave_max(fmax(fabs(v[0]), fabs(v[1])));
+  const double inv = (m > 0.0) ? 1.0 / m : 1.0;
+  for (int h = 0; h < 2; ++h) {
+    const int al = lane + 64 * h;
+    if (al < chi) Rout[a * rstride + al] = v[h] * inv;
+  }
+}
+
+// out[b*d + s] = (add_score ? score[b] : 0) + log p(s | b)
+__global__ __launch_bounds__(256) void k_marginals(SearchTabs t, int r, int c, int n_beam,
+                                                   const uint8_t *cfg, int N, const double *A,
+                                                   const double *L, const int32_t *anc,
+                                                   const double *Rv, long rstride,
+                                                   const double *score, double *out,
+                                                   int add_score) {
+  __shared__ double Ls[kWaves][kMaxChi];
+  __shared__ double Rs[kWaves][kMaxChi];
+  __shared__ double qs[kWaves][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b0 = blockIdx.x * kWaves + w;
+  const bool valid = b0 < n_beam;
+  const int b = valid ? b0 : 0;
+  const int chi = t.chi, d = t.d;
+  const double *Rn = Rv + (long)anc[b] * rstride + (long)(c + 1) * chi;
+  if (valid)
+    for (int i = lane; i < chi; i += 64) {
+      Ls[w][i] = L[(long)b * chi + i];
+      Rs[w][i] = Rn[i];
+    }
+  __syncthreads();
+  if (!valid) return;
+  const uint8_t *cb = cfg + (long)b * N;
+  double part = 0.0;
+  for (int s = lane; s < d; s += 64) {
+    double acc = 0.0;
+    for (int al = 0; al < chi; ++al) {
+      const double la = Ls[w][al];
+      if (la == 0.0) continue;
+      const double *row = A + ((long)al * d + s) * chi;
+      double u = 0.0;
+      for (int bb = 0; bb < chi; ++bb) u += row[bb] * Rs[w][bb];
+      acc += la * u;
+    }
+    double q = field(t, r, c, cb, s) * acc;
+    q = (q > 0.0) ? q : 0.0;               // negative q (truncation error) = probability 0
+    qs[w][s] = q;
+    part += q;
+  }
+  const double tot = wave_sum(part);
+  const double base = add_score ? score[b] : 0.0;
+  const double ltot = log(tot);
+  for (int s = lane; s < d; s += 64) {
+    const double q = qs[w][s];
+    double lp = (q > 0.0 && tot > 0.0) ? log(q) - ltot : -INFINITY;
+    if (!(lp == lp)) lp = -INFINITY;
+    out[(long)b * d + s] = base + lp;
+  }
+}
+
+// Key for ascending sort = descending score; NaN sorts with -inf.
+__device__ __forceinline__ uint64_t desc_key(double v) {
+  if (!(v == v)) v = -INFINITY;
+  uint64_t u = __double_as_longlong(v);
+  const uint64_t sign = 0x8000000000000000ull;
+  u = (u & sign) ? ~u : (u | sign);   // ascending in v
+  return ~u;                          // ascending in -v
+}
+__device__ __forceinline__ uint64_t asc_key(double v) {
+  if (!(v == v)) v = INFINITY;
+  uint64_t u = __double_as_longlong(v);
+  const uint64_t sign = 0x8000000000000000ull;
+  return (u & sign) ? ~u : (u | sign);
+}
+
+// Block-wide exclusive scan of 0/1 flags (blockDim = 1024); returns the prefix
+// and writes the block total to *total.
+__device__ int block_excl_scan(int f, int *wsum, int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const unsigned long long mask = __ballot(f);
+  const int pre = __popcll(mask & ((1ull << lane) - 1ull));
+  __syncthreads();
+  if (lane == 0) wsum[w] = __popcll(mask);
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    if (i < w) off += wsum[i];
+    tot += wsum[i];
+  }
+  *total = tot;
+  return off + pre;
+}
+
+// Sort (key, id) pairs ascending in global memory with one workgroup (bitonic).
+__device__ void bitonic_sort_global(uint64_t *keys, int32_t *ids, int n_pow2) {
+  for (int k = 2; k <= n_pow2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n_pow2; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t ki = keys[i], kj = keys[ixj];
+          const int32_t ii = ids[i], ij = ids[ixj];
+          const bool gt = (ki > kj) || (ki == kj && ii > ij);
+          const bool up = ((i & k) == 0);
+          if (gt == up) {
+            keys[i] = kj; keys[ixj] = ki;
+            ids[i] = ij; ids[ixj] = ii;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Top-M of n_cand scores by (score desc, id asc), written to sel[0..min(M,n)-1]
+// in that order.  Radix select of the M-th key (8 passes of 8 bits), ordered
+// compaction, then a bitonic sort of the survivors.
+__global__ __launch_bounds__(1024) void k_select(int n, int M, const double *cand, int32_t *sel,
+                                                uint64_t *kw, int32_t *iw) {
+  __shared__ unsigned hist[256];
+  __shared__ uint64_t sh_prefix;
+  __shared__ int sh_need, sh_count;
+  __shared__ int wsum[16];
+  const int tid = threadIdx.x;
+  const int Me = (M < n) ? M : n;
+  uint64_t prefix = 0, pmask = 0;
+  int need = Me;
+  if (Me < n) {
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0u;
+      __syncthreads();
+      for (int i = tid; i < n; i += blockDim.x) {
+        const uint64_t k = desc_key(cand[i]);
+        if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int cum = 0, t = 0;
+        for (t = 0; t < 255; ++t) {
+          if (cum + (int)hist[t] >= need) break;
+          cum += hist[t];
+        }
+        sh_need = need - cum;
+        sh_prefix = prefix | ((uint64_t)t << shift);
+      }
+      __syncthreads();
+      need = sh_need;
+      prefix = sh_prefix;
+      pmask |= (255ull << shift);
+      __syncthreads();
+    }
+  } else {
+    prefix = ~0ull;     // everything selected: all keys <= threshold count as "less"
+    need = 0;
+  }
+  // ordered compaction: keys < prefix all taken; keys == prefix the first `need` by id
+  if (tid == 0) sh_count = 0;
+  __syncthreads();
+  int taken_eq = 0, base = 0;
+  for (int c0 = 0; c0 < n; c0 += blockDim.x) {
+    const int i = c0 + tid;
+    uint64_t k = 0;
+    int lt = 0, eq = 0;
+    if (i < n) {
+      k = desc_key(cand[i]);
+      if (Me == n) lt = 1;
+      else { lt = (k < prefix); eq = (k == prefix); }
+    }
+    int tot_eq, tot_lt;
+    const int r_eq = block_excl_scan(eq, wsum, &tot_eq);
+    const int take_eq = eq && (taken_eq + r_eq < need);
+    const int f = lt || take_eq;
+    int tot_f;
+    const int pos = block_excl_scan(f, wsum, &tot_f);
+    if (f) { kw[base + pos] = k; iw[base + pos] = i; }
+    base += tot_f;
+    taken_eq += tot_eq;
+    (void)tot_lt;
+    __syncthreads();
+  }
+  int p2 = 1;
+  while (p2 < Me) p2 <<= 1;
+  for (int i = Me + tid; i < p2; i += blockDim.x) { kw[i] = ~0ull; iw[i] = INT_MAX; }
+  __syncthreads();
+  bitonic_sort_global(kw, iw, p2);
+  for (int i = tid; i < Me; i += blockDim.x) sel[i] = iw[i];
+}
+
+__global__ __launch_bounds__(256) void k_beam_update(SearchTabs t, int r, int c, int n_new,
+                                                     const int32_t *sel, int N,
+                                                     const uint8_t *cfg, const double *energy,
+                                                     const double *L, const int32_t *anc,
+                                                     const double *cand, const double *A,
+                                                     int update_L, uint8_t *cfg_o,
+                                                     double *energy_o, double *score_o,
+                                                     double *L_o, int32_t *anc_o) {
+  __shared__ double Ls[kWaves][kMaxChi];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j0 = blockIdx.x * kWaves + w;
+  const bool valid = j0 < n_new;
+  const int j = valid ? j0 : 0;
+  const int d = t.d, chi = t.chi, C = t.cols;
+  const int id = sel[j];
+  const int b = id / d, s = id % d;
+  const uint8_t *cb = cfg + (long)b * N;
+  uint8_t *co = cfg_o + (long)j * N;
+  const int k = r * C + c;
+  if (valid)
+    for (int i = lane; i < N; i += 64) co[i] = (i == k) ? (uint8_t)s : cb[i];
+  if (valid && lane == 0) {
+    energy_o[j] = energy[b] + delta_energy(t, r, c, cb, s);
+    score_o[j] = cand[id];
+    anc_o[j] = anc[b];
+  }
+  if (!update_L) return;
+  if (valid)
+    for (int i = lane; i < chi; i += 64) Ls[w][i] = L[(long)b * chi + i];
+  __syncthreads();
+  if (!valid) return;
+  const double g = field(t, r, c, cb, s);
+  double v[2] = {0.0, 0.0};
+  for (int h = 0; h < 2; ++h) {
+    const int bp = lane + 64 * h;
+    if (bp >= chi) continue;
+    double acc = 0.0;
+    for (int al = 0; al < chi; ++al) acc += Ls[w][al] * A[((long)al * d + s) * chi + bp];
+    v[h] = g * acc;
+  }
+  const double m = wave_max(fmax(fabs(v[0]), fabs(v[1])));
+  const double inv = (m > 0.0) ? 1.0 / m : 1.0;
+  for (int h = 0; h < 2; ++h) {
+    const int bp = lane + 64 * h;
+    if (bp < chi) L_o[(long)j * chi + bp] = v[h] * inv;
+  }
+}
+
+__global__ void k_reset_row(int n, int chi, double *L, int32_t *anc) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)n * chi) return;
+  const int j = (int)(e / chi), i = (int)(e % chi);
+  L[e] = (i == 0) ? 1.0 : 0.0;
+  if (i == 0) anc[j] = j;
+}
+
+// Energy of complete configurations by Eq. (1), one wavefront per state.
+__global__ __launch_bounds__(256) void k_energy(SearchTabs t, int n, int N, const uint8_t *cfg,
+                                                double *E) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * kWaves + w;
+  if (j >= n) return;
+  const int R = t.rows, C = t.cols, d = t.d;
+  const long dd = (long)d * d;
+  const uint8_t *x = cfg + (long)j * N;
+  double acc = 0.0;
+  for (int k = lane; k < N; k += 64) {
+    const int r = k / C, c = k % C;
+    acc += t.E_loc[(long)k * d + x[k]];
+    if (c + 1 < C) acc += t.E_h[((long)r * (C - 1) + c) * dd + x[k] * d + x[k + 1]];
+    if (r + 1 < R) {
+      acc += t.E_v[((long)r * C + c) * dd + x[k] * d + x[k + C]];
+      if (c + 1 < C) {
+        acc += t.E_d[((long)r * (C - 1) + c) * dd + x[k] * d + x[k + C + 1]];
+        acc += t.E_a[((long)r * (C - 1) + c) * dd + x[k + 1] * d + x[k + C]];
+      }
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) E[j] = acc;
+}
+
+__global__ __launch_bounds__(1024) void k_final_sort(int n, const double *E, const double *score,
+                                                    uint64_t *kw, int32_t *iw, int32_t *nv) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int p2 = 1;
+  while (p2 < n) p2 <<= 1;
+  int local = 0;
+  for (int i = threadIdx.x; i < p2; i += blockDim.x) {
+    if (i < n) {
+      kw[i] = asc_key(E[i]);
+      iw[i] = i;
+      const double sc = score[i];
+      local += (sc == sc && sc > -INFINITY);
+    } else {
+      kw[i] = ~0ull;
+      iw[i] = INT_MAX;
+    }
+  }
+  atomicAdd(&cnt, local);
+  __syncthreads();
+  bitonic_sort_global(kw, iw, p2);
+  if (threadIdx.x == 0) *nv = cnt;
+}
+
+__global__ void k_gather_out(int n, int N, const int32_t *perm, const uint8_t *cfg,
+                             const double *E, const double *score, int32_t *states,
+                             double *energies, double *logp) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)n * N) return;
+  const int t = (int)(e / N), k = (int)(e % N);
+  const int j = perm[t];
+  states[e] = cfg[(long)j * N + k];
+  if (k == 0) {
+    energies[t] = E[j];
+    logp[t] = score[j];
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_cutoff(int n, double log_cut, double *cand) {
+  __shared__ double red[1024];
+  double m = -INFINITY;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, cand[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const double thr = red[0] + log_cut;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    if (!(cand[i] >= thr)) cand[i] = -INFINITY;
+}
+
+__global__ void k_cfg_from_i32(long n, const int32_t *src, uint8_t *dst) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = (uint8_t)src[e];
+}
+
+// L^b <- g^b_c(x_c) L^b A[:, x_c, :], max-normalised, x_c read from cfg
+__global__ __launch_bounds__(256) void k_advance_L(SearchTabs t, int r, int c, int n,
+                                                   const uint8_t *cfg, int N, const double *A,
+                                                   double *L) {
+  __shared__ double Ls[kWaves][kMaxChi];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b0 = blockIdx.x * kWaves + w;
+  const bool valid = b0 < n;
+  const int b = valid ? b0 : 0;
+  const int d = t.d, chi = t.chi;
+  const uint8_t *cb = cfg + (long)b * N;
+  const int s = cb[r * t.cols + c];
+  if (valid)
+    for (int i = lane; i < chi; i += 64) Ls[w][i] = L[(long)b * chi + i];
+  __syncthreads();
+  if (!valid) return;
+  const double g = field(t, r, c, cb, s);
+  double v[2] = {0.0, 0.0};
+  for (int h = 0; h < 2; ++h) {
+    const int bp = lane + 64 * h;
+    if (bp >= chi) continue;
+    double acc = 0.0;
+    for (int al = 0; al < chi; ++al) acc += Ls[w][al] * A[((long)al * d + s) * chi + bp];
+    v[h] = g * acc;
+  }
+  const double m = wave_max(fmax(fabs(v[0]), fabs(v[1])));
+  const double inv = (m > 0.0) ? 1.0 / m : 1.0;
+  for (int h = 0; h < 2; ++h) {
+    const int bp = lane + 64 * h;
+    if (bp < chi) L[(long)b * chi + bp] = v[h] * inv;
+  }
+}
+
+}  // namespace
+
+void right_env_col(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *cfg, int N,
+                   const double *A_rc, const double *Rnext, double *Rout, long rstride,
+                   hipStream_t s) {
+  if (n_anc <= 0) return;
+  hipLaunchKernelGGL(k_right_env, dim3(nblk(n_anc, kWaves)), dim3(256), 0, s, t, r, c, n_anc,
+                     cfg, N, A_rc, Rnext, Rout, rstride);
+  SPG_CHECK_LAUNCH();
+}
+
+void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
+               const double *A_rc, const double *L, const int32_t *anc, const double *Rv,
+               long rstride, const double *score, double *out, int add_score, hipStream_t s) {
+  if (n_beam <= 0) return;
+  hipLaunchKernelGGL(k_marginals, dim3(nblk(n_beam, kWaves)), dim3(256), 0, s, t, r, c, n_beam,
+                     cfg, N, A_rc, L, anc, Rv, rstride, score, out, add_score);
+  SPG_CHECK_LAUNCH();
+}
+
+void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *keys_work,
+                 int32_t *ids_work, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, n_cand, M, cand, sel, keys_work,
+                     ids_work);
+  SPG_CHECK_LAUNCH();
+}
+
+void beam_update(const SearchTabs &t, int r, int c, int n_new, const int32_t *sel, int N,
+                 const uint8_t *cfg, const double *energy, const double *L, const int32_t *anc,
+                 const double *cand, const double *A_rc, int update_L, uint8_t *cfg_o,
+                 double *energy_o, double *score_o, double *L_o, int32_t *anc_o,
+                 hipStream_t s) {
+  if (n_new <= 0) return;
+  hipLaunchKernelGGL(k_beam_update, dim3(nblk(n_new, kWaves)), dim3(256), 0, s, t, r, c, n_new,
+                     sel, N, cfg, energy, L, anc, cand, A_rc, update_L, cfg_o, energy_o,
+                     score_o, L_o, anc_o);
+  SPG_CHECK_LAUNCH();
+}
+
+void beam_reset_row(int n, int chi, double *L, int32_t *anc, hipStream_t s) {
+  const long tot = (long)n * chi;
+  hipLaunchKernelGGL(k_reset_row, dim3(nblk(tot, 256)), dim3(256), 0, s, n, chi, L, anc);
+  SPG_CHECK_LAUNCH();
+}
+
+void final_sort(const SearchTabs &t, int n, int N, const uint8_t *cfg, const double *score,
+                int32_t *states_out, double *energies_out, double *logp_out, double *e_work,
+                int32_t *perm_work, int32_t *n_valid, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy, dim3(nblk(n, kWaves)), dim3(256), 0, s, t, n, N, cfg, e_work);
+  SPG_CHECK_LAUNCH();
+  uint64_t *kw = reinterpret_cast<uint64_t *>(e_work + n);
+  hipLaunchKernelGGL(k_final_sort, dim3(1), dim3(1024), 0, s, n, e_work, score, kw, perm_work,
+                     n_valid);
+  SPG_CHECK_LAUNCH();
+  const long tot = (long)n * N;
+  hipLaunchKernelGGL(k_gather_out, dim3(nblk(tot, 256)), dim3(256), 0, s, n, N, perm_work, cfg,
+                     e_work, score, states_out, energies_out, logp_out);
+  SPG_CHECK_LAUNCH();
+}
+
+void apply_cutoff(int n, double log_cut, double *cand, hipStream_t s) {
+  hipLaunchKernelGGL(k_cutoff, dim3(1), dim3(1024), 0, s, n, log_cut, cand);
+  SPG_CHECK_LAUNCH();
+}
+
+void cfg_from_i32(int n, int N, const int32_t *src, uint8_t *dst, hipStream_t s) {
+  const long tot = (long)n * N;
+  hipLaunchKernelGGL(k_cfg_from_i32, dim3(nblk(tot, 256)), dim3(256), 0, s, tot, src, dst);
+  SPG_CHECK_LAUNCH();
+}
+
+void advance_L(const SearchTabs &t, int r, int c, int n, const uint8_t *cfg, int N,
+               const double *A_rc, double *L, double *tmp, hipStream_t s) {
+  (void)tmp;
+  hipLaunchKernelGGL(k_advance_L, dim3(nblk(n, kWaves)), dim3(256), 0, s, t, r, c, n, cfg, N,
+                     A_rc, L);
+  SPG_CHECK_LAUNCH();
+}
+
+}  // namespace spg

@@ -1,0 +1,159 @@
+// Internal declarations of the HIP implementation behind include/spg.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/spg.h"
+
+namespace spg {
+
+// ---- error plumbing ------------------------------------------------------
+void set_error(const std::string &msg);
+struct Fail {
+  int code;
+};
+#define SPG_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::spg::set_error(std::string(#call) + ": " + hipGetErrorString(e_));         \
+      throw ::spg::Fail{SPG_ERR_HIP};                                              \
+    }                                                                              \
+  } while (0)
+#define SPG_CHECK_LAUNCH() SPG_HIP(hipGetLastError())
+
+// ---- device buffers -------------------------------------------------------
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void ensure(size_t n);  // grows (contents lost), zero-filled on growth (device-synchronous)
+  void release();
+  template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Maximum sketch width of the truncated SVD (chi + oversample).
+constexpr int kMaxSketch = 96;
+constexpr int kMaxChi = 80;
+
+// ---- linear algebra kernels (k_linalg.hip) --------------------------------
+// C[b1,b2](i,j) = alpha * sum_k A[b1,b2](i,k) B[b1,b2](k,j) + beta * C[b1,b2](i,j)
+struct GemmDesc {
+  int M, N, K, nb1, nb2;
+  const double *A; long a_i, a_k, a_b1, a_b2;
+  const double *B; long b_k, b_j, b_b1, b_b2;
+  double *C; long c_i, c_j, c_b1, c_b2;
+  double alpha, beta;
+};
+void gemm_f64(const GemmDesc &g, hipStream_t s);
+
+// Householder QR of an m x n matrix (m >= n), element (i,j) at X[i*xr + j*xc].
+// Writes Q (m x n, orthonormal columns) to Q[i*qr + j*qc] and, if R != nullptr,
+// the n x n upper-triangular factor to R[i*n + j] (row-major).  `work` holds
+// 2*m*n + n doubles.  One workgroup per call.
+void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr, long qc,
+            double *R, double *work, hipStream_t s);
+
+// One-sided Jacobi SVD of an l x l matrix (row-major, l <= kMaxSketch): writes
+// the right singular vectors as columns of V (row-major l x l) sorted by
+// singular value, descending (ties by index), and the singular values to sig.
+void jacobi_svd_f64(int l, const double *Rm, double *V, double *sig, hipStream_t s);
+
+// Sketch matrix of the truncated SVD: Om[i*l + j] = 2 u(SplitMix64(seed, i*ld + j)) - 1.
+void fill_sketch(int n, int l, double *Om, hipStream_t s);
+
+// Frobenius norm of a 4-index box (n0,n1,n2,n3 with strides) -> scales the box
+// by 1/norm and writes logs[out] = logs[in] + log(norm) (in < 0 means 0).
+void normalize_box(double *T, int n0, int n1, int n2, int n3, long s0, long s1, long s2,
+                   long s3, double *logs, int out, int in, hipStream_t s);
+void fill_zero(double *p, size_t n, hipStream_t s);
+
+// ---- boundary-MPS contraction kernels (k_bmps.hip) -------------------------
+struct RowFactors {         // device d x d tables (row-major) / d vectors of one column
+  const double *w;          // w_c(x)
+  const double *V;          // V_c[x][y]
+  const double *Hl, *Dl, *Al;  // H_{c-1}[a][x], D_{c-1}[a][y], A_{c-1}[x][e]
+};
+void init_guess(int d, int chi, int bl, int br, const double *psi, const RowFactors &f,
+                double *phi, hipStream_t s);
+// P[p][x][y][Q] = w(x)V(x,y) sum_{q,a,e} EL[p][a][e][q] Hl(a,x)Dl(a,y)Al(x,e) psi[q][y][Q]
+void left_part(int d, int chi, int pl, int ql, int qr, const double *EL, const double *psi,
+               const RowFactors &f, double *T1, double *P, hipStream_t s);
+void env_left(int d, int chi, int pl, int pr, int qr, const double *phi, const double *P,
+              double *ELn, hipStream_t s);
+void env_right(int d, int chi, int pl, int pr, int ql, int qr, const double *phi,
+               const double *psi, const double *ER, const RowFactors &f, double *G1,
+               double *G2, double *ERn, hipStream_t s);
+void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, const double *EL,
+                    const double *ER, const double *psi0, const double *psi1,
+                    const RowFactors &f0, const RowFactors &f1, double *T1, double *P,
+                    double *Qr, double *P2, double *Q2, double *B, hipStream_t s);
+// dst[k][z][P] (padded chi) = src[k*sk + (z*pr + P)*sj] for k < nk, z < d, P < pr
+void unpack_right(int d, int chi, int nk, int pr, const double *src, long sk, long sj,
+                  double *dst, hipStream_t s);
+void lq_fold(int d, int chi, int bl, int k, const double *R, double *phi_prev, double *tmp,
+             hipStream_t s);
+void add_logs(double *logs, int out, int a, int b, int c, hipStream_t s);
+// dst[k*(d*pr) + z*pr + P] = src[(k*d + z)*chi + P]  (padded MPS site -> compact rows)
+void pack_right(int d, int chi, int nk, int pr, const double *src, double *dst, hipStream_t s);
+void build_weights(int ntab, int tsize, double beta, const double *E, double *W, double *mins,
+                   hipStream_t s);
+void set_e0(int n, int chi, double *p, long stride, hipStream_t s);
+
+// ---- search kernels (k_search.hip) ----------------------------------------
+struct SearchTabs {         // device tables of the instance
+  int rows, cols, d, chi;
+  const double *E_loc, *E_h, *E_v, *E_d, *E_a;
+  const double *W_v, *W_d, *W_a;
+};
+void right_env_col(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *cfg, int N,
+                   const double *A_rc, const double *Rnext, double *Rout, long rstride,
+                   hipStream_t s);
+void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
+               const double *A_rc, const double *L, const int32_t *anc, const double *Rv,
+               long rstride, const double *score, double *out, int add_score, hipStream_t s);
+void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *keys_work,
+                 int32_t *ids_work, hipStream_t s);
+void beam_update(const SearchTabs &t, int r, int c, int n_new, const int32_t *sel, int N,
+                 const uint8_t *cfg, const double *energy, const double *L, const int32_t *anc,
+                 const double *cand, const double *A_rc, int update_L, uint8_t *cfg_o,
+                 double *energy_o, double *score_o, double *L_o, int32_t *anc_o,
+                 hipStream_t s);
+void beam_reset_row(int n, int chi, double *L, int32_t *anc, hipStream_t s);
+void final_sort(const SearchTabs &t, int n, int N, const uint8_t *cfg, const double *score,
+                int32_t *states_out, double *energies_out, double *logp_out, double *e_work,
+                int32_t *perm_work, int32_t *n_valid, hipStream_t s);
+void apply_cutoff(int n, double log_cut, double *cand, hipStream_t s);
+void cfg_from_i32(int n, int N, const int32_t *src, uint8_t *dst, hipStream_t s);
+void advance_L(const SearchTabs &t, int r, int c, int n, const uint8_t *cfg, int N,
+               const double *A_rc, double *L, double *tmp, hipStream_t s);
+
+}  // namespace spg
+
+// ---- opaque handles ---------------------------------------------------------
+struct spg_peps {
+  int rows = 0, cols = 0, d = 0, kings = 0;
+  double beta = 0, shift = 0;
+  int device = 0;
+  spg::DevBuf E_loc, E_h, E_v, E_d, E_a;   // energies (zero tables for absent classes)
+  spg::DevBuf W_loc, W_h, W_v, W_d, W_a;   // Boltzmann weights of the min-shifted tables
+  spg::DevBuf ones, e0row, e0col, e0vec;   // d x d all-ones, first row / column ones; e_0
+};
+
+struct spg_env {
+  const spg_peps *peps = nullptr;
+  int chi = 0, precision = SPG_FP64;
+  std::vector<int32_t> dims;     // [rows][cols+1]
+  spg::DevBuf A;                 // [rows][cols][chi][d][chi] float64, zero padded
+  spg::DevBuf lam;               // [rows] float64 log-scales
+  // search workspace (grown on demand)
+  spg::DevBuf cfg[2], score[2], energy[2], L[2], anc[2], Rv, cand, sel, keys, ids, ework,
+      perm, nvalid, tmp, cfg32;
+};

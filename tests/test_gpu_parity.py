@@ -1,0 +1,215 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (FP64 everywhere on both sides; derived from the arithmetic):
+* log Z and the boundary functions in the exact regime: both sides compute
+  the same contraction up to summation order, ~1e-15 relative per GEMM,
+  amplified by the conditioning of the orthonormal gauge; 1e-9 absolute on
+  log Z and on normalised row functions.
+* teacher-forced conditionals with the same boundary MPS: each side evaluates
+  q = g L A R with n ~ chi^2 + chi*d*cols operations; the running error bound
+  gives |dlog p(s)| <= 2 n eps (kappa_s + kappa_Z), with kappa the ratio of the
+  absolute-value contraction to the value (oracle.search.teacher_forced_condition),
+  plus 1e-12.  Well-conditioned values are thus held to ~1e-12; values whose
+  computation cancels (random partial configurations far from the dominant
+  region of an ill-conditioned MPS) get the looser bound they need.
+* beam search with the same boundary MPS: the sorted final scores agree to
+  1e-8 (near-ties may swap members, not the multiset of scores) and the best
+  energies agree exactly up to FP64 rounding of the Eq. (1) sums (1e-9); on the
+  ill-conditioned 8x8 d=16 MPS, 99% of the scores agree to 1e-8 and all to 1e-4.
+"""
+import numpy as np
+import pytest
+
+from workloads import random_potts, config_instance, spin_instance, potts_from_spins
+from oracle.exact import brute_force
+from oracle.bmps import boundary_mps as oracle_bmps, mps_full
+from oracle.search import beam_search, teacher_forced_logp, teacher_forced_condition
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2502_02317_amd import spg  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _gpu_mps(inst, chi, **kw):
+    peps = spg.build_peps(inst)
+    env, lz = spg.boundary_mps(peps, chi, **kw)
+    return peps, env, lz
+
+
+def _rows_dense(env):
+    T, lam = spg.env_export(env)
+    info = spg.env_info(env)
+    return spg.unpack_mps(T, info.bond_dims), lam
+
+
+@pytest.mark.parametrize("shape", [(2, 2, 2, True), (3, 3, 2, True), (2, 3, 3, True),
+                                   (3, 4, 2, False), (4, 4, 2, True), (3, 3, 4, True),
+                                   (1, 4, 3, False)])
+def test_logZ_exact_regime_vs_brute_force(shape):
+    R, C, d, k = shape
+    inst = random_potts(R, C, d, k, seed=40 + R + 3 * C + 7 * d, beta=0.9)
+    bf = brute_force(inst)
+    chi = min(d ** (C // 2), 80)
+    _, env, lz = _gpu_mps(inst, chi)
+    assert abs(lz - bf["logZ"]) < 1e-9, (lz, bf["logZ"])
+    rows, _ = _rows_dense(env)
+    ora = oracle_bmps(inst, chi)
+    for r in range(R):
+        a, b = mps_full(rows[r]), mps_full(ora["A"][r])
+        np.testing.assert_allclose(a / np.linalg.norm(a), b / np.linalg.norm(b), atol=1e-9)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_config1_logZ(seed):
+    inst = config_instance("square4x4_d2", seed)
+    bf = brute_force(inst)
+    _, env, lz = _gpu_mps(inst, 16)
+    assert abs(lz - bf["logZ"]) < 1e-9
+
+
+@pytest.mark.parametrize("chi,sweeps", [(3, 1), (5, 2), (8, 1)])
+def test_truncated_bmps_matches_oracle(chi, sweeps):
+    """Well-conditioned king's lattice with truncation active: same protocol,
+    same result (log Z, log-scales and every row function)."""
+    si = spin_instance(4, 5, 2, True, seed=6, h=("normal", 1.0), j_in=("normal", 1.0),
+                       j_out=("normal", 0.4))
+    inst = potts_from_spins(si, beta=0.5)
+    _, env, lz = _gpu_mps(inst, chi, num_sweeps=sweeps)
+    ora = oracle_bmps(inst, chi, num_sweeps=sweeps)
+    assert abs(lz - ora["logZ"]) < 1e-9
+    rows, lam = _rows_dense(env)
+    np.testing.assert_allclose(lam, ora["lam"], atol=1e-9)
+    for r in range(inst.rows):
+        a, b = mps_full(rows[r]), mps_full(ora["A"][r])
+        np.testing.assert_allclose(a, b, atol=1e-9 * np.abs(b).max())
+
+
+def _import_oracle(inst, chi):
+    ora = oracle_bmps(inst, chi)
+    T, dims = spg.pack_oracle_mps(ora["A"], chi, inst.d)
+    peps = spg.build_peps(inst)
+    env = spg.env_import(peps, chi, dims, T, np.array(ora["lam"]))
+    return ora, peps, env
+
+
+def _check_marginals(inst, ora, env, site, cfg):
+    cfg_t = torch.tensor(cfg, dtype=torch.int32, device=DEV)
+    out = torch.empty((cfg.shape[0], inst.d), dtype=torch.float64, device=DEV)
+    spg.marginals(env, site, cfg_t, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    r, c = divmod(site, inst.cols)
+    ref = teacher_forced_logp(inst, ora["A"], r, c, cfg)
+    ks, kz = teacher_forced_condition(inst, ora["A"], r, c, cfg)
+    n_ops = inst.d * ora["A"][0][0].shape[2] * inst.cols + max(a.shape[0] for a in ora["A"][r]) ** 2
+    tol = 1e-12 + 2 * n_ops * np.finfo(float).eps * (ks + kz[:, None])
+    fin = np.isfinite(ref) & np.isfinite(tol)
+    err = np.abs(got - ref)
+    assert np.all(err[fin] <= tol[fin]), (err[fin].max(), np.argmax(err[fin] - tol[fin]))
+    np.testing.assert_allclose(np.exp(got).sum(axis=1), 1.0, atol=1e-12)
+    return err[fin], tol[fin]
+
+
+@pytest.mark.parametrize("inst_kind", ["cfg1", "kings_d3"])
+def test_teacher_forced_marginals_every_site(inst_kind):
+    inst = (config_instance("square4x4_d2", 3) if inst_kind == "cfg1"
+            else random_potts(3, 4, 3, True, seed=5, beta=0.8))
+    chi = 16 if inst_kind == "cfg1" else 9
+    ora, peps, env = _import_oracle(inst, chi)
+    rng = np.random.default_rng(1)
+    cfg = rng.integers(0, inst.d, size=(37, inst.n_sites))
+    for site in range(inst.n_sites):
+        _check_marginals(inst, ora, env, site, cfg)
+
+
+def test_teacher_forced_marginals_kings8x8_d16():
+    """Full-size 8x8 king's lattice, d=16, chi=32, with the oracle's boundary MPS:
+    sampled sites, 300 random partial configurations each."""
+    inst = config_instance("kings8x8_d16", 0)
+    ora, peps, env = _import_oracle(inst, 32)
+    rng = np.random.default_rng(2)
+    cfg = rng.integers(0, 16, size=(300, inst.n_sites))
+    for site in [0, 5, 7, 8, 13, 27, 36, 63]:
+        _check_marginals(inst, ora, env, site, cfg)
+    # the partial configurations the search visits: the oracle's beam at each site
+    trace = []
+    beam_search(inst, ora["A"], 256, trace=trace)
+    med = []
+    for site in [1, 9, 20, 31, 40, 55, 63]:
+        err, tol = _check_marginals(inst, ora, env, site, trace[site]["cfg"])
+        med.append(np.median(err))
+    assert max(med) < 1e-10
+
+
+def _gpu_search(env, inst, M, cut=0.0):
+    N = inst.n_sites
+    st = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+    en = torch.zeros(M, dtype=torch.float64, device=DEV)
+    lp = torch.zeros(M, dtype=torch.float64, device=DEV)
+    n = spg.branch_and_bound(env, M, st, en, lp, cut_off_prob=cut)
+    nb = min(M, inst.d ** N) if N * np.log(inst.d) < 60 else M
+    return st.cpu().numpy()[:nb], en.cpu().numpy()[:nb], lp.cpu().numpy()[:nb], n
+
+
+def _compare_search(inst, ora, env, M, cut=0.0, ill_conditioned=False):
+    st, en, lp, n = _gpu_search(env, inst, M, cut)
+    ref = beam_search(inst, ora["A"], M, cut_off_prob=cut)
+    assert n == ref["n_valid"]
+    fin = np.isfinite(ref["scores"])
+    a, b = np.sort(lp[np.isfinite(lp)]), np.sort(ref["scores"][fin])
+    if ill_conditioned:
+        assert np.mean(np.abs(a - b) <= 1e-8) >= 0.99
+        np.testing.assert_allclose(a, b, atol=1e-4)
+    else:
+        np.testing.assert_allclose(a, b, atol=1e-8)
+    assert abs(en[0] - ref["energies"][0]) < 1e-9
+    # every returned state's energy is its Eq. (1) energy
+    from oracle.energy import potts_energy
+    np.testing.assert_allclose(en, potts_energy(inst, st), atol=1e-9)
+    return st, en, lp
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_search_config1_vs_oracle_and_brute_force(seed):
+    inst = config_instance("square4x4_d2", seed)
+    ora, peps, env = _import_oracle(inst, 16)
+    st, en, lp = _compare_search(inst, ora, env, 64)
+    assert abs(en[0] - brute_force(inst)["E_min"]) < 1e-9
+
+
+@pytest.mark.parametrize("M", [1, 7, 729])
+def test_search_edge_beam_sizes(M):
+    inst = random_potts(2, 3, 3, True, seed=8, beta=1.1)
+    ora, peps, env = _import_oracle(inst, 9)
+    st, en, lp = _compare_search(inst, ora, env, M)
+    if M >= 3 ** 6:
+        assert abs(en[0] - brute_force(inst)["E_min"]) < 1e-12
+
+
+def test_search_cutoff():
+    inst = random_potts(2, 3, 3, True, seed=3, beta=2.0)
+    ora, peps, env = _import_oracle(inst, 9)
+    _compare_search(inst, ora, env, 27, cut=1e-2)
+
+
+def test_search_kings8x8_d16_vs_oracle():
+    """Full-size bench workload with a shared boundary MPS (the oracle's)."""
+    inst = config_instance("kings8x8_d16", 0)
+    ora, peps, env = _import_oracle(inst, 32)
+    _compare_search(inst, ora, env, 1024, ill_conditioned=True)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_full_gpu_pipeline_config1(seed):
+    inst = config_instance("square4x4_d2", seed)
+    _, env, lz = _gpu_mps(inst, 16)
+    st, en, lp, n = _gpu_search(env, inst, 64)
+    bf = brute_force(inst)
+    assert abs(en[0] - bf["E_min"]) < 1e-9
+    assert n == 64
