@@ -157,6 +157,19 @@ int spg_env_import(const spg_peps_t *peps, int32_t chi, const int32_t *bond_dims
                    const double *tensors, const double *lam, int32_t precision, void *stream,
                    spg_env_t **out);
 
+/* Opt-in kernel timing: while enabled, every launch of a timed kernel class
+ * ("gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box", "right_env",
+ * "marginals", "select_topm", "beam_update", "final_sort") is bracketed by HIP
+ * events recorded on the stream it is launched on.  spg_profile_query
+ * synchronises on those events and returns, since the last reset, the number
+ * of launches, their summed duration in milliseconds and (total_work, may be
+ * NULL) their summed algorithmic work: flops for the contraction classes
+ * (gemm_f64, qr_f64, right_env, marginals, beam_update), bytes for
+ * normalize_box and select_topm, 0 for the others.  Not thread-safe. */
+void spg_profile_enable(int32_t on);
+void spg_profile_reset(void);
+int spg_profile_query(const char *name, int64_t *count, double *total_ms, double *total_work);
+
 #ifdef __cplusplus
 }
 #endif

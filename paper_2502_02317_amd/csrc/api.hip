@@ -12,6 +12,41 @@ namespace spg {
 thread_local std::string g_err;
 void set_error(const std::string &m) { g_err = m; }
 
+// Per-launch timing: when enabled, every timed launch records a start and a
+// stop event on its own stream; queries synchronise on the stop events.
+struct TimerRec {
+  const char *name;
+  hipEvent_t a, b;
+  double work;
+};
+static bool g_prof = false;
+static std::vector<TimerRec> g_recs;
+static std::vector<hipEvent_t> g_pool;
+
+static hipEvent_t pool_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  SPG_HIP(hipEventCreate(&e));
+  return e;
+}
+
+KTimer::KTimer(const char *name, hipStream_t st, double work) {
+  if (!g_prof) return;
+  s = st;
+  TimerRec r{name, pool_event(), pool_event(), work};
+  SPG_HIP(hipEventRecord(r.a, s));
+  g_recs.push_back(r);
+  slot = (int)g_recs.size() - 1;
+}
+
+KTimer::~KTimer() {
+  if (slot >= 0) (void)hipEventRecord(g_recs[slot].b, s);
+}
+
 void DevBuf::ensure(size_t n) {
   if (n <= bytes) return;
   release();
@@ -52,7 +87,7 @@ static int fail(int code, const std::string &m) {
 struct BmpsWork {
   int R, C, d, chi, lmax;
   DevBuf EL, ER, T1, P, Qr, P2, Q2, G1, G2, B, Y, Q, Z, Qz, Om, Cm, Qc, Rc, V, sig, U, Rm,
-      qrwork, tmp, logs, psi0;
+      qrwork, tmp, logs, psi0, nscr;
   size_t env_sz() const { return (size_t)chi * d * d * chi; }
   size_t site_sz() const { return (size_t)chi * d * chi; }
   double *ELc(int c) { return EL.as<double>() + (size_t)c * env_sz(); }
@@ -73,7 +108,8 @@ struct BmpsWork {
     sig.ensure((size_t)lmax * sizeof(double));
     U.ensure(ml);
     Rm.ensure(ml);
-    qrwork.ensure((2 * mn * lmax + lmax) * sizeof(double));
+    qrwork.ensure(qr_work_doubles((int)mn, lmax) * sizeof(double));
+    nscr.ensure(kNormScratch * sizeof(double));
     tmp.ensure(site_sz() * sizeof(double));
     logs.ensure((size_t)(2 * C + 8 + R) * sizeof(double));
     psi0.ensure(site_sz() * C * sizeof(double));
@@ -111,7 +147,7 @@ static int tsvd_left(BmpsWork &w, const double *B, long br, long bc, int m, int 
     qr_f64(m, l, Y, l, 1, Q, l, 1, nullptr, qw, s);
   }
   mm(l, n, m, Q, 1, l, B, br, bc, Cm, n, 1);                 // Cm = Q^T B   (l x n)
-  qr_f64(n, l, Cm, 1, n, w.Qc.as<double>(), l, 1, w.Rc.as<double>(), qw, s);  // Cm^T = Qc Rc
+  qr_f64(n, l, Cm, 1, n, nullptr, l, 1, w.Rc.as<double>(), qw, s);  // Cm^T = Qc Rc (R only)
   jacobi_svd_f64(l, w.Rc.as<double>(), w.V.as<double>(), w.sig.as<double>(), s);
   mm(m, kk, l, Q, l, 1, w.V.as<double>(), l, 1, U, ur, uc);  // U = Q V[:, :kk]
   return kk;
@@ -184,7 +220,7 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
                 psi + c * site, w.ERc(c + 1), f[c], w.G1.as<double>(), w.G2.as<double>(),
                 w.ERc(c), s);
       normalize_box(w.ERc(c), fdims[c], d, d, pdims[c], (long)d * d * chi, (long)d * chi, chi, 1,
-                    logs, sER + c, sER + c + 1, s);
+                    logs, sER + c, sER + c + 1, w.nscr.as<double>(), s);
     };
     auto build_EL = [&](int c) {
       left_part(d, chi, fdims[c], pdims[c], pdims[c + 1], w.ELc(c), psi + c * site, f[c],
@@ -192,7 +228,7 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
       env_left(d, chi, fdims[c], fdims[c + 1], pdims[c + 1], phi + c * site, w.P.as<double>(),
                w.ELc(c + 1), s);
       normalize_box(w.ELc(c + 1), fdims[c + 1], d, d, pdims[c + 1], (long)d * d * chi,
-                    (long)d * chi, chi, 1, logs, sEL + c + 1, sEL + c, s);
+                    (long)d * chi, chi, 1, logs, sEL + c + 1, sEL + c, w.nscr.as<double>(), s);
     };
     // two-site update at (c, c+1); right = true: centre moves left (phi_c = U S, phi_{c+1} = V^T)
     auto update = [&](int c, bool right) {
@@ -251,7 +287,8 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
     }
     (void)last_pair_lam_slot;
     // normalise the centre phi_0; lam_r = lam_{r+1} + log-scale of ER[2] + log |phi_0|
-    normalize_box(phi, 1, d, fdims[1], 1, (long)d * chi, chi, 1, 1, logs, sCen, -1, s);
+    normalize_box(phi, 1, d, fdims[1], 1, (long)d * chi, chi, 1, 1, logs, sCen, -1,
+                  w.nscr.as<double>(), s);
     add_logs(logs, sLam + r, bottom ? -1 : sLam + r + 1, (C > 2) ? sER + 2 : -1, sCen, s);
     for (int c = 0; c <= C; ++c) env->dims[r * (C + 1) + c] = fdims[c];
   }
@@ -284,6 +321,36 @@ using namespace spg;
 extern "C" {
 
 const char *spg_last_error(void) { return g_err.c_str(); }
+
+void spg_profile_enable(int32_t on) { g_prof = (on != 0); }
+
+void spg_profile_reset(void) {
+  for (auto &r : g_recs) {
+    (void)hipEventSynchronize(r.b);
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+}
+
+int spg_profile_query(const char *name, int64_t *count, double *total_ms, double *total_work) {
+  if (!name || !count || !total_ms) return fail(SPG_ERR_INVALID, "spg_profile_query: null argument");
+  int64_t n = 0;
+  double t = 0.0, wk = 0.0;
+  for (auto &r : g_recs) {
+    if (std::strcmp(r.name, name) != 0) continue;
+    if (hipEventSynchronize(r.b) != hipSuccess) return fail(SPG_ERR_HIP, "spg_profile_query: event");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return fail(SPG_ERR_HIP, "spg_profile_query: elapsed");
+    ++n;
+    t += ms;
+    wk += r.work;
+  }
+  *count = n;
+  *total_ms = t;
+  if (total_work) *total_work = wk;
+  return SPG_OK;
+}
 
 int spg_build_peps(const spg_instance_desc *desc, void *stream, spg_peps_t **out) {
   SPG_TRY
@@ -542,14 +609,15 @@ int spg_marginals(const spg_env_t *cenv, int32_t site, int32_t n_beam, const int
   set_e0(n_beam, chi, Rv + (size_t)C * chi, rstride, s);
   for (int cc = C - 1; cc > c; --cc)
     right_env_col(t, r, cc, n_beam, cfg, N, A + ((size_t)r * C + cc) * site_sz,
-                  Rv + (size_t)(cc + 1) * chi, Rv + (size_t)cc * chi, rstride, s);
+                  Rv + (size_t)(cc + 1) * chi, Rv + (size_t)cc * chi, rstride,
+                  env->dims[r * (C + 1) + cc], env->dims[r * (C + 1) + cc + 1], s);
   double *L = env->L[0].as<double>();
   int32_t *anc = env->anc[0].as<int32_t>();
   beam_reset_row(n_beam, chi, L, anc, s);
   for (int cc = 0; cc < c; ++cc)
     advance_L(t, r, cc, n_beam, cfg, N, A + ((size_t)r * C + cc) * site_sz, L, nullptr, s);
   marginals(t, r, c, n_beam, cfg, N, A + ((size_t)r * C + c) * site_sz, L, anc, Rv, rstride,
-            nullptr, log_cond_out, 0, s);
+            nullptr, log_cond_out, 0, env->dims[r * (C + 1) + c], env->dims[r * (C + 1) + c + 1], s);
   (void)d;
   return SPG_OK;
   SPG_CATCH
@@ -587,12 +655,14 @@ int spg_branch_and_bound(const spg_env_t *cenv, const spg_search_params *prm, in
     for (int c = C - 1; c >= 1; --c)
       right_env_col(t, r, c, n_anc, env->cfg[cur].as<uint8_t>(), N,
                     A + ((size_t)r * C + c) * site_sz, Rv + (size_t)(c + 1) * chi,
-                    Rv + (size_t)c * chi, rstride, s);
+                    Rv + (size_t)c * chi, rstride, env->dims[r * (C + 1) + c],
+                    env->dims[r * (C + 1) + c + 1], s);
     for (int c = 0; c < C; ++c) {
       const double *Arc = A + ((size_t)r * C + c) * site_sz;
       marginals(t, r, c, (int)B, env->cfg[cur].as<uint8_t>(), N, Arc, env->L[cur].as<double>(),
                 env->anc[cur].as<int32_t>(), Rv, rstride, env->score[cur].as<double>(),
-                env->cand.as<double>(), 1, s);
+                env->cand.as<double>(), 1, env->dims[r * (C + 1) + c],
+                env->dims[r * (C + 1) + c + 1], s);
       if (prm->cut_off_prob > 0.0) apply_cutoff((int)(B * d), log_cut, env->cand.as<double>(), s);
       const long Bn = std::min<long>(M, B * d);
       select_topm((int)(B * d), M, env->cand.as<double>(), env->sel.as<int32_t>(),
@@ -603,7 +673,8 @@ int spg_branch_and_bound(const spg_env_t *cenv, const spg_search_params *prm, in
                   env->anc[cur].as<int32_t>(), env->cand.as<double>(), Arc, c < C - 1,
                   env->cfg[nx].as<uint8_t>(), env->energy[nx].as<double>(),
                   env->score[nx].as<double>(), env->L[nx].as<double>(),
-                  env->anc[nx].as<int32_t>(), s);
+                  env->anc[nx].as<int32_t>(), env->dims[r * (C + 1) + c],
+                  env->dims[r * (C + 1) + c + 1], s);
       cur = nx;
       B = Bn;
     }

@@ -1,6 +1,7 @@
 // Dense FP64 linear algebra for the boundary-MPS compression on gfx950:
 // strided batched GEMM, Householder QR, one-sided Jacobi SVD of the small
 // projected matrix, the SplitMix64 sketch and box normalisation.
+#include <algorithm>
 #include <cmath>
 
 #include "spg_internal.h"
@@ -170,6 +171,93 @@ __global__ __launch_bounds__(1024) void k_qr(int m, int n, const double *X, long
   }
 }
 
+// LDS-resident Householder QR of one row block (in place: factor, write R,
+// then form Q over the reflectors as LAPACK dorg2r does).  Block b covers rows
+// [b*mb, min(m, (b+1)*mb)); missing rows are zero.  R_b goes to Rs + b*n*n
+// (row-major n x n), Q rows to Qo.
+constexpr int kQrLds = 18432;   // doubles of LDS for the panel (144 KiB)
+__global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const double *X, long xr,
+                                                long xc, double *Qo, long qr, long qc, double *Rs,
+                                                int want_q) {
+  __shared__ double W[kQrLds];
+  __shared__ double tau[kMaxSketch + 32];
+  __shared__ double red[16];
+  __shared__ double sh_beta;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  const int r0 = blockIdx.x * mb;
+  const int mr = min(mb, m - r0);          // real rows of this block
+  const int ld = max(mr, n);               // rows in LDS (zero rows appended if short)
+  for (int e = tid; e < ld * n; e += blockDim.x) {
+    const int i = e % ld, j = e / ld;
+    W[e] = (i < mr) ? X[(long)(r0 + i) * xr + (long)j * xc] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double *col = W + j * ld;
+    double loc = 0.0;
+    for (int i = j + 1 + tid; i < ld; i += blockDim.x) loc += col[i] * col[i];
+    const double sig = block_sum(loc, red);
+    const double alpha = col[j];
+    double tj = 0.0, sc = 0.0, beta = alpha;
+    if (sig != 0.0) {
+      const double nrm = sqrt(alpha * alpha + sig);
+      beta = (alpha >= 0.0) ? -nrm : nrm;
+      tj = (beta - alpha) / beta;
+      sc = 1.0 / (alpha - beta);
+    }
+    if (tj != 0.0)
+      for (int i = j + 1 + tid; i < ld; i += blockDim.x) col[i] *= sc;
+    __syncthreads();
+    if (tj != 0.0)
+      for (int k = j + 1 + wid; k < n; k += nw) {
+        double *ck = W + k * ld;
+        double dot = (lane == 0) ? ck[j] : 0.0;
+        for (int i = j + 1 + lane; i < ld; i += 64) dot += col[i] * ck[i];
+        dot = wave_sum(dot);
+        const double f = tj * dot;
+        if (lane == 0) ck[j] -= f;
+        for (int i = j + 1 + lane; i < ld; i += 64) ck[i] -= f * col[i];
+      }
+    if (tid == 0) { tau[j] = tj; sh_beta = beta; }
+    __syncthreads();
+    if (tid == 0) col[j] = sh_beta;
+    __syncthreads();
+  }
+  double *Rb = Rs + (long)blockIdx.x * n * n;
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    Rb[e] = (i <= j) ? W[j * ld + i] : 0.0;
+  }
+  if (!want_q) return;
+  __syncthreads();
+  // Q in place: for j = n-1 .. 0 apply H_j to columns j+1.., then column j = H_j e_j
+  for (int j = n - 1; j >= 0; --j) {
+    const double tj = tau[j];
+    double *v = W + j * ld;                  // v[i] for i > j, v[j] = 1 implicit
+    if (tj != 0.0)
+      for (int k = j + 1 + wid; k < n; k += nw) {
+        double *ck = W + k * ld;
+        double dot = (lane == 0) ? ck[j] : 0.0;
+        for (int i = j + 1 + lane; i < ld; i += 64) dot += v[i] * ck[i];
+        dot = wave_sum(dot);
+        const double f = tj * dot;
+        if (lane == 0) ck[j] -= f;
+        for (int i = j + 1 + lane; i < ld; i += 64) ck[i] -= f * v[i];
+      }
+    __syncthreads();
+    for (int i = tid; i < ld; i += blockDim.x) {
+      if (i < j) v[i] = 0.0;
+      else if (i == j) v[i] = 1.0 - tj;
+      else v[i] = -tj * v[i];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < mr * n; e += blockDim.x) {
+    const int i = e % mr, j = e / mr;
+    Qo[(long)(r0 + i) * qr + (long)j * qc] = W[j * ld + i];
+  }
+}
+
 // ---------------------------------------------------------------- Jacobi SVD
 // One-sided (Hestenes) Jacobi on the columns of an l x l matrix held in LDS,
 // round-robin pair ordering, one wavefront per column pair.
@@ -186,7 +274,18 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double
     V[j * l + i] = (i == j) ? 1.0 : 0.0;
   }
   const int le = (l + 1) & ~1;
+  __shared__ double sh_fro;
   __syncthreads();
+  // columns below (1e-17 |R|_F)^2 are numerically zero: rotating them only
+  // shuffles rounding noise, so they are left alone
+  if (wid == 0) {
+    double a = 0.0;
+    for (int e = lane; e < l * l; e += 64) a += W[e] * W[e];
+    a = wave_sum(a);
+    if (lane == 0) sh_fro = a;
+  }
+  __syncthreads();
+  const double tiny = 1e-34 * sh_fro;
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -203,7 +302,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double
           a += x * x; b += y * y; g += x * y;
         }
         a = wave_sum(a); b = wave_sum(b); g = wave_sum(g);
-        if (a > 0.0 && b > 0.0 && fabs(g) > 1e-15 * sqrt(a * b)) {
+        if (a > tiny && b > tiny && fabs(g) > 1e-14 * sqrt(a * b)) {
           const double zeta = (b - a) / (2.0 * g);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -254,32 +353,49 @@ __global__ void k_sketch(int n, int l, double *Om) {
   Om[e] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
 }
 
-__global__ __launch_bounds__(1024) void k_normalize_box(double *T, int n0, int n1, int n2,
-                                                       int n3, long s0, long s1, long s2,
-                                                       long s3, double *logs, int out,
-                                                       int in) {
+// Box normalisation in three deterministic stages: per-block partial sums of
+// squares (fixed block count and order), one block folds them and writes the
+// log-scale and 1/norm, then every block rescales.
+constexpr int kNormBlocks = 128;
+__device__ __forceinline__ long box_offset(long e, int n1, int n2, int n3, long s0, long s1,
+                                           long s2, long s3) {
+  const int i3 = e % n3; e /= n3;
+  const int i2 = e % n2; e /= n2;
+  const int i1 = e % n1; const long i0 = e / n1;
+  return i0 * s0 + i1 * s1 + i2 * s2 + i3 * s3;
+}
+
+__global__ __launch_bounds__(256) void k_box_sumsq(const double *T, long tot, int n1, int n2,
+                                                   int n3, long s0, long s1, long s2, long s3,
+                                                   double *part) {
   __shared__ double red[16];
-  const long tot = (long)n0 * n1 * n2 * n3;
   double acc = 0.0;
-  for (long e = threadIdx.x; e < tot; e += blockDim.x) {
-    long r = e;
-    const int i3 = r % n3; r /= n3;
-    const int i2 = r % n2; r /= n2;
-    const int i1 = r % n1; const int i0 = (int)(r / n1);
-    const double v = T[i0 * s0 + i1 * s1 + i2 * s2 + i3 * s3];
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x) {
+    const double v = T[box_offset(e, n1, n2, n3, s0, s1, s2, s3)];
     acc += v * v;
   }
-  const double ss = block_sum(acc, red);
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void k_box_fold(const double *part, int np, double *logs, int out, int in,
+                           double *inv_out) {
+  if (threadIdx.x != 0) return;
+  double ss = 0.0;
+  for (int i = 0; i < np; ++i) ss += part[i];
   const double nr = sqrt(ss);
-  const double inv = (nr > 0.0) ? 1.0 / nr : 1.0;
-  for (long e = threadIdx.x; e < tot; e += blockDim.x) {
-    long r = e;
-    const int i3 = r % n3; r /= n3;
-    const int i2 = r % n2; r /= n2;
-    const int i1 = r % n1; const int i0 = (int)(r / n1);
-    T[i0 * s0 + i1 * s1 + i2 * s2 + i3 * s3] *= inv;
-  }
-  if (threadIdx.x == 0) logs[out] = (in >= 0 ? logs[in] : 0.0) + (nr > 0.0 ? log(nr) : 0.0);
+  *inv_out = (nr > 0.0) ? 1.0 / nr : 1.0;
+  logs[out] = (in >= 0 ? logs[in] : 0.0) + (nr > 0.0 ? log(nr) : 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_box_scale(double *T, long tot, int n1, int n2, int n3,
+                                                   long s0, long s1, long s2, long s3,
+                                                   const double *inv) {
+  const double f = *inv;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x)
+    T[box_offset(e, n1, n2, n3, s0, s1, s2, s3)] *= f;
 }
 
 __global__ void k_fill_zero(double *p, size_t n) {
@@ -290,24 +406,81 @@ __global__ void k_fill_zero(double *p, size_t n) {
 }  // namespace
 
 void gemm_f64(const GemmDesc &g, hipStream_t s) {
+  KTimer kt_("gemm_f64", s, 2.0 * g.M * g.N * g.K * g.nb1 * g.nb2);
   if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
   dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.nb1 * g.nb2);
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
   SPG_CHECK_LAUNCH();
 }
 
+size_t qr_work_doubles(int m, int n) {
+  return 3 * (size_t)m * n + 2 * (size_t)kQrLds + 2 * (size_t)n * n + n + 64;
+}
+
 void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr, long qc,
             double *R, double *work, hipStream_t s) {
+  KTimer kt_("qr_f64", s, 4.0 * m * n * n - 4.0 * n * n * n / 3.0);
   if (m <= 0 || n <= 0) return;
   if (m < n) {
     set_error("qr_f64: needs rows >= columns");
     throw Fail{SPG_ERR_INVALID};
   }
-  hipLaunchKernelGGL(k_qr, dim3(1), dim3(1024), 0, s, m, n, X, xr, xc, Q, qr, qc, R, work);
+  if (n > kMaxSketch) {
+    set_error("qr_f64: more columns than supported");
+    throw Fail{SPG_ERR_UNSUPPORTED};
+  }
+  const int want_q = (Q != nullptr);
+  if ((long)m * n <= kQrLds) {
+    // one LDS-resident block; R straight to the caller (or to scratch)
+    double *Rd = R ? R : work;
+    hipLaunchKernelGGL(k_qr_lds, dim3(1), dim3(1024), 0, s, m, n, m, X, xr, xc, Q, qr, qc, Rd,
+                       want_q);
+    SPG_CHECK_LAUNCH();
+    return;
+  }
+  const int mb = kQrLds / n;                    // >= n since n <= kMaxSketch
+  const int p = (m + mb - 1) / mb;
+  if ((long)p * n * n <= kQrLds) {
+    // one level of TSQR: block QRs, QR of the stacked R factors, Q = diag(Q_b) Q_s
+    double *Q1 = work;                          // m x n row-major
+    double *S = Q1 + (long)m * n;               // p*n x n row-major (stacked R_b)
+    double *Qs = S + (long)p * n * n;           // p*n x n row-major
+    double *Rt = Qs + (long)p * n * n;          // n x n
+    hipLaunchKernelGGL(k_qr_lds, dim3(p), dim3(1024), 0, s, m, n, mb, X, xr, xc, Q1, (long)n, 1L,
+                       S, want_q);
+    SPG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_qr_lds, dim3(1), dim3(1024), 0, s, p * n, n, p * n, S, (long)n, 1L, Qs,
+                       (long)n, 1L, R ? R : Rt, want_q);
+    SPG_CHECK_LAUNCH();
+    if (!want_q) return;
+    const int full = m / mb, tail = m - full * mb;
+    GemmDesc g{};
+    g.N = n; g.K = n; g.nb2 = 1; g.alpha = 1.0; g.beta = 0.0;
+    g.a_i = n; g.a_k = 1; g.b_k = n; g.b_j = 1; g.c_i = qr; g.c_j = qc;
+    if (full > 0) {
+      g.M = mb; g.nb1 = full;
+      g.A = Q1; g.a_b1 = (long)mb * n;
+      g.B = Qs; g.b_b1 = (long)n * n;
+      g.C = Q; g.c_b1 = (long)mb * qr;
+      gemm_f64(g, s);
+    }
+    if (tail > 0) {
+      g.M = tail; g.nb1 = 1;
+      g.A = Q1 + (long)full * mb * n; g.a_b1 = 0;
+      g.B = Qs + (long)full * n * n; g.b_b1 = 0;
+      g.C = Q + (long)full * mb * qr; g.c_b1 = 0;
+      gemm_f64(g, s);
+    }
+    return;
+  }
+  // large panels: global-memory Householder in one workgroup
+  hipLaunchKernelGGL(k_qr, dim3(1), dim3(1024), 0, s, m, n, X, xr, xc, Q ? Q : work + 2L * m * n + n,
+                     Q ? qr : (long)n, Q ? qc : 1L, R, work);
   SPG_CHECK_LAUNCH();
 }
 
 void jacobi_svd_f64(int l, const double *Rm, double *V, double *sig, hipStream_t s) {
+  KTimer kt_("jacobi_svd_f64", s);
   if (l <= 0) return;
   if (l > kMaxSketch) {
     set_error("jacobi_svd_f64: size above the LDS limit");
@@ -325,9 +498,19 @@ void fill_sketch(int n, int l, double *Om, hipStream_t s) {
 }
 
 void normalize_box(double *T, int n0, int n1, int n2, int n3, long s0, long s1, long s2,
-                   long s3, double *logs, int out, int in, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize_box, dim3(1), dim3(1024), 0, s, T, n0, n1, n2, n3, s0, s1, s2,
-                     s3, logs, out, in);
+                   long s3, double *logs, int out, int in, double *scratch, hipStream_t s) {
+  KTimer kt_("normalize_box", s, 16.0 * n0 * n1 * n2 * n3);
+  const long tot = (long)n0 * n1 * n2 * n3;
+  if (tot <= 0) return;
+  const int nb = (int)std::min<long>(kNormBlocks, (tot + 255) / 256);
+  hipLaunchKernelGGL(k_box_sumsq, dim3(nb), dim3(256), 0, s, T, tot, n1, n2, n3, s0, s1, s2, s3,
+                     scratch);
+  SPG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_box_fold, dim3(1), dim3(64), 0, s, scratch, nb, logs, out, in,
+                     scratch + kNormBlocks);
+  SPG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_box_scale, dim3(nb), dim3(256), 0, s, T, tot, n1, n2, n3, s0, s1, s2, s3,
+                     scratch + kNormBlocks);
   SPG_CHECK_LAUNCH();
 }
 

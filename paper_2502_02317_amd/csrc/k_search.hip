@@ -459,7 +459,8 @@ __global__ __launch_bounds__(256) void k_advance_L(SearchTabs t, int r, int c, i
 
 void right_env_col(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *cfg, int N,
                    const double *A_rc, const double *Rnext, double *Rout, long rstride,
-                   hipStream_t s) {
+                   int cl, int cr, hipStream_t s) {
+  KTimer kt_("right_env", s, 2.0 * n_anc * cl * t.d * cr);
   if (n_anc <= 0) return;
   hipLaunchKernelGGL(k_right_env, dim3(nblk(n_anc, kWaves)), dim3(256), 0, s, t, r, c, n_anc,
                      cfg, N, A_rc, Rnext, Rout, rstride);
@@ -468,7 +469,9 @@ void right_env_col(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *
 
 void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
                const double *A_rc, const double *L, const int32_t *anc, const double *Rv,
-               long rstride, const double *score, double *out, int add_score, hipStream_t s) {
+               long rstride, const double *score, double *out, int add_score, int cl, int cr,
+               hipStream_t s) {
+  KTimer kt_("marginals", s, 2.0 * n_beam * t.d * cl * cr);
   if (n_beam <= 0) return;
   hipLaunchKernelGGL(k_marginals, dim3(nblk(n_beam, kWaves)), dim3(256), 0, s, t, r, c, n_beam,
                      cfg, N, A_rc, L, anc, Rv, rstride, score, out, add_score);
@@ -477,6 +480,7 @@ void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg
 
 void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *keys_work,
                  int32_t *ids_work, hipStream_t s) {
+  KTimer kt_("select_topm", s, 8.0 * n_cand + 4.0 * (M < n_cand ? M : n_cand));
   hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, n_cand, M, cand, sel, keys_work,
                      ids_work);
   SPG_CHECK_LAUNCH();
@@ -485,8 +489,9 @@ void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *
 void beam_update(const SearchTabs &t, int r, int c, int n_new, const int32_t *sel, int N,
                  const uint8_t *cfg, const double *energy, const double *L, const int32_t *anc,
                  const double *cand, const double *A_rc, int update_L, uint8_t *cfg_o,
-                 double *energy_o, double *score_o, double *L_o, int32_t *anc_o,
-                 hipStream_t s) {
+                 double *energy_o, double *score_o, double *L_o, int32_t *anc_o, int cl,
+                 int cr, hipStream_t s) {
+  KTimer kt_("beam_update", s, 2.0 * n_new * cl * cr);
   if (n_new <= 0) return;
   hipLaunchKernelGGL(k_beam_update, dim3(nblk(n_new, kWaves)), dim3(256), 0, s, t, r, c, n_new,
                      sel, N, cfg, energy, L, anc, cand, A_rc, update_L, cfg_o, energy_o,
@@ -503,6 +508,7 @@ void beam_reset_row(int n, int chi, double *L, int32_t *anc, hipStream_t s) {
 void final_sort(const SearchTabs &t, int n, int N, const uint8_t *cfg, const double *score,
                 int32_t *states_out, double *energies_out, double *logp_out, double *e_work,
                 int32_t *perm_work, int32_t *n_valid, hipStream_t s) {
+  KTimer kt_("final_sort", s);
   hipLaunchKernelGGL(k_energy, dim3(nblk(n, kWaves)), dim3(256), 0, s, t, n, N, cfg, e_work);
   SPG_CHECK_LAUNCH();
   uint64_t *kw = reinterpret_cast<uint64_t *>(e_work + n);

@@ -26,6 +26,15 @@ struct Fail {
   } while (0)
 #define SPG_CHECK_LAUNCH() SPG_HIP(hipGetLastError())
 
+// ---- opt-in per-launch timing (HIP events on the launch stream) ----------
+struct KTimer {
+  // `work`: algorithmic flops (or bytes for memory-bound classes) of the launch
+  KTimer(const char *name, hipStream_t s, double work = 0.0);
+  ~KTimer();
+  int slot = -1;
+  hipStream_t s = nullptr;
+};
+
 // ---- device buffers -------------------------------------------------------
 struct DevBuf {
   void *p = nullptr;
@@ -54,10 +63,12 @@ struct GemmDesc {
 };
 void gemm_f64(const GemmDesc &g, hipStream_t s);
 
-// Householder QR of an m x n matrix (m >= n), element (i,j) at X[i*xr + j*xc].
-// Writes Q (m x n, orthonormal columns) to Q[i*qr + j*qc] and, if R != nullptr,
-// the n x n upper-triangular factor to R[i*n + j] (row-major).  `work` holds
-// 2*m*n + n doubles.  One workgroup per call.
+// Householder QR of an m x n matrix (m >= n, n <= kMaxSketch), element (i,j) at
+// X[i*xr + j*xc].  Writes Q (m x n, orthonormal columns) to Q[i*qr + j*qc]
+// unless Q == nullptr and, if R != nullptr, the n x n upper-triangular factor
+// to R[i*n + j] (row-major).  Panels that fit in LDS are factored there (one
+// level of TSQR above that size); `work` holds qr_work_doubles(m, n) doubles.
+size_t qr_work_doubles(int m, int n);
 void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr, long qc,
             double *R, double *work, hipStream_t s);
 
@@ -71,8 +82,10 @@ void fill_sketch(int n, int l, double *Om, hipStream_t s);
 
 // Frobenius norm of a 4-index box (n0,n1,n2,n3 with strides) -> scales the box
 // by 1/norm and writes logs[out] = logs[in] + log(norm) (in < 0 means 0).
+// `scratch` holds kNormScratch doubles.
+constexpr int kNormScratch = 160;
 void normalize_box(double *T, int n0, int n1, int n2, int n3, long s0, long s1, long s2,
-                   long s3, double *logs, int out, int in, hipStream_t s);
+                   long s3, double *logs, int out, int in, double *scratch, hipStream_t s);
 void fill_zero(double *p, size_t n, hipStream_t s);
 
 // ---- boundary-MPS contraction kernels (k_bmps.hip) -------------------------
@@ -113,19 +126,21 @@ struct SearchTabs {         // device tables of the instance
   const double *E_loc, *E_h, *E_v, *E_d, *E_a;
   const double *W_v, *W_d, *W_a;
 };
+// cl, cr: actual bond dimensions left / right of column c (work accounting only)
 void right_env_col(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *cfg, int N,
                    const double *A_rc, const double *Rnext, double *Rout, long rstride,
-                   hipStream_t s);
+                   int cl, int cr, hipStream_t s);
 void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
                const double *A_rc, const double *L, const int32_t *anc, const double *Rv,
-               long rstride, const double *score, double *out, int add_score, hipStream_t s);
+               long rstride, const double *score, double *out, int add_score, int cl, int cr,
+               hipStream_t s);
 void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *keys_work,
                  int32_t *ids_work, hipStream_t s);
 void beam_update(const SearchTabs &t, int r, int c, int n_new, const int32_t *sel, int N,
                  const uint8_t *cfg, const double *energy, const double *L, const int32_t *anc,
                  const double *cand, const double *A_rc, int update_L, uint8_t *cfg_o,
-                 double *energy_o, double *score_o, double *L_o, int32_t *anc_o,
-                 hipStream_t s);
+                 double *energy_o, double *score_o, double *L_o, int32_t *anc_o, int cl,
+                 int cr, hipStream_t s);
 void beam_reset_row(int n, int chi, double *L, int32_t *anc, hipStream_t s);
 void final_sort(const SearchTabs &t, int n, int N, const uint8_t *cfg, const double *score,
                 int32_t *states_out, double *energies_out, double *logp_out, double *e_work,

@@ -46,7 +46,9 @@ class SearchParams(C.Structure):
 
 EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_branch_and_bound",
            "spg_free_peps", "spg_free_env", "spg_last_error", "spg_env_info", "spg_env_export",
-           "spg_env_import"]
+           "spg_env_import", "spg_profile_enable", "spg_profile_reset", "spg_profile_query"]
+KERNEL_CLASSES = ["gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box", "right_env",
+                  "marginals", "select_topm", "beam_update", "final_sort"]
 
 _lib = None
 
@@ -70,8 +72,13 @@ def load() -> C.CDLL:
     lib.spg_env_info.argtypes = [vp, i32p, i32p, i32p, i32p, vp]
     lib.spg_env_export.argtypes = [vp, vp, vp]
     lib.spg_env_import.argtypes = [vp, i32, vp, vp, vp, i32, vp, C.POINTER(vp)]
+    lib.spg_profile_enable.argtypes = [i32]
+    lib.spg_profile_enable.restype = None
+    lib.spg_profile_reset.argtypes = []
+    lib.spg_profile_reset.restype = None
+    lib.spg_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_int64), f64p, f64p]
     for name in ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_branch_and_bound",
-                 "spg_env_info", "spg_env_export", "spg_env_import"]:
+                 "spg_env_info", "spg_env_export", "spg_env_import", "spg_profile_query"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -206,6 +213,22 @@ def env_import(peps: Peps, chi: int, bond_dims, tensors, lam=None, precision: st
                               None if lm is None else lm.ctypes.data, PRECISION[precision],
                               _stream(stream), C.byref(h)))
     return Env(h, peps)
+
+
+def profile_enable(on: bool = True):
+    load().spg_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    load().spg_profile_reset()
+
+
+def profile_query(name: str):
+    """(launch count, summed milliseconds, summed algorithmic work) of a timed
+    kernel class since the last reset."""
+    n, t, w = C.c_int64(0), C.c_double(0.0), C.c_double(0.0)
+    _check(load().spg_profile_query(name.encode(), C.byref(n), C.byref(t), C.byref(w)))
+    return n.value, t.value, w.value
 
 
 def pack_oracle_mps(A_rows, chi: int, d: int):
