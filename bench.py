@@ -27,6 +27,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# truncated SVD: randomized range finder, oversampling 16, one power iteration
 WORKLOAD = dict(name="kings8x8_d16", seed=0, chi=32, max_states=1024, num_sweeps=1,
                 oversample=16, power_iters=1)
 # MI355X published peaks

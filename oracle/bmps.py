@@ -35,7 +35,7 @@ from __future__ import annotations
 import numpy as np
 
 from .energy import Weights
-from .linalg import tsvd_left, tsvd_right
+from .linalg import tsvd_left, tsvd_right, drop_null
 
 
 def row_weights(W: Weights, r: int):
@@ -110,11 +110,13 @@ def _norm(T):
 
 
 def right_canonicalize(phi):
-    """LQ sweep from the right: phi_c (c >= 1) become right isometries."""
+    """LQ sweep from the right: phi_c (c >= 1) become right isometries (partial
+    ones where a direction sits at the rounding floor, see linalg.drop_null)."""
     phi = [t.copy() for t in phi]
     for c in range(len(phi) - 1, 0, -1):
         bl, d, br = phi[c].shape
         Q, Rr = np.linalg.qr(phi[c].reshape(bl, d * br).T, mode="reduced")
+        Q, Rr = drop_null(Q, Rr)           # directions of M^T = Q R weigh |row of R|
         k = Q.shape[1]
         phi[c] = Q.T.reshape(k, d, br)
         phi[c - 1] = np.einsum("pxq,kq->pxk", phi[c - 1], Rr)

@@ -13,8 +13,13 @@ finder with subspace (power) iteration of Halko, Martinsson and Tropp (SIAM
 Review 53, 2011, Alg. 4.4 + 5.1): sketch width l = min(k + p, m, n), a fixed
 sketch matrix Omega whose entries are SplitMix64 outputs mapped to [-1, 1), q
 power iterations with re-orthonormalisation, then the exact SVD of the small
-projected matrix.  When rank(B) <= l the result is the exact truncated SVD.
-Pinned against numpy's dense SVD in tests/test_oracle_linalg.py.
+projected matrix (skipped when l = k: the kept subspace is then span(Q)).
+When rank(B) <= l the result is the exact truncated SVD.
+Directions of the kept subspace whose weight in B (the norm of their row of
+U^T B) is at most NULL_TOL times the largest weight lie at the rounding floor;
+any orthonormal completion could stand there, so they are discarded (zeroed)
+to keep the result unique.  Pinned against numpy's dense SVD in
+tests/test_oracle_linalg.py.
 """
 from __future__ import annotations
 
@@ -24,6 +29,7 @@ GOLDEN = 0x9E3779B97F4A7C15
 MASK = (1 << 64) - 1
 SKETCH_SEED = 0x5EED5EED12345678
 SKETCH_LD = 1024            # row stride of the fixed sketch table
+NULL_TOL = 1e-11
 
 
 def splitmix64(seed: int, idx) -> np.ndarray:
@@ -62,10 +68,27 @@ def tsvd_left(B: np.ndarray, k: int, p: int, q: int):
     for _ in range(q):
         Qz = orth(B.T @ Q)
         Q = orth(B @ Qz)
-    Csm = Q.T @ B                               # l x n
-    Us, s, _ = np.linalg.svd(Csm, full_matrices=False)
-    U = Q @ Us[:, :kk]
-    return U, U.T @ B
+    if l == kk:
+        # the sketch width is the kept rank: the subspace is span(Q) itself
+        U = Q
+    else:
+        Csm = Q.T @ B                           # l x n
+        Us, s, _ = np.linalg.svd(Csm, full_matrices=False)
+        U = Q @ Us[:, :kk]
+    return drop_null(U, U.T @ B)
+
+
+def drop_null(U, Rm):
+    """Zero the directions (columns of U, rows of Rm) whose weight, the norm of
+    their row of Rm, is at most NULL_TOL times the largest."""
+    w = np.linalg.norm(Rm, axis=1)
+    if w.size and w.max() > 0:
+        null = w <= NULL_TOL * w.max()
+        U = U.copy()
+        Rm = Rm.copy()
+        U[:, null] = 0.0
+        Rm[null, :] = 0.0
+    return U, Rm
 
 
 def tsvd_right(B: np.ndarray, k: int, p: int, q: int):

@@ -87,7 +87,7 @@ static int fail(int code, const std::string &m) {
 struct BmpsWork {
   int R, C, d, chi, lmax;
   DevBuf EL, ER, T1, P, Qr, P2, Q2, G1, G2, B, Y, Q, Z, Qz, Om, Cm, Qc, Rc, V, sig, U, Rm,
-      qrwork, tmp, logs, psi0, nscr;
+      qrwork, tmp, logs, psi0, nscr, ident;
   size_t env_sz() const { return (size_t)chi * d * d * chi; }
   size_t site_sz() const { return (size_t)chi * d * chi; }
   double *ELc(int c) { return EL.as<double>() + (size_t)c * env_sz(); }
@@ -110,6 +110,7 @@ struct BmpsWork {
     Rm.ensure(ml);
     qrwork.ensure(qr_work_doubles((int)mn, lmax) * sizeof(double));
     nscr.ensure(kNormScratch * sizeof(double));
+    ident.ensure((size_t)lmax * lmax * sizeof(double));
     tmp.ensure(site_sz() * sizeof(double));
     logs.ensure((size_t)(2 * C + 8 + R) * sizeof(double));
     psi0.ensure(site_sz() * C * sizeof(double));
@@ -146,6 +147,11 @@ static int tsvd_left(BmpsWork &w, const double *B, long br, long bc, int m, int 
     mm(m, l, n, B, br, bc, Qz, l, 1, Y, l, 1);               // Y = B Qz
     qr_f64(m, l, Y, l, 1, Q, l, 1, nullptr, qw, s);
   }
+  if (l == kk) {
+    // sketch width = kept rank: U U^T B only depends on span(Q), so U = Q
+    mm(m, kk, l, Q, l, 1, w.ident.as<double>(), w.lmax, 1, U, ur, uc);
+    return kk;
+  }
   mm(l, n, m, Q, 1, l, B, br, bc, Cm, n, 1);                 // Cm = Q^T B   (l x n)
   qr_f64(n, l, Cm, 1, n, nullptr, l, 1, w.Rc.as<double>(), qw, s);  // Cm^T = Qc Rc (R only)
   jacobi_svd_f64(l, w.Rc.as<double>(), w.V.as<double>(), w.sig.as<double>(), s);
@@ -178,6 +184,11 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
   w.lmax = std::min(chi + std::max(prm->oversample, 0), chi * d);
   w.alloc();
   const size_t site = w.site_sz(), es = w.env_sz();
+  {
+    std::vector<double> I((size_t)w.lmax * w.lmax, 0.0);
+    for (int i = 0; i < w.lmax; ++i) I[(size_t)i * w.lmax + i] = 1.0;
+    SPG_HIP(hipMemcpy(w.ident.p, I.data(), I.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
   double *A = env->A.as<double>();
   double *logs = w.logs.as<double>();
   // log slots: EL[c] at c, ER[c] at C+1+c, centre at 2C+2, lam[r] at 2C+4+r
@@ -211,6 +222,8 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
       // QR of Mc^T (d*br x bl): Q -> new right isometry, R folded into phi_{c-1}
       qr_f64(d * br, bl, Mc, 1, (long)d * br, w.Qc.as<double>(), bl, 1, w.Rc.as<double>(),
              w.qrwork.as<double>(), s);
+      // direction i of M^T = Q R weighs |row i of R|
+      drop_null(bl, bl, w.Rc.as<double>(), bl, 1, w.Qc.as<double>(), d * br, 1, bl, s);
       fill_zero(phi + c * site, site, s);
       unpack_right(d, chi, bl, br, w.Qc.as<double>(), 1, bl, phi + c * site, s);
       lq_fold(d, chi, bl, bl, w.Rc.as<double>(), phi + (c - 1) * site, w.tmp.as<double>(), s);
@@ -254,17 +267,20 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
         g.B = Bm; g.b_k = n; g.b_j = 1;
         g.C = w.Rm.as<double>(); g.c_i = n; g.c_j = 1;
         gemm_f64(g, s);
+        drop_null(kk, n, w.Rm.as<double>(), n, 1, phic, m, 1, chi, s);
         unpack_right(d, chi, kk, pr, w.Rm.as<double>(), n, 1, phin, s);
       } else {
         // tsvd of B^T (n x m): U' (n x kk) -> phi_{c+1} = U'^T;  phi_c = B U'
         double *Up = w.U.as<double>();
         kk = tsvd_left(w, Bm, 1, n, n, m, k, prm->oversample, prm->power_iters, Up, k, 1, s);
-        unpack_right(d, chi, kk, pr, Up, 1, k, phin, s);
         g.M = m; g.N = kk; g.K = n;
         g.A = Bm; g.a_i = n; g.a_k = 1;
         g.B = Up; g.b_k = k; g.b_j = 1;
         g.C = phic; g.c_i = chi; g.c_j = 1;
         gemm_f64(g, s);
+        // weight of direction i = column i of B U'
+        drop_null(kk, m, phic, 1, chi, Up, n, 1, k, s);
+        unpack_right(d, chi, kk, pr, Up, 1, k, phin, s);
       }
       fdims[c + 1] = kk;
     };

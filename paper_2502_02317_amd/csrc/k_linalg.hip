@@ -5,15 +5,12 @@
 #include <cmath>
 
 #include "spg_internal.h"
+#include "wave.h"
 
 namespace spg {
 
 namespace {
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // Block-wide sum; every thread receives the result.  `red` holds >= 16 doubles.
 __device__ double block_sum(double v, double *red) {
@@ -182,7 +179,6 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
   __shared__ double W[kQrLds];
   __shared__ double tau[kMaxSketch + 32];
   __shared__ double red[16];
-  __shared__ double sh_beta;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
   const int r0 = blockIdx.x * mb;
   const int mr = min(mb, m - r0);          // real rows of this block
@@ -192,11 +188,19 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
     W[e] = (i < mr) ? X[(long)(r0 + i) * xr + (long)j * xc] : 0.0;
   }
   __syncthreads();
+  // squared norm of column 0 below the diagonal; later columns get theirs from
+  // the wavefront that applies the previous reflector to them (lookahead)
+  __shared__ double sh_sig;
+  {
+    double loc = 0.0;
+    for (int i = 1 + tid; i < ld; i += blockDim.x) loc += W[i] * W[i];
+    const double t = block_sum(loc, red);
+    if (tid == 0) sh_sig = t;
+  }
+  __syncthreads();
   for (int j = 0; j < n; ++j) {
     double *col = W + j * ld;
-    double loc = 0.0;
-    for (int i = j + 1 + tid; i < ld; i += blockDim.x) loc += col[i] * col[i];
-    const double sig = block_sum(loc, red);
+    const double sig = sh_sig;
     const double alpha = col[j];
     double tj = 0.0, sc = 0.0, beta = alpha;
     if (sig != 0.0) {
@@ -208,9 +212,10 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
     if (tj != 0.0)
       for (int i = j + 1 + tid; i < ld; i += blockDim.x) col[i] *= sc;
     __syncthreads();
-    if (tj != 0.0)
-      for (int k = j + 1 + wid; k < n; k += nw) {
-        double *ck = W + k * ld;
+    if (tid == 0) { tau[j] = tj; col[j] = beta; }
+    for (int k = j + 1 + wid; k < n; k += nw) {
+      double *ck = W + k * ld;
+      if (tj != 0.0) {
         double dot = (lane == 0) ? ck[j] : 0.0;
         for (int i = j + 1 + lane; i < ld; i += 64) dot += col[i] * ck[i];
         dot = wave_sum(dot);
@@ -218,9 +223,13 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
         if (lane == 0) ck[j] -= f;
         for (int i = j + 1 + lane; i < ld; i += 64) ck[i] -= f * col[i];
       }
-    if (tid == 0) { tau[j] = tj; sh_beta = beta; }
-    __syncthreads();
-    if (tid == 0) col[j] = sh_beta;
+      if (k == j + 1) {
+        double a = 0.0;
+        for (int i = j + 2 + lane; i < ld; i += 64) a += ck[i] * ck[i];
+        a = wave_sum(a);
+        if (lane == 0) sh_sig = a;
+      }
+    }
     __syncthreads();
   }
   double *Rb = Rs + (long)blockIdx.x * n * n;
@@ -259,25 +268,27 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
 }
 
 // ---------------------------------------------------------------- Jacobi SVD
-// One-sided (Hestenes) Jacobi on the columns of an l x l matrix held in LDS,
-// round-robin pair ordering, one wavefront per column pair.
+// Right singular vectors of an upper-triangular l x l factor R (row-major):
+// one-sided (Hestenes) Jacobi orthogonalises the columns of R^T (faster than
+// R's own columns for a triangular factor); R^T J = X Sigma gives the wanted
+// vectors as the normalised columns of X, so no rotations are accumulated.
+// Round-robin pair ordering, one wavefront per pair.  The sorted columns are
+// then checked for orthonormality and, if off by more than 1e-13 (directions
+// with singular values near rounding), re-orthonormalised by CGS2 with a
+// deterministic completion from the unit vectors.
 __global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double *Vo,
                                                 double *sig) {
   __shared__ double W[kMaxSketch * kMaxSketch];
   __shared__ double V[kMaxSketch * kMaxSketch];
   __shared__ double nrm[kMaxSketch];
-  __shared__ int rotated;
+  __shared__ double hbuf[kMaxSketch];
+  __shared__ int rotated, bad;
+  __shared__ double sh_fro, sh_nv;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
-  for (int e = tid; e < l * l; e += blockDim.x) {
-    const int i = e / l, j = e % l;          // Rm row-major; W, V column-major
-    W[j * l + i] = Rm[e];
-    V[j * l + i] = (i == j) ? 1.0 : 0.0;
-  }
+  // W column-major with column j = row j of R, i.e. W = R^T; same storage as Rm
+  for (int e = tid; e < l * l; e += blockDim.x) W[e] = Rm[e];
   const int le = (l + 1) & ~1;
-  __shared__ double sh_fro;
   __syncthreads();
-  // columns below (1e-17 |R|_F)^2 are numerically zero: rotating them only
-  // shuffles rounding noise, so they are left alone
   if (wid == 0) {
     double a = 0.0;
     for (int e = lane; e < l * l; e += 64) a += W[e] * W[e];
@@ -285,6 +296,8 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double
     if (lane == 0) sh_fro = a;
   }
   __syncthreads();
+  // columns below (1e-17 |R|_F)^2 are numerically zero: rotating them only
+  // shuffles rounding noise, so they are left alone
   const double tiny = 1e-34 * sh_fro;
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) rotated = 0;
@@ -310,9 +323,6 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double
             const double x = W[p * l + r], y = W[q * l + r];
             W[p * l + r] = cs * x - sn * y;
             W[q * l + r] = sn * x + cs * y;
-            const double vx = V[p * l + r], vy = V[q * l + r];
-            V[p * l + r] = cs * vx - sn * vy;
-            V[q * l + r] = sn * vx + cs * vy;
           }
           if (lane == 0) rotated = 1;
         }
@@ -329,12 +339,69 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double
     if (lane == 0) nrm[j] = sqrt(a);
   }
   __syncthreads();
-  for (int j = tid; j < l; j += blockDim.x) {
+  // sorted, normalised columns into V (column-major)
+  for (int j = wid; j < l; j += nw) {
     int rank = 0;
-    for (int i = 0; i < l; ++i)
-      rank += (nrm[i] > nrm[j]) || (nrm[i] == nrm[j] && i < j);
-    sig[rank] = nrm[j];
-    for (int r = 0; r < l; ++r) Vo[r * l + rank] = V[j * l + r];
+    for (int i = 0; i < l; ++i) rank += (nrm[i] > nrm[j]) || (nrm[i] == nrm[j] && i < j);
+    const double inv = (nrm[j] > 0.0) ? 1.0 / nrm[j] : 0.0;
+    for (int r = lane; r < l; r += 64) V[rank * l + r] = W[j * l + r] * inv;
+    if (lane == 0) sig[rank] = nrm[j];
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int e = wid; e < l * l; e += nw) {
+    const int i = e / l, j = e % l;
+    if (j > i) continue;
+    double g = 0.0;
+    for (int r = lane; r < l; r += 64) g += V[i * l + r] * V[j * l + r];
+    g = wave_sum(g);
+    if (lane == 0 && fabs(g - (i == j ? 1.0 : 0.0)) > 1e-13) bad = 1;
+  }
+  __syncthreads();
+  if (bad) {
+    // CGS2 in sorted order; a column that loses its norm is replaced by the
+    // first unit vector that survives the projection
+    for (int i = 0; i < l; ++i) {
+      int cand = -1;
+      for (;;) {
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int j = wid; j < i; j += nw) {
+            double g = 0.0;
+            for (int r = lane; r < l; r += 64) g += V[j * l + r] * V[i * l + r];
+            g = wave_sum(g);
+            if (lane == 0) hbuf[j] = g;
+          }
+          __syncthreads();
+          for (int r = tid; r < l; r += blockDim.x) {
+            double acc = V[i * l + r];
+            for (int j = 0; j < i; ++j) acc -= hbuf[j] * V[j * l + r];
+            V[i * l + r] = acc;
+          }
+          __syncthreads();
+        }
+        if (wid == 0) {
+          double a = 0.0;
+          for (int r = lane; r < l; r += 64) a += V[i * l + r] * V[i * l + r];
+          a = wave_sum(a);
+          if (lane == 0) sh_nv = sqrt(a);
+        }
+        __syncthreads();
+        const double nv = sh_nv;
+        if (nv > 0.5 || cand >= l - 1) {
+          const double inv = (nv > 0.0) ? 1.0 / nv : 0.0;
+          for (int r = tid; r < l; r += blockDim.x) V[i * l + r] *= inv;
+          __syncthreads();
+          break;
+        }
+        ++cand;
+        for (int r = tid; r < l; r += blockDim.x) V[i * l + r] = (r == cand) ? 1.0 : 0.0;
+        __syncthreads();
+      }
+    }
+  }
+  for (int e = tid; e < l * l; e += blockDim.x) {
+    const int r = e / l, c = e % l;      // Vo row-major
+    Vo[e] = V[c * l + r];
   }
 }
 
@@ -396,6 +463,39 @@ __global__ __launch_bounds__(256) void k_box_scale(double *T, long tot, int n1, 
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
        e += (long)gridDim.x * blockDim.x)
     T[box_offset(e, n1, n2, n3, s0, s1, s2, s3)] *= f;
+}
+
+// Zero the directions whose weight (norm of their row of Wm) is at most
+// 1e-11 of the largest: direction i is row i of Wm (len entries, element
+// stride w_el, row stride w_dir) and column i of U (ulen entries).
+__global__ __launch_bounds__(1024) void k_drop_null(int nd, int len, double *Wm, long w_dir,
+                                                   long w_el, double *U, int ulen, long u_dir,
+                                                   long u_el) {
+  __shared__ double wn[kMaxSketch + 32];
+  __shared__ double wmax;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int i = wid; i < nd; i += nw) {
+    double a = 0.0;
+    for (int e = lane; e < len; e += 64) {
+      const double v = Wm[i * w_dir + e * w_el];
+      a += v * v;
+    }
+    a = wave_sum(a);
+    if (lane == 0) wn[i] = sqrt(a);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int i = 0; i < nd; ++i) m = fmax(m, wn[i]);
+    wmax = m;
+  }
+  __syncthreads();
+  const double thr = 1e-11 * wmax;
+  for (int i = wid; i < nd; i += nw) {
+    if (!(wn[i] <= thr) || wmax == 0.0) continue;
+    for (int e = lane; e < len; e += 64) Wm[i * w_dir + e * w_el] = 0.0;
+    for (int e = lane; e < ulen; e += 64) U[i * u_dir + e * u_el] = 0.0;
+  }
 }
 
 __global__ void k_fill_zero(double *p, size_t n) {
@@ -511,6 +611,18 @@ void normalize_box(double *T, int n0, int n1, int n2, int n3, long s0, long s1, 
   SPG_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_box_scale, dim3(nb), dim3(256), 0, s, T, tot, n1, n2, n3, s0, s1, s2, s3,
                      scratch + kNormBlocks);
+  SPG_CHECK_LAUNCH();
+}
+
+void drop_null(int nd, int len, double *Wm, long w_dir, long w_el, double *U, int ulen,
+               long u_dir, long u_el, hipStream_t s) {
+  if (nd <= 0) return;
+  if (nd > kMaxSketch + 32) {
+    set_error("drop_null: too many directions");
+    throw Fail{SPG_ERR_UNSUPPORTED};
+  }
+  hipLaunchKernelGGL(k_drop_null, dim3(1), dim3(1024), 0, s, nd, len, Wm, w_dir, w_el, U, ulen,
+                     u_dir, u_el);
   SPG_CHECK_LAUNCH();
 }
 

@@ -14,6 +14,7 @@
 #include <climits>
 
 #include "spg_internal.h"
+#include "wave.h"
 
 namespace spg {
 
@@ -21,14 +22,6 @@ namespace {
 
 inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-__device__ __forceinline__ double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // g^b_c(s): couplings of x_{r,c} = s to the fixed row above (1 for r = 0).
 __device__ __forceinline__ double field(const SearchTabs &t, int r, int c, const uint8_t *cb,
@@ -93,7 +86,7 @@ __global__ __launch_bounds__(256) void k_right_env(SearchTabs t, int r, int c, i
     }
     v[h] = acc;
   }
-  const double m = wave_max(fmax(fabs(v[0]), fabs(v[1])));
+  const double m = wave_max_nonneg(fmax(fabs(v[0]), fabs(v[1])));
   const double inv = (m > 0.0) ? 1.0 / m : 1.0;
   for (int h = 0; h < 2; ++h) {
     const int al = lane + 64 * h;
@@ -321,7 +314,7 @@ __global__ __launch_bounds__(256) void k_beam_update(SearchTabs t, int r, int c,
     for (int al = 0; al < chi; ++al) acc += Ls[w][al] * A[((long)al * d + s) * chi + bp];
     v[h] = g * acc;
   }
-  const double m = wave_max(fmax(fabs(v[0]), fabs(v[1])));
+  const double m = wave_max_nonneg(fmax(fabs(v[0]), fabs(v[1])));
   const double inv = (m > 0.0) ? 1.0 / m : 1.0;
   for (int h = 0; h < 2; ++h) {
     const int bp = lane + 64 * h;
@@ -447,7 +440,7 @@ __global__ __launch_bounds__(256) void k_advance_L(SearchTabs t, int r, int c, i
     for (int al = 0; al < chi; ++al) acc += Ls[w][al] * A[((long)al * d + s) * chi + bp];
     v[h] = g * acc;
   }
-  const double m = wave_max(fmax(fabs(v[0]), fabs(v[1])));
+  const double m = wave_max_nonneg(fmax(fabs(v[0]), fabs(v[1])));
   const double inv = (m > 0.0) ? 1.0 / m : 1.0;
   for (int h = 0; h < 2; ++h) {
     const int bp = lane + 64 * h;

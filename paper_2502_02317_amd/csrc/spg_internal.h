@@ -87,6 +87,11 @@ constexpr int kNormScratch = 160;
 void normalize_box(double *T, int n0, int n1, int n2, int n3, long s0, long s1, long s2,
                    long s3, double *logs, int out, int in, double *scratch, hipStream_t s);
 void fill_zero(double *p, size_t n, hipStream_t s);
+// Directions at the rounding floor of a truncation are not unique: zero every
+// direction i (row i of Wm, column i of U) whose weight |Wm row i| is at most
+// 1e-11 of the largest.
+void drop_null(int nd, int len, double *Wm, long w_dir, long w_el, double *U, int ulen,
+               long u_dir, long u_el, hipStream_t s);
 
 // ---- boundary-MPS contraction kernels (k_bmps.hip) -------------------------
 struct RowFactors {         // device d x d tables (row-major) / d vectors of one column

@@ -1,0 +1,46 @@
+// Wavefront (64-lane) reductions on gfx950 through DPP lane moves, which stay
+// in the VALU instead of round-tripping through LDS like a permute shuffle.
+// All 64 lanes must be active where these are called.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace spg {
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane63(double v) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the wave, returned to every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0xB1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);         // quad_perm [2,3,0,1]
+  v += dpp_move<0x124>(v);        // row_ror:4
+  v += dpp_move<0x128>(v);        // row_ror:8  -> every lane holds its row sum
+  v += dpp_move<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3 -> lane 63 = total
+  return lane63(v);
+}
+
+// Max over the wave, returned to every lane (max(x, 0-fill) is safe for the
+// non-negative arguments it is used with).
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+  v = fmax(v, dpp_move<0xB1>(v));
+  v = fmax(v, dpp_move<0x4E>(v));
+  v = fmax(v, dpp_move<0x124>(v));
+  v = fmax(v, dpp_move<0x128>(v));
+  v = fmax(v, dpp_move<0x142, 0xA>(v));
+  v = fmax(v, dpp_move<0x143, 0xC>(v));
+  return lane63(v);
+}
+
+}  // namespace spg

@@ -76,15 +76,16 @@ def test_config1_logZ(seed):
     assert abs(lz - bf["logZ"]) < 1e-9
 
 
-@pytest.mark.parametrize("chi,sweeps", [(3, 1), (5, 2), (8, 1)])
-def test_truncated_bmps_matches_oracle(chi, sweeps):
+@pytest.mark.parametrize("chi,sweeps,p,q", [(3, 1, 16, 1), (5, 2, 16, 1), (8, 1, 16, 1),
+                                           (6, 1, 16, 2), (4, 2, 24, 1)])
+def test_truncated_bmps_matches_oracle(chi, sweeps, p, q):
     """Well-conditioned king's lattice with truncation active: same protocol,
     same result (log Z, log-scales and every row function)."""
     si = spin_instance(4, 5, 2, True, seed=6, h=("normal", 1.0), j_in=("normal", 1.0),
                        j_out=("normal", 0.4))
     inst = potts_from_spins(si, beta=0.5)
-    _, env, lz = _gpu_mps(inst, chi, num_sweeps=sweeps)
-    ora = oracle_bmps(inst, chi, num_sweeps=sweeps)
+    _, env, lz = _gpu_mps(inst, chi, num_sweeps=sweeps, oversample=p, power_iters=q)
+    ora = oracle_bmps(inst, chi, num_sweeps=sweeps, p=p, q=q)
     assert abs(lz - ora["logZ"]) < 1e-9
     rows, lam = _rows_dense(env)
     np.testing.assert_allclose(lam, ora["lam"], atol=1e-9)

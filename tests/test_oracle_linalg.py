@@ -22,7 +22,11 @@ def test_tsvd_exact_when_rank_fits(m, n, r, k):
     rng = np.random.default_rng(m + n)
     B = rng.normal(size=(m, r)) @ rng.normal(size=(r, n))
     U, Rm = tsvd_left(B, k, 16, 1)
-    np.testing.assert_allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
+    # an isometry on the kept directions; directions beyond rank(B) carry no
+    # weight and are zeroed (the null-direction rule)
+    G = U.T @ U
+    np.testing.assert_allclose(G, np.diag(np.round(np.diag(G))), atol=1e-12)
+    assert int(round(np.trace(G))) == min(r, k, U.shape[1])
     if r <= k:
         np.testing.assert_allclose(U @ Rm, B, atol=1e-10 * np.abs(B).max())
     s_ref = np.linalg.svd(B, compute_uv=False)[: U.shape[1]]
