@@ -87,7 +87,7 @@ static int fail(int code, const std::string &m) {
 struct BmpsWork {
   int R, C, d, chi, lmax;
   DevBuf EL, ER, T1, P, Qr, P2, Q2, G1, G2, B, Y, Q, Z, Qz, Om, Cm, Qc, Rc, V, sig, U, Rm,
-      qrwork, tmp, logs, psi0, nscr, ident;
+      qrwork, tmp, logs, psi0, nscr, ident, skws;
   size_t env_sz() const { return (size_t)chi * d * d * chi; }
   size_t site_sz() const { return (size_t)chi * d * chi; }
   double *ELc(int c) { return EL.as<double>() + (size_t)c * env_sz(); }
@@ -111,6 +111,7 @@ struct BmpsWork {
     qrwork.ensure(qr_work_doubles((int)mn, lmax) * sizeof(double));
     nscr.ensure(kNormScratch * sizeof(double));
     ident.ensure((size_t)lmax * lmax * sizeof(double));
+    skws.ensure(16 * mn * lmax * sizeof(double));
     tmp.ensure(site_sz() * sizeof(double));
     logs.ensure((size_t)(2 * C + 8 + R) * sizeof(double));
     psi0.ensure(site_sz() * C * sizeof(double));
@@ -136,6 +137,7 @@ static int tsvd_left(BmpsWork &w, const double *B, long br, long bc, int m, int 
     g.B = Bp; g.b_k = bk; g.b_j = bj;
     g.C = Cp; g.c_i = ci; g.c_j = cj;
     g.alpha = 1.0; g.beta = 0.0;
+    g.ws = w.skws.as<double>(); g.ws_len = w.skws.bytes / sizeof(double);
     gemm_f64(g, s);
   };
   double *qw = w.qrwork.as<double>();

@@ -36,21 +36,23 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
   __shared__ double Bs[16][65];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  // split-K chunks: chunk b1 covers global k in [b1*K, min((b1+1)*K, kmax))
+  const int Kend = (g.kmax > 0) ? min(g.K, g.kmax - b1 * g.K) : g.K;
   double acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
+  for (int k0 = 0; k0 < Kend; k0 += 16) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int r = e >> 4, kk = e & 15;
       const int gi = i0 + r, gk = k0 + kk;
-      As[kk][r] = (gi < g.M && gk < g.K) ? A[gi * g.a_i + gk * g.a_k] : 0.0;
+      As[kk][r] = (gi < g.M && gk < Kend) ? A[gi * g.a_i + gk * g.a_k] : 0.0;
       const int kb = e >> 6, cb = e & 63;
       const int gkb = k0 + kb, gj = j0 + cb;
-      Bs[kb][cb] = (gkb < g.K && gj < g.N) ? B[gkb * g.b_k + gj * g.b_j] : 0.0;
+      Bs[kb][cb] = (gkb < Kend && gj < g.N) ? B[gkb * g.b_k + gj * g.b_j] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -80,6 +82,19 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
       *cp = (g.beta != 0.0) ? v + g.beta * (*cp) : v;
     }
   }
+}
+
+// Deterministic split-K epilogue: C = alpha * sum_s P[s] + beta * C (P: [S][M][N]).
+__global__ void k_splitk_reduce(int M, int N, int S, const double *P, double *C, long c_i,
+                                long c_j, double alpha, double beta) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)M * N) return;
+  double acc = 0.0;
+  for (int s = 0; s < S; ++s) acc += P[(long)s * M * N + e];
+  const int i = (int)(e / N), j = (int)(e % N);
+  double *cp = C + i * c_i + j * c_j;
+  const double v = alpha * acc;
+  *cp = (beta != 0.0) ? v + beta * (*cp) : v;
 }
 
 // ---------------------------------------------------------------- QR
@@ -296,10 +311,11 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double
     if (lane == 0) sh_fro = a;
   }
   __syncthreads();
-  // columns below (1e-17 |R|_F)^2 are numerically zero: rotating them only
-  // shuffles rounding noise, so they are left alone
-  const double tiny = 1e-34 * sh_fro;
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  // columns below 1e-13 |R|_F sit at the rounding floor (the truncation drops
+  // such directions anyway) and off-diagonal mass below 1e-30 |R|_F^2 is
+  // rounding noise: rotating either only shuffles noise, so both are skipped
+  const double tiny = 1e-26 * sh_fro, gfloor = 1e-30 * sh_fro;
+  for (int sweep = 0; sweep < 30; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int t = 0; t < le - 1; ++t) {
@@ -315,7 +331,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double
           a += x * x; b += y * y; g += x * y;
         }
         a = wave_sum(a); b = wave_sum(b); g = wave_sum(g);
-        if (a > tiny && b > tiny && fabs(g) > 1e-14 * sqrt(a * b)) {
+        if (a > tiny && b > tiny && fabs(g) > gfloor && fabs(g) > 1e-14 * sqrt(a * b)) {
           const double zeta = (b - a) / (2.0 * g);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -508,6 +524,31 @@ __global__ void k_fill_zero(double *p, size_t n) {
 void gemm_f64(const GemmDesc &g, hipStream_t s) {
   KTimer kt_("gemm_f64", s, 2.0 * g.M * g.N * g.K * g.nb1 * g.nb2);
   if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
+  const long tiles = (long)((g.N + 63) / 64) * ((g.M + 63) / 64) * g.nb1 * g.nb2;
+  if (g.ws && tiles < 64 && g.nb1 * g.nb2 == 1 && g.K >= 256) {
+    // few output tiles and a long K: split K into chunks of >= 64 written to
+    // a workspace, then sum them in a fixed order
+    int S = (int)std::min<long>(std::min<long>(g.K / 64, 128 / tiles), 16);
+    while (S > 1 && (size_t)S * g.M * g.N > g.ws_len) --S;
+    if (S > 1) {
+      const int kc = ((g.K + S - 1) / S + 15) / 16 * 16;
+      S = (g.K + kc - 1) / kc;
+      GemmDesc h = g;
+      h.nb1 = S; h.nb2 = 1;
+      h.K = kc;
+      h.a_b1 = kc * g.a_k; h.b_b1 = kc * g.b_k;
+      h.C = g.ws; h.c_i = g.N; h.c_j = 1; h.c_b1 = (long)g.M * g.N;
+      h.alpha = 1.0; h.beta = 0.0; h.kmax = g.K;
+      dim3 grid((h.N + 63) / 64, (h.M + 63) / 64, S);
+      hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, h);
+      SPG_CHECK_LAUNCH();
+      const long mn = (long)g.M * g.N;
+      hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g.M,
+                         g.N, S, g.ws, g.C, g.c_i, g.c_j, g.alpha, g.beta);
+      SPG_CHECK_LAUNCH();
+      return;
+    }
+  }
   dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.nb1 * g.nb2);
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
   SPG_CHECK_LAUNCH();

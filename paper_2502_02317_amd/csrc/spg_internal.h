@@ -60,6 +60,9 @@ struct GemmDesc {
   const double *B; long b_k, b_j, b_b1, b_b2;
   double *C; long c_i, c_j, c_b1, c_b2;
   double alpha, beta;
+  double *ws = nullptr;   // optional split-K workspace (ws_len doubles)
+  size_t ws_len = 0;
+  int kmax = 0;           // internal: global K bound of split-K chunks (0 = K)
 };
 void gemm_f64(const GemmDesc &g, hipStream_t s);
 
