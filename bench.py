@@ -9,7 +9,11 @@ contract the boundary MPSs, run the branch-and-bound search.
 Metric: conditional-marginal evaluations per second, one evaluation being one
 resolved candidate (beam state b, local state s) at one site, so a step does
 sum_k min(M, d^k) * d of them.  ``value`` is evaluations / wall time of the
-whole step (inputs already on the host; the PEPS build copies them over).
+whole step (inputs already on the host; the PEPS build copies them over) for
+the mixed path (search contractions in FP32, boundary MPS in FP64); the FP64
+plain path is timed on the same workload and reported beside it, together with
+dlogP, the largest |log p_mixed - log p_fp64| teacher-forced on the FP64
+path's beam over states with p >= 1e-4 of the best at their parent.
 
 The JSON line also carries the roofline of the dominant kernel class (HIP
 events on its launch stream over the timed region, algorithmic work counted by
@@ -34,6 +38,41 @@ WORKLOAD = dict(name="kings8x8_d16", seed=0, chi=32, max_states=1024, num_sweeps
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "hbm_GBs": 8000.0}
 FLOP_CLASSES = {"gemm_f64", "qr_f64", "right_env", "marginals", "beam_update"}
 BYTE_CLASSES = {"normalize_box", "select_topm"}
+
+
+CLASS_KERNEL = {"gemm_f64": "k_gemm", "qr_f64": "k_qr_lds", "jacobi_svd_f64": "k_jacobi",
+                "normalize_box": "k_box_scale", "right_env": "k_right_env",
+                "marginals": "k_marginals", "select_topm": "k_select",
+                "beam_update": "k_beam_update", "final_sort": "k_final_sort"}
+KERNEL_SOURCES = ["k_linalg.hip", "k_bmps.hip", "k_search.hip"]
+
+
+def kernel_source_sha(name):
+    """(file, sha256 of the kernel's own source text) for a __global__ function."""
+    import hashlib
+    import re
+    for f in KERNEL_SOURCES:
+        path = os.path.join(ROOT, "paper_2502_02317_amd", "csrc", f)
+        src = open(path).read()
+        m = re.search(r"__global__[^{;]*?\b" + re.escape(name) + r"\(", src)
+        if not m:
+            continue
+        end = src.find("\n}\n", m.start())
+        body = src[m.start(): end + 3]
+        return "paper_2502_02317_amd/csrc/" + f, hashlib.sha256(body.encode()).hexdigest()
+    return None, None
+
+
+def committed_traffic(kernel, workload_tag):
+    """HBM bytes per dispatch from the committed counter summary, or None when
+    the kernel's source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload_tag}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("kernels", {}).get(kernel)
+    if rec is None or kernel_source_sha(kernel)[1] != rec["kernel_sha256"]:
+        return None
+    return rec["bytes_per_dispatch"]
 
 
 def evals_per_step(R, C, d, M):
@@ -71,14 +110,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--precision", default="fp32",
+                    help="search-contraction precision of the timed (mixed) path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 256 MiB device-to-device (a known-size kernel for "
+                         "scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the hot path of one instance per GPU); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_2502_02317_amd import spg
     from workloads import config_instance
@@ -92,35 +136,45 @@ def main():
     en = torch.zeros(M, dtype=torch.float64, device=dev)
     lp = torch.zeros(M, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
-    def step():
+    def step(prec):
         peps = spg.build_peps(inst, stream)
-        env, _ = spg.boundary_mps(peps, wl["chi"], num_sweeps=wl["num_sweeps"],
-                                  precision=args.precision, oversample=wl["oversample"],
-                                  power_iters=wl["power_iters"], stream=stream, want_logZ=False)
+        env, _ = spg.boundary_mps(peps, wl["chi"], num_sweeps=wl["num_sweeps"], precision=prec,
+                                  oversample=wl["oversample"], power_iters=wl["power_iters"],
+                                  stream=stream, want_logZ=False)
         n = spg.branch_and_bound(env, M, st, en, lp, stream=stream)
         return env, n
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    def timed(prec, profile):
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        spg.profile_reset()
+        spg.profile_enable(profile)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(prec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        spg.profile_enable(False)
+        prof = {k: spg.profile_query(k) for k in spg.KERNEL_CLASSES}
+        spg.profile_reset()
+        return (t1 - t0) * 1e3 / args.steps, prof
 
-    # timed region (kernel classes timed with HIP events on the launch stream)
-    spg.profile_reset()
-    spg.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        env, n = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    spg.profile_enable(False)
-    ms = (t1 - t0) * 1e3 / args.steps
     ev = evals_per_step(R, C, d, M)
-    prof = {k: spg.profile_query(k) for k in spg.KERNEL_CLASSES}
-    spg.profile_reset()
+    # the mixed path (the precision form) and the FP64 plain path, same workload
+    ms, prof = timed(args.precision, True)
+    ms64 = ms if args.precision == "fp64" else timed("fp64", False)[0]
+    best_E = float(en[0])
 
-    # search-only and boundary-MPS-only split (untimed region, same work)
+    # search-only and boundary-MPS-only split (untimed, same work)
     peps = spg.build_peps(inst, stream)
     torch.cuda.synchronize()
     a = time.perf_counter()
@@ -133,35 +187,82 @@ def main():
     torch.cuda.synchronize()
     c = time.perf_counter()
 
+    # dlogP: teacher-forced on the FP64 path's beam (the oracle's search on the
+    # GPU's FP64 boundary MPS gives that beam), states with p64 >= 1e-4 max
+    dlogp = None
+    dlogp_info = None
+    if args.precision != "fp64":
+        from oracle.search import beam_search, teacher_forced_condition
+        env64, _ = spg.boundary_mps(peps, wl["chi"], num_sweeps=wl["num_sweeps"], precision="fp64",
+                                    oversample=wl["oversample"], power_iters=wl["power_iters"],
+                                    stream=stream, want_logZ=False)
+        T, _lam = spg.env_export(env64)
+        rows = spg.unpack_mps(T, spg.env_info(env64).bond_dims)
+        trace = []
+        beam_search(inst, rows, M, trace=trace)
+        dlogp, n_keep, n_unres, n_unres64 = 0.0, 0, 0, 0
+        u_in = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -9}[args.precision]
+        for k in range(N):
+            cfg_np = trace[k]["cfg"]
+            cfg = torch.tensor(cfg_np, dtype=torch.int32, device=dev)
+            o64 = torch.empty((cfg.shape[0], d), dtype=torch.float64, device=dev)
+            olo = torch.empty_like(o64)
+            spg.marginals(env64, k, cfg, o64)
+            spg.marginals(env, k, cfg, olo)
+            r64, rlo = o64.cpu().numpy(), olo.cpu().numpy()
+            keep = r64 >= r64.max(axis=1, keepdims=True) + np.log(1e-4)
+            # entries whose value the reduced precision determines (running-error
+            # bound on q below 1); the rest are counted as unresolved
+            rr, cc = divmod(k, C)
+            ks, _kz = teacher_forced_condition(inst, rows, rr, cc, cfg_np)
+            n_ops = wl["chi"] ** 2 + d * wl["chi"] * C
+            g = 2 * ((C + 2) * u_in + n_ops * 2.0 ** -24)
+            tol = g * (ks + _kz[:, None])
+            g64 = 2 * n_ops * 2.0 ** -53
+            fine = keep & np.isfinite(tol) & (tol <= 1e-3)
+            n_keep += int(keep.sum())
+            n_unres += int((keep & ~fine).sum())
+            n_unres64 += int((keep & ~(g64 * (ks + _kz[:, None]) <= 1e-3)).sum())
+            if fine.any():
+                dlogp = max(dlogp, float(np.abs(rlo[fine] - r64[fine]).max()))
+        dlogp_info = {"entries": n_keep, "not_resolved_to_1e-3_at_this_precision": n_unres,
+                      "not_resolved_to_1e-3_even_in_fp64": n_unres64,
+                      "floor": "p64 >= 1e-4 max at the parent"}
+
     dom = max(prof, key=lambda k: prof[k][1])
     cnt, tms, work = prof[dom]
     if dom in FLOP_CLASSES:
         achieved = work / (tms * 1e-3) / 1e12
-        peak = PEAK[args.precision]
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
+        # the QR kernels run on the FP64 vector ALU; the GEMM-shaped
+        # contractions are MFMA candidates (FP64 peak: the boundary MPS is FP64)
+        bound = "alu" if dom in ("qr_f64",) else "mfma"
+        roof = {"bound": bound, "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s"}
     elif dom in BYTE_CLASSES:
         achieved = work / (tms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"], "unit": "GB/s"}
     else:
         roof = {"bound": "latency", "achieved": None, "peak": None, "unit": None}
-    if roof["achieved"] is not None:
-        roof["frac"] = roof["achieved"] / roof["peak"]
-    else:
-        roof["frac"] = None
-    roof["traffic"] = None
-    roof["kernel"] = dom
+    roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] is not None else None
+    roof["traffic"] = committed_traffic(CLASS_KERNEL[dom], "kings8x8_d16")
+    roof["kernel"] = CLASS_KERNEL[dom]
+    roof["kernel_class"] = dom
     roof["launches_per_step"] = cnt / args.steps
     roof["avg_launch_us"] = tms * 1e3 / max(cnt, 1)
 
+    dt = {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16"}[args.precision]
     out = {
         "metric": "conditional-marginal evals/s", "value": ev / (ms * 1e-3), "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.precision],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
         "data": "synthetic",
         "config": {"workload": "kings8x8_d16 beta=2 chi=32 M=1024 (seed 0)", "rows": R, "cols": C,
                    "d": d, "chi": wl["chi"], "max_states": M, "num_sweeps": wl["num_sweeps"],
-                   "evals_per_step": ev},
+                   "evals_per_step": ev, "search_precision": args.precision,
+                   "boundary_mps_precision": "fp64"},
+        "fp64_plain": {"value": ev / (ms64 * 1e-3), "ms_per_step": ms64},
+        "dlogP": dlogp,
+        "dlogP_coverage": dlogp_info,
+        "best_energy": best_E,
         "split": {"boundary_mps_ms": (b - a) * 1e3, "search_ms": (c - b) * 1e3,
                   "search_evals_per_s": ev / (c - b)},
         "kernels": {k: {"launches": v[0], "ms": v[1], "work": v[2]} for k, v in prof.items()},

@@ -44,9 +44,10 @@ enum {
   SPG_ERR_UNSUPPORTED = -5  /* size outside the supported limits                 */
 };
 
-/* Working precision of the contractions (boundary MPS, environments,
- * marginals).  QR/SVD factorisations, energies and accumulated scores are
- * always FP64. */
+/* Working precision of the search contractions (right environments,
+ * conditional marginals, beam-update vectors): FP64, FP32, or BF16 inputs with
+ * FP32 accumulation.  The boundary MPS itself (its GEMMs and the QR/SVD
+ * factorisations), energies and accumulated scores are always FP64. */
 enum { SPG_FP64 = 0, SPG_FP32 = 1, SPG_BF16 = 2 };
 
 typedef struct spg_peps spg_peps_t;
@@ -75,7 +76,7 @@ typedef struct {
   int32_t chi;          /* bond dimension cap of every boundary MPS                 */
   int32_t num_sweeps;   /* variational sweeps per row (>= 1); one sweep is a       */
                         /* left-to-right then a right-to-left pass                  */
-  int32_t precision;    /* SPG_FP64 / SPG_FP32 / SPG_BF16                           */
+  int32_t precision;    /* SPG_FP64 / SPG_FP32 / SPG_BF16: search contractions      */
   int32_t oversample;   /* sketch oversampling p of the truncated SVD (>= 0)       */
   int32_t power_iters;  /* subspace (power) iterations q of the truncated SVD      */
 } spg_mps_params;

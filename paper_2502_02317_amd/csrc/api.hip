@@ -316,6 +316,17 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
   SPG_HIP(hipStreamSynchronize(s));
 }
 
+// Search copy of the boundary MPS in the env's precision (no-op for FP64).
+static void make_lp_copy(spg_env *env, hipStream_t s) {
+  if (env->precision == SPG_FP64) return;
+  const spg_peps *pp = env->peps;
+  const long n = (long)pp->rows * pp->cols * env->chi * pp->d * env->chi;
+  env->Alp.ensure((size_t)n * (env->precision == SPG_FP32 ? 4 : 2));
+  lp_convert(n, env->A.as<double>(), env->Alp.p, env->precision, s);
+}
+
+static size_t lp_elt(const spg_env *env) { return env->precision == SPG_FP32 ? 4 : 2; }
+
 static SearchTabs tabs_of(const spg_env *env) {
   const spg_peps *pp = env->peps;
   SearchTabs t;
@@ -454,7 +465,7 @@ void spg_free_peps(spg_peps_t *pp) {
 
 void spg_free_env(spg_env_t *env) {
   if (!env) return;
-  for (DevBuf *b : {&env->A, &env->lam, &env->cfg[0], &env->cfg[1], &env->score[0],
+  for (DevBuf *b : {&env->A, &env->Alp, &env->lam, &env->cfg[0], &env->cfg[1], &env->score[0],
                     &env->score[1], &env->energy[0], &env->energy[1], &env->L[0], &env->L[1],
                     &env->anc[0], &env->anc[1], &env->Rv, &env->cand, &env->sel, &env->keys,
                     &env->ids, &env->ework, &env->perm, &env->nvalid, &env->tmp, &env->cfg32})
@@ -470,8 +481,8 @@ static int check_mps_params(const spg_mps_params *p) {
     return fail(SPG_ERR_INVALID, "oversample >= 0 and power_iters in 0..8 required");
   if (p->chi + p->oversample > kMaxSketch)
     return fail(SPG_ERR_UNSUPPORTED, "chi + oversample must be <= 96");
-  if (p->precision != SPG_FP64)
-    return fail(SPG_ERR_UNSUPPORTED, "this precision is not available for the boundary MPS");
+  if (p->precision != SPG_FP64 && p->precision != SPG_FP32 && p->precision != SPG_BF16)
+    return fail(SPG_ERR_INVALID, "precision must be SPG_FP64, SPG_FP32 or SPG_BF16");
   return SPG_OK;
 }
 
@@ -492,6 +503,7 @@ int spg_boundary_mps(const spg_peps_t *peps, const spg_mps_params *params, void 
     env->A.ensure((size_t)R * C * chi * d * chi * sizeof(double));
     env->lam.ensure((size_t)R * sizeof(double));
     boundary_mps_fp64(env, params, s);
+    make_lp_copy(env, s);
     if (log_Z_out) {
       // log Z = lam_0 + log sum_X A_0[x_0]..A_{C-1}[x_{C-1}] - beta * shift (host, small)
       std::vector<double> A0((size_t)C * chi * d * chi), lam(R);
@@ -552,7 +564,8 @@ int spg_env_import(const spg_peps_t *peps, int32_t chi, const int32_t *bond_dims
   SPG_TRY
   if (!peps || !bond_dims || !tensors || !out) return fail(SPG_ERR_INVALID, "spg_env_import: null argument");
   if (chi < 1 || chi > kMaxChi) return fail(SPG_ERR_UNSUPPORTED, "spg_env_import: chi must be in 1..80");
-  if (precision != SPG_FP64) return fail(SPG_ERR_UNSUPPORTED, "spg_env_import: precision");
+  if (precision != SPG_FP64 && precision != SPG_FP32 && precision != SPG_BF16)
+    return fail(SPG_ERR_INVALID, "spg_env_import: precision");
   const int R = peps->rows, C = peps->cols, d = peps->d;
   for (int r = 0; r < R; ++r) {
     if (bond_dims[r * (C + 1)] != 1 || bond_dims[r * (C + 1) + C] != 1)
@@ -573,6 +586,7 @@ int spg_env_import(const spg_peps_t *peps, int32_t chi, const int32_t *bond_dims
     env->lam.ensure((size_t)R * 8);
     SPG_HIP(hipMemcpyAsync(env->A.p, tensors, n * 8, hipMemcpyHostToDevice, s));
     if (lam) SPG_HIP(hipMemcpyAsync(env->lam.p, lam, (size_t)R * 8, hipMemcpyHostToDevice, s));
+    make_lp_copy(env, s);
     SPG_HIP(hipStreamSynchronize(s));
   } catch (...) {
     spg_free_env(env);
@@ -623,19 +637,39 @@ int spg_marginals(const spg_env_t *cenv, int32_t site, int32_t n_beam, const int
   const double *A = env->A.as<double>();
   const size_t site_sz = (size_t)chi * d * chi;
   const long rstride = (long)(C + 1) * chi;
-  double *Rv = env->Rv.as<double>();
-  set_e0(n_beam, chi, Rv + (size_t)C * chi, rstride, s);
-  for (int cc = C - 1; cc > c; --cc)
-    right_env_col(t, r, cc, n_beam, cfg, N, A + ((size_t)r * C + cc) * site_sz,
-                  Rv + (size_t)(cc + 1) * chi, Rv + (size_t)cc * chi, rstride,
-                  env->dims[r * (C + 1) + cc], env->dims[r * (C + 1) + cc + 1], s);
-  double *L = env->L[0].as<double>();
   int32_t *anc = env->anc[0].as<int32_t>();
-  beam_reset_row(n_beam, chi, L, anc, s);
-  for (int cc = 0; cc < c; ++cc)
-    advance_L(t, r, cc, n_beam, cfg, N, A + ((size_t)r * C + cc) * site_sz, L, nullptr, s);
-  marginals(t, r, c, n_beam, cfg, N, A + ((size_t)r * C + c) * site_sz, L, anc, Rv, rstride,
-            nullptr, log_cond_out, 0, env->dims[r * (C + 1) + c], env->dims[r * (C + 1) + c + 1], s);
+  const int* dm = env->dims.data() + r * (C + 1);
+  if (env->precision == SPG_FP64) {
+    double *Rv = env->Rv.as<double>();
+    set_e0(n_beam, chi, Rv + (size_t)C * chi, rstride, s);
+    for (int cc = C - 1; cc > c; --cc)
+      right_env_col(t, r, cc, n_beam, cfg, N, A + ((size_t)r * C + cc) * site_sz,
+                    Rv + (size_t)(cc + 1) * chi, Rv + (size_t)cc * chi, rstride, dm[cc],
+                    dm[cc + 1], s);
+    double *L = env->L[0].as<double>();
+    beam_reset_row(n_beam, chi, L, anc, s);
+    for (int cc = 0; cc < c; ++cc)
+      advance_L(t, r, cc, n_beam, cfg, N, A + ((size_t)r * C + cc) * site_sz, L, nullptr, s);
+    marginals(t, r, c, n_beam, cfg, N, A + ((size_t)r * C + c) * site_sz, L, anc, Rv, rstride,
+              nullptr, log_cond_out, 0, dm[c], dm[c + 1], s);
+  } else {
+    const int pr = env->precision;
+    const char *Al = env->Alp.as<char>();
+    const size_t eb = lp_elt(env);
+    float *Rv = env->Rv.as<float>();
+    lp_set_e0(n_beam, chi, Rv + (size_t)C * chi, rstride, s);
+    for (int cc = C - 1; cc > c; --cc)
+      lp_right_env_col(t, pr, r, cc, n_beam, cfg, N, Al + ((size_t)r * C + cc) * site_sz * eb,
+                       Rv + (size_t)(cc + 1) * chi, Rv + (size_t)cc * chi, rstride, dm[cc],
+                       dm[cc + 1], s);
+    float *L = env->L[0].as<float>();
+    beam_reset_row(n_beam, chi, env->L[1].as<double>(), anc, s);
+    lp_set_e0(n_beam, chi, L, chi, s);
+    for (int cc = 0; cc < c; ++cc)
+      lp_advance_L(t, pr, r, cc, n_beam, cfg, N, Al + ((size_t)r * C + cc) * site_sz * eb, L, s);
+    lp_marginals(t, pr, r, c, n_beam, cfg, N, Al + ((size_t)r * C + c) * site_sz * eb, L, anc, Rv,
+                 rstride, nullptr, log_cond_out, 0, dm[c], dm[c + 1], s);
+  }
   (void)d;
   return SPG_OK;
   SPG_CATCH
@@ -666,33 +700,60 @@ int spg_branch_and_bound(const spg_env_t *cenv, const spg_search_params *prm, in
   fill_zero(env->score[0].as<double>(), 1, s);
   fill_zero(env->energy[0].as<double>(), 1, s);
   const double log_cut = (prm->cut_off_prob > 0.0) ? std::log(prm->cut_off_prob) : 0.0;
+  const bool lp = env->precision != SPG_FP64;
+  const char *Al = env->Alp.as<char>();
+  const size_t eb = lp ? lp_elt(env) : 0;
   for (int r = 0; r < R; ++r) {
     const int n_anc = (int)B;
-    beam_reset_row(n_anc, chi, env->L[cur].as<double>(), env->anc[cur].as<int32_t>(), s);
-    set_e0(n_anc, chi, Rv + (size_t)C * chi, rstride, s);
-    for (int c = C - 1; c >= 1; --c)
-      right_env_col(t, r, c, n_anc, env->cfg[cur].as<uint8_t>(), N,
-                    A + ((size_t)r * C + c) * site_sz, Rv + (size_t)(c + 1) * chi,
-                    Rv + (size_t)c * chi, rstride, env->dims[r * (C + 1) + c],
-                    env->dims[r * (C + 1) + c + 1], s);
+    const int *dm = env->dims.data() + r * (C + 1);
+    beam_reset_row(n_anc, chi, lp ? env->L[cur ^ 1].as<double>() : env->L[cur].as<double>(),
+                   env->anc[cur].as<int32_t>(), s);
+    if (lp) {
+      lp_set_e0(n_anc, chi, env->L[cur].as<float>(), chi, s);
+      float *Rf = env->Rv.as<float>();
+      lp_set_e0(n_anc, chi, Rf + (size_t)C * chi, rstride, s);
+      for (int c = C - 1; c >= 1; --c)
+        lp_right_env_col(t, env->precision, r, c, n_anc, env->cfg[cur].as<uint8_t>(), N,
+                         Al + ((size_t)r * C + c) * site_sz * eb, Rf + (size_t)(c + 1) * chi,
+                         Rf + (size_t)c * chi, rstride, dm[c], dm[c + 1], s);
+    } else {
+      set_e0(n_anc, chi, Rv + (size_t)C * chi, rstride, s);
+      for (int c = C - 1; c >= 1; --c)
+        right_env_col(t, r, c, n_anc, env->cfg[cur].as<uint8_t>(), N,
+                      A + ((size_t)r * C + c) * site_sz, Rv + (size_t)(c + 1) * chi,
+                      Rv + (size_t)c * chi, rstride, dm[c], dm[c + 1], s);
+    }
     for (int c = 0; c < C; ++c) {
       const double *Arc = A + ((size_t)r * C + c) * site_sz;
-      marginals(t, r, c, (int)B, env->cfg[cur].as<uint8_t>(), N, Arc, env->L[cur].as<double>(),
-                env->anc[cur].as<int32_t>(), Rv, rstride, env->score[cur].as<double>(),
-                env->cand.as<double>(), 1, env->dims[r * (C + 1) + c],
-                env->dims[r * (C + 1) + c + 1], s);
+      const void *Alc = lp ? (const void *)(Al + ((size_t)r * C + c) * site_sz * eb) : nullptr;
+      if (lp)
+        lp_marginals(t, env->precision, r, c, (int)B, env->cfg[cur].as<uint8_t>(), N, Alc,
+                     env->L[cur].as<float>(), env->anc[cur].as<int32_t>(), env->Rv.as<float>(),
+                     rstride, env->score[cur].as<double>(), env->cand.as<double>(), 1, dm[c],
+                     dm[c + 1], s);
+      else
+        marginals(t, r, c, (int)B, env->cfg[cur].as<uint8_t>(), N, Arc, env->L[cur].as<double>(),
+                  env->anc[cur].as<int32_t>(), Rv, rstride, env->score[cur].as<double>(),
+                  env->cand.as<double>(), 1, dm[c], dm[c + 1], s);
       if (prm->cut_off_prob > 0.0) apply_cutoff((int)(B * d), log_cut, env->cand.as<double>(), s);
       const long Bn = std::min<long>(M, B * d);
       select_topm((int)(B * d), M, env->cand.as<double>(), env->sel.as<int32_t>(),
                   env->keys.as<uint64_t>(), env->ids.as<int32_t>(), s);
       const int nx = cur ^ 1;
-      beam_update(t, r, c, (int)Bn, env->sel.as<int32_t>(), N, env->cfg[cur].as<uint8_t>(),
-                  env->energy[cur].as<double>(), env->L[cur].as<double>(),
-                  env->anc[cur].as<int32_t>(), env->cand.as<double>(), Arc, c < C - 1,
-                  env->cfg[nx].as<uint8_t>(), env->energy[nx].as<double>(),
-                  env->score[nx].as<double>(), env->L[nx].as<double>(),
-                  env->anc[nx].as<int32_t>(), env->dims[r * (C + 1) + c],
-                  env->dims[r * (C + 1) + c + 1], s);
+      if (lp)
+        lp_beam_update(t, env->precision, r, c, (int)Bn, env->sel.as<int32_t>(), N,
+                       env->cfg[cur].as<uint8_t>(), env->energy[cur].as<double>(),
+                       env->L[cur].as<float>(), env->anc[cur].as<int32_t>(),
+                       env->cand.as<double>(), Alc, c < C - 1, env->cfg[nx].as<uint8_t>(),
+                       env->energy[nx].as<double>(), env->score[nx].as<double>(),
+                       env->L[nx].as<float>(), env->anc[nx].as<int32_t>(), dm[c], dm[c + 1], s);
+      else
+        beam_update(t, r, c, (int)Bn, env->sel.as<int32_t>(), N, env->cfg[cur].as<uint8_t>(),
+                    env->energy[cur].as<double>(), env->L[cur].as<double>(),
+                    env->anc[cur].as<int32_t>(), env->cand.as<double>(), Arc, c < C - 1,
+                    env->cfg[nx].as<uint8_t>(), env->energy[nx].as<double>(),
+                    env->score[nx].as<double>(), env->L[nx].as<double>(),
+                    env->anc[nx].as<int32_t>(), dm[c], dm[c + 1], s);
       cur = nx;
       B = Bn;
     }

@@ -554,13 +554,18 @@ void gemm_f64(const GemmDesc &g, hipStream_t s) {
   SPG_CHECK_LAUNCH();
 }
 
+// Householder QR flops: 2mn^2 - 2n^3/3 for R, the same again to form Q.
+static double qr_flops(int m, int n, int want_q) {
+  const double r = 2.0 * m * n * n - 2.0 * n * n * n / 3.0;
+  return want_q ? 2.0 * r : r;
+}
+
 size_t qr_work_doubles(int m, int n) {
   return 3 * (size_t)m * n + 2 * (size_t)kQrLds + 2 * (size_t)n * n + n + 64;
 }
 
 void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr, long qc,
             double *R, double *work, hipStream_t s) {
-  KTimer kt_("qr_f64", s, 4.0 * m * n * n - 4.0 * n * n * n / 3.0);
   if (m <= 0 || n <= 0) return;
   if (m < n) {
     set_error("qr_f64: needs rows >= columns");
@@ -574,6 +579,7 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
   if ((long)m * n <= kQrLds) {
     // one LDS-resident block; R straight to the caller (or to scratch)
     double *Rd = R ? R : work;
+    KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
     hipLaunchKernelGGL(k_qr_lds, dim3(1), dim3(1024), 0, s, m, n, m, X, xr, xc, Q, qr, qc, Rd,
                        want_q);
     SPG_CHECK_LAUNCH();
@@ -587,12 +593,18 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
     double *S = Q1 + (long)m * n;               // p*n x n row-major (stacked R_b)
     double *Qs = S + (long)p * n * n;           // p*n x n row-major
     double *Rt = Qs + (long)p * n * n;          // n x n
-    hipLaunchKernelGGL(k_qr_lds, dim3(p), dim3(1024), 0, s, m, n, mb, X, xr, xc, Q1, (long)n, 1L,
-                       S, want_q);
-    SPG_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_qr_lds, dim3(1), dim3(1024), 0, s, p * n, n, p * n, S, (long)n, 1L, Qs,
-                       (long)n, 1L, R ? R : Rt, want_q);
-    SPG_CHECK_LAUNCH();
+    {
+      KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
+      hipLaunchKernelGGL(k_qr_lds, dim3(p), dim3(1024), 0, s, m, n, mb, X, xr, xc, Q1, (long)n,
+                         1L, S, want_q);
+      SPG_CHECK_LAUNCH();
+    }
+    {
+      KTimer kt_("qr_f64", s, qr_flops(p * n, n, want_q));
+      hipLaunchKernelGGL(k_qr_lds, dim3(1), dim3(1024), 0, s, p * n, n, p * n, S, (long)n, 1L,
+                         Qs, (long)n, 1L, R ? R : Rt, want_q);
+      SPG_CHECK_LAUNCH();
+    }
     if (!want_q) return;
     const int full = m / mb, tail = m - full * mb;
     GemmDesc g{};
@@ -615,6 +627,7 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
     return;
   }
   // large panels: global-memory Householder in one workgroup
+  KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
   hipLaunchKernelGGL(k_qr, dim3(1), dim3(1024), 0, s, m, n, X, xr, xc, Q ? Q : work + 2L * m * n + n,
                      Q ? qr : (long)n, Q ? qc : 1L, R, work);
   SPG_CHECK_LAUNCH();

@@ -158,6 +158,25 @@ void cfg_from_i32(int n, int N, const int32_t *src, uint8_t *dst, hipStream_t s)
 void advance_L(const SearchTabs &t, int r, int c, int n, const uint8_t *cfg, int N,
                const double *A_rc, double *L, double *tmp, hipStream_t s);
 
+// ---- reduced-precision search contractions (k_search_lp.hip) --------------
+// precision: SPG_FP32 (A in FP32) or SPG_BF16 (A in BF16); vectors L, R FP32.
+void lp_convert(long n, const double *src, void *dst, int precision, hipStream_t s);
+void lp_set_e0(int n, int chi, float *p, long stride, hipStream_t s);
+void lp_right_env_col(const SearchTabs &t, int precision, int r, int c, int n_anc,
+                      const uint8_t *cfg, int N, const void *A_rc, const float *Rnext,
+                      float *Rout, long rstride, int cl, int cr, hipStream_t s);
+void lp_marginals(const SearchTabs &t, int precision, int r, int c, int n_beam,
+                  const uint8_t *cfg, int N, const void *A_rc, const float *L, const int32_t *anc,
+                  const float *Rv, long rstride, const double *score, double *out, int add_score,
+                  int cl, int cr, hipStream_t s);
+void lp_beam_update(const SearchTabs &t, int precision, int r, int c, int n_new,
+                    const int32_t *sel, int N, const uint8_t *cfg, const double *energy,
+                    const float *L, const int32_t *anc, const double *cand, const void *A_rc,
+                    int update_L, uint8_t *cfg_o, double *energy_o, double *score_o, float *L_o,
+                    int32_t *anc_o, int cl, int cr, hipStream_t s);
+void lp_advance_L(const SearchTabs &t, int precision, int r, int c, int n, const uint8_t *cfg,
+                  int N, const void *A_rc, float *L, hipStream_t s);
+
 }  // namespace spg
 
 // ---- opaque handles ---------------------------------------------------------
@@ -175,6 +194,7 @@ struct spg_env {
   int chi = 0, precision = SPG_FP64;
   std::vector<int32_t> dims;     // [rows][cols+1]
   spg::DevBuf A;                 // [rows][cols][chi][d][chi] float64, zero padded
+  spg::DevBuf Alp;               // same tensors in the search precision (FP32 or BF16)
   spg::DevBuf lam;               // [rows] float64 log-scales
   // search workspace (grown on demand)
   spg::DevBuf cfg[2], score[2], energy[2], L[2], anc[2], Rv, cand, sel, keys, ids, ework,
