@@ -82,11 +82,16 @@ typedef struct {
 } spg_mps_params;
 
 /* Search parameters (the paper's SearchParameters). */
+typedef struct spg_proposal spg_proposal_t;
 typedef struct {
   int32_t max_states;   /* beam width M: partial configurations kept per step      */
   double cut_off_prob;  /* 0 disables; else a child whose probability is below     */
                         /* cut_off_prob times the best child of the step is        */
                         /* discarded (kept only as -inf padding)                   */
+  const spg_proposal_t *proposal;  /* NULL: every child evaluated exactly; else    */
+                        /* the learned proposal ranks children first (see below)   */
+  double kappa;         /* with a proposal: about kappa * max_states children are  */
+                        /* evaluated exactly per step before the guard (> 0)       */
 } spg_search_params;
 
 /* Build the PEPS of an instance (Sec. 2, Fig. 1(c)): copies the energy tables
@@ -121,7 +126,16 @@ int spg_marginals(const spg_env_t *env, int32_t site, int32_t n_beam, const int3
 /* Branch-and-bound search (Sec. 2; Fig. 1(d)-(e)): visits the sites in
  * row-major order, keeping the max_states most probable partial
  * configurations (ties: parent position, then state), and returns the final
- * beam sorted by energy ascending:
+ * beam sorted by energy ascending.
+ * With params->proposal set (FP64 envs only, else SPG_ERR_UNSUPPORTED), each
+ * step first ranks the children with the network, evaluates exactly only the
+ * best-ranked ones (about kappa * max_states), and bounds every other child
+ * of parent b by b's unevaluated weight Z_b - sum of its evaluated q, where
+ * Z_b = L^b R_c comes from the right environments at no extra cost; parents
+ * whose bound reaches the max_states-th exact score are evaluated in full.
+ * The finite part of the result is then the plain search's whatever the
+ * network predicts (exact up to rounding while no conditional weight is
+ * negative, i.e. outside the truncation-error regime).  Outputs:
  *   states_out   DEVICE int32   [max_states][rows*cols]
  *   energies_out DEVICE float64 [max_states]  (Eq. (1), recomputed in FP64)
  *   logp_out     DEVICE float64 [max_states]  (accumulated log-probability)
@@ -136,6 +150,77 @@ int spg_branch_and_bound(const spg_env_t *env, const spg_search_params *params,
 void spg_free_peps(spg_peps_t *peps);
 void spg_free_env(spg_env_t *env);
 const char *spg_last_error(void);
+
+/* ---- learned proposal ---------------------------------------------------
+ * Not part of the paper's method: a 2-layer FP32 network that ranks the
+ * children (b, s) of the beam so the exact contraction runs for few of them.
+ * Per child, F = 6 features (each clamped at -30 and divided by 10 where the
+ * value is a log-weight relative to its maximum): -beta dE(b, s) (Eq. (1)
+ * terms closing at the site) relative to the best s; the one-step look-ahead
+ * sum over the unexplored neighbours n of log sum_y exp(-beta (E_n(y) +
+ * E_pair(s, y))) relative to the best s; log of the site's unconditioned
+ * one-site weight of the boundary MPS relative to the best s; c / (cols - 1);
+ * r / (rows - 1); score(b) minus the best score of the beam.
+ * Network: h = relu(W1 f + b1) (H hidden units, 1 <= H <= 64),
+ * logit = w2 . h + b2, p(s | b) = softmax over s.  Parameters (float32,
+ * n = 8 H + 1): [W1 (H x F, row-major), b1 (H), w2 (H), b2].
+ * Loss: cross-entropy against the exact conditionals, averaged over parents. */
+#define SPG_PROPOSAL_FEATURES 6
+
+typedef struct {
+  int32_t epochs;        /* passes over the collected steps (>= 1)                 */
+  float learning_rate;   /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8)      */
+  int32_t max_states;    /* beam width of the exact search that provides targets  */
+} spg_train_params;
+
+/* New network with deterministic initial weights drawn from `seed`
+ * (SplitMix64, uniform in +-sqrt(6 / fan_in), biases 0).  Owned by the caller,
+ * released with spg_proposal_free.  Errors: SPG_ERR_INVALID, SPG_ERR_OOM. */
+int spg_proposal_create(int32_t hidden, uint64_t seed, spg_proposal_t **out);
+void spg_proposal_free(spg_proposal_t *prop);
+
+/* Copy parameters out (host_out, HOST float32 [n], may be NULL) and/or in
+ * (host_in, may be NULL; resets the Adam state); *n_params (HOST) receives n.
+ * Synchronous. */
+int spg_proposal_params(spg_proposal_t *prop, float *host_out, const float *host_in,
+                        int32_t *n_params);
+
+/* Train on one instance: runs the exact search of `env` with
+ * tp->max_states, records every step's features and exact conditionals, then
+ * takes tp->epochs passes over the steps in order, one Adam step per step.
+ * Repeated calls continue the same optimiser state.  loss_out (HOST float32
+ * [epochs], may be NULL) receives the mean loss of each pass.  Synchronises.
+ * Errors: SPG_ERR_INVALID, SPG_ERR_UNSUPPORTED (non-FP64 env), SPG_ERR_OOM,
+ * SPG_ERR_HIP. */
+int spg_proposal_train(spg_proposal_t *prop, const spg_env_t *env, const spg_train_params *tp,
+                       void *stream, float *loss_out);
+
+/* Building blocks of the training (tests, custom loops); all asynchronous.
+ * Features of the children of n_beam partial configurations at `site`:
+ * beam_cfg DEVICE int32 [n_beam][rows*cols], beam_score DEVICE float64
+ * [n_beam] -> feats_out DEVICE float32 [n_beam][d][F]. */
+int spg_proposal_features(const spg_env_t *env, int32_t site, int32_t n_beam,
+                          const int32_t *beam_cfg, const double *beam_score, float *feats_out,
+                          void *stream);
+/* log p(s | b) of the network: feats DEVICE float32 [n_beam][d][F] ->
+ * logp_out DEVICE float32 [n_beam][d]. */
+int spg_proposal_forward(const spg_proposal_t *prop, int32_t n_beam, int32_t d,
+                         const float *feats, float *logp_out, void *stream);
+/* Loss and its gradient for targets target_logp DEVICE float32 [n_beam][d]
+ * (-inf allowed): grad_out DEVICE float32 [n], loss_out DEVICE float32 [1].
+ * Reduction order is fixed, so results are bitwise reproducible. */
+int spg_proposal_loss_grad(const spg_proposal_t *prop, int32_t n_beam, int32_t d,
+                           const float *feats, const float *target_logp, float *grad_out,
+                           float *loss_out, void *stream);
+/* One Adam step with gradient grad DEVICE float32 [n]. */
+int spg_proposal_adam(spg_proposal_t *prop, const float *grad, float learning_rate,
+                      void *stream);
+
+/* Counters of the env's last spg_branch_and_bound call: counts[0] children
+ * evaluated exactly (fallback evaluations included), counts[1] children
+ * resolved (sum over steps of parents x d), counts[2] parents that fell back
+ * to full evaluation.  HOST int64 [3].  Synchronous. */
+int spg_search_stats(const spg_env_t *env, int64_t *counts);
 
 /* ---- inspection hooks (tests and tools) -------------------------------- */
 

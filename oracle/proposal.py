@@ -21,9 +21,9 @@ Per site, with parents b sorted by score (score_0 the best) and d states:
    (-inf when E_b holds every state).  A parent with Z_b <= 0, a non-finite Z_b
    or a negative evaluated q is marked for fallback.
 4. tau = the M-th best exact score over E (-inf when |E| < M).
-5. Fallback parents: marked ones and those with bound_b >= tau - MARGIN.  Their d
-   children are evaluated exactly as in the plain search (normaliser
-   sum_s max(q, 0)).
+5. Fallback parents: marked ones and those with an unevaluated child and
+   bound_b >= tau - MARGIN.  Their d children are evaluated exactly as in the
+   plain search (normaliser sum_s max(q, 0)).
 6. The M best of the evaluated children by (score desc, id asc), id = b d + s,
    after the cut-off rule of the plain search.
 A child outside E of a parent that does not fall back scores at most
@@ -110,7 +110,7 @@ def guided_beam_search(inst, A, M, params, H, kappa=2.0, cut_off_prob=0.0, stats
                     bound[b] = score[b] + math.log((max(U, 0.0) + EPS * Z[b]) / Z[b])
             ev = cand[have]
             tau = np.sort(ev)[::-1][M - 1] if ev.size >= M else -np.inf
-            fb = mark | (bound >= tau - MARGIN)
+            fb = mark | (~E.all(axis=1) & (bound >= tau - MARGIN))
             for b in np.nonzero(fb)[0]:
                 cand[b] = score[b] + log_conditionals(q[b: b + 1])[0]
                 have[b] = True

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libspg.so")
-SOURCES = ["api.hip", "k_linalg.hip", "k_bmps.hip", "k_search.hip", "k_search_lp.hip"]
+SOURCES = ["api.hip", "k_linalg.hip", "k_bmps.hip", "k_search.hip", "k_search_lp.hip",
+           "k_propose.hip", "k_mlp.hip"]
 # Packed FP32 instructions are disabled for every HIP source of the library.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 
+#include "mlp_dev.h"
 #include "spg_internal.h"
 
 namespace spg {
@@ -330,7 +331,8 @@ static size_t lp_elt(const spg_env *env) { return env->precision == SPG_FP32 ? 4
 static SearchTabs tabs_of(const spg_env *env) {
   const spg_peps *pp = env->peps;
   SearchTabs t;
-  t.rows = pp->rows; t.cols = pp->cols; t.d = pp->d; t.chi = env->chi;
+  t.rows = pp->rows; t.cols = pp->cols; t.d = pp->d; t.chi = env->chi; t.beta = pp->beta;
+  t.kings = pp->kings;
   t.E_loc = pp->E_loc.as<double>(); t.E_h = pp->E_h.as<double>(); t.E_v = pp->E_v.as<double>();
   t.E_d = pp->E_d.as<double>(); t.E_a = pp->E_a.as<double>();
   t.W_v = pp->W_v.as<double>(); t.W_d = pp->W_d.as<double>(); t.W_a = pp->W_a.as<double>();
@@ -675,26 +677,78 @@ int spg_marginals(const spg_env_t *cenv, int32_t site, int32_t n_beam, const int
   SPG_CATCH
 }
 
-int spg_branch_and_bound(const spg_env_t *cenv, const spg_search_params *prm, int32_t *states_out,
-                         double *energies_out, double *logp_out, int32_t *n_out, void *stream) {
-  SPG_TRY
-  if (!cenv || !prm || !states_out || !energies_out || !logp_out || !n_out)
-    return fail(SPG_ERR_INVALID, "spg_branch_and_bound: null argument");
-  if (prm->max_states < 1 || prm->max_states > 65536)
-    return fail(SPG_ERR_UNSUPPORTED, "spg_branch_and_bound: max_states must be in 1..65536");
-  if (!(prm->cut_off_prob >= 0.0) || prm->cut_off_prob >= 1.0)
-    return fail(SPG_ERR_INVALID, "spg_branch_and_bound: cut_off_prob must be in [0, 1)");
-  spg_env *env = const_cast<spg_env *>(cenv);
+// Training targets recorded by an exact search: per step k, features
+// [B_k][d][F] at feats + off[k] * F and exact log-conditionals [B_k][d] at
+// targets + off[k].
+struct TrainData {
+  DevBuf feats, targets;
+  std::vector<long> off;
+  std::vector<int> nb;
+};
+
+static void ensure_guide(spg_env *env, int M) {
+  const spg_peps *pp = env->peps;
+  const int R = pp->rows, C = pp->cols, N = R * C, d = pp->d, chi = env->chi;
+  env->Rsc.ensure((size_t)M * (C + 1) * 8);
+  env->sf.ensure((size_t)N * d * 2 * 4);
+  env->rscr.ensure((size_t)R * (C + 1) * chi * 8);
+  env->gbins.ensure((size_t)M * d * 2);
+  env->ghist.ensure(2048 * 4);
+  env->gint.ensure(64);
+  env->glkey.ensure((size_t)M * d * 8);
+  env->glid.ensure((size_t)M * d * 4);
+  env->gbound.ensure((size_t)M * 8);
+  env->gtau.ensure(8);
+  env->goff.ensure((size_t)M * 4);
+  env->gcnt.ensure((size_t)M * 4);
+  env->gstats.ensure(3 * 8);
+  env->selscore.ensure((size_t)M * 8);
+  env->smax.ensure(8);
+}
+
+static GuideWork guide_of(spg_env *env) {
+  GuideWork g;
+  g.bins = env->gbins.as<uint16_t>();
+  g.hist = env->ghist.as<unsigned>();
+  g.jstar = env->gint.as<int>();
+  g.n_list = env->gint.as<int>() + 1;
+  g.lkey = env->glkey.as<double>();
+  g.lid = env->glid.as<int32_t>();
+  g.bound = env->gbound.as<double>();
+  g.tau = env->gtau.as<double>();
+  g.off = env->goff.as<int32_t>();
+  g.cnt = env->gcnt.as<int32_t>();
+  g.stats = env->gstats.as<unsigned long long>();
+  return g;
+}
+
+// The search of spg_branch_and_bound; with `prop` the guarded steps, with
+// `td` (exact path only) the training targets of every step are recorded.
+static void run_search(spg_env *env, const spg_search_params *prm, const spg_proposal *prop,
+                       TrainData *td, int32_t *states_out, double *energies_out,
+                       double *logp_out, int32_t *n_out, hipStream_t s) {
   const spg_peps *pp = env->peps;
   const int R = pp->rows, C = pp->cols, N = R * C, d = pp->d, chi = env->chi;
   const int M = prm->max_states;
-  hipStream_t s = (hipStream_t)stream;
   ensure_search(env, M);
+  const bool guided = prop != nullptr;
+  if (guided || td) {
+    ensure_guide(env, M);
+    fill_zero(env->gstats.as<double>(), 3, s);
+    fill_zero(env->ghist.as<double>(), 1024, s);
+  }
   const SearchTabs t = tabs_of(env);
   const double *A = env->A.as<double>();
   const size_t site_sz = (size_t)chi * d * chi;
   const long rstride = (long)(C + 1) * chi;
   double *Rv = env->Rv.as<double>();
+  double *Rsc = (guided || td) ? env->Rsc.as<double>() : nullptr;
+  GuideWork g{};
+  if (guided || td) {
+    g = guide_of(env);
+    site_features(t, A, env->sf.as<float>(), env->rscr.as<double>(), s);
+  }
+  const int K = guided ? (int)std::min<double>(std::ceil(prm->kappa * M), 2147483647.0) : 0;
   int cur = 0;
   long B = 1;
   fill_zero(env->score[0].as<double>(), 1, s);
@@ -703,6 +757,21 @@ int spg_branch_and_bound(const spg_env_t *cenv, const spg_search_params *prm, in
   const bool lp = env->precision != SPG_FP64;
   const char *Al = env->Alp.as<char>();
   const size_t eb = lp ? lp_elt(env) : 0;
+  int64_t n_resolved = 0;
+  if (td) {
+    td->off.clear();
+    td->nb.clear();
+    long tot = 0, b = 1;
+    for (int k = 0; k < N; ++k) {
+      td->off.push_back(tot);
+      td->nb.push_back((int)b);
+      tot += b * d;
+      b = std::min<long>(M, b * d);
+    }
+    td->feats.ensure((size_t)tot * SPG_PROPOSAL_FEATURES * 4);
+    td->targets.ensure((size_t)tot * 4);
+    env->tmp.ensure((size_t)M * d * 8);
+  }
   for (int r = 0; r < R; ++r) {
     const int n_anc = (int)B;
     const int *dm = env->dims.data() + r * (C + 1);
@@ -718,53 +787,281 @@ int spg_branch_and_bound(const spg_env_t *cenv, const spg_search_params *prm, in
                          Rf + (size_t)c * chi, rstride, dm[c], dm[c + 1], s);
     } else {
       set_e0(n_anc, chi, Rv + (size_t)C * chi, rstride, s);
-      for (int c = C - 1; c >= 1; --c)
+      // the guarded steps also need R_0 and the scales (Z_b = scale * L^b . R_c)
+      const int c_lo = guided ? 0 : 1;
+      for (int c = C - 1; c >= c_lo; --c)
         right_env_col(t, r, c, n_anc, env->cfg[cur].as<uint8_t>(), N,
                       A + ((size_t)r * C + c) * site_sz, Rv + (size_t)(c + 1) * chi,
-                      Rv + (size_t)c * chi, rstride, dm[c], dm[c + 1], s);
+                      Rv + (size_t)c * chi, rstride, dm[c], dm[c + 1], s,
+                      guided ? Rsc + c : nullptr, C + 1);
     }
     for (int c = 0; c < C; ++c) {
+      const int k = r * C + c;
       const double *Arc = A + ((size_t)r * C + c) * site_sz;
       const void *Alc = lp ? (const void *)(Al + ((size_t)r * C + c) * site_sz * eb) : nullptr;
-      if (lp)
-        lp_marginals(t, env->precision, r, c, (int)B, env->cfg[cur].as<uint8_t>(), N, Alc,
-                     env->L[cur].as<float>(), env->anc[cur].as<int32_t>(), env->Rv.as<float>(),
-                     rstride, env->score[cur].as<double>(), env->cand.as<double>(), 1, dm[c],
-                     dm[c + 1], s);
-      else
-        marginals(t, r, c, (int)B, env->cfg[cur].as<uint8_t>(), N, Arc, env->L[cur].as<double>(),
-                  env->anc[cur].as<int32_t>(), Rv, rstride, env->score[cur].as<double>(),
-                  env->cand.as<double>(), 1, dm[c], dm[c + 1], s);
-      if (prm->cut_off_prob > 0.0) apply_cutoff((int)(B * d), log_cut, env->cand.as<double>(), s);
+      const uint8_t *cfg = env->cfg[cur].as<uint8_t>();
+      const double *score = env->score[cur].as<double>();
       const long Bn = std::min<long>(M, B * d);
-      select_topm((int)(B * d), M, env->cand.as<double>(), env->sel.as<int32_t>(),
-                  env->keys.as<uint64_t>(), env->ids.as<int32_t>(), s);
+      n_resolved += B * d;
+      const double *sel_score = nullptr;
+      if (guided) {
+        // parents are sorted by score: score[0] is the best
+        propose(t, r, c, (int)B, cfg, N, score, score, env->sf.as<float>(),
+                prop->prm.as<float>(), prop->H, nullptr, g.bins, g.hist, s);
+        guided_step(t, r, c, (int)B, M, K, cfg, N, Arc, env->L[cur].as<double>(),
+                    env->anc[cur].as<int32_t>(), Rv, rstride, Rsc, score, g, dm[c], dm[c + 1],
+                    s);
+        if (prm->cut_off_prob > 0.0)
+          apply_cutoff((int)(B * d), log_cut, g.lkey, s, g.n_list);
+        select_topm((int)(B * d), M, g.lkey, env->sel.as<int32_t>(), env->keys.as<uint64_t>(),
+                    env->ids.as<int32_t>(), s, g.n_list, g.lid, env->selscore.as<double>());
+        sel_score = env->selscore.as<double>();
+      } else {
+        if (lp)
+          lp_marginals(t, env->precision, r, c, (int)B, cfg, N, Alc, env->L[cur].as<float>(),
+                       env->anc[cur].as<int32_t>(), env->Rv.as<float>(), rstride, score,
+                       env->cand.as<double>(), 1, dm[c], dm[c + 1], s);
+        else
+          marginals(t, r, c, (int)B, cfg, N, Arc, env->L[cur].as<double>(),
+                    env->anc[cur].as<int32_t>(), Rv, rstride, score, env->cand.as<double>(), 1,
+                    dm[c], dm[c + 1], s);
+        if (td) {
+          propose(t, r, c, (int)B, cfg, N, score, score, env->sf.as<float>(), nullptr, 1,
+                  td->feats.as<float>() + td->off[k] * SPG_PROPOSAL_FEATURES, nullptr, nullptr,
+                  s);
+          marginals(t, r, c, (int)B, cfg, N, Arc, env->L[cur].as<double>(),
+                    env->anc[cur].as<int32_t>(), Rv, rstride, nullptr, env->tmp.as<double>(), 0,
+                    dm[c], dm[c + 1], s);
+          to_float(B * d, env->tmp.as<double>(), td->targets.as<float>() + td->off[k], s);
+        }
+        if (prm->cut_off_prob > 0.0)
+          apply_cutoff((int)(B * d), log_cut, env->cand.as<double>(), s);
+        select_topm((int)(B * d), M, env->cand.as<double>(), env->sel.as<int32_t>(),
+                    env->keys.as<uint64_t>(), env->ids.as<int32_t>(), s);
+      }
       const int nx = cur ^ 1;
       if (lp)
-        lp_beam_update(t, env->precision, r, c, (int)Bn, env->sel.as<int32_t>(), N,
-                       env->cfg[cur].as<uint8_t>(), env->energy[cur].as<double>(),
-                       env->L[cur].as<float>(), env->anc[cur].as<int32_t>(),
-                       env->cand.as<double>(), Alc, c < C - 1, env->cfg[nx].as<uint8_t>(),
-                       env->energy[nx].as<double>(), env->score[nx].as<double>(),
-                       env->L[nx].as<float>(), env->anc[nx].as<int32_t>(), dm[c], dm[c + 1], s);
+        lp_beam_update(t, env->precision, r, c, (int)Bn, env->sel.as<int32_t>(), N, cfg,
+                       env->energy[cur].as<double>(), env->L[cur].as<float>(),
+                       env->anc[cur].as<int32_t>(), env->cand.as<double>(), Alc, c < C - 1,
+                       env->cfg[nx].as<uint8_t>(), env->energy[nx].as<double>(),
+                       env->score[nx].as<double>(), env->L[nx].as<float>(),
+                       env->anc[nx].as<int32_t>(), dm[c], dm[c + 1], s);
       else
-        beam_update(t, r, c, (int)Bn, env->sel.as<int32_t>(), N, env->cfg[cur].as<uint8_t>(),
+        beam_update(t, r, c, (int)Bn, env->sel.as<int32_t>(), N, cfg,
                     env->energy[cur].as<double>(), env->L[cur].as<double>(),
                     env->anc[cur].as<int32_t>(), env->cand.as<double>(), Arc, c < C - 1,
                     env->cfg[nx].as<uint8_t>(), env->energy[nx].as<double>(),
                     env->score[nx].as<double>(), env->L[nx].as<double>(),
-                    env->anc[nx].as<int32_t>(), dm[c], dm[c + 1], s);
+                    env->anc[nx].as<int32_t>(), dm[c], dm[c + 1], s, sel_score);
       cur = nx;
       B = Bn;
     }
   }
-  final_sort(t, (int)B, N, env->cfg[cur].as<uint8_t>(), env->score[cur].as<double>(), states_out,
-             energies_out, logp_out, env->ework.as<double>(), env->perm.as<int32_t>(),
-             env->nvalid.as<int32_t>(), s);
+  if (states_out)
+    final_sort(t, (int)B, N, env->cfg[cur].as<uint8_t>(), env->score[cur].as<double>(),
+               states_out, energies_out, logp_out, env->ework.as<double>(),
+               env->perm.as<int32_t>(), env->nvalid.as<int32_t>(), s);
   int32_t nv = 0;
-  SPG_HIP(hipMemcpyAsync(&nv, env->nvalid.p, 4, hipMemcpyDeviceToHost, s));
+  unsigned long long st[3] = {0, 0, 0};
+  if (states_out) SPG_HIP(hipMemcpyAsync(&nv, env->nvalid.p, 4, hipMemcpyDeviceToHost, s));
+  if (guided) SPG_HIP(hipMemcpyAsync(st, env->gstats.p, sizeof(st), hipMemcpyDeviceToHost, s));
   SPG_HIP(hipStreamSynchronize(s));
-  *n_out = nv;
+  env->last_stats[0] = guided ? (int64_t)st[0] : n_resolved;
+  env->last_stats[1] = n_resolved;
+  env->last_stats[2] = guided ? (int64_t)st[2] : 0;
+  if (n_out) *n_out = nv;
+}
+
+int spg_branch_and_bound(const spg_env_t *cenv, const spg_search_params *prm, int32_t *states_out,
+                         double *energies_out, double *logp_out, int32_t *n_out, void *stream) {
+  SPG_TRY
+  if (!cenv || !prm || !states_out || !energies_out || !logp_out || !n_out)
+    return fail(SPG_ERR_INVALID, "spg_branch_and_bound: null argument");
+  if (prm->max_states < 1 || prm->max_states > 65536)
+    return fail(SPG_ERR_UNSUPPORTED, "spg_branch_and_bound: max_states must be in 1..65536");
+  if (!(prm->cut_off_prob >= 0.0) || prm->cut_off_prob >= 1.0)
+    return fail(SPG_ERR_INVALID, "spg_branch_and_bound: cut_off_prob must be in [0, 1)");
+  spg_env *env = const_cast<spg_env *>(cenv);
+  if (prm->proposal) {
+    if (!(prm->kappa > 0.0))
+      return fail(SPG_ERR_INVALID, "spg_branch_and_bound: kappa must be > 0 with a proposal");
+    if (env->precision != SPG_FP64)
+      return fail(SPG_ERR_UNSUPPORTED, "spg_branch_and_bound: the proposal needs an FP64 env");
+  }
+  run_search(env, prm, prm->proposal, nullptr, states_out, energies_out, logp_out, n_out,
+             (hipStream_t)stream);
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_search_stats(const spg_env_t *env, int64_t *counts) {
+  if (!env || !counts) return fail(SPG_ERR_INVALID, "spg_search_stats: null argument");
+  for (int i = 0; i < 3; ++i) counts[i] = env->last_stats[i];
+  return SPG_OK;
+}
+
+// ---- learned proposal ------------------------------------------------------
+
+int spg_proposal_create(int32_t hidden, uint64_t seed, spg_proposal_t **out) {
+  SPG_TRY
+  if (!out) return fail(SPG_ERR_INVALID, "spg_proposal_create: null out");
+  if (hidden < 1 || hidden > kMaxHidden)
+    return fail(SPG_ERR_INVALID, "spg_proposal_create: hidden must be in 1..64");
+  const int H = hidden, P = mlp_n_params(H);
+  std::vector<float> w(P, 0.0f);
+  // uniform(-1, 1) from SplitMix64 output i (top 53 bits), scaled per layer
+  for (int i = 0; i < P; ++i) {
+    const bool w1 = i < H * kFeat, w2 = i >= H * kFeat + H && i < H * kFeat + 2 * H;
+    if (!w1 && !w2) continue;
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    w[i] = (float)(u * std::sqrt(6.0 / (w1 ? kFeat : H)));
+  }
+  spg_proposal *p = new spg_proposal();
+  try {
+    p->H = H;
+    p->prm.ensure((size_t)P * 4);
+    p->m.ensure((size_t)P * 4);
+    p->v.ensure((size_t)P * 4);
+    p->grad.ensure((size_t)P * 4);
+    p->loss.ensure(64);
+    p->partial.ensure(mlp_partial_floats(H) * 4);
+    SPG_HIP(hipMemcpy(p->prm.p, w.data(), (size_t)P * 4, hipMemcpyHostToDevice));
+  } catch (...) {
+    delete p;
+    throw;
+  }
+  *out = p;
+  return SPG_OK;
+  SPG_CATCH
+}
+
+void spg_proposal_free(spg_proposal_t *prop) { delete prop; }
+
+int spg_proposal_params(spg_proposal_t *prop, float *host_out, const float *host_in,
+                        int32_t *n_params) {
+  SPG_TRY
+  if (!prop) return fail(SPG_ERR_INVALID, "spg_proposal_params: null proposal");
+  const int P = mlp_n_params(prop->H);
+  if (n_params) *n_params = P;
+  SPG_HIP(hipDeviceSynchronize());
+  if (host_out) SPG_HIP(hipMemcpy(host_out, prop->prm.p, (size_t)P * 4, hipMemcpyDeviceToHost));
+  if (host_in) {
+    SPG_HIP(hipMemcpy(prop->prm.p, host_in, (size_t)P * 4, hipMemcpyHostToDevice));
+    SPG_HIP(hipMemset(prop->m.p, 0, (size_t)P * 4));
+    SPG_HIP(hipMemset(prop->v.p, 0, (size_t)P * 4));
+    prop->t = 0;
+  }
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_proposal_features(const spg_env_t *cenv, int32_t site, int32_t n_beam,
+                          const int32_t *beam_cfg, const double *beam_score, float *feats_out,
+                          void *stream) {
+  SPG_TRY
+  if (!cenv || !beam_cfg || !beam_score || !feats_out)
+    return fail(SPG_ERR_INVALID, "spg_proposal_features: null argument");
+  spg_env *env = const_cast<spg_env *>(cenv);
+  const spg_peps *pp = env->peps;
+  const int C = pp->cols, N = pp->rows * C;
+  if (site < 0 || site >= N) return fail(SPG_ERR_INVALID, "spg_proposal_features: site out of range");
+  if (n_beam < 1) return fail(SPG_ERR_INVALID, "spg_proposal_features: n_beam must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  ensure_search(env, n_beam);
+  ensure_guide(env, n_beam);
+  env->cfg32.ensure((size_t)n_beam * N);
+  uint8_t *cfg = env->cfg32.as<uint8_t>();
+  cfg_from_i32(n_beam, N, beam_cfg, cfg, s);
+  const SearchTabs t = tabs_of(env);
+  site_features(t, env->A.as<double>(), env->sf.as<float>(), env->rscr.as<double>(), s);
+  max_of(n_beam, beam_score, env->smax.as<double>(), s);
+  propose(t, site / C, site % C, n_beam, cfg, N, beam_score, env->smax.as<double>(),
+          env->sf.as<float>(), nullptr, 1, feats_out, nullptr, nullptr, s);
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_proposal_forward(const spg_proposal_t *prop, int32_t n_beam, int32_t d,
+                         const float *feats, float *logp_out, void *stream) {
+  SPG_TRY
+  if (!prop || !feats || !logp_out) return fail(SPG_ERR_INVALID, "spg_proposal_forward: null argument");
+  if (n_beam < 1 || d < 1 || d > 256)
+    return fail(SPG_ERR_INVALID, "spg_proposal_forward: n_beam >= 1 and 1 <= d <= 256");
+  mlp_forward(n_beam, d, feats, prop->prm.as<float>(), prop->H, logp_out, (hipStream_t)stream);
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_proposal_loss_grad(const spg_proposal_t *prop, int32_t n_beam, int32_t d,
+                           const float *feats, const float *target_logp, float *grad_out,
+                           float *loss_out, void *stream) {
+  SPG_TRY
+  if (!prop || !feats || !target_logp || !grad_out || !loss_out)
+    return fail(SPG_ERR_INVALID, "spg_proposal_loss_grad: null argument");
+  if (n_beam < 1 || d < 1 || d > 256)
+    return fail(SPG_ERR_INVALID, "spg_proposal_loss_grad: n_beam >= 1 and 1 <= d <= 256");
+  spg_proposal *p = const_cast<spg_proposal *>(prop);
+  mlp_loss_grad(n_beam, d, feats, target_logp, p->prm.as<float>(), p->H, p->partial.as<float>(),
+                grad_out, loss_out, nullptr, (hipStream_t)stream);
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_proposal_adam(spg_proposal_t *prop, const float *grad, float learning_rate,
+                      void *stream) {
+  SPG_TRY
+  if (!prop || !grad) return fail(SPG_ERR_INVALID, "spg_proposal_adam: null argument");
+  if (!(learning_rate > 0.0f)) return fail(SPG_ERR_INVALID, "spg_proposal_adam: learning_rate must be > 0");
+  prop->t += 1;
+  const double tt = (double)prop->t;
+  mlp_adam(mlp_n_params(prop->H), prop->prm.as<float>(), prop->m.as<float>(),
+           prop->v.as<float>(), grad, learning_rate, (float)(1.0 - std::pow(0.9, tt)),
+           (float)(1.0 - std::pow(0.999, tt)), (hipStream_t)stream);
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_proposal_train(spg_proposal_t *prop, const spg_env_t *cenv, const spg_train_params *tp,
+                       void *stream, float *loss_out) {
+  SPG_TRY
+  if (!prop || !cenv || !tp) return fail(SPG_ERR_INVALID, "spg_proposal_train: null argument");
+  if (tp->epochs < 1 || !(tp->learning_rate > 0.0f))
+    return fail(SPG_ERR_INVALID, "spg_proposal_train: epochs >= 1 and learning_rate > 0");
+  if (tp->max_states < 1 || tp->max_states > 65536)
+    return fail(SPG_ERR_UNSUPPORTED, "spg_proposal_train: max_states must be in 1..65536");
+  spg_env *env = const_cast<spg_env *>(cenv);
+  if (env->precision != SPG_FP64)
+    return fail(SPG_ERR_UNSUPPORTED, "spg_proposal_train: needs an FP64 env");
+  hipStream_t s = (hipStream_t)stream;
+  const int N = env->peps->rows * env->peps->cols, d = env->peps->d;
+  spg_search_params sp{};
+  sp.max_states = tp->max_states;
+  TrainData td;
+  run_search(env, &sp, nullptr, &td, nullptr, nullptr, nullptr, nullptr, s);
+  DevBuf eloss;
+  eloss.ensure((size_t)tp->epochs * 4);
+  for (int e = 0; e < tp->epochs; ++e)
+    for (int k = 0; k < N; ++k) {
+      mlp_loss_grad(td.nb[k], d, td.feats.as<float>() + td.off[k] * SPG_PROPOSAL_FEATURES,
+                    td.targets.as<float>() + td.off[k], prop->prm.as<float>(), prop->H,
+                    prop->partial.as<float>(), prop->grad.as<float>(), prop->loss.as<float>(),
+                    eloss.as<float>() + e, s);
+      prop->t += 1;
+      const double tt = (double)prop->t;
+      mlp_adam(mlp_n_params(prop->H), prop->prm.as<float>(), prop->m.as<float>(),
+               prop->v.as<float>(), prop->grad.as<float>(), tp->learning_rate,
+               (float)(1.0 - std::pow(0.9, tt)), (float)(1.0 - std::pow(0.999, tt)), s);
+    }
+  std::vector<float> h(tp->epochs);
+  SPG_HIP(hipMemcpyAsync(h.data(), eloss.p, (size_t)tp->epochs * 4, hipMemcpyDeviceToHost, s));
+  SPG_HIP(hipStreamSynchronize(s));
+  if (loss_out)
+    for (int e = 0; e < tp->epochs; ++e) loss_out[e] = h[e] / (float)N;
   return SPG_OK;
   SPG_CATCH
 }

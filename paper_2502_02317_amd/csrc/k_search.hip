@@ -13,6 +13,7 @@
 #include <cfloat>
 #include <climits>
 
+#include "search_dev.h"
 #include "spg_internal.h"
 #include "wave.h"
 
@@ -23,42 +24,13 @@ namespace {
 inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 
-// g^b_c(s): couplings of x_{r,c} = s to the fixed row above (1 for r = 0).
-__device__ __forceinline__ double field(const SearchTabs &t, int r, int c, const uint8_t *cb,
-                                        int s) {
-  if (r == 0) return 1.0;
-  const int C = t.cols, d = t.d;
-  const uint8_t *up = cb + (r - 1) * C;
-  const long dd = (long)d * d;
-  double g = t.W_v[((long)(r - 1) * C + c) * dd + up[c] * d + s];
-  if (c > 0) g *= t.W_d[((long)(r - 1) * (C - 1) + (c - 1)) * dd + up[c - 1] * d + s];
-  if (c < C - 1) g *= t.W_a[((long)(r - 1) * (C - 1) + c) * dd + up[c + 1] * d + s];
-  return g;
-}
-
-// Energy added by x_{r,c} = s: the Eq. (1) terms that close at this site.
-__device__ __forceinline__ double delta_energy(const SearchTabs &t, int r, int c,
-                                               const uint8_t *cb, int s) {
-  const int C = t.cols, d = t.d;
-  const long dd = (long)d * d;
-  double e = t.E_loc[((long)r * C + c) * d + s];
-  if (c > 0) e += t.E_h[((long)r * (C - 1) + (c - 1)) * dd + cb[r * C + c - 1] * d + s];
-  if (r > 0) {
-    const uint8_t *up = cb + (r - 1) * C;
-    e += t.E_v[((long)(r - 1) * C + c) * dd + up[c] * d + s];
-    if (c > 0) e += t.E_d[((long)(r - 1) * (C - 1) + (c - 1)) * dd + up[c - 1] * d + s];
-    if (c < C - 1) e += t.E_a[((long)(r - 1) * (C - 1) + c) * dd + up[c + 1] * d + s];
-  }
-  return e;
-}
-
 constexpr int kWaves = 4;   // wavefronts (work items) per 256-thread block
 
 // R^a_c[alpha] = sum_s g^a_c(s) sum_alpha' A[alpha][s][alpha'] R^a_{c+1}[alpha'], max-normalised
 __global__ __launch_bounds__(256) void k_right_env(SearchTabs t, int r, int c, int n_anc,
                                                    const uint8_t *cfg, int N, const double *A,
                                                    const double *Rnext, double *Rout,
-                                                   long rstride) {
+                                                   long rstride, double *scale, int sstride) {
   __shared__ double Rs[kWaves][kMaxChi];
   __shared__ double gs[kWaves][256];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -92,6 +64,7 @@ __global__ __launch_bounds__(256) void k_right_env(SearchTabs t, int r, int c, i
     const int al = lane + 64 * h;
     if (al < chi) Rout[a * rstride + al] = v[h] * inv;
   }
+  if (scale && lane == 0) scale[(long)a * sstride] = m;
 }
 
 // out[b*d + s] = (add_score ? score[b] : 0) + log p(s | b)
@@ -145,125 +118,68 @@ __global__ __launch_bounds__(256) void k_marginals(SearchTabs t, int r, int c, i
   }
 }
 
-// Key for ascending sort = descending score; NaN sorts with -inf.
-__device__ __forceinline__ uint64_t desc_key(double v) {
-  if (!(v == v)) v = -INFINITY;
-  uint64_t u = __double_as_longlong(v);
-  const uint64_t sign = 0x8000000000000000ull;
-  u = (u & sign) ? ~u : (u | sign);   // ascending in v
-  return ~u;                          // ascending in -v
-}
-__device__ __forceinline__ uint64_t asc_key(double v) {
-  if (!(v == v)) v = INFINITY;
-  uint64_t u = __double_as_longlong(v);
-  const uint64_t sign = 0x8000000000000000ull;
-  return (u & sign) ? ~u : (u | sign);
-}
-
-// Block-wide exclusive scan of 0/1 flags (blockDim = 1024); returns the prefix
-// and writes the block total to *total.
-__device__ int block_excl_scan(int f, int *wsum, int *total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const unsigned long long mask = __ballot(f);
-  const int pre = __popcll(mask & ((1ull << lane) - 1ull));
-  __syncthreads();
-  if (lane == 0) wsum[w] = __popcll(mask);
-  __syncthreads();
-  int off = 0, tot = 0;
-  for (int i = 0; i < nw; ++i) {
-    if (i < w) off += wsum[i];
-    tot += wsum[i];
-  }
-  *total = tot;
-  return off + pre;
-}
-
-// Sort (key, id) pairs ascending in global memory with one workgroup (bitonic).
-__device__ void bitonic_sort_global(uint64_t *keys, int32_t *ids, int n_pow2) {
-  for (int k = 2; k <= n_pow2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n_pow2; i += blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t ki = keys[i], kj = keys[ixj];
-          const int32_t ii = ids[i], ij = ids[ixj];
-          const bool gt = (ki > kj) || (ki == kj && ii > ij);
-          const bool up = ((i & k) == 0);
-          if (gt == up) {
-            keys[i] = kj; keys[ixj] = ki;
-            ids[i] = ij; ids[ixj] = ii;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Top-M of n_cand scores by (score desc, id asc), written to sel[0..min(M,n)-1]
-// in that order.  Radix select of the M-th key (8 passes of 8 bits), ordered
-// compaction, then a bitonic sort of the survivors.
-__global__ __launch_bounds__(1024) void k_select(int n, int M, const double *cand, int32_t *sel,
-                                                uint64_t *kw, int32_t *iw) {
+// Top-M of n scores by (score desc, id asc), written to sel[0..min(M,n)-1] in
+// that order, with the selected scores in sel_score (may be null).  Candidate
+// i has score cand[i] and id cid[i] (cid null: id = i; ids must be unique and
+// non-negative); n is *n_dev when n_dev is given.  Radix select of the M-th
+// key (8 passes of 8 bits), then of the id among keys equal to it, compaction,
+// then a bitonic sort of the survivors.
+__global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, int M,
+                                                const double *cand, const int32_t *cid,
+                                                int32_t *sel, double *sel_score, uint64_t *kw,
+                                                int32_t *iw) {
   __shared__ unsigned hist[256];
   __shared__ uint64_t sh_prefix;
-  __shared__ int sh_need, sh_count;
+  __shared__ int sh_need;
   __shared__ int wsum[16];
   const int tid = threadIdx.x;
+  const int n = n_dev ? *n_dev : n_host;
   const int Me = (M < n) ? M : n;
-  uint64_t prefix = 0, pmask = 0;
-  int need = Me;
+  auto key_at = [&](int i) { return desc_key(cand[i]); };
+  auto id_at = [&](int i) { return cid ? cid[i] : i; };
+  uint64_t kthr = ~0ull;         // take keys < kthr, and keys == kthr with id <= ithr
+  uint64_t ithr = 0;
+  bool all_eq = true;
   if (Me < n) {
+    uint64_t prefix = 0, pmask = 0;
+    int need = Me;
     for (int shift = 56; shift >= 0; shift -= 8) {
-      for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0u;
-      __syncthreads();
-      for (int i = tid; i < n; i += blockDim.x) {
-        const uint64_t k = desc_key(cand[i]);
-        if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
-      }
-      __syncthreads();
-      if (tid == 0) {
-        int cum = 0, t = 0;
-        for (t = 0; t < 255; ++t) {
-          if (cum + (int)hist[t] >= need) break;
-          cum += hist[t];
-        }
-        sh_need = need - cum;
-        sh_prefix = prefix | ((uint64_t)t << shift);
-      }
-      __syncthreads();
-      need = sh_need;
-      prefix = sh_prefix;
+      radix_digit(n, shift, key_at, pmask, prefix, need, hist, &sh_prefix, &sh_need);
       pmask |= (255ull << shift);
-      __syncthreads();
     }
-  } else {
-    prefix = ~0ull;     // everything selected: all keys <= threshold count as "less"
-    need = 0;
+    kthr = prefix;
+    // need = how many keys equal to kthr are taken; hist still counts them
+    const int n_eq = (int)hist[kthr & 255u];
+    if (need < n_eq) {
+      all_eq = false;
+      const uint64_t kk = kthr;
+      auto idkey_at = [&](int i) -> uint64_t {
+        return (key_at(i) == kk) ? (uint64_t)(uint32_t)id_at(i) : ~0ull;
+      };
+      uint64_t ip = 0, im = 0xFFFFFFFF00000000ull;   // ids fit in 32 bits
+      int need_id = need;
+      for (int shift = 24; shift >= 0; shift -= 8) {
+        radix_digit(n, shift, idkey_at, im, ip, need_id, hist, &sh_prefix, &sh_need);
+        im |= (255ull << shift);
+      }
+      ithr = ip;
+    }
   }
-  // ordered compaction: keys < prefix all taken; keys == prefix the first `need` by id
-  if (tid == 0) sh_count = 0;
-  __syncthreads();
-  int taken_eq = 0, base = 0;
+  // compaction of the survivors (any order: they are sorted next)
+  int base = 0;
   for (int c0 = 0; c0 < n; c0 += blockDim.x) {
     const int i = c0 + tid;
     uint64_t k = 0;
-    int lt = 0, eq = 0;
+    int f = 0;
     if (i < n) {
-      k = desc_key(cand[i]);
-      if (Me == n) lt = 1;
-      else { lt = (k < prefix); eq = (k == prefix); }
+      k = key_at(i);
+      f = (k < kthr) || (k == kthr && (all_eq || (uint64_t)(uint32_t)id_at(i) <= ithr));
+      if (Me == n) f = 1;
     }
-    int tot_eq, tot_lt;
-    const int r_eq = block_excl_scan(eq, wsum, &tot_eq);
-    const int take_eq = eq && (taken_eq + r_eq < need);
-    const int f = lt || take_eq;
     int tot_f;
     const int pos = block_excl_scan(f, wsum, &tot_f);
-    if (f) { kw[base + pos] = k; iw[base + pos] = i; }
+    if (f) { kw[base + pos] = k; iw[base + pos] = id_at(i); }
     base += tot_f;
-    taken_eq += tot_eq;
-    (void)tot_lt;
     __syncthreads();
   }
   int p2 = 1;
@@ -271,14 +187,18 @@ __global__ __launch_bounds__(1024) void k_select(int n, int M, const double *can
   for (int i = Me + tid; i < p2; i += blockDim.x) { kw[i] = ~0ull; iw[i] = INT_MAX; }
   __syncthreads();
   bitonic_sort_global(kw, iw, p2);
-  for (int i = tid; i < Me; i += blockDim.x) sel[i] = iw[i];
+  for (int i = tid; i < Me; i += blockDim.x) {
+    sel[i] = iw[i];
+    if (sel_score) sel_score[i] = key_value(kw[i]);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_beam_update(SearchTabs t, int r, int c, int n_new,
                                                      const int32_t *sel, int N,
                                                      const uint8_t *cfg, const double *energy,
                                                      const double *L, const int32_t *anc,
-                                                     const double *cand, const double *A,
+                                                     const double *cand,
+                                                     const double *sel_score, const double *A,
                                                      int update_L, uint8_t *cfg_o,
                                                      double *energy_o, double *score_o,
                                                      double *L_o, int32_t *anc_o) {
@@ -297,7 +217,7 @@ __global__ __launch_bounds__(256) void k_beam_update(SearchTabs t, int r, int c,
     for (int i = lane; i < N; i += 64) co[i] = (i == k) ? (uint8_t)s : cb[i];
   if (valid && lane == 0) {
     energy_o[j] = energy[b] + delta_energy(t, r, c, cb, s);
-    score_o[j] = cand[id];
+    score_o[j] = sel_score ? sel_score[j] : cand[id];
     anc_o[j] = anc[b];
   }
   if (!update_L) return;
@@ -395,8 +315,10 @@ __global__ void k_gather_out(int n, int N, const int32_t *perm, const uint8_t *c
   }
 }
 
-__global__ __launch_bounds__(1024) void k_cutoff(int n, double log_cut, double *cand) {
+__global__ __launch_bounds__(1024) void k_cutoff(int n_host, const int *n_dev, double log_cut,
+                                                double *cand) {
   __shared__ double red[1024];
+  const int n = n_dev ? *n_dev : n_host;
   double m = -INFINITY;
   for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, cand[i]);
   red[threadIdx.x] = m;
@@ -452,11 +374,11 @@ __global__ __launch_bounds__(256) void k_advance_L(SearchTabs t, int r, int c, i
 
 void right_env_col(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *cfg, int N,
                    const double *A_rc, const double *Rnext, double *Rout, long rstride,
-                   int cl, int cr, hipStream_t s) {
+                   int cl, int cr, hipStream_t s, double *scale, int sstride) {
   KTimer kt_("right_env", s, 2.0 * n_anc * cl * t.d * cr);
   if (n_anc <= 0) return;
   hipLaunchKernelGGL(k_right_env, dim3(nblk(n_anc, kWaves)), dim3(256), 0, s, t, r, c, n_anc,
-                     cfg, N, A_rc, Rnext, Rout, rstride);
+                     cfg, N, A_rc, Rnext, Rout, rstride, scale, sstride);
   SPG_CHECK_LAUNCH();
 }
 
@@ -472,10 +394,11 @@ void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg
 }
 
 void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *keys_work,
-                 int32_t *ids_work, hipStream_t s) {
-  KTimer kt_("select_topm", s, 8.0 * n_cand + 4.0 * (M < n_cand ? M : n_cand));
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, n_cand, M, cand, sel, keys_work,
-                     ids_work);
+                 int32_t *ids_work, hipStream_t s, const int *n_dev, const int32_t *cid,
+                 double *sel_score) {
+  KTimer kt_("select_topm", s, (cid ? 12.0 : 8.0) * n_cand + 4.0 * (M < n_cand ? M : n_cand));
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, n_cand, n_dev, M, cand, cid, sel,
+                     sel_score, keys_work, ids_work);
   SPG_CHECK_LAUNCH();
 }
 
@@ -483,12 +406,12 @@ void beam_update(const SearchTabs &t, int r, int c, int n_new, const int32_t *se
                  const uint8_t *cfg, const double *energy, const double *L, const int32_t *anc,
                  const double *cand, const double *A_rc, int update_L, uint8_t *cfg_o,
                  double *energy_o, double *score_o, double *L_o, int32_t *anc_o, int cl,
-                 int cr, hipStream_t s) {
+                 int cr, hipStream_t s, const double *sel_score) {
   KTimer kt_("beam_update", s, 2.0 * n_new * cl * cr);
   if (n_new <= 0) return;
   hipLaunchKernelGGL(k_beam_update, dim3(nblk(n_new, kWaves)), dim3(256), 0, s, t, r, c, n_new,
-                     sel, N, cfg, energy, L, anc, cand, A_rc, update_L, cfg_o, energy_o,
-                     score_o, L_o, anc_o);
+                     sel, N, cfg, energy, L, anc, cand, sel_score, A_rc, update_L, cfg_o,
+                     energy_o, score_o, L_o, anc_o);
   SPG_CHECK_LAUNCH();
 }
 
@@ -514,8 +437,8 @@ void final_sort(const SearchTabs &t, int n, int N, const uint8_t *cfg, const dou
   SPG_CHECK_LAUNCH();
 }
 
-void apply_cutoff(int n, double log_cut, double *cand, hipStream_t s) {
-  hipLaunchKernelGGL(k_cutoff, dim3(1), dim3(1024), 0, s, n, log_cut, cand);
+void apply_cutoff(int n, double log_cut, double *cand, hipStream_t s, const int *n_dev) {
+  hipLaunchKernelGGL(k_cutoff, dim3(1), dim3(1024), 0, s, n, n_dev, log_cut, cand);
   SPG_CHECK_LAUNCH();
 }
 

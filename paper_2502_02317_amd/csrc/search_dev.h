@@ -1,0 +1,150 @@
+// Device helpers shared by the search kernels: site fields and energies,
+// order-preserving keys, block scans, radix-select steps and a bitonic sort.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <climits>
+#include <cstdint>
+
+#include "spg_internal.h"
+
+namespace spg {
+
+// g^b_c(s): couplings of x_{r,c} = s to the fixed row above (1 for r = 0).
+__device__ __forceinline__ double field(const SearchTabs &t, int r, int c, const uint8_t *cb,
+                                        int s) {
+  if (r == 0) return 1.0;
+  const int C = t.cols, d = t.d;
+  const uint8_t *up = cb + (r - 1) * C;
+  const long dd = (long)d * d;
+  double g = t.W_v[((long)(r - 1) * C + c) * dd + up[c] * d + s];
+  if (c > 0) g *= t.W_d[((long)(r - 1) * (C - 1) + (c - 1)) * dd + up[c - 1] * d + s];
+  if (c < C - 1) g *= t.W_a[((long)(r - 1) * (C - 1) + c) * dd + up[c + 1] * d + s];
+  return g;
+}
+
+// Energy added by x_{r,c} = s: the Eq. (1) terms that close at this site.
+__device__ __forceinline__ double delta_energy(const SearchTabs &t, int r, int c,
+                                               const uint8_t *cb, int s) {
+  const int C = t.cols, d = t.d;
+  const long dd = (long)d * d;
+  double e = t.E_loc[((long)r * C + c) * d + s];
+  if (c > 0) e += t.E_h[((long)r * (C - 1) + (c - 1)) * dd + cb[r * C + c - 1] * d + s];
+  if (r > 0) {
+    const uint8_t *up = cb + (r - 1) * C;
+    e += t.E_v[((long)(r - 1) * C + c) * dd + up[c] * d + s];
+    if (c > 0) e += t.E_d[((long)(r - 1) * (C - 1) + (c - 1)) * dd + up[c - 1] * d + s];
+    if (c < C - 1) e += t.E_a[((long)(r - 1) * (C - 1) + c) * dd + up[c + 1] * d + s];
+  }
+  return e;
+}
+
+// Key for ascending sort = descending score; NaN sorts with -inf.
+__device__ __forceinline__ uint64_t desc_key(double v) {
+  if (!(v == v)) v = -INFINITY;
+  uint64_t u = __double_as_longlong(v);
+  const uint64_t sign = 0x8000000000000000ull;
+  u = (u & sign) ? ~u : (u | sign);   // ascending in v
+  return ~u;                          // ascending in -v
+}
+__device__ __forceinline__ uint64_t asc_key(double v) {
+  if (!(v == v)) v = INFINITY;
+  uint64_t u = __double_as_longlong(v);
+  const uint64_t sign = 0x8000000000000000ull;
+  return (u & sign) ? ~u : (u | sign);
+}
+
+// Block-wide exclusive scan of 0/1 flags (blockDim = 1024); returns the prefix
+// and writes the block total to *total.
+__device__ inline int block_excl_scan(int f, int *wsum, int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const unsigned long long mask = __ballot(f);
+  const int pre = __popcll(mask & ((1ull << lane) - 1ull));
+  __syncthreads();
+  if (lane == 0) wsum[w] = __popcll(mask);
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    if (i < w) off += wsum[i];
+    tot += wsum[i];
+  }
+  *total = tot;
+  return off + pre;
+}
+
+// Sort (key, id) pairs ascending in global memory with one workgroup (bitonic).
+__device__ inline void bitonic_sort_global(uint64_t *keys, int32_t *ids, int n_pow2) {
+  for (int k = 2; k <= n_pow2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n_pow2; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t ki = keys[i], kj = keys[ixj];
+          const int32_t ii = ids[i], ij = ids[ixj];
+          const bool gt = (ki > kj) || (ki == kj && ii > ij);
+          const bool up = ((i & k) == 0);
+          if (gt == up) {
+            keys[i] = kj; keys[ixj] = ki;
+            ids[i] = ij; ids[ixj] = ii;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Inverse of desc_key (NaN came in as -inf).
+__device__ __forceinline__ double key_value(uint64_t k) {
+  const uint64_t sign = 0x8000000000000000ull;
+  const uint64_t w = ~k;
+  return __longlong_as_double((long long)((w & sign) ? (w ^ sign) : ~w));
+}
+
+// One radix-select step: among the items with (key & pmask) == prefix, find
+// the 8-bit digit at `shift` holding the need-th smallest key; updates prefix
+// and need.  Keys come from key_at(i), i < n.  blockDim = 1024.
+template <class KeyAt>
+__device__ inline void radix_digit(int n, int shift, const KeyAt &key_at, uint64_t pmask,
+                            uint64_t &prefix, int &need, unsigned *hist, uint64_t *sh_prefix,
+                            int *sh_need) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0u;
+  __syncthreads();
+  for (int i = tid; i < n; i += blockDim.x) {
+    const uint64_t k = key_at(i);
+    if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  if (tid < 64) {
+    // wave-parallel scan over the 256 digits: lane l owns digits 4l..4l+3
+    unsigned h[4], own = 0u;
+    for (int j = 0; j < 4; ++j) { h[j] = hist[4 * tid + j]; own += h[j]; }
+    unsigned inc = own;
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned v = __shfl_up(inc, o);
+      if (tid >= o) inc += v;
+    }
+    const unsigned excl = inc - own;
+    const unsigned long long hit = __ballot(inc >= (unsigned)need);
+    const int first = hit ? (__ffsll((long long)hit) - 1) : 63;
+    if (tid == first) {
+      unsigned cum = excl;
+      int t = 4 * tid;
+      for (int j = 0; j < 3; ++j, ++t) {
+        if (cum + h[j] >= (unsigned)need) break;
+        cum += h[j];
+      }
+      *sh_need = need - (int)cum;
+      *sh_prefix = prefix | ((uint64_t)t << shift);
+    }
+  }
+  __syncthreads();
+  need = *sh_need;
+  prefix = *sh_prefix;
+  __syncthreads();
+}
+
+}  // namespace spg

@@ -130,33 +130,80 @@ void set_e0(int n, int chi, double *p, long stride, hipStream_t s);
 
 // ---- search kernels (k_search.hip) ----------------------------------------
 struct SearchTabs {         // device tables of the instance
-  int rows, cols, d, chi;
+  int rows, cols, d, chi, kings;
+  double beta;
   const double *E_loc, *E_h, *E_v, *E_d, *E_a;
   const double *W_v, *W_d, *W_a;
 };
 // cl, cr: actual bond dimensions left / right of column c (work accounting only)
+// scale (optional): scale[a * sstride] receives the max-normalisation divisor
 void right_env_col(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *cfg, int N,
                    const double *A_rc, const double *Rnext, double *Rout, long rstride,
-                   int cl, int cr, hipStream_t s);
+                   int cl, int cr, hipStream_t s, double *scale = nullptr, int sstride = 0);
 void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
                const double *A_rc, const double *L, const int32_t *anc, const double *Rv,
                long rstride, const double *score, double *out, int add_score, int cl, int cr,
                hipStream_t s);
+// n_dev (optional): the count is read on the device (n_cand bounds it);
+// cid (optional): candidate ids (default: position); sel_score (optional):
+// the selected scores in selection order.
 void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *keys_work,
-                 int32_t *ids_work, hipStream_t s);
+                 int32_t *ids_work, hipStream_t s, const int *n_dev = nullptr,
+                 const int32_t *cid = nullptr, double *sel_score = nullptr);
 void beam_update(const SearchTabs &t, int r, int c, int n_new, const int32_t *sel, int N,
                  const uint8_t *cfg, const double *energy, const double *L, const int32_t *anc,
                  const double *cand, const double *A_rc, int update_L, uint8_t *cfg_o,
                  double *energy_o, double *score_o, double *L_o, int32_t *anc_o, int cl,
-                 int cr, hipStream_t s);
+                 int cr, hipStream_t s, const double *sel_score = nullptr);
 void beam_reset_row(int n, int chi, double *L, int32_t *anc, hipStream_t s);
 void final_sort(const SearchTabs &t, int n, int N, const uint8_t *cfg, const double *score,
                 int32_t *states_out, double *energies_out, double *logp_out, double *e_work,
                 int32_t *perm_work, int32_t *n_valid, hipStream_t s);
-void apply_cutoff(int n, double log_cut, double *cand, hipStream_t s);
+void apply_cutoff(int n, double log_cut, double *cand, hipStream_t s,
+                  const int *n_dev = nullptr);
 void cfg_from_i32(int n, int N, const int32_t *src, uint8_t *dst, hipStream_t s);
 void advance_L(const SearchTabs &t, int r, int c, int n, const uint8_t *cfg, int N,
                const double *A_rc, double *L, double *tmp, hipStream_t s);
+
+// ---- learned proposal and guarded steps (k_propose.hip, k_mlp.hip) --------
+// Device workspace of the guarded search steps.
+struct GuideWork {
+  uint16_t *bins;           // [n_beam][d] gap bin of each child
+  unsigned *hist;           // [2048] bin counts (cleared by each step)
+  int *jstar, *n_list;      // last bin of the candidate set; list length
+  double *lkey;             // [n_beam * d] list scores
+  int32_t *lid;             // [n_beam * d] list ids b * d + s
+  double *bound, *tau;      // [n_beam] bound of unevaluated children; M-th list score
+  int32_t *off, *cnt;       // [n_beam] list offset and size of each parent's candidates
+  unsigned long long *stats;  // [3] exact evaluations, (unused), fallback parents
+};
+// sf [rows*cols][d][2]: parent-independent features; rscr [rows][cols+1][chi]
+void site_features(const SearchTabs &t, const double *A, float *sf, double *rscr,
+                   hipStream_t s);
+// Features ([n_beam][d][F], optional) and, when bins/hist are given, the gap
+// bins of score_b + log p^(s|b) below *smax counted into hist.
+void propose(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
+             const double *score, const double *smax, const float *sf, const float *prm, int H,
+             float *feat_out, uint16_t *bins, unsigned *hist, hipStream_t s);
+// Candidate threshold, exact weights on the set, guard and fallback; leaves
+// the step's list (lkey, lid, *n_list) for the top-M selection.
+void guided_step(const SearchTabs &t, int r, int c, int n_beam, int M, int K, const uint8_t *cfg,
+                 int N, const double *A_rc, const double *L, const int32_t *anc, const double *Rv,
+                 long rstride, const double *Rsc, const double *score, GuideWork &g, int cl,
+                 int cr, hipStream_t s);
+void max_of(int n, const double *v, double *out, hipStream_t s);
+// Network evaluation and training (k_mlp.hip); deterministic reductions.
+void mlp_forward(int n_beam, int d, const float *feats, const float *prm, int H, float *logp,
+                 hipStream_t s);
+// grad [P] and loss [1] of the mean cross-entropy; partial holds
+// mlp_partial_floats(H) floats; loss_acc (optional) += loss.
+size_t mlp_partial_floats(int H);
+void mlp_loss_grad(int n_beam, int d, const float *feats, const float *target, const float *prm,
+                   int H, float *partial, float *grad, float *loss, float *loss_acc,
+                   hipStream_t s);
+void mlp_adam(int P, float *prm, float *m, float *v, const float *grad, float lr, float bc1,
+              float bc2, hipStream_t s);
+void to_float(long n, const double *src, float *dst, hipStream_t s);
 
 // ---- reduced-precision search contractions (k_search_lp.hip) --------------
 // precision: SPG_FP32 (A in FP32) or SPG_BF16 (A in BF16); vectors L, R FP32.
@@ -199,4 +246,15 @@ struct spg_env {
   // search workspace (grown on demand)
   spg::DevBuf cfg[2], score[2], energy[2], L[2], anc[2], Rv, cand, sel, keys, ids, ework,
       perm, nvalid, tmp, cfg32;
+  // guarded search with a proposal: right-environment scales, per-site
+  // features, step workspace and counters
+  spg::DevBuf Rsc, sf, rscr, gbins, ghist, gint, glkey, glid, gbound, gtau, goff, gcnt, gstats,
+      selscore, smax;
+  int64_t last_stats[3] = {0, 0, 0};
+};
+
+struct spg_proposal {
+  int H = 0;
+  int64_t t = 0;                 // Adam steps taken
+  spg::DevBuf prm, m, v, grad, partial, loss;
 };

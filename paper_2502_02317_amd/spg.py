@@ -41,14 +41,26 @@ class MpsParams(C.Structure):
 
 
 class SearchParams(C.Structure):
-    _fields_ = [("max_states", C.c_int32), ("cut_off_prob", C.c_double)]
+    _fields_ = [("max_states", C.c_int32), ("cut_off_prob", C.c_double),
+                ("proposal", C.c_void_p), ("kappa", C.c_double)]
+
+
+class TrainParams(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("learning_rate", C.c_float), ("max_states", C.c_int32)]
+
+
+N_FEATURES = 6
 
 
 EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_branch_and_bound",
            "spg_free_peps", "spg_free_env", "spg_last_error", "spg_env_info", "spg_env_export",
-           "spg_env_import", "spg_profile_enable", "spg_profile_reset", "spg_profile_query"]
+           "spg_env_import", "spg_profile_enable", "spg_profile_reset", "spg_profile_query",
+           "spg_proposal_create", "spg_proposal_free", "spg_proposal_params",
+           "spg_proposal_train", "spg_proposal_features", "spg_proposal_forward",
+           "spg_proposal_loss_grad", "spg_proposal_adam", "spg_search_stats"]
 KERNEL_CLASSES = ["gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box", "right_env",
-                  "marginals", "select_topm", "beam_update", "final_sort"]
+                  "marginals", "select_topm", "beam_update", "final_sort", "propose",
+                  "guided_eval", "mlp_grad"]
 
 _lib = None
 
@@ -77,8 +89,22 @@ def load() -> C.CDLL:
     lib.spg_profile_reset.argtypes = []
     lib.spg_profile_reset.restype = None
     lib.spg_profile_query.argtypes = [C.c_char_p, C.POINTER(C.c_int64), f64p, f64p]
+    f32p = C.POINTER(C.c_float)
+    lib.spg_proposal_create.argtypes = [i32, C.c_uint64, C.POINTER(vp)]
+    lib.spg_proposal_free.argtypes = [vp]
+    lib.spg_proposal_free.restype = None
+    lib.spg_proposal_params.argtypes = [vp, vp, vp, i32p]
+    lib.spg_proposal_train.argtypes = [vp, vp, C.POINTER(TrainParams), vp, f32p]
+    lib.spg_proposal_features.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    lib.spg_proposal_forward.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.spg_proposal_loss_grad.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+    lib.spg_proposal_adam.argtypes = [vp, vp, C.c_float, vp]
+    lib.spg_search_stats.argtypes = [vp, C.POINTER(C.c_int64)]
     for name in ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_branch_and_bound",
-                 "spg_env_info", "spg_env_export", "spg_env_import", "spg_profile_query"]:
+                 "spg_env_info", "spg_env_export", "spg_env_import", "spg_profile_query",
+                 "spg_proposal_create", "spg_proposal_params", "spg_proposal_train",
+                 "spg_proposal_features", "spg_proposal_forward", "spg_proposal_loss_grad",
+                 "spg_proposal_adam", "spg_search_stats"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -165,9 +191,13 @@ def marginals(env: Env, site: int, beam_cfg, out, stream=None):
 
 
 def branch_and_bound(env: Env, max_states: int, states_out, energies_out, logp_out,
-                     cut_off_prob: float = 0.0, stream=None) -> int:
-    """spg_branch_and_bound into device tensors; returns n_out."""
-    prm = SearchParams(int(max_states), float(cut_off_prob))
+                     cut_off_prob: float = 0.0, stream=None, proposal=None,
+                     kappa: float = 2.0) -> int:
+    """spg_branch_and_bound into device tensors; returns n_out.  With a
+    Proposal the guarded steps run (kappa * max_states exact children per step
+    before the guard)."""
+    prm = SearchParams(int(max_states), float(cut_off_prob),
+                       proposal.handle if proposal is not None else None, float(kappa))
     n = C.c_int32(0)
     _check(load().spg_branch_and_bound(env.handle, C.byref(prm), _ptr(states_out),
                                        _ptr(energies_out), _ptr(logp_out), C.byref(n),
@@ -249,3 +279,77 @@ def unpack_mps(T, dims):
     """Inverse of pack_oracle_mps: list of rows of (chi_c, d, chi_c+1) arrays."""
     R, Cc = T.shape[0], T.shape[1]
     return [[T[r, c, :dims[r, c], :, :dims[r, c + 1]].copy() for c in range(Cc)] for r in range(R)]
+
+
+# ---- learned proposal ---------------------------------------------------------
+
+class Proposal:
+    """Owner of an spg_proposal_t handle (2-layer FP32 network, hidden units H)."""
+
+    def __init__(self, hidden: int = 32, seed: int = 1):
+        h = C.c_void_p()
+        _check(load().spg_proposal_create(int(hidden), int(seed), C.byref(h)))
+        self.handle = h
+        self.hidden = int(hidden)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.spg_proposal_free(self.handle)
+            self.handle = None
+
+    @property
+    def n_params(self) -> int:
+        n = C.c_int32(0)
+        _check(load().spg_proposal_params(self.handle, None, None, C.byref(n)))
+        return n.value
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        n = C.c_int32(0)
+        _check(load().spg_proposal_params(self.handle, out.ctypes.data, None, C.byref(n)))
+        return out
+
+    def set_params(self, p) -> None:
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        n = C.c_int32(0)
+        _check(load().spg_proposal_params(self.handle, None, p.ctypes.data, C.byref(n)))
+
+    def train(self, env: Env, epochs: int = 10, learning_rate: float = 1e-2,
+              max_states: int = 64, stream=None) -> np.ndarray:
+        tp = TrainParams(int(epochs), float(learning_rate), int(max_states))
+        loss = np.zeros(int(epochs), dtype=np.float32)
+        _check(load().spg_proposal_train(self.handle, env.handle, C.byref(tp), _stream(stream),
+                                         loss.ctypes.data_as(C.POINTER(C.c_float))))
+        return loss
+
+    def forward(self, feats, logp_out, stream=None):
+        n, d = int(feats.shape[0]), int(feats.shape[1])
+        _check(load().spg_proposal_forward(self.handle, n, d, _ptr(feats), _ptr(logp_out),
+                                           _stream(stream)))
+        return logp_out
+
+    def loss_grad(self, feats, target, grad_out, loss_out, stream=None):
+        n, d = int(feats.shape[0]), int(feats.shape[1])
+        _check(load().spg_proposal_loss_grad(self.handle, n, d, _ptr(feats), _ptr(target),
+                                             _ptr(grad_out), _ptr(loss_out), _stream(stream)))
+
+    def adam(self, grad, learning_rate: float, stream=None):
+        _check(load().spg_proposal_adam(self.handle, _ptr(grad), float(learning_rate),
+                                        _stream(stream)))
+
+
+def proposal_features(env: Env, site: int, beam_cfg, beam_score, feats_out, stream=None):
+    """spg_proposal_features: beam_cfg int32 [n][N], beam_score float64 [n] ->
+    feats_out float32 [n][d][6] (device tensors)."""
+    _check(load().spg_proposal_features(env.handle, int(site), int(beam_cfg.shape[0]),
+                                        _ptr(beam_cfg), _ptr(beam_score), _ptr(feats_out),
+                                        _stream(stream)))
+    return feats_out
+
+
+def search_stats(env: Env):
+    """(children evaluated exactly, children resolved, fallback parents) of the
+    env's last search."""
+    out = (C.c_int64 * 3)()
+    _check(load().spg_search_stats(env.handle, out))
+    return int(out[0]), int(out[1]), int(out[2])

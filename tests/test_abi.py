@@ -64,3 +64,23 @@ def test_null_arguments():
     assert lib.spg_branch_and_bound(None, None, None, None, None, C.byref(n), None) == -1
     lib.spg_free_peps(None)
     lib.spg_free_env(None)
+
+
+def test_proposal_entry_points_reject_bad_arguments():
+    """Checked before any device call, so these run without a GPU."""
+    from paper_2502_02317_amd import spg
+    lib = spg.load()
+    h = C.c_void_p()
+    assert lib.spg_proposal_create(0, 1, C.byref(h)) == -1
+    assert lib.spg_proposal_create(65, 1, C.byref(h)) == -1
+    assert lib.spg_proposal_create(8, 1, None) == -1
+    assert not h.value
+    n = C.c_int32()
+    assert lib.spg_proposal_params(None, None, None, C.byref(n)) == -1
+    assert lib.spg_proposal_train(None, None, None, None, None) == -1
+    assert lib.spg_proposal_features(None, 0, 1, None, None, None, None) == -1
+    assert lib.spg_proposal_forward(None, 1, 2, None, None, None) == -1
+    assert lib.spg_proposal_loss_grad(None, 1, 2, None, None, None, None, None) == -1
+    assert lib.spg_proposal_adam(None, None, C.c_float(0.1), None) == -1
+    assert lib.spg_search_stats(None, None) == -1
+    lib.spg_proposal_free(None)
