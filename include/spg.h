@@ -151,6 +151,48 @@ void spg_free_peps(spg_peps_t *peps);
 void spg_free_env(spg_env_t *env);
 const char *spg_last_error(void);
 
+/* ---- batches ------------------------------------------------------------
+ * Many independent instances (each its own lattice size, d, chi and beam)
+ * run as one unit: every instance's contraction and search is enqueued on
+ * one of n_streams streams (round-robin; instances sharing a stream share one
+ * contraction workspace), forked from and joined back into the caller's
+ * stream.  With use_graph the whole batch is captured once into a HIP graph
+ * and later runs replay it as a single launch.  Each instance's results are
+ * those of spg_boundary_mps + spg_branch_and_bound on it with the same GEMM
+ * tile (bitwise: the kernels are deterministic). */
+typedef struct spg_batch spg_batch_t;
+typedef struct {
+  int32_t chi, num_sweeps, precision, oversample, power_iters;  /* as spg_mps_params */
+  int32_t max_states;                                           /* as spg_search_params */
+  double cut_off_prob;
+} spg_batch_item;
+
+/* peps HOST array [n] of PEPS handles (kept alive by the caller while the
+ * batch exists), items HOST [n].  Allocates every per-instance buffer.
+ * Errors: SPG_ERR_INVALID, SPG_ERR_UNSUPPORTED, SPG_ERR_OOM, SPG_ERR_HIP. */
+int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items, int32_t n,
+                     int32_t n_streams, spg_batch_t **out);
+void spg_batch_free(spg_batch_t *batch);
+/* Runs every instance (asynchronous on `stream`).  The first run is eager
+ * and synchronises once (it sizes the workspaces); with use_graph != 0 the
+ * following runs capture the batch into a graph (once) and replay it. */
+int spg_batch_run(spg_batch_t *batch, int32_t use_graph, void *stream);
+/* Results of instance i after a run (synchronises the device): n_out HOST =
+ * rows with finite log-probability; the first n_out rows of its states
+ * (int32 [.][rows*cols]), energies and log-probabilities (float64, sorted by
+ * energy) are copied to the caller's DEVICE buffers states_out, energies_out,
+ * logp_out (each may be NULL); log_Z HOST (may be NULL) = its log Z. */
+int spg_batch_result(const spg_batch_t *batch, int32_t i, int32_t *states_out,
+                     double *energies_out, double *logp_out, int32_t *n_out, double *log_Z);
+/* GEMM output tile (32 or 64) of instance i; drops a captured graph. */
+int spg_batch_set_tuning(spg_batch_t *batch, int32_t i, int32_t gemm_tile);
+/* Autotuner: for each (chi, d) bucket, times the bucket's first instance with
+ * every GEMM tile and keeps the fastest for the bucket; reruns the batch with
+ * the choices (synchronous).  tile_out HOST int32 [n] (may be NULL). */
+int spg_batch_autotune(spg_batch_t *batch, void *stream, int32_t *tile_out);
+/* Process default GEMM tile (32 or 64) of calls outside batches on this thread. */
+int spg_set_tuning(int32_t gemm_tile);
+
 /* ---- learned proposal ---------------------------------------------------
  * Not part of the paper's method: a 2-layer FP32 network that ranks the
  * children (b, s) of the beam so the exact contraction runs for few of them.

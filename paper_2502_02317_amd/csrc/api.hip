@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 
 #include "mlp_dev.h"
@@ -84,7 +85,8 @@ static int fail(int code, const std::string &m) {
   }
 
 // ---------------------------------------------------------------------------
-// Boundary MPS: one workspace per call.
+// Boundary MPS workspace: one per call of spg_boundary_mps, one per stream of a
+// batch (instances on one stream run in order and share it).
 struct BmpsWork {
   int R, C, d, chi, lmax;
   DevBuf EL, ER, T1, P, Qr, P2, Q2, G1, G2, B, Y, Q, Z, Qz, Om, Cm, Qc, Rc, V, sig, U, Rm,
@@ -179,19 +181,21 @@ static void row_factors(const spg_peps *pp, int r, int c, bool bottom, RowFactor
   }
 }
 
-static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream_t s) {
+static int bmps_lmax(int chi, int d, const spg_mps_params *prm) {
+  return std::min(chi + std::max(prm->oversample, 0), chi * d);
+}
+
+// Enqueues the contraction on s with workspace w (sized beforehand when the
+// call is captured into a graph: growing it allocates and synchronises).
+static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream_t s,
+                              BmpsWork &w) {
   const spg_peps *pp = env->peps;
   const int R = pp->rows, C = pp->cols, d = pp->d, chi = env->chi;
-  BmpsWork w;
   w.R = R; w.C = C; w.d = d; w.chi = chi;
-  w.lmax = std::min(chi + std::max(prm->oversample, 0), chi * d);
+  w.lmax = bmps_lmax(chi, d, prm);
   w.alloc();
   const size_t site = w.site_sz(), es = w.env_sz();
-  {
-    std::vector<double> I((size_t)w.lmax * w.lmax, 0.0);
-    for (int i = 0; i < w.lmax; ++i) I[(size_t)i * w.lmax + i] = 1.0;
-    SPG_HIP(hipMemcpy(w.ident.p, I.data(), I.size() * sizeof(double), hipMemcpyHostToDevice));
-  }
+  set_identity(w.lmax, w.ident.as<double>(), s);
   double *A = env->A.as<double>();
   double *logs = w.logs.as<double>();
   // log slots: EL[c] at c, ER[c] at C+1+c, centre at 2C+2, lam[r] at 2C+4+r
@@ -313,8 +317,6 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
   }
   SPG_HIP(hipMemcpyAsync(env->lam.as<double>(), logs + sLam, sizeof(double) * R,
                          hipMemcpyDeviceToDevice, s));
-  // keep the workspace alive until the stream has consumed it
-  SPG_HIP(hipStreamSynchronize(s));
 }
 
 // Search copy of the boundary MPS in the env's precision (no-op for FP64).
@@ -467,12 +469,34 @@ void spg_free_peps(spg_peps_t *pp) {
 
 void spg_free_env(spg_env_t *env) {
   if (!env) return;
+  (void)hipDeviceSynchronize();
   for (DevBuf *b : {&env->A, &env->Alp, &env->lam, &env->cfg[0], &env->cfg[1], &env->score[0],
                     &env->score[1], &env->energy[0], &env->energy[1], &env->L[0], &env->L[1],
                     &env->anc[0], &env->anc[1], &env->Rv, &env->cand, &env->sel, &env->keys,
                     &env->ids, &env->ework, &env->perm, &env->nvalid, &env->tmp, &env->cfg32})
     b->release();
   delete env;
+}
+
+// log Z = lam_0 + log sum_X A_0[x_0]..A_{C-1}[x_{C-1}] - beta * shift, from the
+// top row copied to the host (small); the device work must be complete.
+static double host_log_Z(const spg_env *env) {
+  const spg_peps *pp = env->peps;
+  const int R = pp->rows, C = pp->cols, d = pp->d, chi = env->chi;
+  std::vector<double> A0((size_t)C * chi * d * chi), lam(R);
+  SPG_HIP(hipMemcpy(A0.data(), env->A.p, A0.size() * 8, hipMemcpyDeviceToHost));
+  SPG_HIP(hipMemcpy(lam.data(), env->lam.p, R * 8, hipMemcpyDeviceToHost));
+  std::vector<double> v(chi, 0.0), nv(chi);
+  v[0] = 1.0;
+  for (int c = 0; c < C; ++c) {
+    std::fill(nv.begin(), nv.end(), 0.0);
+    const double *T = A0.data() + (size_t)c * chi * d * chi;
+    for (int a = 0; a < chi; ++a)
+      for (int x = 0; x < d; ++x)
+        for (int b = 0; b < chi; ++b) nv[b] += v[a] * T[((size_t)a * d + x) * chi + b];
+    v = nv;
+  }
+  return lam[0] + std::log(v[0]) - pp->beta * pp->shift;
 }
 
 static int check_mps_params(const spg_mps_params *p) {
@@ -504,25 +528,16 @@ int spg_boundary_mps(const spg_peps_t *peps, const spg_mps_params *params, void 
     env->dims.assign((size_t)R * (C + 1), 1);
     env->A.ensure((size_t)R * C * chi * d * chi * sizeof(double));
     env->lam.ensure((size_t)R * sizeof(double));
-    boundary_mps_fp64(env, params, s);
-    make_lp_copy(env, s);
-    if (log_Z_out) {
-      // log Z = lam_0 + log sum_X A_0[x_0]..A_{C-1}[x_{C-1}] - beta * shift (host, small)
-      std::vector<double> A0((size_t)C * chi * d * chi), lam(R);
-      SPG_HIP(hipMemcpyAsync(A0.data(), env->A.p, A0.size() * 8, hipMemcpyDeviceToHost, s));
-      SPG_HIP(hipMemcpyAsync(lam.data(), env->lam.p, R * 8, hipMemcpyDeviceToHost, s));
+    {
+      BmpsWork w;
+      boundary_mps_fp64(env, params, s, w);
+      make_lp_copy(env, s);
+      // keep the workspace alive until the stream has consumed it
       SPG_HIP(hipStreamSynchronize(s));
-      std::vector<double> v(chi, 0.0), nv(chi);
-      v[0] = 1.0;
-      for (int c = 0; c < C; ++c) {
-        std::fill(nv.begin(), nv.end(), 0.0);
-        const double *T = A0.data() + (size_t)c * chi * d * chi;
-        for (int a = 0; a < chi; ++a)
-          for (int x = 0; x < d; ++x)
-            for (int b = 0; b < chi; ++b) nv[b] += v[a] * T[((size_t)a * d + x) * chi + b];
-        v = nv;
-      }
-      const double lz = lam[0] + std::log(v[0]) - peps->beta * peps->shift;
+    }
+    if (log_Z_out) {
+      SPG_HIP(hipStreamSynchronize(s));
+      const double lz = host_log_Z(env);
       *log_Z_out = lz;
       if (!std::isfinite(lz)) {
         *out = env;
@@ -726,7 +741,7 @@ static GuideWork guide_of(spg_env *env) {
 // `td` (exact path only) the training targets of every step are recorded.
 static void run_search(spg_env *env, const spg_search_params *prm, const spg_proposal *prop,
                        TrainData *td, int32_t *states_out, double *energies_out,
-                       double *logp_out, int32_t *n_out, hipStream_t s) {
+                       double *logp_out, int32_t *n_out, hipStream_t s, bool sync_out = true) {
   const spg_peps *pp = env->peps;
   const int R = pp->rows, C = pp->cols, N = R * C, d = pp->d, chi = env->chi;
   const int M = prm->max_states;
@@ -862,6 +877,7 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
     final_sort(t, (int)B, N, env->cfg[cur].as<uint8_t>(), env->score[cur].as<double>(),
                states_out, energies_out, logp_out, env->ework.as<double>(),
                env->perm.as<int32_t>(), env->nvalid.as<int32_t>(), s);
+  if (!sync_out) return;           // enqueued only (batches read env->nvalid later)
   int32_t nv = 0;
   unsigned long long st[3] = {0, 0, 0};
   if (states_out) SPG_HIP(hipMemcpyAsync(&nv, env->nvalid.p, 4, hipMemcpyDeviceToHost, s));
@@ -1064,6 +1080,278 @@ int spg_proposal_train(spg_proposal_t *prop, const spg_env_t *cenv, const spg_tr
     for (int e = 0; e < tp->epochs; ++e) loss_out[e] = h[e] / (float)N;
   return SPG_OK;
   SPG_CATCH
+}
+
+
+// ---- batches ------------------------------------------------------------------
+struct spg_batch {
+  int n = 0;
+  std::vector<spg_batch_item> items;
+  std::vector<spg_env *> envs;
+  std::vector<Tuning> tune;
+  std::vector<std::unique_ptr<BmpsWork>> slots;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> done;
+  hipEvent_t fork = nullptr, ev_in = nullptr, ev_out = nullptr;
+  hipStream_t origin = nullptr;   // capture and replay stream (the caller's may be the null stream)
+  std::vector<std::unique_ptr<DevBuf>> states, energies, logp;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool warm = false;
+  ~spg_batch() {
+    (void)hipDeviceSynchronize();
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto e : done) (void)hipEventDestroy(e);
+    for (auto e : {fork, ev_in, ev_out})
+      if (e) (void)hipEventDestroy(e);
+    if (origin) (void)hipStreamDestroy(origin);
+    for (auto st : streams) (void)hipStreamDestroy(st);
+    for (auto e : envs) spg_free_env(e);
+  }
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+};
+
+static spg_mps_params item_mps(const spg_batch_item &it) {
+  spg_mps_params m{};
+  m.chi = it.chi; m.num_sweeps = it.num_sweeps; m.precision = it.precision;
+  m.oversample = it.oversample; m.power_iters = it.power_iters;
+  return m;
+}
+
+// Instance i's whole path (contraction, search, output) enqueued on stream st.
+static void enqueue_instance(spg_batch *b, int i, hipStream_t st) {
+  const Tuning saved = g_tune;
+  g_tune = b->tune[i];
+  const spg_batch_item &it = b->items[i];
+  spg_env *env = b->envs[i];
+  const spg_mps_params mp = item_mps(it);
+  boundary_mps_fp64(env, &mp, st, *b->slots[i % b->slots.size()]);
+  make_lp_copy(env, st);
+  spg_search_params sp{};
+  sp.max_states = it.max_states;
+  sp.cut_off_prob = it.cut_off_prob;
+  run_search(env, &sp, nullptr, nullptr, b->states[i]->as<int32_t>(),
+             b->energies[i]->as<double>(), b->logp[i]->as<double>(), nullptr, st, false);
+  g_tune = saved;
+}
+
+// Every instance, round-robin over the batch's streams, forked from and
+// joined back into s.
+static void enqueue_batch(spg_batch *b, hipStream_t s) {
+  SPG_HIP(hipEventRecord(b->fork, s));
+  for (auto st : b->streams) SPG_HIP(hipStreamWaitEvent(st, b->fork, 0));
+  const int S = (int)b->streams.size();
+  for (int i = 0; i < b->n; ++i) enqueue_instance(b, i, b->streams[i % S]);
+  for (int k = 0; k < S; ++k) {
+    SPG_HIP(hipEventRecord(b->done[k], b->streams[k]));
+    SPG_HIP(hipStreamWaitEvent(s, b->done[k], 0));
+  }
+}
+
+int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items, int32_t n,
+                     int32_t n_streams, spg_batch_t **out) {
+  SPG_TRY
+  if (!peps || !items || !out) return fail(SPG_ERR_INVALID, "spg_batch_create: null argument");
+  if (n < 1) return fail(SPG_ERR_INVALID, "spg_batch_create: n must be >= 1");
+  if (n_streams < 1 || n_streams > 64)
+    return fail(SPG_ERR_INVALID, "spg_batch_create: n_streams must be in 1..64");
+  for (int i = 0; i < n; ++i) {
+    if (!peps[i]) return fail(SPG_ERR_INVALID, "spg_batch_create: null peps");
+    const spg_mps_params mp = item_mps(items[i]);
+    int rc = check_mps_params(&mp);
+    if (rc) return rc;
+    if (items[i].max_states < 1 || items[i].max_states > 65536)
+      return fail(SPG_ERR_UNSUPPORTED, "spg_batch_create: max_states must be in 1..65536");
+    if (!(items[i].cut_off_prob >= 0.0) || items[i].cut_off_prob >= 1.0)
+      return fail(SPG_ERR_INVALID, "spg_batch_create: cut_off_prob must be in [0, 1)");
+  }
+  spg_batch *b = new spg_batch();
+  try {
+    b->n = n;
+    b->items.assign(items, items + n);
+    b->tune.assign(n, g_tune);
+    const int S = std::min<int>(n_streams, n);
+    for (int k = 0; k < S; ++k) {
+      hipStream_t st;
+      SPG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      b->streams.push_back(st);
+      hipEvent_t e;
+      SPG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b->done.push_back(e);
+      b->slots.emplace_back(new BmpsWork());
+    }
+    SPG_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    SPG_HIP(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    SPG_HIP(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    SPG_HIP(hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking));
+    for (int i = 0; i < n; ++i) {
+      const spg_peps *pp = peps[i];
+      spg_env *env = new spg_env();
+      b->envs.push_back(env);
+      env->peps = pp;
+      env->chi = items[i].chi;
+      env->precision = items[i].precision;
+      const int R = pp->rows, C = pp->cols, d = pp->d, chi = items[i].chi, M = items[i].max_states;
+      env->dims.assign((size_t)R * (C + 1), 1);
+      env->A.ensure((size_t)R * C * chi * d * chi * sizeof(double));
+      env->lam.ensure((size_t)R * sizeof(double));
+      b->states.emplace_back(new DevBuf());
+      b->energies.emplace_back(new DevBuf());
+      b->logp.emplace_back(new DevBuf());
+      b->states[i]->ensure((size_t)M * R * C * 4);
+      b->energies[i]->ensure((size_t)M * 8);
+      b->logp[i]->ensure((size_t)M * 8);
+      ensure_search(env, M);
+    }
+  } catch (...) {
+    delete b;
+    throw;
+  }
+  *out = b;
+  return SPG_OK;
+  SPG_CATCH
+}
+
+void spg_batch_free(spg_batch_t *b) { delete b; }
+
+int spg_batch_run(spg_batch_t *b, int32_t use_graph, void *stream) {
+  SPG_TRY
+  if (!b) return fail(SPG_ERR_INVALID, "spg_batch_run: null batch");
+  hipStream_t s = (hipStream_t)stream;
+  if (!use_graph || !b->warm) {
+    // eager pass: also sizes every workspace so a later capture allocates nothing
+    enqueue_batch(b, s);
+    if (!b->warm) SPG_HIP(hipStreamSynchronize(s));
+    b->warm = true;
+    if (!use_graph) return SPG_OK;
+  }
+  hipStream_t o = b->origin;
+  if (!b->exec) {
+    SPG_HIP(hipStreamSynchronize(o));
+    const bool prof = g_prof;
+    g_prof = false;                    // no timing events inside the graph
+    SPG_HIP(hipStreamBeginCapture(o, hipStreamCaptureModeRelaxed));
+    try {
+      enqueue_batch(b, o);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(o, &g);
+      if (g) (void)hipGraphDestroy(g);
+      g_prof = prof;
+      throw;
+    }
+    g_prof = prof;
+    SPG_HIP(hipStreamEndCapture(o, &b->graph));
+    SPG_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  // the replay runs on the batch's own stream, ordered after and before s
+  SPG_HIP(hipEventRecord(b->ev_in, s));
+  SPG_HIP(hipStreamWaitEvent(o, b->ev_in, 0));
+  SPG_HIP(hipGraphLaunch(b->exec, o));
+  SPG_HIP(hipEventRecord(b->ev_out, o));
+  SPG_HIP(hipStreamWaitEvent(s, b->ev_out, 0));
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_batch_result(const spg_batch_t *b, int32_t i, int32_t *states_out, double *energies_out,
+                     double *logp_out, int32_t *n_out, double *log_Z) {
+  SPG_TRY
+  if (!b || !n_out) return fail(SPG_ERR_INVALID, "spg_batch_result: null argument");
+  if (i < 0 || i >= b->n) return fail(SPG_ERR_INVALID, "spg_batch_result: index out of range");
+  SPG_HIP(hipDeviceSynchronize());
+  spg_env *env = b->envs[i];
+  int32_t nv = 0;
+  SPG_HIP(hipMemcpy(&nv, env->nvalid.p, 4, hipMemcpyDeviceToHost));
+  *n_out = nv;
+  const size_t N = (size_t)env->peps->rows * env->peps->cols;
+  if (nv > 0) {
+    if (states_out)
+      SPG_HIP(hipMemcpy(states_out, b->states[i]->p, (size_t)nv * N * 4, hipMemcpyDeviceToDevice));
+    if (energies_out)
+      SPG_HIP(hipMemcpy(energies_out, b->energies[i]->p, (size_t)nv * 8, hipMemcpyDeviceToDevice));
+    if (logp_out)
+      SPG_HIP(hipMemcpy(logp_out, b->logp[i]->p, (size_t)nv * 8, hipMemcpyDeviceToDevice));
+  }
+  if (log_Z) *log_Z = host_log_Z(env);
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_batch_set_tuning(spg_batch_t *b, int32_t i, int32_t gemm_tile) {
+  if (!b || i < 0 || i >= b->n) return fail(SPG_ERR_INVALID, "spg_batch_set_tuning: bad batch or index");
+  if (gemm_tile != 32 && gemm_tile != 64)
+    return fail(SPG_ERR_INVALID, "spg_batch_set_tuning: gemm_tile must be 32 or 64");
+  b->tune[i].gemm_tile = gemm_tile;
+  b->drop_graph();
+  return SPG_OK;
+}
+
+int spg_batch_autotune(spg_batch_t *b, void *stream, int32_t *tile_out) {
+  SPG_TRY
+  if (!b) return fail(SPG_ERR_INVALID, "spg_batch_autotune: null batch");
+  hipStream_t s = (hipStream_t)stream;
+  if (!b->warm) {
+    enqueue_batch(b, s);
+    SPG_HIP(hipStreamSynchronize(s));
+    b->warm = true;
+  }
+  // one bucket per (chi, d): time its first instance with every tile, twice
+  // each (the first run only warms), keep the fastest for the whole bucket
+  std::vector<int> done(b->n, 0);
+  hipEvent_t e0, e1;
+  SPG_HIP(hipEventCreate(&e0));
+  SPG_HIP(hipEventCreate(&e1));
+  const int cand[2] = {64, 32};
+  for (int i = 0; i < b->n; ++i) {
+    if (done[i]) continue;
+    const int chi = b->items[i].chi, d = b->envs[i]->peps->d;
+    float best = 1e30f;
+    int best_tile = 64;
+    for (int t : cand) {
+      b->tune[i].gemm_tile = t;
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2; ++rep) {
+        SPG_HIP(hipEventRecord(e0, s));
+        enqueue_instance(b, i, s);
+        SPG_HIP(hipEventRecord(e1, s));
+        SPG_HIP(hipEventSynchronize(e1));
+        SPG_HIP(hipEventElapsedTime(&ms, e0, e1));
+      }
+      if (ms < best) {
+        best = ms;
+        best_tile = t;
+      }
+    }
+    for (int j = i; j < b->n; ++j)
+      if (!done[j] && b->items[j].chi == chi && b->envs[j]->peps->d == d) {
+        b->tune[j].gemm_tile = best_tile;
+        done[j] = 1;
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->drop_graph();
+  // refresh every instance's results with its chosen tiles
+  enqueue_batch(b, s);
+  SPG_HIP(hipStreamSynchronize(s));
+  if (tile_out)
+    for (int i = 0; i < b->n; ++i) tile_out[i] = b->tune[i].gemm_tile;
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_set_tuning(int32_t gemm_tile) {
+  if (gemm_tile != 32 && gemm_tile != 64)
+    return fail(SPG_ERR_INVALID, "spg_set_tuning: gemm_tile must be 32 or 64");
+  g_tune.gemm_tile = gemm_tile;
+  return SPG_OK;
 }
 
 }  // extern "C"

@@ -190,6 +190,12 @@ __global__ void k_set_e0(int n, int chi, double *p, long stride) {
   p[j * stride + i] = (i == 0) ? 1.0 : 0.0;
 }
 
+__global__ void k_set_identity(int n, double *p) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  p[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+
 __global__ void k_add_logs(double *logs, int out, int a, int b, int c) {
   logs[out] = (a >= 0 ? logs[a] : 0.0) + (b >= 0 ? logs[b] : 0.0) + (c >= 0 ? logs[c] : 0.0);
 }
@@ -352,6 +358,13 @@ void set_e0(int n, int chi, double *p, long stride, hipStream_t s) {
   const long tot = (long)n * chi;
   if (tot <= 0) return;
   hipLaunchKernelGGL(k_set_e0, dim3(nblk(tot, 256)), dim3(256), 0, s, n, chi, p, stride);
+  SPG_CHECK_LAUNCH();
+}
+
+void set_identity(int n, double *p, hipStream_t s) {
+  const long tot = (long)n * n;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_set_identity, dim3(nblk(tot, 256)), dim3(256), 0, s, n, p);
   SPG_CHECK_LAUNCH();
 }
 

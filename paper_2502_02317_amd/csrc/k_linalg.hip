@@ -25,56 +25,59 @@ __device__ double block_sum(double v, double *red) {
 }
 
 // ---------------------------------------------------------------- GEMM
-// 64x64 output tile per 256-thread workgroup, K staged through LDS in steps of
-// 16; each thread owns a 4x4 sub-tile (rows ty+16i, cols tx+16j).
+// TILE x TILE output tile per 256-thread workgroup (TILE = 64 or 32), K staged
+// through LDS in steps of 16; each thread owns a (TILE/16)^2 sub-tile (rows
+// ty+16i, cols tx+16j).  The tile is picked per launch by the tuning.
+template <int TILE>
 __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
+  constexpr int P = TILE / 16, NQ = 16 * TILE / 256;
   const int b1 = blockIdx.z / g.nb2, b2 = blockIdx.z % g.nb2;
   const double *A = g.A + b1 * g.a_b1 + b2 * g.a_b2;
   const double *B = g.B + b1 * g.b_b1 + b2 * g.b_b2;
   double *C = g.C + b1 * g.c_b1 + b2 * g.c_b2;
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
+  __shared__ double As[16][TILE + 1];
+  __shared__ double Bs[16][TILE + 1];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int i0 = blockIdx.y * TILE, j0 = blockIdx.x * TILE;
   // split-K chunks: chunk b1 covers global k in [b1*K, min((b1+1)*K, kmax))
   const int Kend = (g.kmax > 0) ? min(g.K, g.kmax - b1 * g.K) : g.K;
-  double acc[4][4];
+  double acc[P][P];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < P; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int j = 0; j < P; ++j) acc[i][j] = 0.0;
   for (int k0 = 0; k0 < Kend; k0 += 16) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int e = tid + 256 * q;
       const int r = e >> 4, kk = e & 15;
       const int gi = i0 + r, gk = k0 + kk;
       As[kk][r] = (gi < g.M && gk < Kend) ? A[gi * g.a_i + gk * g.a_k] : 0.0;
-      const int kb = e >> 6, cb = e & 63;
+      const int kb = e / TILE, cb = e % TILE;
       const int gkb = k0 + kb, gj = j0 + cb;
       Bs[kb][cb] = (gkb < Kend && gj < g.N) ? B[gkb * g.b_k + gj * g.b_j] : 0.0;
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
+      double a[P], b[P];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int i = 0; i < P; ++i) a[i] = As[kk][ty + 16 * i];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+      for (int j = 0; j < P; ++j) b[j] = Bs[kk][tx + 16 * j];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < P; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < P; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < P; ++i) {
     const int gi = i0 + ty + 16 * i;
     if (gi >= g.M) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < P; ++j) {
       const int gj = j0 + tx + 16 * j;
       if (gj >= g.N) continue;
       double *cp = C + gi * g.c_i + gj * g.c_j;
@@ -521,11 +524,12 @@ __global__ void k_fill_zero(double *p, size_t n) {
 
 }  // namespace
 
-void gemm_f64(const GemmDesc &g, hipStream_t s) {
-  KTimer kt_("gemm_f64", s, 2.0 * g.M * g.N * g.K * g.nb1 * g.nb2);
-  if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
-  const long tiles = (long)((g.N + 63) / 64) * ((g.M + 63) / 64) * g.nb1 * g.nb2;
-  if (g.ws && tiles < 64 && g.nb1 * g.nb2 == 1 && g.K >= 256) {
+thread_local Tuning g_tune;
+
+template <int TILE>
+static void gemm_launch(const GemmDesc &g, hipStream_t s) {
+  const long tiles = (long)((g.N + TILE - 1) / TILE) * ((g.M + TILE - 1) / TILE) * g.nb1 * g.nb2;
+  if (g_tune.splitk && g.ws && tiles < 64 && g.nb1 * g.nb2 == 1 && g.K >= 256) {
     // few output tiles and a long K: split K into chunks of >= 64 written to
     // a workspace, then sum them in a fixed order
     int S = (int)std::min<long>(std::min<long>(g.K / 64, 128 / tiles), 16);
@@ -539,8 +543,8 @@ void gemm_f64(const GemmDesc &g, hipStream_t s) {
       h.a_b1 = kc * g.a_k; h.b_b1 = kc * g.b_k;
       h.C = g.ws; h.c_i = g.N; h.c_j = 1; h.c_b1 = (long)g.M * g.N;
       h.alpha = 1.0; h.beta = 0.0; h.kmax = g.K;
-      dim3 grid((h.N + 63) / 64, (h.M + 63) / 64, S);
-      hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, h);
+      dim3 grid((h.N + TILE - 1) / TILE, (h.M + TILE - 1) / TILE, S);
+      hipLaunchKernelGGL(k_gemm<TILE>, grid, dim3(256), 0, s, h);
       SPG_CHECK_LAUNCH();
       const long mn = (long)g.M * g.N;
       hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g.M,
@@ -549,9 +553,18 @@ void gemm_f64(const GemmDesc &g, hipStream_t s) {
       return;
     }
   }
-  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.nb1 * g.nb2);
-  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+  dim3 grid((g.N + TILE - 1) / TILE, (g.M + TILE - 1) / TILE, g.nb1 * g.nb2);
+  hipLaunchKernelGGL(k_gemm<TILE>, grid, dim3(256), 0, s, g);
   SPG_CHECK_LAUNCH();
+}
+
+void gemm_f64(const GemmDesc &g, hipStream_t s) {
+  KTimer kt_("gemm_f64", s, 2.0 * g.M * g.N * g.K * g.nb1 * g.nb2);
+  if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
+  if (g_tune.gemm_tile == 32)
+    gemm_launch<32>(g, s);
+  else
+    gemm_launch<64>(g, s);
 }
 
 // Householder QR flops: 2mn^2 - 2n^3/3 for R, the same again to form Q.

@@ -66,6 +66,14 @@ struct GemmDesc {
 };
 void gemm_f64(const GemmDesc &g, hipStream_t s);
 
+// Launch-shape choices read when work is enqueued (set per instance by the
+// batch driver and its autotuner; process default 64 / split-K on).
+struct Tuning {
+  int gemm_tile = 64;   // GEMM output tile: 64 or 32
+  int splitk = 1;       // deterministic split-K for skinny long-K products
+};
+extern thread_local Tuning g_tune;
+
 // Householder QR of an m x n matrix (m >= n, n <= kMaxSketch), element (i,j) at
 // X[i*xr + j*xc].  Writes Q (m x n, orthonormal columns) to Q[i*qr + j*qc]
 // unless Q == nullptr and, if R != nullptr, the n x n upper-triangular factor
@@ -127,6 +135,8 @@ void pack_right(int d, int chi, int nk, int pr, const double *src, double *dst, 
 void build_weights(int ntab, int tsize, double beta, const double *E, double *W, double *mins,
                    hipStream_t s);
 void set_e0(int n, int chi, double *p, long stride, hipStream_t s);
+// p[n][n] = identity (row-major, leading dimension n)
+void set_identity(int n, double *p, hipStream_t s);
 
 // ---- search kernels (k_search.hip) ----------------------------------------
 struct SearchTabs {         // device tables of the instance

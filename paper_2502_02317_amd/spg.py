@@ -52,12 +52,20 @@ class TrainParams(C.Structure):
 N_FEATURES = 6
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("chi", C.c_int32), ("num_sweeps", C.c_int32), ("precision", C.c_int32),
+                ("oversample", C.c_int32), ("power_iters", C.c_int32),
+                ("max_states", C.c_int32), ("cut_off_prob", C.c_double)]
+
+
 EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_branch_and_bound",
            "spg_free_peps", "spg_free_env", "spg_last_error", "spg_env_info", "spg_env_export",
            "spg_env_import", "spg_profile_enable", "spg_profile_reset", "spg_profile_query",
            "spg_proposal_create", "spg_proposal_free", "spg_proposal_params",
            "spg_proposal_train", "spg_proposal_features", "spg_proposal_forward",
-           "spg_proposal_loss_grad", "spg_proposal_adam", "spg_search_stats"]
+           "spg_proposal_loss_grad", "spg_proposal_adam", "spg_search_stats",
+           "spg_batch_create", "spg_batch_free", "spg_batch_run", "spg_batch_result",
+           "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning"]
 KERNEL_CLASSES = ["gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box", "right_env",
                   "marginals", "select_topm", "beam_update", "final_sort", "propose",
                   "guided_eval", "mlp_grad"]
@@ -100,11 +108,22 @@ def load() -> C.CDLL:
     lib.spg_proposal_loss_grad.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
     lib.spg_proposal_adam.argtypes = [vp, vp, C.c_float, vp]
     lib.spg_search_stats.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.spg_batch_create.argtypes = [C.POINTER(vp), C.POINTER(BatchItem), i32, i32,
+                                     C.POINTER(vp)]
+    lib.spg_batch_free.argtypes = [vp]
+    lib.spg_batch_free.restype = None
+    lib.spg_batch_run.argtypes = [vp, i32, vp]
+    lib.spg_batch_result.argtypes = [vp, i32, vp, vp, vp, i32p, f64p]
+    lib.spg_batch_set_tuning.argtypes = [vp, i32, i32]
+    lib.spg_batch_autotune.argtypes = [vp, vp, vp]
+    lib.spg_set_tuning.argtypes = [i32]
     for name in ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_branch_and_bound",
                  "spg_env_info", "spg_env_export", "spg_env_import", "spg_profile_query",
                  "spg_proposal_create", "spg_proposal_params", "spg_proposal_train",
                  "spg_proposal_features", "spg_proposal_forward", "spg_proposal_loss_grad",
-                 "spg_proposal_adam", "spg_search_stats"]:
+                 "spg_proposal_adam", "spg_search_stats", "spg_batch_create", "spg_batch_run",
+                 "spg_batch_result", "spg_batch_set_tuning", "spg_batch_autotune",
+                 "spg_set_tuning"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -353,3 +372,68 @@ def search_stats(env: Env):
     out = (C.c_int64 * 3)()
     _check(load().spg_search_stats(env.handle, out))
     return int(out[0]), int(out[1]), int(out[2])
+
+
+# ---- batches --------------------------------------------------------------------
+
+def set_tuning(gemm_tile: int) -> None:
+    """Default GEMM tile (32 or 64) of calls outside batches on this thread."""
+    _check(load().spg_set_tuning(int(gemm_tile)))
+
+
+class Batch:
+    """Owner of an spg_batch_t: many instances run as one unit (optionally one
+    captured graph).  Keeps its Peps objects alive."""
+
+    def __init__(self, peps_list, chi, max_states, num_sweeps=1, precision="fp64",
+                 oversample=16, power_iters=1, cut_off_prob=0.0, n_streams=8):
+        n = len(peps_list)
+        chis = list(chi) if hasattr(chi, "__len__") else [chi] * n
+        Ms = list(max_states) if hasattr(max_states, "__len__") else [max_states] * n
+        precs = [precision] * n if isinstance(precision, str) else list(precision)
+        items = (BatchItem * n)(*[BatchItem(int(chis[i]), int(num_sweeps), PRECISION[precs[i]],
+                                            int(oversample), int(power_iters), int(Ms[i]),
+                                            float(cut_off_prob)) for i in range(n)])
+        handles = (C.c_void_p * n)(*[p.handle.value for p in peps_list])
+        h = C.c_void_p()
+        _check(load().spg_batch_create(handles, items, n, int(n_streams), C.byref(h)))
+        self.handle = h
+        self.peps = list(peps_list)
+        self.n = n
+        self.max_states = Ms
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.spg_batch_free(self.handle)
+            self.handle = None
+
+    def run(self, use_graph: bool = True, stream=None) -> None:
+        _check(load().spg_batch_run(self.handle, 1 if use_graph else 0, _stream(stream)))
+
+    def result(self, i: int):
+        """(states int32 [n][N], energies, logp, log Z) of instance i as host arrays."""
+        import torch
+        if not 0 <= i < self.n:
+            n = C.c_int32(0)
+            _check(load().spg_batch_result(self.handle, int(i), None, None, None, C.byref(n),
+                                           None))
+        inst = self.peps[i].inst
+        N, M = inst.rows * inst.cols, self.max_states[i]
+        st = torch.zeros((M, N), dtype=torch.int32, device="cuda")
+        en = torch.zeros(M, dtype=torch.float64, device="cuda")
+        lp = torch.zeros(M, dtype=torch.float64, device="cuda")
+        n = C.c_int32(0)
+        lz = C.c_double(0.0)
+        _check(load().spg_batch_result(self.handle, int(i), _ptr(st), _ptr(en), _ptr(lp),
+                                       C.byref(n), C.byref(lz)))
+        k = n.value
+        return st[:k].cpu().numpy(), en[:k].cpu().numpy(), lp[:k].cpu().numpy(), lz.value
+
+    def set_tuning(self, i: int, gemm_tile: int) -> None:
+        _check(load().spg_batch_set_tuning(self.handle, int(i), int(gemm_tile)))
+
+    def autotune(self, stream=None) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.int32)
+        _check(load().spg_batch_autotune(self.handle, _stream(stream), out.ctypes.data))
+        return out
+
