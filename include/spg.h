@@ -167,11 +167,22 @@ typedef struct {
   double cut_off_prob;
 } spg_batch_item;
 
-/* peps HOST array [n] of PEPS handles (kept alive by the caller while the
- * batch exists), items HOST [n].  Allocates every per-instance buffer.
- * Errors: SPG_ERR_INVALID, SPG_ERR_UNSUPPORTED, SPG_ERR_OOM, SPG_ERR_HIP. */
+/* flags: SPG_BATCH_CLASSES groups FP64 instances of equal shape (rows,
+ * cols, d, lattice kind, chi, beam, sweeps, truncation parameters, cut-off)
+ * into classes whose members share every launch: each kernel of the path runs
+ * once per class with one workgroup set per member.  Other instances run one
+ * by one on the streams. */
+#define SPG_BATCH_CLASSES 1
+
+/* peps HOST array [n] of PEPS handles (the batch copies their tables; they
+ * must stay alive while the batch exists), items HOST [n].  Allocates every
+ * per-instance buffer.  Errors: SPG_ERR_INVALID, SPG_ERR_UNSUPPORTED,
+ * SPG_ERR_OOM, SPG_ERR_HIP. */
 int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items, int32_t n,
-                     int32_t n_streams, spg_batch_t **out);
+                     int32_t n_streams, int32_t flags, spg_batch_t **out);
+/* Number of units (classes and single instances) and, in unit_of HOST int32
+ * [n] (may be NULL), the unit of each instance. */
+int spg_batch_info(const spg_batch_t *batch, int32_t *n_units, int32_t *unit_of);
 void spg_batch_free(spg_batch_t *batch);
 /* Runs every instance (asynchronous on `stream`).  The first run is eager
  * and synchronises once (it sizes the workspaces); with use_graph != 0 the
@@ -184,11 +195,11 @@ int spg_batch_run(spg_batch_t *batch, int32_t use_graph, void *stream);
  * logp_out (each may be NULL); log_Z HOST (may be NULL) = its log Z. */
 int spg_batch_result(const spg_batch_t *batch, int32_t i, int32_t *states_out,
                      double *energies_out, double *logp_out, int32_t *n_out, double *log_Z);
-/* GEMM output tile (32 or 64) of instance i; drops a captured graph. */
+/* GEMM output tile (32 or 64) of instance i's unit; drops a captured graph. */
 int spg_batch_set_tuning(spg_batch_t *batch, int32_t i, int32_t gemm_tile);
-/* Autotuner: for each (chi, d) bucket, times the bucket's first instance with
- * every GEMM tile and keeps the fastest for the bucket; reruns the batch with
- * the choices (synchronous).  tile_out HOST int32 [n] (may be NULL). */
+/* Autotuner: times every unit (class or single instance) with each GEMM tile
+ * and keeps the fastest; reruns the batch with the choices (synchronous).
+ * tile_out HOST int32 [n] (may be NULL): the tile of each instance. */
 int spg_batch_autotune(spg_batch_t *batch, void *stream, int32_t *tile_out);
 /* Process default GEMM tile (32 or 64) of calls outside batches on this thread. */
 int spg_set_tuning(int32_t gemm_tile);

@@ -39,7 +39,7 @@ static hipEvent_t pool_event() {
 KTimer::KTimer(const char *name, hipStream_t st, double work) {
   if (!g_prof) return;
   s = st;
-  TimerRec r{name, pool_event(), pool_event(), work};
+  TimerRec r{name, pool_event(), pool_event(), work * g_bc.n};
   SPG_HIP(hipEventRecord(r.a, s));
   g_recs.push_back(r);
   slot = (int)g_recs.size() - 1;
@@ -49,8 +49,46 @@ KTimer::~KTimer() {
   if (slot >= 0) (void)hipEventRecord(g_recs[slot].b, s);
 }
 
+thread_local BatchCtx g_bc;
+
+void bc_check(const void *p, const char *what) {
+  if (g_bc.n <= 1 || p == nullptr) return;
+  const char *c = (const char *)p;
+  if (c < g_bc.lo || c >= g_bc.hi) {
+    set_error(std::string("class-batched launch with a pointer outside the instance slice: ") +
+              what);
+    throw Fail{SPG_ERR_INVALID};
+  }
+}
+
+void copy_d2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  if (g_bc.n <= 1) {
+    SPG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  SPG_BC(dst);
+  SPG_BC(src);
+  SPG_BC((const char *)dst + bytes - 1);
+  SPG_BC((const char *)src + bytes - 1);
+  // one row per instance, rows ist bytes apart
+  SPG_HIP(hipMemcpy2DAsync(dst, (size_t)g_bc.ist, src, (size_t)g_bc.ist, bytes, (size_t)g_bc.n,
+                           hipMemcpyDeviceToDevice, s));
+}
+
+void bc_single(const char *what) {
+  if (g_bc.n > 1) {
+    set_error(std::string(what) + " has no class-batched form");
+    throw Fail{SPG_ERR_UNSUPPORTED};
+  }
+}
+
 void DevBuf::ensure(size_t n) {
   if (n <= bytes) return;
+  if (!owned) {
+    set_error("a buffer view cannot grow");
+    throw Fail{SPG_ERR_INVALID};
+  }
   release();
   if (hipMalloc(&p, n) != hipSuccess) {
     p = nullptr;
@@ -65,9 +103,10 @@ void DevBuf::ensure(size_t n) {
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p && owned) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
+  owned = true;
 }
 
 static int fail(int code, const std::string &m) {
@@ -95,29 +134,31 @@ struct BmpsWork {
   size_t site_sz() const { return (size_t)chi * d * chi; }
   double *ELc(int c) { return EL.as<double>() + (size_t)c * env_sz(); }
   double *ERc(int c) { return ER.as<double>() + (size_t)c * env_sz(); }
-  void alloc() {
+  // every buffer with its size in bytes for the current shape
+  template <class F>
+  void each(F &&f) {
     const size_t es = env_sz() * sizeof(double);
-    EL.ensure(es * (C + 1));
-    ER.ensure(es * (C + 1));
-    T1.ensure(2 * es);
-    P.ensure(es); Qr.ensure(es); P2.ensure(es); Q2.ensure(es); G1.ensure(es); G2.ensure(es);
+    f(EL, es * (C + 1));
+    f(ER, es * (C + 1));
+    f(T1, 2 * es);
+    for (DevBuf *b : {&P, &Qr, &P2, &Q2, &G1, &G2}) f(*b, es);
     const size_t mn = (size_t)chi * d;                  // max rows / cols of a two-site block
-    B.ensure(mn * mn * sizeof(double));
+    f(B, mn * mn * sizeof(double));
     const size_t ml = mn * lmax * sizeof(double);
-    Y.ensure(ml); Q.ensure(ml); Z.ensure(ml); Qz.ensure(ml); Om.ensure(ml); Qc.ensure(ml);
-    Cm.ensure(ml);
-    Rc.ensure((size_t)lmax * lmax * sizeof(double));
-    V.ensure((size_t)lmax * lmax * sizeof(double));
-    sig.ensure((size_t)lmax * sizeof(double));
-    U.ensure(ml);
-    Rm.ensure(ml);
-    qrwork.ensure(qr_work_doubles((int)mn, lmax) * sizeof(double));
-    nscr.ensure(kNormScratch * sizeof(double));
-    ident.ensure((size_t)lmax * lmax * sizeof(double));
-    skws.ensure(16 * mn * lmax * sizeof(double));
-    tmp.ensure(site_sz() * sizeof(double));
-    logs.ensure((size_t)(2 * C + 8 + R) * sizeof(double));
-    psi0.ensure(site_sz() * C * sizeof(double));
+    for (DevBuf *b : {&Y, &Q, &Z, &Qz, &Om, &Qc, &Cm, &U, &Rm}) f(*b, ml);
+    f(Rc, (size_t)lmax * lmax * sizeof(double));
+    f(V, (size_t)lmax * lmax * sizeof(double));
+    f(sig, (size_t)lmax * sizeof(double));
+    f(qrwork, qr_work_doubles((int)mn, lmax) * sizeof(double));
+    f(nscr, kNormScratch * sizeof(double));
+    f(ident, (size_t)lmax * lmax * sizeof(double));
+    f(skws, 16 * mn * lmax * sizeof(double));
+    f(tmp, site_sz() * sizeof(double));
+    f(logs, (size_t)(2 * C + 8 + R) * sizeof(double));
+    f(psi0, site_sz() * C * sizeof(double));
+  }
+  void alloc() {
+    each([](DevBuf &b, size_t n) { b.ensure(n); });
   }
 };
 
@@ -315,8 +356,7 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
     add_logs(logs, sLam + r, bottom ? -1 : sLam + r + 1, (C > 2) ? sER + 2 : -1, sCen, s);
     for (int c = 0; c <= C; ++c) env->dims[r * (C + 1) + c] = fdims[c];
   }
-  SPG_HIP(hipMemcpyAsync(env->lam.as<double>(), logs + sLam, sizeof(double) * R,
-                         hipMemcpyDeviceToDevice, s));
+  copy_d2d(env->lam.as<double>(), logs + sLam, sizeof(double) * R, s);
 }
 
 // Search copy of the boundary MPS in the env's precision (no-op for FP64).
@@ -480,12 +520,15 @@ void spg_free_env(spg_env_t *env) {
 
 // log Z = lam_0 + log sum_X A_0[x_0]..A_{C-1}[x_{C-1}] - beta * shift, from the
 // top row copied to the host (small); the device work must be complete.
-static double host_log_Z(const spg_env *env) {
+// `off` (bytes) selects an instance of a class-batched env; beta and shift are
+// that instance's.
+static double host_log_Z(const spg_env *env, size_t off, double beta, double shift) {
   const spg_peps *pp = env->peps;
   const int R = pp->rows, C = pp->cols, d = pp->d, chi = env->chi;
   std::vector<double> A0((size_t)C * chi * d * chi), lam(R);
-  SPG_HIP(hipMemcpy(A0.data(), env->A.p, A0.size() * 8, hipMemcpyDeviceToHost));
-  SPG_HIP(hipMemcpy(lam.data(), env->lam.p, R * 8, hipMemcpyDeviceToHost));
+  SPG_HIP(hipMemcpy(A0.data(), (const char *)env->A.p + off, A0.size() * 8,
+                    hipMemcpyDeviceToHost));
+  SPG_HIP(hipMemcpy(lam.data(), (const char *)env->lam.p + off, R * 8, hipMemcpyDeviceToHost));
   std::vector<double> v(chi, 0.0), nv(chi);
   v[0] = 1.0;
   for (int c = 0; c < C; ++c) {
@@ -496,7 +539,11 @@ static double host_log_Z(const spg_env *env) {
         for (int b = 0; b < chi; ++b) nv[b] += v[a] * T[((size_t)a * d + x) * chi + b];
     v = nv;
   }
-  return lam[0] + std::log(v[0]) - pp->beta * pp->shift;
+  return lam[0] + std::log(v[0]) - beta * shift;
+}
+
+static double host_log_Z(const spg_env *env) {
+  return host_log_Z(env, 0, env->peps->beta, env->peps->shift);
 }
 
 static int check_mps_params(const spg_mps_params *p) {
@@ -614,25 +661,31 @@ int spg_env_import(const spg_peps_t *peps, int32_t chi, const int32_t *bond_dims
   SPG_CATCH
 }
 
-static void ensure_search(spg_env *env, int M) {
+// Search buffers of an env with beam M, with their sizes in bytes.
+extern "C++" template <class F>
+static void each_search_buffer(spg_env *env, int M, F &&f) {
   const spg_peps *pp = env->peps;
   const int N = pp->rows * pp->cols, d = pp->d, chi = env->chi, C = pp->cols;
   const int p2 = pow2_at_least(std::max(M, 1));
   for (int i = 0; i < 2; ++i) {
-    env->cfg[i].ensure((size_t)M * N);
-    env->score[i].ensure((size_t)M * 8);
-    env->energy[i].ensure((size_t)M * 8);
-    env->L[i].ensure((size_t)M * chi * 8);
-    env->anc[i].ensure((size_t)M * 4);
+    f(env->cfg[i], (size_t)M * N);
+    f(env->score[i], (size_t)M * 8);
+    f(env->energy[i], (size_t)M * 8);
+    f(env->L[i], (size_t)M * chi * 8);
+    f(env->anc[i], (size_t)M * 4);
   }
-  env->Rv.ensure((size_t)M * (C + 1) * chi * 8);
-  env->cand.ensure((size_t)M * d * 8);
-  env->sel.ensure((size_t)M * 4);
-  env->keys.ensure((size_t)p2 * 8);
-  env->ids.ensure((size_t)p2 * 4);
-  env->ework.ensure((size_t)(M + p2) * 8);
-  env->perm.ensure((size_t)p2 * 4);
-  env->nvalid.ensure(8);
+  f(env->Rv, (size_t)M * (C + 1) * chi * 8);
+  f(env->cand, (size_t)M * d * 8);
+  f(env->sel, (size_t)M * 4);
+  f(env->keys, (size_t)p2 * 8);
+  f(env->ids, (size_t)p2 * 4);
+  f(env->ework, (size_t)(M + p2) * 8);
+  f(env->perm, (size_t)p2 * 4);
+  f(env->nvalid, 8);
+}
+
+static void ensure_search(spg_env *env, int M) {
+  each_search_buffer(env, M, [](DevBuf &b, size_t n) { b.ensure(n); });
 }
 
 int spg_marginals(const spg_env_t *cenv, int32_t site, int32_t n_beam, const int32_t *beam_cfg,
@@ -1084,11 +1137,30 @@ int spg_proposal_train(spg_proposal_t *prop, const spg_env_t *cenv, const spg_tr
 
 
 // ---- batches ------------------------------------------------------------------
+// A shape class: instances with equal lattice, d, kings, chi, beam, sweeps and
+// truncation parameters and an FP64 search.  All their device data sit in
+// equal slices of one allocation; the class runs its whole path once with
+// every launch covering all members (class-batched launches).
+struct BatchClass {
+  std::vector<int> members;
+  DevBuf arena;
+  size_t slice = 0;
+  spg_peps peps;                  // tables: views into slice 0
+  spg_env env;                    // boundary MPS and search buffers: views into slice 0
+  BmpsWork w;                     // contraction workspace: views into slice 0
+  DevBuf states, energies, logp;  // outputs: views into slice 0
+};
+
 struct spg_batch {
   int n = 0;
   std::vector<spg_batch_item> items;
-  std::vector<spg_env *> envs;
-  std::vector<Tuning> tune;
+  std::vector<const spg_peps *> src;
+  // unit u: a class (cls[u] >= 0) or one instance on the stream path
+  std::vector<int> unit_cls, unit_inst;
+  std::vector<Tuning> unit_tune;
+  std::vector<int> inst_unit, inst_member;
+  std::vector<std::unique_ptr<BatchClass>> classes;
+  std::vector<spg_env *> envs;    // stream-path instances (nullptr for class members)
   std::vector<std::unique_ptr<BmpsWork>> slots;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> done;
@@ -1100,8 +1172,7 @@ struct spg_batch {
   bool warm = false;
   ~spg_batch() {
     (void)hipDeviceSynchronize();
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    drop_graph();
     for (auto e : done) (void)hipEventDestroy(e);
     for (auto e : {fork, ev_in, ev_out})
       if (e) (void)hipEventDestroy(e);
@@ -1124,30 +1195,120 @@ static spg_mps_params item_mps(const spg_batch_item &it) {
   return m;
 }
 
-// Instance i's whole path (contraction, search, output) enqueued on stream st.
-static void enqueue_instance(spg_batch *b, int i, hipStream_t st) {
-  const Tuning saved = g_tune;
-  g_tune = b->tune[i];
-  const spg_batch_item &it = b->items[i];
-  spg_env *env = b->envs[i];
-  const spg_mps_params mp = item_mps(it);
-  boundary_mps_fp64(env, &mp, st, *b->slots[i % b->slots.size()]);
-  make_lp_copy(env, st);
-  spg_search_params sp{};
-  sp.max_states = it.max_states;
-  sp.cut_off_prob = it.cut_off_prob;
-  run_search(env, &sp, nullptr, nullptr, b->states[i]->as<int32_t>(),
-             b->energies[i]->as<double>(), b->logp[i]->as<double>(), nullptr, st, false);
-  g_tune = saved;
+static bool same_class(const spg_batch_item &a, const spg_peps *pa, const spg_batch_item &b,
+                       const spg_peps *pb) {
+  return a.precision == SPG_FP64 && b.precision == SPG_FP64 && a.chi == b.chi &&
+         a.num_sweeps == b.num_sweeps && a.oversample == b.oversample &&
+         a.power_iters == b.power_iters && a.max_states == b.max_states &&
+         a.cut_off_prob == b.cut_off_prob && pa->rows == pb->rows && pa->cols == pb->cols &&
+         pa->d == pb->d && pa->kings == pb->kings;
 }
 
-// Every instance, round-robin over the batch's streams, forked from and
-// joined back into s.
+// Lay out one slice: every buffer of the class's peps, env, workspace and
+// outputs, 256-byte aligned; allocate n slices and point the views at slice 0.
+static void build_class(BatchClass &k, const std::vector<const spg_peps *> &src,
+                        const spg_batch_item &it) {
+  const spg_peps *p0 = src[k.members[0]];
+  const int R = p0->rows, C = p0->cols, d = p0->d, chi = it.chi, M = it.max_states;
+  k.peps.rows = R; k.peps.cols = C; k.peps.d = d; k.peps.kings = p0->kings;
+  k.peps.beta = p0->beta; k.peps.shift = p0->shift; k.peps.device = p0->device;
+  k.env.peps = &k.peps;
+  k.env.chi = chi;
+  k.env.precision = SPG_FP64;
+  k.env.dims.assign((size_t)R * (C + 1), 1);
+  const spg_mps_params mp = item_mps(it);
+  k.w.R = R; k.w.C = C; k.w.d = d; k.w.chi = chi;
+  k.w.lmax = bmps_lmax(chi, d, &mp);
+  std::vector<std::pair<DevBuf *, size_t>> list;
+  auto add = [&](DevBuf &b, size_t n) { list.emplace_back(&b, std::max<size_t>(n, 8)); };
+  spg_peps *pk = &k.peps;
+  const DevBuf *srcb[] = {&p0->E_loc, &p0->E_h, &p0->E_v, &p0->E_d, &p0->E_a, &p0->W_loc,
+                          &p0->W_h, &p0->W_v, &p0->W_d, &p0->W_a, &p0->ones, &p0->e0row,
+                          &p0->e0col, &p0->e0vec};
+  DevBuf *dstb[] = {&pk->E_loc, &pk->E_h, &pk->E_v, &pk->E_d, &pk->E_a, &pk->W_loc, &pk->W_h,
+                    &pk->W_v, &pk->W_d, &pk->W_a, &pk->ones, &pk->e0row, &pk->e0col, &pk->e0vec};
+  for (int t = 0; t < 14; ++t) add(*dstb[t], srcb[t]->bytes);
+  add(k.env.A, (size_t)R * C * chi * d * chi * sizeof(double));
+  add(k.env.lam, (size_t)R * sizeof(double));
+  each_search_buffer(&k.env, M, add);
+  k.w.each(add);
+  add(k.states, (size_t)M * R * C * 4);
+  add(k.energies, (size_t)M * 8);
+  add(k.logp, (size_t)M * 8);
+  std::vector<size_t> off;
+  size_t tot = 0;
+  for (auto &e : list) {
+    off.push_back(tot);
+    tot += (e.second + 255) / 256 * 256;
+  }
+  k.slice = tot;
+  const int n = (int)k.members.size();
+  k.arena.ensure(tot * n);
+  char *base = k.arena.as<char>();
+  for (size_t q = 0; q < list.size(); ++q) list[q].first->view(base + off[q], list[q].second);
+  // each member's tables into its slice
+  for (int m = 0; m < n; ++m) {
+    const spg_peps *pm = src[k.members[m]];
+    const DevBuf *sb[] = {&pm->E_loc, &pm->E_h, &pm->E_v, &pm->E_d, &pm->E_a, &pm->W_loc,
+                          &pm->W_h, &pm->W_v, &pm->W_d, &pm->W_a, &pm->ones, &pm->e0row,
+                          &pm->e0col, &pm->e0vec};
+    for (int t = 0; t < 14; ++t)
+      if (sb[t]->bytes)
+        SPG_HIP(hipMemcpy(base + (size_t)m * tot + off[t], sb[t]->p, sb[t]->bytes,
+                          hipMemcpyDeviceToDevice));
+  }
+}
+
+// Unit u's whole path (contraction, search, output) enqueued on stream st.
+static void enqueue_unit(spg_batch *b, int u, hipStream_t st) {
+  const Tuning saved_t = g_tune;
+  const BatchCtx saved_b = g_bc;
+  g_tune = b->unit_tune[u];
+  try {
+    if (b->unit_cls[u] >= 0) {
+      BatchClass &k = *b->classes[b->unit_cls[u]];
+      const spg_batch_item &it = b->items[k.members[0]];
+      g_bc.n = (int)k.members.size();
+      g_bc.ist = (long)k.slice;
+      g_bc.lo = k.arena.as<char>();
+      g_bc.hi = k.arena.as<char>() + k.slice;
+      const spg_mps_params mp = item_mps(it);
+      boundary_mps_fp64(&k.env, &mp, st, k.w);
+      spg_search_params sp{};
+      sp.max_states = it.max_states;
+      sp.cut_off_prob = it.cut_off_prob;
+      run_search(&k.env, &sp, nullptr, nullptr, k.states.as<int32_t>(), k.energies.as<double>(),
+                 k.logp.as<double>(), nullptr, st, false);
+    } else {
+      const int i = b->unit_inst[u];
+      const spg_batch_item &it = b->items[i];
+      spg_env *env = b->envs[i];
+      const spg_mps_params mp = item_mps(it);
+      boundary_mps_fp64(env, &mp, st, *b->slots[u % b->slots.size()]);
+      make_lp_copy(env, st);
+      spg_search_params sp{};
+      sp.max_states = it.max_states;
+      sp.cut_off_prob = it.cut_off_prob;
+      run_search(env, &sp, nullptr, nullptr, b->states[i]->as<int32_t>(),
+                 b->energies[i]->as<double>(), b->logp[i]->as<double>(), nullptr, st, false);
+    }
+  } catch (...) {
+    g_tune = saved_t;
+    g_bc = saved_b;
+    throw;
+  }
+  g_tune = saved_t;
+  g_bc = saved_b;
+}
+
+// Every unit, round-robin over the batch's streams, forked from and joined
+// back into s.
 static void enqueue_batch(spg_batch *b, hipStream_t s) {
   SPG_HIP(hipEventRecord(b->fork, s));
   for (auto st : b->streams) SPG_HIP(hipStreamWaitEvent(st, b->fork, 0));
   const int S = (int)b->streams.size();
-  for (int i = 0; i < b->n; ++i) enqueue_instance(b, i, b->streams[i % S]);
+  const int U = (int)b->unit_cls.size();
+  for (int u = 0; u < U; ++u) enqueue_unit(b, u, b->streams[u % S]);
   for (int k = 0; k < S; ++k) {
     SPG_HIP(hipEventRecord(b->done[k], b->streams[k]));
     SPG_HIP(hipStreamWaitEvent(s, b->done[k], 0));
@@ -1155,12 +1316,13 @@ static void enqueue_batch(spg_batch *b, hipStream_t s) {
 }
 
 int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items, int32_t n,
-                     int32_t n_streams, spg_batch_t **out) {
+                     int32_t n_streams, int32_t flags, spg_batch_t **out) {
   SPG_TRY
   if (!peps || !items || !out) return fail(SPG_ERR_INVALID, "spg_batch_create: null argument");
   if (n < 1) return fail(SPG_ERR_INVALID, "spg_batch_create: n must be >= 1");
   if (n_streams < 1 || n_streams > 64)
     return fail(SPG_ERR_INVALID, "spg_batch_create: n_streams must be in 1..64");
+  if (flags & ~SPG_BATCH_CLASSES) return fail(SPG_ERR_INVALID, "spg_batch_create: unknown flags");
   for (int i = 0; i < n; ++i) {
     if (!peps[i]) return fail(SPG_ERR_INVALID, "spg_batch_create: null peps");
     const spg_mps_params mp = item_mps(items[i]);
@@ -1175,8 +1337,65 @@ int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items,
   try {
     b->n = n;
     b->items.assign(items, items + n);
-    b->tune.assign(n, g_tune);
-    const int S = std::min<int>(n_streams, n);
+    b->src.assign(peps, peps + n);
+    b->inst_unit.assign(n, -1);
+    b->inst_member.assign(n, 0);
+    b->envs.assign(n, nullptr);
+    // units: classes of two or more FP64 instances (with SPG_BATCH_CLASSES), else single
+    std::vector<int> placed(n, 0);
+    for (int i = 0; i < n; ++i) {
+      if (placed[i]) continue;
+      std::vector<int> mem{i};
+      if ((flags & SPG_BATCH_CLASSES) && items[i].precision == SPG_FP64)
+        for (int j = i + 1; j < n; ++j)
+          if (!placed[j] && same_class(items[i], peps[i], items[j], peps[j])) mem.push_back(j);
+      const int u = (int)b->unit_cls.size();
+      if (mem.size() > 1) {
+        std::unique_ptr<BatchClass> k(new BatchClass());
+        k->members = mem;
+        build_class(*k, b->src, items[i]);
+        for (size_t m = 0; m < mem.size(); ++m) {
+          placed[mem[m]] = 1;
+          b->inst_unit[mem[m]] = u;
+          b->inst_member[mem[m]] = (int)m;
+        }
+        b->unit_cls.push_back((int)b->classes.size());
+        b->unit_inst.push_back(-1);
+        b->classes.push_back(std::move(k));
+      } else {
+        placed[i] = 1;
+        b->inst_unit[i] = u;
+        b->unit_cls.push_back(-1);
+        b->unit_inst.push_back(i);
+        const spg_peps *pp = peps[i];
+        spg_env *env = new spg_env();
+        b->envs[i] = env;
+        env->peps = pp;
+        env->chi = items[i].chi;
+        env->precision = items[i].precision;
+        const int R = pp->rows, C = pp->cols, d = pp->d, chi = items[i].chi;
+        env->dims.assign((size_t)R * (C + 1), 1);
+        env->A.ensure((size_t)R * C * chi * d * chi * sizeof(double));
+        env->lam.ensure((size_t)R * sizeof(double));
+        ensure_search(env, items[i].max_states);
+      }
+    }
+    b->states.resize(n);
+    b->energies.resize(n);
+    b->logp.resize(n);
+    for (int i = 0; i < n; ++i) {
+      if (!b->envs[i]) continue;
+      const spg_peps *pp = peps[i];
+      const int M = items[i].max_states;
+      b->states[i].reset(new DevBuf());
+      b->energies[i].reset(new DevBuf());
+      b->logp[i].reset(new DevBuf());
+      b->states[i]->ensure((size_t)M * pp->rows * pp->cols * 4);
+      b->energies[i]->ensure((size_t)M * 8);
+      b->logp[i]->ensure((size_t)M * 8);
+    }
+    b->unit_tune.assign(b->unit_cls.size(), g_tune);
+    const int S = std::min<int>(n_streams, (int)b->unit_cls.size());
     for (int k = 0; k < S; ++k) {
       hipStream_t st;
       SPG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -1190,25 +1409,6 @@ int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items,
     SPG_HIP(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
     SPG_HIP(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
     SPG_HIP(hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking));
-    for (int i = 0; i < n; ++i) {
-      const spg_peps *pp = peps[i];
-      spg_env *env = new spg_env();
-      b->envs.push_back(env);
-      env->peps = pp;
-      env->chi = items[i].chi;
-      env->precision = items[i].precision;
-      const int R = pp->rows, C = pp->cols, d = pp->d, chi = items[i].chi, M = items[i].max_states;
-      env->dims.assign((size_t)R * (C + 1), 1);
-      env->A.ensure((size_t)R * C * chi * d * chi * sizeof(double));
-      env->lam.ensure((size_t)R * sizeof(double));
-      b->states.emplace_back(new DevBuf());
-      b->energies.emplace_back(new DevBuf());
-      b->logp.emplace_back(new DevBuf());
-      b->states[i]->ensure((size_t)M * R * C * 4);
-      b->energies[i]->ensure((size_t)M * 8);
-      b->logp[i]->ensure((size_t)M * 8);
-      ensure_search(env, M);
-    }
   } catch (...) {
     delete b;
     throw;
@@ -1219,6 +1419,14 @@ int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items,
 }
 
 void spg_batch_free(spg_batch_t *b) { delete b; }
+
+int spg_batch_info(const spg_batch_t *b, int32_t *n_units, int32_t *unit_of) {
+  if (!b) return fail(SPG_ERR_INVALID, "spg_batch_info: null batch");
+  if (n_units) *n_units = (int32_t)b->unit_cls.size();
+  if (unit_of)
+    for (int i = 0; i < b->n; ++i) unit_of[i] = b->inst_unit[i];
+  return SPG_OK;
+}
 
 int spg_batch_run(spg_batch_t *b, int32_t use_graph, void *stream) {
   SPG_TRY
@@ -1266,20 +1474,35 @@ int spg_batch_result(const spg_batch_t *b, int32_t i, int32_t *states_out, doubl
   if (!b || !n_out) return fail(SPG_ERR_INVALID, "spg_batch_result: null argument");
   if (i < 0 || i >= b->n) return fail(SPG_ERR_INVALID, "spg_batch_result: index out of range");
   SPG_HIP(hipDeviceSynchronize());
-  spg_env *env = b->envs[i];
+  const spg_peps *pp = b->src[i];
+  const size_t N = (size_t)pp->rows * pp->cols;
+  const int u = b->inst_unit[i];
+  const spg_env *env;
+  size_t off = 0;
+  const char *st, *en, *lp;
+  if (b->unit_cls[u] >= 0) {
+    const BatchClass &k = *b->classes[b->unit_cls[u]];
+    off = (size_t)b->inst_member[i] * k.slice;
+    env = &k.env;
+    st = k.states.as<char>() + off;
+    en = k.energies.as<char>() + off;
+    lp = k.logp.as<char>() + off;
+  } else {
+    env = b->envs[i];
+    st = b->states[i]->as<char>();
+    en = b->energies[i]->as<char>();
+    lp = b->logp[i]->as<char>();
+  }
   int32_t nv = 0;
-  SPG_HIP(hipMemcpy(&nv, env->nvalid.p, 4, hipMemcpyDeviceToHost));
+  SPG_HIP(hipMemcpy(&nv, (const char *)env->nvalid.p + off, 4, hipMemcpyDeviceToHost));
   *n_out = nv;
-  const size_t N = (size_t)env->peps->rows * env->peps->cols;
   if (nv > 0) {
     if (states_out)
-      SPG_HIP(hipMemcpy(states_out, b->states[i]->p, (size_t)nv * N * 4, hipMemcpyDeviceToDevice));
-    if (energies_out)
-      SPG_HIP(hipMemcpy(energies_out, b->energies[i]->p, (size_t)nv * 8, hipMemcpyDeviceToDevice));
-    if (logp_out)
-      SPG_HIP(hipMemcpy(logp_out, b->logp[i]->p, (size_t)nv * 8, hipMemcpyDeviceToDevice));
+      SPG_HIP(hipMemcpy(states_out, st, (size_t)nv * N * 4, hipMemcpyDeviceToDevice));
+    if (energies_out) SPG_HIP(hipMemcpy(energies_out, en, (size_t)nv * 8, hipMemcpyDeviceToDevice));
+    if (logp_out) SPG_HIP(hipMemcpy(logp_out, lp, (size_t)nv * 8, hipMemcpyDeviceToDevice));
   }
-  if (log_Z) *log_Z = host_log_Z(env);
+  if (log_Z) *log_Z = host_log_Z(env, off, pp->beta, pp->shift);
   return SPG_OK;
   SPG_CATCH
 }
@@ -1288,7 +1511,7 @@ int spg_batch_set_tuning(spg_batch_t *b, int32_t i, int32_t gemm_tile) {
   if (!b || i < 0 || i >= b->n) return fail(SPG_ERR_INVALID, "spg_batch_set_tuning: bad batch or index");
   if (gemm_tile != 32 && gemm_tile != 64)
     return fail(SPG_ERR_INVALID, "spg_batch_set_tuning: gemm_tile must be 32 or 64");
-  b->tune[i].gemm_tile = gemm_tile;
+  b->unit_tune[b->inst_unit[i]].gemm_tile = gemm_tile;
   b->drop_graph();
   return SPG_OK;
 }
@@ -1302,38 +1525,37 @@ int spg_batch_autotune(spg_batch_t *b, void *stream, int32_t *tile_out) {
     SPG_HIP(hipStreamSynchronize(s));
     b->warm = true;
   }
-  // one bucket per (chi, d): time its first instance with every tile, twice
-  // each (the first run only warms), keep the fastest for the whole bucket
-  std::vector<int> done(b->n, 0);
+  // every unit (a class or a single instance) timed with each GEMM tile,
+  // twice each (the first run only warms); the fastest tile is kept
   hipEvent_t e0, e1;
   SPG_HIP(hipEventCreate(&e0));
   SPG_HIP(hipEventCreate(&e1));
   const int cand[2] = {64, 32};
-  for (int i = 0; i < b->n; ++i) {
-    if (done[i]) continue;
-    const int chi = b->items[i].chi, d = b->envs[i]->peps->d;
-    float best = 1e30f;
-    int best_tile = 64;
-    for (int t : cand) {
-      b->tune[i].gemm_tile = t;
-      float ms = 0.0f;
-      for (int rep = 0; rep < 2; ++rep) {
-        SPG_HIP(hipEventRecord(e0, s));
-        enqueue_instance(b, i, s);
-        SPG_HIP(hipEventRecord(e1, s));
-        SPG_HIP(hipEventSynchronize(e1));
-        SPG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  try {
+    for (size_t u = 0; u < b->unit_cls.size(); ++u) {
+      float best = 1e30f;
+      int best_tile = 64;
+      for (int t : cand) {
+        b->unit_tune[u].gemm_tile = t;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {
+          SPG_HIP(hipEventRecord(e0, s));
+          enqueue_unit(b, (int)u, s);
+          SPG_HIP(hipEventRecord(e1, s));
+          SPG_HIP(hipEventSynchronize(e1));
+          SPG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        }
+        if (ms < best) {
+          best = ms;
+          best_tile = t;
+        }
       }
-      if (ms < best) {
-        best = ms;
-        best_tile = t;
-      }
+      b->unit_tune[u].gemm_tile = best_tile;
     }
-    for (int j = i; j < b->n; ++j)
-      if (!done[j] && b->items[j].chi == chi && b->envs[j]->peps->d == d) {
-        b->tune[j].gemm_tile = best_tile;
-        done[j] = 1;
-      }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1342,7 +1564,7 @@ int spg_batch_autotune(spg_batch_t *b, void *stream, int32_t *tile_out) {
   enqueue_batch(b, s);
   SPG_HIP(hipStreamSynchronize(s));
   if (tile_out)
-    for (int i = 0; i < b->n; ++i) tile_out[i] = b->tune[i].gemm_tile;
+    for (int i = 0; i < b->n; ++i) tile_out[i] = b->unit_tune[b->inst_unit[i]].gemm_tile;
   return SPG_OK;
   SPG_CATCH
 }

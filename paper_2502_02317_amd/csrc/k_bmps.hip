@@ -18,7 +18,11 @@ inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // phi[p][x][P] = w(x) sum_y V(x,y) psi[p][y][P]
 __global__ void k_init_guess(int d, int chi, int bl, int br, const double *psi, const double *w,
-                             const double *V, double *phi) {
+                             const double *V, double *phi, long ist) {
+  SPG_INST(psi);
+  SPG_INST(w);
+  SPG_INST(V);
+  SPG_INST(phi);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long tot = (long)bl * d * br;
   if (e >= tot) return;
@@ -30,7 +34,10 @@ __global__ void k_init_guess(int d, int chi, int bl, int br, const double *psi, 
 
 // T1[p][a][x][q] = sum_e Al[x][e] EL[p][a][e][q]
 __global__ void k_T1(int d, int chi, int pl, int ql, const double *EL, const double *Al,
-                     double *T1) {
+                     double *T1, long ist) {
+  SPG_INST(EL);
+  SPG_INST(Al);
+  SPG_INST(T1);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long tot = (long)pl * d * d * ql;
   if (e >= tot) return;
@@ -44,7 +51,11 @@ __global__ void k_T1(int d, int chi, int pl, int ql, const double *EL, const dou
 
 // T2[p][x][y][q] = sum_a Hl[a][x] Dl[a][y] T1[p][a][x][q]
 __global__ void k_T2(int d, int chi, int pl, int ql, const double *T1, const double *Hl,
-                     const double *Dl, double *T2) {
+                     const double *Dl, double *T2, long ist) {
+  SPG_INST(T1);
+  SPG_INST(Hl);
+  SPG_INST(Dl);
+  SPG_INST(T2);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long tot = (long)pl * d * d * ql;
   if (e >= tot) return;
@@ -58,7 +69,10 @@ __global__ void k_T2(int d, int chi, int pl, int ql, const double *T1, const dou
 
 // T[p][x][y][Q] *= w(x) V(x,y)   (box p < n0, Q < n3)
 __global__ void k_scale_wv(int d, int chi, int n0, int n3, const double *w, const double *V,
-                           double *T) {
+                           double *T, long ist) {
+  SPG_INST(w);
+  SPG_INST(V);
+  SPG_INST(T);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long tot = (long)n0 * d * d * n3;
   if (e >= tot) return;
@@ -69,7 +83,10 @@ __global__ void k_scale_wv(int d, int chi, int n0, int n3, const double *w, cons
 
 // G3[p][x][a][q] = sum_y G2[p][x][y][q] Dl[a][y]
 __global__ void k_G3(int d, int chi, int pl, int ql, const double *G2, const double *Dl,
-                     double *G3) {
+                     double *G3, long ist) {
+  SPG_INST(G2);
+  SPG_INST(Dl);
+  SPG_INST(G3);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long tot = (long)pl * d * d * ql;
   if (e >= tot) return;
@@ -83,7 +100,11 @@ __global__ void k_G3(int d, int chi, int pl, int ql, const double *G2, const dou
 
 // ER[p][a][e][q] = sum_x G3[p][x][a][q] Hl[a][x] Al[x][e]
 __global__ void k_ERfin(int d, int chi, int pl, int ql, const double *G3, const double *Hl,
-                        const double *Al, double *ER) {
+                        const double *Al, double *ER, long ist) {
+  SPG_INST(G3);
+  SPG_INST(Hl);
+  SPG_INST(Al);
+  SPG_INST(ER);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long tot = (long)pl * d * d * ql;
   if (e >= tot) return;
@@ -97,7 +118,10 @@ __global__ void k_ERfin(int d, int chi, int pl, int ql, const double *G3, const 
 
 // P2[p][x][z][Q] = sum_y P[p][x][y][Q] A1[z][y]
 __global__ void k_P2(int d, int chi, int pl, int nq, const double *P, const double *A1,
-                     double *P2) {
+                     double *P2, long ist) {
+  SPG_INST(P);
+  SPG_INST(A1);
+  SPG_INST(P2);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long tot = (long)pl * d * d * nq;
   if (e >= tot) return;
@@ -111,7 +135,10 @@ __global__ void k_P2(int d, int chi, int pl, int nq, const double *P, const doub
 
 // Q2[Q][x][z][P] = sum_v Qr[Q][z][v][P] D1[x][v]
 __global__ void k_Q2(int d, int chi, int nq, int pr, const double *Qr, const double *D1,
-                     double *Q2) {
+                     double *Q2, long ist) {
+  SPG_INST(Qr);
+  SPG_INST(D1);
+  SPG_INST(Q2);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long tot = (long)nq * d * d * pr;
   if (e >= tot) return;
@@ -124,7 +151,9 @@ __global__ void k_Q2(int d, int chi, int nq, int pr, const double *Qr, const dou
 }
 
 // B[p][x][z][P] (compact) *= H1[x][z]
-__global__ void k_scale_H(int d, int pl, int pr, const double *H1, double *B) {
+__global__ void k_scale_H(int d, int pl, int pr, const double *H1, double *B, long ist) {
+  SPG_INST(H1);
+  SPG_INST(B);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long tot = (long)pl * d * d * pr;
   if (e >= tot) return;
@@ -133,7 +162,9 @@ __global__ void k_scale_H(int d, int pl, int pr, const double *H1, double *B) {
 }
 
 __global__ void k_unpack_right(int d, int chi, int nk, int pr, const double *src, long sk,
-                               long sj, double *dst) {
+                               long sj, double *dst, long ist) {
+  SPG_INST(src);
+  SPG_INST(dst);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long tot = (long)nk * d * pr;
   if (e >= tot) return;
@@ -143,7 +174,10 @@ __global__ void k_unpack_right(int d, int chi, int nk, int pr, const double *src
 
 // tmp[p][x][k] = sum_q phi[p][x][q] R[k][q]  (R row-major k x bl), then copy back
 __global__ void k_lq_fold(int d, int chi, int pl, int bl, int kk, const double *R,
-                          const double *phi, double *tmp) {
+                          const double *phi, double *tmp, long ist) {
+  SPG_INST(R);
+  SPG_INST(phi);
+  SPG_INST(tmp);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long tot = (long)pl * d * kk;
   if (e >= tot) return;
@@ -154,7 +188,9 @@ __global__ void k_lq_fold(int d, int chi, int pl, int bl, int kk, const double *
   tmp[px * chi + k] = acc;
 }
 
-__global__ void k_pack_right(int d, int chi, int nk, int pr, const double *src, double *dst) {
+__global__ void k_pack_right(int d, int chi, int nk, int pr, const double *src, double *dst, long ist) {
+  SPG_INST(src);
+  SPG_INST(dst);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long tot = (long)nk * d * pr;
   if (e >= tot) return;
@@ -164,7 +200,10 @@ __global__ void k_pack_right(int d, int chi, int nk, int pr, const double *src, 
 
 // w = exp(-beta (E - min E)) per table of `tsize` entries, one block per table.
 __global__ __launch_bounds__(256) void k_weights(int ntab, int tsize, double beta,
-                                                 const double *E, double *W, double *mins) {
+                                                 const double *E, double *W, double *mins, long ist) {
+  SPG_INST(E);
+  SPG_INST(W);
+  SPG_INST(mins);
   __shared__ double red[256];
   const int t = blockIdx.x;
   if (t >= ntab) return;
@@ -183,20 +222,23 @@ __global__ __launch_bounds__(256) void k_weights(int ntab, int tsize, double bet
   if (threadIdx.x == 0) mins[t] = mn;
 }
 
-__global__ void k_set_e0(int n, int chi, double *p, long stride) {
+__global__ void k_set_e0(int n, int chi, double *p, long stride, long ist) {
+  SPG_INST(p);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e >= (long)n * chi) return;
   const int j = (int)(e / chi), i = (int)(e % chi);
   p[j * stride + i] = (i == 0) ? 1.0 : 0.0;
 }
 
-__global__ void k_set_identity(int n, double *p) {
+__global__ void k_set_identity(int n, double *p, long ist) {
+  SPG_INST(p);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e >= (long)n * n) return;
   p[e] = (e / n == e % n) ? 1.0 : 0.0;
 }
 
-__global__ void k_add_logs(double *logs, int out, int a, int b, int c) {
+__global__ void k_add_logs(double *logs, int out, int a, int b, int c, long ist) {
+  SPG_INST(logs);
   logs[out] = (a >= 0 ? logs[a] : 0.0) + (b >= 0 ? logs[b] : 0.0) + (c >= 0 ? logs[c] : 0.0);
 }
 
@@ -205,21 +247,30 @@ __global__ void k_add_logs(double *logs, int out, int a, int b, int c) {
 void init_guess(int d, int chi, int bl, int br, const double *psi, const RowFactors &f,
                 double *phi, hipStream_t s) {
   const long tot = (long)bl * d * br;
-  hipLaunchKernelGGL(k_init_guess, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, bl, br, psi,
-                     f.w, f.V, phi);
+  SPG_BC(psi);
+  SPG_BC(f.w);
+  SPG_BC(f.V);
+  SPG_BC(phi);
+  hipLaunchKernelGGL(k_init_guess, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, bl, br, psi, f.w, f.V, phi, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
 void left_part(int d, int chi, int pl, int ql, int qr, const double *EL, const double *psi,
                const RowFactors &f, double *T1, double *P, hipStream_t s) {
   const long tot = (long)pl * d * d * ql;
-  hipLaunchKernelGGL(k_T1, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, pl, ql, EL, f.Al, T1);
+  SPG_BC(EL);
+  SPG_BC(f.Al);
+  SPG_BC(T1);
+  hipLaunchKernelGGL(k_T1, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, EL, f.Al, T1, g_bc.ist);
   SPG_CHECK_LAUNCH();
   // T2 written into P (the GEMM below reads T2 and writes P in place would alias),
   // so T2 goes to the second half of T1's buffer.
   double *T2 = T1 + (long)chi * d * d * chi;
-  hipLaunchKernelGGL(k_T2, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, pl, ql, T1, f.Hl,
-                     f.Dl, T2);
+  SPG_BC(T1);
+  SPG_BC(f.Hl);
+  SPG_BC(f.Dl);
+  SPG_BC(T2);
+  hipLaunchKernelGGL(k_T2, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, T1, f.Hl, f.Dl, T2, g_bc.ist);
   SPG_CHECK_LAUNCH();
   // P[p][x][y][Q] = sum_q T2[p][x][y][q] psi[q][y][Q]   (batch y; rows (p,x))
   GemmDesc g{};
@@ -230,8 +281,10 @@ void left_part(int d, int chi, int pl, int ql, int qr, const double *EL, const d
   g.alpha = 1.0; g.beta = 0.0;
   gemm_f64(g, s);
   const long tot2 = (long)pl * d * d * qr;
-  hipLaunchKernelGGL(k_scale_wv, dim3(nblk(tot2, 256)), dim3(256), 0, s, d, chi, pl, qr, f.w,
-                     f.V, P);
+  SPG_BC(f.w);
+  SPG_BC(f.V);
+  SPG_BC(P);
+  hipLaunchKernelGGL(k_scale_wv, dim3(nblk(tot2, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, qr, f.w, f.V, P, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
@@ -269,14 +322,22 @@ void env_right(int d, int chi, int pl, int pr, int ql, int qr, const double *phi
   h.alpha = 1.0; h.beta = 0.0;
   gemm_f64(h, s);
   const long tot = (long)pl * d * d * ql;
-  hipLaunchKernelGGL(k_scale_wv, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, pl, ql, f.w,
-                     f.V, G2);
+  SPG_BC(f.w);
+  SPG_BC(f.V);
+  SPG_BC(G2);
+  hipLaunchKernelGGL(k_scale_wv, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, f.w, f.V, G2, g_bc.ist);
   SPG_CHECK_LAUNCH();
   double *G3 = G1;  // G1 no longer needed
-  hipLaunchKernelGGL(k_G3, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, pl, ql, G2, f.Dl, G3);
+  SPG_BC(G2);
+  SPG_BC(f.Dl);
+  SPG_BC(G3);
+  hipLaunchKernelGGL(k_G3, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, G2, f.Dl, G3, g_bc.ist);
   SPG_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_ERfin, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, pl, ql, G3, f.Hl,
-                     f.Al, ERn);
+  SPG_BC(G3);
+  SPG_BC(f.Hl);
+  SPG_BC(f.Al);
+  SPG_BC(ERn);
+  hipLaunchKernelGGL(k_ERfin, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, G3, f.Hl, f.Al, ERn, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
@@ -295,14 +356,21 @@ void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, cons
   g.alpha = 1.0; g.beta = 0.0;
   gemm_f64(g, s);
   const long totq = (long)qm * d * d * pr;
-  hipLaunchKernelGGL(k_scale_wv, dim3(nblk(totq, 256)), dim3(256), 0, s, d, chi, qm, pr, f1.w,
-                     f1.V, Qr);
+  SPG_BC(f1.w);
+  SPG_BC(f1.V);
+  SPG_BC(Qr);
+  hipLaunchKernelGGL(k_scale_wv, dim3(nblk(totq, 256), g_bc.n), dim3(256), 0, s, d, chi, qm, pr, f1.w, f1.V, Qr, g_bc.ist);
   SPG_CHECK_LAUNCH();
   const long totp = (long)pl * d * d * qm;
-  hipLaunchKernelGGL(k_P2, dim3(nblk(totp, 256)), dim3(256), 0, s, d, chi, pl, qm, P, f1.Al, P2);
+  SPG_BC(P);
+  SPG_BC(f1.Al);
+  SPG_BC(P2);
+  hipLaunchKernelGGL(k_P2, dim3(nblk(totp, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, qm, P, f1.Al, P2, g_bc.ist);
   SPG_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_Q2, dim3(nblk(totq, 256)), dim3(256), 0, s, d, chi, qm, pr, Qr, f1.Dl,
-                     Q2);
+  SPG_BC(Qr);
+  SPG_BC(f1.Dl);
+  SPG_BC(Q2);
+  hipLaunchKernelGGL(k_Q2, dim3(nblk(totq, 256), g_bc.n), dim3(256), 0, s, d, chi, qm, pr, Qr, f1.Dl, Q2, g_bc.ist);
   SPG_CHECK_LAUNCH();
   // B[p][x][z][P] = sum_Q P2[p][x][z][Q] Q2[Q][x][z][P]   (batch (x,z)), compact output
   GemmDesc h{};
@@ -313,7 +381,9 @@ void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, cons
   h.alpha = 1.0; h.beta = 0.0;
   gemm_f64(h, s);
   const long totb = (long)pl * d * d * pr;
-  hipLaunchKernelGGL(k_scale_H, dim3(nblk(totb, 256)), dim3(256), 0, s, d, pl, pr, f1.Hl, B);
+  SPG_BC(f1.Hl);
+  SPG_BC(B);
+  hipLaunchKernelGGL(k_scale_H, dim3(nblk(totb, 256), g_bc.n), dim3(256), 0, s, d, pl, pr, f1.Hl, B, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
@@ -321,8 +391,9 @@ void unpack_right(int d, int chi, int nk, int pr, const double *src, long sk, lo
                   double *dst, hipStream_t s) {
   const long tot = (long)nk * d * pr;
   if (tot <= 0) return;
-  hipLaunchKernelGGL(k_unpack_right, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, nk, pr, src,
-                     sk, sj, dst);
+  SPG_BC(src);
+  SPG_BC(dst);
+  hipLaunchKernelGGL(k_unpack_right, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, nk, pr, src, sk, sj, dst, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
@@ -332,44 +403,52 @@ void lq_fold(int d, int chi, int bl, int k, const double *R, double *phi_prev, d
   const int pl = chi;
   const long tot = (long)pl * d * k;
   fill_zero(tmp, (size_t)chi * d * chi, s);
-  hipLaunchKernelGGL(k_lq_fold, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, pl, bl, k, R,
-                     phi_prev, tmp);
+  SPG_BC(R);
+  SPG_BC(phi_prev);
+  SPG_BC(tmp);
+  hipLaunchKernelGGL(k_lq_fold, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, bl, k, R, phi_prev, tmp, g_bc.ist);
   SPG_CHECK_LAUNCH();
-  SPG_HIP(hipMemcpyAsync(phi_prev, tmp, sizeof(double) * chi * d * chi, hipMemcpyDeviceToDevice,
-                         s));
+  copy_d2d(phi_prev, tmp, sizeof(double) * chi * d * chi, s);
 }
 
 void pack_right(int d, int chi, int nk, int pr, const double *src, double *dst, hipStream_t s) {
   const long tot = (long)nk * d * pr;
   if (tot <= 0) return;
-  hipLaunchKernelGGL(k_pack_right, dim3(nblk(tot, 256)), dim3(256), 0, s, d, chi, nk, pr, src,
-                     dst);
+  SPG_BC(src);
+  SPG_BC(dst);
+  hipLaunchKernelGGL(k_pack_right, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, nk, pr, src, dst, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
 void build_weights(int ntab, int tsize, double beta, const double *E, double *W, double *mins,
                    hipStream_t s) {
   if (ntab <= 0) return;
-  hipLaunchKernelGGL(k_weights, dim3(ntab), dim3(256), 0, s, ntab, tsize, beta, E, W, mins);
+  SPG_BC(E);
+  SPG_BC(W);
+  SPG_BC(mins);
+  hipLaunchKernelGGL(k_weights, dim3(ntab, g_bc.n), dim3(256), 0, s, ntab, tsize, beta, E, W, mins, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
 void set_e0(int n, int chi, double *p, long stride, hipStream_t s) {
   const long tot = (long)n * chi;
   if (tot <= 0) return;
-  hipLaunchKernelGGL(k_set_e0, dim3(nblk(tot, 256)), dim3(256), 0, s, n, chi, p, stride);
+  SPG_BC(p);
+  hipLaunchKernelGGL(k_set_e0, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, n, chi, p, stride, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
 void set_identity(int n, double *p, hipStream_t s) {
   const long tot = (long)n * n;
   if (tot <= 0) return;
-  hipLaunchKernelGGL(k_set_identity, dim3(nblk(tot, 256)), dim3(256), 0, s, n, p);
+  SPG_BC(p);
+  hipLaunchKernelGGL(k_set_identity, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, n, p, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
 void add_logs(double *logs, int out, int a, int b, int c, hipStream_t s) {
-  hipLaunchKernelGGL(k_add_logs, dim3(1), dim3(1), 0, s, logs, out, a, b, c);
+  SPG_BC(logs);
+  hipLaunchKernelGGL(k_add_logs, dim3(1, g_bc.n), dim3(1), 0, s, logs, out, a, b, c, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 

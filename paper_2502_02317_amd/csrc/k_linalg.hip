@@ -31,10 +31,13 @@ __device__ double block_sum(double v, double *red) {
 template <int TILE>
 __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
   constexpr int P = TILE / 16, NQ = 16 * TILE / 256;
-  const int b1 = blockIdx.z / g.nb2, b2 = blockIdx.z % g.nb2;
-  const double *A = g.A + b1 * g.a_b1 + b2 * g.a_b2;
-  const double *B = g.B + b1 * g.b_b1 + b2 * g.b_b2;
-  double *C = g.C + b1 * g.c_b1 + b2 * g.c_b2;
+  const int nbb = g.nb1 * g.nb2;
+  const int inst = blockIdx.z / nbb, bz = blockIdx.z % nbb;   // class-batched instance
+  const int b1 = bz / g.nb2, b2 = bz % g.nb2;
+  const long io = (long)inst * g.ist;
+  const double *A = (const double *)((const char *)g.A + io) + b1 * g.a_b1 + b2 * g.a_b2;
+  const double *B = (const double *)((const char *)g.B + io) + b1 * g.b_b1 + b2 * g.b_b2;
+  double *C = (double *)((char *)g.C + io) + b1 * g.c_b1 + b2 * g.c_b2;
   __shared__ double As[16][TILE + 1];
   __shared__ double Bs[16][TILE + 1];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
@@ -89,7 +92,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
 
 // Deterministic split-K epilogue: C = alpha * sum_s P[s] + beta * C (P: [S][M][N]).
 __global__ void k_splitk_reduce(int M, int N, int S, const double *P, double *C, long c_i,
-                                long c_j, double alpha, double beta) {
+                                long c_j, double alpha, double beta, long ist) {
+  SPG_INST(P);
+  SPG_INST(C);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e >= (long)M * N) return;
   double acc = 0.0;
@@ -106,7 +111,11 @@ __global__ void k_splitk_reduce(int M, int N, int S, const double *P, double *C,
 // column-major workspace; Q is formed by backward accumulation.
 __global__ __launch_bounds__(1024) void k_qr(int m, int n, const double *X, long xr, long xc,
                                             double *Qo, long qr, long qc, double *R,
-                                            double *work) {
+                                            double *work, long ist) {
+  SPG_INST(X);
+  SPG_INST(Qo);
+  SPG_INST(R);
+  SPG_INST(work);
   double *W = work;                      // m x n column-major (v below diagonal, R above)
   double *Qw = work + (size_t)m * n;     // m x n column-major
   double *tau = work + 2 * (size_t)m * n;
@@ -193,7 +202,10 @@ __global__ __launch_bounds__(1024) void k_qr(int m, int n, const double *X, long
 constexpr int kQrLds = 18432;   // doubles of LDS for the panel (144 KiB)
 __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const double *X, long xr,
                                                 long xc, double *Qo, long qr, long qc, double *Rs,
-                                                int want_q) {
+                                                int want_q, long ist) {
+  SPG_INST(X);
+  SPG_INST(Qo);
+  SPG_INST(Rs);
   __shared__ double W[kQrLds];
   __shared__ double tau[kMaxSketch + 32];
   __shared__ double red[16];
@@ -295,7 +307,10 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
 // with singular values near rounding), re-orthonormalised by CGS2 with a
 // deterministic completion from the unit vectors.
 __global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double *Vo,
-                                                double *sig) {
+                                                double *sig, long ist) {
+  SPG_INST(Rm);
+  SPG_INST(Vo);
+  SPG_INST(sig);
   __shared__ double W[kMaxSketch * kMaxSketch];
   __shared__ double V[kMaxSketch * kMaxSketch];
   __shared__ double nrm[kMaxSketch];
@@ -431,7 +446,8 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t idx) {
   return z ^ (z >> 31);
 }
 
-__global__ void k_sketch(int n, int l, double *Om) {
+__global__ void k_sketch(int n, int l, double *Om, long ist) {
+  SPG_INST(Om);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e >= (long)n * l) return;
   const long i = e / l, j = e % l;
@@ -453,7 +469,9 @@ __device__ __forceinline__ long box_offset(long e, int n1, int n2, int n3, long 
 
 __global__ __launch_bounds__(256) void k_box_sumsq(const double *T, long tot, int n1, int n2,
                                                    int n3, long s0, long s1, long s2, long s3,
-                                                   double *part) {
+                                                   double *part, long ist) {
+  SPG_INST(T);
+  SPG_INST(part);
   __shared__ double red[16];
   double acc = 0.0;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
@@ -466,7 +484,10 @@ __global__ __launch_bounds__(256) void k_box_sumsq(const double *T, long tot, in
 }
 
 __global__ void k_box_fold(const double *part, int np, double *logs, int out, int in,
-                           double *inv_out) {
+                           double *inv_out, long ist) {
+  SPG_INST(part);
+  SPG_INST(logs);
+  SPG_INST(inv_out);
   if (threadIdx.x != 0) return;
   double ss = 0.0;
   for (int i = 0; i < np; ++i) ss += part[i];
@@ -477,7 +498,9 @@ __global__ void k_box_fold(const double *part, int np, double *logs, int out, in
 
 __global__ __launch_bounds__(256) void k_box_scale(double *T, long tot, int n1, int n2, int n3,
                                                    long s0, long s1, long s2, long s3,
-                                                   const double *inv) {
+                                                   const double *inv, long ist) {
+  SPG_INST(T);
+  SPG_INST(inv);
   const double f = *inv;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
        e += (long)gridDim.x * blockDim.x)
@@ -489,7 +512,9 @@ __global__ __launch_bounds__(256) void k_box_scale(double *T, long tot, int n1, 
 // stride w_el, row stride w_dir) and column i of U (ulen entries).
 __global__ __launch_bounds__(1024) void k_drop_null(int nd, int len, double *Wm, long w_dir,
                                                    long w_el, double *U, int ulen, long u_dir,
-                                                   long u_el) {
+                                                   long u_el, long ist) {
+  SPG_INST(Wm);
+  SPG_INST(U);
   __shared__ double wn[kMaxSketch + 32];
   __shared__ double wmax;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -517,7 +542,8 @@ __global__ __launch_bounds__(1024) void k_drop_null(int nd, int len, double *Wm,
   }
 }
 
-__global__ void k_fill_zero(double *p, size_t n) {
+__global__ void k_fill_zero(double *p, size_t n, long ist) {
+  SPG_INST(p);
   const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (e < n) p[e] = 0.0;
 }
@@ -543,17 +569,17 @@ static void gemm_launch(const GemmDesc &g, hipStream_t s) {
       h.a_b1 = kc * g.a_k; h.b_b1 = kc * g.b_k;
       h.C = g.ws; h.c_i = g.N; h.c_j = 1; h.c_b1 = (long)g.M * g.N;
       h.alpha = 1.0; h.beta = 0.0; h.kmax = g.K;
-      dim3 grid((h.N + TILE - 1) / TILE, (h.M + TILE - 1) / TILE, S);
+      dim3 grid((h.N + TILE - 1) / TILE, (h.M + TILE - 1) / TILE, S * g_bc.n);
       hipLaunchKernelGGL(k_gemm<TILE>, grid, dim3(256), 0, s, h);
       SPG_CHECK_LAUNCH();
       const long mn = (long)g.M * g.N;
-      hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g.M,
-                         g.N, S, g.ws, g.C, g.c_i, g.c_j, g.alpha, g.beta);
+      hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256), g_bc.n), dim3(256), 0,
+                         s, g.M, g.N, S, g.ws, g.C, g.c_i, g.c_j, g.alpha, g.beta, g_bc.ist);
       SPG_CHECK_LAUNCH();
       return;
     }
   }
-  dim3 grid((g.N + TILE - 1) / TILE, (g.M + TILE - 1) / TILE, g.nb1 * g.nb2);
+  dim3 grid((g.N + TILE - 1) / TILE, (g.M + TILE - 1) / TILE, g.nb1 * g.nb2 * g_bc.n);
   hipLaunchKernelGGL(k_gemm<TILE>, grid, dim3(256), 0, s, g);
   SPG_CHECK_LAUNCH();
 }
@@ -561,10 +587,20 @@ static void gemm_launch(const GemmDesc &g, hipStream_t s) {
 void gemm_f64(const GemmDesc &g, hipStream_t s) {
   KTimer kt_("gemm_f64", s, 2.0 * g.M * g.N * g.K * g.nb1 * g.nb2);
   if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
+  SPG_BC(g.A);
+  SPG_BC(g.B);
+  SPG_BC(g.C);
+  SPG_BC(g.ws);
+  GemmDesc h = g;
+  h.ist = g_bc.ist;
+  if ((long)h.nb1 * h.nb2 * g_bc.n > 65535) {
+    set_error("gemm_f64: batch too large for one launch");
+    throw Fail{SPG_ERR_UNSUPPORTED};
+  }
   if (g_tune.gemm_tile == 32)
-    gemm_launch<32>(g, s);
+    gemm_launch<32>(h, s);
   else
-    gemm_launch<64>(g, s);
+    gemm_launch<64>(h, s);
 }
 
 // Householder QR flops: 2mn^2 - 2n^3/3 for R, the same again to form Q.
@@ -589,12 +625,18 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
     throw Fail{SPG_ERR_UNSUPPORTED};
   }
   const int want_q = (Q != nullptr);
+  SPG_BC(X);
+  SPG_BC(Q);
+  SPG_BC(R);
+  SPG_BC(work);
+  const unsigned nI = (unsigned)g_bc.n;
+  const long ist = g_bc.ist;
   if ((long)m * n <= kQrLds) {
     // one LDS-resident block; R straight to the caller (or to scratch)
     double *Rd = R ? R : work;
     KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
-    hipLaunchKernelGGL(k_qr_lds, dim3(1), dim3(1024), 0, s, m, n, m, X, xr, xc, Q, qr, qc, Rd,
-                       want_q);
+    hipLaunchKernelGGL(k_qr_lds, dim3(1, nI), dim3(1024), 0, s, m, n, m, X, xr, xc, Q, qr, qc,
+                       Rd, want_q, ist);
     SPG_CHECK_LAUNCH();
     return;
   }
@@ -608,14 +650,14 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
     double *Rt = Qs + (long)p * n * n;          // n x n
     {
       KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
-      hipLaunchKernelGGL(k_qr_lds, dim3(p), dim3(1024), 0, s, m, n, mb, X, xr, xc, Q1, (long)n,
-                         1L, S, want_q);
+      hipLaunchKernelGGL(k_qr_lds, dim3(p, nI), dim3(1024), 0, s, m, n, mb, X, xr, xc, Q1,
+                         (long)n, 1L, S, want_q, ist);
       SPG_CHECK_LAUNCH();
     }
     {
       KTimer kt_("qr_f64", s, qr_flops(p * n, n, want_q));
-      hipLaunchKernelGGL(k_qr_lds, dim3(1), dim3(1024), 0, s, p * n, n, p * n, S, (long)n, 1L,
-                         Qs, (long)n, 1L, R ? R : Rt, want_q);
+      hipLaunchKernelGGL(k_qr_lds, dim3(1, nI), dim3(1024), 0, s, p * n, n, p * n, S, (long)n,
+                         1L, Qs, (long)n, 1L, R ? R : Rt, want_q, ist);
       SPG_CHECK_LAUNCH();
     }
     if (!want_q) return;
@@ -641,8 +683,8 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
   }
   // large panels: global-memory Householder in one workgroup
   KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
-  hipLaunchKernelGGL(k_qr, dim3(1), dim3(1024), 0, s, m, n, X, xr, xc, Q ? Q : work + 2L * m * n + n,
-                     Q ? qr : (long)n, Q ? qc : 1L, R, work);
+  hipLaunchKernelGGL(k_qr, dim3(1, nI), dim3(1024), 0, s, m, n, X, xr, xc,
+                     Q ? Q : work + 2L * m * n + n, Q ? qr : (long)n, Q ? qc : 1L, R, work, ist);
   SPG_CHECK_LAUNCH();
 }
 
@@ -653,14 +695,19 @@ void jacobi_svd_f64(int l, const double *Rm, double *V, double *sig, hipStream_t
     set_error("jacobi_svd_f64: size above the LDS limit");
     throw Fail{SPG_ERR_UNSUPPORTED};
   }
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, l, Rm, V, sig);
+  SPG_BC(Rm);
+  SPG_BC(V);
+  SPG_BC(sig);
+  hipLaunchKernelGGL(k_jacobi, dim3(1, g_bc.n), dim3(1024), 0, s, l, Rm, V, sig, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
 void fill_sketch(int n, int l, double *Om, hipStream_t s) {
   const long tot = (long)n * l;
   if (tot <= 0) return;
-  hipLaunchKernelGGL(k_sketch, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, l, Om);
+  SPG_BC(Om);
+  hipLaunchKernelGGL(k_sketch, dim3((unsigned)((tot + 255) / 256), g_bc.n), dim3(256), 0, s, n, l,
+                     Om, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
@@ -670,14 +717,18 @@ void normalize_box(double *T, int n0, int n1, int n2, int n3, long s0, long s1, 
   const long tot = (long)n0 * n1 * n2 * n3;
   if (tot <= 0) return;
   const int nb = (int)std::min<long>(kNormBlocks, (tot + 255) / 256);
-  hipLaunchKernelGGL(k_box_sumsq, dim3(nb), dim3(256), 0, s, T, tot, n1, n2, n3, s0, s1, s2, s3,
-                     scratch);
+  SPG_BC(T);
+  SPG_BC(logs);
+  SPG_BC(scratch);
+  const unsigned nI = (unsigned)g_bc.n;
+  hipLaunchKernelGGL(k_box_sumsq, dim3(nb, nI), dim3(256), 0, s, T, tot, n1, n2, n3, s0, s1, s2,
+                     s3, scratch, g_bc.ist);
   SPG_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_box_fold, dim3(1), dim3(64), 0, s, scratch, nb, logs, out, in,
-                     scratch + kNormBlocks);
+  hipLaunchKernelGGL(k_box_fold, dim3(1, nI), dim3(64), 0, s, scratch, nb, logs, out, in,
+                     scratch + kNormBlocks, g_bc.ist);
   SPG_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_box_scale, dim3(nb), dim3(256), 0, s, T, tot, n1, n2, n3, s0, s1, s2, s3,
-                     scratch + kNormBlocks);
+  hipLaunchKernelGGL(k_box_scale, dim3(nb, nI), dim3(256), 0, s, T, tot, n1, n2, n3, s0, s1, s2,
+                     s3, scratch + kNormBlocks, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
@@ -688,14 +739,18 @@ void drop_null(int nd, int len, double *Wm, long w_dir, long w_el, double *U, in
     set_error("drop_null: too many directions");
     throw Fail{SPG_ERR_UNSUPPORTED};
   }
-  hipLaunchKernelGGL(k_drop_null, dim3(1), dim3(1024), 0, s, nd, len, Wm, w_dir, w_el, U, ulen,
-                     u_dir, u_el);
+  SPG_BC(Wm);
+  SPG_BC(U);
+  hipLaunchKernelGGL(k_drop_null, dim3(1, g_bc.n), dim3(1024), 0, s, nd, len, Wm, w_dir, w_el, U,
+                     ulen, u_dir, u_el, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
 void fill_zero(double *p, size_t n, hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  SPG_BC(p);
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256), g_bc.n), dim3(256), 0, s, p, n,
+                     g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 

@@ -192,6 +192,7 @@ inline int grad_blocks(int n) {
 
 void mlp_forward(int n_beam, int d, const float *feats, const float *prm, int H, float *logp,
                  hipStream_t s) {
+  bc_single("mlp_forward");
   if (n_beam <= 0) return;
   hipLaunchKernelGGL(k_mlp_fwd, dim3(nblk(n_beam, kWaves)), dim3(256), 0, s, n_beam, d, feats,
                      prm, H, logp);
@@ -203,6 +204,7 @@ size_t mlp_partial_floats(int H) { return (size_t)kGradBlocks * (mlp_n_params(H)
 void mlp_loss_grad(int n_beam, int d, const float *feats, const float *target, const float *prm,
                    int H, float *partial, float *grad, float *loss, float *loss_acc,
                    hipStream_t s) {
+  bc_single("mlp_loss_grad");
   KTimer kt_("mlp_grad", s, 4.0 * n_beam * d * (kFeat * H + 2 * H));
   const int nb = grad_blocks(n_beam);
   if (nb > 0) {
@@ -217,12 +219,14 @@ void mlp_loss_grad(int n_beam, int d, const float *feats, const float *target, c
 
 void mlp_adam(int P, float *prm, float *m, float *v, const float *grad, float lr, float bc1,
               float bc2, hipStream_t s) {
+  bc_single("mlp_adam");
   hipLaunchKernelGGL(k_adam, dim3(nblk(P, 256)), dim3(256), 0, s, P, prm, m, v, grad, lr, bc1,
                      bc2);
   SPG_CHECK_LAUNCH();
 }
 
 void to_float(long n, const double *src, float *dst, hipStream_t s) {
+  bc_single("to_float");
   if (n <= 0) return;
   hipLaunchKernelGGL(k_to_float, dim3(nblk(n, 256)), dim3(256), 0, s, n, src, dst);
   SPG_CHECK_LAUNCH();

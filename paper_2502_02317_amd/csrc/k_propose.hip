@@ -468,6 +468,7 @@ __global__ __launch_bounds__(256) void k_max(int n, const double *v, double *out
 
 void site_features(const SearchTabs &t, const double *A, float *sf, double *rscr,
                    hipStream_t s) {
+  bc_single("site_features");
   hipLaunchKernelGGL(k_site_feats, dim3(t.rows), dim3(256), 0, s, t, A, sf, rscr);
   SPG_CHECK_LAUNCH();
 }
@@ -475,6 +476,7 @@ void site_features(const SearchTabs &t, const double *A, float *sf, double *rscr
 void propose(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
              const double *score, const double *smax, const float *sf, const float *prm, int H,
              float *feat_out, uint16_t *bins, unsigned *hist, hipStream_t s) {
+  bc_single("propose");
   KTimer kt_("propose", s, 2.0 * n_beam * t.d * (kFeat * H + 2 * H));
   if (n_beam <= 0) return;
   hipLaunchKernelGGL(k_propose, dim3(nblk(n_beam, kWaves)), dim3(256), 0, s, t, r, c, n_beam,
@@ -486,6 +488,7 @@ void guided_step(const SearchTabs &t, int r, int c, int n_beam, int M, int K, co
                  int N, const double *A_rc, const double *L, const int32_t *anc, const double *Rv,
                  long rstride, const double *Rsc, const double *score, GuideWork &g, int cl,
                  int cr, hipStream_t s) {
+  bc_single("guided_step");
   hipLaunchKernelGGL(k_tau_pred, dim3(1), dim3(64), 0, s, g.hist, K, g.jstar, g.n_list);
   SPG_CHECK_LAUNCH();
   {
@@ -506,6 +509,7 @@ void guided_step(const SearchTabs &t, int r, int c, int n_beam, int M, int K, co
 }
 
 void max_of(int n, const double *v, double *out, hipStream_t s) {
+  bc_single("max_of");
   hipLaunchKernelGGL(k_max, dim3(1), dim3(256), 0, s, n, v, out);
   SPG_CHECK_LAUNCH();
 }

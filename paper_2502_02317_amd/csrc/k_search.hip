@@ -30,7 +30,13 @@ constexpr int kWaves = 4;   // wavefronts (work items) per 256-thread block
 __global__ __launch_bounds__(256) void k_right_env(SearchTabs t, int r, int c, int n_anc,
                                                    const uint8_t *cfg, int N, const double *A,
                                                    const double *Rnext, double *Rout,
-                                                   long rstride, double *scale, int sstride) {
+                                                   long rstride, double *scale, int sstride, long ist) {
+  SPG_INST(cfg);
+  SPG_INST(A);
+  SPG_INST(Rnext);
+  SPG_INST(Rout);
+  SPG_INST(scale);
+  shift_tabs(t, ist);
   __shared__ double Rs[kWaves][kMaxChi];
   __shared__ double gs[kWaves][256];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -73,7 +79,15 @@ __global__ __launch_bounds__(256) void k_marginals(SearchTabs t, int r, int c, i
                                                    const double *L, const int32_t *anc,
                                                    const double *Rv, long rstride,
                                                    const double *score, double *out,
-                                                   int add_score) {
+                                                   int add_score, long ist) {
+  SPG_INST(cfg);
+  SPG_INST(A);
+  SPG_INST(L);
+  SPG_INST(anc);
+  SPG_INST(Rv);
+  SPG_INST(score);
+  SPG_INST(out);
+  shift_tabs(t, ist);
   __shared__ double Ls[kWaves][kMaxChi];
   __shared__ double Rs[kWaves][kMaxChi];
   __shared__ double qs[kWaves][256];
@@ -127,7 +141,14 @@ __global__ __launch_bounds__(256) void k_marginals(SearchTabs t, int r, int c, i
 __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, int M,
                                                 const double *cand, const int32_t *cid,
                                                 int32_t *sel, double *sel_score, uint64_t *kw,
-                                                int32_t *iw) {
+                                                int32_t *iw, long ist) {
+  SPG_INST(n_dev);
+  SPG_INST(cand);
+  SPG_INST(cid);
+  SPG_INST(sel);
+  SPG_INST(sel_score);
+  SPG_INST(kw);
+  SPG_INST(iw);
   __shared__ unsigned hist[256];
   __shared__ uint64_t sh_prefix;
   __shared__ int sh_need;
@@ -201,7 +222,21 @@ __global__ __launch_bounds__(256) void k_beam_update(SearchTabs t, int r, int c,
                                                      const double *sel_score, const double *A,
                                                      int update_L, uint8_t *cfg_o,
                                                      double *energy_o, double *score_o,
-                                                     double *L_o, int32_t *anc_o) {
+                                                     double *L_o, int32_t *anc_o, long ist) {
+  SPG_INST(sel);
+  SPG_INST(cfg);
+  SPG_INST(energy);
+  SPG_INST(L);
+  SPG_INST(anc);
+  SPG_INST(cand);
+  SPG_INST(sel_score);
+  SPG_INST(A);
+  SPG_INST(cfg_o);
+  SPG_INST(energy_o);
+  SPG_INST(score_o);
+  SPG_INST(L_o);
+  SPG_INST(anc_o);
+  shift_tabs(t, ist);
   __shared__ double Ls[kWaves][kMaxChi];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j0 = blockIdx.x * kWaves + w;
@@ -242,7 +277,9 @@ __global__ __launch_bounds__(256) void k_beam_update(SearchTabs t, int r, int c,
   }
 }
 
-__global__ void k_reset_row(int n, int chi, double *L, int32_t *anc) {
+__global__ void k_reset_row(int n, int chi, double *L, int32_t *anc, long ist) {
+  SPG_INST(L);
+  SPG_INST(anc);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e >= (long)n * chi) return;
   const int j = (int)(e / chi), i = (int)(e % chi);
@@ -252,7 +289,10 @@ __global__ void k_reset_row(int n, int chi, double *L, int32_t *anc) {
 
 // Energy of complete configurations by Eq. (1), one wavefront per state.
 __global__ __launch_bounds__(256) void k_energy(SearchTabs t, int n, int N, const uint8_t *cfg,
-                                                double *E) {
+                                                double *E, long ist) {
+  SPG_INST(cfg);
+  SPG_INST(E);
+  shift_tabs(t, ist);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = blockIdx.x * kWaves + w;
   if (j >= n) return;
@@ -277,7 +317,12 @@ __global__ __launch_bounds__(256) void k_energy(SearchTabs t, int n, int N, cons
 }
 
 __global__ __launch_bounds__(1024) void k_final_sort(int n, const double *E, const double *score,
-                                                    uint64_t *kw, int32_t *iw, int32_t *nv) {
+                                                    uint64_t *kw, int32_t *iw, int32_t *nv, long ist) {
+  SPG_INST(E);
+  SPG_INST(score);
+  SPG_INST(kw);
+  SPG_INST(iw);
+  SPG_INST(nv);
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
@@ -303,7 +348,14 @@ __global__ __launch_bounds__(1024) void k_final_sort(int n, const double *E, con
 
 __global__ void k_gather_out(int n, int N, const int32_t *perm, const uint8_t *cfg,
                              const double *E, const double *score, int32_t *states,
-                             double *energies, double *logp) {
+                             double *energies, double *logp, long ist) {
+  SPG_INST(perm);
+  SPG_INST(cfg);
+  SPG_INST(E);
+  SPG_INST(score);
+  SPG_INST(states);
+  SPG_INST(energies);
+  SPG_INST(logp);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e >= (long)n * N) return;
   const int t = (int)(e / N), k = (int)(e % N);
@@ -316,7 +368,9 @@ __global__ void k_gather_out(int n, int N, const int32_t *perm, const uint8_t *c
 }
 
 __global__ __launch_bounds__(1024) void k_cutoff(int n_host, const int *n_dev, double log_cut,
-                                                double *cand) {
+                                                double *cand, long ist) {
+  SPG_INST(n_dev);
+  SPG_INST(cand);
   __shared__ double red[1024];
   const int n = n_dev ? *n_dev : n_host;
   double m = -INFINITY;
@@ -332,7 +386,9 @@ __global__ __launch_bounds__(1024) void k_cutoff(int n_host, const int *n_dev, d
     if (!(cand[i] >= thr)) cand[i] = -INFINITY;
 }
 
-__global__ void k_cfg_from_i32(long n, const int32_t *src, uint8_t *dst) {
+__global__ void k_cfg_from_i32(long n, const int32_t *src, uint8_t *dst, long ist) {
+  SPG_INST(src);
+  SPG_INST(dst);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e < n) dst[e] = (uint8_t)src[e];
 }
@@ -340,7 +396,11 @@ __global__ void k_cfg_from_i32(long n, const int32_t *src, uint8_t *dst) {
 // L^b <- g^b_c(x_c) L^b A[:, x_c, :], max-normalised, x_c read from cfg
 __global__ __launch_bounds__(256) void k_advance_L(SearchTabs t, int r, int c, int n,
                                                    const uint8_t *cfg, int N, const double *A,
-                                                   double *L) {
+                                                   double *L, long ist) {
+  SPG_INST(cfg);
+  SPG_INST(A);
+  SPG_INST(L);
+  shift_tabs(t, ist);
   __shared__ double Ls[kWaves][kMaxChi];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int b0 = blockIdx.x * kWaves + w;
@@ -377,8 +437,13 @@ void right_env_col(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *
                    int cl, int cr, hipStream_t s, double *scale, int sstride) {
   KTimer kt_("right_env", s, 2.0 * n_anc * cl * t.d * cr);
   if (n_anc <= 0) return;
-  hipLaunchKernelGGL(k_right_env, dim3(nblk(n_anc, kWaves)), dim3(256), 0, s, t, r, c, n_anc,
-                     cfg, N, A_rc, Rnext, Rout, rstride, scale, sstride);
+  SPG_BC(cfg);
+  SPG_BC(A_rc);
+  SPG_BC(Rnext);
+  SPG_BC(Rout);
+  SPG_BC(scale);
+  bc_check_tabs(t);
+  hipLaunchKernelGGL(k_right_env, dim3(nblk(n_anc, kWaves), g_bc.n), dim3(256), 0, s, t, r, c, n_anc, cfg, N, A_rc, Rnext, Rout, rstride, scale, sstride, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
@@ -388,8 +453,15 @@ void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg
                hipStream_t s) {
   KTimer kt_("marginals", s, 2.0 * n_beam * t.d * cl * cr);
   if (n_beam <= 0) return;
-  hipLaunchKernelGGL(k_marginals, dim3(nblk(n_beam, kWaves)), dim3(256), 0, s, t, r, c, n_beam,
-                     cfg, N, A_rc, L, anc, Rv, rstride, score, out, add_score);
+  SPG_BC(cfg);
+  SPG_BC(A_rc);
+  SPG_BC(L);
+  SPG_BC(anc);
+  SPG_BC(Rv);
+  SPG_BC(score);
+  SPG_BC(out);
+  bc_check_tabs(t);
+  hipLaunchKernelGGL(k_marginals, dim3(nblk(n_beam, kWaves), g_bc.n), dim3(256), 0, s, t, r, c, n_beam, cfg, N, A_rc, L, anc, Rv, rstride, score, out, add_score, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
@@ -397,8 +469,14 @@ void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *
                  int32_t *ids_work, hipStream_t s, const int *n_dev, const int32_t *cid,
                  double *sel_score) {
   KTimer kt_("select_topm", s, (cid ? 12.0 : 8.0) * n_cand + 4.0 * (M < n_cand ? M : n_cand));
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, n_cand, n_dev, M, cand, cid, sel,
-                     sel_score, keys_work, ids_work);
+  SPG_BC(n_dev);
+  SPG_BC(cand);
+  SPG_BC(cid);
+  SPG_BC(sel);
+  SPG_BC(sel_score);
+  SPG_BC(keys_work);
+  SPG_BC(ids_work);
+  hipLaunchKernelGGL(k_select, dim3(1, g_bc.n), dim3(1024), 0, s, n_cand, n_dev, M, cand, cid, sel, sel_score, keys_work, ids_work, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
@@ -409,15 +487,29 @@ void beam_update(const SearchTabs &t, int r, int c, int n_new, const int32_t *se
                  int cr, hipStream_t s, const double *sel_score) {
   KTimer kt_("beam_update", s, 2.0 * n_new * cl * cr);
   if (n_new <= 0) return;
-  hipLaunchKernelGGL(k_beam_update, dim3(nblk(n_new, kWaves)), dim3(256), 0, s, t, r, c, n_new,
-                     sel, N, cfg, energy, L, anc, cand, sel_score, A_rc, update_L, cfg_o,
-                     energy_o, score_o, L_o, anc_o);
+  SPG_BC(sel);
+  SPG_BC(cfg);
+  SPG_BC(energy);
+  SPG_BC(L);
+  SPG_BC(anc);
+  SPG_BC(cand);
+  SPG_BC(sel_score);
+  SPG_BC(A_rc);
+  SPG_BC(cfg_o);
+  SPG_BC(energy_o);
+  SPG_BC(score_o);
+  SPG_BC(L_o);
+  SPG_BC(anc_o);
+  bc_check_tabs(t);
+  hipLaunchKernelGGL(k_beam_update, dim3(nblk(n_new, kWaves), g_bc.n), dim3(256), 0, s, t, r, c, n_new, sel, N, cfg, energy, L, anc, cand, sel_score, A_rc, update_L, cfg_o, energy_o, score_o, L_o, anc_o, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
 void beam_reset_row(int n, int chi, double *L, int32_t *anc, hipStream_t s) {
   const long tot = (long)n * chi;
-  hipLaunchKernelGGL(k_reset_row, dim3(nblk(tot, 256)), dim3(256), 0, s, n, chi, L, anc);
+  SPG_BC(L);
+  SPG_BC(anc);
+  hipLaunchKernelGGL(k_reset_row, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, n, chi, L, anc, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
@@ -425,34 +517,54 @@ void final_sort(const SearchTabs &t, int n, int N, const uint8_t *cfg, const dou
                 int32_t *states_out, double *energies_out, double *logp_out, double *e_work,
                 int32_t *perm_work, int32_t *n_valid, hipStream_t s) {
   KTimer kt_("final_sort", s);
-  hipLaunchKernelGGL(k_energy, dim3(nblk(n, kWaves)), dim3(256), 0, s, t, n, N, cfg, e_work);
+  SPG_BC(cfg);
+  SPG_BC(e_work);
+  bc_check_tabs(t);
+  hipLaunchKernelGGL(k_energy, dim3(nblk(n, kWaves), g_bc.n), dim3(256), 0, s, t, n, N, cfg, e_work, g_bc.ist);
   SPG_CHECK_LAUNCH();
   uint64_t *kw = reinterpret_cast<uint64_t *>(e_work + n);
-  hipLaunchKernelGGL(k_final_sort, dim3(1), dim3(1024), 0, s, n, e_work, score, kw, perm_work,
-                     n_valid);
+  SPG_BC(e_work);
+  SPG_BC(score);
+  SPG_BC(kw);
+  SPG_BC(perm_work);
+  SPG_BC(n_valid);
+  hipLaunchKernelGGL(k_final_sort, dim3(1, g_bc.n), dim3(1024), 0, s, n, e_work, score, kw, perm_work, n_valid, g_bc.ist);
   SPG_CHECK_LAUNCH();
   const long tot = (long)n * N;
-  hipLaunchKernelGGL(k_gather_out, dim3(nblk(tot, 256)), dim3(256), 0, s, n, N, perm_work, cfg,
-                     e_work, score, states_out, energies_out, logp_out);
+  SPG_BC(perm_work);
+  SPG_BC(cfg);
+  SPG_BC(e_work);
+  SPG_BC(score);
+  SPG_BC(states_out);
+  SPG_BC(energies_out);
+  SPG_BC(logp_out);
+  hipLaunchKernelGGL(k_gather_out, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, n, N, perm_work, cfg, e_work, score, states_out, energies_out, logp_out, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
 void apply_cutoff(int n, double log_cut, double *cand, hipStream_t s, const int *n_dev) {
-  hipLaunchKernelGGL(k_cutoff, dim3(1), dim3(1024), 0, s, n, n_dev, log_cut, cand);
+  SPG_BC(n_dev);
+  SPG_BC(cand);
+  hipLaunchKernelGGL(k_cutoff, dim3(1, g_bc.n), dim3(1024), 0, s, n, n_dev, log_cut, cand, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
 void cfg_from_i32(int n, int N, const int32_t *src, uint8_t *dst, hipStream_t s) {
   const long tot = (long)n * N;
-  hipLaunchKernelGGL(k_cfg_from_i32, dim3(nblk(tot, 256)), dim3(256), 0, s, tot, src, dst);
+  SPG_BC(src);
+  SPG_BC(dst);
+  hipLaunchKernelGGL(k_cfg_from_i32, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, tot, src, dst, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
 void advance_L(const SearchTabs &t, int r, int c, int n, const uint8_t *cfg, int N,
                const double *A_rc, double *L, double *tmp, hipStream_t s) {
   (void)tmp;
-  hipLaunchKernelGGL(k_advance_L, dim3(nblk(n, kWaves)), dim3(256), 0, s, t, r, c, n, cfg, N,
-                     A_rc, L);
+  SPG_BC(cfg);
+  SPG_BC(A_rc);
+  SPG_BC(L);
+  bc_check_tabs(t);
+  hipLaunchKernelGGL(k_advance_L, dim3(nblk(n, kWaves), g_bc.n), dim3(256), 0, s, t, r, c, n, cfg, N, A_rc, L, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 

@@ -271,6 +271,7 @@ __global__ void k_set_e0_f(int n, int chi, float *p, long stride) {
 }  // namespace
 
 void lp_convert(long n, const double *src, void *dst, int precision, hipStream_t s) {
+  bc_single("lp_convert");
   if (n <= 0) return;
   if (precision == SPG_FP32)
     hipLaunchKernelGGL(k_to_f32, dim3(nblk(n, 256)), dim3(256), 0, s, n, src, (float *)dst);
@@ -280,6 +281,7 @@ void lp_convert(long n, const double *src, void *dst, int precision, hipStream_t
 }
 
 void lp_set_e0(int n, int chi, float *p, long stride, hipStream_t s) {
+  bc_single("lp_set_e0");
   const long tot = (long)n * chi;
   if (tot <= 0) return;
   hipLaunchKernelGGL(k_set_e0_f, dim3(nblk(tot, 256)), dim3(256), 0, s, n, chi, p, stride);
@@ -289,6 +291,7 @@ void lp_set_e0(int n, int chi, float *p, long stride, hipStream_t s) {
 void lp_right_env_col(const SearchTabs &t, int precision, int r, int c, int n_anc,
                       const uint8_t *cfg, int N, const void *A_rc, const float *Rnext,
                       float *Rout, long rstride, int cl, int cr, hipStream_t s) {
+  bc_single("lp_right_env_col");
   if (n_anc <= 0) return;
   KTimer kt_("right_env", s, 2.0 * n_anc * cl * t.d * cr);
   if (precision == SPG_FP32)
@@ -304,6 +307,7 @@ void lp_marginals(const SearchTabs &t, int precision, int r, int c, int n_beam,
                   const uint8_t *cfg, int N, const void *A_rc, const float *L, const int32_t *anc,
                   const float *Rv, long rstride, const double *score, double *out, int add_score,
                   int cl, int cr, hipStream_t s) {
+  bc_single("lp_marginals");
   if (n_beam <= 0) return;
   KTimer kt_("marginals", s, 2.0 * n_beam * t.d * cl * cr);
   if (precision == SPG_FP32)
@@ -322,6 +326,7 @@ void lp_beam_update(const SearchTabs &t, int precision, int r, int c, int n_new,
                     const float *L, const int32_t *anc, const double *cand, const void *A_rc,
                     int update_L, uint8_t *cfg_o, double *energy_o, double *score_o, float *L_o,
                     int32_t *anc_o, int cl, int cr, hipStream_t s) {
+  bc_single("lp_beam_update");
   if (n_new <= 0) return;
   KTimer kt_("beam_update", s, 2.0 * n_new * cl * cr);
   if (precision == SPG_FP32)
@@ -337,6 +342,7 @@ void lp_beam_update(const SearchTabs &t, int precision, int r, int c, int n_new,
 
 void lp_advance_L(const SearchTabs &t, int precision, int r, int c, int n, const uint8_t *cfg,
                   int N, const void *A_rc, float *L, hipStream_t s) {
+  bc_single("lp_advance_L");
   if (n <= 0) return;
   if (precision == SPG_FP32)
     hipLaunchKernelGGL(k_advance_L_lp<float>, dim3(nblk(n, kW)), dim3(256), 0, s, t, r, c, n, cfg,

@@ -12,6 +12,18 @@
 
 namespace spg {
 
+// Class-batched launches: the instance's own tables.
+__device__ __forceinline__ void shift_tabs(SearchTabs &t, long ist) {
+  SPG_INST(t.E_loc);
+  SPG_INST(t.E_h);
+  SPG_INST(t.E_v);
+  SPG_INST(t.E_d);
+  SPG_INST(t.E_a);
+  SPG_INST(t.W_v);
+  SPG_INST(t.W_d);
+  SPG_INST(t.W_a);
+}
+
 // g^b_c(s): couplings of x_{r,c} = s to the fixed row above (1 for r = 0).
 __device__ __forceinline__ double field(const SearchTabs &t, int r, int c, const uint8_t *cb,
                                         int s) {

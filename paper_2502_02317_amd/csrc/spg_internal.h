@@ -35,16 +35,47 @@ struct KTimer {
   hipStream_t s = nullptr;
 };
 
+// ---- class-batched launches -------------------------------------------------
+// Instances of one shape class keep all their device data in equal-sized
+// slices of one allocation, `ist` bytes apart.  While a class runs, every
+// launch covers all its instances at once: grid y (z for the GEMM) selects
+// the instance and each kernel shifts its pointers by instance * ist.  Host
+// wrappers check that every pointer they pass lies in the first slice
+// [lo, hi) so no shifted access can leave the allocation.
+struct BatchCtx {
+  int n = 1;            // instances per launch
+  long ist = 0;         // bytes between instances
+  const char *lo = nullptr, *hi = nullptr;
+};
+extern thread_local BatchCtx g_bc;
+void bc_check(const void *p, const char *what);   // throws when p is outside [lo, hi)
+// Device-to-device copy of `bytes` at dst from src, for every instance of the class.
+void copy_d2d(void *dst, const void *src, size_t bytes, hipStream_t s);
+#define SPG_BC(p) ::spg::bc_check((const void *)(p), #p)
+
+template <class T>
+__device__ __forceinline__ T *inst_ptr(T *p, long ist) {
+  return p ? (T *)((const char *)p + (long)blockIdx.y * ist) : p;
+}
+#define SPG_INST(p) p = ::spg::inst_ptr(p, ist)
+
 // ---- device buffers -------------------------------------------------------
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  bool owned = true;      // false: a view into another allocation (never grows)
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
   ~DevBuf() { release(); }
   void ensure(size_t n);  // grows (contents lost), zero-filled on growth (device-synchronous)
   void release();
+  void view(void *q, size_t n) {  // point at memory owned elsewhere
+    release();
+    p = q;
+    bytes = n;
+    owned = false;
+  }
   template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
@@ -63,6 +94,7 @@ struct GemmDesc {
   double *ws = nullptr;   // optional split-K workspace (ws_len doubles)
   size_t ws_len = 0;
   int kmax = 0;           // internal: global K bound of split-K chunks (0 = K)
+  long ist = 0;           // internal: class-batched instance stride (bytes)
 };
 void gemm_f64(const GemmDesc &g, hipStream_t s);
 
@@ -145,6 +177,12 @@ struct SearchTabs {         // device tables of the instance
   const double *E_loc, *E_h, *E_v, *E_d, *E_a;
   const double *W_v, *W_d, *W_a;
 };
+inline void bc_check_tabs(const SearchTabs &t) {
+  SPG_BC(t.E_loc); SPG_BC(t.E_h); SPG_BC(t.E_v); SPG_BC(t.E_d); SPG_BC(t.E_a);
+  SPG_BC(t.W_v); SPG_BC(t.W_d); SPG_BC(t.W_a);
+}
+// Throws when a launch that has no class-batched form runs inside a class.
+void bc_single(const char *what);
 // cl, cr: actual bond dimensions left / right of column c (work accounting only)
 // scale (optional): scale[a * sstride] receives the max-normalisation divisor
 void right_env_col(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *cfg, int N,

@@ -50,6 +50,7 @@ class TrainParams(C.Structure):
 
 
 N_FEATURES = 6
+BATCH_CLASSES = 1
 
 
 class BatchItem(C.Structure):
@@ -65,7 +66,7 @@ EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_branch_an
            "spg_proposal_train", "spg_proposal_features", "spg_proposal_forward",
            "spg_proposal_loss_grad", "spg_proposal_adam", "spg_search_stats",
            "spg_batch_create", "spg_batch_free", "spg_batch_run", "spg_batch_result",
-           "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning"]
+           "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning", "spg_batch_info"]
 KERNEL_CLASSES = ["gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box", "right_env",
                   "marginals", "select_topm", "beam_update", "final_sort", "propose",
                   "guided_eval", "mlp_grad"]
@@ -108,8 +109,9 @@ def load() -> C.CDLL:
     lib.spg_proposal_loss_grad.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
     lib.spg_proposal_adam.argtypes = [vp, vp, C.c_float, vp]
     lib.spg_search_stats.argtypes = [vp, C.POINTER(C.c_int64)]
-    lib.spg_batch_create.argtypes = [C.POINTER(vp), C.POINTER(BatchItem), i32, i32,
+    lib.spg_batch_create.argtypes = [C.POINTER(vp), C.POINTER(BatchItem), i32, i32, i32,
                                      C.POINTER(vp)]
+    lib.spg_batch_info.argtypes = [vp, i32p, vp]
     lib.spg_batch_free.argtypes = [vp]
     lib.spg_batch_free.restype = None
     lib.spg_batch_run.argtypes = [vp, i32, vp]
@@ -123,7 +125,7 @@ def load() -> C.CDLL:
                  "spg_proposal_features", "spg_proposal_forward", "spg_proposal_loss_grad",
                  "spg_proposal_adam", "spg_search_stats", "spg_batch_create", "spg_batch_run",
                  "spg_batch_result", "spg_batch_set_tuning", "spg_batch_autotune",
-                 "spg_set_tuning"]:
+                 "spg_set_tuning", "spg_batch_info"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -386,7 +388,7 @@ class Batch:
     captured graph).  Keeps its Peps objects alive."""
 
     def __init__(self, peps_list, chi, max_states, num_sweeps=1, precision="fp64",
-                 oversample=16, power_iters=1, cut_off_prob=0.0, n_streams=8):
+                 oversample=16, power_iters=1, cut_off_prob=0.0, n_streams=8, classes=True):
         n = len(peps_list)
         chis = list(chi) if hasattr(chi, "__len__") else [chi] * n
         Ms = list(max_states) if hasattr(max_states, "__len__") else [max_states] * n
@@ -396,7 +398,8 @@ class Batch:
                                             float(cut_off_prob)) for i in range(n)])
         handles = (C.c_void_p * n)(*[p.handle.value for p in peps_list])
         h = C.c_void_p()
-        _check(load().spg_batch_create(handles, items, n, int(n_streams), C.byref(h)))
+        _check(load().spg_batch_create(handles, items, n, int(n_streams),
+                                       BATCH_CLASSES if classes else 0, C.byref(h)))
         self.handle = h
         self.peps = list(peps_list)
         self.n = n
@@ -431,6 +434,14 @@ class Batch:
 
     def set_tuning(self, i: int, gemm_tile: int) -> None:
         _check(load().spg_batch_set_tuning(self.handle, int(i), int(gemm_tile)))
+
+    def units(self):
+        """(number of units, unit of each instance): a unit is a class of
+        same-shape instances sharing every launch, or one instance."""
+        nu = C.c_int32(0)
+        of = np.zeros(self.n, dtype=np.int32)
+        _check(load().spg_batch_info(self.handle, C.byref(nu), of.ctypes.data))
+        return nu.value, of
 
     def autotune(self, stream=None) -> np.ndarray:
         out = np.zeros(self.n, dtype=np.int32)

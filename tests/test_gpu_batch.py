@@ -1,7 +1,8 @@
 """Batches on the GPU (through the C ABI): every instance of a batch, eager or
 replayed from the captured graph, gives bitwise the results of running it on
 its own (spg_boundary_mps + spg_branch_and_bound with the same GEMM tile):
-the same deterministic kernels run on the same data, only on other streams.
+the same deterministic kernels run on the same data, on other streams or, for
+members of a shape class, in launches that cover the whole class.
 Graph replays are interleaved with other eager work and synchronisations and
 each replay is checked."""
 import numpy as np
@@ -62,12 +63,31 @@ def _same(a, b, label):
     assert a[3] == b[3] or (np.isnan(a[3]) and np.isnan(b[3])), label
 
 
-@pytest.mark.parametrize("n_streams", [1, 3])
-def test_batch_equals_each_instance_alone(n_streams):
-    insts = _instances()
+def _class_instances():
+    """Several members per shape class (equal lattice, d, chi, beam), plus
+    single instances, so both unit kinds run in one batch."""
+    out = []
+    for k in range(3):
+        out.append((random_potts(3, 4, 4, True, seed=600 + k, beta=1.0), 8, 20, "fp64"))
+    for k in range(2):
+        out.append((random_potts(2, 5, 3, False, seed=610 + k, beta=0.7), 6, 33, "fp64"))
+    out.append((random_potts(4, 4, 4, True, seed=620, beta=1.0), 8, 33, "fp32"))
+    out.append((random_potts(3, 4, 4, True, seed=621, beta=1.0), 8, 21, "fp64"))
+    for k in range(3):
+        out.append((cfg3_instance(40 + k, 6), 16, 512, "fp64"))
+    return out
+
+
+@pytest.mark.parametrize("n_streams,classes,which", [(1, False, "mixed"), (3, False, "mixed"),
+                                                     (2, True, "classes"), (1, True, "mixed")])
+def test_batch_equals_each_instance_alone(n_streams, classes, which):
+    insts = _instances() if which == "mixed" else _class_instances()
     peps = [spg.build_peps(i) for i, _, _, _ in insts]
     b = spg.Batch(peps, chi=[c for _, c, _, _ in insts], max_states=[m for _, _, m, _ in insts],
-                  precision=[p for _, _, _, p in insts], n_streams=n_streams)
+                  precision=[p for _, _, _, p in insts], n_streams=n_streams, classes=classes)
+    n_units, _ = b.units()
+    if which == "classes":
+        assert n_units == 5            # three classes and two single instances
     b.run(use_graph=False)
     eager = [b.result(i) for i in range(b.n)]
     for i, (inst, chi, M, prec) in enumerate(insts):
@@ -84,7 +104,7 @@ def test_batch_equals_each_instance_alone(n_streams):
 
 
 def test_autotuned_batch_equals_each_instance_alone_with_its_tile():
-    insts = _instances()[:4] + _instances()[4:5]
+    insts = _class_instances()
     peps = [spg.build_peps(i) for i, _, _, _ in insts]
     b = spg.Batch(peps, chi=[c for _, c, _, _ in insts], max_states=[m for _, _, m, _ in insts],
                   precision=[p for _, _, _, p in insts], n_streams=2)
