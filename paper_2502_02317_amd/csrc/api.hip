@@ -67,13 +67,10 @@ void copy_d2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
     SPG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
     return;
   }
-  SPG_BC(dst);
-  SPG_BC(src);
   SPG_BC((const char *)dst + bytes - 1);
   SPG_BC((const char *)src + bytes - 1);
-  // one row per instance, rows ist bytes apart
-  SPG_HIP(hipMemcpy2DAsync(dst, (size_t)g_bc.ist, src, (size_t)g_bc.ist, bytes, (size_t)g_bc.n,
-                           hipMemcpyDeviceToDevice, s));
+  // one copy per instance by a kernel of our own (instance offsets in 64 bits)
+  copy_doubles((double *)dst, (const double *)src, bytes / sizeof(double), s);
 }
 
 void bc_single(const char *what) {
@@ -1204,10 +1201,15 @@ static bool same_class(const spg_batch_item &a, const spg_peps *pa, const spg_ba
          pa->d == pb->d && pa->kings == pb->kings;
 }
 
+// Largest allocation of one class: classes whose slices would exceed it are
+// split, so every address within a class stays inside a 1 GiB span.
+constexpr size_t kClassBytes = (size_t)1 << 30;
+
 // Lay out one slice: every buffer of the class's peps, env, workspace and
-// outputs, 256-byte aligned; allocate n slices and point the views at slice 0.
-static void build_class(BatchClass &k, const std::vector<const spg_peps *> &src,
-                        const spg_batch_item &it) {
+// outputs, 256-byte aligned; allocate n slices (unless layout_only) and point
+// the views at slice 0.  Returns the slice size.
+static size_t build_class(BatchClass &k, const std::vector<const spg_peps *> &src,
+                          const spg_batch_item &it, bool layout_only = false) {
   const spg_peps *p0 = src[k.members[0]];
   const int R = p0->rows, C = p0->cols, d = p0->d, chi = it.chi, M = it.max_states;
   k.peps.rows = R; k.peps.cols = C; k.peps.d = d; k.peps.kings = p0->kings;
@@ -1242,7 +1244,12 @@ static void build_class(BatchClass &k, const std::vector<const spg_peps *> &src,
     tot += (e.second + 255) / 256 * 256;
   }
   k.slice = tot;
+  if (layout_only) return tot;
   const int n = (int)k.members.size();
+  if (tot * n > kClassBytes) {
+    set_error("build_class: class allocation above its cap");
+    throw Fail{SPG_ERR_UNSUPPORTED};
+  }
   k.arena.ensure(tot * n);
   char *base = k.arena.as<char>();
   for (size_t q = 0; q < list.size(); ++q) list[q].first->view(base + off[q], list[q].second);
@@ -1257,6 +1264,7 @@ static void build_class(BatchClass &k, const std::vector<const spg_peps *> &src,
         SPG_HIP(hipMemcpy(base + (size_t)m * tot + off[t], sb[t]->p, sb[t]->bytes,
                           hipMemcpyDeviceToDevice));
   }
+  return tot;
 }
 
 // Unit u's whole path (contraction, search, output) enqueued on stream st.
@@ -1346,9 +1354,14 @@ int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items,
     for (int i = 0; i < n; ++i) {
       if (placed[i]) continue;
       std::vector<int> mem{i};
-      if ((flags & SPG_BATCH_CLASSES) && items[i].precision == SPG_FP64)
-        for (int j = i + 1; j < n; ++j)
+      if ((flags & SPG_BATCH_CLASSES) && items[i].precision == SPG_FP64) {
+        BatchClass probe;
+        probe.members = mem;
+        const size_t slice = build_class(probe, b->src, items[i], true);
+        const size_t cap = std::max<size_t>(1, kClassBytes / slice);
+        for (int j = i + 1; j < n && mem.size() < cap; ++j)
           if (!placed[j] && same_class(items[i], peps[i], items[j], peps[j])) mem.push_back(j);
+      }
       const int u = (int)b->unit_cls.size();
       if (mem.size() > 1) {
         std::unique_ptr<BatchClass> k(new BatchClass());

@@ -542,6 +542,13 @@ __global__ __launch_bounds__(1024) void k_drop_null(int nd, int len, double *Wm,
   }
 }
 
+__global__ void k_copy(double *dst, const double *src, size_t n, long ist) {
+  SPG_INST(dst);
+  SPG_INST(src);
+  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = src[e];
+}
+
 __global__ void k_fill_zero(double *p, size_t n, long ist) {
   SPG_INST(p);
   const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -743,6 +750,15 @@ void drop_null(int nd, int len, double *Wm, long w_dir, long w_el, double *U, in
   SPG_BC(U);
   hipLaunchKernelGGL(k_drop_null, dim3(1, g_bc.n), dim3(1024), 0, s, nd, len, Wm, w_dir, w_el, U,
                      ulen, u_dir, u_el, g_bc.ist);
+  SPG_CHECK_LAUNCH();
+}
+
+void copy_doubles(double *dst, const double *src, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  SPG_BC(dst);
+  SPG_BC(src);
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256), g_bc.n), dim3(256), 0, s, dst, src,
+                     n, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 

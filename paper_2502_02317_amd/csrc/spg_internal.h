@@ -130,6 +130,7 @@ constexpr int kNormScratch = 160;
 void normalize_box(double *T, int n0, int n1, int n2, int n3, long s0, long s1, long s2,
                    long s3, double *logs, int out, int in, double *scratch, hipStream_t s);
 void fill_zero(double *p, size_t n, hipStream_t s);
+void copy_doubles(double *dst, const double *src, size_t n, hipStream_t s);
 // Directions at the rounding floor of a truncation are not unique: zero every
 // direction i (row i of Wm, column i of U) whose weight |Wm row i| is at most
 // 1e-11 of the largest.
