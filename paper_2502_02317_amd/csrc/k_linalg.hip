@@ -199,6 +199,15 @@ __global__ __launch_bounds__(1024) void k_qr(int m, int n, const double *X, long
 // then form Q over the reflectors as LAPACK dorg2r does).  Block b covers rows
 // [b*mb, min(m, (b+1)*mb)); missing rows are zero.  R_b goes to Rs + b*n*n
 // (row-major n x n), Q rows to Qo.
+//
+// Each wavefront owns trailing columns in turn, so one step costs strided
+// passes over a few columns with wavefront DPP sums, and one barrier.  Writes that would race with the step's readers are
+// deferred by a step: during the factorisation column j keeps its raw entries
+// (every group rescales them on the fly) and is finalised (v_j scaled below
+// the diagonal, beta_j on it) during step j+1, when nobody reads it; while Q
+// is formed, column j is turned into H_j e_j during step j-1 by the group that
+// then applies H_{j-1} to it.  Norms of the next pivot column come from the
+// group that updates it (lookahead), one slot per column.
 constexpr int kQrLds = 18432;   // doubles of LDS for the panel (144 KiB)
 __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const double *X, long xr,
                                                 long xc, double *Qo, long qr, long qc, double *Rs,
@@ -208,8 +217,10 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
   SPG_INST(Rs);
   __shared__ double W[kQrLds];
   __shared__ double tau[kMaxSketch + 32];
+  __shared__ double sig2[kMaxSketch + 32];   // |column j below the diagonal|^2 before step j
   __shared__ double red[16];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  const int tid = threadIdx.x;
+  const int grp = tid >> 6, l16 = tid & 63, ngrp = blockDim.x >> 6;
   const int r0 = blockIdx.x * mb;
   const int mr = min(mb, m - r0);          // real rows of this block
   const int ld = max(mr, n);               // rows in LDS (zero rows appended if short)
@@ -218,50 +229,70 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
     W[e] = (i < mr) ? X[(long)(r0 + i) * xr + (long)j * xc] : 0.0;
   }
   __syncthreads();
-  // squared norm of column 0 below the diagonal; later columns get theirs from
-  // the wavefront that applies the previous reflector to them (lookahead)
-  __shared__ double sh_sig;
   {
     double loc = 0.0;
     for (int i = 1 + tid; i < ld; i += blockDim.x) loc += W[i] * W[i];
     const double t = block_sum(loc, red);
-    if (tid == 0) sh_sig = t;
+    if (tid == 0) sig2[0] = t;
   }
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    double *col = W + j * ld;
-    const double sig = sh_sig;
-    const double alpha = col[j];
-    double tj = 0.0, sc = 0.0, beta = alpha;
-    if (sig != 0.0) {
-      const double nrm = sqrt(alpha * alpha + sig);
+  // reflector of column j from its raw entries: H_j = I - tau v v^T with
+  // v_j = 1, v_i = scale * col[i] (i > j), and R[j][j] = beta
+  auto reflector = [&](int j, double &tj, double &sc, double &beta) {
+    const double sg = sig2[j], alpha = W[j * ld + j];
+    tj = 0.0; sc = 0.0; beta = alpha;
+    if (sg != 0.0) {
+      const double nrm = sqrt(alpha * alpha + sg);
       beta = (alpha >= 0.0) ? -nrm : nrm;
       tj = (beta - alpha) / beta;
       sc = 1.0 / (alpha - beta);
     }
-    if (tj != 0.0)
-      for (int i = j + 1 + tid; i < ld; i += blockDim.x) col[i] *= sc;
-    __syncthreads();
-    if (tid == 0) { tau[j] = tj; col[j] = beta; }
-    for (int k = j + 1 + wid; k < n; k += nw) {
+  };
+  for (int j = 0; j < n; ++j) {
+    double tj, sc, beta;
+    reflector(j, tj, sc, beta);
+    const double *col = W + j * ld;
+    for (int k = j + 1 + grp; k < n; k += ngrp) {
       double *ck = W + k * ld;
       if (tj != 0.0) {
-        double dot = (lane == 0) ? ck[j] : 0.0;
-        for (int i = j + 1 + lane; i < ld; i += 64) dot += col[i] * ck[i];
-        dot = wave_sum(dot);
-        const double f = tj * dot;
-        if (lane == 0) ck[j] -= f;
-        for (int i = j + 1 + lane; i < ld; i += 64) ck[i] -= f * col[i];
+        double dot = 0.0;
+        for (int i = j + 1 + l16; i < ld; i += 64) dot += col[i] * ck[i];
+        dot = ck[j] + sc * wave_sum(dot);
+        const double f = tj * dot, fs = f * sc;
+        if (l16 == 0) ck[j] -= f;
+        for (int i = j + 1 + l16; i < ld; i += 64) ck[i] -= fs * col[i];
       }
       if (k == j + 1) {
         double a = 0.0;
-        for (int i = j + 2 + lane; i < ld; i += 64) a += ck[i] * ck[i];
+        for (int i = j + 2 + l16; i < ld; i += 64) a += ck[i] * ck[i];
         a = wave_sum(a);
-        if (lane == 0) sh_sig = a;
+        if (l16 == 0) sig2[j + 1] = a;
+      }
+    }
+    // finalise column j - 1 (nobody reads it any more)
+    if (j > 0 && grp == ngrp - 1) {
+      double tp, sp, bp;
+      reflector(j - 1, tp, sp, bp);
+      double *cp = W + (j - 1) * ld;
+      for (int i = j + l16; i < ld; i += 64) cp[i] *= sp;
+      if (l16 == 0) {
+        tau[j - 1] = tp;
+        cp[j - 1] = bp;
       }
     }
     __syncthreads();
   }
+  if (tid < 64) {
+    double tp, sp, bp;
+    reflector(n - 1, tp, sp, bp);
+    double *cp = W + (n - 1) * ld;
+    for (int i = n + l16; i < ld; i += 64) cp[i] *= sp;
+    if (l16 == 0) {
+      tau[n - 1] = tp;
+      cp[n - 1] = bp;
+    }
+  }
+  __syncthreads();
   double *Rb = Rs + (long)blockIdx.x * n * n;
   for (int e = tid; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
@@ -269,28 +300,35 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
   }
   if (!want_q) return;
   __syncthreads();
-  // Q in place: for j = n-1 .. 0 apply H_j to columns j+1.., then column j = H_j e_j
+  // Q = H_0 H_1 ... H_{n-1} [I; 0], backward: step j applies H_j to columns
+  // j+1..; the group that takes column k = j+1 first turns it into
+  // H_{j+1} e_{j+1} (its reflector is no longer read by anyone)
+  auto to_unit = [&](int k) {
+    double *ck = W + k * ld;
+    const double tk = tau[k];
+    for (int i = l16; i < ld; i += 64) {
+      const double v = ck[i];
+      ck[i] = (i < k) ? 0.0 : (i == k) ? 1.0 - tk : -tk * v;
+    }
+  };
   for (int j = n - 1; j >= 0; --j) {
     const double tj = tau[j];
-    double *v = W + j * ld;                  // v[i] for i > j, v[j] = 1 implicit
-    if (tj != 0.0)
-      for (int k = j + 1 + wid; k < n; k += nw) {
-        double *ck = W + k * ld;
-        double dot = (lane == 0) ? ck[j] : 0.0;
-        for (int i = j + 1 + lane; i < ld; i += 64) dot += v[i] * ck[i];
-        dot = wave_sum(dot);
-        const double f = tj * dot;
-        if (lane == 0) ck[j] -= f;
-        for (int i = j + 1 + lane; i < ld; i += 64) ck[i] -= f * v[i];
-      }
-    __syncthreads();
-    for (int i = tid; i < ld; i += blockDim.x) {
-      if (i < j) v[i] = 0.0;
-      else if (i == j) v[i] = 1.0 - tj;
-      else v[i] = -tj * v[i];
+    const double *v = W + j * ld;
+    for (int k = j + 1 + grp; k < n; k += ngrp) {
+      if (k == j + 1) to_unit(k);
+      if (tj == 0.0) continue;
+      double *ck = W + k * ld;
+      double dot = 0.0;
+      for (int i = j + 1 + l16; i < ld; i += 64) dot += v[i] * ck[i];
+      dot = ck[j] + wave_sum(dot);
+      const double f = tj * dot;
+      if (l16 == 0) ck[j] -= f;
+      for (int i = j + 1 + l16; i < ld; i += 64) ck[i] -= f * v[i];
     }
     __syncthreads();
   }
+  if (tid < 64) to_unit(0);
+  __syncthreads();
   for (int e = tid; e < mr * n; e += blockDim.x) {
     const int i = e % mr, j = e / mr;
     Qo[(long)(r0 + i) * qr + (long)j * qc] = W[j * ld + i];
@@ -336,29 +374,41 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double
   for (int sweep = 0; sweep < 30; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
+    // one half-wavefront (32 lanes, rows l32, l32 + 32, l32 + 64) per pair, so
+    // a round of up to 32 pairs is one pass; the three column sums of a pair
+    // are reduced together (16-lane DPP sums, then across the two rows)
+    const int hw = tid >> 5, l32 = tid & 31, nhw = blockDim.x >> 5;
     for (int t = 0; t < le - 1; ++t) {
-      for (int k = wid; k < le / 2; k += nw) {
+      for (int k = hw; k < le / 2; k += nhw) {
         int p, q;
         if (k == 0) { p = t; q = le - 1; }
         else { p = (t + k) % (le - 1); q = (t - k + le - 1) % (le - 1); }
         if (p > q) { const int tmp = p; p = q; q = tmp; }
         if (q >= l) continue;
+        double x[3], y[3];
         double a = 0.0, b = 0.0, g = 0.0;
-        for (int r = lane; r < l; r += 64) {
-          const double x = W[p * l + r], y = W[q * l + r];
-          a += x * x; b += y * y; g += x * y;
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+          const int r = l32 + 32 * h;
+          x[h] = (r < l) ? W[p * l + r] : 0.0;
+          y[h] = (r < l) ? W[q * l + r] : 0.0;
+          a += x[h] * x[h]; b += y[h] * y[h]; g += x[h] * y[h];
         }
-        a = wave_sum(a); b = wave_sum(b); g = wave_sum(g);
-        if (a > tiny && b > tiny && fabs(g) > gfloor && fabs(g) > 1e-14 * sqrt(a * b)) {
+        a = row16_sum(a); b = row16_sum(b); g = row16_sum(g);
+        a += __shfl_xor(a, 16); b += __shfl_xor(b, 16); g += __shfl_xor(g, 16);
+        if (a > tiny && b > tiny && fabs(g) > gfloor && g * g > 1e-28 * (a * b)) {
           const double zeta = (b - a) / (2.0 * g);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-          for (int r = lane; r < l; r += 64) {
-            const double x = W[p * l + r], y = W[q * l + r];
-            W[p * l + r] = cs * x - sn * y;
-            W[q * l + r] = sn * x + cs * y;
+#pragma unroll
+          for (int h = 0; h < 3; ++h) {
+            const int r = l32 + 32 * h;
+            if (r < l) {
+              W[p * l + r] = cs * x[h] - sn * y[h];
+              W[q * l + r] = sn * x[h] + cs * y[h];
+            }
           }
-          if (lane == 0) rotated = 1;
+          if (l32 == 0) rotated = 1;
         }
       }
       __syncthreads();

@@ -31,6 +31,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return lane63(v);
 }
 
+// Sum over each row of 16 lanes, returned to every lane of that row (all 16
+// lanes of the row must be active).
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_move<0xB1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);         // quad_perm [2,3,0,1]
+  v += dpp_move<0x124>(v);        // row_ror:4
+  v += dpp_move<0x128>(v);        // row_ror:8
+  return v;
+}
+
 // Max over the wave, returned to every lane (max(x, 0-fill) is safe for the
 // non-negative arguments it is used with).
 __device__ __forceinline__ double wave_max_nonneg(double v) {
