@@ -197,7 +197,7 @@ static int tsvd_left(BmpsWork &w, const double *B, long br, long bc, int m, int 
   }
   mm(l, n, m, Q, 1, l, B, br, bc, Cm, n, 1);                 // Cm = Q^T B   (l x n)
   qr_f64(n, l, Cm, 1, n, nullptr, l, 1, w.Rc.as<double>(), qw, s);  // Cm^T = Qc Rc (R only)
-  jacobi_svd_f64(l, w.Rc.as<double>(), w.V.as<double>(), w.sig.as<double>(), s);
+  jacobi_svd_f64(l, kk, w.Rc.as<double>(), w.V.as<double>(), w.sig.as<double>(), s);
   mm(m, kk, l, Q, l, 1, w.V.as<double>(), l, 1, U, ur, uc);  // U = Q V[:, :kk]
   return kk;
 }

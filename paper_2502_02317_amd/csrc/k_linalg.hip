@@ -344,7 +344,7 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
 // then checked for orthonormality and, if off by more than 1e-13 (directions
 // with singular values near rounding), re-orthonormalised by CGS2 with a
 // deterministic completion from the unit vectors.
-__global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double *Vo,
+__global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm, double *Vo,
                                                 double *sig, long ist) {
   SPG_INST(Rm);
   SPG_INST(Vo);
@@ -433,8 +433,9 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double
   }
   if (tid == 0) bad = 0;
   __syncthreads();
-  for (int e = wid; e < l * l; e += nw) {
-    const int i = e / l, j = e % l;
+  // only the leading kk columns are used: check and repair those
+  for (int e = wid; e < kk * kk; e += nw) {
+    const int i = e / kk, j = e % kk;
     if (j > i) continue;
     double g = 0.0;
     for (int r = lane; r < l; r += 64) g += V[i * l + r] * V[j * l + r];
@@ -445,7 +446,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, const double *Rm, double
   if (bad) {
     // CGS2 in sorted order; a column that loses its norm is replaced by the
     // first unit vector that survives the projection
-    for (int i = 0; i < l; ++i) {
+    for (int i = 0; i < kk; ++i) {
       int cand = -1;
       for (;;) {
         for (int pass = 0; pass < 2; ++pass) {
@@ -697,8 +698,11 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
     SPG_CHECK_LAUNCH();
     return;
   }
-  const int mb = kQrLds / n;                    // >= n since n <= kMaxSketch
-  const int p = (m + mb - 1) / mb;
+  // fewest blocks that fit in LDS, with rows split evenly between them (the
+  // cost of a block grows with its rows)
+  const int mb_max = kQrLds / n;                // >= n since n <= kMaxSketch
+  const int p = (m + mb_max - 1) / mb_max;
+  const int mb = std::max((m + p - 1) / p, n);
   if ((long)p * n * n <= kQrLds) {
     // one level of TSQR: block QRs, QR of the stacked R factors, Q = diag(Q_b) Q_s
     double *Q1 = work;                          // m x n row-major
@@ -745,7 +749,7 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
   SPG_CHECK_LAUNCH();
 }
 
-void jacobi_svd_f64(int l, const double *Rm, double *V, double *sig, hipStream_t s) {
+void jacobi_svd_f64(int l, int kk, const double *Rm, double *V, double *sig, hipStream_t s) {
   KTimer kt_("jacobi_svd_f64", s);
   if (l <= 0) return;
   if (l > kMaxSketch) {
@@ -755,7 +759,11 @@ void jacobi_svd_f64(int l, const double *Rm, double *V, double *sig, hipStream_t
   SPG_BC(Rm);
   SPG_BC(V);
   SPG_BC(sig);
-  hipLaunchKernelGGL(k_jacobi, dim3(1, g_bc.n), dim3(1024), 0, s, l, Rm, V, sig, g_bc.ist);
+  if (kk < 1 || kk > l) {
+    set_error("jacobi_svd_f64: kk must be in 1..l");
+    throw Fail{SPG_ERR_INVALID};
+  }
+  hipLaunchKernelGGL(k_jacobi, dim3(1, g_bc.n), dim3(1024), 0, s, l, kk, Rm, V, sig, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 

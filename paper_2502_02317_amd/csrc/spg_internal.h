@@ -118,7 +118,9 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
 // One-sided Jacobi SVD of an l x l matrix (row-major, l <= kMaxSketch): writes
 // the right singular vectors as columns of V (row-major l x l) sorted by
 // singular value, descending (ties by index), and the singular values to sig.
-void jacobi_svd_f64(int l, const double *Rm, double *V, double *sig, hipStream_t s);
+// The leading kk columns are made orthonormal to 1e-13 (the others are the
+// normalised Jacobi columns and may not be, when they sit at rounding level).
+void jacobi_svd_f64(int l, int kk, const double *Rm, double *V, double *sig, hipStream_t s);
 
 // Sketch matrix of the truncated SVD: Om[i*l + j] = 2 u(SplitMix64(seed, i*ld + j)) - 1.
 void fill_sketch(int n, int l, double *Om, hipStream_t s);
