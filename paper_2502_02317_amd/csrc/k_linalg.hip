@@ -671,6 +671,14 @@ size_t qr_work_doubles(int m, int n) {
   return 3 * (size_t)m * n + 2 * (size_t)kQrLds + 2 * (size_t)n * n + n + 64;
 }
 
+// One LDS panel factorisation launch.
+static void qr_panel(dim3 grid, int m, int n, int mb, const double *X, long xr, long xc,
+                     double *Q, long qr, long qc, double *R, int want_q, long ist, hipStream_t s) {
+  hipLaunchKernelGGL(k_qr_lds, grid, dim3(1024), 0, s, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q,
+                     ist);
+  SPG_CHECK_LAUNCH();
+}
+
 void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr, long qc,
             double *R, double *work, hipStream_t s) {
   if (m <= 0 || n <= 0) return;
@@ -693,9 +701,7 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
     // one LDS-resident block; R straight to the caller (or to scratch)
     double *Rd = R ? R : work;
     KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
-    hipLaunchKernelGGL(k_qr_lds, dim3(1, nI), dim3(1024), 0, s, m, n, m, X, xr, xc, Q, qr, qc,
-                       Rd, want_q, ist);
-    SPG_CHECK_LAUNCH();
+    qr_panel(dim3(1, nI), m, n, m, X, xr, xc, Q, qr, qc, Rd, want_q, ist, s);
     return;
   }
   // fewest blocks that fit in LDS, with rows split evenly between them (the
@@ -711,15 +717,12 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
     double *Rt = Qs + (long)p * n * n;          // n x n
     {
       KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
-      hipLaunchKernelGGL(k_qr_lds, dim3(p, nI), dim3(1024), 0, s, m, n, mb, X, xr, xc, Q1,
-                         (long)n, 1L, S, want_q, ist);
-      SPG_CHECK_LAUNCH();
+      qr_panel(dim3(p, nI), m, n, mb, X, xr, xc, Q1, (long)n, 1L, S, want_q, ist, s);
     }
     {
       KTimer kt_("qr_f64", s, qr_flops(p * n, n, want_q));
-      hipLaunchKernelGGL(k_qr_lds, dim3(1, nI), dim3(1024), 0, s, p * n, n, p * n, S, (long)n,
-                         1L, Qs, (long)n, 1L, R ? R : Rt, want_q, ist);
-      SPG_CHECK_LAUNCH();
+      qr_panel(dim3(1, nI), p * n, n, p * n, S, (long)n, 1L, Qs, (long)n, 1L, R ? R : Rt, want_q,
+               ist, s);
     }
     if (!want_q) return;
     const int full = m / mb, tail = m - full * mb;
