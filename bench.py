@@ -195,6 +195,51 @@ def batching_leg(spg, torch, stream):
             "evals_per_s_one_by_one": ev / t_one, "evals_per_s_batched": ev / t_batch}
 
 
+def transforms_leg(spg, torch, inst, wl, M, stream):
+    """The bench instance on all eight orientations of its grid: one batch
+    (a single shape class) against eight single runs; best of eight and the
+    spread of the eight best energies on the original lattice."""
+    import numpy as np
+    from workloads.transforms import lattice_transform
+    from oracle.energy import potts_energy
+    ts = [lattice_transform(inst, k) for k in range(8)]
+    peps = [spg.build_peps(t, stream) for t, _ in ts]
+    dev = torch.device("cuda:0")
+    N = inst.rows * inst.cols
+    s_ = torch.zeros((M, N), dtype=torch.int32, device=dev)
+    e_ = torch.zeros(M, dtype=torch.float64, device=dev)
+    l_ = torch.zeros(M, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for p in peps:
+        env, _ = spg.boundary_mps(p, wl["chi"], num_sweeps=wl["num_sweeps"], precision="fp64",
+                                  oversample=wl["oversample"], power_iters=wl["power_iters"],
+                                  stream=stream, want_logZ=False)
+        spg.branch_and_bound(env, M, s_, e_, l_, stream=stream)
+        del env
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - a
+    b = spg.Batch(peps, chi=wl["chi"], max_states=M, num_sweeps=wl["num_sweeps"],
+                  oversample=wl["oversample"], power_iters=wl["power_iters"], n_streams=2,
+                  classes=True)
+    b.run(use_graph=False, stream=stream)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    b.run(use_graph=False, stream=stream)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - a
+    bests = []
+    for k, (t, back) in enumerate(ts):
+        st, en, _, _ = b.result(k)
+        x_old = np.empty_like(st)
+        x_old[:, back] = st
+        # energies recomputed on the original lattice
+        bests.append(float(potts_energy(inst, x_old[:1])[0]))
+    return {"orientations": 8, "units": b.units()[0], "one_by_one_s": t_one,
+            "batched_s": t_batch, "speedup": t_one / t_batch, "best_of_8": min(bests),
+            "best_energies": bests, "spread": max(bests) - min(bests)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,7 +411,8 @@ def main():
     if not args.no_forms:
         out["forms"] = {"learned_proposal": proposal_leg(spg, torch, inst, wl, M, st, en, lp,
                                                          stream),
-                        "batching": batching_leg(spg, torch, stream)}
+                        "batching": batching_leg(spg, torch, stream),
+                        "lattice_transforms": transforms_leg(spg, torch, inst, wl, M, stream)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, wl)
     print(json.dumps(out), flush=True)
