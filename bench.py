@@ -40,7 +40,7 @@ FLOP_CLASSES = {"gemm_f64", "qr_f64", "right_env", "marginals", "beam_update"}
 BYTE_CLASSES = {"normalize_box", "select_topm"}
 
 
-CLASS_KERNEL = {"gemm_f64": "k_gemm", "qr_f64": "k_qr_lds", "jacobi_svd_f64": "k_jacobi",
+CLASS_KERNEL = {"gemm_f64": "k_gemm<64>", "qr_f64": "k_qr_lds", "jacobi_svd_f64": "k_jacobi",
                 "normalize_box": "k_box_scale", "right_env": "k_right_env",
                 "marginals": "k_marginals", "select_topm": "k_select",
                 "beam_update": "k_beam_update", "final_sort": "k_final_sort"}
@@ -56,6 +56,7 @@ def kernel_source_sha(name):
     """(file, sha256 of the kernel's own source text) for a __global__ function."""
     import hashlib
     import re
+    name = name.split("<")[0]            # a template's instances share its source
     for f in KERNEL_SOURCES:
         path = os.path.join(ROOT, "paper_2502_02317_amd", "csrc", f)
         src = open(path).read()
@@ -248,6 +249,9 @@ def main():
     ap.add_argument("--precision", default="fp32",
                     help="search-contraction precision of the timed (mixed) path")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--verbose", action="store_true", help="progress lines on stderr")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="skip the pass with per-launch HIP events (no roofline; for counter runs)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batching and learned-proposal legs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -263,6 +267,10 @@ def main():
     import torch
     from paper_2502_02317_amd import spg
     from workloads import config_instance
+
+    def say(msg):
+        if args.verbose:
+            print(f"bench: {msg}", file=sys.stderr, flush=True)
 
     wl = WORKLOAD
     inst = config_instance(wl["name"], wl["seed"])
@@ -296,8 +304,11 @@ def main():
         spg.profile_enable(profile)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for i in range(args.steps):
             step(prec)
+            if args.verbose:
+                torch.cuda.synchronize()
+                say(f"{prec} step {i + 1}/{args.steps}")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         spg.profile_enable(False)
@@ -310,8 +321,13 @@ def main():
     # timed without per-kernel events; then the kernel classes from a separate
     # profiled pass (events on each launch's stream) over the same number of steps
     ms = timed(args.precision, False)[0]
+    say(f"timed {args.precision}: {ms:.1f} ms/step")
     ms64 = ms if args.precision == "fp64" else timed("fp64", False)[0]
-    _, prof = timed(args.precision, True)
+    if args.no_kernel_timing:
+        prof = {k: (0, 0.0, 0.0) for k in spg.KERNEL_CLASSES}
+    else:
+        _, prof = timed(args.precision, True)
+        say("profiled pass done")
     best_E = float(en[0])
 
     # search-only and boundary-MPS-only split (untimed, same work)
@@ -329,6 +345,7 @@ def main():
 
     # dlogP: teacher-forced on the FP64 path's beam (the oracle's search on the
     # GPU's FP64 boundary MPS gives that beam), states with p64 >= 1e-4 max
+    say("split done")
     dlogp = None
     dlogp_info = None
     if args.precision != "fp64":
@@ -370,8 +387,12 @@ def main():
                       "floor": "p64 >= 1e-4 max at the parent"}
 
     dom = max(prof, key=lambda k: prof[k][1])
+    if prof[dom][1] == 0.0:
+        dom = "qr_f64"
     cnt, tms, work = prof[dom]
-    if dom in FLOP_CLASSES:
+    if tms <= 0.0:
+        roof = {"bound": None, "achieved": None, "peak": None, "unit": None}
+    elif dom in FLOP_CLASSES:
         achieved = work / (tms * 1e-3) / 1e12
         # the QR kernels run on the FP64 vector ALU; the GEMM-shaped
         # contractions are MFMA candidates (FP64 peak: the boundary MPS is FP64)
