@@ -17,7 +17,16 @@ configurations.  Adopted reading:
   with ``cut_off_prob`` > 0, children below cut_off_prob times the best child
   of the step get score -inf (they sort last and count as discarded);
 * output: the final beam, energies recomputed by Eq. (1), sorted by energy
-  ascending (ties keep beam order).
+  ascending (ties keep beam order);
+* merging branches (optional; the paper's merge of branches, Sec. 3.1, whose
+  exact rule it leaves open): after site k, the sites still coupled to the
+  unexplored ones are among the last cols + 1 sites of the order (the
+  frontier); two partial configurations with the same frontier have the same
+  conditional future, and the one with the lower energy of its fixed part
+  completes to the lower total energy, so among the children of a step that
+  share a frontier only the one with the lowest energy (ties: lowest id
+  b d + s) keeps its score, the others get -inf.  Merging comes before the
+  cut-off and the selection.
 
 The vectors L and R only need a positive scale (it cancels in p(s | b)), so
 they are kept max-normalised without log-scales.
@@ -102,7 +111,34 @@ def right_envs(A_row, g):
     return R
 
 
-def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None):
+def frontier_width(inst, k: int) -> int:
+    """Sites k - w + 1 .. k form the frontier after site k (row-major order)."""
+    return min(k + 1, inst.cols + 1)
+
+
+def merge_branches(cand, cfg, energy, dE, k, w):
+    """Keep, per frontier (states of sites k-w+1..k-1 and the child's state),
+    only the finite child with the lowest energy (ties: lowest id)."""
+    B, d = cand.shape
+    out = np.full_like(cand, -np.inf)
+    best = {}
+    for b in range(B):
+        prefix = tuple(cfg[b, k - w + 1: k].tolist())
+        for s in range(d):
+            if not np.isfinite(cand[b, s]):
+                continue
+            key = prefix + (s,)
+            e = energy[b] + dE[b, s]
+            idx = b * d + s
+            if key not in best or (e, idx) < best[key]:
+                best[key] = (e, idx)
+    for e, idx in best.values():
+        b, s = divmod(idx, d)
+        out[b, s] = cand[b, s]
+    return out
+
+
+def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None, merge=False):
     """Run the search with boundary MPS tensors A[r][c].  Returns dict with
     'states' [n][N], 'energies', 'scores' (sorted by energy) and 'beam_energies'
     (the final beam in beam order).  ``trace`` (optional list) receives per-site
@@ -123,12 +159,15 @@ def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None):
             q = marginals(A[r][c], g_anc[anc, c], L, R[c + 1][anc])
             lp = log_conditionals(q)
             cand = score[:, None] + lp
+            dE = delta_energy(inst, cfg, r, c)
+            if merge:
+                k = r * C + c
+                cand = merge_branches(cand, cfg, energy, dE, k, frontier_width(inst, k))
             if cut_off_prob > 0:
                 best = cand.max()
                 cand = np.where(cand >= best + np.log(cut_off_prob), cand, -np.inf)
             if trace is not None:
                 trace.append({"site": r * C + c, "cfg": cfg.copy(), "logp": lp.copy()})
-            dE = delta_energy(inst, cfg, r, c)
             keep = select_top(cand, M)
             b, s = np.divmod(keep, d)
             cfg = cfg[b].copy()

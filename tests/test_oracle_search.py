@@ -74,3 +74,50 @@ def test_cutoff_marks_discarded():
     fin = np.isfinite(cut["beam_scores"])
     # every surviving state is within the cut of the best at the last step
     assert np.all(cut["beam_scores"][fin] >= cut["beam_scores"][0] + np.log(1e-2) - 1e-12)
+
+
+# ---- merging branches ---------------------------------------------------------
+
+import itertools
+
+import pytest as _pytest
+
+from oracle.search import beam_search as _beam, frontier_width
+
+
+@_pytest.mark.parametrize("R,C,d,kings,seed", [(3, 3, 2, True, 1), (3, 4, 2, False, 2),
+                                               (2, 4, 3, True, 3), (4, 3, 2, True, 4)])
+def test_merged_search_with_a_frontier_sized_beam_is_exact(R, C, d, kings, seed):
+    """With merging, at most d^(cols+1) children survive a step (one per
+    frontier); a beam that large keeps them all, so the search is exact
+    dynamic programming over frontiers and must reach the brute-force ground
+    state, with any exact boundary MPS."""
+    from workloads import random_potts
+    from oracle.exact import brute_force
+    from oracle.bmps import boundary_mps
+    inst = random_potts(R, C, d, kings, seed=seed, beta=0.9)
+    ref = brute_force(inst)
+    A = boundary_mps(inst, d ** C)["A"]
+    M = d ** (C + 1)
+    res = _beam(inst, A, M, merge=True)
+    assert abs(res["energies"][0] - ref["E_min"]) < 1e-9
+    # one survivor per frontier in the final beam
+    fin = res["beam_states"][np.isfinite(res["beam_scores"])]
+    w = frontier_width(inst, R * C - 1)
+    keys = {tuple(x[-w:]) for x in fin.tolist()}
+    assert len(keys) == len(fin)
+
+
+def test_merge_keeps_the_lowest_energy_child_per_frontier():
+    from oracle.search import merge_branches
+    cand = np.array([[0.0, -1.0], [-0.5, -np.inf], [-2.0, -0.1]])
+    cfg = np.array([[1, 0, 0], [1, 0, 0], [0, 0, 0]])
+    energy = np.array([5.0, 4.0, 1.0])
+    dE = np.zeros((3, 2))
+    out = merge_branches(cand, cfg, energy, dE, k=1, w=2)     # frontier = (cfg[:,0], s)
+    # rows 0 and 1 share frontier (1, s): row 1 has the lower energy for s = 0;
+    # s = 1 of row 1 is -inf, so row 0 keeps s = 1; row 2 is alone with frontier (0, s)
+    assert np.array_equal(np.isfinite(out), [[False, True], [True, False], [True, True]])
+    energy[1] = 5.0                                            # tie: lowest id wins
+    out = merge_branches(cand, cfg, energy, dE, k=1, w=2)
+    assert np.isfinite(out[0, 0]) and not np.isfinite(out[1, 0])
