@@ -241,6 +241,26 @@ def transforms_leg(spg, torch, inst, wl, M, stream):
             "best_energies": bests, "spread": max(bests) - min(bests)}
 
 
+def merge_leg(spg, torch, inst, wl, M, st, en, lp, stream):
+    """Merging branches with equal frontiers: the FP64 search on the same
+    boundary MPS with and without it (search-only time, best energy)."""
+    peps = spg.build_peps(inst, stream)
+    env, _ = spg.boundary_mps(peps, wl["chi"], num_sweeps=wl["num_sweeps"], precision="fp64",
+                              oversample=wl["oversample"], power_iters=wl["power_iters"],
+                              stream=stream, want_logZ=False)
+    res = {}
+    for label, merge in (("plain", False), ("merged", True)):
+        spg.branch_and_bound(env, M, st, en, lp, stream=stream, merge_branches=merge)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        n = spg.branch_and_bound(env, M, st, en, lp, stream=stream, merge_branches=merge)
+        torch.cuda.synchronize()
+        res[f"search_ms_{label}"] = (time.perf_counter() - a) * 1e3
+        res[f"best_energy_{label}"] = float(en[0])
+        res[f"n_states_{label}"] = n
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -432,8 +452,11 @@ def main():
     if not args.no_forms:
         out["forms"] = {"learned_proposal": proposal_leg(spg, torch, inst, wl, M, st, en, lp,
                                                          stream),
-                        "batching": batching_leg(spg, torch, stream),
-                        "lattice_transforms": transforms_leg(spg, torch, inst, wl, M, stream)}
+                        "batching": batching_leg(spg, torch, stream)}
+        out["extensions"] = {"lattice_transforms": transforms_leg(spg, torch, inst, wl, M,
+                                                                  stream),
+                             "merge_branches": merge_leg(spg, torch, inst, wl, M, st, en, lp,
+                                                         stream)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, wl)
     print(json.dumps(out), flush=True)

@@ -92,6 +92,11 @@ typedef struct {
                         /* the learned proposal ranks children first (see below)   */
   double kappa;         /* with a proposal: about kappa * max_states children are  */
                         /* evaluated exactly per step before the guard (> 0)       */
+  int32_t merge_branches;  /* != 0: children of a step whose frontiers (states of  */
+                        /* the last cols + 1 sites, own state included) are equal */
+                        /* are merged: only the one with the lowest energy of its  */
+                        /* fixed sites (ties: lowest b*d + s) keeps its score      */
+                        /* (Sec. 3.1 merge of branches); not with a proposal       */
 } spg_search_params;
 
 /* Build the PEPS of an instance (Sec. 2, Fig. 1(c)): copies the energy tables

@@ -771,6 +771,25 @@ static void ensure_guide(spg_env *env, int M) {
   env->smax.ensure(8);
 }
 
+static MergeWork merge_work(spg_env *env, int M) {
+  const int d = env->peps->d;
+  int T = 1;
+  while (T < 2 * M * d) T <<= 1;
+  env->mkey.ensure((size_t)T * 8);
+  env->me.ensure((size_t)T * 8);
+  env->mid.ensure((size_t)T * 4);
+  env->mslot.ensure((size_t)M * d * 4);
+  env->mekey.ensure((size_t)M * d * 8);
+  MergeWork mw;
+  mw.capacity = T;
+  mw.tkey = env->mkey.as<unsigned long long>();
+  mw.te = env->me.as<unsigned long long>();
+  mw.tid = env->mid.as<int32_t>();
+  mw.slot = env->mslot.as<int32_t>();
+  mw.ekey = env->mekey.as<unsigned long long>();
+  return mw;
+}
+
 static GuideWork guide_of(spg_env *env) {
   GuideWork g;
   g.bins = env->gbins.as<uint16_t>();
@@ -814,6 +833,8 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
     site_features(t, A, env->sf.as<float>(), env->rscr.as<double>(), s);
   }
   const int K = guided ? (int)std::min<double>(std::ceil(prm->kappa * M), 2147483647.0) : 0;
+  MergeWork mw;
+  if (prm->merge_branches) mw = merge_work(env, M);
   int cur = 0;
   long B = 1;
   fill_zero(env->score[0].as<double>(), 1, s);
@@ -899,6 +920,9 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
                     dm[c], dm[c + 1], s);
           to_float(B * d, env->tmp.as<double>(), td->targets.as<float>() + td->off[k], s);
         }
+        if (prm->merge_branches)
+          merge_branches(t, r, c, (int)B, cfg, N, env->energy[cur].as<double>(),
+                         env->cand.as<double>(), mw, s);
         if (prm->cut_off_prob > 0.0)
           apply_cutoff((int)(B * d), log_cut, env->cand.as<double>(), s);
         select_topm((int)(B * d), M, env->cand.as<double>(), env->sel.as<int32_t>(),
@@ -949,6 +973,8 @@ int spg_branch_and_bound(const spg_env_t *cenv, const spg_search_params *prm, in
   if (!(prm->cut_off_prob >= 0.0) || prm->cut_off_prob >= 1.0)
     return fail(SPG_ERR_INVALID, "spg_branch_and_bound: cut_off_prob must be in [0, 1)");
   spg_env *env = const_cast<spg_env *>(cenv);
+  if (prm->proposal && prm->merge_branches)
+    return fail(SPG_ERR_UNSUPPORTED, "spg_branch_and_bound: merging with a proposal");
   if (prm->proposal) {
     if (!(prm->kappa > 0.0))
       return fail(SPG_ERR_INVALID, "spg_branch_and_bound: kappa must be > 0 with a proposal");

@@ -10,6 +10,7 @@
 //   q(b,s) = g^b_c(s) * L^b A_{r,c}[:, s, :] R^{a(b)}_{c+1},
 // g^b_c(s) = the Boltzmann weights of the couplings between s and the fixed
 // row r-1 (V from (r-1,c), D from (r-1,c-1), A from (r-1,c+1)).
+#include <algorithm>
 #include <cfloat>
 #include <climits>
 
@@ -430,6 +431,82 @@ __global__ __launch_bounds__(256) void k_advance_L(SearchTabs t, int r, int c, i
   }
 }
 
+// ---- merging branches ------------------------------------------------------
+// Children of one step that share a frontier (the states of the last w sites
+// of the order, the child's own included) compete; the one with the lowest
+// energy of its fixed part (ties: lowest id b d + s) keeps its score, the
+// others get -inf.  The frontier is packed exactly into 63 bits when
+// w * bits <= 63 (bits per state), else hashed.  An open-addressing table
+// (power-of-two size, at least twice the children) collects per frontier the
+// least energy key and then the least id among children with that energy.
+constexpr unsigned long long kEmpty = ~0ull;
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_merge_clear(int T, unsigned long long *tkey, unsigned long long *te,
+                              int32_t *tid) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= T) return;
+  tkey[e] = kEmpty;
+  te[e] = kEmpty;
+  tid[e] = INT_MAX;
+}
+
+__global__ void k_merge_insert(SearchTabs t, int r, int c, int n_beam, const uint8_t *cfg, int N,
+                               const double *energy, const double *cand, int w, int bits,
+                               int T, unsigned long long *tkey, unsigned long long *te,
+                               int32_t *slot_of, unsigned long long *ekey_of) {
+  const int d = t.d;
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)n_beam * d) return;
+  const int b = (int)(e / d), s = (int)(e % d);
+  const double sc = cand[e];
+  slot_of[e] = -1;
+  if (!(sc > -INFINITY)) return;
+  const uint8_t *cb = cfg + (long)b * N;
+  const int k = r * t.cols + c;
+  unsigned long long key;
+  if (w * bits <= 63) {
+    key = (unsigned long long)s;
+    for (int i = 1; i < w; ++i) key |= (unsigned long long)cb[k - i] << (bits * i);
+  } else {
+    key = mix64(0x9E3779B97F4A7C15ull + (unsigned long long)s);
+    for (int i = 1; i < w; ++i) key = mix64(key + cb[k - i] + 0x9E3779B97F4A7C15ull * i);
+    key &= 0x7FFFFFFFFFFFFFFFull;
+  }
+  const unsigned long long ek = asc_key(energy[b] + delta_energy(t, r, c, cb, s));
+  unsigned h = (unsigned)mix64(key) & (unsigned)(T - 1);
+  for (int probe = 0; probe < T; ++probe) {
+    const unsigned long long cur = atomicCAS(&tkey[h], kEmpty, key);
+    if (cur == kEmpty || cur == key) {
+      atomicMin(&te[h], ek);
+      slot_of[e] = (int)h;
+      ekey_of[e] = ek;
+      return;
+    }
+    h = (h + 1) & (unsigned)(T - 1);
+  }
+}
+
+__global__ void k_merge_tie(long n, const int32_t *slot_of, const unsigned long long *ekey_of,
+                            const unsigned long long *te, int32_t *tid) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int h = slot_of[e];
+  if (h >= 0 && ekey_of[e] == te[h]) atomicMin(&tid[h], (int32_t)e);
+}
+
+__global__ void k_merge_apply(long n, const int32_t *slot_of, const int32_t *tid, double *cand) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int h = slot_of[e];
+  if (h >= 0 && tid[h] != (int32_t)e) cand[e] = -INFINITY;
+}
+
 }  // namespace
 
 void right_env_col(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *cfg, int N,
@@ -565,6 +642,34 @@ void advance_L(const SearchTabs &t, int r, int c, int n, const uint8_t *cfg, int
   SPG_BC(L);
   bc_check_tabs(t);
   hipLaunchKernelGGL(k_advance_L, dim3(nblk(n, kWaves), g_bc.n), dim3(256), 0, s, t, r, c, n, cfg, N, A_rc, L, g_bc.ist);
+  SPG_CHECK_LAUNCH();
+}
+
+void merge_branches(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
+                    const double *energy, double *cand, MergeWork &mw, hipStream_t s) {
+  bc_single("merge_branches");
+  KTimer kt_("merge_branches", s, 24.0 * n_beam * t.d);
+  const long n = (long)n_beam * t.d;
+  if (n <= 0) return;
+  int T = 1;
+  while (T < 2 * n) T <<= 1;
+  if (T > mw.capacity) {
+    set_error("merge_branches: table too small");
+    throw Fail{SPG_ERR_INVALID};
+  }
+  const int k = r * t.cols + c;
+  const int w = std::min(k + 1, t.cols + 1);
+  int bits = 1;
+  while ((1 << bits) < t.d) ++bits;
+  hipLaunchKernelGGL(k_merge_clear, dim3(nblk(T, 256)), dim3(256), 0, s, T, mw.tkey, mw.te, mw.tid);
+  SPG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_merge_insert, dim3(nblk(n, 256)), dim3(256), 0, s, t, r, c, n_beam, cfg, N,
+                     energy, cand, w, bits, T, mw.tkey, mw.te, mw.slot, mw.ekey);
+  SPG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_merge_tie, dim3(nblk(n, 256)), dim3(256), 0, s, n, mw.slot, mw.ekey, mw.te,
+                     mw.tid);
+  SPG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_merge_apply, dim3(nblk(n, 256)), dim3(256), 0, s, n, mw.slot, mw.tid, cand);
   SPG_CHECK_LAUNCH();
 }
 

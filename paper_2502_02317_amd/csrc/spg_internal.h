@@ -207,6 +207,17 @@ void beam_update(const SearchTabs &t, int r, int c, int n_new, const int32_t *se
                  double *energy_o, double *score_o, double *L_o, int32_t *anc_o, int cl,
                  int cr, hipStream_t s, const double *sel_score = nullptr);
 void beam_reset_row(int n, int chi, double *L, int32_t *anc, hipStream_t s);
+// Merging of branches with equal frontiers: workspace (table of `capacity`
+// slots, capacity a power of two >= 2 n_beam d; per-child slot and energy key).
+struct MergeWork {
+  int capacity = 0;
+  unsigned long long *tkey = nullptr, *te = nullptr, *ekey = nullptr;
+  int32_t *tid = nullptr, *slot = nullptr;
+};
+// Children of equal frontier: all but the lowest-energy one (ties: lowest id)
+// get cand = -inf.
+void merge_branches(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
+                    const double *energy, double *cand, MergeWork &mw, hipStream_t s);
 void final_sort(const SearchTabs &t, int n, int N, const uint8_t *cfg, const double *score,
                 int32_t *states_out, double *energies_out, double *logp_out, double *e_work,
                 int32_t *perm_work, int32_t *n_valid, hipStream_t s);
@@ -301,6 +312,7 @@ struct spg_env {
   // features, step workspace and counters
   spg::DevBuf Rsc, sf, rscr, gbins, ghist, gint, glkey, glid, gbound, gtau, goff, gcnt, gstats,
       selscore, smax;
+  spg::DevBuf mkey, me, mid, mslot, mekey;   // merging branches
   int64_t last_stats[3] = {0, 0, 0};
 };
 

@@ -42,7 +42,8 @@ class MpsParams(C.Structure):
 
 class SearchParams(C.Structure):
     _fields_ = [("max_states", C.c_int32), ("cut_off_prob", C.c_double),
-                ("proposal", C.c_void_p), ("kappa", C.c_double)]
+                ("proposal", C.c_void_p), ("kappa", C.c_double),
+                ("merge_branches", C.c_int32)]
 
 
 class TrainParams(C.Structure):
@@ -69,7 +70,7 @@ EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_branch_an
            "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning", "spg_batch_info"]
 KERNEL_CLASSES = ["gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box", "right_env",
                   "marginals", "select_topm", "beam_update", "final_sort", "propose",
-                  "guided_eval", "mlp_grad"]
+                  "guided_eval", "mlp_grad", "merge_branches"]
 
 _lib = None
 
@@ -213,12 +214,13 @@ def marginals(env: Env, site: int, beam_cfg, out, stream=None):
 
 def branch_and_bound(env: Env, max_states: int, states_out, energies_out, logp_out,
                      cut_off_prob: float = 0.0, stream=None, proposal=None,
-                     kappa: float = 2.0) -> int:
+                     kappa: float = 2.0, merge_branches: bool = False) -> int:
     """spg_branch_and_bound into device tensors; returns n_out.  With a
     Proposal the guarded steps run (kappa * max_states exact children per step
     before the guard)."""
     prm = SearchParams(int(max_states), float(cut_off_prob),
-                       proposal.handle if proposal is not None else None, float(kappa))
+                       proposal.handle if proposal is not None else None, float(kappa),
+                       1 if merge_branches else 0)
     n = C.c_int32(0)
     _check(load().spg_branch_and_bound(env.handle, C.byref(prm), _ptr(states_out),
                                        _ptr(energies_out), _ptr(logp_out), C.byref(n),
