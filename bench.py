@@ -402,6 +402,8 @@ def main():
             n_unres64 += int((keep & ~(g64 * (ks + _kz[:, None]) <= 1e-3)).sum())
             if fine.any():
                 dlogp = max(dlogp, float(np.abs(rlo[fine] - r64[fine]).max()))
+        if n_keep == n_unres:
+            dlogp = None                  # no entry resolved: nothing measured
         dlogp_info = {"entries": n_keep, "not_resolved_to_1e-3_at_this_precision": n_unres,
                       "not_resolved_to_1e-3_even_in_fp64": n_unres64,
                       "floor": "p64 >= 1e-4 max at the parent"}

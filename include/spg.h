@@ -303,7 +303,8 @@ int spg_env_import(const spg_peps_t *peps, int32_t chi, const int32_t *bond_dims
 
 /* Opt-in kernel timing: while enabled, every launch of a timed kernel class
  * ("gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box", "right_env",
- * "marginals", "select_topm", "beam_update", "final_sort") is bracketed by HIP
+ * "marginals", "select_topm", "beam_update", "final_sort", "propose",
+ * "guided_eval", "mlp_grad", "merge_branches") is bracketed by HIP
  * events recorded on the stream it is launched on.  spg_profile_query
  * synchronises on those events and returns, since the last reset, the number
  * of launches, their summed duration in milliseconds and (total_work, may be
