@@ -335,15 +335,286 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
   }
 }
 
+// ---------------------------------------------------------------- QR (registers)
+// Householder QR of one panel of at most 64*RPL rows and 16*CPW columns in one
+// workgroup of 16 wavefronts, held in registers: wave w owns columns
+// [w*CPW, (w+1)*CPW) and lane l rows l + 64 t (t < RPL; zero beyond m).
+//
+// Factorisation, step j: the owner of column j forms its reflector
+// H_j = I - tau_j v_j v_j^T (v_j = 1 at row j, zero above; R[j][j] = beta)
+// from its registers and publishes v_j to an LDS slot; after one barrier
+// every wave applies H_j to its own columns k > j (a wave-wide dot product
+// per column, then an axpy).  Slot j mod kRegSlots is rewritten only after
+// kRegSlots further barriers, so one barrier per step suffices.
+//
+// Q = H_0 H_1 ... H_{n-1} [I; 0] is formed in place as LAPACK's dorg2r does
+// (backwards; column j turns into H_j e_j once H_j has been applied to the
+// columns right of it).  The reflectors never change, so they are published
+// kRegSlots at a time and each wave then runs through the chunk on its own
+// columns without further barriers.
+//
+// HBM traffic goes through LDS 64 rows at a time, in whichever order is
+// contiguous for the strides given, so loads and stores are coalesced for
+// row- and column-major panels alike.  The panel is scaled by a power of two
+// (largest entry in [1/2, 1)) before the factorisation and R scaled back, so
+// squared norms neither underflow nor overflow; Q does not depend on it.
+constexpr int kRegSlots = 16;
+constexpr int kStageLd = 65;                 // padded row count of the staging tile
+
+template <int RPL, int CPW>
+struct QrRegLds {
+  static constexpr int kSlots = kRegSlots * 64 * RPL;
+  static constexpr int kStage = 16 * CPW * kStageLd;
+  static constexpr int kBuf = kSlots > kStage ? kSlots : kStage;
+};
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+template <int RPL, int CPW>
+__global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, long xr, long xc,
+                                                double *Qo, long qr, long qc, double *Rs,
+                                                int want_q, long ist) {
+  SPG_INST(X);
+  SPG_INST(Qo);
+  SPG_INST(Rs);
+  __shared__ double buf[QrRegLds<RPL, CPW>::kBuf];
+  __shared__ double taus[16 * CPW];
+  __shared__ double red[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int c0 = w * CPW;
+  double a[CPW][RPL];
+
+  // ---- load, 64 rows per pass through the staging tile buf[j*kStageLd + r]
+  const bool in_cols = (xc == 1) || (xr != 1 && (xc < 0 ? -xc : xc) < (xr < 0 ? -xr : xr));
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r0 = 64 * t;
+    if (r0 < m) {
+      for (int e = tid; e < 64 * n; e += 1024) {
+        int r, j;
+        if (in_cols) { r = e / n; j = e - r * n; }
+        else { j = e >> 6; r = e & 63; }
+        const int i = r0 + r;
+        buf[j * kStageLd + r] = (i < m) ? X[(long)i * xr + (long)j * xc] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < CPW; ++s)
+      a[s][t] = (r0 < m && c0 + s < n) ? buf[(c0 + s) * kStageLd + lane] : 0.0;
+    __syncthreads();
+  }
+
+  // ---- scale by a power of two so that the largest entry lies in [1/2, 1):
+  // exact, and squared norms stay clear of underflow and overflow
+  {
+    double mx = 0.0;
+#pragma unroll
+    for (int s = 0; s < CPW; ++s)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) mx = fmax(mx, fabs(a[s][t]));
+    mx = wave_max_nonneg(mx);
+    if (lane == 0) red[w] = mx;
+  }
+  __syncthreads();
+  int ex = 0;
+  {
+    double mx = 0.0;
+    for (int v = 0; v < 16; ++v) mx = fmax(mx, red[v]);
+    if (mx > 0.0 && mx <= 1.7e308) (void)frexp(mx, &ex);
+  }
+#pragma unroll
+  for (int s = 0; s < CPW; ++s)
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) a[s][t] = ldexp(a[s][t], -ex);
+
+  // ---- factorisation
+  for (int j = 0; j < n; ++j) {
+    double *vj = buf + (j % kRegSlots) * (64 * RPL);
+    if (w == j / CPW) {
+      const int os = j - c0;
+#pragma unroll
+      for (int s = 0; s < CPW; ++s) {
+        if (s != os) continue;
+        double sg = 0.0, at = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int i = lane + 64 * t;
+          const double x = a[s][t];
+          if (i > j) sg = fma(x, x, sg);
+          if (t == (j >> 6)) at = x;
+        }
+        sg = wave_sum(sg);
+        const double al = read_lane(at, j & 63);
+        double tj = 0.0, sc = 0.0, beta = al;
+        if (sg != 0.0) {
+          const double nrm = sqrt(al * al + sg);
+          beta = (al >= 0.0) ? -nrm : nrm;
+          tj = (beta - al) / beta;
+          sc = 1.0 / (al - beta);
+        }
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int i = lane + 64 * t;
+          const double v = (i < j) ? 0.0 : (i == j) ? 1.0 : a[s][t] * sc;
+          vj[i] = v;
+          if (i == j) a[s][t] = beta;
+          else if (i > j) a[s][t] = v;
+        }
+        if (lane == 0) taus[j] = tj;
+      }
+    }
+    __syncthreads();
+    const double tj = taus[j];
+    if (tj != 0.0 && max(c0, j + 1) < min(c0 + CPW, n)) {      // some own column k > j
+      double v[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) v[t] = vj[lane + 64 * t];
+      double dot[CPW];
+#pragma unroll
+      for (int s = 0; s < CPW; ++s) {
+        dot[s] = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) dot[s] = fma(v[t], a[s][t], dot[s]);
+      }
+#pragma unroll
+      for (int s = 0; s < CPW; ++s)
+        if (c0 + s > j && c0 + s < n) dot[s] = wave_sum(dot[s]);
+#pragma unroll
+      for (int s = 0; s < CPW; ++s) {
+        if (c0 + s > j && c0 + s < n) {
+          const double f = -tj * dot[s];
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) a[s][t] = fma(f, v[t], a[s][t]);
+        }
+      }
+    }
+  }
+
+  // ---- R (row-major n x n), through the staging tile
+  if (Rs) {
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      if (64 * t < n) {
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < CPW; ++s)
+          if (c0 + s < n) buf[(c0 + s) * kStageLd + lane] = a[s][t];
+        __syncthreads();
+        for (int e = tid; e < 64 * n; e += 1024) {
+          const int r = e / n, j = e - r * n, i = 64 * t + r;
+          if (i < n) Rs[(long)i * n + j] = (i <= j) ? ldexp(buf[j * kStageLd + r], ex) : 0.0;
+        }
+      }
+    }
+  }
+  if (!want_q) return;
+
+  // ---- Q in place, reflectors published kRegSlots at a time
+  for (int lo = ((n - 1) / kRegSlots) * kRegSlots; lo >= 0; lo -= kRegSlots) {
+    const int hi = min(n, lo + kRegSlots);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < CPW; ++s) {
+      const int c = c0 + s;
+      if (c >= lo && c < hi) {
+        double *vc = buf + (c - lo) * (64 * RPL);
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int i = lane + 64 * t;
+          vc[i] = (i < c) ? 0.0 : (i == c) ? 1.0 : a[s][t];
+        }
+      }
+    }
+    __syncthreads();
+    if (c0 >= n || c0 + CPW - 1 < lo) continue;      // no own column is touched by this chunk
+    for (int j = hi - 1; j >= lo; --j) {
+      const double tj = taus[j];
+      const double *vj = buf + (j - lo) * (64 * RPL);
+      if (tj != 0.0 && max(c0, j + 1) < min(c0 + CPW, n)) {
+        double v[RPL];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) v[t] = vj[lane + 64 * t];
+        double dot[CPW];
+#pragma unroll
+        for (int s = 0; s < CPW; ++s) {
+          dot[s] = 0.0;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) dot[s] = fma(v[t], a[s][t], dot[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < CPW; ++s)
+          if (c0 + s > j && c0 + s < n) dot[s] = wave_sum(dot[s]);
+#pragma unroll
+        for (int s = 0; s < CPW; ++s) {
+          if (c0 + s > j && c0 + s < n) {
+            const double f = -tj * dot[s];
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) a[s][t] = fma(f, v[t], a[s][t]);
+          }
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < CPW; ++s) {
+        if (c0 + s == j) {
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            const int i = lane + 64 * t;
+            a[s][t] = (i < j) ? 0.0 : (i == j) ? 1.0 - tj : -tj * a[s][t];
+          }
+        }
+      }
+    }
+  }
+
+  // ---- store Q, 64 rows per pass
+  const bool out_cols = (qc == 1) || (qr != 1 && (qc < 0 ? -qc : qc) < (qr < 0 ? -qr : qr));
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int r0 = 64 * t;
+    if (r0 < m) {
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < CPW; ++s)
+        if (c0 + s < n) buf[(c0 + s) * kStageLd + lane] = a[s][t];
+      __syncthreads();
+      for (int e = tid; e < 64 * n; e += 1024) {
+        int r, j;
+        if (out_cols) { r = e / n; j = e - r * n; }
+        else { j = e >> 6; r = e & 63; }
+        const int i = r0 + r;
+        if (i < m) Qo[(long)i * qr + (long)j * qc] = buf[j * kStageLd + r];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- Jacobi SVD
 // Right singular vectors of an upper-triangular l x l factor R (row-major):
 // one-sided (Hestenes) Jacobi orthogonalises the columns of R^T (faster than
 // R's own columns for a triangular factor); R^T J = X Sigma gives the wanted
 // vectors as the normalised columns of X, so no rotations are accumulated.
-// Round-robin pair ordering, one wavefront per pair.  The sorted columns are
-// then checked for orthonormality and, if off by more than 1e-13 (directions
-// with singular values near rounding), re-orthonormalised by CGS2 with a
-// deterministic completion from the unit vectors.
+// R is first scaled by a power of two so that its largest entry lies in
+// [1/2, 1) (exact, and it keeps squared column norms and their products far
+// from underflow at the tiny scales two-site blocks can have).  Round-robin pair ordering, one
+// 16-lane DPP row per pair, so a round of up to 48 pairs is one pass and its
+// sums need no LDS.
+//
+// The sorted columns are then checked for orthonormality (1e-13).  Columns
+// at the rounding floor are never rotated and fail it; when everything from
+// the first failing column i0 on has joint norm below 5e-12 of the largest
+// singular value, every direction orthogonal to the first i0 columns weighs
+// less than half the null threshold of the truncation (1e-11 of the largest
+// weight), so columns i0.. are returned as zeros, which the truncation drops
+// like any such direction.  Otherwise the columns are re-orthonormalised by
+// CGS2 in sorted order with a deterministic completion from the unit vectors.
+constexpr int kJacRows = kMaxSketch / 16;     // rows per lane of a pair group
+constexpr double kJacTail = 5e-12;
+
 __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm, double *Vo,
                                                 double *sig, long ist) {
   SPG_INST(Rm);
@@ -352,63 +623,77 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
   __shared__ double W[kMaxSketch * kMaxSketch];
   __shared__ double V[kMaxSketch * kMaxSketch];
   __shared__ double nrm[kMaxSketch];
+  __shared__ double snrm[kMaxSketch];
   __shared__ double hbuf[kMaxSketch];
-  __shared__ int rotated, bad;
+  __shared__ int rotated, bad, first_bad;
   __shared__ double sh_fro, sh_nv;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
-  // W column-major with column j = row j of R, i.e. W = R^T; same storage as Rm
-  for (int e = tid; e < l * l; e += blockDim.x) W[e] = Rm[e];
+  if (wid == 0) {
+    double a = 0.0;
+    for (int e = lane; e < l * l; e += 64) a = fmax(a, fabs(Rm[e]));
+    a = wave_max_nonneg(a);
+    if (lane == 0) sh_nv = a;
+  }
+  __syncthreads();
+  // W column-major with column j = row j of R, i.e. W = R^T (same storage as
+  // Rm), times 2^-e with max |R_ij| = m 2^e, 1/2 <= m < 1
+  int ex = 0;
+  if (sh_nv > 0.0 && sh_nv <= 1.7e308) (void)frexp(sh_nv, &ex);
+  for (int e = tid; e < l * l; e += blockDim.x) W[e] = ldexp(Rm[e], -ex);
   const int le = (l + 1) & ~1;
   __syncthreads();
   if (wid == 0) {
     double a = 0.0;
-    for (int e = lane; e < l * l; e += 64) a += W[e] * W[e];
+    for (int e = lane; e < l * l; e += 64) a = fma(W[e], W[e], a);
     a = wave_sum(a);
     if (lane == 0) sh_fro = a;
   }
   __syncthreads();
   // columns below 1e-13 |R|_F sit at the rounding floor (the truncation drops
-  // such directions anyway) and off-diagonal mass below 1e-30 |R|_F^2 is
-  // rounding noise: rotating either only shuffles noise, so both are skipped
-  const double tiny = 1e-26 * sh_fro, gfloor = 1e-30 * sh_fro;
+  // such directions anyway): rotating them only shuffles noise
+  const double tiny = 1e-26 * sh_fro;
+  const int grp = tid >> 4, r16 = tid & 15, ngrp = blockDim.x >> 4;
+  const int np = le / 2, nc = le - 1;
   for (int sweep = 0; sweep < 30; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
-    // one half-wavefront (32 lanes, rows l32, l32 + 32, l32 + 64) per pair, so
-    // a round of up to 32 pairs is one pass; the three column sums of a pair
-    // are reduced together (16-lane DPP sums, then across the two rows)
-    const int hw = tid >> 5, l32 = tid & 31, nhw = blockDim.x >> 5;
-    for (int t = 0; t < le - 1; ++t) {
-      for (int k = hw; k < le / 2; k += nhw) {
+    for (int t = 0; t < nc; ++t) {
+      for (int k = grp; k < np; k += ngrp) {
         int p, q;
-        if (k == 0) { p = t; q = le - 1; }
-        else { p = (t + k) % (le - 1); q = (t - k + le - 1) % (le - 1); }
+        if (k == 0) { p = t; q = nc; }
+        else {
+          p = t + k; if (p >= nc) p -= nc;
+          q = t - k; if (q < 0) q += nc;
+        }
         if (p > q) { const int tmp = p; p = q; q = tmp; }
         if (q >= l) continue;
-        double x[3], y[3];
+        double x[kJacRows], y[kJacRows];
         double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
-        for (int h = 0; h < 3; ++h) {
-          const int r = l32 + 32 * h;
+        for (int h = 0; h < kJacRows; ++h) {
+          const int r = r16 + 16 * h;
           x[h] = (r < l) ? W[p * l + r] : 0.0;
           y[h] = (r < l) ? W[q * l + r] : 0.0;
-          a += x[h] * x[h]; b += y[h] * y[h]; g += x[h] * y[h];
+          a = fma(x[h], x[h], a);
+          b = fma(y[h], y[h], b);
+          g = fma(x[h], y[h], g);
         }
-        a = row16_sum(a); b = row16_sum(b); g = row16_sum(g);
-        a += __shfl_xor(a, 16); b += __shfl_xor(b, 16); g += __shfl_xor(g, 16);
-        if (a > tiny && b > tiny && fabs(g) > gfloor && g * g > 1e-28 * (a * b)) {
+        a = row16_sum(a);
+        b = row16_sum(b);
+        g = row16_sum(g);
+        if (a > tiny && b > tiny && g * g > 1e-28 * (a * b)) {
           const double zeta = (b - a) / (2.0 * g);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+          const double cs = rsqrt(1.0 + tt * tt), sn = cs * tt;
 #pragma unroll
-          for (int h = 0; h < 3; ++h) {
-            const int r = l32 + 32 * h;
+          for (int h = 0; h < kJacRows; ++h) {
+            const int r = r16 + 16 * h;
             if (r < l) {
               W[p * l + r] = cs * x[h] - sn * y[h];
               W[q * l + r] = sn * x[h] + cs * y[h];
             }
           }
-          if (l32 == 0) rotated = 1;
+          if (r16 == 0) rotated = 1;
         }
       }
       __syncthreads();
@@ -429,21 +714,41 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
     for (int i = 0; i < l; ++i) rank += (nrm[i] > nrm[j]) || (nrm[i] == nrm[j] && i < j);
     const double inv = (nrm[j] > 0.0) ? 1.0 / nrm[j] : 0.0;
     for (int r = lane; r < l; r += 64) V[rank * l + r] = W[j * l + r] * inv;
-    if (lane == 0) sig[rank] = nrm[j];
+    if (lane == 0) {
+      sig[rank] = ldexp(nrm[j], ex);
+      snrm[rank] = nrm[j];
+    }
   }
-  if (tid == 0) bad = 0;
+  if (tid == 0) {
+    bad = 0;
+    first_bad = kk;
+  }
   __syncthreads();
-  // only the leading kk columns are used: check and repair those
+  // only the leading kk columns are used: check those
   for (int e = wid; e < kk * kk; e += nw) {
     const int i = e / kk, j = e % kk;
     if (j > i) continue;
     double g = 0.0;
     for (int r = lane; r < l; r += 64) g += V[i * l + r] * V[j * l + r];
     g = wave_sum(g);
-    if (lane == 0 && fabs(g - (i == j ? 1.0 : 0.0)) > 1e-13) bad = 1;
+    if (lane == 0 && fabs(g - (i == j ? 1.0 : 0.0)) > 1e-13) {
+      bad = 1;
+      atomicMin(&first_bad, i);
+    }
   }
   __syncthreads();
-  if (bad) {
+  if (bad && wid == 0) {
+    // joint norm of the sorted columns from the first failing one on
+    double t2 = 0.0;
+    for (int j = first_bad + lane; j < l; j += 64) t2 = fma(snrm[j], snrm[j], t2);
+    t2 = wave_sum(t2);
+    if (lane == 0 && snrm[0] > 0.0 && sqrt(t2) <= kJacTail * snrm[0]) bad = 2;
+  }
+  __syncthreads();
+  if (bad == 2) {
+    for (int e = tid; e < (kk - first_bad) * l; e += blockDim.x) V[first_bad * l + e] = 0.0;
+    __syncthreads();
+  } else if (bad) {
     // CGS2 in sorted order; a column that loses its norm is replaced by the
     // first unit vector that survives the projection
     for (int i = 0; i < kk; ++i) {
@@ -671,6 +976,42 @@ size_t qr_work_doubles(int m, int n) {
   return 3 * (size_t)m * n + 2 * (size_t)kQrLds + 2 * (size_t)n * n + n + 64;
 }
 
+// Register-resident panels: up to 512 rows (8 per lane) and 80 columns (5 per
+// wavefront).
+constexpr int kQrRegRows = 512, kQrRegCols = 80;
+
+template <int RPL>
+static void qr_reg_rows(int cpw, int m, int n, const double *X, long xr, long xc, double *Q,
+                        long qr, long qc, double *R, int want_q, dim3 grid, long ist,
+                        hipStream_t s) {
+#define SPG_QR_REG(C)                                                                         \
+  case C:                                                                                      \
+    hipLaunchKernelGGL((k_qr_reg<RPL, C>), grid, dim3(1024), 0, s, m, n, X, xr, xc, Q, qr, qc, \
+                       R, want_q, ist);                                                        \
+    break;
+  switch (cpw) {
+    SPG_QR_REG(1)
+    SPG_QR_REG(2)
+    SPG_QR_REG(3)
+    SPG_QR_REG(4)
+    SPG_QR_REG(5)
+    default:
+      set_error("qr_f64: register panel too wide");
+      throw Fail{SPG_ERR_UNSUPPORTED};
+  }
+#undef SPG_QR_REG
+  SPG_CHECK_LAUNCH();
+}
+
+static void qr_reg(int m, int n, const double *X, long xr, long xc, double *Q, long qr, long qc,
+                   double *R, int want_q, dim3 grid, long ist, hipStream_t s) {
+  const int cpw = (n + 15) / 16;
+  if (m <= 64) qr_reg_rows<1>(cpw, m, n, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
+  else if (m <= 128) qr_reg_rows<2>(cpw, m, n, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
+  else if (m <= 256) qr_reg_rows<4>(cpw, m, n, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
+  else qr_reg_rows<8>(cpw, m, n, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
+}
+
 // One LDS panel factorisation launch.
 static void qr_panel(dim3 grid, int m, int n, int mb, const double *X, long xr, long xc,
                      double *Q, long qr, long qc, double *R, int want_q, long ist, hipStream_t s) {
@@ -697,6 +1038,11 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
   SPG_BC(work);
   const unsigned nI = (unsigned)g_bc.n;
   const long ist = g_bc.ist;
+  if (m <= kQrRegRows && n <= kQrRegCols) {
+    KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
+    qr_reg(m, n, X, xr, xc, Q, qr, qc, R, want_q, dim3(1, nI), ist, s);
+    return;
+  }
   if ((long)m * n <= kQrLds) {
     // one LDS-resident block; R straight to the caller (or to scratch)
     double *Rd = R ? R : work;

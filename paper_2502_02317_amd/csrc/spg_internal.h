@@ -118,8 +118,10 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
 // One-sided Jacobi SVD of an l x l matrix (row-major, l <= kMaxSketch): writes
 // the right singular vectors as columns of V (row-major l x l) sorted by
 // singular value, descending (ties by index), and the singular values to sig.
-// The leading kk columns are made orthonormal to 1e-13 (the others are the
-// normalised Jacobi columns and may not be, when they sit at rounding level).
+// The leading kk columns are orthonormal to 1e-13, except that a trailing run
+// of them whose joint singular-value norm is below 5e-12 of the largest may
+// come back as zero columns (directions the truncation's null rule drops);
+// the others are the normalised Jacobi columns and need not be orthonormal.
 void jacobi_svd_f64(int l, int kk, const double *Rm, double *V, double *sig, hipStream_t s);
 
 // Sketch matrix of the truncated SVD: Om[i*l + j] = 2 u(SplitMix64(seed, i*ld + j)) - 1.
