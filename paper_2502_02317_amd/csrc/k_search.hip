@@ -137,8 +137,13 @@ __global__ __launch_bounds__(256) void k_marginals(SearchTabs t, int r, int c, i
 // that order, with the selected scores in sel_score (may be null).  Candidate
 // i has score cand[i] and id cid[i] (cid null: id = i; ids must be unique and
 // non-negative); n is *n_dev when n_dev is given.  Radix select of the M-th
-// key (8 passes of 8 bits), then of the id among keys equal to it, compaction,
-// then a bitonic sort of the survivors.
+// key (8-bit digits), then of the id among keys equal to it, compaction, then
+// a bitonic sort of the survivors.  Up to kSelRegKeys * 1024 candidates are
+// held in registers for all passes, which then start at the highest digit
+// where the keys differ; survivors are sorted in LDS up to kSelLdsSort slots.
+constexpr int kSelRegKeys = 16;
+constexpr int kSelLdsSort = 4096;
+
 __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, int M,
                                                 const double *cand, const int32_t *cid,
                                                 int32_t *sel, double *sel_score, uint64_t *kw,
@@ -154,64 +159,181 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
   __shared__ uint64_t sh_prefix;
   __shared__ int sh_need;
   __shared__ int wsum[16];
+  __shared__ uint64_t wmin[16], wmax[16];
+  __shared__ uint64_t skey[kSelLdsSort];
+  __shared__ int32_t sid[kSelLdsSort];
   const int tid = threadIdx.x;
   const int n = n_dev ? *n_dev : n_host;
   const int Me = (M < n) ? M : n;
+  int p2 = 1;
+  while (p2 < Me) p2 <<= 1;
+  const bool lds_sort = p2 <= kSelLdsSort;
   auto key_at = [&](int i) { return desc_key(cand[i]); };
   auto id_at = [&](int i) { return cid ? cid[i] : i; };
   uint64_t kthr = ~0ull;         // take keys < kthr, and keys == kthr with id <= ithr
   uint64_t ithr = 0;
   bool all_eq = true;
-  if (Me < n) {
-    uint64_t prefix = 0, pmask = 0;
-    int need = Me;
-    for (int shift = 56; shift >= 0; shift -= 8) {
-      radix_digit(n, shift, key_at, pmask, prefix, need, hist, &sh_prefix, &sh_need);
-      pmask |= (255ull << shift);
-    }
-    kthr = prefix;
-    // need = how many keys equal to kthr are taken; hist still counts them
-    const int n_eq = (int)hist[kthr & 255u];
-    if (need < n_eq) {
-      all_eq = false;
-      const uint64_t kk = kthr;
-      auto idkey_at = [&](int i) -> uint64_t {
-        return (key_at(i) == kk) ? (uint64_t)(uint32_t)id_at(i) : ~0ull;
-      };
-      uint64_t ip = 0, im = 0xFFFFFFFF00000000ull;   // ids fit in 32 bits
-      int need_id = need;
-      for (int shift = 24; shift >= 0; shift -= 8) {
-        radix_digit(n, shift, idkey_at, im, ip, need_id, hist, &sh_prefix, &sh_need);
-        im |= (255ull << shift);
+  if (n <= kSelRegKeys * 1024) {
+    // ---- keys held in registers, kSelRegKeys per thread (ids are the index
+    // or read back for ties and survivors only)
+    uint64_t kr[kSelRegKeys];
+    uint64_t lo = ~0ull, hi = 0;
+#pragma unroll
+    for (int q = 0; q < kSelRegKeys; ++q) {
+      const int i = tid + 1024 * q;
+      kr[q] = (i < n) ? key_at(i) : 0ull;
+      if (i < n) {
+        lo = (kr[q] < lo) ? kr[q] : lo;
+        hi = (kr[q] > hi) ? kr[q] : hi;
       }
-      ithr = ip;
+    }
+    if (Me < n) {
+      // digits above the highest bit where the keys differ are shared by all
+      // of them: the radix passes start below it
+      lo = wave_min_u64(lo);
+      hi = wave_max_u64(hi);
+      if ((tid & 63) == 0) {
+        wmin[tid >> 6] = lo;
+        wmax[tid >> 6] = hi;
+      }
+      __syncthreads();
+      lo = ~0ull;
+      hi = 0;
+      for (int w = 0; w < 16; ++w) {
+        lo = (wmin[w] < lo) ? wmin[w] : lo;
+        hi = (wmax[w] > hi) ? wmax[w] : hi;
+      }
+      int need = Me, n_eq = n;
+      uint64_t prefix = lo;
+      if (lo != hi) {
+        const int top = (63 - __clzll((long long)(lo ^ hi))) & ~7;   // shift of the first digit that differs
+        uint64_t pmask = (top == 56) ? 0ull : ~((1ull << (top + 8)) - 1ull);
+        prefix = lo & pmask;
+        for (int shift = top; shift >= 0; shift -= 8) {
+          for (int i = tid; i < 256; i += 1024) hist[i] = 0u;
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < kSelRegKeys; ++q) {
+            const int i = tid + 1024 * q;
+            if (i < n && (kr[q] & pmask) == prefix) atomicAdd(&hist[(kr[q] >> shift) & 255u], 1u);
+          }
+          __syncthreads();
+          radix_find(shift, prefix, need, hist, &sh_prefix, &sh_need);
+          pmask |= (255ull << shift);
+        }
+        n_eq = (int)hist[prefix & 255u];
+      }
+      kthr = prefix;
+      if (need < n_eq) {
+        all_eq = false;
+        uint64_t ip = 0, im = 0xFFFFFFFF00000000ull;   // ids fit in 32 bits
+        int need_id = need;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+          for (int i = tid; i < 256; i += 1024) hist[i] = 0u;
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < kSelRegKeys; ++q) {
+            const int i = tid + 1024 * q;
+            const uint64_t ik = (i < n && kr[q] == kthr) ? (uint64_t)(uint32_t)id_at(i) : ~0ull;
+            if ((ik & im) == ip) atomicAdd(&hist[(ik >> shift) & 255u], 1u);
+          }
+          __syncthreads();
+          radix_find(shift, ip, need_id, hist, &sh_prefix, &sh_need);
+          im |= (255ull << shift);
+        }
+        ithr = ip;
+      }
+    }
+    // ---- compaction: per-thread counts, one block scan
+    int cnt = 0;
+    unsigned fl = 0u;
+#pragma unroll
+    for (int q = 0; q < kSelRegKeys; ++q) {
+      const int i = tid + 1024 * q;
+      bool f = false;
+      if (i < n) {
+        f = (Me == n) || (kr[q] < kthr) ||
+            (kr[q] == kthr && (all_eq || (uint64_t)(uint32_t)id_at(i) <= ithr));
+      }
+      fl |= (f ? 1u : 0u) << q;
+      cnt += f;
+    }
+    int tot;
+    int pos = block_excl_scan_count(cnt, wsum, &tot);
+#pragma unroll
+    for (int q = 0; q < kSelRegKeys; ++q) {
+      if (((fl >> q) & 1u) && pos < Me) {      // exactly Me flags by construction
+        const int i = tid + 1024 * q;
+        if (lds_sort) { skey[pos] = kr[q]; sid[pos] = id_at(i); }
+        else { kw[pos] = kr[q]; iw[pos] = id_at(i); }
+        ++pos;
+      }
+    }
+  } else {
+    // ---- keys read from memory on every pass
+    if (Me < n) {
+      uint64_t prefix = 0, pmask = 0;
+      int need = Me;
+      for (int shift = 56; shift >= 0; shift -= 8) {
+        radix_digit(n, shift, key_at, pmask, prefix, need, hist, &sh_prefix, &sh_need);
+        pmask |= (255ull << shift);
+      }
+      kthr = prefix;
+      // need = how many keys equal to kthr are taken; hist still counts them
+      const int n_eq = (int)hist[kthr & 255u];
+      if (need < n_eq) {
+        all_eq = false;
+        const uint64_t kk = kthr;
+        auto idkey_at = [&](int i) -> uint64_t {
+          return (key_at(i) == kk) ? (uint64_t)(uint32_t)id_at(i) : ~0ull;
+        };
+        uint64_t ip = 0, im = 0xFFFFFFFF00000000ull;   // ids fit in 32 bits
+        int need_id = need;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+          radix_digit(n, shift, idkey_at, im, ip, need_id, hist, &sh_prefix, &sh_need);
+          im |= (255ull << shift);
+        }
+        ithr = ip;
+      }
+    }
+    // compaction of the survivors (any order: they are sorted next)
+    int base = 0;
+    for (int c0 = 0; c0 < n; c0 += blockDim.x) {
+      const int i = c0 + tid;
+      uint64_t k = 0;
+      int f = 0;
+      if (i < n) {
+        k = key_at(i);
+        f = (k < kthr) || (k == kthr && (all_eq || (uint64_t)(uint32_t)id_at(i) <= ithr));
+        if (Me == n) f = 1;
+      }
+      int tot_f;
+      const int pos = block_excl_scan(f, wsum, &tot_f);
+      if (f) {
+        if (lds_sort) { skey[base + pos] = k; sid[base + pos] = id_at(i); }
+        else { kw[base + pos] = k; iw[base + pos] = id_at(i); }
+      }
+      base += tot_f;
+      __syncthreads();
     }
   }
-  // compaction of the survivors (any order: they are sorted next)
-  int base = 0;
-  for (int c0 = 0; c0 < n; c0 += blockDim.x) {
-    const int i = c0 + tid;
-    uint64_t k = 0;
-    int f = 0;
-    if (i < n) {
-      k = key_at(i);
-      f = (k < kthr) || (k == kthr && (all_eq || (uint64_t)(uint32_t)id_at(i) <= ithr));
-      if (Me == n) f = 1;
-    }
-    int tot_f;
-    const int pos = block_excl_scan(f, wsum, &tot_f);
-    if (f) { kw[base + pos] = k; iw[base + pos] = id_at(i); }
-    base += tot_f;
+  // ---- sort the Me survivors (padded to a power of two) by (key, id)
+  if (lds_sort) {
+    for (int i = Me + tid; i < p2; i += blockDim.x) { skey[i] = ~0ull; sid[i] = INT_MAX; }
     __syncthreads();
-  }
-  int p2 = 1;
-  while (p2 < Me) p2 <<= 1;
-  for (int i = Me + tid; i < p2; i += blockDim.x) { kw[i] = ~0ull; iw[i] = INT_MAX; }
-  __syncthreads();
-  bitonic_sort_global(kw, iw, p2);
-  for (int i = tid; i < Me; i += blockDim.x) {
-    sel[i] = iw[i];
-    if (sel_score) sel_score[i] = key_value(kw[i]);
+    bitonic_sort_lds(skey, sid, p2);
+    for (int i = tid; i < Me; i += blockDim.x) {
+      sel[i] = sid[i];
+      if (sel_score) sel_score[i] = key_value(skey[i]);
+    }
+  } else {
+    for (int i = Me + tid; i < p2; i += blockDim.x) { kw[i] = ~0ull; iw[i] = INT_MAX; }
+    __syncthreads();
+    bitonic_sort(kw, iw, p2);
+    for (int i = tid; i < Me; i += blockDim.x) {
+      sel[i] = iw[i];
+      if (sel_score) sel_score[i] = key_value(kw[i]);
+    }
   }
 }
 
@@ -343,7 +465,7 @@ __global__ __launch_bounds__(1024) void k_final_sort(int n, const double *E, con
   }
   atomicAdd(&cnt, local);
   __syncthreads();
-  bitonic_sort_global(kw, iw, p2);
+  bitonic_sort(kw, iw, p2);
   if (threadIdx.x == 0) *nv = cnt;
 }
 

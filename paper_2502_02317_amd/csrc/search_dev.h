@@ -86,8 +86,9 @@ __device__ inline int block_excl_scan(int f, int *wsum, int *total) {
   return off + pre;
 }
 
-// Sort (key, id) pairs ascending in global memory with one workgroup (bitonic).
-__device__ inline void bitonic_sort_global(uint64_t *keys, int32_t *ids, int n_pow2) {
+// Sort (key, id) pairs ascending with one workgroup (bitonic); the arrays may
+// live in global memory or LDS (each call site is inlined with its own).
+__device__ __forceinline__ void bitonic_sort(uint64_t *keys, int32_t *ids, int n_pow2) {
   for (int k = 2; k <= n_pow2; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       for (int i = threadIdx.x; i < n_pow2; i += blockDim.x) {
@@ -108,6 +109,76 @@ __device__ inline void bitonic_sort_global(uint64_t *keys, int32_t *ids, int n_p
   }
 }
 
+// The same sort for (key, id) pairs held in LDS, blockDim = 1024, n_pow2 <=
+// 4096: thread t keeps elements t + 1024 r in registers; stages whose partner
+// lies in the same wavefront (distance < 64) exchange through lane shuffles
+// without barriers, the others go through LDS.  Leaves the sorted pairs in LDS.
+__device__ inline void bitonic_sort_lds(uint64_t *keys, int32_t *ids, int n_pow2) {
+  const int tid = threadIdx.x;
+  const int R = (n_pow2 + 1023) >> 10;          // 1..4
+  uint64_t kv[4];
+  int32_t iv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = tid + 1024 * r;
+    kv[r] = (r < R && i < n_pow2) ? keys[i] : ~0ull;
+    iv[r] = (r < R && i < n_pow2) ? ids[i] : INT_MAX;
+  }
+  for (int k = 2; k <= n_pow2; k <<= 1) {
+    int j = k >> 1;
+    if (j >= 64) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = tid + 1024 * r;
+        if (r < R && i < n_pow2) { keys[i] = kv[r]; ids[i] = iv[r]; }
+      }
+      __syncthreads();
+      for (; j >= 64; j >>= 1) {
+        for (int i = tid; i < n_pow2; i += blockDim.x) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const uint64_t ki = keys[i], kj = keys[ixj];
+            const int32_t ii = ids[i], ij = ids[ixj];
+            const bool gt = (ki > kj) || (ki == kj && ii > ij);
+            const bool up = ((i & k) == 0);
+            if (gt == up) {
+              keys[i] = kj; keys[ixj] = ki;
+              ids[i] = ij; ids[ixj] = ii;
+            }
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = tid + 1024 * r;
+        if (r < R && i < n_pow2) { kv[r] = keys[i]; iv[r] = ids[i]; }
+      }
+    }
+    for (; j > 0; j >>= 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (r < R) {
+          const int i = tid + 1024 * r;
+          const uint64_t pk = __shfl_xor(kv[r], j);
+          const int32_t pi = __shfl_xor(iv[r], j);
+          const bool gt = (kv[r] > pk) || (kv[r] == pk && iv[r] > pi);   // mine after partner's
+          const bool lower = (i & j) == 0, up = (i & k) == 0;
+          if (lower == up ? gt : !gt) { kv[r] = pk; iv[r] = pi; }
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = tid + 1024 * r;
+    if (r < R && i < n_pow2) { keys[i] = kv[r]; ids[i] = iv[r]; }
+  }
+  __syncthreads();
+}
+
 // Inverse of desc_key (NaN came in as -inf).
 __device__ __forceinline__ double key_value(uint64_t k) {
   const uint64_t sign = 0x8000000000000000ull;
@@ -115,21 +186,13 @@ __device__ __forceinline__ double key_value(uint64_t k) {
   return __longlong_as_double((long long)((w & sign) ? (w ^ sign) : ~w));
 }
 
-// One radix-select step: among the items with (key & pmask) == prefix, find
-// the 8-bit digit at `shift` holding the need-th smallest key; updates prefix
-// and need.  Keys come from key_at(i), i < n.  blockDim = 1024.
-template <class KeyAt>
-__device__ inline void radix_digit(int n, int shift, const KeyAt &key_at, uint64_t pmask,
-                            uint64_t &prefix, int &need, unsigned *hist, uint64_t *sh_prefix,
-                            int *sh_need) {
+// Second half of a radix-select step: hist holds the counts of the 8-bit
+// digit at `shift` among the items with (key & pmask) == prefix; finds the
+// digit holding the need-th smallest key and updates prefix and need.
+// blockDim = 1024; ends with a barrier.
+__device__ inline void radix_find(int shift, uint64_t &prefix, int &need, const unsigned *hist,
+                                  uint64_t *sh_prefix, int *sh_need) {
   const int tid = threadIdx.x;
-  for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0u;
-  __syncthreads();
-  for (int i = tid; i < n; i += blockDim.x) {
-    const uint64_t k = key_at(i);
-    if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
-  }
-  __syncthreads();
   if (tid < 64) {
     // wave-parallel scan over the 256 digits: lane l owns digits 4l..4l+3
     unsigned h[4], own = 0u;
@@ -157,6 +220,60 @@ __device__ inline void radix_digit(int n, int shift, const KeyAt &key_at, uint64
   need = *sh_need;
   prefix = *sh_prefix;
   __syncthreads();
+}
+
+// One radix-select step: among the items with (key & pmask) == prefix, find
+// the 8-bit digit at `shift` holding the need-th smallest key; updates prefix
+// and need.  Keys come from key_at(i), i < n.  blockDim = 1024.
+template <class KeyAt>
+__device__ inline void radix_digit(int n, int shift, const KeyAt &key_at, uint64_t pmask,
+                            uint64_t &prefix, int &need, unsigned *hist, uint64_t *sh_prefix,
+                            int *sh_need) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0u;
+  __syncthreads();
+  for (int i = tid; i < n; i += blockDim.x) {
+    const uint64_t k = key_at(i);
+    if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  radix_find(shift, prefix, need, hist, sh_prefix, sh_need);
+}
+
+// Block-wide exclusive scan of non-negative counts (blockDim = 1024); returns
+// the prefix and writes the block total to *total.
+__device__ inline int block_excl_scan_count(int v, int *wsum, int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int inc = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(inc, o);
+    if (lane >= o) inc += t;
+  }
+  __syncthreads();
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    if (i < w) off += wsum[i];
+    tot += wsum[i];
+  }
+  *total = tot;
+  return off + inc - v;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t w = __shfl_xor(v, o);
+    v = (w < v) ? w : v;
+  }
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t w = __shfl_xor(v, o);
+    v = (w > v) ? w : v;
+  }
+  return v;
 }
 
 }  // namespace spg
