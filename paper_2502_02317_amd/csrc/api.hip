@@ -303,6 +303,7 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
       fill_zero(phin, site, s);
       GemmDesc g{};
       g.nb1 = 1; g.nb2 = 1; g.alpha = 1.0; g.beta = 0.0;
+      g.ws = w.skws.as<double>(); g.ws_len = w.skws.bytes / sizeof(double);
       int kk;
       if (!right) {
         kk = tsvd_left(w, Bm, n, 1, m, n, k, prm->oversample, prm->power_iters, phic, chi, 1, s);

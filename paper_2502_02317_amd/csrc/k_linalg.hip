@@ -49,14 +49,18 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
   for (int i = 0; i < P; ++i)
 #pragma unroll
     for (int j = 0; j < P; ++j) acc[i][j] = 0.0;
+  // consecutive threads take consecutive addresses of whichever index has
+  // unit stride, so tile loads are contiguous for either operand layout
+  const bool a_rows = (g.a_i == 1 && g.a_k != 1);      // A column-major: i fastest
+  const bool b_cols = (g.b_k == 1 && g.b_j != 1);      // B column-major: k fastest
   for (int k0 = 0; k0 < Kend; k0 += 16) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int e = tid + 256 * q;
-      const int r = e >> 4, kk = e & 15;
+      const int r = a_rows ? (e % TILE) : (e >> 4), kk = a_rows ? (e / TILE) : (e & 15);
       const int gi = i0 + r, gk = k0 + kk;
       As[kk][r] = (gi < g.M && gk < Kend) ? A[gi * g.a_i + gk * g.a_k] : 0.0;
-      const int kb = e / TILE, cb = e % TILE;
+      const int kb = b_cols ? (e & 15) : (e / TILE), cb = b_cols ? (e >> 4) : (e % TILE);
       const int gkb = k0 + kb, gj = j0 + cb;
       Bs[kb][cb] = (gkb < Kend && gj < g.N) ? B[gkb * g.b_k + gj * g.b_j] : 0.0;
     }
