@@ -182,23 +182,25 @@ static int tsvd_left(BmpsWork &w, const double *B, long br, long bc, int m, int 
     gemm_f64(g, s);
   };
   double *qw = w.qrwork.as<double>();
-  mm(m, l, n, B, br, bc, Om, l, 1, Y, l, 1);                 // Y = B Om
-  qr_f64(m, l, Y, l, 1, Q, l, 1, nullptr, qw, s);           // Q = orth(Y)
+  // the range-finder panels Y, Z, Q, Qz are column-major (the QR reads and
+  // writes them straight from registers)
+  mm(m, l, n, B, br, bc, Om, l, 1, Y, 1, m);                 // Y = B Om
+  qr_f64(m, l, Y, 1, m, Q, 1, m, nullptr, qw, s);           // Q = orth(Y)
   for (int it = 0; it < q; ++it) {
-    mm(n, l, m, B, bc, br, Q, l, 1, Z, l, 1);                // Z = B^T Q
-    qr_f64(n, l, Z, l, 1, Qz, l, 1, nullptr, qw, s);
-    mm(m, l, n, B, br, bc, Qz, l, 1, Y, l, 1);               // Y = B Qz
-    qr_f64(m, l, Y, l, 1, Q, l, 1, nullptr, qw, s);
+    mm(n, l, m, B, bc, br, Q, 1, m, Z, 1, n);                // Z = B^T Q
+    qr_f64(n, l, Z, 1, n, Qz, 1, n, nullptr, qw, s);
+    mm(m, l, n, B, br, bc, Qz, 1, n, Y, 1, m);               // Y = B Qz
+    qr_f64(m, l, Y, 1, m, Q, 1, m, nullptr, qw, s);
   }
   if (l == kk) {
     // sketch width = kept rank: U U^T B only depends on span(Q), so U = Q
-    mm(m, kk, l, Q, l, 1, w.ident.as<double>(), w.lmax, 1, U, ur, uc);
+    mm(m, kk, l, Q, 1, m, w.ident.as<double>(), w.lmax, 1, U, ur, uc);
     return kk;
   }
-  mm(l, n, m, Q, 1, l, B, br, bc, Cm, n, 1);                 // Cm = Q^T B   (l x n)
+  mm(l, n, m, Q, m, 1, B, br, bc, Cm, n, 1);                 // Cm = Q^T B   (l x n)
   qr_f64(n, l, Cm, 1, n, nullptr, l, 1, w.Rc.as<double>(), qw, s);  // Cm^T = Qc Rc (R only)
   jacobi_svd_f64(l, kk, w.Rc.as<double>(), w.V.as<double>(), w.sig.as<double>(), s);
-  mm(m, kk, l, Q, l, 1, w.V.as<double>(), l, 1, U, ur, uc);  // U = Q V[:, :kk]
+  mm(m, kk, l, Q, 1, m, w.V.as<double>(), l, 1, U, ur, uc);  // U = Q V[:, :kk]
   return kk;
 }
 
@@ -265,12 +267,12 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
       double *Mc = w.Cm.as<double>();                           // compact bl x (d*br)
       pack_right(d, chi, bl, br, phi + c * site, Mc, s);
       // QR of Mc^T (d*br x bl): Q -> new right isometry, R folded into phi_{c-1}
-      qr_f64(d * br, bl, Mc, 1, (long)d * br, w.Qc.as<double>(), bl, 1, w.Rc.as<double>(),
-             w.qrwork.as<double>(), s);
+      qr_f64(d * br, bl, Mc, 1, (long)d * br, w.Qc.as<double>(), 1, (long)d * br,
+             w.Rc.as<double>(), w.qrwork.as<double>(), s);                 // Q column-major
       // direction i of M^T = Q R weighs |row i of R|
-      drop_null(bl, bl, w.Rc.as<double>(), bl, 1, w.Qc.as<double>(), d * br, 1, bl, s);
+      drop_null(bl, bl, w.Rc.as<double>(), bl, 1, w.Qc.as<double>(), d * br, (long)d * br, 1, s);
       fill_zero(phi + c * site, site, s);
-      unpack_right(d, chi, bl, br, w.Qc.as<double>(), 1, bl, phi + c * site, s);
+      unpack_right(d, chi, bl, br, w.Qc.as<double>(), (long)d * br, 1, phi + c * site, s);
       lq_fold(d, chi, bl, bl, w.Rc.as<double>(), phi + (c - 1) * site, w.tmp.as<double>(), s);
     }
     auto build_ER = [&](int c) {

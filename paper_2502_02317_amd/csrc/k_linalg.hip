@@ -392,8 +392,19 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, 
   const int c0 = w * CPW;
   double a[CPW][RPL];
 
-  // ---- load, 64 rows per pass through the staging tile buf[j*kStageLd + r]
+  // ---- load: column-major panels straight into registers (each wavefront
+  // reads contiguous column segments); others 64 rows per pass through the
+  // staging tile buf[j*kStageLd + r]
   const bool in_cols = (xc == 1) || (xr != 1 && (xc < 0 ? -xc : xc) < (xr < 0 ? -xr : xr));
+  if (xr == 1) {
+#pragma unroll
+    for (int s = 0; s < CPW; ++s)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int i = lane + 64 * t;
+        a[s][t] = (i < m && c0 + s < n) ? X[(long)i + (long)(c0 + s) * xc] : 0.0;
+      }
+  } else
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
     const int r0 = 64 * t;
@@ -575,8 +586,18 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, 
     }
   }
 
-  // ---- store Q, 64 rows per pass
+  // ---- store Q: column-major straight from registers, others 64 rows per pass
   const bool out_cols = (qc == 1) || (qr != 1 && (qc < 0 ? -qc : qc) < (qr < 0 ? -qr : qr));
+  if (qr == 1) {
+#pragma unroll
+    for (int s = 0; s < CPW; ++s)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int i = lane + 64 * t;
+        if (i < m && c0 + s < n) Qo[(long)i + (long)(c0 + s) * qc] = a[s][t];
+      }
+    return;
+  }
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
     const int r0 = 64 * t;
