@@ -26,11 +26,14 @@ __device__ double block_sum(double v, double *red) {
 
 // ---------------------------------------------------------------- GEMM
 // TILE x TILE output tile per 256-thread workgroup (TILE = 64 or 32), K staged
-// through LDS in steps of 16; each thread owns a (TILE/16)^2 sub-tile (rows
-// ty+16i, cols tx+16j).  The tile is picked per launch by the tuning.
+// through LDS in steps of kGemmKs (all of a step's loads are in flight at
+// once: these products are short, so load latency rather than FMA throughput
+// sets their time); each thread owns a (TILE/16)^2 sub-tile (rows ty+16i,
+// cols tx+16j).  The tile is picked per launch by the tuning.
+constexpr int kGemmKs = 32;
 template <int TILE>
 __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
-  constexpr int P = TILE / 16, NQ = 16 * TILE / 256;
+  constexpr int P = TILE / 16, KS = kGemmKs, NQ = KS * TILE / 256;
   const int nbb = g.nb1 * g.nb2;
   const int inst = blockIdx.z / nbb, bz = blockIdx.z % nbb;   // class-batched instance
   const int b1 = bz / g.nb2, b2 = bz % g.nb2;
@@ -38,8 +41,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
   const double *A = (const double *)((const char *)g.A + io) + b1 * g.a_b1 + b2 * g.a_b2;
   const double *B = (const double *)((const char *)g.B + io) + b1 * g.b_b1 + b2 * g.b_b2;
   double *C = (double *)((char *)g.C + io) + b1 * g.c_b1 + b2 * g.c_b2;
-  __shared__ double As[16][TILE + 1];
-  __shared__ double Bs[16][TILE + 1];
+  __shared__ double As[KS][TILE + 1];
+  __shared__ double Bs[KS][TILE + 1];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int i0 = blockIdx.y * TILE, j0 = blockIdx.x * TILE;
   // split-K chunks: chunk b1 covers global k in [b1*K, min((b1+1)*K, kmax))
@@ -53,20 +56,37 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
   // unit stride, so tile loads are contiguous for either operand layout
   const bool a_rows = (g.a_i == 1 && g.a_k != 1);      // A column-major: i fastest
   const bool b_cols = (g.b_k == 1 && g.b_j != 1);      // B column-major: k fastest
-  for (int k0 = 0; k0 < Kend; k0 += 16) {
+  for (int k0 = 0; k0 < Kend; k0 += KS) {
+    // every load of the step is issued before any is used: out-of-range
+    // elements read a valid address (the operand's first element) and are
+    // replaced by zero, so no branch separates the loads
+    double va[NQ], vb[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int e = tid + 256 * q;
-      const int r = a_rows ? (e % TILE) : (e >> 4), kk = a_rows ? (e / TILE) : (e & 15);
+      const int r = a_rows ? (e % TILE) : (e / KS), kk = a_rows ? (e / TILE) : (e % KS);
       const int gi = i0 + r, gk = k0 + kk;
-      As[kk][r] = (gi < g.M && gk < Kend) ? A[gi * g.a_i + gk * g.a_k] : 0.0;
-      const int kb = b_cols ? (e & 15) : (e / TILE), cb = b_cols ? (e >> 4) : (e % TILE);
+      const bool oka = gi < g.M && gk < Kend;
+      const double xa = A[oka ? (long)gi * g.a_i + (long)gk * g.a_k : 0L];
+      va[q] = oka ? xa : 0.0;
+      const int kb = b_cols ? (e % KS) : (e / TILE), cb = b_cols ? (e / KS) : (e % TILE);
       const int gkb = k0 + kb, gj = j0 + cb;
-      Bs[kb][cb] = (gkb < Kend && gj < g.N) ? B[gkb * g.b_k + gj * g.b_j] : 0.0;
+      const bool okb = gkb < Kend && gj < g.N;
+      const double xb = B[okb ? (long)gkb * g.b_k + (long)gj * g.b_j : 0L];
+      vb[q] = okb ? xb : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + 256 * q;
+      const int r = a_rows ? (e % TILE) : (e / KS), kk = a_rows ? (e / TILE) : (e % KS);
+      As[kk][r] = va[q];
+      const int kb = b_cols ? (e % KS) : (e / TILE), cb = b_cols ? (e / KS) : (e % TILE);
+      Bs[kb][cb] = vb[q];
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
+    const int kn = min(KS, Kend - k0);
+#pragma unroll 8
+    for (int kk = 0; kk < kn; ++kk) {
       double a[P], b[P];
 #pragma unroll
       for (int i = 0; i < P; ++i) a[i] = As[kk][ty + 16 * i];
@@ -836,56 +856,93 @@ __global__ void k_sketch(int n, int l, double *Om, long ist) {
   Om[e] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
 }
 
-// Box normalisation in three deterministic stages: per-block partial sums of
-// squares (fixed block count and order), one block folds them and writes the
-// log-scale and 1/norm, then every block rescales.
-constexpr int kNormBlocks = 128;
-__device__ __forceinline__ long box_offset(long e, int n1, int n2, int n3, long s0, long s1,
-                                           long s2, long s3) {
-  const int i3 = e % n3; e /= n3;
-  const int i2 = e % n2; e /= n2;
-  const int i1 = e % n1; const long i0 = e / n1;
-  return i0 * s0 + i1 * s1 + i2 * s2 + i3 * s3;
+// Box normalisation in two launches: per-block partial sums of squares (a
+// fixed block count and order); the last block to finish (found through a
+// release fence and an atomic counter in the scratch) folds them in a fixed
+// order and writes the log-scale and 1/norm, then resets the counter; a
+// second launch rescales.  Each thread keeps four loads in flight.
+constexpr int kNormBlocks = 1024;
+constexpr int kNormInv = kNormBlocks, kNormCount = kNormBlocks + 1;   // scratch slots
+static_assert(kNormScratch >= kNormBlocks + 2, "normalisation scratch too small");
+
+__device__ __forceinline__ long box_offset(unsigned e, unsigned n1, unsigned n2, unsigned n3,
+                                           long s0, long s1, long s2, long s3) {
+  const unsigned i3 = e % n3; e /= n3;
+  const unsigned i2 = e % n2; e /= n2;
+  const unsigned i1 = e % n1; const unsigned i0 = e / n1;
+  return (long)i0 * s0 + (long)i1 * s1 + (long)i2 * s2 + (long)i3 * s3;
 }
 
-__global__ __launch_bounds__(256) void k_box_sumsq(const double *T, long tot, int n1, int n2,
-                                                   int n3, long s0, long s1, long s2, long s3,
-                                                   double *part, long ist) {
+__global__ __launch_bounds__(256) void k_box_sumsq(const double *T, unsigned tot, unsigned n1,
+                                                   unsigned n2, unsigned n3, long s0, long s1,
+                                                   long s2, long s3, double *scr, double *logs,
+                                                   int out, int in, long ist) {
   SPG_INST(T);
-  SPG_INST(part);
-  __shared__ double red[16];
-  double acc = 0.0;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
-       e += (long)gridDim.x * blockDim.x) {
-    const double v = T[box_offset(e, n1, n2, n3, s0, s1, s2, s3)];
-    acc += v * v;
-  }
-  const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
-__global__ void k_box_fold(const double *part, int np, double *logs, int out, int in,
-                           double *inv_out, long ist) {
-  SPG_INST(part);
+  SPG_INST(scr);
   SPG_INST(logs);
-  SPG_INST(inv_out);
-  if (threadIdx.x != 0) return;
-  double ss = 0.0;
-  for (int i = 0; i < np; ++i) ss += part[i];
-  const double nr = sqrt(ss);
-  *inv_out = (nr > 0.0) ? 1.0 / nr : 1.0;
-  logs[out] = (in >= 0 ? logs[in] : 0.0) + (nr > 0.0 ? log(nr) : 0.0);
+  __shared__ double red[16];
+  __shared__ int last;
+  const unsigned stride = gridDim.x * blockDim.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
+  for (; e + 3 * stride < tot; e += 4 * stride) {
+    const double v0 = T[box_offset(e, n1, n2, n3, s0, s1, s2, s3)];
+    const double v1 = T[box_offset(e + stride, n1, n2, n3, s0, s1, s2, s3)];
+    const double v2 = T[box_offset(e + 2 * stride, n1, n2, n3, s0, s1, s2, s3)];
+    const double v3 = T[box_offset(e + 3 * stride, n1, n2, n3, s0, s1, s2, s3)];
+    a0 = fma(v0, v0, a0);
+    a1 = fma(v1, v1, a1);
+    a2 = fma(v2, v2, a2);
+    a3 = fma(v3, v3, a3);
+  }
+  for (; e < tot; e += stride) {
+    const double v = T[box_offset(e, n1, n2, n3, s0, s1, s2, s3)];
+    a0 = fma(v, v, a0);
+  }
+  const double t = block_sum((a0 + a1) + (a2 + a3), red);
+  unsigned *cnt = (unsigned *)(scr + kNormCount);
+  if (threadIdx.x == 0) {
+    scr[blockIdx.x] = t;
+    __threadfence();
+    last = (atomicAdd(cnt, 1u) == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double acc = 0.0;
+  for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) acc += scr[i];
+  const double ss = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    const double nr = sqrt(ss);
+    scr[kNormInv] = (nr > 0.0) ? 1.0 / nr : 1.0;
+    logs[out] = (in >= 0 ? logs[in] : 0.0) + (nr > 0.0 ? log(nr) : 0.0);
+    *cnt = 0u;
+  }
 }
 
-__global__ __launch_bounds__(256) void k_box_scale(double *T, long tot, int n1, int n2, int n3,
-                                                   long s0, long s1, long s2, long s3,
-                                                   const double *inv, long ist) {
+__global__ __launch_bounds__(256) void k_box_scale(double *T, unsigned tot, unsigned n1,
+                                                   unsigned n2, unsigned n3, long s0, long s1,
+                                                   long s2, long s3, const double *scr, long ist) {
   SPG_INST(T);
-  SPG_INST(inv);
-  const double f = *inv;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
-       e += (long)gridDim.x * blockDim.x)
-    T[box_offset(e, n1, n2, n3, s0, s1, s2, s3)] *= f;
+  SPG_INST(scr);
+  const double f = scr[kNormInv];
+  const unsigned stride = gridDim.x * blockDim.x;
+  unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
+  for (; e + 3 * stride < tot; e += 4 * stride) {
+    const long o0 = box_offset(e, n1, n2, n3, s0, s1, s2, s3);
+    const long o1 = box_offset(e + stride, n1, n2, n3, s0, s1, s2, s3);
+    const long o2 = box_offset(e + 2 * stride, n1, n2, n3, s0, s1, s2, s3);
+    const long o3 = box_offset(e + 3 * stride, n1, n2, n3, s0, s1, s2, s3);
+    const double v0 = T[o0], v1 = T[o1], v2 = T[o2], v3 = T[o3];
+    T[o0] = v0 * f;
+    T[o1] = v1 * f;
+    T[o2] = v2 * f;
+    T[o3] = v3 * f;
+  }
+  for (; e < tot; e += stride) {
+    const long o = box_offset(e, n1, n2, n3, s0, s1, s2, s3);
+    T[o] *= f;
+  }
 }
 
 // Zero the directions whose weight (norm of their row of Wm) is at most
@@ -900,12 +957,24 @@ __global__ __launch_bounds__(1024) void k_drop_null(int nd, int len, double *Wm,
   __shared__ double wmax;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int i = wid; i < nd; i += nw) {
-    double a = 0.0;
-    for (int e = lane; e < len; e += 64) {
-      const double v = Wm[i * w_dir + e * w_el];
-      a += v * v;
+    // four independent loads in flight per lane
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int e = lane;
+    for (; e + 192 < len; e += 256) {
+      const double v0 = Wm[i * w_dir + (long)e * w_el];
+      const double v1 = Wm[i * w_dir + (long)(e + 64) * w_el];
+      const double v2 = Wm[i * w_dir + (long)(e + 128) * w_el];
+      const double v3 = Wm[i * w_dir + (long)(e + 192) * w_el];
+      a0 = fma(v0, v0, a0);
+      a1 = fma(v1, v1, a1);
+      a2 = fma(v2, v2, a2);
+      a3 = fma(v3, v3, a3);
     }
-    a = wave_sum(a);
+    for (; e < len; e += 64) {
+      const double v = Wm[i * w_dir + (long)e * w_el];
+      a0 = fma(v, v, a0);
+    }
+    const double a = wave_sum((a0 + a1) + (a2 + a3));
     if (lane == 0) wn[i] = sqrt(a);
   }
   __syncthreads();
@@ -1155,19 +1224,22 @@ void normalize_box(double *T, int n0, int n1, int n2, int n3, long s0, long s1, 
   KTimer kt_("normalize_box", s, 16.0 * n0 * n1 * n2 * n3);
   const long tot = (long)n0 * n1 * n2 * n3;
   if (tot <= 0) return;
-  const int nb = (int)std::min<long>(kNormBlocks, (tot + 255) / 256);
+  if (tot >= (1L << 31)) {
+    set_error("normalize_box: box too large");
+    throw Fail{SPG_ERR_UNSUPPORTED};
+  }
+  // about four elements per thread
+  const int nb = (int)std::min<long>(kNormBlocks, (tot + 1023) / 1024);
   SPG_BC(T);
   SPG_BC(logs);
   SPG_BC(scratch);
   const unsigned nI = (unsigned)g_bc.n;
-  hipLaunchKernelGGL(k_box_sumsq, dim3(nb, nI), dim3(256), 0, s, T, tot, n1, n2, n3, s0, s1, s2,
-                     s3, scratch, g_bc.ist);
+  hipLaunchKernelGGL(k_box_sumsq, dim3(nb, nI), dim3(256), 0, s, T, (unsigned)tot, (unsigned)n1,
+                     (unsigned)n2, (unsigned)n3, s0, s1, s2, s3, scratch, logs, out, in,
+                     g_bc.ist);
   SPG_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_box_fold, dim3(1, nI), dim3(64), 0, s, scratch, nb, logs, out, in,
-                     scratch + kNormBlocks, g_bc.ist);
-  SPG_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_box_scale, dim3(nb, nI), dim3(256), 0, s, T, tot, n1, n2, n3, s0, s1, s2,
-                     s3, scratch + kNormBlocks, g_bc.ist);
+  hipLaunchKernelGGL(k_box_scale, dim3(nb, nI), dim3(256), 0, s, T, (unsigned)tot, (unsigned)n1,
+                     (unsigned)n2, (unsigned)n3, s0, s1, s2, s3, scratch, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 

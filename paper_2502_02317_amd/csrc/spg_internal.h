@@ -130,7 +130,7 @@ void fill_sketch(int n, int l, double *Om, hipStream_t s);
 // Frobenius norm of a 4-index box (n0,n1,n2,n3 with strides) -> scales the box
 // by 1/norm and writes logs[out] = logs[in] + log(norm) (in < 0 means 0).
 // `scratch` holds kNormScratch doubles.
-constexpr int kNormScratch = 160;
+constexpr int kNormScratch = 1040;
 void normalize_box(double *T, int n0, int n1, int n2, int n3, long s0, long s1, long s2,
                    long s3, double *logs, int out, int in, double *scratch, hipStream_t s);
 void fill_zero(double *p, size_t n, hipStream_t s);
