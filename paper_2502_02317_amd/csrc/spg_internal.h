@@ -99,9 +99,9 @@ struct GemmDesc {
 void gemm_f64(const GemmDesc &g, hipStream_t s);
 
 // Launch-shape choices read when work is enqueued (set per instance by the
-// batch driver and its autotuner; process default 64 / split-K on).
+// batch driver and its autotuner; process default 32 / split-K on).
 struct Tuning {
-  int gemm_tile = 64;   // GEMM output tile: 64 or 32
+  int gemm_tile = 32;   // GEMM output tile: 32 or 64
   int splitk = 1;       // deterministic split-K for skinny long-K products
 };
 extern thread_local Tuning g_tune;
