@@ -364,12 +364,11 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
 // workgroup of 16 wavefronts, held in registers: wave w owns columns
 // [w*CPW, (w+1)*CPW) and lane l rows l + 64 t (t < RPL; zero beyond m).
 //
-// Factorisation, step j: the owner of column j forms its reflector
-// H_j = I - tau_j v_j v_j^T (v_j = 1 at row j, zero above; R[j][j] = beta)
-// from its registers and publishes v_j to an LDS slot; after one barrier
-// every wave applies H_j to its own columns k > j (a wave-wide dot product
-// per column, then an axpy).  Slot j mod kRegSlots is rewritten only after
-// kRegSlots further barriers, so one barrier per step suffices.
+// Factorisation, step j: every wave applies H_j = I - tau_j v_j v_j^T
+// (published in an LDS slot) to its own columns k > j, a wave-wide dot product
+// per column, then an axpy; the owner of column j+1 does that column first and
+// publishes the next reflector before the step's one barrier.  Slot j mod
+// kRegSlots is rewritten only after kRegSlots further barriers.
 //
 // Q = H_0 H_1 ... H_{n-1} [I; 0] is formed in place as LAPACK's dorg2r does
 // (backwards; column j turns into H_j e_j once H_j has been applied to the
@@ -467,48 +466,67 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, 
 #pragma unroll
     for (int t = 0; t < RPL; ++t) a[s][t] = ldexp(a[s][t], -ex);
 
-  // ---- factorisation
-  for (int j = 0; j < n; ++j) {
-    double *vj = buf + (j % kRegSlots) * (64 * RPL);
-    if (w == j / CPW) {
-      const int os = j - c0;
+  // ---- factorisation, with lookahead: during step j the owner of column
+  // j+1 applies H_j to that column first, then forms and publishes reflector
+  // j+1 before updating its other columns, so the reflector's serial chain
+  // overlaps the other wavefronts' updates and one barrier ends the step.
+  //
+  // Reflector of column jj (held in `col` by its owner): H = I - tau v v^T
+  // with v = 1 at row jj, zero above, R[jj][jj] = beta; v goes to the LDS slot
+  // of jj and into the column below the diagonal, tau to taus[jj].
+  auto reflect = [&](double (&col)[RPL], int jj) {
+    double sg = 0.0, at = 0.0;
 #pragma unroll
-      for (int s = 0; s < CPW; ++s) {
-        if (s != os) continue;
-        double sg = 0.0, at = 0.0;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int i = lane + 64 * t;
-          const double x = a[s][t];
-          if (i > j) sg = fma(x, x, sg);
-          if (t == (j >> 6)) at = x;
-        }
-        sg = wave_sum(sg);
-        const double al = read_lane(at, j & 63);
-        double tj = 0.0, sc = 0.0, beta = al;
-        if (sg != 0.0) {
-          const double nrm = sqrt(al * al + sg);
-          beta = (al >= 0.0) ? -nrm : nrm;
-          tj = (beta - al) / beta;
-          sc = 1.0 / (al - beta);
-        }
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int i = lane + 64 * t;
-          const double v = (i < j) ? 0.0 : (i == j) ? 1.0 : a[s][t] * sc;
-          vj[i] = v;
-          if (i == j) a[s][t] = beta;
-          else if (i > j) a[s][t] = v;
-        }
-        if (lane == 0) taus[j] = tj;
-      }
+    for (int t = 0; t < RPL; ++t) {
+      const int i = lane + 64 * t;
+      const double x = col[t];
+      if (i > jj) sg = fma(x, x, sg);
+      if (t == (jj >> 6)) at = x;
     }
-    __syncthreads();
+    sg = wave_sum(sg);
+    const double al = read_lane(at, jj & 63);
+    double tj = 0.0, sc = 0.0, beta = al;
+    if (sg != 0.0) {
+      const double nrm = sqrt(al * al + sg);
+      beta = (al >= 0.0) ? -nrm : nrm;
+      tj = (beta - al) / beta;
+      sc = 1.0 / (al - beta);
+    }
+    double *vs = buf + (jj % kRegSlots) * (64 * RPL);
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int i = lane + 64 * t;
+      const double v = (i < jj) ? 0.0 : (i == jj) ? 1.0 : col[t] * sc;
+      vs[i] = v;
+      if (i == jj) col[t] = beta;
+      else if (i > jj) col[t] = v;
+    }
+    if (lane == 0) taus[jj] = tj;
+  };
+  if (w == 0) reflect(a[0], 0);          // column 0 belongs to wavefront 0
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
     const double tj = taus[j];
+    const double *vj = buf + (j % kRegSlots) * (64 * RPL);
+    const int jn = j + 1;
+    const int osn = (jn < n && w == jn / CPW) ? jn - c0 : -1;   // own slot of column j+1
     if (tj != 0.0 && max(c0, j + 1) < min(c0 + CPW, n)) {      // some own column k > j
       double v[RPL];
 #pragma unroll
       for (int t = 0; t < RPL; ++t) v[t] = vj[lane + 64 * t];
+      if (osn >= 0) {
+#pragma unroll
+        for (int s = 0; s < CPW; ++s) {
+          if (s != osn) continue;
+          double dt = 0.0;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) dt = fma(v[t], a[s][t], dt);
+          const double f = -tj * wave_sum(dt);
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) a[s][t] = fma(f, v[t], a[s][t]);
+          reflect(a[s], jn);
+        }
+      }
       double dot[CPW];
 #pragma unroll
       for (int s = 0; s < CPW; ++s) {
@@ -518,16 +536,22 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, 
       }
 #pragma unroll
       for (int s = 0; s < CPW; ++s)
-        if (c0 + s > j && c0 + s < n) dot[s] = wave_sum(dot[s]);
+        if (s != osn && c0 + s > j && c0 + s < n) dot[s] = wave_sum(dot[s]);
 #pragma unroll
       for (int s = 0; s < CPW; ++s) {
-        if (c0 + s > j && c0 + s < n) {
+        if (s != osn && c0 + s > j && c0 + s < n) {
           const double f = -tj * dot[s];
 #pragma unroll
           for (int t = 0; t < RPL; ++t) a[s][t] = fma(f, v[t], a[s][t]);
         }
       }
+    } else if (osn >= 0) {
+      // H_j is the identity here: only the next reflector
+#pragma unroll
+      for (int s = 0; s < CPW; ++s)
+        if (s == osn) reflect(a[s], jn);
     }
+    __syncthreads();
   }
 
   // ---- R (row-major n x n), through the staging tile
