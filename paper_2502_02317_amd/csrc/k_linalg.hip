@@ -397,6 +397,25 @@ __device__ __forceinline__ double read_lane(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
+// Totals over the wave of the CPW per-lane partial sums (uniform results),
+// four at a time.
+template <int CPW>
+__device__ __forceinline__ void wave_sums(const double (&d)[CPW], double (&out)[CPW]) {
+  if constexpr (CPW == 1) {
+    out[0] = wave_sum(d[0]);
+  } else {
+#pragma unroll
+    for (int g = 0; g < CPW; g += 4) {
+      const double r = wave_sum4(d[g], (g + 1 < CPW) ? d[(g + 1) % CPW] : 0.0,
+                                 (g + 2 < CPW) ? d[(g + 2) % CPW] : 0.0,
+                                 (g + 3 < CPW) ? d[(g + 3) % CPW] : 0.0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (g + k < CPW) out[(g + k) % CPW] = read_lane(r, 16 * k);
+    }
+  }
+}
+
 template <int RPL, int CPW>
 __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, long xr, long xc,
                                                 double *Qo, long qr, long qc, double *Rs,
@@ -534,13 +553,12 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, 
 #pragma unroll
         for (int t = 0; t < RPL; ++t) dot[s] = fma(v[t], a[s][t], dot[s]);
       }
-#pragma unroll
-      for (int s = 0; s < CPW; ++s)
-        if (s != osn && c0 + s > j && c0 + s < n) dot[s] = wave_sum(dot[s]);
+      double tot[CPW];
+      wave_sums<CPW>(dot, tot);
 #pragma unroll
       for (int s = 0; s < CPW; ++s) {
         if (s != osn && c0 + s > j && c0 + s < n) {
-          const double f = -tj * dot[s];
+          const double f = -tj * tot[s];
 #pragma unroll
           for (int t = 0; t < RPL; ++t) a[s][t] = fma(f, v[t], a[s][t]);
         }
@@ -605,13 +623,12 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, 
 #pragma unroll
           for (int t = 0; t < RPL; ++t) dot[s] = fma(v[t], a[s][t], dot[s]);
         }
-#pragma unroll
-        for (int s = 0; s < CPW; ++s)
-          if (c0 + s > j && c0 + s < n) dot[s] = wave_sum(dot[s]);
+        double tot[CPW];
+        wave_sums<CPW>(dot, tot);
 #pragma unroll
         for (int s = 0; s < CPW; ++s) {
           if (c0 + s > j && c0 + s < n) {
-            const double f = -tj * dot[s];
+            const double f = -tj * tot[s];
 #pragma unroll
             for (int t = 0; t < RPL; ++t) a[s][t] = fma(f, v[t], a[s][t]);
           }
@@ -751,8 +768,11 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
         b = row16_sum(b);
         g = row16_sum(g);
         if (a > tiny && b > tiny && g * g > 1e-28 * (a * b)) {
-          const double zeta = (b - a) / (2.0 * g);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          // tan of the rotation angle, sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)) with
+          // zeta = (b - a) / 2g, multiplied through by 2|g| (one division; the
+          // prescaling keeps the squares in range)
+          const double dd = b - a;
+          const double tt = (dd >= 0.0 ? 2.0 * g : -2.0 * g) / (fabs(dd) + sqrt(dd * dd + 4.0 * g * g));
           const double cs = rsqrt(1.0 + tt * tt), sn = cs * tt;
 #pragma unroll
           for (int h = 0; h < kJacRows; ++h) {

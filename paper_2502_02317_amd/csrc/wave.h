@@ -41,6 +41,38 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
+// Sums of four values over the wave.  On return row r (lanes 16r..16r+15)
+// holds the total of v_r in every lane (read it with a readlane of lane 16r).
+// A swap between the wave's halves (v0,v2) and (v1,v3), then one between its
+// rows, leave row r with partial sums of v_r alone, so the four totals share
+// one 16-lane DPP sum: 21 instructions instead of four full reductions.
+__device__ __forceinline__ void swap_halves(double &x, double &y) {
+  // x's lanes 32..63 <-> y's lanes 0..31
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(x),
+                                                   (unsigned)__double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(x),
+                                                   (unsigned)__double2hiint(y), false, false);
+  x = __hiloint2double((int)hi[0], (int)lo[0]);
+  y = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ void swap_rows(double &x, double &y) {
+  // x's odd rows <-> y's even rows
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(x),
+                                                   (unsigned)__double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(x),
+                                                   (unsigned)__double2hiint(y), false, false);
+  x = __hiloint2double((int)hi[0], (int)lo[0]);
+  y = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ double wave_sum4(double v0, double v1, double v2, double v3) {
+  swap_halves(v0, v2);          // lanes 0..31: own v0 / partner's v0; 32..63: v2 likewise
+  swap_halves(v1, v3);
+  double a = v0 + v2;           // v0 partials in lanes 0..31, v2 partials in 32..63
+  double b = v1 + v3;           // v1 partials in lanes 0..31, v3 partials in 32..63
+  swap_rows(a, b);              // rows 0..3 of a: v0, v1, v2, v3 partials; b likewise
+  return row16_sum(a + b);
+}
+
 // Max over the wave, returned to every lane (max(x, 0-fill) is safe for the
 // non-negative arguments it is used with).
 __device__ __forceinline__ double wave_max_nonneg(double v) {
