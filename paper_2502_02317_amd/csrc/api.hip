@@ -169,7 +169,6 @@ static int tsvd_left(BmpsWork &w, const double *B, long br, long bc, int m, int 
   const int kk = std::min(k, l);
   double *Om = w.Om.as<double>(), *Y = w.Y.as<double>(), *Q = w.Q.as<double>();
   double *Z = w.Z.as<double>(), *Qz = w.Qz.as<double>(), *Cm = w.Cm.as<double>();
-  fill_sketch(n, l, Om, s);
   auto mm = [&](int M, int N, int K, const double *A, long ai, long ak, const double *Bp, long bk,
                 long bj, double *Cp, long ci, long cj) {
     GemmDesc g{};
@@ -184,7 +183,7 @@ static int tsvd_left(BmpsWork &w, const double *B, long br, long bc, int m, int 
   double *qw = w.qrwork.as<double>();
   // the range-finder panels Y, Z, Q, Qz are column-major (the QR reads and
   // writes them straight from registers)
-  mm(m, l, n, B, br, bc, Om, l, 1, Y, 1, m);                 // Y = B Om
+  mm(m, l, n, B, br, bc, Om, w.lmax, 1, Y, 1, m);            // Y = B Om (Om: stride lmax)
   qr_f64(m, l, Y, 1, m, Q, 1, m, nullptr, qw, s);           // Q = orth(Y)
   for (int it = 0; it < q; ++it) {
     mm(n, l, m, B, bc, br, Q, 1, m, Z, 1, n);                // Z = B^T Q
@@ -236,6 +235,8 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
   w.alloc();
   const size_t site = w.site_sz(), es = w.env_sz();
   set_identity(w.lmax, w.ident.as<double>(), s);
+  // the sketch table, Om[i*lmax + j] for every two-site block of this contraction
+  fill_sketch(chi * d, w.lmax, w.Om.as<double>(), s);
   double *A = env->A.as<double>();
   double *logs = w.logs.as<double>();
   // log slots: EL[c] at c, ER[c] at C+1+c, centre at 2C+2, lam[r] at 2C+4+r
