@@ -142,7 +142,7 @@ def proposal_leg(spg, torch, inst, wl, M, st, en, lp, stream):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - a) * 1e3 / reps
         states = {tuple(x) for x in st[:n].cpu().numpy().tolist()}
-        return ms, states, float(en[0]), spg.search_stats(env)
+        return ms, states, (float(en[0]) if n > 0 else None), spg.search_stats(env)
 
     ms_plain, s_plain, e_plain, st_plain = run()
     ms_g, s_g, e_g, st_g = run(proposal=prop, kappa=2.0)
@@ -232,13 +232,20 @@ def transforms_leg(spg, torch, inst, wl, M, stream):
     bests = []
     for k, (t, back) in enumerate(ts):
         st, en, _, _ = b.result(k)
+        if st.shape[0] == 0:
+            # every child of some step had a non-positive weight: no finite state
+            bests.append(None)
+            continue
         x_old = np.empty_like(st)
         x_old[:, back] = st
         # energies recomputed on the original lattice
         bests.append(float(potts_energy(inst, x_old[:1])[0]))
+    found = [e for e in bests if e is not None]
     return {"orientations": 8, "units": b.units()[0], "one_by_one_s": t_one,
-            "batched_s": t_batch, "speedup": t_one / t_batch, "best_of_8": min(bests),
-            "best_energies": bests, "spread": max(bests) - min(bests)}
+            "batched_s": t_batch, "speedup": t_one / t_batch,
+            "best_of_8": min(found) if found else None, "best_energies": bests,
+            "orientations_without_states": len(bests) - len(found),
+            "spread": (max(found) - min(found)) if found else None}
 
 
 def merge_leg(spg, torch, inst, wl, M, st, en, lp, stream):
@@ -256,7 +263,7 @@ def merge_leg(spg, torch, inst, wl, M, st, en, lp, stream):
         n = spg.branch_and_bound(env, M, st, en, lp, stream=stream, merge_branches=merge)
         torch.cuda.synchronize()
         res[f"search_ms_{label}"] = (time.perf_counter() - a) * 1e3
-        res[f"best_energy_{label}"] = float(en[0])
+        res[f"best_energy_{label}"] = float(en[0]) if n > 0 else None
         res[f"n_states_{label}"] = n
     return res
 
@@ -348,7 +355,8 @@ def main():
     else:
         _, prof = timed(args.precision, True)
         say("profiled pass done")
-    best_E = float(en[0])
+    n_last = step(args.precision)[1]
+    best_E = float(en[0]) if n_last > 0 else None     # None: the beam ended with no finite state
 
     # search-only and boundary-MPS-only split (untimed, same work)
     peps = spg.build_peps(inst, stream)
