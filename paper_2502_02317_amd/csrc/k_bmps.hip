@@ -67,20 +67,6 @@ __global__ void k_T2(int d, int chi, int pl, int ql, const double *T1, const dou
   T2[(((long)p * d + x) * d + y) * chi + q] = acc;
 }
 
-// T[p][x][y][Q] *= w(x) V(x,y)   (box p < n0, Q < n3)
-__global__ void k_scale_wv(int d, int chi, int n0, int n3, const double *w, const double *V,
-                           double *T, long ist) {
-  SPG_INST(w);
-  SPG_INST(V);
-  SPG_INST(T);
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long tot = (long)n0 * d * d * n3;
-  if (e >= tot) return;
-  const int Q = e % n3, y = (e / n3) % d, x = (e / ((long)n3 * d)) % d;
-  const int p = (int)(e / ((long)n3 * d * d));
-  T[(((long)p * d + x) * d + y) * chi + Q] *= w[x] * V[x * d + y];
-}
-
 // G3[p][x][a][q] = sum_y G2[p][x][y][q] Dl[a][y]
 __global__ void k_G3(int d, int chi, int pl, int ql, const double *G2, const double *Dl,
                      double *G3, long ist) {
@@ -279,13 +265,8 @@ void left_part(int d, int chi, int pl, int ql, int qr, const double *EL, const d
   g.B = psi; g.b_k = (long)d * chi; g.b_j = 1; g.b_b1 = chi; g.b_b2 = 0;
   g.C = P; g.c_i = (long)d * chi; g.c_j = 1; g.c_b1 = chi; g.c_b2 = 0;
   g.alpha = 1.0; g.beta = 0.0;
+  g.sw = f.w; g.sV = f.V; g.sd = d; g.smode = 1;        // P[p][x][y][Q] *= w(x) V(x, y)
   gemm_f64(g, s);
-  const long tot2 = (long)pl * d * d * qr;
-  SPG_BC(f.w);
-  SPG_BC(f.V);
-  SPG_BC(P);
-  hipLaunchKernelGGL(k_scale_wv, dim3(nblk(tot2, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, qr, f.w, f.V, P, g_bc.ist);
-  SPG_CHECK_LAUNCH();
 }
 
 void env_left(int d, int chi, int pl, int pr, int qr, const double *phi, const double *P,
@@ -320,13 +301,9 @@ void env_right(int d, int chi, int pl, int pr, int ql, int qr, const double *phi
   h.B = psi; h.b_k = 1; h.b_j = (long)d * chi; h.b_b1 = chi; h.b_b2 = 0;
   h.C = G2; h.c_i = (long)d * chi; h.c_j = 1; h.c_b1 = chi; h.c_b2 = 0;
   h.alpha = 1.0; h.beta = 0.0;
+  h.sw = f.w; h.sV = f.V; h.sd = d; h.smode = 1;        // G2[p][x][y][q] *= w(x) V(x, y)
   gemm_f64(h, s);
   const long tot = (long)pl * d * d * ql;
-  SPG_BC(f.w);
-  SPG_BC(f.V);
-  SPG_BC(G2);
-  hipLaunchKernelGGL(k_scale_wv, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, f.w, f.V, G2, g_bc.ist);
-  SPG_CHECK_LAUNCH();
   double *G3 = G1;  // G1 no longer needed
   SPG_BC(G2);
   SPG_BC(f.Dl);
@@ -354,13 +331,9 @@ void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, cons
   g.B = ER; g.b_k = 1; g.b_j = (long)d * d * chi; g.b_b1 = (long)d * chi; g.b_b2 = chi;
   g.C = Qr; g.c_i = (long)d * d * chi; g.c_j = 1; g.c_b1 = (long)d * chi; g.c_b2 = chi;
   g.alpha = 1.0; g.beta = 0.0;
+  g.sw = f1.w; g.sV = f1.V; g.sd = d; g.smode = 2;      // Qr[q][x][y][P] *= w1(x) V1(x, y)
   gemm_f64(g, s);
   const long totq = (long)qm * d * d * pr;
-  SPG_BC(f1.w);
-  SPG_BC(f1.V);
-  SPG_BC(Qr);
-  hipLaunchKernelGGL(k_scale_wv, dim3(nblk(totq, 256), g_bc.n), dim3(256), 0, s, d, chi, qm, pr, f1.w, f1.V, Qr, g_bc.ist);
-  SPG_CHECK_LAUNCH();
   const long totp = (long)pl * d * d * qm;
   SPG_BC(P);
   SPG_BC(f1.Al);

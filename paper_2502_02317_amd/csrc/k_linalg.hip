@@ -99,16 +99,25 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
     }
     __syncthreads();
   }
+  const double *sw = g.sw ? (const double *)((const char *)g.sw + io) : nullptr;
+  const double *sV = g.sV ? (const double *)((const char *)g.sV + io) : nullptr;
+  const double fb = (g.smode == 2) ? sw[b1] * sV[b1 * g.sd + b2] : 1.0;
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     const int gi = i0 + ty + 16 * i;
     if (gi >= g.M) continue;
+    double f = fb;
+    if (g.smode == 1) {
+      const int x = gi % g.sd;
+      f = sw[x] * sV[x * g.sd + b1];
+    }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const int gj = j0 + tx + 16 * j;
       if (gj >= g.N) continue;
       double *cp = C + gi * g.c_i + gj * g.c_j;
-      const double v = g.alpha * acc[i][j];
+      double v = g.alpha * acc[i][j];
+      if (g.smode) v *= f;
       *cp = (g.beta != 0.0) ? v + g.beta * (*cp) : v;
     }
   }
@@ -1092,6 +1101,12 @@ void gemm_f64(const GemmDesc &g, hipStream_t s) {
   SPG_BC(g.B);
   SPG_BC(g.C);
   SPG_BC(g.ws);
+  SPG_BC(g.sw);
+  SPG_BC(g.sV);
+  if (g.smode != 0 && (g.sw == nullptr || g.sV == nullptr || g.sd <= 0 || g.ws != nullptr)) {
+    set_error("gemm_f64: epilogue factor needs both tables and no split-K workspace");
+    throw Fail{SPG_ERR_INVALID};
+  }
   GemmDesc h = g;
   h.ist = g_bc.ist;
   if ((long)h.nb1 * h.nb2 * g_bc.n > 65535) {

@@ -95,6 +95,11 @@ struct GemmDesc {
   size_t ws_len = 0;
   int kmax = 0;           // internal: global K bound of split-K chunks (0 = K)
   long ist = 0;           // internal: class-batched instance stride (bytes)
+  // optional epilogue factor (the MPO site weights w(x) V(x, y)), d = sd:
+  // smode 1: C(i, j) of batch b1 times w[i % d] V[(i % d) d + b1];
+  // smode 2: every C(i, j) of batch (b1, b2) times w[b1] V[b1 d + b2]
+  const double *sw = nullptr, *sV = nullptr;
+  int sd = 0, smode = 0;
 };
 void gemm_f64(const GemmDesc &g, hipStream_t s);
 
