@@ -272,7 +272,6 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
              w.Rc.as<double>(), w.qrwork.as<double>(), s);                 // Q column-major
       // direction i of M^T = Q R weighs |row i of R|
       drop_null(bl, bl, w.Rc.as<double>(), bl, 1, w.Qc.as<double>(), d * br, (long)d * br, 1, s);
-      fill_zero(phi + c * site, site, s);
       unpack_right(d, chi, bl, br, w.Qc.as<double>(), (long)d * br, 1, phi + c * site, s);
       lq_fold(d, chi, bl, bl, w.Rc.as<double>(), phi + (c - 1) * site, w.tmp.as<double>(), s);
     }
@@ -302,8 +301,7 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
       const int k = std::min(chi, std::min(m, n));
       double *Bm = w.B.as<double>();
       double *phic = phi + c * site, *phin = phi + (c + 1) * site;
-      fill_zero(phic, site, s);
-      fill_zero(phin, site, s);
+      fill_zero(phic, site, s);                    // phi_{c+1} is written whole by unpack_right
       GemmDesc g{};
       g.nb1 = 1; g.nb2 = 1; g.alpha = 1.0; g.beta = 0.0;
       g.ws = w.skws.as<double>(); g.ws_len = w.skws.bytes / sizeof(double);

@@ -147,15 +147,17 @@ __global__ void k_scale_H(int d, int pl, int pr, const double *H1, double *B, lo
   B[e] *= H1[x * d + z];
 }
 
+// The whole padded site dst[chi][d][chi]: entries k < nk, P < pr from src,
+// zero elsewhere.
 __global__ void k_unpack_right(int d, int chi, int nk, int pr, const double *src, long sk,
                                long sj, double *dst, long ist) {
   SPG_INST(src);
   SPG_INST(dst);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long tot = (long)nk * d * pr;
+  const long tot = (long)chi * d * chi;
   if (e >= tot) return;
-  const int P = e % pr, z = (e / pr) % d, k = (int)(e / ((long)pr * d));
-  dst[((long)k * d + z) * chi + P] = src[k * sk + ((long)z * pr + P) * sj];
+  const int P = e % chi, z = (e / chi) % d, k = (int)(e / ((long)chi * d));
+  dst[e] = (k < nk && P < pr) ? src[k * sk + ((long)z * pr + P) * sj] : 0.0;
 }
 
 // tmp[p][x][k] = sum_q phi[p][x][q] R[k][q]  (R row-major k x bl), then copy back
@@ -165,12 +167,13 @@ __global__ void k_lq_fold(int d, int chi, int pl, int bl, int kk, const double *
   SPG_INST(phi);
   SPG_INST(tmp);
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long tot = (long)pl * d * kk;
+  const long tot = (long)pl * d * chi;            // every entry of the padded site
   if (e >= tot) return;
-  const int k = e % kk;
-  const long px = e / kk;
+  const int k = e % chi;
+  const long px = e / chi;
   double acc = 0.0;
-  for (int q = 0; q < bl; ++q) acc += phi[px * chi + q] * R[(long)k * bl + q];
+  if (k < kk)
+    for (int q = 0; q < bl; ++q) acc += phi[px * chi + q] * R[(long)k * bl + q];
   tmp[px * chi + k] = acc;
 }
 
@@ -362,8 +365,7 @@ void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, cons
 
 void unpack_right(int d, int chi, int nk, int pr, const double *src, long sk, long sj,
                   double *dst, hipStream_t s) {
-  const long tot = (long)nk * d * pr;
-  if (tot <= 0) return;
+  const long tot = (long)chi * d * chi;
   SPG_BC(src);
   SPG_BC(dst);
   hipLaunchKernelGGL(k_unpack_right, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, nk, pr, src, sk, sj, dst, g_bc.ist);
@@ -374,8 +376,7 @@ void lq_fold(int d, int chi, int bl, int k, const double *R, double *phi_prev, d
              hipStream_t s) {
   // phi_prev has left dim pl = chi rows at most; fold over all padded rows (zeros stay zero)
   const int pl = chi;
-  const long tot = (long)pl * d * k;
-  fill_zero(tmp, (size_t)chi * d * chi, s);
+  const long tot = (long)pl * d * chi;
   SPG_BC(R);
   SPG_BC(phi_prev);
   SPG_BC(tmp);

@@ -1031,10 +1031,11 @@ __global__ __launch_bounds__(1024) void k_drop_null(int nd, int len, double *Wm,
     if (lane == 0) wn[i] = sqrt(a);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (wid == 0) {
     double m = 0.0;
-    for (int i = 0; i < nd; ++i) m = fmax(m, wn[i]);
-    wmax = m;
+    for (int i = lane; i < nd; i += 64) m = fmax(m, wn[i]);
+    m = wave_max_nonneg(m);
+    if (lane == 0) wmax = m;
   }
   __syncthreads();
   const double thr = 1e-11 * wmax;

@@ -166,7 +166,8 @@ void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, cons
                     const double *ER, const double *psi0, const double *psi1,
                     const RowFactors &f0, const RowFactors &f1, double *T1, double *P,
                     double *Qr, double *P2, double *Q2, double *B, hipStream_t s);
-// dst[k][z][P] (padded chi) = src[k*sk + (z*pr + P)*sj] for k < nk, z < d, P < pr
+// The whole padded site dst[chi][d][chi]: src[k*sk + (z*pr + P)*sj] for k < nk,
+// z < d, P < pr, zero elsewhere.
 void unpack_right(int d, int chi, int nk, int pr, const double *src, long sk, long sj,
                   double *dst, hipStream_t s);
 void lq_fold(int d, int chi, int bl, int k, const double *R, double *phi_prev, double *tmp,
