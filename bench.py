@@ -439,6 +439,11 @@ def main():
     roof["kernel_class"] = dom
     roof["launches_per_step"] = cnt / args.steps
     roof["avg_launch_us"] = tms * 1e3 / max(cnt, 1)
+    if dom in ("qr_f64", "jacobi_svd_f64") and roof["frac"] is not None:
+        # one workgroup per launch at these panel sizes: the rate against the
+        # peak of the one compute unit it occupies (256 on the chip)
+        roof["workgroups_per_launch"] = 1
+        roof["frac_of_one_cu"] = roof["frac"] * 256
 
     dt = {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16"}[args.precision]
     out = {
