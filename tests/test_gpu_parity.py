@@ -233,6 +233,16 @@ def test_search_edge_beam_sizes(M):
         assert abs(en[0] - brute_force(inst)["E_min"]) < 1e-12
 
 
+@pytest.mark.parametrize("M", [2048, 5000])
+def test_search_large_beams(M):
+    """More than 16384 candidates per step (the select reads keys from memory
+    on every radix pass) and, for M = 5000, more than 4096 survivors (the sort
+    runs in global memory rather than LDS)."""
+    inst = random_potts(2, 4, 16, True, seed=31, beta=1.0)
+    ora, peps, env = _import_oracle(inst, 16)
+    _compare_search(inst, ora, env, M)
+
+
 def test_search_cutoff():
     inst = random_potts(2, 3, 3, True, seed=3, beta=2.0)
     ora, peps, env = _import_oracle(inst, 9)
