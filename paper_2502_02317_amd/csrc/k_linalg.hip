@@ -699,9 +699,11 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, 
 // 16-lane DPP row per pair, so a round of up to 48 pairs is one pass and its
 // sums need no LDS.
 //
-// The sorted columns are then checked for orthonormality (1e-13).  Columns
-// at the rounding floor are never rotated and fail it; when everything from
-// the first failing column i0 on has joint norm below 5e-12 of the largest
+// After convergence every pair of columns above the rounding floor passed the
+// rotation test, so only the floor columns (never rotated, last in sorted
+// order) can fail orthonormality: the first of them is the first failing
+// column i0 (without convergence the sorted columns are checked to 1e-13).
+// When everything from i0 on has joint norm below 5e-12 of the largest
 // singular value, every direction orthogonal to the first i0 columns weighs
 // less than half the null threshold of the truncation (1e-11 of the largest
 // weight), so columns i0.. are returned as zeros, which the truncation drops
@@ -749,6 +751,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
   const double tiny = 1e-26 * sh_fro;
   const int grp = tid >> 4, r16 = tid & 15, ngrp = blockDim.x >> 4;
   const int np = le / 2, nc = le - 1;
+  bool converged = false;
   for (int sweep = 0; sweep < 30; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -796,7 +799,10 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
       }
       __syncthreads();
     }
-    if (rotated == 0) break;
+    if (rotated == 0) {
+      converged = true;
+      break;
+    }
     __syncthreads();
   }
   for (int j = wid; j < l; j += nw) {
@@ -808,8 +814,13 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
   __syncthreads();
   // sorted, normalised columns into V (column-major)
   for (int j = wid; j < l; j += nw) {
+    const double nj = nrm[j];
     int rank = 0;
-    for (int i = 0; i < l; ++i) rank += (nrm[i] > nrm[j]) || (nrm[i] == nrm[j] && i < j);
+    for (int base = 0; base < l; base += 64) {
+      const int i = base + lane;
+      const bool before = (i < l) && (nrm[i] > nj || (nrm[i] == nj && i < j));
+      rank += __popcll(__ballot(before));
+    }
     const double inv = (nrm[j] > 0.0) ? 1.0 / nrm[j] : 0.0;
     for (int r = lane; r < l; r += 64) V[rank * l + r] = W[j * l + r] * inv;
     if (lane == 0) {
@@ -822,16 +833,35 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
     first_bad = kk;
   }
   __syncthreads();
-  // only the leading kk columns are used: check those
-  for (int e = wid; e < kk * kk; e += nw) {
-    const int i = e / kk, j = e % kk;
-    if (j > i) continue;
-    double g = 0.0;
-    for (int r = lane; r < l; r += 64) g += V[i * l + r] * V[j * l + r];
-    g = wave_sum(g);
-    if (lane == 0 && fabs(g - (i == j ? 1.0 : 0.0)) > 1e-13) {
-      bad = 1;
-      atomicMin(&first_bad, i);
+  if (converged) {
+    // every pair of columns above the rounding floor passed the rotation test
+    // (|cos| <= 1e-14): only columns at the floor, never rotated, can fail the
+    // check, and in sorted order they come last.  The first of them (norm^2
+    // within twice the floor) starts the tail.
+    if (wid == 0) {
+      int fb = kk;
+      for (int base = 0; base < kk && fb == kk; base += 64) {
+        const int j = base + lane;
+        const unsigned long long hit = __ballot(j < kk && snrm[j] * snrm[j] <= 2.0 * tiny);
+        if (hit) fb = base + __ffsll((long long)hit) - 1;
+      }
+      if (lane == 0 && fb < kk) {
+        bad = 1;
+        first_bad = fb;
+      }
+    }
+  } else {
+    // only the leading kk columns are used: check those
+    for (int e = wid; e < kk * kk; e += nw) {
+      const int i = e / kk, j = e % kk;
+      if (j > i) continue;
+      double g = 0.0;
+      for (int r = lane; r < l; r += 64) g += V[i * l + r] * V[j * l + r];
+      g = wave_sum(g);
+      if (lane == 0 && fabs(g - (i == j ? 1.0 : 0.0)) > 1e-13) {
+        bad = 1;
+        atomicMin(&first_bad, i);
+      }
     }
   }
   __syncthreads();
