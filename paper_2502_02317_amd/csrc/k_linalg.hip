@@ -725,26 +725,34 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
   __shared__ int rotated, bad, first_bad;
   __shared__ double sh_fro, sh_nv;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
-  if (wid == 0) {
-    double a = 0.0;
-    for (int e = lane; e < l * l; e += 64) a = fmax(a, fabs(Rm[e]));
-    a = wave_max_nonneg(a);
-    if (lane == 0) sh_nv = a;
-  }
-  __syncthreads();
   // W column-major with column j = row j of R, i.e. W = R^T (same storage as
   // Rm), times 2^-e with max |R_ij| = m 2^e, 1/2 <= m < 1
+  double mx = 0.0;
+  for (int e = tid; e < l * l; e += blockDim.x) {
+    const double x = Rm[e];
+    W[e] = x;
+    mx = fmax(mx, fabs(x));
+  }
+  mx = wave_max_nonneg(mx);
+  if (lane == 0) hbuf[wid] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int v = 0; v < nw; ++v) t = fmax(t, hbuf[v]);
+    sh_nv = t;
+  }
+  __syncthreads();
   int ex = 0;
   if (sh_nv > 0.0 && sh_nv <= 1.7e308) (void)frexp(sh_nv, &ex);
-  for (int e = tid; e < l * l; e += blockDim.x) W[e] = ldexp(Rm[e], -ex);
-  const int le = (l + 1) & ~1;
-  __syncthreads();
-  if (wid == 0) {
-    double a = 0.0;
-    for (int e = lane; e < l * l; e += 64) a = fma(W[e], W[e], a);
-    a = wave_sum(a);
-    if (lane == 0) sh_fro = a;
+  double ss = 0.0;
+  for (int e = tid; e < l * l; e += blockDim.x) {
+    const double x = ldexp(W[e], -ex);
+    W[e] = x;
+    ss = fma(x, x, ss);
   }
+  const int le = (l + 1) & ~1;
+  ss = block_sum(ss, hbuf);
+  if (tid == 0) sh_fro = ss;
   __syncthreads();
   // columns below 1e-13 |R|_F sit at the rounding floor (the truncation drops
   // such directions anyway): rotating them only shuffles noise
