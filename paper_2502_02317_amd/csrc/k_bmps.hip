@@ -16,6 +16,28 @@ namespace {
 
 inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// sum over k < n, in order, of fa(k) * fb(k) as an fma chain (the rounding of
+// `acc += fa(k) * fb(k)`), with the loads of four iterations in flight
+// before their terms are added.
+template <class FA, class FB>
+__device__ __forceinline__ double fma_chain(int n, const FA &fa, const FB &fb) {
+  double acc = 0.0;
+  int k = 0;
+  for (; k + 3 < n; k += 4) {
+    const double a0 = fa(k), a1 = fa(k + 1), a2 = fa(k + 2), a3 = fa(k + 3);
+    const double b0 = fb(k), b1 = fb(k + 1), b2 = fb(k + 2), b3 = fb(k + 3);
+    acc = fma(a0, b0, acc);
+    acc = fma(a1, b1, acc);
+    acc = fma(a2, b2, acc);
+    acc = fma(a3, b3, acc);
+  }
+  for (; k < n; ++k) acc = fma(fa(k), fb(k), acc);
+  return acc;
+}
+
+// Index of this thread in a flat launch (every box here holds < 2^31 entries).
+__device__ __forceinline__ unsigned flat_id() { return blockIdx.x * blockDim.x + threadIdx.x; }
+
 // phi[p][x][P] = w(x) sum_y V(x,y) psi[p][y][P]
 __global__ void k_init_guess(int d, int chi, int bl, int br, const double *psi, const double *w,
                              const double *V, double *phi, long ist) {
@@ -23,12 +45,12 @@ __global__ void k_init_guess(int d, int chi, int bl, int br, const double *psi, 
   SPG_INST(w);
   SPG_INST(V);
   SPG_INST(phi);
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long tot = (long)bl * d * br;
-  if (e >= tot) return;
-  const int P = e % br, x = (e / br) % d, p = (int)(e / ((long)br * d));
-  double acc = 0.0;
-  for (int y = 0; y < d; ++y) acc += V[x * d + y] * psi[((long)p * d + y) * chi + P];
+  const unsigned e = flat_id();
+  if (e >= (unsigned)(bl * d * br)) return;
+  const int P = e % br, x = (e / br) % d, p = e / (br * d);
+  const double *src = psi + (long)p * d * chi + P;
+  const double acc = fma_chain(d, [&](int y) { return V[x * d + y]; },
+                               [&](int y) { return src[(long)y * chi]; });
   phi[((long)p * d + x) * chi + P] = w[x] * acc;
 }
 
@@ -38,14 +60,13 @@ __global__ void k_T1(int d, int chi, int pl, int ql, const double *EL, const dou
   SPG_INST(EL);
   SPG_INST(Al);
   SPG_INST(T1);
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long tot = (long)pl * d * d * ql;
-  if (e >= tot) return;
-  const int q = e % ql, x = (e / ql) % d, a = (e / ((long)ql * d)) % d;
-  const int p = (int)(e / ((long)ql * d * d));
+  const unsigned e = flat_id();
+  if (e >= (unsigned)(pl * d * d * ql)) return;
+  const int q = e % ql, x = (e / ql) % d, a = (e / (ql * d)) % d;
+  const int p = e / (ql * d * d);
   const double *src = EL + (((long)p * d + a) * d) * chi + q;
-  double acc = 0.0;
-  for (int ee = 0; ee < d; ++ee) acc += Al[x * d + ee] * src[(long)ee * chi];
+  const double acc = fma_chain(d, [&](int ee) { return Al[x * d + ee]; },
+                               [&](int ee) { return src[(long)ee * chi]; });
   T1[(((long)p * d + a) * d + x) * chi + q] = acc;
 }
 
@@ -56,14 +77,13 @@ __global__ void k_T2(int d, int chi, int pl, int ql, const double *T1, const dou
   SPG_INST(Hl);
   SPG_INST(Dl);
   SPG_INST(T2);
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long tot = (long)pl * d * d * ql;
-  if (e >= tot) return;
-  const int q = e % ql, y = (e / ql) % d, x = (e / ((long)ql * d)) % d;
-  const int p = (int)(e / ((long)ql * d * d));
-  double acc = 0.0;
-  for (int a = 0; a < d; ++a)
-    acc += Hl[a * d + x] * Dl[a * d + y] * T1[(((long)p * d + a) * d + x) * chi + q];
+  const unsigned e = flat_id();
+  if (e >= (unsigned)(pl * d * d * ql)) return;
+  const int q = e % ql, y = (e / ql) % d, x = (e / (ql * d)) % d;
+  const int p = e / (ql * d * d);
+  const double *src = T1 + ((long)p * d * d + x) * chi + q;
+  const double acc = fma_chain(d, [&](int a) { return Hl[a * d + x] * Dl[a * d + y]; },
+                               [&](int a) { return src[(long)a * d * chi]; });
   T2[(((long)p * d + x) * d + y) * chi + q] = acc;
 }
 
@@ -73,14 +93,13 @@ __global__ void k_G3(int d, int chi, int pl, int ql, const double *G2, const dou
   SPG_INST(G2);
   SPG_INST(Dl);
   SPG_INST(G3);
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long tot = (long)pl * d * d * ql;
-  if (e >= tot) return;
-  const int q = e % ql, a = (e / ql) % d, x = (e / ((long)ql * d)) % d;
-  const int p = (int)(e / ((long)ql * d * d));
+  const unsigned e = flat_id();
+  if (e >= (unsigned)(pl * d * d * ql)) return;
+  const int q = e % ql, a = (e / ql) % d, x = (e / (ql * d)) % d;
+  const int p = e / (ql * d * d);
   const double *src = G2 + (((long)p * d + x) * d) * chi + q;
-  double acc = 0.0;
-  for (int y = 0; y < d; ++y) acc += Dl[a * d + y] * src[(long)y * chi];
+  const double acc = fma_chain(d, [&](int y) { return Dl[a * d + y]; },
+                               [&](int y) { return src[(long)y * chi]; });
   G3[(((long)p * d + x) * d + a) * chi + q] = acc;
 }
 
@@ -91,14 +110,13 @@ __global__ void k_ERfin(int d, int chi, int pl, int ql, const double *G3, const 
   SPG_INST(Hl);
   SPG_INST(Al);
   SPG_INST(ER);
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long tot = (long)pl * d * d * ql;
-  if (e >= tot) return;
-  const int q = e % ql, ee = (e / ql) % d, a = (e / ((long)ql * d)) % d;
-  const int p = (int)(e / ((long)ql * d * d));
-  double acc = 0.0;
-  for (int x = 0; x < d; ++x)
-    acc += Hl[a * d + x] * Al[x * d + ee] * G3[(((long)p * d + x) * d + a) * chi + q];
+  const unsigned e = flat_id();
+  if (e >= (unsigned)(pl * d * d * ql)) return;
+  const int q = e % ql, ee = (e / ql) % d, a = (e / (ql * d)) % d;
+  const int p = e / (ql * d * d);
+  const double *src = G3 + ((long)p * d * d + a) * chi + q;
+  const double acc = fma_chain(d, [&](int x) { return Hl[a * d + x] * Al[x * d + ee]; },
+                               [&](int x) { return src[(long)x * d * chi]; });
   ER[(((long)p * d + a) * d + ee) * chi + q] = acc;
 }
 
@@ -108,14 +126,13 @@ __global__ void k_P2(int d, int chi, int pl, int nq, const double *P, const doub
   SPG_INST(P);
   SPG_INST(A1);
   SPG_INST(P2);
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long tot = (long)pl * d * d * nq;
-  if (e >= tot) return;
-  const int Q = e % nq, z = (e / nq) % d, x = (e / ((long)nq * d)) % d;
-  const int p = (int)(e / ((long)nq * d * d));
+  const unsigned e = flat_id();
+  if (e >= (unsigned)(pl * d * d * nq)) return;
+  const int Q = e % nq, z = (e / nq) % d, x = (e / (nq * d)) % d;
+  const int p = e / (nq * d * d);
   const double *src = P + (((long)p * d + x) * d) * chi + Q;
-  double acc = 0.0;
-  for (int y = 0; y < d; ++y) acc += A1[z * d + y] * src[(long)y * chi];
+  const double acc = fma_chain(d, [&](int y) { return A1[z * d + y]; },
+                               [&](int y) { return src[(long)y * chi]; });
   P2[(((long)p * d + x) * d + z) * chi + Q] = acc;
 }
 
@@ -125,14 +142,13 @@ __global__ void k_Q2(int d, int chi, int nq, int pr, const double *Qr, const dou
   SPG_INST(Qr);
   SPG_INST(D1);
   SPG_INST(Q2);
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long tot = (long)nq * d * d * pr;
-  if (e >= tot) return;
-  const int P = e % pr, z = (e / pr) % d, x = (e / ((long)pr * d)) % d;
-  const int Q = (int)(e / ((long)pr * d * d));
+  const unsigned e = flat_id();
+  if (e >= (unsigned)(nq * d * d * pr)) return;
+  const int P = e % pr, z = (e / pr) % d, x = (e / (pr * d)) % d;
+  const int Q = e / (pr * d * d);
   const double *src = Qr + (((long)Q * d + z) * d) * chi + P;
-  double acc = 0.0;
-  for (int v = 0; v < d; ++v) acc += D1[x * d + v] * src[(long)v * chi];
+  const double acc = fma_chain(d, [&](int v) { return D1[x * d + v]; },
+                               [&](int v) { return src[(long)v * chi]; });
   Q2[(((long)Q * d + x) * d + z) * chi + P] = acc;
 }
 
@@ -173,7 +189,8 @@ __global__ void k_lq_fold(int d, int chi, int pl, int bl, int kk, const double *
   const long px = e / chi;
   double acc = 0.0;
   if (k < kk)
-    for (int q = 0; q < bl; ++q) acc += phi[px * chi + q] * R[(long)k * bl + q];
+    acc = fma_chain(bl, [&](int q) { return phi[px * chi + q]; },
+                    [&](int q) { return R[(long)k * bl + q]; });
   tmp[px * chi + k] = acc;
 }
 
