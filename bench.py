@@ -40,7 +40,7 @@ FLOP_CLASSES = {"gemm_f64", "qr_f64", "right_env", "marginals", "beam_update"}
 BYTE_CLASSES = {"normalize_box", "select_topm"}
 
 
-CLASS_KERNEL = {"gemm_f64": "k_gemm<64>", "qr_f64": "k_qr_reg<8, 3>", "jacobi_svd_f64": "k_jacobi",
+CLASS_KERNEL = {"gemm_f64": "k_gemm<32>", "qr_f64": "k_qr_reg<8, 3>", "jacobi_svd_f64": "k_jacobi<3>",
                 "normalize_box": "k_box_scale", "right_env": "k_right_env",
                 "marginals": "k_marginals", "select_topm": "k_select",
                 "beam_update": "k_beam_update", "final_sort": "k_final_sort"}

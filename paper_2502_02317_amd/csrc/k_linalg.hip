@@ -56,11 +56,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
   // unit stride, so tile loads are contiguous for either operand layout
   const bool a_rows = (g.a_i == 1 && g.a_k != 1);      // A column-major: i fastest
   const bool b_cols = (g.b_k == 1 && g.b_j != 1);      // B column-major: k fastest
-  for (int k0 = 0; k0 < Kend; k0 += KS) {
-    // every load of the step is issued before any is used: out-of-range
-    // elements read a valid address (the operand's first element) and are
-    // replaced by zero, so no branch separates the loads
-    double va[NQ], vb[NQ];
+  // every load of a step is issued before any is used, and the loads of the
+  // next step are in flight while this one is multiplied: out-of-range
+  // elements read a valid address (the operand's first element) and are
+  // replaced by zero, so no branch separates the loads
+  double va[NQ], vb[NQ];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int e = tid + 256 * q;
@@ -75,6 +76,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
       const double xb = B[okb ? (long)gkb * g.b_k + (long)gj * g.b_j : 0L];
       vb[q] = okb ? xb : 0.0;
     }
+  };
+  if (Kend > 0) fetch(0);
+  for (int k0 = 0; k0 < Kend; k0 += KS) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int e = tid + 256 * q;
@@ -84,6 +88,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
       Bs[kb][cb] = vb[q];
     }
     __syncthreads();
+    if (k0 + KS < Kend) fetch(k0 + KS);
     const int kn = min(KS, Kend - k0);
 #pragma unroll 8
     for (int kk = 0; kk < kn; ++kk) {
@@ -128,10 +133,19 @@ __global__ void k_splitk_reduce(int M, int N, int S, const double *P, double *C,
                                 long c_j, double alpha, double beta, long ist) {
   SPG_INST(P);
   SPG_INST(C);
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (e >= (long)M * N) return;
+  const unsigned e = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned mn = (unsigned)(M * N);
+  if (e >= mn) return;
+  // chunks summed in order, four loads in flight (clamped to the last chunk)
   double acc = 0.0;
-  for (int s = 0; s < S; ++s) acc += P[(long)s * M * N + e];
+  for (int s0 = 0; s0 < S; s0 += 4) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = P[(long)min(s0 + k, S - 1) * mn + e];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (s0 + k < S) acc += v[k];
+  }
   const int i = (int)(e / N), j = (int)(e % N);
   double *cp = C + i * c_i + j * c_j;
   const double v = alpha * acc;
@@ -709,9 +723,11 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, 
 // weight), so columns i0.. are returned as zeros, which the truncation drops
 // like any such direction.  Otherwise the columns are re-orthonormalised by
 // CGS2 in sorted order with a deterministic completion from the unit vectors.
-constexpr int kJacRows = kMaxSketch / 16;     // rows per lane of a pair group
+constexpr int kJacRows = kMaxSketch / 16;     // most rows per lane of a pair group
 constexpr double kJacTail = 5e-12;
 
+// NR = rows per lane of a pair group, ceil(l / 16)
+template <int NR>
 __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm, double *Vo,
                                                 double *sig, long ist) {
   SPG_INST(Rm);
@@ -773,10 +789,10 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
         }
         if (p > q) { const int tmp = p; p = q; q = tmp; }
         if (q >= l) continue;
-        double x[kJacRows], y[kJacRows];
+        double x[NR], y[NR];
         double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
-        for (int h = 0; h < kJacRows; ++h) {
+        for (int h = 0; h < NR; ++h) {
           const int r = r16 + 16 * h;
           x[h] = (r < l) ? W[p * l + r] : 0.0;
           y[h] = (r < l) ? W[q * l + r] : 0.0;
@@ -788,14 +804,18 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
         b = row16_sum(b);
         g = row16_sum(g);
         if (a > tiny && b > tiny && g * g > 1e-28 * (a * b)) {
-          // tan of the rotation angle, sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)) with
-          // zeta = (b - a) / 2g, multiplied through by 2|g| (one division; the
-          // prescaling keeps the squares in range)
+          // tan of the rotation angle is t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2))
+          // with zeta = (b - a) / 2g; multiplied through by 2|g| it is
+          // t = g2 / den, g2 = sgn(b - a) 2g, den = |b - a| + sqrt((b - a)^2 + 4g^2),
+          // so cos = den / sqrt(den^2 + g2^2) and sin = g2 / sqrt(den^2 + g2^2):
+          // no division (the prescaling keeps the squares in range)
           const double dd = b - a;
-          const double tt = (dd >= 0.0 ? 2.0 * g : -2.0 * g) / (fabs(dd) + sqrt(dd * dd + 4.0 * g * g));
-          const double cs = rsqrt(1.0 + tt * tt), sn = cs * tt;
+          const double g2 = (dd >= 0.0) ? 2.0 * g : -2.0 * g;
+          const double den = fabs(dd) + sqrt(fma(dd, dd, g2 * g2));
+          const double hn = rsqrt(fma(den, den, g2 * g2));
+          const double cs = den * hn, sn = g2 * hn;
 #pragma unroll
-          for (int h = 0; h < kJacRows; ++h) {
+          for (int h = 0; h < NR; ++h) {
             const int r = r16 + 16 * h;
             if (r < l) {
               W[p * l + r] = cs * x[h] - sn * y[h];
@@ -1304,7 +1324,15 @@ void jacobi_svd_f64(int l, int kk, const double *Rm, double *V, double *sig, hip
     set_error("jacobi_svd_f64: kk must be in 1..l");
     throw Fail{SPG_ERR_INVALID};
   }
-  hipLaunchKernelGGL(k_jacobi, dim3(1, g_bc.n), dim3(1024), 0, s, l, kk, Rm, V, sig, g_bc.ist);
+  const dim3 grid(1, g_bc.n);
+  switch ((l + 15) / 16) {
+    case 1: hipLaunchKernelGGL(k_jacobi<1>, grid, dim3(1024), 0, s, l, kk, Rm, V, sig, g_bc.ist); break;
+    case 2: hipLaunchKernelGGL(k_jacobi<2>, grid, dim3(1024), 0, s, l, kk, Rm, V, sig, g_bc.ist); break;
+    case 3: hipLaunchKernelGGL(k_jacobi<3>, grid, dim3(1024), 0, s, l, kk, Rm, V, sig, g_bc.ist); break;
+    case 4: hipLaunchKernelGGL(k_jacobi<4>, grid, dim3(1024), 0, s, l, kk, Rm, V, sig, g_bc.ist); break;
+    case 5: hipLaunchKernelGGL(k_jacobi<5>, grid, dim3(1024), 0, s, l, kk, Rm, V, sig, g_bc.ist); break;
+    default: hipLaunchKernelGGL(k_jacobi<kJacRows>, grid, dim3(1024), 0, s, l, kk, Rm, V, sig, g_bc.ist); break;
+  }
   SPG_CHECK_LAUNCH();
 }
 
