@@ -163,6 +163,103 @@ __global__ __launch_bounds__(256) void k_marginals_lp(SearchTabs t, int r, int c
   }
 }
 
+// The same conditionals with the site tensor staged in LDS once per
+// workgroup (when its cl x d x cr block fits): all 64 lanes of a beam's wave
+// take (al, s) pairs, u[al][s] = sum_b A[al][s][b] R[b] in b order with eight
+// pairs in flight per lane, then lane s sums L[al] u[al][s] in al order.
+// Every sum runs in the same order as above, so the results are identical.
+constexpr int kMargLds = 32 * 16 * 33;     // floats of the staged block, cl * d * (cr + 1)
+constexpr int kMargU = 32 * 16;            // per-wave u[al][s], cl * d
+
+__host__ __device__ constexpr bool marg_lds_fits(int cl, int d, int cr) {
+  return d <= 64 && cr <= 64 && cl * d <= kMargU && cl * d * (cr + 1) <= kMargLds;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_marginals_lp_lds(SearchTabs t, int r, int c, int n_beam,
+                                                          const uint8_t *cfg, int N, const T *A,
+                                                          const float *L, const int32_t *anc,
+                                                          const float *Rv, long rstride,
+                                                          const double *score, double *out,
+                                                          int add_score, int cl, int cr) {
+  __shared__ float As[kMargLds];
+  __shared__ float us[kW][kMargU];
+  __shared__ float Ls[kW][kMaxChi];
+  __shared__ float Rs[kW][kMaxChi];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int b0 = blockIdx.x * kW + w;
+  const bool valid = b0 < n_beam;
+  const int b = valid ? b0 : 0;
+  const int chi = t.chi, d = t.d;
+  const int npair = cl * d, ldr = cr + 1;
+  // A[al][s][0..cr) -> As[(al*d + s)*ldr + .]: each wave copies whole rows,
+  // 64 / cr rows per pass, eight rows' loads in flight
+  {
+    const int rpp = 64 / cr, sub = lane / cr, bb = lane - sub * cr;
+    if (sub < rpp) {
+      const int step = kW * rpp;
+      int p = w * rpp + sub;
+      for (; p + 7 * step < npair; p += 8 * step) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = ld(A, (long)(p + k * step) * chi + bb);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) As[(p + k * step) * ldr + bb] = v[k];
+      }
+      for (; p < npair; p += step) As[p * ldr + bb] = ld(A, (long)p * chi + bb);
+    }
+  }
+  if (valid) {
+    const float *Rn = Rv + (long)anc[b] * rstride + (long)(c + 1) * chi;
+    for (int i = lane; i < chi; i += 64) {
+      Ls[w][i] = L[(long)b * chi + i];
+      Rs[w][i] = Rn[i];
+    }
+  }
+  __syncthreads();
+  if (valid) {
+    for (int p0 = 0; p0 < npair; p0 += 64 * 8) {
+      float u[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) u[k] = 0.f;
+      const int pl = p0 + lane;
+      for (int bb = 0; bb < cr; ++bb) {
+        const float rb = Rs[w][bb];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (pl + 64 * k < npair) u[k] = fmaf(As[(pl + 64 * k) * ldr + bb], rb, u[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (pl + 64 * k < npair) us[w][pl + 64 * k] = u[k];
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+  const uint8_t *cb = cfg + (long)b * N;
+  float lq = -INFINITY;
+  const int s = lane;
+  if (s < d) {
+    float acc = 0.f;
+    for (int al = 0; al < cl; ++al) {
+      const float la = Ls[w][al];
+      if (la == 0.f) continue;
+      acc = fmaf(la, us[w][al * d + s], acc);
+    }
+    // negative q (truncation error) = probability 0
+    lq = (acc > 0.f) ? (float)log_field(t, r, c, cb, s) + logf(acc) : -INFINITY;
+  }
+  const float mx = wave_max_f(lq);
+  float se = (s < d && lq > -INFINITY) ? expf(lq - mx) : 0.f;
+  se = wave_sum_f(se);
+  const float lse = mx + logf(se);
+  if (s < d) {
+    const double base = add_score ? score[b] : 0.0;
+    const float lp = (lq > -INFINITY && mx > -INFINITY) ? lq - lse : -INFINITY;
+    out[(long)b * d + s] = base + (double)lp;
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_beam_update_lp(SearchTabs t, int r, int c, int n_new,
                                                         const int32_t *sel, int N,
@@ -310,6 +407,18 @@ void lp_marginals(const SearchTabs &t, int precision, int r, int c, int n_beam,
   bc_single("lp_marginals");
   if (n_beam <= 0) return;
   KTimer kt_("marginals", s, 2.0 * n_beam * t.d * cl * cr);
+  if (cl > 0 && cr > 0 && marg_lds_fits(cl, t.d, cr)) {
+    if (precision == SPG_FP32)
+      hipLaunchKernelGGL(k_marginals_lp_lds<float>, dim3(nblk(n_beam, kW)), dim3(256), 0, s, t, r,
+                         c, n_beam, cfg, N, (const float *)A_rc, L, anc, Rv, rstride, score, out,
+                         add_score, cl, cr);
+    else
+      hipLaunchKernelGGL(k_marginals_lp_lds<uint16_t>, dim3(nblk(n_beam, kW)), dim3(256), 0, s, t,
+                         r, c, n_beam, cfg, N, (const uint16_t *)A_rc, L, anc, Rv, rstride, score,
+                         out, add_score, cl, cr);
+    SPG_CHECK_LAUNCH();
+    return;
+  }
   if (precision == SPG_FP32)
     hipLaunchKernelGGL(k_marginals_lp<float>, dim3(nblk(n_beam, kW)), dim3(256), 0, s, t, r, c,
                        n_beam, cfg, N, (const float *)A_rc, L, anc, Rv, rstride, score, out,
