@@ -133,6 +133,113 @@ __global__ __launch_bounds__(256) void k_marginals(SearchTabs t, int r, int c, i
   }
 }
 
+// The same conditionals with the site tensor staged in LDS once per
+// workgroup (when its cl x d x cr block fits): every lane of a beam's
+// wavefront takes (al, s) pairs, u[al][s] = sum_b A[al][s][b] R[b] in b order,
+// four pairs in flight per lane, then lane s sums L[al] u[al][s] in al order.
+// Every sum runs in the same order as above, so the results are identical.
+constexpr int kMargLds = 32 * 16 * 33;     // doubles of the staged block, cl * d * (cr + 1)
+constexpr int kMargU = 32 * 16;            // per-wave u[al][s], cl * d
+
+__host__ __device__ constexpr bool marg_lds_fits(int cl, int d, int cr) {
+  return d <= 64 && cr <= 64 && cl * d <= kMargU && cl * d * (cr + 1) <= kMargLds;
+}
+
+__global__ __launch_bounds__(256) void k_marginals_lds(SearchTabs t, int r, int c, int n_beam,
+                                                       const uint8_t *cfg, int N, const double *A,
+                                                       const double *L, const int32_t *anc,
+                                                       const double *Rv, long rstride,
+                                                       const double *score, double *out,
+                                                       int add_score, int cl, int cr, long ist) {
+  SPG_INST(cfg);
+  SPG_INST(A);
+  SPG_INST(L);
+  SPG_INST(anc);
+  SPG_INST(Rv);
+  SPG_INST(score);
+  SPG_INST(out);
+  shift_tabs(t, ist);
+  __shared__ double As[kMargLds];
+  __shared__ double us[kWaves][kMargU];
+  __shared__ double Ls[kWaves][kMaxChi];
+  __shared__ double Rs[kWaves][kMaxChi];
+  __shared__ double qs[kWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b0 = blockIdx.x * kWaves + w;
+  const bool valid = b0 < n_beam;
+  const int b = valid ? b0 : 0;
+  const int chi = t.chi, d = t.d;
+  const int npair = cl * d, ldr = cr + 1;
+  // A[al][s][0..cr) -> As[(al*d + s)*ldr + .]: each wavefront copies whole
+  // rows, 64 / cr rows per pass, eight rows' loads in flight
+  {
+    const int rpp = 64 / cr, sub = lane / cr, bb = lane - sub * cr;
+    if (sub < rpp) {
+      const int step = kWaves * rpp;
+      int p = w * rpp + sub;
+      for (; p + 7 * step < npair; p += 8 * step) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = A[(long)(p + k * step) * chi + bb];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) As[(p + k * step) * ldr + bb] = v[k];
+      }
+      for (; p < npair; p += step) As[p * ldr + bb] = A[(long)p * chi + bb];
+    }
+  }
+  if (valid) {
+    const double *Rn = Rv + (long)anc[b] * rstride + (long)(c + 1) * chi;
+    for (int i = lane; i < chi; i += 64) {
+      Ls[w][i] = L[(long)b * chi + i];
+      Rs[w][i] = Rn[i];
+    }
+  }
+  __syncthreads();
+  if (valid) {
+    for (int p0 = 0; p0 < npair; p0 += 64 * 4) {
+      double u[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u[k] = 0.0;
+      const int pl = p0 + lane;
+      for (int bb = 0; bb < cr; ++bb) {
+        const double rb = Rs[w][bb];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (pl + 64 * k < npair) u[k] = fma(As[(pl + 64 * k) * ldr + bb], rb, u[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (pl + 64 * k < npair) us[w][pl + 64 * k] = u[k];
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+  const uint8_t *cb = cfg + (long)b * N;
+  double part = 0.0;
+  const int s = lane;
+  if (s < d) {
+    double acc = 0.0;
+    for (int al = 0; al < cl; ++al) {
+      const double la = Ls[w][al];
+      if (la == 0.0) continue;
+      acc = fma(la, us[w][al * d + s], acc);
+    }
+    double q = field(t, r, c, cb, s) * acc;
+    q = (q > 0.0) ? q : 0.0;               // negative q (truncation error) = probability 0
+    qs[w][s] = q;
+    part = q;
+  }
+  const double tot = wave_sum(part);
+  const double base = add_score ? score[b] : 0.0;
+  const double ltot = log(tot);
+  if (s < d) {
+    const double q = qs[w][s];
+    double lp = (q > 0.0 && tot > 0.0) ? log(q) - ltot : -INFINITY;
+    if (!(lp == lp)) lp = -INFINITY;
+    out[(long)b * d + s] = base + lp;
+  }
+}
+
 // Top-M of n scores by (score desc, id asc), written to sel[0..min(M,n)-1] in
 // that order, with the selected scores in sel_score (may be null).  Candidate
 // i has score cand[i] and id cid[i] (cid null: id = i; ids must be unique and
@@ -660,7 +767,12 @@ void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg
   SPG_BC(score);
   SPG_BC(out);
   bc_check_tabs(t);
-  hipLaunchKernelGGL(k_marginals, dim3(nblk(n_beam, kWaves), g_bc.n), dim3(256), 0, s, t, r, c, n_beam, cfg, N, A_rc, L, anc, Rv, rstride, score, out, add_score, g_bc.ist);
+  if (cl > 0 && cr > 0 && marg_lds_fits(cl, t.d, cr))
+    hipLaunchKernelGGL(k_marginals_lds, dim3(nblk(n_beam, kWaves), g_bc.n), dim3(256), 0, s, t, r,
+                       c, n_beam, cfg, N, A_rc, L, anc, Rv, rstride, score, out, add_score, cl, cr,
+                       g_bc.ist);
+  else
+    hipLaunchKernelGGL(k_marginals, dim3(nblk(n_beam, kWaves), g_bc.n), dim3(256), 0, s, t, r, c, n_beam, cfg, N, A_rc, L, anc, Rv, rstride, score, out, add_score, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
