@@ -74,6 +74,96 @@ __global__ __launch_bounds__(256) void k_right_env(SearchTabs t, int r, int c, i
   if (scale && lane == 0) scale[(long)a * sstride] = m;
 }
 
+// The same right environments with the site tensor staged in LDS once per
+// workgroup (when its cl x d x cr block fits, see marg_lds_fits): every lane of
+// an ancestor's wavefront takes (al, s) pairs, u[al][s] = sum_b A[al][s][b] R[b]
+// in b order, then lane al sums g(s) u[al][s] in s order; rows al >= cl are
+// zero as before.  The same order of terms as k_right_env: identical results.
+constexpr int kEnvLds = 32 * 16 * 33;      // doubles of the staged block, cl * d * (cr + 1)
+constexpr int kEnvU = 32 * 16;             // per-wave u[al][s], cl * d
+
+__host__ __device__ constexpr bool env_lds_fits(int cl, int d, int cr) {
+  return d <= 64 && cr <= 64 && cl * d <= kEnvU && cl * d * (cr + 1) <= kEnvLds;
+}
+
+__global__ __launch_bounds__(256) void k_right_env_lds(SearchTabs t, int r, int c, int n_anc,
+                                                       const uint8_t *cfg, int N, const double *A,
+                                                       const double *Rnext, double *Rout,
+                                                       long rstride, double *scale, int sstride,
+                                                       int cl, int cr, long ist) {
+  SPG_INST(cfg);
+  SPG_INST(A);
+  SPG_INST(Rnext);
+  SPG_INST(Rout);
+  SPG_INST(scale);
+  shift_tabs(t, ist);
+  __shared__ double As[kEnvLds];
+  __shared__ double us[kWaves][kEnvU];
+  __shared__ double Rs[kWaves][kMaxChi];
+  __shared__ double gs[kWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int a0 = blockIdx.x * kWaves + w;
+  const bool valid = a0 < n_anc;
+  const int a = valid ? a0 : 0;
+  const int chi = t.chi, d = t.d;
+  const int npair = cl * d, ldr = cr + 1;
+  {
+    const int rpp = 64 / cr, sub = lane / cr, bb = lane - sub * cr;
+    if (sub < rpp) {
+      const int step = kWaves * rpp;
+      int p = w * rpp + sub;
+      for (; p + 7 * step < npair; p += 8 * step) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = A[(long)(p + k * step) * chi + bb];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) As[(p + k * step) * ldr + bb] = v[k];
+      }
+      for (; p < npair; p += step) As[p * ldr + bb] = A[(long)p * chi + bb];
+    }
+  }
+  const uint8_t *cb = cfg + (long)a * N;
+  if (valid) {
+    for (int i = lane; i < chi; i += 64) Rs[w][i] = Rnext[a * rstride + i];
+    if (lane < d) gs[w][lane] = field(t, r, c, cb, lane);
+  }
+  __syncthreads();
+  if (valid) {
+    for (int p0 = 0; p0 < npair; p0 += 64 * 4) {
+      double u[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u[k] = 0.0;
+      const int pl = p0 + lane;
+      for (int b = 0; b < cr; ++b) {
+        const double rb = Rs[w][b];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (pl + 64 * k < npair) u[k] = fma(As[(pl + 64 * k) * ldr + b], rb, u[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (pl + 64 * k < npair) us[w][pl + 64 * k] = u[k];
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+  double v[2] = {0.0, 0.0};
+  for (int h = 0; h < 2; ++h) {
+    const int al = lane + 64 * h;
+    if (al >= cl) continue;
+    double acc = 0.0;
+    for (int s = 0; s < d; ++s) acc = fma(gs[w][s], us[w][al * d + s], acc);
+    v[h] = acc;
+  }
+  const double m = wave_max_nonneg(fmax(fabs(v[0]), fabs(v[1])));
+  const double inv = (m > 0.0) ? 1.0 / m : 1.0;
+  for (int h = 0; h < 2; ++h) {
+    const int al = lane + 64 * h;
+    if (al < chi) Rout[a * rstride + al] = v[h] * inv;
+  }
+  if (scale && lane == 0) scale[(long)a * sstride] = m;
+}
+
 // out[b*d + s] = (add_score ? score[b] : 0) + log p(s | b)
 __global__ __launch_bounds__(256) void k_marginals(SearchTabs t, int r, int c, int n_beam,
                                                    const uint8_t *cfg, int N, const double *A,
@@ -749,7 +839,12 @@ void right_env_col(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *
   SPG_BC(Rout);
   SPG_BC(scale);
   bc_check_tabs(t);
-  hipLaunchKernelGGL(k_right_env, dim3(nblk(n_anc, kWaves), g_bc.n), dim3(256), 0, s, t, r, c, n_anc, cfg, N, A_rc, Rnext, Rout, rstride, scale, sstride, g_bc.ist);
+  if (cl > 0 && cr > 0 && env_lds_fits(cl, t.d, cr))
+    hipLaunchKernelGGL(k_right_env_lds, dim3(nblk(n_anc, kWaves), g_bc.n), dim3(256), 0, s, t, r,
+                       c, n_anc, cfg, N, A_rc, Rnext, Rout, rstride, scale, sstride, cl, cr,
+                       g_bc.ist);
+  else
+    hipLaunchKernelGGL(k_right_env, dim3(nblk(n_anc, kWaves), g_bc.n), dim3(256), 0, s, t, r, c, n_anc, cfg, N, A_rc, Rnext, Rout, rstride, scale, sstride, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 

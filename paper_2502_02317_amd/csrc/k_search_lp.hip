@@ -106,6 +106,93 @@ __global__ __launch_bounds__(256) void k_right_env_lp(SearchTabs t, int r, int c
 }
 
 // out[b*d+s] = (add_score ? score[b] : 0) + log p(s | b)
+// The same with the site tensor staged in LDS once per workgroup (when its
+// cl x d x cr block fits): every lane of an ancestor's wavefront takes
+// (al, s) pairs, u[al][s] = sum_b A[al][s][b] R[b] in b order, then lane al
+// sums g(s) u[al][s] in s order; rows al >= cl are zero as before.  The same
+// order of terms as k_right_env_lp: identical results.
+constexpr int kEnvLds = 32 * 16 * 33;      // floats of the staged block, cl * d * (cr + 1)
+constexpr int kEnvU = 32 * 16;             // per-wave u[al][s], cl * d
+
+__host__ __device__ constexpr bool env_lds_fits(int cl, int d, int cr) {
+  return d <= 64 && cr <= 64 && cl * d <= kEnvU && cl * d * (cr + 1) <= kEnvLds;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_right_env_lp_lds(SearchTabs t, int r, int c, int n_anc,
+                                                          const uint8_t *cfg, int N, const T *A,
+                                                          const float *Rnext, float *Rout,
+                                                          long rstride, int bf16, int cl, int cr) {
+  __shared__ float As[kEnvLds];
+  __shared__ float us[kW][kEnvU];
+  __shared__ float Rs[kW][kMaxChi];
+  __shared__ float gs[kW][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int a0 = blockIdx.x * kW + w;
+  const bool valid = a0 < n_anc;
+  const int a = valid ? a0 : 0;
+  const int chi = t.chi, d = t.d;
+  const int npair = cl * d, ldr = cr + 1;
+  {
+    const int rpp = 64 / cr, sub = lane / cr, bb = lane - sub * cr;
+    if (sub < rpp) {
+      const int step = kW * rpp;
+      int p = w * rpp + sub;
+      for (; p + 7 * step < npair; p += 8 * step) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = ld(A, (long)(p + k * step) * chi + bb);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) As[(p + k * step) * ldr + bb] = v[k];
+      }
+      for (; p < npair; p += step) As[p * ldr + bb] = ld(A, (long)p * chi + bb);
+    }
+  }
+  const uint8_t *cb = cfg + (long)a * N;
+  // couplings relative to their largest value over s
+  double lg = (lane < d) ? log_field(t, r, c, cb, lane) : -INFINITY;
+  double lmax = lg;
+  for (int o = 32; o > 0; o >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, o, 64));
+  if (valid) {
+    for (int i = lane; i < chi; i += 64) Rs[w][i] = Rnext[a * rstride + i];
+    if (lane < d) gs[w][lane] = (float)exp(lg - lmax);
+  }
+  __syncthreads();
+  if (valid) {
+    for (int p0 = 0; p0 < npair; p0 += 64 * 8) {
+      float u[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) u[k] = 0.f;
+      const int pl = p0 + lane;
+      for (int b = 0; b < cr; ++b) {
+        const float rb = Rs[w][b];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (pl + 64 * k < npair) u[k] = fmaf(As[(pl + 64 * k) * ldr + b], rb, u[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (pl + 64 * k < npair) us[w][pl + 64 * k] = u[k];
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+  float v[2] = {0.f, 0.f};
+  for (int h = 0; h < 2; ++h) {
+    const int al = lane + 64 * h;
+    if (al >= cl) continue;
+    float acc = 0.f;
+    for (int s = 0; s < d; ++s) acc = fmaf(gs[w][s], us[w][al * d + s], acc);
+    v[h] = acc;
+  }
+  const float m = wave_max_f(fmaxf(fabsf(v[0]), fabsf(v[1])));
+  const float inv = (m > 0.f) ? 1.f / m : 1.f;
+  for (int h = 0; h < 2; ++h) {
+    const int al = lane + 64 * h;
+    if (al < chi) Rout[a * rstride + al] = vround(v[h] * inv, bf16);
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_marginals_lp(SearchTabs t, int r, int c, int n_beam,
                                                       const uint8_t *cfg, int N, const T *A,
@@ -391,6 +478,17 @@ void lp_right_env_col(const SearchTabs &t, int precision, int r, int c, int n_an
   bc_single("lp_right_env_col");
   if (n_anc <= 0) return;
   KTimer kt_("right_env", s, 2.0 * n_anc * cl * t.d * cr);
+  if (cl > 0 && cr > 0 && env_lds_fits(cl, t.d, cr)) {
+    if (precision == SPG_FP32)
+      hipLaunchKernelGGL(k_right_env_lp_lds<float>, dim3(nblk(n_anc, kW)), dim3(256), 0, s, t, r,
+                         c, n_anc, cfg, N, (const float *)A_rc, Rnext, Rout, rstride, 0, cl, cr);
+    else
+      hipLaunchKernelGGL(k_right_env_lp_lds<uint16_t>, dim3(nblk(n_anc, kW)), dim3(256), 0, s, t,
+                         r, c, n_anc, cfg, N, (const uint16_t *)A_rc, Rnext, Rout, rstride, 1, cl,
+                         cr);
+    SPG_CHECK_LAUNCH();
+    return;
+  }
   if (precision == SPG_FP32)
     hipLaunchKernelGGL(k_right_env_lp<float>, dim3(nblk(n_anc, kW)), dim3(256), 0, s, t, r, c,
                        n_anc, cfg, N, (const float *)A_rc, Rnext, Rout, rstride, 0);
