@@ -27,6 +27,17 @@ configurations.  Adopted reading:
   share a frontier only the one with the lowest energy (ties: lowest id
   b d + s) keeps its score, the others get -inf.  Merging comes before the
   cut-off and the selection.
+* droplets (optional, with merging; the paper collects low-energy excitations
+  while merging, Sec. 3.1, and names only an energy cut-off and a Hamming
+  cut-off): the member of a merged group that comes right after the kept one
+  in (energy, id) order differs from it only in sites no longer coupled to
+  the unexplored ones, so its energy gap dE to the kept one is final.  A
+  state inherits its parent's droplets (stored as whole configurations, the
+  new site set to the state's own value) and, if it kept a group with a
+  runner-up whose dE <= energy_cutoff, takes that runner-up as a new droplet
+  when its Hamming distance (sites with different states) to the state and to
+  every droplet the state already holds exceeds hamming_cutoff and fewer than
+  max_droplets are held.  A droplet's energy is the state's energy plus dE.
 
 The vectors L and R only need a positive scale (it cancels in p(s | b)), so
 they are kept max-normalised without log-scales.
@@ -116,39 +127,77 @@ def frontier_width(inst, k: int) -> int:
     return min(k + 1, inst.cols + 1)
 
 
-def merge_branches(cand, cfg, energy, dE, k, w):
+def merge_branches(cand, cfg, energy, dE, k, w, runners=None):
     """Keep, per frontier (states of sites k-w+1..k-1 and the child's state),
-    only the finite child with the lowest energy (ties: lowest id)."""
+    only the finite child with the lowest energy (ties: lowest id).  With
+    ``runners`` (a dict), runners[kept id] = (id, energy) of the group's member
+    that comes next in (energy, id) order, for groups of two or more."""
     B, d = cand.shape
     out = np.full_like(cand, -np.inf)
-    best = {}
+    groups = {}
     for b in range(B):
         prefix = tuple(cfg[b, k - w + 1: k].tolist())
         for s in range(d):
             if not np.isfinite(cand[b, s]):
                 continue
             key = prefix + (s,)
-            e = energy[b] + dE[b, s]
-            idx = b * d + s
-            if key not in best or (e, idx) < best[key]:
-                best[key] = (e, idx)
-    for e, idx in best.values():
+            groups.setdefault(key, []).append((energy[b] + dE[b, s], b * d + s))
+    for members in groups.values():
+        members.sort()
+        e, idx = members[0]
         b, s = divmod(idx, d)
         out[b, s] = cand[b, s]
+        if runners is not None and len(members) > 1:
+            runners[idx] = (members[1][1], members[1][0])
     return out
 
 
-def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None, merge=False):
+def hamming(x, y, upto):
+    """Number of sites among 0..upto where x and y hold different states."""
+    return int(np.count_nonzero(x[: upto + 1] != y[: upto + 1]))
+
+
+def update_droplets(drops, cfg_new, kept, b, s, k, runners, cfg, energy_kept, d, droplets):
+    """Droplet list of the child kept from parent b with state s at site k
+    (cfg_new its configuration): the parent's droplets with site k set to s,
+    then the group's runner-up if it qualifies (module docstring)."""
+    e_cut, h_cut, cap = droplets
+    out = []
+    for x, de in drops[b]:
+        x = x.copy()
+        x[k] = s
+        out.append((x, de))
+    if kept in runners and len(out) < cap:
+        o, e_o = runners[kept]
+        de = e_o - energy_kept
+        if de <= e_cut:
+            bo, so = divmod(o, d)
+            x = cfg[bo].copy()
+            x[k] = so
+            if (hamming(x, cfg_new, k) > h_cut
+                    and all(hamming(x, y, k) > h_cut for y, _ in out)):
+                out.append((x, de))
+    return out
+
+
+def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None, merge=False,
+                droplets=None):
     """Run the search with boundary MPS tensors A[r][c].  Returns dict with
     'states' [n][N], 'energies', 'scores' (sorted by energy) and 'beam_energies'
     (the final beam in beam order).  ``trace`` (optional list) receives per-site
-    dicts with the parents' log-conditionals for teacher-forced comparisons."""
+    dicts with the parents' log-conditionals for teacher-forced comparisons.
+    ``droplets`` = (energy_cutoff, hamming_cutoff, max_droplets), with merging:
+    'droplets' then holds, for each returned state, its list of
+    (configuration, energy) in the order they were taken."""
+    if droplets is not None and not merge:
+        raise ValueError("droplets are collected while merging branches")
     W = Weights(inst)
     Rr, C, d = inst.rows, inst.cols, inst.d
     N = Rr * C
     cfg = np.zeros((1, N), dtype=np.int64)
     score = np.zeros(1)
     energy = np.zeros(1)
+    drops = [[]]
     for r in range(Rr):
         above = cfg[:, (r - 1) * C: r * C] if r > 0 else None
         g_anc = _fields(W, r, above)                                  # [n_anc][C][d]
@@ -160,9 +209,11 @@ def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None, merge=Fa
             lp = log_conditionals(q)
             cand = score[:, None] + lp
             dE = delta_energy(inst, cfg, r, c)
+            runners = {}
             if merge:
                 k = r * C + c
-                cand = merge_branches(cand, cfg, energy, dE, k, frontier_width(inst, k))
+                cand = merge_branches(cand, cfg, energy, dE, k, frontier_width(inst, k),
+                                      runners if droplets is not None else None)
             if cut_off_prob > 0:
                 best = cand.max()
                 cand = np.where(cand >= best + np.log(cut_off_prob), cand, -np.inf)
@@ -170,10 +221,18 @@ def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None, merge=Fa
                 trace.append({"site": r * C + c, "cfg": cfg.copy(), "logp": lp.copy()})
             keep = select_top(cand, M)
             b, s = np.divmod(keep, d)
+            parents = cfg
             cfg = cfg[b].copy()
             cfg[:, r * C + c] = s
             score = cand.reshape(-1)[keep]
+            e_par = energy
             energy = energy[b] + dE[b, s]
+            if droplets is not None:
+                k = r * C + c
+                drops = [update_droplets(drops, cfg[j], int(keep[j]), int(b[j]), int(s[j]), k,
+                                         runners, parents, float(e_par[b[j]] + dE[b[j], s[j]]),
+                                         d, droplets)
+                         for j in range(len(keep))]
             # L^child = g^b_c(s) * L^b A_{r,c}[:, s, :]
             Lb = np.einsum("ba,baz->bz", L[b], np.transpose(A[r][c][:, s, :], (1, 0, 2)))
             Lb = Lb * g_anc[anc[b], c, s][:, None]
@@ -182,9 +241,12 @@ def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None, merge=Fa
             anc = anc[b]
     E = potts_energy(inst, cfg)
     order = np.lexsort((np.arange(len(E)), E))
-    return {"states": cfg[order], "energies": E[order], "scores": score[order],
-            "beam_states": cfg, "beam_scores": score, "beam_energies": energy,
-            "n_valid": int(np.isfinite(score).sum())}
+    out = {"states": cfg[order], "energies": E[order], "scores": score[order],
+           "beam_states": cfg, "beam_scores": score, "beam_energies": energy,
+           "n_valid": int(np.isfinite(score).sum())}
+    if droplets is not None:
+        out["droplets"] = [[(x, float(E[i] + de)) for x, de in drops[i]] for i in order]
+    return out
 
 
 def teacher_forced_logp(inst, A, r: int, c: int, cfg: np.ndarray) -> np.ndarray:
