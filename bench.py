@@ -250,21 +250,38 @@ def transforms_leg(spg, torch, inst, wl, M, stream):
 
 def merge_leg(spg, torch, inst, wl, M, st, en, lp, stream):
     """Merging branches with equal frontiers: the FP64 search on the same
-    boundary MPS with and without it (search-only time, best energy)."""
+    boundary MPS with and without it, and with droplets collected while
+    merging (search-only time, best energy, droplets of the best states)."""
     peps = spg.build_peps(inst, stream)
     env, _ = spg.boundary_mps(peps, wl["chi"], num_sweeps=wl["num_sweeps"], precision="fp64",
                               oversample=wl["oversample"], power_iters=wl["power_iters"],
                               stream=stream, want_logZ=False)
     res = {}
-    for label, merge in (("plain", False), ("merged", True)):
-        spg.branch_and_bound(env, M, st, en, lp, stream=stream, merge_branches=merge)
+    # droplets: the paper's example cut-offs (energy 10, Hamming 5), 16 per state
+    drop = (10.0, 5, 16)
+    for label, merge, dl in (("plain", False, None), ("merged", True, None),
+                             ("droplets", True, drop)):
+        spg.branch_and_bound(env, M, st, en, lp, stream=stream, merge_branches=merge, droplets=dl)
         torch.cuda.synchronize()
         a = time.perf_counter()
-        n = spg.branch_and_bound(env, M, st, en, lp, stream=stream, merge_branches=merge)
+        n = spg.branch_and_bound(env, M, st, en, lp, stream=stream, merge_branches=merge,
+                                 droplets=dl)
         torch.cuda.synchronize()
         res[f"search_ms_{label}"] = (time.perf_counter() - a) * 1e3
         res[f"best_energy_{label}"] = float(en[0]) if n > 0 else None
         res[f"n_states_{label}"] = n
+    if n > 0:
+        counts, gaps = [], []
+        for i in range(min(n, 64)):
+            _, de = spg.droplets(env, i)
+            counts.append(len(de))
+            gaps.extend((de - float(en[i])).tolist())
+        res["droplet_cutoffs"] = {"energy": drop[0], "hamming": drop[1], "max_per_state": drop[2]}
+        res["droplets_of_best_state"] = counts[0]
+        res["droplets_best_64_states"] = int(sum(counts))
+        res["droplet_gap_range"] = [min(gaps), max(gaps)] if gaps else None
+        _, de0 = spg.droplets(env, 0)
+        res["best_state_droplet_energies"] = [round(float(x), 6) for x in de0]
     return res
 
 

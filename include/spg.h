@@ -97,7 +97,22 @@ typedef struct {
                         /* are merged: only the one with the lowest energy of its  */
                         /* fixed sites (ties: lowest b*d + s) keeps its score      */
                         /* (Sec. 3.1 merge of branches); not with a proposal       */
+  double droplet_energy;   /* with max_droplets > 0: largest energy gap of a      */
+                        /* droplet above its state (>= 0)                          */
+  int32_t droplet_hamming; /* a droplet must differ from its state and from each  */
+                        /* droplet the state holds in more than this many sites   */
+  int32_t max_droplets;    /* 0: none; else up to this many (<= SPG_MAX_DROPLETS) */
+                        /* low-energy excitations kept per state while merging     */
+                        /* branches (Sec. 3.1 low-energy excitations): the member */
+                        /* of a merged group next after the kept one in (energy,  */
+                        /* id) order differs from it only in sites no later site  */
+                        /* couples to, so its energy gap is final; a state        */
+                        /* inherits its parent's droplets and takes its group's   */
+                        /* runner-up if the gap and Hamming tests pass. Needs     */
+                        /* merge_branches; read them with spg_droplets            */
 } spg_search_params;
+
+#define SPG_MAX_DROPLETS 64
 
 /* Build the PEPS of an instance (Sec. 2, Fig. 1(c)): copies the energy tables
  * to the device and forms the Boltzmann weights w = exp(-beta (E - eps)) of
@@ -278,6 +293,19 @@ int spg_proposal_adam(spg_proposal_t *prop, const float *grad, float learning_ra
  * evaluated exactly (fallback evaluations included), counts[1] children
  * resolved (sum over steps of parents x d), counts[2] parents that fell back
  * to full evaluation.  HOST int64 [3].  Synchronous. */
+/* Droplets of the state returned at position `state` (0-based, energy order)
+ * by the last spg_branch_and_bound on this env, which must have run with
+ * max_droplets > 0 (Sec. 3.1 low-energy excitations; the rule is described
+ * with spg_search_params).  Writes min(count, max_out) whole configurations to
+ * configs_out (HOST int32 [max_out][rows*cols], row-major sites) with their
+ * Eq. (1) energies (the state's energy plus the recorded gap) to energies_out
+ * (HOST [max_out]), in the order they were taken; *n_out = count.  Buffers are
+ * caller-owned.  Blocks until the device is idle.
+ * Errors: SPG_ERR_INVALID (null pointers, no droplets collected, state out of
+ * range), SPG_ERR_HIP. */
+int spg_droplets(const spg_env_t *env, int32_t state, int32_t max_out, int32_t *configs_out,
+                 double *energies_out, int32_t *n_out);
+
 int spg_search_stats(const spg_env_t *env, int64_t *counts);
 
 /* ---- inspection hooks (tests and tools) -------------------------------- */

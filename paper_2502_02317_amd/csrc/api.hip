@@ -773,7 +773,7 @@ static void ensure_guide(spg_env *env, int M) {
   env->smax.ensure(8);
 }
 
-static MergeWork merge_work(spg_env *env, int M) {
+static MergeWork merge_work(spg_env *env, int M, bool runners) {
   const int d = env->peps->d;
   int T = 1;
   while (T < 2 * M * d) T <<= 1;
@@ -789,6 +789,14 @@ static MergeWork merge_work(spg_env *env, int M) {
   mw.tid = env->mid.as<int32_t>();
   mw.slot = env->mslot.as<int32_t>();
   mw.ekey = env->mekey.as<unsigned long long>();
+  if (runners) {
+    env->me2.ensure((size_t)T * 8);
+    env->mid2.ensure((size_t)T * 4);
+    env->mrun.ensure((size_t)M * d * 4);
+    mw.te2 = env->me2.as<unsigned long long>();
+    mw.tid2 = env->mid2.as<int32_t>();
+    mw.run = env->mrun.as<int32_t>();
+  }
   return mw;
 }
 
@@ -835,8 +843,18 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
     site_features(t, A, env->sf.as<float>(), env->rscr.as<double>(), s);
   }
   const int K = guided ? (int)std::min<double>(std::ceil(prm->kappa * M), 2147483647.0) : 0;
+  const int D = prm->merge_branches ? prm->max_droplets : 0;
   MergeWork mw;
-  if (prm->merge_branches) mw = merge_work(env, M);
+  if (prm->merge_branches) mw = merge_work(env, M, D > 0);
+  env->drop_buf = -1;
+  if (D > 0) {
+    for (int i = 0; i < 2; ++i) {
+      env->dcfg[i].ensure((size_t)M * D * N);
+      env->dde[i].ensure((size_t)M * D * 8);
+      env->dn[i].ensure((size_t)std::max(M, 2) * 4);
+    }
+    fill_zero(env->dn[0].as<double>(), 1, s);       // the root holds no droplet (count 0)
+  }
   int cur = 0;
   long B = 1;
   fill_zero(env->score[0].as<double>(), 1, s);
@@ -945,14 +963,27 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
                     env->cfg[nx].as<uint8_t>(), env->energy[nx].as<double>(),
                     env->score[nx].as<double>(), env->L[nx].as<double>(),
                     env->anc[nx].as<int32_t>(), dm[c], dm[c + 1], s, sel_score);
+      if (D > 0)
+        droplet_update(t, r, c, (int)Bn, env->sel.as<int32_t>(), N, cfg,
+                       env->energy[cur].as<double>(), mw.run, env->dcfg[cur].as<uint8_t>(),
+                       env->dde[cur].as<double>(), env->dn[cur].as<int32_t>(),
+                       env->dcfg[nx].as<uint8_t>(), env->dde[nx].as<double>(),
+                       env->dn[nx].as<int32_t>(), D, prm->droplet_energy, prm->droplet_hamming,
+                       s);
       cur = nx;
       B = Bn;
     }
   }
-  if (states_out)
+  if (states_out) {
     final_sort(t, (int)B, N, env->cfg[cur].as<uint8_t>(), env->score[cur].as<double>(),
                states_out, energies_out, logp_out, env->ework.as<double>(),
                env->perm.as<int32_t>(), env->nvalid.as<int32_t>(), s);
+    if (D > 0) {
+      env->drop_buf = cur;
+      env->drop_slots = (int)B;
+      env->drop_cap = D;
+    }
+  }
   if (!sync_out) return;           // enqueued only (batches read env->nvalid later)
   int32_t nv = 0;
   unsigned long long st[3] = {0, 0, 0};
@@ -977,6 +1008,15 @@ int spg_branch_and_bound(const spg_env_t *cenv, const spg_search_params *prm, in
   spg_env *env = const_cast<spg_env *>(cenv);
   if (prm->proposal && prm->merge_branches)
     return fail(SPG_ERR_UNSUPPORTED, "spg_branch_and_bound: merging with a proposal");
+  if (prm->max_droplets < 0 || prm->max_droplets > SPG_MAX_DROPLETS)
+    return fail(SPG_ERR_UNSUPPORTED, "spg_branch_and_bound: max_droplets must be in 0..64");
+  if (prm->max_droplets > 0) {
+    if (!prm->merge_branches)
+      return fail(SPG_ERR_INVALID, "spg_branch_and_bound: droplets need merge_branches");
+    if (!(prm->droplet_energy >= 0.0) || prm->droplet_hamming < 0)
+      return fail(SPG_ERR_INVALID,
+                  "spg_branch_and_bound: droplet_energy >= 0 and droplet_hamming >= 0 required");
+  }
   if (prm->proposal) {
     if (!(prm->kappa > 0.0))
       return fail(SPG_ERR_INVALID, "spg_branch_and_bound: kappa must be > 0 with a proposal");
@@ -985,6 +1025,43 @@ int spg_branch_and_bound(const spg_env_t *cenv, const spg_search_params *prm, in
   }
   run_search(env, prm, prm->proposal, nullptr, states_out, energies_out, logp_out, n_out,
              (hipStream_t)stream);
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_droplets(const spg_env_t *cenv, int32_t state, int32_t max_out, int32_t *configs_out,
+                 double *energies_out, int32_t *n_out) {
+  SPG_TRY
+  if (!cenv || !n_out || max_out < 0 || (max_out > 0 && (!configs_out || !energies_out)))
+    return fail(SPG_ERR_INVALID, "spg_droplets: null argument or negative max_out");
+  const spg_env *env = cenv;
+  if (env->drop_buf < 0)
+    return fail(SPG_ERR_INVALID, "spg_droplets: the last search on this env collected none");
+  const int N = env->peps->rows * env->peps->cols, D = env->drop_cap, buf = env->drop_buf;
+  int32_t nv = 0;
+  SPG_HIP(hipDeviceSynchronize());
+  SPG_HIP(hipMemcpy(&nv, env->nvalid.p, 4, hipMemcpyDeviceToHost));
+  if (state < 0 || state >= nv)
+    return fail(SPG_ERR_INVALID, "spg_droplets: state outside the returned states");
+  int32_t slot = 0, cnt = 0;
+  double e = 0.0;
+  SPG_HIP(hipMemcpy(&slot, env->perm.as<int32_t>() + state, 4, hipMemcpyDeviceToHost));
+  if (slot < 0 || slot >= env->drop_slots)
+    return fail(SPG_ERR_INVALID, "spg_droplets: internal slot out of range");
+  SPG_HIP(hipMemcpy(&cnt, env->dn[buf].as<int32_t>() + slot, 4, hipMemcpyDeviceToHost));
+  SPG_HIP(hipMemcpy(&e, env->ework.as<double>() + slot, 8, hipMemcpyDeviceToHost));
+  const int n = std::min(cnt, max_out);
+  if (n > 0) {
+    std::vector<uint8_t> x((size_t)n * N);
+    std::vector<double> de(n);
+    SPG_HIP(hipMemcpy(x.data(), env->dcfg[buf].as<uint8_t>() + (size_t)slot * D * N, x.size(),
+                      hipMemcpyDeviceToHost));
+    SPG_HIP(hipMemcpy(de.data(), env->dde[buf].as<double>() + (size_t)slot * D, (size_t)n * 8,
+                      hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < x.size(); ++i) configs_out[i] = x[i];
+    for (int m = 0; m < n; ++m) energies_out[m] = e + de[m];
+  }
+  *n_out = cnt;
   return SPG_OK;
   SPG_CATCH
 }

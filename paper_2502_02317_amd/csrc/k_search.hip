@@ -767,12 +767,16 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
 }
 
 __global__ void k_merge_clear(int T, unsigned long long *tkey, unsigned long long *te,
-                              int32_t *tid) {
+                              int32_t *tid, unsigned long long *te2, int32_t *tid2) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= T) return;
   tkey[e] = kEmpty;
   te[e] = kEmpty;
   tid[e] = INT_MAX;
+  if (te2) {
+    te2[e] = kEmpty;
+    tid2[e] = INT_MAX;
+  }
 }
 
 __global__ void k_merge_insert(SearchTabs t, int r, int c, int n_beam, const uint8_t *cfg, int N,
@@ -819,11 +823,93 @@ __global__ void k_merge_tie(long n, const int32_t *slot_of, const unsigned long 
   if (h >= 0 && ekey_of[e] == te[h]) atomicMin(&tid[h], (int32_t)e);
 }
 
-__global__ void k_merge_apply(long n, const int32_t *slot_of, const int32_t *tid, double *cand) {
+// Runner-up of each group: least energy key among the members that were not
+// kept, then the least id among those at that energy.
+__global__ void k_merge_second(long n, const int32_t *slot_of, const unsigned long long *ekey_of,
+                               const int32_t *tid, unsigned long long *te2) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int h = slot_of[e];
+  if (h >= 0 && tid[h] != (int32_t)e) atomicMin(&te2[h], ekey_of[e]);
+}
+
+__global__ void k_merge_second_tie(long n, const int32_t *slot_of,
+                                   const unsigned long long *ekey_of, const int32_t *tid,
+                                   const unsigned long long *te2, int32_t *tid2) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int h = slot_of[e];
+  if (h >= 0 && tid[h] != (int32_t)e && ekey_of[e] == te2[h]) atomicMin(&tid2[h], (int32_t)e);
+}
+
+__global__ void k_merge_apply(long n, const int32_t *slot_of, const int32_t *tid, double *cand,
+                              const int32_t *tid2, int32_t *run) {
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e >= n) return;
   const int h = slot_of[e];
   if (h >= 0 && tid[h] != (int32_t)e) cand[e] = -INFINITY;
+  if (run) run[e] = (h >= 0 && tid[h] == (int32_t)e && tid2[h] != INT_MAX) ? tid2[h] : -1;
+}
+
+// One wavefront per survivor j (see droplet_update).  Configurations are
+// compared over the sites fixed so far, 0..k.
+__global__ __launch_bounds__(256) void k_droplet_update(SearchTabs t, int r, int c, int n_new,
+                                                        const int32_t *sel, int N,
+                                                        const uint8_t *cfg, const double *energy,
+                                                        const int32_t *run, const uint8_t *din,
+                                                        const double *dein, const int32_t *dnin,
+                                                        uint8_t *dout, double *deout,
+                                                        int32_t *dnout, int D, double ecut,
+                                                        int hcut) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = blockIdx.x * kWaves + w;
+  if (j >= n_new) return;
+  const int d = t.d, k = r * t.cols + c;
+  const int id = sel[j], b = id / d, s = id % d;
+  const uint8_t *cb = cfg + (long)b * N;
+  const int nin = dnin[b];
+  // inherited droplets, the new site set to this state's value
+  for (long e = lane; e < (long)nin * N; e += 64) {
+    const int m = (int)(e / N), i = (int)(e % N);
+    dout[((long)j * D + m) * N + i] = (i == k) ? (uint8_t)s : din[((long)b * D + m) * N + i];
+  }
+  for (int m = lane; m < nin; m += 64) deout[(long)j * D + m] = dein[(long)b * D + m];
+  int cnt = nin;
+  const int o = run[id];
+  if (o >= 0 && cnt < D) {
+    const int bo = o / d, so = o % d;
+    const uint8_t *co = cfg + (long)bo * N;
+    const double ek = energy[b] + delta_energy(t, r, c, cb, s);
+    const double eo = energy[bo] + delta_energy(t, r, c, co, so);
+    const double de = eo - ek;
+    if (de <= ecut) {
+      // distance of the runner-up to this state, then to each inherited droplet
+      auto dist = [&](int m) {
+        int cntd = 0;
+        for (int i0 = 0; i0 <= k; i0 += 64) {
+          const int i = i0 + lane;
+          bool diff = false;
+          if (i <= k) {
+            const uint8_t x = (i == k) ? (uint8_t)so : co[i];
+            const uint8_t y = (i == k) ? (uint8_t)s
+                              : (m < 0 ? cb[i] : din[((long)b * D + m) * N + i]);
+            diff = x != y;
+          }
+          cntd += __popcll(__ballot(diff));
+        }
+        return cntd;
+      };
+      bool ok = dist(-1) > hcut;
+      for (int m = 0; m < nin && ok; ++m) ok = dist(m) > hcut;
+      if (ok) {
+        for (int i = lane; i < N; i += 64)
+          dout[((long)j * D + cnt) * N + i] = (i == k) ? (uint8_t)so : (i < k ? co[i] : (uint8_t)0);
+        if (lane == 0) deout[(long)j * D + cnt] = de;
+        ++cnt;
+      }
+    }
+  }
+  if (lane == 0) dnout[j] = cnt;
 }
 
 }  // namespace
@@ -990,7 +1076,8 @@ void merge_branches(const SearchTabs &t, int r, int c, int n_beam, const uint8_t
   const int w = std::min(k + 1, t.cols + 1);
   int bits = 1;
   while ((1 << bits) < t.d) ++bits;
-  hipLaunchKernelGGL(k_merge_clear, dim3(nblk(T, 256)), dim3(256), 0, s, T, mw.tkey, mw.te, mw.tid);
+  hipLaunchKernelGGL(k_merge_clear, dim3(nblk(T, 256)), dim3(256), 0, s, T, mw.tkey, mw.te, mw.tid,
+                     mw.te2, mw.tid2);
   SPG_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_merge_insert, dim3(nblk(n, 256)), dim3(256), 0, s, t, r, c, n_beam, cfg, N,
                      energy, cand, w, bits, T, mw.tkey, mw.te, mw.slot, mw.ekey);
@@ -998,7 +1085,28 @@ void merge_branches(const SearchTabs &t, int r, int c, int n_beam, const uint8_t
   hipLaunchKernelGGL(k_merge_tie, dim3(nblk(n, 256)), dim3(256), 0, s, n, mw.slot, mw.ekey, mw.te,
                      mw.tid);
   SPG_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_merge_apply, dim3(nblk(n, 256)), dim3(256), 0, s, n, mw.slot, mw.tid, cand);
+  if (mw.run) {
+    hipLaunchKernelGGL(k_merge_second, dim3(nblk(n, 256)), dim3(256), 0, s, n, mw.slot, mw.ekey,
+                       mw.tid, mw.te2);
+    SPG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_merge_second_tie, dim3(nblk(n, 256)), dim3(256), 0, s, n, mw.slot,
+                       mw.ekey, mw.tid, mw.te2, mw.tid2);
+    SPG_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_merge_apply, dim3(nblk(n, 256)), dim3(256), 0, s, n, mw.slot, mw.tid, cand,
+                     mw.tid2, mw.run);
+  SPG_CHECK_LAUNCH();
+}
+
+void droplet_update(const SearchTabs &t, int r, int c, int n_new, const int32_t *sel, int N,
+                    const uint8_t *cfg, const double *energy, const int32_t *run,
+                    const uint8_t *din, const double *dein, const int32_t *dnin, uint8_t *dout,
+                    double *deout, int32_t *dnout, int D, double ecut, int hcut, hipStream_t s) {
+  bc_single("droplet_update");
+  KTimer kt_("droplets", s);
+  if (n_new <= 0) return;
+  hipLaunchKernelGGL(k_droplet_update, dim3(nblk(n_new, kWaves)), dim3(256), 0, s, t, r, c, n_new,
+                     sel, N, cfg, energy, run, din, dein, dnin, dout, deout, dnout, D, ecut, hcut);
   SPG_CHECK_LAUNCH();
 }
 

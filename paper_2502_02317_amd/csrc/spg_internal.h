@@ -221,11 +221,24 @@ struct MergeWork {
   int capacity = 0;
   unsigned long long *tkey = nullptr, *te = nullptr, *ekey = nullptr;
   int32_t *tid = nullptr, *slot = nullptr;
+  // droplets (all null without): per slot the next member in (energy, id)
+  // order, per child the id of its group's runner-up if it is kept, else -1
+  unsigned long long *te2 = nullptr;
+  int32_t *tid2 = nullptr, *run = nullptr;
 };
 // Children of equal frontier: all but the lowest-energy one (ties: lowest id)
-// get cand = -inf.
+// get cand = -inf; with mw.run, run[kept id] = id of the group's runner-up.
 void merge_branches(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
                     const double *energy, double *cand, MergeWork &mw, hipStream_t s);
+// Droplet lists of the n_new survivors sel[] of step (r, c): each inherits its
+// parent's list (configurations [D][N] bytes, gaps [D], count) with the new
+// site set to its own state, then takes its group's runner-up run[sel[j]] if
+// the gap is <= ecut, the runner-up differs from the survivor and from every
+// droplet it holds in more than hcut sites, and fewer than D are held.
+void droplet_update(const SearchTabs &t, int r, int c, int n_new, const int32_t *sel, int N,
+                    const uint8_t *cfg, const double *energy, const int32_t *run,
+                    const uint8_t *din, const double *dein, const int32_t *dnin, uint8_t *dout,
+                    double *deout, int32_t *dnout, int D, double ecut, int hcut, hipStream_t s);
 void final_sort(const SearchTabs &t, int n, int N, const uint8_t *cfg, const double *score,
                 int32_t *states_out, double *energies_out, double *logp_out, double *e_work,
                 int32_t *perm_work, int32_t *n_valid, hipStream_t s);
@@ -321,6 +334,12 @@ struct spg_env {
   spg::DevBuf Rsc, sf, rscr, gbins, ghist, gint, glkey, glid, gbound, gtau, goff, gcnt, gstats,
       selscore, smax;
   spg::DevBuf mkey, me, mid, mslot, mekey;   // merging branches
+  spg::DevBuf me2, mid2, mrun;               // runner-ups of merged groups
+  // droplets [M][D][N] bytes, gaps [M][D], counts [M], double-buffered like
+  // the beam; after a search with droplets: the buffer holding them, the
+  // number of final beam slots and D
+  spg::DevBuf dcfg[2], dde[2], dn[2];
+  int drop_buf = -1, drop_slots = 0, drop_cap = 0;
   int64_t last_stats[3] = {0, 0, 0};
 };
 

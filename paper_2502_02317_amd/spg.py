@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspg.so")
 
 SPG_FP64, SPG_FP32, SPG_BF16 = 0, 1, 2
+SPG_MAX_DROPLETS = 64         # include/spg.h
 PRECISION = {"fp64": SPG_FP64, "fp32": SPG_FP32, "bf16": SPG_BF16}
 ERRORS = {-1: "SPG_ERR_INVALID", -2: "SPG_ERR_OOM", -3: "SPG_ERR_HIP",
           -4: "SPG_ERR_NONFINITE", -5: "SPG_ERR_UNSUPPORTED"}
@@ -43,7 +44,8 @@ class MpsParams(C.Structure):
 class SearchParams(C.Structure):
     _fields_ = [("max_states", C.c_int32), ("cut_off_prob", C.c_double),
                 ("proposal", C.c_void_p), ("kappa", C.c_double),
-                ("merge_branches", C.c_int32)]
+                ("merge_branches", C.c_int32), ("droplet_energy", C.c_double),
+                ("droplet_hamming", C.c_int32), ("max_droplets", C.c_int32)]
 
 
 class TrainParams(C.Structure):
@@ -67,10 +69,11 @@ EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_branch_an
            "spg_proposal_train", "spg_proposal_features", "spg_proposal_forward",
            "spg_proposal_loss_grad", "spg_proposal_adam", "spg_search_stats",
            "spg_batch_create", "spg_batch_free", "spg_batch_run", "spg_batch_result",
-           "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning", "spg_batch_info"]
+           "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning", "spg_batch_info",
+           "spg_droplets"]
 KERNEL_CLASSES = ["gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box", "right_env",
                   "marginals", "select_topm", "beam_update", "final_sort", "propose",
-                  "guided_eval", "mlp_grad", "merge_branches"]
+                  "guided_eval", "mlp_grad", "merge_branches", "droplets"]
 
 _lib = None
 
@@ -110,6 +113,7 @@ def load() -> C.CDLL:
     lib.spg_proposal_loss_grad.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
     lib.spg_proposal_adam.argtypes = [vp, vp, C.c_float, vp]
     lib.spg_search_stats.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.spg_droplets.argtypes = [vp, i32, i32, vp, vp, i32p]
     lib.spg_batch_create.argtypes = [C.POINTER(vp), C.POINTER(BatchItem), i32, i32, i32,
                                      C.POINTER(vp)]
     lib.spg_batch_info.argtypes = [vp, i32p, vp]
@@ -126,7 +130,7 @@ def load() -> C.CDLL:
                  "spg_proposal_features", "spg_proposal_forward", "spg_proposal_loss_grad",
                  "spg_proposal_adam", "spg_search_stats", "spg_batch_create", "spg_batch_run",
                  "spg_batch_result", "spg_batch_set_tuning", "spg_batch_autotune",
-                 "spg_set_tuning", "spg_batch_info"]:
+                 "spg_set_tuning", "spg_batch_info", "spg_droplets"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -214,18 +218,35 @@ def marginals(env: Env, site: int, beam_cfg, out, stream=None):
 
 def branch_and_bound(env: Env, max_states: int, states_out, energies_out, logp_out,
                      cut_off_prob: float = 0.0, stream=None, proposal=None,
-                     kappa: float = 2.0, merge_branches: bool = False) -> int:
+                     kappa: float = 2.0, merge_branches: bool = False,
+                     droplets=None) -> int:
     """spg_branch_and_bound into device tensors; returns n_out.  With a
     Proposal the guarded steps run (kappa * max_states exact children per step
-    before the guard)."""
+    before the guard).  ``droplets`` = (energy_cutoff, hamming_cutoff,
+    max_droplets) collects droplets while merging (read them with droplets())."""
+    de, dh, dm = droplets if droplets is not None else (0.0, 0, 0)
     prm = SearchParams(int(max_states), float(cut_off_prob),
                        proposal.handle if proposal is not None else None, float(kappa),
-                       1 if merge_branches else 0)
+                       1 if merge_branches else 0, float(de), int(dh), int(dm))
     n = C.c_int32(0)
     _check(load().spg_branch_and_bound(env.handle, C.byref(prm), _ptr(states_out),
                                        _ptr(energies_out), _ptr(logp_out), C.byref(n),
                                        _stream(stream)))
     return n.value
+
+
+def droplets(env: Env, state: int, max_out: int = SPG_MAX_DROPLETS):
+    """spg_droplets: (configurations [n][rows*cols] int32, energies [n]) of the
+    state returned at position ``state`` by the last search on ``env``."""
+    info = env_info(env)
+    N = info.rows * info.cols
+    cfg = np.zeros((max_out, N), dtype=np.int32)
+    en = np.zeros(max_out)
+    n = C.c_int32(0)
+    _check(load().spg_droplets(env.handle, int(state), int(max_out), cfg.ctypes.data,
+                               en.ctypes.data, C.byref(n)))
+    k = min(n.value, max_out)
+    return cfg[:k], en[:k]
 
 
 @dataclass
