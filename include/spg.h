@@ -306,6 +306,29 @@ int spg_proposal_adam(spg_proposal_t *prop, const float *grad, float learning_ra
 int spg_droplets(const spg_env_t *env, int32_t state, int32_t max_out, int32_t *configs_out,
                  double *energies_out, int32_t *n_out);
 
+/* Ising instance -> Potts tables of a lattice of spin clusters (host only, no
+ * device work): the paper's Ising input (Sec. 2, Eq. (2)) grouped into the
+ * Potts variables of Eq. (1) by a cluster assignment rule (Sec. 3.1).
+ * E(s) = sum_q J_q s_{i_q} s_{j_q} over the n_terms listed terms (0-based
+ * spin indices; i_q == j_q is a field J_q s_i; repeated terms add), s = +-1.
+ * cluster_of[i] = r * cols + c places spin i (of n_spins = rows * cols * t) in
+ * cluster (r, c); every cluster holds t spins (1 <= t <= 8), ordered by spin
+ * index: the k-th is bit k of the cluster's state x, s = 2 bit_k(x) - 1, so
+ * d = 2^t.  Couplings must join spins of one cluster or of neighbouring
+ * clusters (r,c)-(r,c+1), (r,c)-(r+1,c), and with kings != 0 also
+ * (r,c)-(r+1,c+1) and (r,c+1)-(r+1,c).  Writes the tables of
+ * spg_instance_desc, in its layouts, to caller-owned HOST arrays: local_E
+ * [rows*cols][d], pair_E_h [rows][cols-1][d][d], pair_E_v [rows-1][cols][d][d],
+ * pair_E_d and pair_E_a [rows-1][cols-1][d][d] (these two only with kings;
+ * tables of an absent edge class may be NULL).
+ * Errors: SPG_ERR_INVALID (sizes, null pointers, indices out of range, a
+ * cluster with more or fewer than t spins, a coupling between clusters that
+ * are not neighbours), SPG_ERR_UNSUPPORTED (t outside 1..8), SPG_ERR_NONFINITE. */
+int spg_ising_to_potts(int32_t n_spins, int32_t n_terms, const int32_t *term_i,
+                       const int32_t *term_j, const double *term_J, int32_t rows, int32_t cols,
+                       int32_t t, int32_t kings, const int32_t *cluster_of, double *local_E,
+                       double *pair_E_h, double *pair_E_v, double *pair_E_d, double *pair_E_a);
+
 int spg_search_stats(const spg_env_t *env, int64_t *counts);
 
 /* ---- inspection hooks (tests and tools) -------------------------------- */

@@ -1066,6 +1066,86 @@ int spg_droplets(const spg_env_t *cenv, int32_t state, int32_t max_out, int32_t 
   SPG_CATCH
 }
 
+// ---------------------------------------------------------------------------
+// Ising instance -> Potts tables of a cluster lattice (host only).
+int spg_ising_to_potts(int32_t n_spins, int32_t n_terms, const int32_t *term_i,
+                       const int32_t *term_j, const double *term_J, int32_t rows, int32_t cols,
+                       int32_t t, int32_t kings, const int32_t *cluster_of, double *local_E,
+                       double *pair_E_h, double *pair_E_v, double *pair_E_d,
+                       double *pair_E_a) {
+  SPG_TRY
+  if (n_spins < 1 || n_terms < 0 || rows < 1 || cols < 1 || !cluster_of || !local_E ||
+      (n_terms > 0 && (!term_i || !term_j || !term_J)))
+    return fail(SPG_ERR_INVALID, "spg_ising_to_potts: bad sizes or null argument");
+  if (t < 1 || t > 8)
+    return fail(SPG_ERR_UNSUPPORTED, "spg_ising_to_potts: spins per cluster must be in 1..8");
+  const long ncl = (long)rows * cols;
+  if (ncl * t != n_spins)
+    return fail(SPG_ERR_INVALID, "spg_ising_to_potts: rows * cols * t must equal n_spins");
+  if ((cols > 1 && !pair_E_h) || (rows > 1 && !pair_E_v) ||
+      (kings && rows > 1 && cols > 1 && (!pair_E_d || !pair_E_a)))
+    return fail(SPG_ERR_INVALID, "spg_ising_to_potts: a needed pair table is null");
+  const int d = 1 << t;
+  // position of each spin in its cluster (ascending spin index)
+  std::vector<int> pos(n_spins), fill(ncl, 0);
+  for (int i = 0; i < n_spins; ++i) {
+    const int cl = cluster_of[i];
+    if (cl < 0 || cl >= ncl)
+      return fail(SPG_ERR_INVALID, "spg_ising_to_potts: cluster index out of range");
+    if (fill[cl] >= t)
+      return fail(SPG_ERR_INVALID, "spg_ising_to_potts: a cluster holds more than t spins");
+    pos[i] = fill[cl]++;
+  }
+  const size_t dd = (size_t)d * d;
+  std::fill(local_E, local_E + ncl * d, 0.0);
+  if (cols > 1) std::fill(pair_E_h, pair_E_h + (size_t)rows * (cols - 1) * dd, 0.0);
+  if (rows > 1) std::fill(pair_E_v, pair_E_v + (size_t)(rows - 1) * cols * dd, 0.0);
+  if (kings && rows > 1 && cols > 1) {
+    std::fill(pair_E_d, pair_E_d + (size_t)(rows - 1) * (cols - 1) * dd, 0.0);
+    std::fill(pair_E_a, pair_E_a + (size_t)(rows - 1) * (cols - 1) * dd, 0.0);
+  }
+  auto spin = [](int x, int k) { return ((x >> k) & 1) ? 1.0 : -1.0; };
+  for (int q = 0; q < n_terms; ++q) {
+    int i = term_i[q], j = term_j[q];
+    const double J = term_J[q];
+    if (i < 0 || i >= n_spins || j < 0 || j >= n_spins)
+      return fail(SPG_ERR_INVALID, "spg_ising_to_potts: spin index out of range");
+    if (!std::isfinite(J)) return fail(SPG_ERR_NONFINITE, "spg_ising_to_potts: coupling not finite");
+    int a = cluster_of[i], b = cluster_of[j];
+    if (i == j || a == b) {
+      // field h_i s_i, or a coupling inside one cluster
+      double *row = local_E + (size_t)a * d;
+      for (int x = 0; x < d; ++x)
+        row[x] += (i == j) ? J * spin(x, pos[i]) : J * spin(x, pos[i]) * spin(x, pos[j]);
+      continue;
+    }
+    int ra = a / cols, ca = a % cols, rb = b / cols, cb = b % cols;
+    // orient the pair as the table stores it: first index the upper (or left) cluster
+    if (rb < ra || (rb == ra && cb < ca)) {
+      std::swap(i, j);
+      std::swap(a, b);
+      std::swap(ra, rb);
+      std::swap(ca, cb);
+    }
+    double *tab = nullptr;
+    if (rb == ra && cb == ca + 1) tab = pair_E_h + ((size_t)ra * (cols - 1) + ca) * dd;
+    else if (rb == ra + 1 && cb == ca) tab = pair_E_v + ((size_t)ra * cols + ca) * dd;
+    else if (kings && rb == ra + 1 && cb == ca + 1)
+      tab = pair_E_d + ((size_t)ra * (cols - 1) + ca) * dd;
+    else if (kings && rb == ra + 1 && cb == ca - 1)
+      tab = pair_E_a + ((size_t)ra * (cols - 1) + cb) * dd;    // [x_(r,c+1)][x_(r+1,c)]
+    else
+      return fail(SPG_ERR_INVALID,
+                  "spg_ising_to_potts: a coupling joins clusters that are not lattice neighbours");
+    for (int x = 0; x < d; ++x) {
+      const double sx = J * spin(x, pos[i]);
+      for (int y = 0; y < d; ++y) tab[(size_t)x * d + y] += sx * spin(y, pos[j]);
+    }
+  }
+  return SPG_OK;
+  SPG_CATCH
+}
+
 int spg_search_stats(const spg_env_t *env, int64_t *counts) {
   if (!env || !counts) return fail(SPG_ERR_INVALID, "spg_search_stats: null argument");
   for (int i = 0; i < 3; ++i) counts[i] = env->last_stats[i];

@@ -70,7 +70,7 @@ EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_branch_an
            "spg_proposal_loss_grad", "spg_proposal_adam", "spg_search_stats",
            "spg_batch_create", "spg_batch_free", "spg_batch_run", "spg_batch_result",
            "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning", "spg_batch_info",
-           "spg_droplets"]
+           "spg_droplets", "spg_ising_to_potts"]
 KERNEL_CLASSES = ["gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box", "right_env",
                   "marginals", "select_topm", "beam_update", "final_sort", "propose",
                   "guided_eval", "mlp_grad", "merge_branches", "droplets"]
@@ -114,6 +114,8 @@ def load() -> C.CDLL:
     lib.spg_proposal_adam.argtypes = [vp, vp, C.c_float, vp]
     lib.spg_search_stats.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.spg_droplets.argtypes = [vp, i32, i32, vp, vp, i32p]
+    lib.spg_ising_to_potts.argtypes = [i32, i32, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp,
+                                       vp, vp, vp]
     lib.spg_batch_create.argtypes = [C.POINTER(vp), C.POINTER(BatchItem), i32, i32, i32,
                                      C.POINTER(vp)]
     lib.spg_batch_info.argtypes = [vp, i32p, vp]
@@ -130,7 +132,7 @@ def load() -> C.CDLL:
                  "spg_proposal_features", "spg_proposal_forward", "spg_proposal_loss_grad",
                  "spg_proposal_adam", "spg_search_stats", "spg_batch_create", "spg_batch_run",
                  "spg_batch_result", "spg_batch_set_tuning", "spg_batch_autotune",
-                 "spg_set_tuning", "spg_batch_info", "spg_droplets"]:
+                 "spg_set_tuning", "spg_batch_info", "spg_droplets", "spg_ising_to_potts"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -247,6 +249,82 @@ def droplets(env: Env, state: int, max_out: int = SPG_MAX_DROPLETS):
                                en.ctypes.data, C.byref(n)))
     k = min(n.value, max_out)
     return cfg[:k], en[:k]
+
+
+# ---- Ising input -------------------------------------------------------------
+
+def read_ising(path: str):
+    """Ising instance from text: one term per line, ``i j J`` with 1-based spin
+    indices (i == j: a field), ``#`` starts a comment.  Returns (n_spins, i, j, J)
+    with 0-based int32 indices; n_spins is the largest index seen."""
+    ii, jj, JJ = [], [], []
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if not line:
+                continue
+            if len(line) != 3:
+                raise ValueError(f"{path}: expected 'i j J', got {' '.join(line)!r}")
+            ii.append(int(line[0]) - 1)
+            jj.append(int(line[1]) - 1)
+            JJ.append(float(line[2]))
+    i = np.asarray(ii, dtype=np.int32)
+    j = np.asarray(jj, dtype=np.int32)
+    if i.size and min(i.min(), j.min()) < 0:
+        raise ValueError(f"{path}: spin indices start at 1")
+    n = int(max(i.max(), j.max()) + 1) if i.size else 0
+    return n, i, j, np.asarray(JJ, dtype=np.float64)
+
+
+def lattice_clusters(rows: int, cols: int, t: int) -> np.ndarray:
+    """Cluster of every spin when the spins come in consecutive runs of t per
+    cluster, clusters row-major: spin i -> cluster i // t."""
+    return (np.arange(rows * cols * t) // t).astype(np.int32)
+
+
+@dataclass
+class IsingPotts:
+    """Potts tables made from an Ising instance (accepted by build_peps)."""
+    rows: int
+    cols: int
+    d: int
+    kings: bool
+    local_E: np.ndarray
+    pair_h: np.ndarray
+    pair_v: np.ndarray
+    pair_d: np.ndarray
+    pair_a: np.ndarray
+    beta: float = 1.0
+
+    @property
+    def n_sites(self) -> int:
+        return self.rows * self.cols
+
+    def tables(self):
+        return self.local_E, self.pair_h, self.pair_v, self.pair_d, self.pair_a
+
+
+def ising_to_potts(n_spins: int, i, j, J, rows: int, cols: int, t: int, kings: bool,
+                   cluster_of=None, beta: float = 1.0) -> IsingPotts:
+    """spg_ising_to_potts: the Potts tables of an Ising instance on a rows x cols
+    lattice of t-spin clusters (cluster_of defaults to lattice_clusters)."""
+    d = 1 << t
+    ti = np.ascontiguousarray(i, dtype=np.int32)
+    tj = np.ascontiguousarray(j, dtype=np.int32)
+    tJ = np.ascontiguousarray(J, dtype=np.float64)
+    cl = np.ascontiguousarray(lattice_clusters(rows, cols, t) if cluster_of is None
+                              else cluster_of, dtype=np.int32)
+    le = np.zeros((rows, cols, d))
+    ph = np.zeros((rows, max(cols - 1, 0), d, d))
+    pv = np.zeros((max(rows - 1, 0), cols, d, d))
+    pd = np.zeros((max(rows - 1, 0), max(cols - 1, 0), d, d))
+    pa = np.zeros_like(pd)
+    _check(load().spg_ising_to_potts(int(n_spins), int(ti.size), ti.ctypes.data, tj.ctypes.data,
+                                     tJ.ctypes.data, int(rows), int(cols), int(t),
+                                     1 if kings else 0, cl.ctypes.data, le.ctypes.data,
+                                     ph.ctypes.data, pv.ctypes.data, pd.ctypes.data,
+                                     pa.ctypes.data))
+    return IsingPotts(rows, cols, d, bool(kings), le, ph, pv, pd, pa, float(beta))
 
 
 @dataclass
