@@ -92,3 +92,34 @@ def test_droplets_need_merging_and_a_search():
     with pytest.raises(spg.SpgError) as e:
         _run(env, inst, 8, merge_branches=True, droplets=(1.0, 0, 65))
     assert e.value.code == -5
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_droplets_reduced_precision_search(precision):
+    """With FP32 / BF16 search contractions the beam need not equal the
+    oracle's; the droplets must still be exact excitations of their states:
+    Eq. (1) energies, gaps within the cut-off, the Hamming rule, and the same
+    beam as merging without droplets."""
+    R, C, d, kings, chi, M = 3, 4, 2, True, 16, 40
+    ecut, hcut, cap = 5.0, 1, 8
+    inst = random_potts(R, C, d, kings, seed=3, beta=1.0)
+    peps = spg.build_peps(inst)
+    env, _ = spg.boundary_mps(peps, chi, precision=precision, want_logZ=False)
+    st0, en0 = _run(env, inst, M, merge_branches=True)
+    st, en = _run(env, inst, M, merge_branches=True, droplets=(ecut, hcut, cap))
+    np.testing.assert_array_equal(st, st0)
+    np.testing.assert_array_equal(en, en0)
+    total = 0
+    for i in range(len(st)):
+        cfg, de = spg.droplets(env, i)
+        assert len(cfg) <= cap
+        if len(cfg) == 0:
+            continue
+        np.testing.assert_allclose(de, potts_energy(inst, cfg), atol=1e-9)
+        assert np.all(de - en[i] >= -1e-9) and np.all(de - en[i] <= ecut + 1e-9)
+        for a in range(len(cfg)):
+            assert np.count_nonzero(cfg[a] != st[i]) > hcut
+            for b in range(a):
+                assert np.count_nonzero(cfg[a] != cfg[b]) > hcut
+        total += len(cfg)
+    assert total > 0
