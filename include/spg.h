@@ -146,7 +146,8 @@ int spg_marginals(const spg_env_t *env, int32_t site, int32_t n_beam, const int3
 /* Branch-and-bound search (Sec. 2; Fig. 1(d)-(e)): visits the sites in
  * row-major order, keeping the max_states most probable partial
  * configurations (ties: parent position, then state), and returns the final
- * beam sorted by energy ascending.
+ * beam: the states with a finite log-probability first, sorted by energy
+ * ascending (ties: beam position), then the beam's other slots.
  * With params->proposal set (FP64 envs only, else SPG_ERR_UNSUPPORTED), each
  * step first ranks the children with the network, evaluates exactly only the
  * best-ranked ones (about kappa * max_states), and bounds every other child

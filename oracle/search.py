@@ -183,7 +183,8 @@ def update_droplets(drops, cfg_new, kept, b, s, k, runners, cfg, energy_kept, d,
 def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None, merge=False,
                 droplets=None):
     """Run the search with boundary MPS tensors A[r][c].  Returns dict with
-    'states' [n][N], 'energies', 'scores' (sorted by energy) and 'beam_energies'
+    'states' [n][N], 'energies', 'scores' (the states of finite score first,
+    sorted by energy, then the other beam slots) and 'beam_energies'
     (the final beam in beam order).  ``trace`` (optional list) receives per-site
     dicts with the parents' log-conditionals for teacher-forced comparisons.
     ``droplets`` = (energy_cutoff, hamming_cutoff, max_droplets), with merging:
@@ -240,7 +241,9 @@ def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None, merge=Fa
             L = Lb / np.where(m > 0, m, 1.0)
             anc = anc[b]
     E = potts_energy(inst, cfg)
-    order = np.lexsort((np.arange(len(E)), E))
+    # finite log-probabilities first, by energy, then index; then the slots
+    # that hold pruned or merged-away children
+    order = np.lexsort((np.arange(len(E)), E, ~np.isfinite(score)))
     out = {"states": cfg[order], "energies": E[order], "scores": score[order],
            "beam_states": cfg, "beam_scores": score, "beam_energies": energy,
            "n_valid": int(np.isfinite(score).sum())}

@@ -651,10 +651,13 @@ __global__ __launch_bounds__(1024) void k_final_sort(int n, const double *E, con
   int local = 0;
   for (int i = threadIdx.x; i < p2; i += blockDim.x) {
     if (i < n) {
-      kw[i] = asc_key(E[i]);
-      iw[i] = i;
+      // rows with a finite log-probability first, by energy; the rest (beam
+      // slots filled with pruned or merged-away children) after them
       const double sc = score[i];
-      local += (sc == sc && sc > -INFINITY);
+      const bool live = (sc == sc && sc > -INFINITY);
+      kw[i] = live ? asc_key(E[i]) : ~0ull;
+      iw[i] = i;
+      local += live;
     } else {
       kw[i] = ~0ull;
       iw[i] = INT_MAX;

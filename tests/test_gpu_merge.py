@@ -7,8 +7,10 @@ energy, ties by id, so the kept sets must be identical.  Checked: the final
 beam (states bitwise, scores 1e-8, energies 1e-9) on square and king's
 lattices with several d and beams, with the cut-off, with FP32 search
 contractions (where only the dynamic-programming property is checked), and the
-exact dynamic-programming case: a beam of d^(cols+1) after merging must reach
-the brute-force ground state."""
+exact dynamic-programming case: a beam of d^(cols+1) or more after merging
+must return the brute-force least-energy state of every final frontier."""
+import itertools
+
 import numpy as np
 import pytest
 
@@ -67,14 +69,35 @@ def test_merged_search_matches_oracle(name, R, C, d, kings, chi, M, cut):
     assert len({tuple(x[-w:]) for x in st.tolist()}) == len(st)
 
 
+def _dp_states(inst):
+    """Per final frontier (the last cols + 1 sites), the configuration of least
+    Eq. (1) energy over all d^N, ties by lowest enumeration index."""
+    N, d = inst.rows * inst.cols, inst.d
+    X = np.array(list(itertools.product(range(d), repeat=N)), dtype=np.int64)
+    E = potts_energy(inst, X)
+    w = frontier_width(inst, N - 1)
+    best = {}
+    for i in np.lexsort((np.arange(len(E)), E)):
+        best.setdefault(tuple(X[i, N - w:].tolist()), tuple(X[i].tolist()))
+    return set(best.values())
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("R,C,d,kings", [(3, 3, 2, True), (2, 4, 3, True), (3, 4, 2, False)])
-def test_frontier_sized_beam_is_exact_dynamic_programming(R, C, d, kings, precision):
+@pytest.mark.parametrize("wide", [1, 3])
+@pytest.mark.parametrize("R,C,d,kings", [(3, 3, 2, True), (2, 4, 3, True), (3, 4, 2, False),
+                                         (3, 2, 3, True)])
+def test_frontier_sized_beam_is_exact_dynamic_programming(R, C, d, kings, wide, precision):
+    # A beam of at least d^(cols+1) never prunes after merging, so it returns
+    # exactly one least-energy state per final frontier, whatever the scores.
+    # With wide = 3 most beam slots hold merged-away children (score -inf),
+    # which must not be returned among the n_out states.
     inst = random_potts(R, C, d, kings, seed=R + C + d + 40, beta=0.9)
     ref = brute_force(inst)
     _, _, env = _env(inst, d ** (C // 2), precision)          # exact bond dimension
-    st, en, lp = _run(env, inst, d ** (C + 1), merge_branches=True)
+    st, en, lp = _run(env, inst, wide * d ** (C + 1), merge_branches=True)
     assert abs(en[0] - ref["E_min"]) < 1e-9
+    assert {tuple(x) for x in st.tolist()} == _dp_states(inst)
+    assert np.all(np.isfinite(lp)) and np.all(np.diff(en) >= 0)
 
 
 def test_merging_with_a_proposal_is_refused():

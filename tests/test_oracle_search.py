@@ -121,3 +121,29 @@ def test_merge_keeps_the_lowest_energy_child_per_frontier():
     energy[1] = 5.0                                            # tie: lowest id wins
     out = merge_branches(cand, cfg, energy, dE, k=1, w=2)
     assert np.isfinite(out[0, 0]) and not np.isfinite(out[1, 0])
+
+
+@_pytest.mark.parametrize("R,C,d,kings,seed", [(3, 2, 3, True, 5), (3, 3, 2, False, 6)])
+def test_merged_wide_beam_returns_the_least_energy_state_of_every_frontier(R, C, d, kings, seed):
+    """A beam three times the number of frontiers: most slots then hold
+    merged-away children of score -inf.  The finite states must be exactly the
+    brute-force least-energy configuration of each final frontier, and they
+    come first in the returned order."""
+    from workloads import random_potts
+    from oracle.bmps import boundary_mps
+    from oracle.energy import potts_energy
+    inst = random_potts(R, C, d, kings, seed=seed, beta=0.7)
+    N = R * C
+    X = np.array(list(itertools.product(range(d), repeat=N)), dtype=np.int64)
+    E = potts_energy(inst, X)
+    w = frontier_width(inst, N - 1)
+    best = {}
+    for i in np.argsort(E, kind="stable"):
+        best.setdefault(tuple(X[i, N - w:].tolist()), tuple(X[i].tolist()))
+    res = _beam(inst, boundary_mps(inst, d ** C)["A"], 3 * d ** (C + 1), merge=True)
+    n = res["n_valid"]
+    assert n == len(best) and np.all(np.isfinite(res["scores"][:n]))
+    assert {tuple(x) for x in res["states"][:n].tolist()} == set(best.values())
+    # merged-away children of lower energy than some returned state exist,
+    # so the finite-first order is really exercised
+    assert res["energies"][n:].min() < res["energies"][:n].max()
