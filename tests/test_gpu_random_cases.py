@@ -59,3 +59,131 @@ def test_random_case_matches_oracle(k):
     np.testing.assert_allclose(en, potts_energy(inst, st), atol=1e-9)
     if n:
         assert abs(en[0] - ref["energies"][fin].min()) < 1e-9
+
+
+def _search(env, N, M, **kw):
+    st = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+    en = torch.zeros(M, dtype=torch.float64, device=DEV)
+    lp = torch.zeros(M, dtype=torch.float64, device=DEV)
+    n = spg.branch_and_bound(env, M, st, en, lp, **kw)
+    torch.cuda.synchronize()
+    return st.cpu().numpy()[:n], en.cpu().numpy()[:n], lp.cpu().numpy()[:n]
+
+
+def _small_shape(rng, max_states=1 << 15, min_sites=1):
+    while True:
+        R, C, d = int(rng.integers(1, 5)), int(rng.integers(2, 6)), int(rng.choice([2, 3, 4]))
+        if d ** (R * C) <= max_states and d ** (C // 2) <= 64 and R * C >= min_sites:
+            return R, C, d
+
+
+@pytest.mark.parametrize("k", range(12))
+def test_random_exact_regime_gpu_pipeline_vs_brute_force(k):
+    """The whole GPU pipeline (PEPS, boundary MPS at the exact bond dimension,
+    search) against brute force: log Z to 1e-9; with a beam of every state
+    the returned energies are the sorted spectrum."""
+    from oracle.exact import brute_force
+    rng = np.random.default_rng(3000 + k)
+    R, C, d = _small_shape(rng)
+    kings = bool(rng.integers(0, 2))
+    inst = random_potts(R, C, d, kings, seed=4000 + k, beta=float(rng.uniform(0.2, 1.2)))
+    bf = brute_force(inst)
+    peps = spg.build_peps(inst)
+    env, lz = spg.boundary_mps(peps, d ** (C // 2))
+    assert abs(lz - bf["logZ"]) < 1e-9 * max(1.0, abs(bf["logZ"]))
+    N = R * C
+    if d ** N <= 2048:
+        st, en, lp = _search(env, N, d ** N)
+        assert len(st) == d ** N
+        np.testing.assert_allclose(en, np.sort(bf["E"]), atol=1e-9)
+        np.testing.assert_allclose(en, potts_energy(inst, st), atol=1e-9)
+        # the scores are the exact log-probabilities -beta E - log Z
+        np.testing.assert_allclose(lp, -inst.beta * en - bf["logZ"], atol=1e-8)
+    else:
+        st, en, lp = _search(env, N, 64)
+        np.testing.assert_allclose(en, potts_energy(inst, st), atol=1e-9)
+        assert en[0] >= bf["E_min"] - 1e-9
+
+
+def _alone(inst, chi, M, prec, cut):
+    peps = spg.build_peps(inst)
+    try:
+        env, lz = spg.boundary_mps(peps, chi, precision=prec)
+    except spg.SpgError as e:
+        assert e.code == -4            # non-finite log Z: a batch reports NaN
+        env, _ = spg.boundary_mps(peps, chi, precision=prec, want_logZ=False)
+        lz = float("nan")
+    st, en, lp = _search(env, inst.rows * inst.cols, M, cut_off_prob=cut)
+    return st, en, lp, lz
+
+
+@pytest.mark.parametrize("k", range(6))
+def test_random_batch_equals_each_instance_alone(k):
+    """Random batches (shapes, d, chi, beams, precisions, shared shape classes,
+    stream counts, cut-off): eager runs and graph replays give bitwise each
+    instance's own run."""
+    rng = np.random.default_rng(5000 + k)
+    cut = float(rng.choice([0.0, 1e-3]))
+    insts = []
+    for i in range(int(rng.integers(2, 6))):
+        if insts and rng.random() < 0.4:            # a member of the previous shape class
+            p = insts[-1]
+            inst = random_potts(p[0].rows, p[0].cols, p[0].d, p[4], seed=6000 + 10 * k + i,
+                                beta=1.0)
+            insts.append((inst, p[1], p[2], p[3], p[4]))
+            continue
+        R, C = int(rng.integers(2, 6)), int(rng.integers(2, 6))
+        d = int(rng.choice([2, 3, 4, 5]))
+        kings = bool(rng.integers(0, 2))
+        inst = random_potts(R, C, d, kings, seed=6000 + 10 * k + i,
+                            beta=float(rng.uniform(0.3, 1.2)))
+        insts.append((inst, int(rng.choice([4, 8, 12])), int(rng.choice([1, 9, 40, 100])),
+                      str(rng.choice(["fp64", "fp64", "fp32"])), kings))
+    peps = [spg.build_peps(x[0]) for x in insts]
+    b = spg.Batch(peps, chi=[x[1] for x in insts], max_states=[x[2] for x in insts],
+                  precision=[x[3] for x in insts], cut_off_prob=cut,
+                  n_streams=int(rng.integers(1, 4)), classes=bool(rng.integers(0, 2)))
+    b.run(use_graph=False)
+    eager = [b.result(i) for i in range(b.n)]
+    for i, (inst, chi, M, prec, _) in enumerate(insts):
+        a = _alone(inst, chi, M, prec, cut)
+        for u, v in zip(eager[i][:3], a[:3]):
+            assert np.array_equal(u, v), f"instance {i}"
+        assert eager[i][3] == a[3] or (np.isnan(eager[i][3]) and np.isnan(a[3])), f"instance {i}"
+    for rep in range(2):
+        b.run(use_graph=True)
+        torch.cuda.synchronize()
+        for i in range(b.n):
+            for u, v in zip(b.result(i)[:3], eager[i][:3]):
+                assert np.array_equal(u, v), f"replay {rep} instance {i}"
+
+
+@pytest.mark.parametrize("k", range(10))
+def test_random_droplets_match_oracle(k):
+    """Random merged searches with droplets (cut-offs, beams narrower and wider
+    than the number of frontiers): per returned state the oracle's droplets in
+    its order, bitwise configurations and energies to 1e-9."""
+    rng = np.random.default_rng(7000 + k)
+    R, C, d = _small_shape(rng, 1 << 20, min_sites=6)
+    kings = bool(rng.integers(0, 2))
+    inst = random_potts(R, C, d, kings, seed=8000 + k, beta=float(rng.uniform(0.3, 1.0)))
+    chi = min(d ** (C // 2), 16)
+    ora = oracle_bmps(inst, chi)
+    T, dims = spg.pack_oracle_mps(ora["A"], chi, d)
+    env = spg.env_import(spg.build_peps(inst), chi, dims, T, np.array(ora["lam"]))
+    M = int(rng.choice([3, 20, 60, 3 * d ** min(C + 1, R * C)]))
+    cut = float(rng.choice([0.0, 1e-3]))
+    drop = (float(rng.choice([0.5, 3.0, 20.0])), int(rng.integers(0, 3)), int(rng.choice([1, 4, 64])))
+    N = R * C
+    st, en, _ = _search(env, N, M, cut_off_prob=cut, merge_branches=True, droplets=drop)
+    ref = beam_search(inst, ora["A"], M, cut_off_prob=cut, merge=True, droplets=drop)
+    fin = np.isfinite(ref["scores"])
+    assert {tuple(x) for x in st.tolist()} == {tuple(x) for x in ref["states"][fin].tolist()}
+    by_state = {tuple(x.tolist()): dl for x, dl, f in zip(ref["states"], ref["droplets"], fin) if f}
+    for i in range(len(st)):
+        cfg, de = spg.droplets(env, i)
+        want = by_state[tuple(st[i].tolist())]
+        assert len(cfg) == len(want), i
+        for (x, e), y, g in zip(want, cfg, de):
+            np.testing.assert_array_equal(y, x)
+            assert abs(g - e) < 1e-9
