@@ -36,14 +36,15 @@ WORKLOAD = dict(name="kings8x8_d16", seed=0, chi=32, max_states=1024, num_sweeps
                 oversample=16, power_iters=1)
 # MI355X published peaks
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "hbm_GBs": 8000.0}
-FLOP_CLASSES = {"gemm_f64", "qr_f64", "right_env", "marginals", "beam_update"}
+FLOP_CLASSES = {"gemm_f64", "qr_f64", "right_env", "marginals", "beam_update", "u_mfma"}
 BYTE_CLASSES = {"normalize_box", "select_topm"}
 
 
 CLASS_KERNEL = {"gemm_f64": "k_gemm<32>", "qr_f64": "k_qr_reg<8, 3>", "jacobi_svd_f64": "k_jacobi<3>",
                 "normalize_box": "k_box_scale", "right_env": "k_right_env",
                 "marginals": "k_marginals", "select_topm": "k_select",
-                "beam_update": "k_beam_update", "final_sort": "k_final_sort"}
+                "beam_update": "k_beam_update", "final_sort": "k_final_sort",
+                "u_mfma": "k_u_mfma<float>"}
 KERNEL_SOURCES = ["k_linalg.hip", "k_bmps.hip", "k_search.hip", "k_search_lp.hip",
                   "k_propose.hip", "k_mlp.hip"]
 # batching form: the first BATCH_N instances of the batched workload (lattice
@@ -462,6 +463,20 @@ def main():
         roof["workgroups_per_launch"] = 1
         roof["frac_of_one_cu"] = roof["frac"] * 256
 
+    # the matrix-core product of the reduced-precision search (U = R A^T over
+    # all ancestors of a row), against the dense MFMA peak of its input type
+    mfma = None
+    if args.precision != "fp64" and prof.get("u_mfma", (0, 0.0, 0.0))[1] > 0.0:
+        mc, mt, mw = prof["u_mfma"]
+        ach = mw / (mt * 1e-3) / 1e12
+        mfma = {"kernel": "k_u_mfma<float>" if args.precision == "fp32"
+                else "k_u_mfma<unsigned short>",
+                "instruction": "v_mfma_f32_16x16x4_f32" if args.precision == "fp32"
+                else "v_mfma_f32_16x16x16_bf16",
+                "achieved": ach, "peak": PEAK[args.precision], "unit": "TFLOP/s",
+                "frac": ach / PEAK[args.precision], "launches_per_step": mc / args.steps,
+                "avg_launch_us": mt * 1e3 / max(mc, 1)}
+
     dt = {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16"}[args.precision]
     out = {
         "metric": "conditional-marginal evals/s", "value": ev / (ms * 1e-3), "unit": "evals/s",
@@ -480,6 +495,7 @@ def main():
                   "search_evals_per_s": ev / (c - b)},
         "kernels": {k: {"launches": v[0], "ms": v[1], "work": v[2]} for k, v in prof.items()},
         "roofline": roof,
+        "matrix_cores": mfma,
     }
     if not args.no_forms:
         out["forms"] = {"learned_proposal": proposal_leg(spg, torch, inst, wl, M, st, en, lp,

@@ -511,7 +511,8 @@ void spg_free_env(spg_env_t *env) {
   (void)hipDeviceSynchronize();
   for (DevBuf *b : {&env->A, &env->Alp, &env->lam, &env->cfg[0], &env->cfg[1], &env->score[0],
                     &env->score[1], &env->energy[0], &env->energy[1], &env->L[0], &env->L[1],
-                    &env->anc[0], &env->anc[1], &env->Rv, &env->cand, &env->sel, &env->keys,
+                    &env->anc[0], &env->anc[1], &env->Rv, &env->Ulp, &env->cand, &env->sel,
+                    &env->keys,
                     &env->ids, &env->ework, &env->perm, &env->nvalid, &env->tmp, &env->cfg32})
     b->release();
   delete env;
@@ -674,6 +675,8 @@ static void each_search_buffer(spg_env *env, int M, F &&f) {
     f(env->anc[i], (size_t)M * 4);
   }
   f(env->Rv, (size_t)M * (C + 1) * chi * 8);
+  // reduced-precision search: U_c of every column for the row's ancestors
+  if (env->precision != SPG_FP64) f(env->Ulp, (size_t)C * M * chi * d * 4);
   f(env->cand, (size_t)M * d * 8);
   f(env->sel, (size_t)M * 4);
   f(env->keys, (size_t)p2 * 8);
@@ -726,18 +729,23 @@ int spg_marginals(const spg_env_t *cenv, int32_t site, int32_t n_beam, const int
     const char *Al = env->Alp.as<char>();
     const size_t eb = lp_elt(env);
     float *Rv = env->Rv.as<float>();
+    float *U = env->Ulp.as<float>();
+    const long ldu = (long)chi * d;
     lp_set_e0(n_beam, chi, Rv + (size_t)C * chi, rstride, s);
-    for (int cc = C - 1; cc > c; --cc)
-      lp_right_env_col(t, pr, r, cc, n_beam, cfg, N, Al + ((size_t)r * C + cc) * site_sz * eb,
-                       Rv + (size_t)(cc + 1) * chi, Rv + (size_t)cc * chi, rstride, dm[cc],
-                       dm[cc + 1], s);
+    // the products and environments of the search, each beam state its own ancestor
+    for (int cc = C - 1; cc >= c; --cc) {
+      lp_u_col(t, pr, n_beam, Al + ((size_t)r * C + cc) * site_sz * eb,
+               Rv + (size_t)(cc + 1) * chi, rstride, U, ldu, dm[cc], dm[cc + 1], s);
+      if (cc > c)
+        lp_env_from_u(t, pr, r, cc, n_beam, cfg, N, U, ldu, Rv + (size_t)cc * chi, rstride,
+                      dm[cc], s);
+    }
     float *L = env->L[0].as<float>();
     beam_reset_row(n_beam, chi, env->L[1].as<double>(), anc, s);
     lp_set_e0(n_beam, chi, L, chi, s);
     for (int cc = 0; cc < c; ++cc)
       lp_advance_L(t, pr, r, cc, n_beam, cfg, N, Al + ((size_t)r * C + cc) * site_sz * eb, L, s);
-    lp_marginals(t, pr, r, c, n_beam, cfg, N, Al + ((size_t)r * C + c) * site_sz * eb, L, anc, Rv,
-                 rstride, nullptr, log_cond_out, 0, dm[c], dm[c + 1], s);
+    lp_marginals_u(t, r, c, n_beam, cfg, N, U, ldu, L, anc, nullptr, log_cond_out, 0, dm[c], s);
   }
   (void)d;
   return SPG_OK;
@@ -861,6 +869,7 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
   fill_zero(env->energy[0].as<double>(), 1, s);
   const double log_cut = (prm->cut_off_prob > 0.0) ? std::log(prm->cut_off_prob) : 0.0;
   const bool lp = env->precision != SPG_FP64;
+  const long ldu = (long)chi * d;                  // U row stride (reduced precision)
   const char *Al = env->Alp.as<char>();
   const size_t eb = lp ? lp_elt(env) : 0;
   int64_t n_resolved = 0;
@@ -887,10 +896,16 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
       lp_set_e0(n_anc, chi, env->L[cur].as<float>(), chi, s);
       float *Rf = env->Rv.as<float>();
       lp_set_e0(n_anc, chi, Rf + (size_t)C * chi, rstride, s);
-      for (int c = C - 1; c >= 1; --c)
-        lp_right_env_col(t, env->precision, r, c, n_anc, env->cfg[cur].as<uint8_t>(), N,
-                         Al + ((size_t)r * C + c) * site_sz * eb, Rf + (size_t)(c + 1) * chi,
-                         Rf + (size_t)c * chi, rstride, dm[c], dm[c + 1], s);
+      // U_c = A_c R_{c+1} for every ancestor and column: R_c comes from U_c,
+      // and the conditionals of column c read U_c again
+      for (int c = C - 1; c >= 0; --c) {
+        float *Uc = env->Ulp.as<float>() + (size_t)c * M * ldu;
+        lp_u_col(t, env->precision, n_anc, Al + ((size_t)r * C + c) * site_sz * eb,
+                 Rf + (size_t)(c + 1) * chi, rstride, Uc, ldu, dm[c], dm[c + 1], s);
+        if (c >= 1)
+          lp_env_from_u(t, env->precision, r, c, n_anc, env->cfg[cur].as<uint8_t>(), N, Uc, ldu,
+                        Rf + (size_t)c * chi, rstride, dm[c], s);
+      }
     } else {
       set_e0(n_anc, chi, Rv + (size_t)C * chi, rstride, s);
       // the guarded steps also need R_0 and the scales (Z_b = scale * L^b . R_c)
@@ -924,9 +939,9 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
         sel_score = env->selscore.as<double>();
       } else {
         if (lp)
-          lp_marginals(t, env->precision, r, c, (int)B, cfg, N, Alc, env->L[cur].as<float>(),
-                       env->anc[cur].as<int32_t>(), env->Rv.as<float>(), rstride, score,
-                       env->cand.as<double>(), 1, dm[c], dm[c + 1], s);
+          lp_marginals_u(t, r, c, (int)B, cfg, N, env->Ulp.as<float>() + (size_t)c * M * ldu, ldu,
+                         env->L[cur].as<float>(), env->anc[cur].as<int32_t>(), score,
+                         env->cand.as<double>(), 1, dm[c], s);
         else
           marginals(t, r, c, (int)B, cfg, N, Arc, env->L[cur].as<double>(),
                     env->anc[cur].as<int32_t>(), Rv, rstride, score, env->cand.as<double>(), 1,

@@ -54,12 +54,73 @@ __device__ __forceinline__ double log_field(const SearchTabs &t, int r, int c, c
 
 constexpr int kW = 4;
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+// U[a][p] = sum_b R^a[b] A[p][b] for every ancestor a and every pair p =
+// (al, s) of the site tensor A[al][s][b] (p = al * d + s, row stride chi):
+// the product shared by the right environments and the conditionals of a
+// column, one GEMM over all ancestors on the matrix cores (M = ancestors,
+// N = cl * d, K = cr).  A wavefront computes a 16 x 16 tile of U: lane l
+// supplies ancestor a0 + l % 16 and pair n0 + l % 16, and the four k of its
+// group l / 16 within each block of 16; FP32 inputs use four
+// v_mfma_f32_16x16x4f32 per block, BF16 inputs one v_mfma_f32_16x16x16bf16
+// (R is rounded to BF16, as it is stored in that form), accumulation in FP32.
+// Out-of-range rows, pairs and k read element 0 and contribute zero.
 template <class T>
-__global__ __launch_bounds__(256) void k_right_env_lp(SearchTabs t, int r, int c, int n_anc,
-                                                      const uint8_t *cfg, int N, const T *A,
-                                                      const float *Rnext, float *Rout,
-                                                      long rstride, int bf16) {
-  __shared__ float Rs[kW][kMaxChi];
+__global__ __launch_bounds__(256) void k_u_mfma(int n_anc, int npair, int cr, int chi, const T *A,
+                                                const float *R, long rstride, float *U,
+                                                long ldu) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int a0 = blockIdx.y * 16, n0 = (blockIdx.x * 4 + w) * 16;
+  if (n0 >= npair) return;                    // no barrier below
+  const int i = lane & 15, g = lane >> 4;
+  const bool oka = a0 + i < n_anc, okp = n0 + i < npair;
+  const float *Rrow = R + (oka ? (long)(a0 + i) * rstride : 0L);
+  const T *Arow = A + (okp ? (long)(n0 + i) * chi : 0L);
+  f4v acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < cr; k0 += 16) {
+    float rv[4];
+    T av[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + 4 * g + j;
+      const bool ok = k < cr;
+      const float x = Rrow[(ok && oka) ? k : 0];
+      const T y = Arow[(ok && okp) ? k : 0];
+      rv[j] = (ok && oka) ? x : 0.f;
+      av[j] = (ok && okp) ? y : (T)0;
+    }
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[j], (float)av[j], acc, 0, 0, 0);
+    } else {
+      s4v x, y;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        x[j] = (short)f2bf(rv[j]);
+        y[j] = (short)av[j];
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, acc, 0, 0, 0);
+    }
+  }
+  // lane l holds U[a0 + 4 (l / 16) + q][n0 + l % 16], q = 0..3
+  if (okp) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int a = a0 + 4 * g + q;
+      if (a < n_anc) U[(long)a * ldu + n0 + i] = acc[q];
+    }
+  }
+}
+
+// R^a_c[al] = sum_s g^a_c(s) U^a[al][s], normalised by its largest |entry|
+// (one wavefront per ancestor; couplings relative to their maximum over s).
+__global__ __launch_bounds__(256) void k_env_from_u(SearchTabs t, int r, int c, int n_anc,
+                                                    const uint8_t *cfg, int N, const float *U,
+                                                    long ldu, float *Rout, long rstride,
+                                                    int bf16, int cl) {
   __shared__ float gs[kW][256];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int a0 = blockIdx.x * kW + w;
@@ -75,146 +136,63 @@ __global__ __launch_bounds__(256) void k_right_env_lp(SearchTabs t, int r, int c
     lmax = fmax(lmax, lg[h]);
   }
   for (int o = 32; o > 0; o >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, o, 64));
-  if (valid) {
-    for (int i = lane; i < chi; i += 64) Rs[w][i] = Rnext[a * rstride + i];
+  if (valid)
     for (int h = 0; h < 4; ++h) {
       const int s = lane + 64 * h;
       if (s < d) gs[w][s] = (float)exp(lg[h] - lmax);
     }
-  }
   __syncthreads();
   if (!valid) return;
-  float v[2] = {0.f, 0.f};
-  for (int h = 0; h < 2; ++h) {
-    const int al = lane + 64 * h;
-    if (al >= chi) continue;
-    float acc = 0.f;
-    for (int s = 0; s < d; ++s) {
-      const long base = ((long)al * d + s) * chi;
-      float u = 0.f;
-      for (int b = 0; b < chi; ++b) u = fmaf(ld(A, base + b), Rs[w][b], u);
-      acc = fmaf(gs[w][s], u, acc);
-    }
-    v[h] = acc;
-  }
-  const float m = wave_max_f(fmaxf(fabsf(v[0]), fabsf(v[1])));
-  const float inv = (m > 0.f) ? 1.f / m : 1.f;
-  for (int h = 0; h < 2; ++h) {
-    const int al = lane + 64 * h;
-    if (al < chi) Rout[a * rstride + al] = vround(v[h] * inv, bf16);
-  }
-}
-
-// out[b*d+s] = (add_score ? score[b] : 0) + log p(s | b)
-// The same with the site tensor staged in LDS once per workgroup (when its
-// cl x d x cr block fits): every lane of an ancestor's wavefront takes
-// (al, s) pairs, u[al][s] = sum_b A[al][s][b] R[b] in b order, then lane al
-// sums g(s) u[al][s] in s order; rows al >= cl are zero as before.  The same
-// order of terms as k_right_env_lp: identical results.
-constexpr int kEnvLds = 32 * 16 * 33;      // floats of the staged block, cl * d * (cr + 1)
-constexpr int kEnvU = 32 * 16;             // per-wave u[al][s], cl * d
-
-__host__ __device__ constexpr bool env_lds_fits(int cl, int d, int cr) {
-  return d <= 64 && cr <= 64 && cl * d <= kEnvU && cl * d * (cr + 1) <= kEnvLds;
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_right_env_lp_lds(SearchTabs t, int r, int c, int n_anc,
-                                                          const uint8_t *cfg, int N, const T *A,
-                                                          const float *Rnext, float *Rout,
-                                                          long rstride, int bf16, int cl, int cr) {
-  __shared__ float As[kEnvLds];
-  __shared__ float us[kW][kEnvU];
-  __shared__ float Rs[kW][kMaxChi];
-  __shared__ float gs[kW][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int a0 = blockIdx.x * kW + w;
-  const bool valid = a0 < n_anc;
-  const int a = valid ? a0 : 0;
-  const int chi = t.chi, d = t.d;
-  const int npair = cl * d, ldr = cr + 1;
-  {
-    const int rpp = 64 / cr, sub = lane / cr, bb = lane - sub * cr;
-    if (sub < rpp) {
-      const int step = kW * rpp;
-      int p = w * rpp + sub;
-      for (; p + 7 * step < npair; p += 8 * step) {
-        float v[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = ld(A, (long)(p + k * step) * chi + bb);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) As[(p + k * step) * ldr + bb] = v[k];
-      }
-      for (; p < npair; p += step) As[p * ldr + bb] = ld(A, (long)p * chi + bb);
-    }
-  }
-  const uint8_t *cb = cfg + (long)a * N;
-  // couplings relative to their largest value over s
-  double lg = (lane < d) ? log_field(t, r, c, cb, lane) : -INFINITY;
-  double lmax = lg;
-  for (int o = 32; o > 0; o >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, o, 64));
-  if (valid) {
-    for (int i = lane; i < chi; i += 64) Rs[w][i] = Rnext[a * rstride + i];
-    if (lane < d) gs[w][lane] = (float)exp(lg - lmax);
-  }
-  __syncthreads();
-  if (valid) {
-    for (int p0 = 0; p0 < npair; p0 += 64 * 8) {
-      float u[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) u[k] = 0.f;
-      const int pl = p0 + lane;
-      for (int b = 0; b < cr; ++b) {
-        const float rb = Rs[w][b];
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-          if (pl + 64 * k < npair) u[k] = fmaf(As[(pl + 64 * k) * ldr + b], rb, u[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (pl + 64 * k < npair) us[w][pl + 64 * k] = u[k];
-    }
-  }
-  __syncthreads();
-  if (!valid) return;
+  const float *Ua = U + (long)a * ldu;
   float v[2] = {0.f, 0.f};
   for (int h = 0; h < 2; ++h) {
     const int al = lane + 64 * h;
     if (al >= cl) continue;
     float acc = 0.f;
-    for (int s = 0; s < d; ++s) acc = fmaf(gs[w][s], us[w][al * d + s], acc);
+    for (int s = 0; s < d; ++s) acc = fmaf(gs[w][s], Ua[(long)al * d + s], acc);
     v[h] = acc;
   }
   const float m = wave_max_f(fmaxf(fabsf(v[0]), fabsf(v[1])));
   const float inv = (m > 0.f) ? 1.f / m : 1.f;
   for (int h = 0; h < 2; ++h) {
     const int al = lane + 64 * h;
-    if (al < chi) Rout[a * rstride + al] = vround(v[h] * inv, bf16);
+    if (al < chi) Rout[a * rstride + al] = (al < cl) ? vround(v[h] * inv, bf16) : 0.f;
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_marginals_lp(SearchTabs t, int r, int c, int n_beam,
-                                                      const uint8_t *cfg, int N, const T *A,
-                                                      const float *L, const int32_t *anc,
-                                                      const float *Rv, long rstride,
-                                                      const double *score, double *out,
-                                                      int add_score) {
-  __shared__ float Ls[kW][kMaxChi];
-  __shared__ float Rs[kW][kMaxChi];
+// out[b*d+s] = (add_score ? score[b] : 0) + log p(s | b), with
+// q(b, s) = g^b(s) sum_al L^b[al] U^{anc(b)}[al][s] (one wavefront per beam
+// state).  For d <= 64 the lanes form 64 / d groups, group j summing the al
+// = j mod (64 / d) terms, and lane s adds the groups' sums in group order.
+__global__ __launch_bounds__(256) void k_marg_from_u(SearchTabs t, int r, int c, int n_beam,
+                                                     const uint8_t *cfg, int N, const float *U,
+                                                     long ldu, const float *L,
+                                                     const int32_t *anc, const double *score,
+                                                     double *out, int add_score, int cl) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int b0 = blockIdx.x * kW + w;
-  const bool valid = b0 < n_beam;
-  const int b = valid ? b0 : 0;
+  const int b = blockIdx.x * kW + w;
+  if (b >= n_beam) return;                    // no barrier below
   const int chi = t.chi, d = t.d;
-  const float *Rn = Rv + (long)anc[b] * rstride + (long)(c + 1) * chi;
-  if (valid)
-    for (int i = lane; i < chi; i += 64) {
-      Ls[w][i] = L[(long)b * chi + i];
-      Rs[w][i] = Rn[i];
+  const float *Ua = U + (long)anc[b] * ldu;
+  const float *Lb = L + (long)b * chi;
+  float q[4] = {0.f, 0.f, 0.f, 0.f};
+  if (d <= 64) {
+    const int G = 64 / d, s = lane % d, j = lane / d;
+    float part = 0.f;
+    if (j < G)
+      for (int al = j; al < cl; al += G) part = fmaf(Lb[al], Ua[(long)al * d + s], part);
+    float tot = 0.f;
+    for (int jj = 0; jj < G; ++jj) tot += __shfl(part, s + jj * d, 64);
+    q[0] = tot;
+  } else {
+    for (int h = 0; h < 4; ++h) {
+      const int s = lane + 64 * h;
+      if (s >= d) continue;
+      float acc = 0.f;
+      for (int al = 0; al < cl; ++al) acc = fmaf(Lb[al], Ua[(long)al * d + s], acc);
+      q[h] = acc;
     }
-  __syncthreads();
-  if (!valid) return;
+  }
   const uint8_t *cb = cfg + (long)b * N;
   float lq[4];
   float mx = -INFINITY;
@@ -222,17 +200,8 @@ __global__ __launch_bounds__(256) void k_marginals_lp(SearchTabs t, int r, int c
     const int s = lane + 64 * h;
     lq[h] = -INFINITY;
     if (s >= d) continue;
-    float acc = 0.f;
-    for (int al = 0; al < chi; ++al) {
-      const float la = Ls[w][al];
-      if (la == 0.f) continue;
-      const long base = ((long)al * d + s) * chi;
-      float u = 0.f;
-      for (int bb = 0; bb < chi; ++bb) u = fmaf(ld(A, base + bb), Rs[w][bb], u);
-      acc = fmaf(la, u, acc);
-    }
     // negative q (truncation error) = probability 0
-    lq[h] = (acc > 0.f) ? (float)log_field(t, r, c, cb, s) + logf(acc) : -INFINITY;
+    lq[h] = (q[h] > 0.f) ? (float)log_field(t, r, c, cb, s) + logf(q[h]) : -INFINITY;
     mx = fmaxf(mx, lq[h]);
   }
   mx = wave_max_f(mx);
@@ -246,103 +215,6 @@ __global__ __launch_bounds__(256) void k_marginals_lp(SearchTabs t, int r, int c
     const int s = lane + 64 * h;
     if (s >= d) continue;
     const float lp = (lq[h] > -INFINITY && mx > -INFINITY) ? lq[h] - lse : -INFINITY;
-    out[(long)b * d + s] = base + (double)lp;
-  }
-}
-
-// The same conditionals with the site tensor staged in LDS once per
-// workgroup (when its cl x d x cr block fits): all 64 lanes of a beam's wave
-// take (al, s) pairs, u[al][s] = sum_b A[al][s][b] R[b] in b order with eight
-// pairs in flight per lane, then lane s sums L[al] u[al][s] in al order.
-// Every sum runs in the same order as above, so the results are identical.
-constexpr int kMargLds = 32 * 16 * 33;     // floats of the staged block, cl * d * (cr + 1)
-constexpr int kMargU = 32 * 16;            // per-wave u[al][s], cl * d
-
-__host__ __device__ constexpr bool marg_lds_fits(int cl, int d, int cr) {
-  return d <= 64 && cr <= 64 && cl * d <= kMargU && cl * d * (cr + 1) <= kMargLds;
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_marginals_lp_lds(SearchTabs t, int r, int c, int n_beam,
-                                                          const uint8_t *cfg, int N, const T *A,
-                                                          const float *L, const int32_t *anc,
-                                                          const float *Rv, long rstride,
-                                                          const double *score, double *out,
-                                                          int add_score, int cl, int cr) {
-  __shared__ float As[kMargLds];
-  __shared__ float us[kW][kMargU];
-  __shared__ float Ls[kW][kMaxChi];
-  __shared__ float Rs[kW][kMaxChi];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int b0 = blockIdx.x * kW + w;
-  const bool valid = b0 < n_beam;
-  const int b = valid ? b0 : 0;
-  const int chi = t.chi, d = t.d;
-  const int npair = cl * d, ldr = cr + 1;
-  // A[al][s][0..cr) -> As[(al*d + s)*ldr + .]: each wave copies whole rows,
-  // 64 / cr rows per pass, eight rows' loads in flight
-  {
-    const int rpp = 64 / cr, sub = lane / cr, bb = lane - sub * cr;
-    if (sub < rpp) {
-      const int step = kW * rpp;
-      int p = w * rpp + sub;
-      for (; p + 7 * step < npair; p += 8 * step) {
-        float v[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = ld(A, (long)(p + k * step) * chi + bb);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) As[(p + k * step) * ldr + bb] = v[k];
-      }
-      for (; p < npair; p += step) As[p * ldr + bb] = ld(A, (long)p * chi + bb);
-    }
-  }
-  if (valid) {
-    const float *Rn = Rv + (long)anc[b] * rstride + (long)(c + 1) * chi;
-    for (int i = lane; i < chi; i += 64) {
-      Ls[w][i] = L[(long)b * chi + i];
-      Rs[w][i] = Rn[i];
-    }
-  }
-  __syncthreads();
-  if (valid) {
-    for (int p0 = 0; p0 < npair; p0 += 64 * 8) {
-      float u[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) u[k] = 0.f;
-      const int pl = p0 + lane;
-      for (int bb = 0; bb < cr; ++bb) {
-        const float rb = Rs[w][bb];
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-          if (pl + 64 * k < npair) u[k] = fmaf(As[(pl + 64 * k) * ldr + bb], rb, u[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (pl + 64 * k < npair) us[w][pl + 64 * k] = u[k];
-    }
-  }
-  __syncthreads();
-  if (!valid) return;
-  const uint8_t *cb = cfg + (long)b * N;
-  float lq = -INFINITY;
-  const int s = lane;
-  if (s < d) {
-    float acc = 0.f;
-    for (int al = 0; al < cl; ++al) {
-      const float la = Ls[w][al];
-      if (la == 0.f) continue;
-      acc = fmaf(la, us[w][al * d + s], acc);
-    }
-    // negative q (truncation error) = probability 0
-    lq = (acc > 0.f) ? (float)log_field(t, r, c, cb, s) + logf(acc) : -INFINITY;
-  }
-  const float mx = wave_max_f(lq);
-  float se = (s < d && lq > -INFINITY) ? expf(lq - mx) : 0.f;
-  se = wave_sum_f(se);
-  const float lse = mx + logf(se);
-  if (s < d) {
-    const double base = add_score ? score[b] : 0.0;
-    const float lp = (lq > -INFINITY && mx > -INFINITY) ? lq - lse : -INFINITY;
     out[(long)b * d + s] = base + (double)lp;
   }
 }
@@ -472,59 +344,54 @@ void lp_set_e0(int n, int chi, float *p, long stride, hipStream_t s) {
   SPG_CHECK_LAUNCH();
 }
 
-void lp_right_env_col(const SearchTabs &t, int precision, int r, int c, int n_anc,
-                      const uint8_t *cfg, int N, const void *A_rc, const float *Rnext,
-                      float *Rout, long rstride, int cl, int cr, hipStream_t s) {
-  bc_single("lp_right_env_col");
-  if (n_anc <= 0) return;
-  KTimer kt_("right_env", s, 2.0 * n_anc * cl * t.d * cr);
-  if (cl > 0 && cr > 0 && env_lds_fits(cl, t.d, cr)) {
-    if (precision == SPG_FP32)
-      hipLaunchKernelGGL(k_right_env_lp_lds<float>, dim3(nblk(n_anc, kW)), dim3(256), 0, s, t, r,
-                         c, n_anc, cfg, N, (const float *)A_rc, Rnext, Rout, rstride, 0, cl, cr);
-    else
-      hipLaunchKernelGGL(k_right_env_lp_lds<uint16_t>, dim3(nblk(n_anc, kW)), dim3(256), 0, s, t,
-                         r, c, n_anc, cfg, N, (const uint16_t *)A_rc, Rnext, Rout, rstride, 1, cl,
-                         cr);
-    SPG_CHECK_LAUNCH();
-    return;
+void lp_u_col(const SearchTabs &t, int precision, int n_anc, const void *A_rc,
+              const float *Rnext, long rstride, float *U, long ldu, int cl, int cr,
+              hipStream_t s) {
+  bc_single("lp_u_col");
+  const int npair = cl * t.d;
+  if (n_anc <= 0 || npair <= 0) return;
+  if (cr < 1 || cr > t.chi || cl > t.chi || ldu < npair) {
+    set_error("lp_u_col: bond dimensions outside the environment's");
+    throw Fail{SPG_ERR_INVALID};
   }
+  KTimer kt_("u_mfma", s, 2.0 * n_anc * npair * cr);
+  dim3 grid(nblk(npair, 64), nblk(n_anc, 16));
   if (precision == SPG_FP32)
-    hipLaunchKernelGGL(k_right_env_lp<float>, dim3(nblk(n_anc, kW)), dim3(256), 0, s, t, r, c,
-                       n_anc, cfg, N, (const float *)A_rc, Rnext, Rout, rstride, 0);
+    hipLaunchKernelGGL(k_u_mfma<float>, grid, dim3(256), 0, s, n_anc, npair, cr, t.chi,
+                       (const float *)A_rc, Rnext, rstride, U, ldu);
   else
-    hipLaunchKernelGGL(k_right_env_lp<uint16_t>, dim3(nblk(n_anc, kW)), dim3(256), 0, s, t, r, c,
-                       n_anc, cfg, N, (const uint16_t *)A_rc, Rnext, Rout, rstride, 1);
+    hipLaunchKernelGGL(k_u_mfma<uint16_t>, grid, dim3(256), 0, s, n_anc, npair, cr, t.chi,
+                       (const uint16_t *)A_rc, Rnext, rstride, U, ldu);
   SPG_CHECK_LAUNCH();
 }
 
-void lp_marginals(const SearchTabs &t, int precision, int r, int c, int n_beam,
-                  const uint8_t *cfg, int N, const void *A_rc, const float *L, const int32_t *anc,
-                  const float *Rv, long rstride, const double *score, double *out, int add_score,
-                  int cl, int cr, hipStream_t s) {
-  bc_single("lp_marginals");
-  if (n_beam <= 0) return;
-  KTimer kt_("marginals", s, 2.0 * n_beam * t.d * cl * cr);
-  if (cl > 0 && cr > 0 && marg_lds_fits(cl, t.d, cr)) {
-    if (precision == SPG_FP32)
-      hipLaunchKernelGGL(k_marginals_lp_lds<float>, dim3(nblk(n_beam, kW)), dim3(256), 0, s, t, r,
-                         c, n_beam, cfg, N, (const float *)A_rc, L, anc, Rv, rstride, score, out,
-                         add_score, cl, cr);
-    else
-      hipLaunchKernelGGL(k_marginals_lp_lds<uint16_t>, dim3(nblk(n_beam, kW)), dim3(256), 0, s, t,
-                         r, c, n_beam, cfg, N, (const uint16_t *)A_rc, L, anc, Rv, rstride, score,
-                         out, add_score, cl, cr);
-    SPG_CHECK_LAUNCH();
-    return;
+void lp_env_from_u(const SearchTabs &t, int precision, int r, int c, int n_anc,
+                   const uint8_t *cfg, int N, const float *U, long ldu, float *Rout, long rstride,
+                   int cl, hipStream_t s) {
+  bc_single("lp_env_from_u");
+  if (n_anc <= 0) return;
+  if (t.d > 256 || cl > 128) {
+    set_error("lp_env_from_u: d or bond dimension too large");
+    throw Fail{SPG_ERR_UNSUPPORTED};
   }
-  if (precision == SPG_FP32)
-    hipLaunchKernelGGL(k_marginals_lp<float>, dim3(nblk(n_beam, kW)), dim3(256), 0, s, t, r, c,
-                       n_beam, cfg, N, (const float *)A_rc, L, anc, Rv, rstride, score, out,
-                       add_score);
-  else
-    hipLaunchKernelGGL(k_marginals_lp<uint16_t>, dim3(nblk(n_beam, kW)), dim3(256), 0, s, t, r,
-                       c, n_beam, cfg, N, (const uint16_t *)A_rc, L, anc, Rv, rstride, score, out,
-                       add_score);
+  KTimer kt_("right_env", s, 2.0 * n_anc * cl * t.d);
+  hipLaunchKernelGGL(k_env_from_u, dim3(nblk(n_anc, kW)), dim3(256), 0, s, t, r, c, n_anc, cfg,
+                     N, U, ldu, Rout, rstride, precision == SPG_BF16 ? 1 : 0, cl);
+  SPG_CHECK_LAUNCH();
+}
+
+void lp_marginals_u(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
+                    const float *U, long ldu, const float *L, const int32_t *anc,
+                    const double *score, double *out, int add_score, int cl, hipStream_t s) {
+  bc_single("lp_marginals_u");
+  if (n_beam <= 0) return;
+  if (t.d > 256) {
+    set_error("lp_marginals_u: d too large");
+    throw Fail{SPG_ERR_UNSUPPORTED};
+  }
+  KTimer kt_("marginals", s, 2.0 * n_beam * t.d * cl);
+  hipLaunchKernelGGL(k_marg_from_u, dim3(nblk(n_beam, kW)), dim3(256), 0, s, t, r, c, n_beam, cfg,
+                     N, U, ldu, L, anc, score, out, add_score, cl);
   SPG_CHECK_LAUNCH();
 }
 

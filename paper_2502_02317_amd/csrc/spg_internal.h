@@ -292,13 +292,19 @@ void to_float(long n, const double *src, float *dst, hipStream_t s);
 // precision: SPG_FP32 (A in FP32) or SPG_BF16 (A in BF16); vectors L, R FP32.
 void lp_convert(long n, const double *src, void *dst, int precision, hipStream_t s);
 void lp_set_e0(int n, int chi, float *p, long stride, hipStream_t s);
-void lp_right_env_col(const SearchTabs &t, int precision, int r, int c, int n_anc,
-                      const uint8_t *cfg, int N, const void *A_rc, const float *Rnext,
-                      float *Rout, long rstride, int cl, int cr, hipStream_t s);
-void lp_marginals(const SearchTabs &t, int precision, int r, int c, int n_beam,
-                  const uint8_t *cfg, int N, const void *A_rc, const float *L, const int32_t *anc,
-                  const float *Rv, long rstride, const double *score, double *out, int add_score,
-                  int cl, int cr, hipStream_t s);
+// U[a][al * d + s] = sum_b R^a[b] A_rc[al][s][b] for every ancestor (MFMA GEMM;
+// U rows of stride ldu >= cl * d).
+void lp_u_col(const SearchTabs &t, int precision, int n_anc, const void *A_rc,
+              const float *Rnext, long rstride, float *U, long ldu, int cl, int cr,
+              hipStream_t s);
+// R^a_c from U and the couplings to the fixed row (normalised per ancestor).
+void lp_env_from_u(const SearchTabs &t, int precision, int r, int c, int n_anc,
+                   const uint8_t *cfg, int N, const float *U, long ldu, float *Rout, long rstride,
+                   int cl, hipStream_t s);
+// Conditionals of every beam state from U of its ancestor and its L.
+void lp_marginals_u(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
+                    const float *U, long ldu, const float *L, const int32_t *anc,
+                    const double *score, double *out, int add_score, int cl, hipStream_t s);
 void lp_beam_update(const SearchTabs &t, int precision, int r, int c, int n_new,
                     const int32_t *sel, int N, const uint8_t *cfg, const double *energy,
                     const float *L, const int32_t *anc, const double *cand, const void *A_rc,
@@ -329,6 +335,7 @@ struct spg_env {
   // search workspace (grown on demand)
   spg::DevBuf cfg[2], score[2], energy[2], L[2], anc[2], Rv, cand, sel, keys, ids, ework,
       perm, nvalid, tmp, cfg32;
+  spg::DevBuf Ulp;               // reduced precision: U_c [cols][M][chi * d] float
   // guarded search with a proposal: right-environment scales, per-site
   // features, step workspace and counters
   spg::DevBuf Rsc, sf, rscr, gbins, ghist, gint, glkey, glid, gbound, gtau, goff, gcnt, gstats,
