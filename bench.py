@@ -442,8 +442,8 @@ def main():
         roof = {"bound": None, "achieved": None, "peak": None, "unit": None}
     elif dom in FLOP_CLASSES:
         achieved = work / (tms * 1e-3) / 1e12
-        # the QR kernels run on the FP64 vector ALU; the GEMM-shaped
-        # contractions are MFMA candidates (FP64 peak: the boundary MPS is FP64)
+        # the QR kernels run on the FP64 vector ALU, the GEMMs on the FP64
+        # matrix cores (the two share one peak on this chip)
         bound = "alu" if dom in ("qr_f64",) else "mfma"
         roof = {"bound": bound, "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s"}
     elif dom in BYTE_CLASSES:

@@ -27,13 +27,18 @@ __device__ double block_sum(double v, double *red) {
 // ---------------------------------------------------------------- GEMM
 // TILE x TILE output tile per 256-thread workgroup (TILE = 64 or 32), K staged
 // through LDS in steps of kGemmKs (all of a step's loads are in flight at
-// once: these products are short, so load latency rather than FMA throughput
-// sets their time); each thread owns a (TILE/16)^2 sub-tile (rows ty+16i,
-// cols tx+16j).  The tile is picked per launch by the tuning.
+// once: these products are short, so load latency rather than arithmetic
+// sets their time); the products run on the matrix cores
+// (v_mfma_f64_16x16x4f64).  Wavefront w owns the (TILE/2)^2 quadrant
+// (w / 2, w % 2) of the tile as (TILE/32)^2 blocks of 16 x 16; per block and
+// k step of 4, lane l supplies A[row l % 16][k + l / 16] and
+// B[k + l / 16][col l % 16], and holds D[l / 16 + 4 q][l % 16], q = 0..3.
+// The tile is picked per launch by the tuning.
+typedef double d4v __attribute__((ext_vector_type(4)));
 constexpr int kGemmKs = 32;
 template <int TILE>
 __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
-  constexpr int P = TILE / 16, KS = kGemmKs, NQ = KS * TILE / 256;
+  constexpr int KS = kGemmKs, NQ = KS * TILE / 256;
   const int nbb = g.nb1 * g.nb2;
   const int inst = blockIdx.z / nbb, bz = blockIdx.z % nbb;   // class-batched instance
   const int b1 = bz / g.nb2, b2 = bz % g.nb2;
@@ -43,15 +48,18 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
   double *C = (double *)((char *)g.C + io) + b1 * g.c_b1 + b2 * g.c_b2;
   __shared__ double As[KS][TILE + 1];
   __shared__ double Bs[KS][TILE + 1];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x;
   const int i0 = blockIdx.y * TILE, j0 = blockIdx.x * TILE;
   // split-K chunks: chunk b1 covers global k in [b1*K, min((b1+1)*K, kmax))
   const int Kend = (g.kmax > 0) ? min(g.K, g.kmax - b1 * g.K) : g.K;
-  double acc[P][P];
+  constexpr int NB = TILE / 32;                 // 16 x 16 blocks per quadrant side
+  d4v macc[NB][NB];
 #pragma unroll
-  for (int i = 0; i < P; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < P; ++j) acc[i][j] = 0.0;
+    for (int j = 0; j < NB; ++j) macc[i][j] = (d4v){0.0, 0.0, 0.0, 0.0};
+  const int lane = tid & 63, wq = tid >> 6;
+  const int qr0 = (wq >> 1) * (TILE / 2), qc0 = (wq & 1) * (TILE / 2);
   // consecutive threads take consecutive addresses of whichever index has
   // unit stride, so tile loads are contiguous for either operand layout
   const bool a_rows = (g.a_i == 1 && g.a_k != 1);      // A column-major: i fastest
@@ -90,42 +98,53 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
     __syncthreads();
     if (k0 + KS < Kend) fetch(k0 + KS);
     const int kn = min(KS, Kend - k0);
-#pragma unroll 8
-    for (int kk = 0; kk < kn; ++kk) {
-      double a[P], b[P];
+    // rows kn..KS-1 of the staged step are not this step's: read as zero
+    for (int kk = 0; kk < kn; kk += 4) {
+      const int k = kk + (lane >> 4);
+      const bool ok = k < kn;
+      const int kr = ok ? k : 0;
+      double a[NB], b[NB];
 #pragma unroll
-      for (int i = 0; i < P; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int i = 0; i < NB; ++i) {
+        const double x = As[kr][qr0 + 16 * i + (lane & 15)];
+        a[i] = ok ? x : 0.0;
+      }
 #pragma unroll
-      for (int j = 0; j < P; ++j) b[j] = Bs[kk][tx + 16 * j];
+      for (int j = 0; j < NB; ++j) {
+        const double x = Bs[kr][qc0 + 16 * j + (lane & 15)];
+        b[j] = ok ? x : 0.0;
+      }
 #pragma unroll
-      for (int i = 0; i < P; ++i)
+      for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < P; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < NB; ++j)
+          macc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], macc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
   const double *sw = g.sw ? (const double *)((const char *)g.sw + io) : nullptr;
   const double *sV = g.sV ? (const double *)((const char *)g.sV + io) : nullptr;
   const double fb = (g.smode == 2) ? sw[b1] * sV[b1 * g.sd + b2] : 1.0;
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const int gi = i0 + ty + 16 * i;
-    if (gi >= g.M) continue;
+  auto put = [&](int gi, int gj, double a) {
+    if (gi >= g.M || gj >= g.N) return;
     double f = fb;
     if (g.smode == 1) {
       const int x = gi % g.sd;
       f = sw[x] * sV[x * g.sd + b1];
     }
+    double *cp = C + gi * g.c_i + gj * g.c_j;
+    double v = g.alpha * a;
+    if (g.smode) v *= f;
+    *cp = (g.beta != 0.0) ? v + g.beta * (*cp) : v;
+  };
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int gj = j0 + tx + 16 * j;
-      if (gj >= g.N) continue;
-      double *cp = C + gi * g.c_i + gj * g.c_j;
-      double v = g.alpha * acc[i][j];
-      if (g.smode) v *= f;
-      *cp = (g.beta != 0.0) ? v + g.beta * (*cp) : v;
-    }
-  }
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        put(i0 + qr0 + 16 * i + (lane >> 4) + 4 * q, j0 + qc0 + 16 * j + (lane & 15),
+            macc[i][j][q]);
 }
 
 // Deterministic split-K epilogue: C = alpha * sum_s P[s] + beta * C (P: [S][M][N]).
