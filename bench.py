@@ -190,11 +190,30 @@ def batching_leg(spg, torch, stream):
     b.run(use_graph=False, stream=stream)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - a
+    # one more batched run with per-launch events: the FP64 kernel classes'
+    # rates when a launch covers every member of a shape class (one
+    # workgroup per member for the QR and the Jacobi SVD); work over the
+    # summed launch durations, on eight overlapping streams
+    spg.profile_reset()
+    spg.profile_enable(True)
+    b.run(use_graph=False, stream=stream)
+    torch.cuda.synchronize()
+    spg.profile_enable(False)
+    rates = {}
+    for k in ("qr_f64", "gemm_f64"):
+        cnt, ms, work = spg.profile_query(k)
+        if ms > 0.0:
+            ach = work / (ms * 1e-3) / 1e12
+            rates[k] = {"launches": cnt, "avg_launch_us": ms * 1e3 / max(cnt, 1),
+                        "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                        "frac": ach / PEAK["fp64"]}
+    spg.profile_reset()
     return {"workload": f"first {n} instances of the batched workload (L 6..12, chi 16/32, "
                         f"d 16, beta 2, M {BATCH_M})",
             "instances": n, "units": units, "evals": ev,
             "one_by_one_s": t_one, "batched_s": t_batch, "speedup": t_one / t_batch,
-            "evals_per_s_one_by_one": ev / t_one, "evals_per_s_batched": ev / t_batch}
+            "evals_per_s_one_by_one": ev / t_one, "evals_per_s_batched": ev / t_batch,
+            "kernel_rates_batched": rates}
 
 
 def transforms_leg(spg, torch, inst, wl, M, stream):

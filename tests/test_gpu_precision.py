@@ -132,3 +132,15 @@ def test_dlogp_kings8x8_d16_fp32():
     # cannot resolve them to 1e-3, so the dlogP target does not apply here
     if fine:
         assert w["fp32"] <= 1e-3, w
+
+
+@pytest.mark.parametrize("R,C,d,kings,chi,M", [(3, 3, 5, True, 7, 33), (2, 4, 17, True, 11, 50),
+                                               (2, 3, 70, True, 6, 40), (2, 2, 130, False, 5, 30)])
+def test_reduced_precision_ragged_shapes(R, C, d, kings, chi, M):
+    """The matrix-core product U = R A^T and the two gathers at shapes that
+    fill no tile evenly: ancestors, pairs chi_c * d and bond chi_{c+1} not
+    multiples of 16, and d above 64 (the gather's per-lane loop over s).
+    Every resolved entry within its running-error bound, FP32 and BF16."""
+    inst = random_potts(R, C, d, kings, seed=70 + d, beta=0.4)
+    ora, peps, envs = _envs(inst, chi)
+    _dlogp(inst, ora, envs, M, range(inst.n_sites))
