@@ -90,6 +90,26 @@ def evals_per_step(R, C, d, M):
     return tot
 
 
+def search_formula_flops(dims, R, C, d, M):
+    """Algorithmic flops of the search contractions by formula, with the
+    actual bond dimensions chi_c = dims[r][c]: 2 chi_c chi_{c+1} per resolved
+    child (conditionals), 2 chi_c chi_{c+1} d per row-start ancestor per
+    column c >= 1 (right environments), 2 chi_c chi_{c+1} per survivor that
+    carries its left vector on (c < cols - 1)."""
+    tot, B = 0.0, 1
+    for r in range(R):
+        n_anc = B
+        for c in range(1, C):
+            tot += 2.0 * dims[r][c] * dims[r][c + 1] * d * n_anc
+        for c in range(C):
+            cc = 2.0 * dims[r][c] * dims[r][c + 1]
+            tot += cc * B * d
+            B = min(M, B * d)
+            if c < C - 1:
+                tot += cc * B
+    return tot
+
+
 def cpu_baseline(inst, wl):
     """The oracle, as it stands, on one step of the same workload."""
     from threadpoolctl import threadpool_info, threadpool_limits
@@ -392,7 +412,8 @@ def main():
     else:
         _, prof = timed(args.precision, True)
         say("profiled pass done")
-    n_last = step(args.precision)[1]
+    env_last, n_last = step(args.precision)
+    dims_last = spg.env_info(env_last).bond_dims.reshape(R, C + 1)
     best_E = float(en[0]) if n_last > 0 else None     # None: the beam ended with no finite state
 
     # search-only and boundary-MPS-only split (untimed, same work)
@@ -496,6 +517,22 @@ def main():
                 "frac": ach / PEAK[args.precision], "launches_per_step": mc / args.steps,
                 "avg_launch_us": mt * 1e3 / max(mc, 1)}
 
+    # the metric's contraction TFLOP/s: formula flops over summed kernel time
+    # (profiled pass), for the search contractions and for the boundary MPS
+    search_cls = ("right_env", "marginals", "beam_update", "u_mfma")
+    bmps_cls = ("gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box")
+    s_ms = sum(prof[k][1] for k in search_cls if k in prof) / args.steps
+    b_ms = sum(prof[k][1] for k in bmps_cls if k in prof) / args.steps
+    s_fl = search_formula_flops(dims_last, R, C, d, M)
+    b_fl = (prof["gemm_f64"][2] + prof["qr_f64"][2]) / args.steps
+    contraction = {
+        "search": {"formula_flops": s_fl, "kernel_ms": s_ms,
+                   "tflops": s_fl / (s_ms * 1e-3) / 1e12 if s_ms > 0 else None,
+                   "precision": args.precision},
+        "boundary_mps": {"gemm_qr_flops": b_fl, "kernel_ms": b_ms,
+                         "tflops": b_fl / (b_ms * 1e-3) / 1e12 if b_ms > 0 else None,
+                         "precision": "fp64"}}
+
     dt = {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16"}[args.precision]
     out = {
         "metric": "conditional-marginal evals/s", "value": ev / (ms * 1e-3), "unit": "evals/s",
@@ -515,6 +552,7 @@ def main():
         "kernels": {k: {"launches": v[0], "ms": v[1], "work": v[2]} for k, v in prof.items()},
         "roofline": roof,
         "matrix_cores": mfma,
+        "contraction_tflops": contraction,
     }
     if not args.no_forms:
         out["forms"] = {"learned_proposal": proposal_leg(spg, torch, inst, wl, M, st, en, lp,
