@@ -209,6 +209,7 @@ static void row_factors(const spg_peps *pp, int r, int c, bool bottom, RowFactor
   const size_t dd = (size_t)d * d;
   f.w = pp->W_loc.as<double>() + ((size_t)r * C + c) * d;
   f.V = bottom ? pp->ones.as<double>() : pp->W_v.as<double>() + ((size_t)r * C + c) * dd;
+  f.ones = pp->ones.as<double>();
   if (c == 0) {
     f.Hl = pp->e0row.as<double>();
     f.Dl = pp->e0row.as<double>();

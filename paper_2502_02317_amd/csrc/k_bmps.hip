@@ -152,17 +152,6 @@ __global__ void k_Q2(int d, int chi, int nq, int pr, const double *Qr, const dou
   Q2[(((long)Q * d + x) * d + z) * chi + P] = acc;
 }
 
-// B[p][x][z][P] (compact) *= H1[x][z]
-__global__ void k_scale_H(int d, int pl, int pr, const double *H1, double *B, long ist) {
-  SPG_INST(H1);
-  SPG_INST(B);
-  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long tot = (long)pl * d * d * pr;
-  if (e >= tot) return;
-  const int z = (e / pr) % d, x = (e / ((long)pr * d)) % d;
-  B[e] *= H1[x * d + z];
-}
-
 // The whole padded site dst[chi][d][chi]: entries k < nk, P < pr from src,
 // zero elsewhere.
 __global__ void k_unpack_right(int d, int chi, int nk, int pr, const double *src, long sk,
@@ -372,12 +361,8 @@ void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, cons
   h.B = Q2; h.b_k = (long)d * d * chi; h.b_j = 1; h.b_b1 = (long)d * chi; h.b_b2 = chi;
   h.C = B; h.c_i = (long)d * d * pr; h.c_j = 1; h.c_b1 = (long)d * pr; h.c_b2 = pr;
   h.alpha = 1.0; h.beta = 0.0;
+  h.sw = f1.ones; h.sV = f1.Hl; h.sd = d; h.smode = 2;  // B[p][x][z][P] *= 1 * H1(x, z)
   gemm_f64(h, s);
-  const long totb = (long)pl * d * d * pr;
-  SPG_BC(f1.Hl);
-  SPG_BC(B);
-  hipLaunchKernelGGL(k_scale_H, dim3(nblk(totb, 256), g_bc.n), dim3(256), 0, s, d, pl, pr, f1.Hl, B, g_bc.ist);
-  SPG_CHECK_LAUNCH();
 }
 
 void unpack_right(int d, int chi, int nk, int pr, const double *src, long sk, long sj,

@@ -151,6 +151,7 @@ struct RowFactors {         // device d x d tables (row-major) / d vectors of on
   const double *w;          // w_c(x)
   const double *V;          // V_c[x][y]
   const double *Hl, *Dl, *Al;  // H_{c-1}[a][x], D_{c-1}[a][y], A_{c-1}[x][e]
+  const double *ones;          // d x d ones (an epilogue factor of 1 per row)
 };
 void init_guess(int d, int chi, int bl, int br, const double *psi, const RowFactors &f,
                 double *phi, hipStream_t s);
