@@ -187,3 +187,36 @@ def test_random_droplets_match_oracle(k):
         for (x, e), y, g in zip(want, cfg, de):
             np.testing.assert_array_equal(y, x)
             assert abs(g - e) < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("k", range(8))
+def test_random_reduced_precision_full_beam(k, prec):
+    """Whole reduced-precision searches (the matrix-core products at every
+    column of every row) at random shapes in the exact regime, with a beam of
+    every state, so nothing is pruned.  A state drops out only if one of its
+    conditionals rounds to zero (its running-error bound reaches 1), which
+    the most probable states cannot: with FP32 inputs the lowest-energy tenth
+    of the spectrum comes back complete and in order, with log-probabilities
+    within 1e-3 of -beta E - log Z; with BF16 inputs the ground state does.
+    Every returned state is distinct, in energy order and carries its Eq. (1)
+    energy."""
+    from oracle.exact import brute_force
+    rng = np.random.default_rng(9000 + k)
+    R, C, d = _small_shape(rng, 2048, min_sites=4)
+    kings = bool(rng.integers(0, 2))
+    inst = random_potts(R, C, d, kings, seed=9100 + k, beta=float(rng.uniform(0.2, 0.8)))
+    bf = brute_force(inst)
+    env, _ = spg.boundary_mps(spg.build_peps(inst), d ** (C // 2), precision=prec)
+    N = R * C
+    st, en, lp = _search(env, N, d ** N)
+    assert len({tuple(x) for x in st.tolist()}) == len(st)
+    np.testing.assert_allclose(en, potts_energy(inst, st), atol=1e-9)
+    assert np.all(np.diff(en) >= 0)
+    if prec == "fp32":
+        top = np.sort(bf["E"])[: max(1, d ** N // 10)]
+        assert len(st) >= len(top)
+        np.testing.assert_allclose(en[: len(top)], top, atol=1e-9)
+        np.testing.assert_allclose(lp[: len(top)], -inst.beta * top - bf["logZ"], atol=1e-3)
+    else:
+        assert len(st) >= 1 and abs(en[0] - bf["E_min"]) < 1e-9
