@@ -512,7 +512,7 @@ void spg_free_env(spg_env_t *env) {
   (void)hipDeviceSynchronize();
   for (DevBuf *b : {&env->A, &env->Alp, &env->lam, &env->cfg[0], &env->cfg[1], &env->score[0],
                     &env->score[1], &env->energy[0], &env->energy[1], &env->L[0], &env->L[1],
-                    &env->anc[0], &env->anc[1], &env->Rv, &env->Ulp, &env->cand, &env->sel,
+                    &env->anc[0], &env->anc[1], &env->Rv, &env->Ulp, &env->selws, &env->cand, &env->sel,
                     &env->keys,
                     &env->ids, &env->ework, &env->perm, &env->nvalid, &env->tmp, &env->cfg32})
     b->release();
@@ -679,6 +679,7 @@ static void each_search_buffer(spg_env *env, int M, F &&f) {
   // reduced-precision search: U_c of every column for the row's ancestors
   if (env->precision != SPG_FP64) f(env->Ulp, (size_t)C * M * chi * d * 4);
   f(env->cand, (size_t)M * d * 8);
+  f(env->selws, (size_t)1280 + 12 * (size_t)M + 256);
   f(env->sel, (size_t)M * 4);
   f(env->keys, (size_t)p2 * 8);
   f(env->ids, (size_t)p2 * 4);
@@ -962,7 +963,8 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
         if (prm->cut_off_prob > 0.0)
           apply_cutoff((int)(B * d), log_cut, env->cand.as<double>(), s);
         select_topm((int)(B * d), M, env->cand.as<double>(), env->sel.as<int32_t>(),
-                    env->keys.as<uint64_t>(), env->ids.as<int32_t>(), s);
+                    env->keys.as<uint64_t>(), env->ids.as<int32_t>(), s, nullptr, nullptr,
+                    nullptr, env->selws.p);
       }
       const int nx = cur ^ 1;
       if (lp)

@@ -534,6 +534,108 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
   }
 }
 
+// ---- top-M for more candidates than the one-workgroup select holds in
+// registers: the same selection (keys below the M-th key, then the least ids
+// among keys equal to it), with every radix pass a histogram over many
+// workgroups (integer atomics: the totals do not depend on their order) and a
+// one-wavefront step that picks the digit.  The survivors are then sorted by
+// k_select itself (n = M), so sel and sel_score are the ones k_select writes.
+struct SelState {
+  unsigned long long prefix, pmask, kthr;
+  int need, n_eq, count, all_eq;
+};
+
+__global__ void k_sel_init(SelState *st, unsigned *gh, int Me) {
+  gh[threadIdx.x] = 0u;                              // 256 threads
+  if (threadIdx.x == 0) {
+    st->prefix = 0ull;
+    st->pmask = 0ull;
+    st->kthr = 0ull;
+    st->need = Me;
+    st->n_eq = 0;
+    st->count = 0;
+    st->all_eq = 1;
+  }
+}
+
+// mode 0: digit of the key; mode 1: digit of the index among keys equal to kthr
+__global__ __launch_bounds__(256) void k_sel_hist(int n, const double *cand, int shift, int mode,
+                                                  const SelState *st, unsigned *gh) {
+  __shared__ unsigned h[256];
+  const int t = threadIdx.x;
+  if (mode && st->all_eq) return;                    // uniform: no id passes needed
+  h[t] = 0u;
+  __syncthreads();
+  const unsigned long long prefix = st->prefix, pmask = st->pmask, kthr = st->kthr;
+  for (int i = blockIdx.x * 256 + t; i < n; i += gridDim.x * 256) {
+    unsigned long long k = desc_key(cand[i]);
+    if (mode) k = (k == kthr) ? (unsigned long long)(unsigned)i : ~0ull;
+    if ((k & pmask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  if (h[t]) atomicAdd(&gh[t], h[t]);
+}
+
+// one wavefront: the digit holding the need-th smallest key, as radix_find;
+// clears the histogram for the next pass.  mode 2: the last key pass (then
+// kthr is known and the id passes are set up when they are needed).
+__global__ void k_sel_find(SelState *st, unsigned *gh, int shift, int mode) {
+  const int lane = threadIdx.x;                      // 64 threads
+  if (mode == 1 && st->all_eq) return;
+  unsigned h[4], own = 0u;
+  for (int j = 0; j < 4; ++j) { h[j] = gh[4 * lane + j]; own += h[j]; }
+  unsigned inc = own;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned v = __shfl_up(inc, o);
+    if (lane >= o) inc += v;
+  }
+  const unsigned excl = inc - own;
+  const int need = st->need;
+  const unsigned long long hit = __ballot(inc >= (unsigned)need);
+  const int first = hit ? (__ffsll((long long)hit) - 1) : 63;
+  for (int j = 0; j < 4; ++j) gh[4 * lane + j] = 0u;
+  if (lane == first) {
+    unsigned cum = excl;
+    int t = 4 * lane, j = 0;
+    for (; j < 3; ++j, ++t) {
+      if (cum + h[j] >= (unsigned)need) break;
+      cum += h[j];
+    }
+    const unsigned long long prefix = st->prefix | ((unsigned long long)t << shift);
+    const int left = need - (int)cum;
+    if (mode == 2) {
+      // the M-th key is known: keys equal to it are taken whole, or by least index
+      st->kthr = prefix;
+      st->n_eq = (int)h[j];
+      st->all_eq = (left >= (int)h[j]) ? 1 : 0;
+      st->need = left;
+      st->prefix = 0ull;
+      st->pmask = 0xFFFFFFFF00000000ull;          // indices fit in 32 bits
+    } else {
+      st->prefix = prefix;
+      st->pmask |= (255ull << shift);
+      st->need = left;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sel_compact(int n, const double *cand, SelState *st,
+                                                     double *cs, int32_t *is, int Me) {
+  const unsigned long long kthr = st->kthr, ithr = st->prefix;
+  const int all_eq = st->all_eq;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const unsigned long long k = desc_key(cand[i]);
+    const bool f = (k < kthr) || (k == kthr && (all_eq || (unsigned long long)(unsigned)i <= ithr));
+    if (f) {
+      const int pos = atomicAdd(&st->count, 1);
+      if (pos < Me) {
+        cs[pos] = cand[i];
+        is[pos] = i;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_beam_update(SearchTabs t, int r, int c, int n_new,
                                                      const int32_t *sel, int N,
                                                      const uint8_t *cfg, const double *energy,
@@ -962,8 +1064,40 @@ void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg
 
 void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *keys_work,
                  int32_t *ids_work, hipStream_t s, const int *n_dev, const int32_t *cid,
-                 double *sel_score) {
+                 double *sel_score, void *big_ws) {
   KTimer kt_("select_topm", s, (cid ? 12.0 : 8.0) * n_cand + 4.0 * (M < n_cand ? M : n_cand));
+  const int Me = (M < n_cand) ? M : n_cand;
+  if (big_ws && !n_dev && !cid && g_bc.n == 1 && n_cand > kSelRegKeys * 1024 && Me < n_cand &&
+      Me >= 1 && Me <= kSelLdsSort) {
+    // workspace: state (256 B), histogram (1 KiB), survivors' scores [Me] and indices [Me]
+    SelState *st = reinterpret_cast<SelState *>(big_ws);
+    unsigned *gh = reinterpret_cast<unsigned *>(static_cast<char *>(big_ws) + 256);
+    double *cs = reinterpret_cast<double *>(static_cast<char *>(big_ws) + 1280);
+    int32_t *is = reinterpret_cast<int32_t *>(cs + Me);
+    const unsigned G = (unsigned)std::min(((long)n_cand + 2047) / 2048, 1024L);
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, st, gh, Me);
+    SPG_CHECK_LAUNCH();
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      hipLaunchKernelGGL(k_sel_hist, dim3(G), dim3(256), 0, s, n_cand, cand, shift, 0, st, gh);
+      SPG_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(64), 0, s, st, gh, shift, shift == 0 ? 2 : 0);
+      SPG_CHECK_LAUNCH();
+    }
+    for (int shift = 24; shift >= 0; shift -= 8) {
+      hipLaunchKernelGGL(k_sel_hist, dim3(G), dim3(256), 0, s, n_cand, cand, shift, 1, st, gh);
+      SPG_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(64), 0, s, st, gh, shift, 1);
+      SPG_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(k_sel_compact, dim3(G), dim3(256), 0, s, n_cand, cand, st, cs, is, Me);
+    SPG_CHECK_LAUNCH();
+    // the Me survivors sorted by (key, index), as the one-workgroup select does
+    hipLaunchKernelGGL(k_select, dim3(1, 1), dim3(1024), 0, s, Me, (const int *)nullptr, Me,
+                       (const double *)cs, (const int32_t *)is, sel, sel_score, keys_work,
+                       ids_work, 0L);
+    SPG_CHECK_LAUNCH();
+    return;
+  }
   SPG_BC(n_dev);
   SPG_BC(cand);
   SPG_BC(cid);

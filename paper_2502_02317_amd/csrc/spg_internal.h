@@ -209,7 +209,11 @@ void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg
 // the selected scores in selection order.
 void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *keys_work,
                  int32_t *ids_work, hipStream_t s, const int *n_dev = nullptr,
-                 const int32_t *cid = nullptr, double *sel_score = nullptr);
+                 const int32_t *cid = nullptr, double *sel_score = nullptr,
+                 void *big_ws = nullptr);
+// big_ws (optional, 1280 + 12 M bytes): more than 16384 candidates of one
+// instance are selected by histogram passes over many workgroups instead
+// (same result).
 void beam_update(const SearchTabs &t, int r, int c, int n_new, const int32_t *sel, int N,
                  const uint8_t *cfg, const double *energy, const double *L, const int32_t *anc,
                  const double *cand, const double *A_rc, int update_L, uint8_t *cfg_o,
@@ -337,6 +341,7 @@ struct spg_env {
   spg::DevBuf cfg[2], score[2], energy[2], L[2], anc[2], Rv, cand, sel, keys, ids, ework,
       perm, nvalid, tmp, cfg32;
   spg::DevBuf Ulp;               // reduced precision: U_c [cols][M][chi * d] float
+  spg::DevBuf selws;             // multi-workgroup top-M workspace (1280 + 12 M bytes)
   // guarded search with a proposal: right-environment scales, per-site
   // features, step workspace and counters
   spg::DevBuf Rsc, sf, rscr, gbins, ghist, gint, glkey, glid, gbound, gtau, goff, gcnt, gstats,

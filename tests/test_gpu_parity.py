@@ -291,3 +291,33 @@ def test_full_gpu_pipeline_config1(seed):
     bf = brute_force(inst)
     assert abs(en[0] - bf["E_min"]) < 1e-9
     assert n == 64
+
+
+@pytest.mark.parametrize("M,cut,merge", [(2048, 0.0, False), (4096, 1e-3, False),
+                                         (2048, 0.0, True)])
+def test_search_more_candidates_than_the_register_select(M, cut, merge):
+    """Steps with up to 65536 candidates (beam 2048 or 4096, d = 16): top-M
+    runs as histogram passes over many workgroups.  Against the oracle's
+    search on the same boundary MPS: the same number of states, sorted scores
+    to 1e-8, at least 99% of the states shared (near-ties at the M-th score
+    may swap), energies equal to Eq. (1)."""
+    inst = random_potts(4, 4, 16, True, seed=77, beta=1.0)
+    chi = 8
+    ora = oracle_bmps(inst, chi)
+    T, dims = spg.pack_oracle_mps(ora["A"], chi, inst.d)
+    env = spg.env_import(spg.build_peps(inst), chi, dims, T, np.array(ora["lam"]))
+    N = inst.rows * inst.cols
+    st = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+    en = torch.zeros(M, dtype=torch.float64, device=DEV)
+    lp = torch.zeros(M, dtype=torch.float64, device=DEV)
+    n = spg.branch_and_bound(env, M, st, en, lp, cut_off_prob=cut, merge_branches=merge)
+    torch.cuda.synchronize()
+    st, en, lp = st.cpu().numpy()[:n], en.cpu().numpy()[:n], lp.cpu().numpy()[:n]
+    ref = beam_search(inst, ora["A"], M, cut_off_prob=cut, merge=merge)
+    fin = np.isfinite(ref["scores"])
+    assert n == ref["n_valid"]
+    np.testing.assert_allclose(np.sort(lp), np.sort(ref["scores"][fin]), atol=1e-8)
+    shared = {tuple(x) for x in st.tolist()} & {tuple(x) for x in ref["states"][fin].tolist()}
+    assert len(shared) >= 0.99 * n
+    from oracle.energy import potts_energy
+    np.testing.assert_allclose(en, potts_energy(inst, st), atol=1e-9)
