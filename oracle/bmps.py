@@ -9,7 +9,8 @@ mechanics to its references, so the steps below are the adopted reading):
 * Boundary functions.  E~_{rows} = 1 and E~_r(X) = F_r(X) sum_Y G_r(X, Y) E~_{r+1}(Y)
   (for r = rows-1 the couplings G are absent).  Then Z = exp(-beta*shift) sum_X E~_0(X).
 * Boundary MPS.  E~_r(X) ~ exp(lam_r) A_{r,0}[x_0] ... A_{r,cols-1}[x_{cols-1}], each
-  A_{r,c} a (chi_c x d x chi_{c+1}) tensor, right-canonical (A_{r,0} normalised).
+  A_{r,c} a (chi_c x d x chi_{c+1}) tensor; the centre (A_{r,0}, or A_{r,1} when
+  column 0 kept its natural basis) has unit norm.
 * One row step (the paper's "SVDTruncate" with "num_sweeps" and
   "graduate_truncation", read as two-site variational fitting):
     1. target T = W_r psi, with psi = the normalised previous boundary MPS and W_r
@@ -21,21 +22,32 @@ mechanics to its references, so the steps below are the adopted reading):
     3. ``num_sweeps`` sweeps; each is a left-to-right then a right-to-left pass of
        two-site updates.  An update at columns (c, c+1) forms the exact projection of
        T onto the orthonormal left/right environment bases,
-       B = <env_L| T |env_R>, and splits it with the truncated SVD protocol of
-       ``linalg`` at rank min(chi, rows(B), cols(B));
+       B = <env_L| T |env_R>, and splits it by the truncated SVD of ``linalg``
+       (at most chi kept directions; a side with at most chi rows or columns
+       keeps its natural basis, so cuts that truncate nothing rotate nothing);
+       the last update of a sweep, at columns (0, 1), keeps the natural basis
+       on column 0 whenever that side has at most chi rows;
     4. normalise: lam_r = lam_{r+1} + log of the norm of the final centre.
 
+Where no cut truncates (narrow strips at the exact rank) every tensor is then
+a product of non-negative factors and the row functions keep full relative
+accuracy; rotations of non-negative blocks into signed factors are where FP64
+accuracy is lost on low-temperature instances, because the next row's couplings
+select entries far below the largest.
+
 Parity status: the exact regime (chi >= every exact Schmidt rank) is pinned
-against brute force and the exact row transfer; the truncated regime is pinned
-only by invariants (normalisation, monotone error in chi) - "parity unpinned"
-beyond those, as any truncated contraction is defined by its own protocol.
+against brute force and the exact row transfer, including king's strips at the
+workloads' d and beta (tests/test_oracle_strips.py); the truncated regime is
+pinned by invariants (normalisation, error against the exact row transfer
+falling with chi) - "parity unpinned" beyond those, as any truncated
+contraction is defined by its own protocol.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from .energy import Weights
-from .linalg import tsvd_left, tsvd_right, drop_null
+from .linalg import svd_truncate_left, svd_truncate_right
 
 
 def row_weights(W: Weights, r: int):
@@ -110,22 +122,22 @@ def _norm(T):
 
 
 def right_canonicalize(phi):
-    """LQ sweep from the right: phi_c (c >= 1) become right isometries (partial
-    ones where a direction sits at the rounding floor, see linalg.drop_null)."""
+    """LQ sweep from the right: phi_c (c >= 1) become right isometries."""
     phi = [t.copy() for t in phi]
     for c in range(len(phi) - 1, 0, -1):
         bl, d, br = phi[c].shape
         Q, Rr = np.linalg.qr(phi[c].reshape(bl, d * br).T, mode="reduced")
-        Q, Rr = drop_null(Q, Rr)           # directions of M^T = Q R weigh |row of R|
         k = Q.shape[1]
         phi[c] = Q.T.reshape(k, d, br)
         phi[c - 1] = np.einsum("pxq,kq->pxk", phi[c - 1], Rr)
     return phi
 
 
-def row_step(psi, fac, chi, num_sweeps, p, q):
-    """One boundary-MPS row update: returns (phi, log_scale) with phi
-    right-canonical, phi_0 normalised, and T ~ exp(log_scale) phi."""
+def row_step(psi, fac, chi, num_sweeps):
+    """One boundary-MPS row update: returns (phi, log_scale) with T ~
+    exp(log_scale) phi, the centre tensor normalised (phi_0, or phi_1 when
+    the last update kept the natural basis at column 0) and the tensors to
+    its right right-canonical."""
     C = len(psi)
     w, V, Hl, Dl, Al = fac
     f = [(w[c], V[c], Hl[c], Dl[c], Al[c]) for c in range(C)]
@@ -149,47 +161,52 @@ def row_step(psi, fac, chi, num_sweeps, p, q):
 
     def block(c):
         B = two_site_block(EL[c][0], ER[c + 2][0], psi[c], psi[c + 1], f[c], f[c + 1])
-        return B, EL[c][1] + ER[c + 2][1]
+        pl, _, _, pr = B.shape
+        return B.reshape(pl * d, d * pr), pl, pr, EL[c][1] + ER[c + 2][1]
 
     lam = 0.0
+    centre = 0
     for _ in range(num_sweeps):
         for c in range(C - 1, 1, -1):
             build_ER(c)
         # left-to-right pass
         for c in range(C - 1):
-            B, s = block(c)
-            pl, _, _, pr = B.shape
-            Bm = B.reshape(pl * d, d * pr)
-            k = min(chi, Bm.shape[0], Bm.shape[1])
+            Bm, pl, pr, s = block(c)
             if c < C - 2:
-                U, Rm = tsvd_left(Bm, k, p, q)
+                U, Rm = svd_truncate_left(Bm, chi)
                 phi[c] = U.reshape(pl, d, -1)
                 phi[c + 1] = Rm.reshape(-1, d, pr)
                 build_EL(c)
             else:
-                Lm, Vt = tsvd_right(Bm, k, p, q)
+                Lm, Vt = svd_truncate_right(Bm, chi)
                 phi[c] = Lm.reshape(pl, d, -1)
                 phi[c + 1] = Vt.reshape(-1, d, pr)
                 lam = s
+                centre = 0
                 if C > 2:
                     build_ER(c + 1)
         # right-to-left pass
         for c in range(C - 3, -1, -1):
-            B, s = block(c)
-            pl, _, _, pr = B.shape
-            Bm = B.reshape(pl * d, d * pr)
-            k = min(chi, Bm.shape[0], Bm.shape[1])
-            Lm, Vt = tsvd_right(Bm, k, p, q)
-            phi[c] = Lm.reshape(pl, d, -1)
-            phi[c + 1] = Vt.reshape(-1, d, pr)
+            Bm, pl, pr, s = block(c)
+            if c == 0 and Bm.shape[0] <= chi:
+                # last update of the sweep with nothing to truncate on the left:
+                # natural basis there, the block itself becomes the centre
+                phi[0] = np.eye(Bm.shape[0]).reshape(pl, d, -1)
+                phi[1] = Bm.reshape(-1, d, pr)
+                centre = 1
+            else:
+                Lm, Vt = svd_truncate_right(Bm, chi)
+                phi[c] = Lm.reshape(pl, d, -1)
+                phi[c + 1] = Vt.reshape(-1, d, pr)
+                centre = 0
             lam = s
             if c > 0:
                 build_ER(c + 1)
-    phi[0], s0 = _norm(phi[0])
+    phi[centre], s0 = _norm(phi[centre])
     return phi, lam + s0
 
 
-def boundary_mps(inst, chi: int, num_sweeps: int = 1, p: int = 16, q: int = 1):
+def boundary_mps(inst, chi: int, num_sweeps: int = 1):
     """All boundary MPSs, bottom row first.  Returns dict with
     'A' [rows][cols] tensors, 'lam' [rows] log-scales and 'logZ'."""
     if inst.cols < 2:
@@ -203,7 +220,7 @@ def boundary_mps(inst, chi: int, num_sweeps: int = 1, p: int = 16, q: int = 1):
     psi = [e0.copy() for _ in range(C)]          # E~_rows = 1 through y = 0 (couplings are ones)
     prev = 0.0
     for r in range(R - 1, -1, -1):
-        phi, s = row_step(psi, row_weights(W, r), chi, num_sweeps, p, q)
+        phi, s = row_step(psi, row_weights(W, r), chi, num_sweeps)
         A[r] = phi
         lam[r] = prev + s
         prev = lam[r]

@@ -111,8 +111,9 @@ def guided_beam_search(inst, A, M, params, H, kappa=2.0, cut_off_prob=0.0, stats
             ev = cand[have]
             tau = np.sort(ev)[::-1][M - 1] if ev.size >= M else -np.inf
             fb = mark | (~E.all(axis=1) & (bound >= tau - MARGIN))
+            dE = delta_energy(inst, cfg, r, c)
             for b in np.nonzero(fb)[0]:
-                cand[b] = score[b] + log_conditionals(q[b: b + 1])[0]
+                cand[b] = score[b] + log_conditionals(q[b: b + 1], dE[b: b + 1], inst.beta)[0]
                 have[b] = True
                 n_exact += d
                 n_fb += 1

@@ -12,7 +12,8 @@ configurations.  Adopted reading:
   p(s | b) = q(b, s) / sum_s' q(b, s'), where g^b_c(s) are the couplings of s to the
   fixed row r-1, R^a_{c+1} the right environment of the row-start ancestor a
   (R^a_cols = 1, R^a_c = sum_s g^a_c(s) A_{r,c}[:, s, :] R^a_{c+1}); negative q
-  (truncation error) counts as zero probability;
+  (truncation error) counts as zero probability, and a parent with no
+  positive q takes softmax_s(-beta dE(b, s)) instead (``log_conditionals``);
 * keep the M best children by (score desc, parent position asc, s asc);
   with ``cut_off_prob`` > 0, children below cut_off_prob times the best child
   of the step get score -inf (they sort last and count as discarded);
@@ -100,12 +101,24 @@ def marginals(A_rc, g_c, L, R_next):
     return g_c * np.einsum("ba,asz,bz->bs", L, A_rc, R_next)
 
 
-def log_conditionals(q: np.ndarray) -> np.ndarray:
-    q = np.where(q > 0, q, 0.0)
-    tot = q.sum(axis=1, keepdims=True)
+def log_conditionals(q: np.ndarray, dE: np.ndarray, beta: float) -> np.ndarray:
+    """log p(s | b) = log q(b, s) - log sum_s' max(q(b, s'), 0).
+
+    A weight q <= 0 (truncation or rounding) counts as probability 0.  A parent
+    none of whose children has a positive weight has no conditional from the
+    contraction; it takes the conditional of the fixed sites' Boltzmann weight
+    alone, softmax_s(-beta dE(b, s)) (the unexplored sites left out), so the
+    search never runs out of children."""
+    qp = np.where(q > 0, q, 0.0)
+    tot = qp.sum(axis=1, keepdims=True)
     with np.errstate(divide="ignore", invalid="ignore"):
-        lp = np.log(q) - np.log(tot)
-    return np.where(np.isfinite(lp), lp, -np.inf)
+        lp = np.log(qp) - np.log(tot)
+    lp = np.where(np.isfinite(lp), lp, -np.inf)
+    dead = ~(tot[:, 0] > 0)
+    if dead.any():
+        x = -beta * (dE[dead] - dE[dead].min(axis=1, keepdims=True))
+        lp[dead] = x - np.log(np.exp(x).sum(axis=1, keepdims=True))
+    return lp
 
 
 def right_envs(A_row, g):
@@ -207,9 +220,9 @@ def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None, merge=Fa
         L = np.ones((cfg.shape[0], 1))
         for c in range(C):
             q = marginals(A[r][c], g_anc[anc, c], L, R[c + 1][anc])
-            lp = log_conditionals(q)
-            cand = score[:, None] + lp
             dE = delta_energy(inst, cfg, r, c)
+            lp = log_conditionals(q, dE, inst.beta)
+            cand = score[:, None] + lp
             runners = {}
             if merge:
                 k = r * C + c
@@ -269,7 +282,7 @@ def teacher_forced_logp(inst, A, r: int, c: int, cfg: np.ndarray) -> np.ndarray:
         m = np.abs(Lb).max(axis=1, keepdims=True)
         L = Lb / np.where(m > 0, m, 1.0)
     q = marginals(A[r][c], g[:, c], L, R[c + 1])
-    return log_conditionals(q)
+    return log_conditionals(q, delta_energy(inst, cfg, r, c), inst.beta)
 
 
 def teacher_forced_condition(inst, A, r: int, c: int, cfg: np.ndarray):

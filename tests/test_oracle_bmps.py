@@ -6,16 +6,23 @@ from oracle.exact import row_transfer
 from oracle.bmps import boundary_mps, mps_full
 
 
-def test_right_canonical_and_normalised():
+def _centre(row):
+    """Index of the centre: the tensor that is not an isometry towards the right
+    (phi_0, or phi_1 when column 0 kept its natural basis)."""
+    return 1 if (row[0].shape[0] == 1 and row[0].shape[2] == row[0].shape[1]
+                 and np.array_equal(row[0].reshape(row[0].shape[1], -1),
+                                    np.eye(row[0].shape[1]))) else 0
+
+
+def test_canonical_form_and_normalised():
     inst = random_potts(4, 5, 3, True, seed=5, beta=0.6)
     mp = boundary_mps(inst, chi=4)
     for row in mp["A"]:
-        assert abs(np.linalg.norm(row[0]) - 1) < 1e-12
-        for A in row[1:]:
+        c0 = _centre(row)
+        assert abs(np.linalg.norm(row[c0]) - 1) < 1e-12
+        for A in row[c0 + 1:]:
             G = np.einsum("axb,cxb->ac", A, A)
-            # a right isometry, or a partial one where null directions were dropped
-            np.testing.assert_allclose(G, np.diag(np.round(np.diag(G))), atol=1e-12)
-            assert np.round(np.diag(G)).sum() >= 1
+            np.testing.assert_allclose(G, np.eye(G.shape[0]), atol=1e-12)
         assert max(A.shape[0] for A in row) <= 4
 
 
@@ -40,36 +47,16 @@ def test_truncation_error_falls_with_chi():
     assert errs[0] > 1e-6
 
 
-def test_result_independent_of_orthonormal_completion(monkeypatch):
-    """Blocks of numerical rank below chi occur; with the null-direction rule
-    the contraction does not depend on how an implementation completes an
-    orthonormal basis (here: Householder QR versus Gram-Schmidt with a
-    different completion order)."""
-    import oracle.linalg as L
-    si = spin_instance(4, 5, 2, True, seed=6, h=("normal", 1.0), j_in=("normal", 1.0),
-                       j_out=("normal", 0.4))
-    inst = potts_from_spins(si, beta=0.5)
-    ref = boundary_mps(inst, 5)
-
-    def orth_gs(Y):
-        m, n = Y.shape
-        Q = np.zeros((m, n))
-        spare = list(range(m))[::-1]
-        for j in range(n):
-            v = Y[:, j].copy()
-            for _ in range(2):
-                v -= Q[:, :j] @ (Q[:, :j].T @ v)
-            while np.linalg.norm(v) < 1e-12 * max(1.0, np.linalg.norm(Y)):
-                v = np.zeros(m)
-                v[spare.pop(0)] = 1.0
-                for _ in range(2):
-                    v -= Q[:, :j] @ (Q[:, :j].T @ v)
-            Q[:, j] = v / np.linalg.norm(v)
-        return Q
-
-    monkeypatch.setattr(L, "orth", orth_gs)
-    alt = boundary_mps(inst, 5)
-    assert abs(alt["logZ"] - ref["logZ"]) < 1e-10
-    for r in range(inst.rows):
-        a, b = mps_full(alt["A"][r]), mps_full(ref["A"][r])
-        np.testing.assert_allclose(a, b, atol=1e-9 * np.abs(b).max())
+def test_truncated_low_temperature_strip():
+    """Truncation active (a 4-wide strip at the 8x8 d=16 workload's
+    distributions, chi = 32 < 256 states on each side of the middle cut): log Z
+    against the exact row transfer falls with chi (measured 1.0e-8, 2.5e-10 and
+    2.1e-11 relative at chi = 16, 32, 64: the truncation's error plus the
+    rounding of the rotated cut)."""
+    si = spin_instance(8, 4, 4, True, seed=0, h=("normal", 1.0), j_in=("normal", 1.0),
+                       j_out=("pm1", 1.0))
+    inst = potts_from_spins(si, beta=2.0)
+    _, lz = row_transfer(inst)
+    e16, e32, e64 = (abs(boundary_mps(inst, chi=chi)["logZ"] - lz) for chi in (16, 32, 64))
+    assert e16 > e32 > e64
+    assert e32 <= 1e-9 * abs(lz)

@@ -1,8 +1,8 @@
-"""Pins of the oracle's generator and truncated-SVD protocol (CPU only)."""
+"""Pins of the oracle's generator and truncated SVD (CPU only)."""
 import numpy as np
 import pytest
 
-from oracle.linalg import splitmix64, sketch, tsvd_left, tsvd_right
+from oracle.linalg import splitmix64, svd, svd_truncate_left, svd_truncate_right
 
 
 def test_splitmix64_reference_outputs():
@@ -11,39 +11,64 @@ def test_splitmix64_reference_outputs():
     assert out == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
 
 
-def test_sketch_range():
-    S = sketch(64, 16)
-    assert S.shape == (64, 16) and S.min() >= -1 and S.max() < 1
-    assert abs(S.mean()) < 0.1
+@pytest.mark.parametrize("m,n", [(40, 30), (30, 40), (17, 17), (64, 5)])
+def test_svd_matches_dense_lapack(m, n):
+    """On a well-conditioned matrix the Jacobi SVD and numpy's bidiagonal SVD
+    agree: same singular values, same factorisation, orthonormal factors."""
+    rng = np.random.default_rng(m * 100 + n)
+    B = rng.normal(size=(m, n))
+    U, s, Vt = svd(B)
+    k = min(m, n)
+    assert U.shape == (m, k) and s.shape == (k,) and Vt.shape == (k, n)
+    np.testing.assert_allclose(s, np.linalg.svd(B, compute_uv=False), rtol=1e-13)
+    assert np.all(np.diff(s) <= 0)
+    np.testing.assert_allclose((U * s) @ Vt, B, atol=1e-13 * np.abs(B).max())
+    np.testing.assert_allclose(U.T @ U, np.eye(k), atol=1e-13)
+    np.testing.assert_allclose(Vt @ Vt.T, np.eye(k), atol=1e-13)
 
 
-@pytest.mark.parametrize("m,n,r,k", [(40, 30, 5, 8), (64, 200, 12, 12), (100, 20, 20, 16)])
-def test_tsvd_exact_when_rank_fits(m, n, r, k):
-    rng = np.random.default_rng(m + n)
-    B = rng.normal(size=(m, r)) @ rng.normal(size=(r, n))
-    U, Rm = tsvd_left(B, k, 16, 1)
-    # an isometry on the kept directions; directions beyond rank(B) carry no
-    # weight and are zeroed (the null-direction rule)
-    G = U.T @ U
-    np.testing.assert_allclose(G, np.diag(np.round(np.diag(G))), atol=1e-12)
-    assert int(round(np.trace(G))) == min(r, k, U.shape[1])
-    if r <= k:
-        np.testing.assert_allclose(U @ Rm, B, atol=1e-10 * np.abs(B).max())
-    s_ref = np.linalg.svd(B, compute_uv=False)[: U.shape[1]]
-    s = np.linalg.svd(Rm, compute_uv=False)
-    np.testing.assert_allclose(s[: min(r, k)], s_ref[: min(r, k)], rtol=1e-9)
+def test_svd_graded_relative_accuracy():
+    """B = Q diag(D) with Q orthogonal has singular values D exactly, here
+    spanning 90 orders of magnitude: the Jacobi SVD returns every one of them
+    to a few ulps (a bidiagonal SVD only resolves them to ~1e-16 max(D))."""
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.normal(size=(40, 30)))
+    D = 10.0 ** (-3.0 * np.arange(30))
+    U, s, Vt = svd(Q * D)
+    np.testing.assert_allclose(s, D, rtol=1e-13)
 
 
-def test_tsvd_near_optimal_for_decaying_spectrum():
-    rng = np.random.default_rng(1)
-    m, n, k = 120, 90, 10
+@pytest.mark.parametrize("chi", [3, 8])
+def test_truncation_is_eckart_young_optimal(chi):
+    """The rank-chi split reaches the optimal error sqrt(sum of the discarded
+    sigma^2) and its factors are an isometry and the projection."""
+    rng = np.random.default_rng(chi)
+    m, n = 30, 20
     Uo, _ = np.linalg.qr(rng.normal(size=(m, n)))
     Vo, _ = np.linalg.qr(rng.normal(size=(n, n)))
-    sv = 0.5 ** np.arange(n)
+    sv = 0.6 ** np.arange(n)
     B = (Uo * sv) @ Vo.T
-    U, Rm = tsvd_left(B, k, 16, 1)
-    err = np.linalg.norm(B - U @ Rm, 2)
-    assert err <= 1.01 * sv[k]
-    Lm, V = tsvd_right(B, k, 16, 1)
-    np.testing.assert_allclose(V @ V.T, np.eye(k), atol=1e-12)
-    assert np.linalg.norm(B - Lm @ V, 2) <= 1.01 * sv[k]
+    U, Rm = svd_truncate_left(B, chi)
+    assert U.shape == (m, chi)
+    np.testing.assert_allclose(U.T @ U, np.eye(chi), atol=1e-13)
+    np.testing.assert_allclose(Rm, U.T @ B, atol=1e-13)
+    opt = np.sqrt((sv[chi:] ** 2).sum())
+    assert abs(np.linalg.norm(B - U @ Rm) - opt) <= 1e-12
+    Lm, V = svd_truncate_right(B, chi)
+    np.testing.assert_allclose(V @ V.T, np.eye(chi), atol=1e-13)
+    assert abs(np.linalg.norm(B - Lm @ V) - opt) <= 1e-12
+
+
+def test_natural_basis_when_nothing_is_truncated():
+    """A side with at most chi rows (left split) or columns (right split) is
+    not rotated: the identity and the block itself, exactly."""
+    rng = np.random.default_rng(5)
+    B = rng.random((6, 50))
+    U, Rm = svd_truncate_left(B, 6)
+    assert np.array_equal(U, np.eye(6)) and np.array_equal(Rm, B)
+    Lm, V = svd_truncate_right(B.T, 8)
+    assert np.array_equal(V, np.eye(6)) and np.array_equal(Lm, B.T)
+    # a tall block with few columns still needs a rotation on the left
+    U, Rm = svd_truncate_left(B.T, 8)
+    assert U.shape == (50, 6)
+    np.testing.assert_allclose(U @ Rm, B.T, atol=1e-13)
