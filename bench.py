@@ -110,8 +110,38 @@ def search_formula_flops(dims, R, C, d, M):
     return tot
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def row_sums(rows):
+    """sum_X of each row's boundary function (normalised MPS, without its
+    log-scale): the exact functions are positive, so a non-positive sum marks a
+    row whose approximation has lost its mass."""
+    import numpy as np
+    out = []
+    for row in rows:
+        v = np.ones(1)
+        for A in row:
+            v = v @ A.sum(axis=1)
+        out.append(float(v[0]))
+    return out
+
+
+def finite_or_none(x):
+    import math
+    return x if (x is not None and math.isfinite(x)) else None
+
+
 def cpu_baseline(inst, wl):
-    """The oracle, as it stands, on one step of the same workload."""
+    """The oracle, as it stands, on one step of the same workload; its own
+    result (log Z, best energy) is returned beside its time."""
     from threadpoolctl import threadpool_info, threadpool_limits
     from oracle.bmps import boundary_mps
     from oracle.search import beam_search
@@ -120,16 +150,22 @@ def cpu_baseline(inst, wl):
         info = threadpool_info()
         used = max([i.get("num_threads", 1) for i in info] or [1])
         t0 = time.perf_counter()
-        mp = boundary_mps(inst, wl["chi"], num_sweeps=wl["num_sweeps"], p=wl["oversample"],
-                          q=wl["power_iters"])
+        mp = boundary_mps(inst, wl["chi"], num_sweeps=wl["num_sweeps"])
         t1 = time.perf_counter()
-        beam_search(inst, mp["A"], wl["max_states"])
+        res = beam_search(inst, mp["A"], wl["max_states"])
         t2 = time.perf_counter()
     ev = evals_per_step(inst.rows, inst.cols, inst.d, wl["max_states"])
+    sums = row_sums(mp["A"])
     return {"value": ev / (t2 - t0), "unit": "evals/s", "cores": used, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"one full step of the same instance (boundary MPS {t1 - t0:.1f} s + "
                       f"search {t2 - t1:.1f} s)",
-            "bmps_s": t1 - t0, "search_s": t2 - t1}
+            "bmps_s": t1 - t0, "search_s": t2 - t1,
+            "oracle_logZ": finite_or_none(mp["logZ"]),
+            "oracle_rows_with_nonpositive_sum": [r for r, v in enumerate(sums) if not v > 0],
+            "oracle_best_energy": float(res["energies"][0]) if res["n_valid"] > 0 else None,
+            "oracle_n_states": res["n_valid"],
+            "_oracle_A": mp["A"]}
 
 
 def proposal_leg(spg, torch, inst, wl, M, st, en, lp, stream):
@@ -562,8 +598,45 @@ def main():
                                                                   stream),
                              "merge_branches": merge_leg(spg, torch, inst, wl, M, st, en, lp,
                                                          stream)}
+    # validity of the contraction and of the search on this workload: the
+    # GPU's log Z, the sign of every row function's sum, and (with the CPU
+    # leg) the oracle's own result beside the GPU's, plus the GPU search run
+    # on the oracle's boundary MPS (search parity at full size)
+    say("validity")
+    peps_v = spg.build_peps(inst, stream)
+    try:
+        env_v, lz_gpu = spg.boundary_mps(peps_v, wl["chi"], num_sweeps=wl["num_sweeps"],
+                                         precision="fp64", oversample=wl["oversample"],
+                                         power_iters=wl["power_iters"], stream=stream)
+    except spg.SpgError:
+        lz_gpu = None                     # the row-0 function's sum is not positive
+        env_v, _ = spg.boundary_mps(peps_v, wl["chi"], num_sweeps=wl["num_sweeps"],
+                                    precision="fp64", oversample=wl["oversample"],
+                                    power_iters=wl["power_iters"], stream=stream,
+                                    want_logZ=False)
+    Tv, _ = spg.env_export(env_v)
+    sums_gpu = row_sums(spg.unpack_mps(Tv, spg.env_info(env_v).bond_dims))
+    n_v = spg.branch_and_bound(env_v, M, st, en, lp, stream=stream)
+    validity = {"gpu_logZ": finite_or_none(lz_gpu),
+                "gpu_rows_with_nonpositive_sum": [r for r, v in enumerate(sums_gpu) if not v > 0],
+                "gpu_n_states": n_v,
+                "gpu_best_energy": float(en[0]) if n_v > 0 else None}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(inst, wl)
+        say("cpu baseline")
+        cb = cpu_baseline(inst, wl)
+        A_ora = cb.pop("_oracle_A")
+        out["cpu_baseline"] = cb
+        T_o, dims_o = spg.pack_oracle_mps(A_ora, wl["chi"], d)
+        env_o = spg.env_import(spg.build_peps(inst, stream), wl["chi"], dims_o, T_o,
+                               np.zeros(R))
+        n_o = spg.branch_and_bound(env_o, M, st, en, lp, stream=stream)
+        validity.update({
+            "oracle_logZ": cb["oracle_logZ"],
+            "oracle_rows_with_nonpositive_sum": cb["oracle_rows_with_nonpositive_sum"],
+            "oracle_best_energy": cb["oracle_best_energy"],
+            "gpu_search_on_oracle_bmps_best_energy": float(en[0]) if n_o > 0 else None,
+            "gpu_search_on_oracle_bmps_n_states": n_o})
+    out["validity"] = validity
     print(json.dumps(out), flush=True)
 
 

@@ -256,6 +256,21 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
     const bool bottom = (r == R - 1);
     const double *psi = bottom ? w.psi0.as<double>() : A + (size_t)(r + 1) * C * site;
     double *phi = A + (size_t)r * C * site;
+    if (bottom && chi >= d) {
+      // the bottom row is a chain of nearest-neighbour factors: written exactly
+      // at bond d (nothing to fit; a fit would keep chi > d directions at its
+      // inner cuts, those beyond the exact rank d weightless and completed
+      // differently by every implementation); lam = sum of the tensors' log-norms
+      bottom_row(C, d, chi, pp->W_loc.as<double>() + (size_t)r * C * d,
+                 pp->W_h.as<double>() + (size_t)r * (C - 1) * d * d, phi, s);
+      for (int c = 0; c < C; ++c) {
+        const int bl = (c == 0) ? 1 : d, br = (c == C - 1) ? 1 : d;
+        normalize_box(phi + c * site, bl, d, br, 1, (long)d * chi, chi, 1, 1, logs, sLam + r,
+                      c == 0 ? -1 : sLam + r, w.nscr.as<double>(), s);
+      }
+      for (int c = 0; c <= C; ++c) env->dims[r * (C + 1) + c] = (c == 0 || c == C) ? 1 : d;
+      continue;
+    }
     if (bottom) std::fill(pdims.begin(), pdims.end(), 1);
     else for (int c = 0; c <= C; ++c) pdims[c] = env->dims[(r + 1) * (C + 1) + c];
     std::vector<RowFactors> f(C);
@@ -271,8 +286,6 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
       // QR of Mc^T (d*br x bl): Q -> new right isometry, R folded into phi_{c-1}
       qr_f64(d * br, bl, Mc, 1, (long)d * br, w.Qc.as<double>(), 1, (long)d * br,
              w.Rc.as<double>(), w.qrwork.as<double>(), s);                 // Q column-major
-      // direction i of M^T = Q R weighs |row i of R|
-      drop_null(bl, bl, w.Rc.as<double>(), bl, 1, w.Qc.as<double>(), d * br, (long)d * br, 1, s);
       unpack_right(d, chi, bl, br, w.Qc.as<double>(), (long)d * br, 1, phi + c * site, s);
       lq_fold(d, chi, bl, bl, w.Rc.as<double>(), phi + (c - 1) * site, w.tmp.as<double>(), s);
     }
@@ -291,8 +304,24 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
       normalize_box(w.ELc(c + 1), fdims[c + 1], d, d, pdims[c + 1], (long)d * d * chi,
                     (long)d * chi, chi, 1, logs, sEL + c + 1, sEL + c, w.nscr.as<double>(), s);
     };
-    // two-site update at (c, c+1); right = true: centre moves left (phi_c = U S, phi_{c+1} = V^T)
-    auto update = [&](int c, bool right) {
+    // two-site update at (c, c+1); right = true: centre moves left (phi_c = U S,
+    // phi_{c+1} = V^T).  A side with at most chi rows (left split) or columns
+    // (right split) needs no truncation and keeps its natural basis (no rotation
+    // of the non-negative block); natural_left: the last update of a sweep,
+    // which keeps the natural basis on column 0 whenever it has at most chi
+    // rows, phi_1 = B becoming the centre.  Returns true when phi_{c+1} is the
+    // centre.
+    auto copy_strided = [&](int M, int N, const double *src, long si, double *dst, long di) {
+      GemmDesc g{};                              // dst = src I: exact copy by the GEMM
+      g.nb1 = 1; g.nb2 = 1; g.alpha = 1.0; g.beta = 0.0;
+      g.ws = w.skws.as<double>(); g.ws_len = w.skws.bytes / sizeof(double);
+      g.M = M; g.N = N; g.K = N;
+      g.A = src; g.a_i = si; g.a_k = 1;
+      g.B = w.ident.as<double>(); g.b_k = w.lmax; g.b_j = 1;
+      g.C = dst; g.c_i = di; g.c_j = 1;
+      gemm_f64(g, s);
+    };
+    auto update = [&](int c, bool right, bool natural_left) -> bool {
       const int pl = fdims[c], pr = fdims[c + 2];
       two_site_block(d, chi, pl, pdims[c], pdims[c + 1], pdims[c + 2], pr, w.ELc(c), w.ERc(c + 2),
                      psi + c * site, psi + (c + 1) * site, f[c], f[c + 1], w.T1.as<double>(),
@@ -307,7 +336,19 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
       g.nb1 = 1; g.nb2 = 1; g.alpha = 1.0; g.beta = 0.0;
       g.ws = w.skws.as<double>(); g.ws_len = w.skws.bytes / sizeof(double);
       int kk;
-      if (!right) {
+      bool centre_next = false;
+      if ((!right || natural_left) && m <= chi) {
+        // natural basis on the left: phi_c = I (m x m), phi_{c+1} = B
+        copy_strided(m, m, w.ident.as<double>(), w.lmax, phic, chi);
+        unpack_right(d, chi, m, pr, Bm, n, 1, phin, s);
+        kk = m;
+        centre_next = right;
+      } else if (right && n <= chi) {
+        // natural basis on the right: phi_{c+1} = I (n x n), phi_c = B
+        copy_strided(m, n, Bm, n, phic, chi);
+        unpack_right(d, chi, n, pr, w.ident.as<double>(), w.lmax, 1, phin, s);
+        kk = n;
+      } else if (!right) {
         kk = tsvd_left(w, Bm, n, 1, m, n, k, prm->oversample, prm->power_iters, phic, chi, 1, s);
         // Rm = U^T B (kk x n) -> phi_{c+1}[k][z][P]
         g.M = kk; g.N = n; g.K = m;
@@ -315,7 +356,6 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
         g.B = Bm; g.b_k = n; g.b_j = 1;
         g.C = w.Rm.as<double>(); g.c_i = n; g.c_j = 1;
         gemm_f64(g, s);
-        drop_null(kk, n, w.Rm.as<double>(), n, 1, phic, m, 1, chi, s);
         unpack_right(d, chi, kk, pr, w.Rm.as<double>(), n, 1, phin, s);
       } else {
         // tsvd of B^T (n x m): U' (n x kk) -> phi_{c+1} = U'^T;  phi_c = B U'
@@ -326,33 +366,37 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
         g.B = Up; g.b_k = k; g.b_j = 1;
         g.C = phic; g.c_i = chi; g.c_j = 1;
         gemm_f64(g, s);
-        // weight of direction i = column i of B U'
-        drop_null(kk, m, phic, 1, chi, Up, n, 1, k, s);
         unpack_right(d, chi, kk, pr, Up, 1, k, phin, s);
       }
       fdims[c + 1] = kk;
+      return centre_next;
     };
     int last_pair_lam_slot = sER + 2;
+    bool centre1 = false;                          // the centre is phi_1 (else phi_0)
     for (int sw = 0; sw < std::max(prm->num_sweeps, 1); ++sw) {
       for (int c = C - 1; c >= 2; --c) build_ER(c);
       for (int c = 0; c <= C - 2; ++c) {
         if (c < C - 2) {
-          update(c, false);
+          update(c, false, false);
           build_EL(c);
         } else {
-          update(c, true);
+          centre1 = update(c, true, false);
           if (C > 2) build_ER(c + 1);
         }
       }
       for (int c = C - 3; c >= 0; --c) {
-        update(c, true);
+        centre1 = update(c, true, c == 0);
         if (c > 0) build_ER(c + 1);
       }
     }
     (void)last_pair_lam_slot;
-    // normalise the centre phi_0; lam_r = lam_{r+1} + log-scale of ER[2] + log |phi_0|
-    normalize_box(phi, 1, d, fdims[1], 1, (long)d * chi, chi, 1, 1, logs, sCen, -1,
-                  w.nscr.as<double>(), s);
+    // normalise the centre; lam_r = lam_{r+1} + log-scale of ER[2] + log |centre|
+    if (centre1)
+      normalize_box(phi + site, fdims[1], d, fdims[2], 1, (long)d * chi, chi, 1, 1, logs, sCen,
+                    -1, w.nscr.as<double>(), s);
+    else
+      normalize_box(phi, 1, d, fdims[1], 1, (long)d * chi, chi, 1, 1, logs, sCen, -1,
+                    w.nscr.as<double>(), s);
     add_logs(logs, sLam + r, bottom ? -1 : sLam + r + 1, (C > 2) ? sER + 2 : -1, sCen, s);
     for (int c = 0; c <= C; ++c) env->dims[r * (C + 1) + c] = fdims[c];
   }

@@ -54,6 +54,32 @@ __global__ void k_init_guess(int d, int chi, int bl, int br, const double *psi, 
   phi[((long)p * d + x) * chi + P] = w[x] * acc;
 }
 
+// The bottom row's boundary function F_{rows-1} written exactly, x_c on the
+// bond: A_c[a][x][x'] = H_{c-1}(a, x) w_c(x) delta(x, x') (a < 1 at c = 0;
+// the last column closes the bond at x' = 0).  Every entry of the C padded
+// chi x d x chi tensors is written.  w: the row's d-vectors [C][d]; H: its
+// horizontal tables [C-1][d][d].
+__global__ void k_bottom_row(int C, int d, int chi, const double *w, const double *H, double *A,
+                             long ist) {
+  SPG_INST(w);
+  SPG_INST(H);
+  SPG_INST(A);
+  const long site = (long)chi * d * chi;
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= site * C) return;
+  const int c = (int)(e / site);
+  const long o = e - c * site;
+  const int k = (int)(o % chi), x = (int)((o / chi) % d), a = (int)(o / ((long)chi * d));
+  const int bl = (c == 0) ? 1 : d;
+  const bool on = (a < bl) && (c < C - 1 ? k == x : k == 0);
+  double v = 0.0;
+  if (on) {
+    v = w[(long)c * d + x];
+    if (c > 0) v *= H[((long)(c - 1) * d + a) * d + x];
+  }
+  A[e] = v;
+}
+
 // T1[p][a][x][q] = sum_e Al[x][e] EL[p][a][e][q]
 __global__ void k_T1(int d, int chi, int pl, int ql, const double *EL, const double *Al,
                      double *T1, long ist) {
@@ -247,6 +273,16 @@ void init_guess(int d, int chi, int bl, int br, const double *psi, const RowFact
   SPG_BC(f.V);
   SPG_BC(phi);
   hipLaunchKernelGGL(k_init_guess, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, bl, br, psi, f.w, f.V, phi, g_bc.ist);
+  SPG_CHECK_LAUNCH();
+}
+
+void bottom_row(int C, int d, int chi, const double *w, const double *H, double *A,
+                hipStream_t s) {
+  const long tot = (long)C * chi * d * chi;
+  SPG_BC(w);
+  SPG_BC(H);
+  SPG_BC(A);
+  hipLaunchKernelGGL(k_bottom_row, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, C, d, chi, w, H, A, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 

@@ -736,14 +736,10 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, 
 // rotation test, so only the floor columns (never rotated, last in sorted
 // order) can fail orthonormality: the first of them is the first failing
 // column i0 (without convergence the sorted columns are checked to 1e-13).
-// When everything from i0 on has joint norm below 5e-12 of the largest
-// singular value, every direction orthogonal to the first i0 columns weighs
-// less than half the null threshold of the truncation (1e-11 of the largest
-// weight), so columns i0.. are returned as zeros, which the truncation drops
-// like any such direction.  Otherwise the columns are re-orthonormalised by
-// CGS2 in sorted order with a deterministic completion from the unit vectors.
+// Then the columns are re-orthonormalised by CGS2 in sorted order, with a
+// deterministic completion from the unit vectors for columns that lose their
+// norm, so the kk returned vectors are always orthonormal.
 constexpr int kJacRows = kMaxSketch / 16;     // most rows per lane of a pair group
-constexpr double kJacTail = 5e-12;
 
 // NR = rows per lane of a pair group, ceil(l / 16)
 template <int NR>
@@ -789,8 +785,8 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
   ss = block_sum(ss, hbuf);
   if (tid == 0) sh_fro = ss;
   __syncthreads();
-  // columns below 1e-13 |R|_F sit at the rounding floor (the truncation drops
-  // such directions anyway): rotating them only shuffles noise
+  // columns below 1e-13 |R|_F sit at the rounding floor of the range finder's
+  // projection: rotating them only shuffles noise
   const double tiny = 1e-26 * sh_fro;
   const int grp = tid >> 4, r16 = tid & 15, ngrp = blockDim.x >> 4;
   const int np = le / 2, nc = le - 1;
@@ -912,18 +908,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
     }
   }
   __syncthreads();
-  if (bad && wid == 0) {
-    // joint norm of the sorted columns from the first failing one on
-    double t2 = 0.0;
-    for (int j = first_bad + lane; j < l; j += 64) t2 = fma(snrm[j], snrm[j], t2);
-    t2 = wave_sum(t2);
-    if (lane == 0 && snrm[0] > 0.0 && sqrt(t2) <= kJacTail * snrm[0]) bad = 2;
-  }
-  __syncthreads();
-  if (bad == 2) {
-    for (int e = tid; e < (kk - first_bad) * l; e += blockDim.x) V[first_bad * l + e] = 0.0;
-    __syncthreads();
-  } else if (bad) {
+  if (bad) {
     // CGS2 in sorted order; a column that loses its norm is replaced by the
     // first unit vector that survives the projection
     for (int i = 0; i < kk; ++i) {
@@ -1072,54 +1057,6 @@ __global__ __launch_bounds__(256) void k_box_scale(double *T, unsigned tot, unsi
   for (; e < tot; e += stride) {
     const long o = box_offset(e, n1, n2, n3, s0, s1, s2, s3);
     T[o] *= f;
-  }
-}
-
-// Zero the directions whose weight (norm of their row of Wm) is at most
-// 1e-11 of the largest: direction i is row i of Wm (len entries, element
-// stride w_el, row stride w_dir) and column i of U (ulen entries).
-__global__ __launch_bounds__(1024) void k_drop_null(int nd, int len, double *Wm, long w_dir,
-                                                   long w_el, double *U, int ulen, long u_dir,
-                                                   long u_el, long ist) {
-  SPG_INST(Wm);
-  SPG_INST(U);
-  __shared__ double wn[kMaxSketch + 32];
-  __shared__ double wmax;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int i = wid; i < nd; i += nw) {
-    // four independent loads in flight per lane
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int e = lane;
-    for (; e + 192 < len; e += 256) {
-      const double v0 = Wm[i * w_dir + (long)e * w_el];
-      const double v1 = Wm[i * w_dir + (long)(e + 64) * w_el];
-      const double v2 = Wm[i * w_dir + (long)(e + 128) * w_el];
-      const double v3 = Wm[i * w_dir + (long)(e + 192) * w_el];
-      a0 = fma(v0, v0, a0);
-      a1 = fma(v1, v1, a1);
-      a2 = fma(v2, v2, a2);
-      a3 = fma(v3, v3, a3);
-    }
-    for (; e < len; e += 64) {
-      const double v = Wm[i * w_dir + (long)e * w_el];
-      a0 = fma(v, v, a0);
-    }
-    const double a = wave_sum((a0 + a1) + (a2 + a3));
-    if (lane == 0) wn[i] = sqrt(a);
-  }
-  __syncthreads();
-  if (wid == 0) {
-    double m = 0.0;
-    for (int i = lane; i < nd; i += 64) m = fmax(m, wn[i]);
-    m = wave_max_nonneg(m);
-    if (lane == 0) wmax = m;
-  }
-  __syncthreads();
-  const double thr = 1e-11 * wmax;
-  for (int i = wid; i < nd; i += nw) {
-    if (!(wn[i] <= thr) || wmax == 0.0) continue;
-    for (int e = lane; e < len; e += 64) Wm[i * w_dir + e * w_el] = 0.0;
-    for (int e = lane; e < ulen; e += 64) U[i * u_dir + e * u_el] = 0.0;
   }
 }
 
@@ -1385,20 +1322,6 @@ void normalize_box(double *T, int n0, int n1, int n2, int n3, long s0, long s1, 
   SPG_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_box_scale, dim3(nb, nI), dim3(256), 0, s, T, (unsigned)tot, (unsigned)n1,
                      (unsigned)n2, (unsigned)n3, s0, s1, s2, s3, scratch, g_bc.ist);
-  SPG_CHECK_LAUNCH();
-}
-
-void drop_null(int nd, int len, double *Wm, long w_dir, long w_el, double *U, int ulen,
-               long u_dir, long u_el, hipStream_t s) {
-  if (nd <= 0) return;
-  if (nd > kMaxSketch + 32) {
-    set_error("drop_null: too many directions");
-    throw Fail{SPG_ERR_UNSUPPORTED};
-  }
-  SPG_BC(Wm);
-  SPG_BC(U);
-  hipLaunchKernelGGL(k_drop_null, dim3(1, g_bc.n), dim3(1024), 0, s, nd, len, Wm, w_dir, w_el, U,
-                     ulen, u_dir, u_el, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 

@@ -419,6 +419,10 @@ __global__ __launch_bounds__(256) void k_fallback(SearchTabs t, int r, int c, in
   const double tot = wave_sum(part_tot);
   const double ltot = log(tot);
   const double sb = score[b];
+  // no child with positive weight: softmax_s(-beta dE) (local_softmax_norm)
+  const bool dead = !(tot > 0.0);
+  double emin = 0.0, lse = 0.0;
+  if (dead) local_softmax_norm(t, r, c, cb, lane, emin, lse);
   const int js = *jstar_p;
   const int nb = cnt[b];
   int extra = 0;
@@ -437,6 +441,7 @@ __global__ __launch_bounds__(256) void k_fallback(SearchTabs t, int r, int c, in
       const double q = myq[j];
       double lp = (q > 0.0 && tot > 0.0) ? log(q) - ltot : -INFINITY;
       if (!(lp == lp)) lp = -INFINITY;
+      if (dead) lp = -t.beta * (delta_energy(t, r, c, cb, s) - emin) - lse;
       const int pos = ins ? o + r_in + __popcll(mi & below) : extra + r_out + __popcll(mo & below);
       lkey[pos] = sb + lp;
       lid[pos] = b * d + s;

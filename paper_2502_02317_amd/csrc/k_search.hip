@@ -164,7 +164,8 @@ __global__ __launch_bounds__(256) void k_right_env_lds(SearchTabs t, int r, int 
   if (scale && lane == 0) scale[(long)a * sstride] = m;
 }
 
-// out[b*d + s] = (add_score ? score[b] : 0) + log p(s | b)
+// out[b*d + s] = (add_score ? score[b] : 0) + log p(s | b); a parent with no
+// positive weight takes softmax_s(-beta dE) (local_softmax_norm)
 __global__ __launch_bounds__(256) void k_marginals(SearchTabs t, int r, int c, int n_beam,
                                                    const uint8_t *cfg, int N, const double *A,
                                                    const double *L, const int32_t *anc,
@@ -214,6 +215,13 @@ __global__ __launch_bounds__(256) void k_marginals(SearchTabs t, int r, int c, i
   }
   const double tot = wave_sum(part);
   const double base = add_score ? score[b] : 0.0;
+  if (!(tot > 0.0)) {                      // no child with positive weight
+    double emin, lse;
+    local_softmax_norm(t, r, c, cb, lane, emin, lse);
+    for (int s = lane; s < d; s += 64)
+      out[(long)b * d + s] = base + (-t.beta * (delta_energy(t, r, c, cb, s) - emin) - lse);
+    return;
+  }
   const double ltot = log(tot);
   for (int s = lane; s < d; s += 64) {
     const double q = qs[w][s];
@@ -321,6 +329,12 @@ __global__ __launch_bounds__(256) void k_marginals_lds(SearchTabs t, int r, int 
   }
   const double tot = wave_sum(part);
   const double base = add_score ? score[b] : 0.0;
+  if (!(tot > 0.0)) {                      // no child with positive weight
+    double emin, lse;
+    local_softmax_norm(t, r, c, cb, lane, emin, lse);
+    if (s < d) out[(long)b * d + s] = base + (-t.beta * (delta_energy(t, r, c, cb, s) - emin) - lse);
+    return;
+  }
   const double ltot = log(tot);
   if (s < d) {
     const double q = qs[w][s];

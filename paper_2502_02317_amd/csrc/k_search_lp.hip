@@ -5,6 +5,7 @@
 // cannot underflow on them; log-probabilities are added to FP64 scores.
 #include <cfloat>
 
+#include "search_dev.h"
 #include "spg_internal.h"
 
 namespace spg {
@@ -205,6 +206,14 @@ __global__ __launch_bounds__(256) void k_marg_from_u(SearchTabs t, int r, int c,
     mx = fmaxf(mx, lq[h]);
   }
   mx = wave_max_f(mx);
+  if (!(mx > -INFINITY)) {                 // no child with positive weight
+    double emin, lse;
+    local_softmax_norm(t, r, c, cb, lane, emin, lse);
+    const double base = add_score ? score[b] : 0.0;
+    for (int s = lane; s < d; s += 64)
+      out[(long)b * d + s] = base + (-t.beta * (delta_energy(t, r, c, cb, s) - emin) - lse);
+    return;
+  }
   float se = 0.f;
   for (int h = 0; h < 4; ++h)
     if (lane + 64 * h < d && lq[h] > -INFINITY) se += expf(lq[h] - mx);

@@ -53,6 +53,23 @@ __device__ __forceinline__ double delta_energy(const SearchTabs &t, int r, int c
   return e;
 }
 
+// A parent none of whose children has a positive conditional weight has no
+// conditional from the contraction; it takes the conditional of the fixed
+// sites' Boltzmann weight alone, p(s) = softmax_s(-beta dE(b, s)).  Every lane
+// of the parent's wavefront calls this; it returns the normalisation of
+// log p(s) = -beta (dE(s) - emin) - lse, reduced over the wavefront.
+__device__ inline void local_softmax_norm(const SearchTabs &t, int r, int c, const uint8_t *cb,
+                                          int lane, double &emin, double &lse) {
+  double m = INFINITY;
+  for (int s = lane; s < t.d; s += 64) m = fmin(m, delta_energy(t, r, c, cb, s));
+  for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+  double z = 0.0;
+  for (int s = lane; s < t.d; s += 64) z += exp(-t.beta * (delta_energy(t, r, c, cb, s) - m));
+  for (int o = 32; o > 0; o >>= 1) z += __shfl_xor(z, o, 64);
+  emin = m;
+  lse = log(z);
+}
+
 // Key for ascending sort = descending score; NaN sorts with -inf.
 __device__ __forceinline__ uint64_t desc_key(double v) {
   if (!(v == v)) v = -INFINITY;

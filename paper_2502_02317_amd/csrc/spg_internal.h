@@ -123,10 +123,9 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
 // One-sided Jacobi SVD of an l x l matrix (row-major, l <= kMaxSketch): writes
 // the right singular vectors as columns of V (row-major l x l) sorted by
 // singular value, descending (ties by index), and the singular values to sig.
-// The leading kk columns are orthonormal to 1e-13, except that a trailing run
-// of them whose joint singular-value norm is below 5e-12 of the largest may
-// come back as zero columns (directions the truncation's null rule drops);
-// the others are the normalised Jacobi columns and need not be orthonormal.
+// The leading kk columns are orthonormal to 1e-13 (re-orthonormalised with a
+// deterministic completion where columns at the rounding floor failed); the
+// others are the normalised Jacobi columns and need not be orthonormal.
 void jacobi_svd_f64(int l, int kk, const double *Rm, double *V, double *sig, hipStream_t s);
 
 // Sketch matrix of the truncated SVD: Om[i*l + j] = 2 u(SplitMix64(seed, i*ld + j)) - 1.
@@ -140,11 +139,6 @@ void normalize_box(double *T, int n0, int n1, int n2, int n3, long s0, long s1, 
                    long s3, double *logs, int out, int in, double *scratch, hipStream_t s);
 void fill_zero(double *p, size_t n, hipStream_t s);
 void copy_doubles(double *dst, const double *src, size_t n, hipStream_t s);
-// Directions at the rounding floor of a truncation are not unique: zero every
-// direction i (row i of Wm, column i of U) whose weight |Wm row i| is at most
-// 1e-11 of the largest.
-void drop_null(int nd, int len, double *Wm, long w_dir, long w_el, double *U, int ulen,
-               long u_dir, long u_el, hipStream_t s);
 
 // ---- boundary-MPS contraction kernels (k_bmps.hip) -------------------------
 struct RowFactors {         // device d x d tables (row-major) / d vectors of one column
@@ -153,6 +147,11 @@ struct RowFactors {         // device d x d tables (row-major) / d vectors of on
   const double *Hl, *Dl, *Al;  // H_{c-1}[a][x], D_{c-1}[a][y], A_{c-1}[x][e]
   const double *ones;          // d x d ones (an epilogue factor of 1 per row)
 };
+// The bottom row's boundary function written exactly (bond d, x_c on the
+// bond): all C padded site tensors of the row at A.  w = W_loc of the row,
+// H = W_h of the row.
+void bottom_row(int C, int d, int chi, const double *w, const double *H, double *A,
+                hipStream_t s);
 void init_guess(int d, int chi, int bl, int br, const double *psi, const RowFactors &f,
                 double *phi, hipStream_t s);
 // P[p][x][y][Q] = w(x)V(x,y) sum_{q,a,e} EL[p][a][e][q] Hl(a,x)Dl(a,y)Al(x,e) psi[q][y][Q]

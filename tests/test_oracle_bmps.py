@@ -15,9 +15,19 @@ def _centre(row):
 
 
 def test_canonical_form_and_normalised():
+    """Fitted rows: the centre has unit norm and the tensors right of it are
+    right isometries.  The bottom row is the exact chain (bond d,
+    non-negative), equal to the exact row function."""
     inst = random_potts(4, 5, 3, True, seed=5, beta=0.6)
     mp = boundary_mps(inst, chi=4)
-    for row in mp["A"]:
+    bottom = mp["A"][-1]
+    assert [a.shape for a in bottom] == [(1, 3, 3)] + [(3, 3, 3)] * 3 + [(3, 3, 1)]
+    assert all((a >= 0).all() for a in bottom)
+    rows, _ = row_transfer(inst)
+    ex = rows[-1][0]
+    ap = mps_full(bottom)
+    np.testing.assert_allclose(ap / ap.max(), ex / ex.max(), rtol=1e-13)
+    for row in mp["A"][:-1]:
         c0 = _centre(row)
         assert abs(np.linalg.norm(row[c0]) - 1) < 1e-12
         for A in row[c0 + 1:]:
