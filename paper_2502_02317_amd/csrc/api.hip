@@ -736,35 +736,49 @@ static void ensure_search(spg_env *env, int M) {
   each_search_buffer(env, M, [](DevBuf &b, size_t n) { b.ensure(n); });
 }
 
-int spg_marginals(const spg_env_t *cenv, int32_t site, int32_t n_beam, const int32_t *beam_cfg,
-                  double *log_cond_out, void *stream) {
-  SPG_TRY
-  if (!cenv || !beam_cfg || !log_cond_out) return fail(SPG_ERR_INVALID, "spg_marginals: null argument");
-  spg_env *env = const_cast<spg_env *>(cenv);
+// Work buffers of one teacher-forced marginals call (n_beam states).
+struct MargBufs {
+  uint8_t *cfg;            // [n][N]
+  int32_t *anc;            // [n]
+  void *Rv;                // [n][C+1][chi] (double; float in reduced precision)
+  void *L;                 // [n][chi] (double; float in reduced precision)
+  double *L2;              // [n][chi] double (reduced precision: beam_reset_row's target)
+  float *U;                // [n][chi*d] (reduced precision)
+};
+
+static int marginals_check(const spg_env_t *cenv, int32_t site, int32_t n_beam,
+                           const int32_t *beam_cfg, const double *log_cond_out,
+                           const char *who) {
+  if (!cenv || !beam_cfg || !log_cond_out)
+    return fail(SPG_ERR_INVALID, std::string(who) + ": null argument");
+  const spg_peps *pp = cenv->peps;
+  if (site < 0 || site >= pp->rows * pp->cols)
+    return fail(SPG_ERR_INVALID, std::string(who) + ": site out of range");
+  if (n_beam < 1) return fail(SPG_ERR_INVALID, std::string(who) + ": n_beam must be >= 1");
+  return SPG_OK;
+}
+
+static void marginals_run(spg_env *env, int32_t site, int32_t n_beam, const int32_t *beam_cfg,
+                          double *log_cond_out, hipStream_t s, const MargBufs &b) {
   const spg_peps *pp = env->peps;
   const int C = pp->cols, N = pp->rows * C, d = pp->d, chi = env->chi;
-  if (site < 0 || site >= N) return fail(SPG_ERR_INVALID, "spg_marginals: site out of range");
-  if (n_beam < 1) return fail(SPG_ERR_INVALID, "spg_marginals: n_beam must be >= 1");
-  hipStream_t s = (hipStream_t)stream;
   const int r = site / C, c = site % C;
-  ensure_search(env, n_beam);
-  env->cfg32.ensure((size_t)n_beam * N);
-  uint8_t *cfg = env->cfg32.as<uint8_t>();
+  uint8_t *cfg = b.cfg;
   cfg_from_i32(n_beam, N, beam_cfg, cfg, s);
   const SearchTabs t = tabs_of(env);
   const double *A = env->A.as<double>();
   const size_t site_sz = (size_t)chi * d * chi;
   const long rstride = (long)(C + 1) * chi;
-  int32_t *anc = env->anc[0].as<int32_t>();
+  int32_t *anc = b.anc;
   const int* dm = env->dims.data() + r * (C + 1);
   if (env->precision == SPG_FP64) {
-    double *Rv = env->Rv.as<double>();
+    double *Rv = static_cast<double *>(b.Rv);
     set_e0(n_beam, chi, Rv + (size_t)C * chi, rstride, s);
     for (int cc = C - 1; cc > c; --cc)
       right_env_col(t, r, cc, n_beam, cfg, N, A + ((size_t)r * C + cc) * site_sz,
                     Rv + (size_t)(cc + 1) * chi, Rv + (size_t)cc * chi, rstride, dm[cc],
                     dm[cc + 1], s);
-    double *L = env->L[0].as<double>();
+    double *L = static_cast<double *>(b.L);
     beam_reset_row(n_beam, chi, L, anc, s);
     for (int cc = 0; cc < c; ++cc)
       advance_L(t, r, cc, n_beam, cfg, N, A + ((size_t)r * C + cc) * site_sz, L, nullptr, s);
@@ -774,8 +788,8 @@ int spg_marginals(const spg_env_t *cenv, int32_t site, int32_t n_beam, const int
     const int pr = env->precision;
     const char *Al = env->Alp.as<char>();
     const size_t eb = lp_elt(env);
-    float *Rv = env->Rv.as<float>();
-    float *U = env->Ulp.as<float>();
+    float *Rv = static_cast<float *>(b.Rv);
+    float *U = b.U;
     const long ldu = (long)chi * d;
     lp_set_e0(n_beam, chi, Rv + (size_t)C * chi, rstride, s);
     // the products and environments of the search, each beam state its own ancestor
@@ -786,14 +800,27 @@ int spg_marginals(const spg_env_t *cenv, int32_t site, int32_t n_beam, const int
         lp_env_from_u(t, pr, r, cc, n_beam, cfg, N, U, ldu, Rv + (size_t)cc * chi, rstride,
                       dm[cc], s);
     }
-    float *L = env->L[0].as<float>();
-    beam_reset_row(n_beam, chi, env->L[1].as<double>(), anc, s);
+    float *L = static_cast<float *>(b.L);
+    beam_reset_row(n_beam, chi, b.L2, anc, s);
     lp_set_e0(n_beam, chi, L, chi, s);
     for (int cc = 0; cc < c; ++cc)
       lp_advance_L(t, pr, r, cc, n_beam, cfg, N, Al + ((size_t)r * C + cc) * site_sz * eb, L, s);
     lp_marginals_u(t, r, c, n_beam, cfg, N, U, ldu, L, anc, nullptr, log_cond_out, 0, dm[c], s);
   }
-  (void)d;
+}
+
+int spg_marginals(const spg_env_t *cenv, int32_t site, int32_t n_beam, const int32_t *beam_cfg,
+                  double *log_cond_out, void *stream) {
+  SPG_TRY
+  const int rc = marginals_check(cenv, site, n_beam, beam_cfg, log_cond_out, "spg_marginals");
+  if (rc != SPG_OK) return rc;
+  spg_env *env = const_cast<spg_env *>(cenv);
+  const int N = env->peps->rows * env->peps->cols;
+  ensure_search(env, n_beam);
+  env->cfg32.ensure((size_t)n_beam * N);
+  MargBufs b{env->cfg32.as<uint8_t>(), env->anc[0].as<int32_t>(), env->Rv.p, env->L[0].p,
+             env->L[1].as<double>(), env->Ulp.as<float>()};
+  marginals_run(env, site, n_beam, beam_cfg, log_cond_out, (hipStream_t)stream, b);
   return SPG_OK;
   SPG_CATCH
 }
