@@ -143,6 +143,26 @@ int spg_boundary_mps(const spg_peps_t *peps, const spg_mps_params *params, void 
 int spg_marginals(const spg_env_t *env, int32_t site, int32_t n_beam, const int32_t *beam_cfg,
                   double *log_cond_out, void *stream);
 
+/* spg_marginals for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments and the same results (same kernels, bitwise), but every work
+ * buffer lies in one static 64 MiB device array per GPU, which the library
+ * holds until the process ends; the call allocates nothing.  A call needs
+ *   FP64 env:     256-byte-rounded parts n_beam*rows*cols + 4 n_beam
+ *                 + 8 n_beam (cols+1) chi + 8 n_beam chi  bytes,
+ *   FP32/BF16:    n_beam*rows*cols + 4 n_beam + 4 n_beam (cols+1) chi
+ *                 + 4 n_beam chi + 8 n_beam chi + 4 n_beam chi d  bytes,
+ * at most 64 MiB (n_beam = 4096 fits at rows = cols = 12, chi = 64); a larger
+ * call returns SPG_ERR_INVALID before any launch.  Every call on one GPU uses
+ * the same array, which keeps the last call's contents and is cleared by each
+ * call (a fill kernel on `stream`): calls that overlap on one GPU (two streams
+ * or threads) race and must be serialised by the caller.  The env's device
+ * must be the current device.
+ * Errors: as spg_marginals; SPG_ERR_INVALID (scratch too small, wrong current
+ * device); SPG_ERR_HIP (the scratch's address cannot be obtained). */
+int spg_marginals_noalloc(const spg_env_t *env, int32_t site, int32_t n_beam,
+                          const int32_t *beam_cfg, double *log_cond_out, void *stream);
+
 /* Branch-and-bound search (Sec. 2; Fig. 1(d)-(e)): visits the sites in
  * row-major order, keeping the max_states most probable partial
  * configurations (ties: parent position, then state), and returns the final

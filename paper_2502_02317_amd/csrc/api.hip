@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 
 #include "mlp_dev.h"
@@ -821,6 +822,76 @@ int spg_marginals(const spg_env_t *cenv, int32_t site, int32_t n_beam, const int
   MargBufs b{env->cfg32.as<uint8_t>(), env->anc[0].as<int32_t>(), env->Rv.p, env->L[0].p,
              env->L[1].as<double>(), env->Ulp.as<float>()};
   marginals_run(env, site, n_beam, beam_cfg, log_cond_out, (hipStream_t)stream, b);
+  return SPG_OK;
+  SPG_CATCH
+}
+
+// ---- spg_marginals_noalloc: the same conditionals without allocating ------
+// All work buffers live in one static device array per GPU (held until the
+// process ends).  In host code `scratch` names a host-side stand-in, not a
+// device address: the address comes from hipGetSymbolAddress, once per device
+// with that device current, and only that address reaches kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kScratchDevices];
+
+static int scratch_address(int dev, unsigned char **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(SPG_ERR_UNSUPPORTED, "spg_marginals_noalloc: device index beyond 63");
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(SPG_ERR_HIP, std::string("spg_marginals_noalloc: hipGetSymbolAddress: ") +
+                                   hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<unsigned char *>(g_scratch_ptr[dev]);
+  return SPG_OK;
+}
+
+static size_t up256(size_t n) { return (n + 255) & ~size_t(255); }
+
+int spg_marginals_noalloc(const spg_env_t *cenv, int32_t site, int32_t n_beam,
+                          const int32_t *beam_cfg, double *log_cond_out, void *stream) {
+  SPG_TRY
+  const int rc = marginals_check(cenv, site, n_beam, beam_cfg, log_cond_out,
+                                 "spg_marginals_noalloc");
+  if (rc != SPG_OK) return rc;
+  spg_env *env = const_cast<spg_env *>(cenv);
+  const spg_peps *pp = env->peps;
+  const int C = pp->cols, N = pp->rows * C, d = pp->d, chi = env->chi;
+  const bool lp = env->precision != SPG_FP64;
+  const size_t n = (size_t)n_beam, eb = lp ? 4 : 8;
+  const size_t o_cfg = 0, o_anc = o_cfg + up256(n * N), o_R = o_anc + up256(n * 4);
+  const size_t o_L = o_R + up256(n * (C + 1) * chi * eb), o_L2 = o_L + up256(n * chi * eb);
+  const size_t o_U = o_L2 + (lp ? up256(n * chi * 8) : 0);
+  const size_t need = o_U + (lp ? up256(n * chi * d * 4) : 0);
+  if (need > kScratchBytes)
+    return fail(SPG_ERR_INVALID, "spg_marginals_noalloc: n_beam = " + std::to_string(n_beam) +
+                                     " needs " + std::to_string(need) +
+                                     " bytes of scratch, more than its " +
+                                     std::to_string(kScratchBytes));
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pp->device) {
+    (void)hipGetLastError();
+    return fail(SPG_ERR_INVALID, "spg_marginals_noalloc: the env's device must be current");
+  }
+  unsigned char *base = nullptr;
+  const int rs = scratch_address(dev, &base);
+  if (rs != SPG_OK) return rs;
+  hipStream_t s = (hipStream_t)stream;
+  // the previous call's contents stay in the array: clear the part this call uses
+  fill_zero(reinterpret_cast<double *>(base), need / 8, s);
+  MargBufs b{base + o_cfg, reinterpret_cast<int32_t *>(base + o_anc), base + o_R, base + o_L,
+             lp ? reinterpret_cast<double *>(base + o_L2) : nullptr,
+             lp ? reinterpret_cast<float *>(base + o_U) : nullptr};
+  marginals_run(env, site, n_beam, beam_cfg, log_cond_out, s, b);
   return SPG_OK;
   SPG_CATCH
 }

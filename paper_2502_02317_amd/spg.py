@@ -62,7 +62,8 @@ class BatchItem(C.Structure):
                 ("max_states", C.c_int32), ("cut_off_prob", C.c_double)]
 
 
-EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_branch_and_bound",
+EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals_noalloc",
+           "spg_branch_and_bound",
            "spg_free_peps", "spg_free_env", "spg_last_error", "spg_env_info", "spg_env_export",
            "spg_env_import", "spg_profile_enable", "spg_profile_reset", "spg_profile_query",
            "spg_proposal_create", "spg_proposal_free", "spg_proposal_params",
@@ -90,6 +91,7 @@ def load() -> C.CDLL:
     lib.spg_build_peps.argtypes = [C.POINTER(InstanceDesc), vp, C.POINTER(vp)]
     lib.spg_boundary_mps.argtypes = [vp, C.POINTER(MpsParams), vp, C.POINTER(vp), f64p]
     lib.spg_marginals.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.spg_marginals_noalloc.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.spg_branch_and_bound.argtypes = [vp, C.POINTER(SearchParams), vp, vp, vp, i32p, vp]
     lib.spg_free_peps.argtypes = [vp]
     lib.spg_free_env.argtypes = [vp]
@@ -126,7 +128,8 @@ def load() -> C.CDLL:
     lib.spg_batch_set_tuning.argtypes = [vp, i32, i32]
     lib.spg_batch_autotune.argtypes = [vp, vp, vp]
     lib.spg_set_tuning.argtypes = [i32]
-    for name in ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_branch_and_bound",
+    for name in ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals_noalloc",
+                 "spg_branch_and_bound",
                  "spg_env_info", "spg_env_export", "spg_env_import", "spg_profile_query",
                  "spg_proposal_create", "spg_proposal_params", "spg_proposal_train",
                  "spg_proposal_features", "spg_proposal_forward", "spg_proposal_loss_grad",
@@ -215,6 +218,13 @@ def marginals(env: Env, site: int, beam_cfg, out, stream=None):
     """spg_marginals: beam_cfg int32 [n][N] and out float64 [n][d], torch device tensors."""
     _check(load().spg_marginals(env.handle, int(site), int(beam_cfg.shape[0]), _ptr(beam_cfg),
                                 _ptr(out), _stream(stream)))
+    return out
+
+
+def marginals_noalloc(env: Env, site: int, beam_cfg, out, stream=None):
+    """spg_marginals_noalloc: as marginals(), with the library's static scratch."""
+    _check(load().spg_marginals_noalloc(env.handle, int(site), int(beam_cfg.shape[0]),
+                                        _ptr(beam_cfg), _ptr(out), _stream(stream)))
     return out
 
 
