@@ -11,6 +11,11 @@ mechanics to its references, so the steps below are the adopted reading):
 * Boundary MPS.  E~_r(X) ~ exp(lam_r) A_{r,0}[x_0] ... A_{r,cols-1}[x_{cols-1}], each
   A_{r,c} a (chi_c x d x chi_{c+1}) tensor; the centre (A_{r,0}, or A_{r,1} when
   column 0 kept its natural basis) has unit norm.
+* Scale.  Each column's local weights w_c are divided by the largest entry of
+  its MPO tensor (``scaled_row``; the logs go to the row's log-scale), so that
+  products of tables, each at most 1 but far below it where the others peak,
+  do not underflow in the blocks (the 12x12 d=24 workload at beta = 4 lost
+  every fitted row to zero without it).
 * The bottom row.  E~_{rows-1} = F_{rows-1} is a chain of nearest-neighbour
   factors; with chi >= d it is written exactly as an MPS of bond d (x_c on the
   bond, non-negative tensors, ``bottom_row``).  A fit would keep chi > d
@@ -136,7 +141,10 @@ def right_canonicalize(phi):
         Q, Rr = np.linalg.qr(phi[c].reshape(bl, d * br).T, mode="reduced")
         k = Q.shape[1]
         phi[c] = Q.T.reshape(k, d, br)
-        phi[c - 1] = np.einsum("pxq,kq->pxk", phi[c - 1], Rr)
+        # the folded factor only carries the guess's scale, which no later step
+        # uses (phi_0 and phi_1 are overwritten before they are read): keep it
+        # at unit norm so that it cannot overflow over many columns
+        phi[c - 1] = _norm(np.einsum("pxq,kq->pxk", phi[c - 1], Rr))[0]
     return phi
 
 
@@ -213,12 +221,38 @@ def row_step(psi, fac, chi, num_sweeps):
     return phi, lam + s0
 
 
-def bottom_row(W: Weights, r: int):
+def site_log_scales(fac):
+    """log of the largest entry of each column's MPO tensor,
+    max over (a, e, x, y) of w_c(x) V_c(x, y) H_{c-1}(a, x) D_{c-1}(a, y) A_{c-1}(x, e)
+    = max over (x, y) of [w V](x, y) max_a [H D](a, x, y) max_e A(x, e), in logs."""
+    w, V, Hl, Dl, Al = fac
+    out = []
+    with np.errstate(divide="ignore"):
+        for c in range(len(w)):
+            t = (np.log(Hl[c])[:, :, None] + np.log(Dl[c])[:, None, :]).max(axis=0)   # [x][y]
+            v = np.log(w[c])[:, None] + np.log(V[c]) + t + np.log(Al[c]).max(axis=1)[:, None]
+            out.append(float(v.max()))
+    return out
+
+
+def scaled_row(W: Weights, r: int):
+    """The row's factors with each column's w_c divided by the largest entry of
+    its MPO tensor, and the sum of the logs of those divisors.  Every table is
+    at most 1, but their products over a column fall far below (at beta = 4
+    with 8-spin clusters, to 1e-100 and less), so that blocks built from them
+    underflow; with this constant per column (returned to the log-scale) each
+    MPO tensor's largest entry is 1."""
+    w, V, Hl, Dl, Al = row_weights(W, r)
+    ls = site_log_scales((w, V, Hl, Dl, Al))
+    return ([w[c] * np.exp(-ls[c]) for c in range(len(w))], V, Hl, Dl, Al), float(sum(ls))
+
+
+def bottom_row(fac):
     """E~_{rows-1} = F_{rows-1} written exactly, x_c carried on the bond:
     A_c[a, x, x'] = H_{c-1}(a, x) w_c(x) delta(x, x') (bond d, non-negative;
     the last column closes the bond).  Each tensor is divided by its norm and
     the logs are summed into the log-scale."""
-    w, _, Hl, _, _ = row_weights(W, r)
+    w, _, Hl, _, _ = fac
     C, d = len(w), w[0].shape[0]
     out, lam = [], 0.0
     for c in range(C):
@@ -244,10 +278,12 @@ def boundary_mps(inst, chi: int, num_sweeps: int = 1):
     psi = [e0.copy() for _ in range(C)]          # E~_rows = 1 through y = 0 (couplings are ones)
     prev = 0.0
     for r in range(R - 1, -1, -1):
+        fac, ls = scaled_row(W, r)
         if r == R - 1 and chi >= d:
-            phi, s = bottom_row(W, r)            # exact at bond d: nothing to fit
+            phi, s = bottom_row(fac)             # exact at bond d: nothing to fit
         else:
-            phi, s = row_step(psi, row_weights(W, r), chi, num_sweeps)
+            phi, s = row_step(psi, fac, chi, num_sweeps)
+        s += ls
         A[r] = phi
         lam[r] = prev + s
         prev = lam[r]

@@ -48,7 +48,8 @@ def ising_energy(si, S: np.ndarray) -> np.ndarray:
 
 class Weights:
     """Boltzmann factors of the min-shifted tables: w = exp(-beta (E - eps)),
-    eps = table minimum.  The shift only rescales Z:  log Z = log Z~ - beta*shift.
+    eps = table minimum, and their exact logs (log_loc, log_h, ...), which stay
+    finite where the weights underflow.  The shift only rescales Z:  log Z = log Z~ - beta*shift.
 
     Absent edge classes (square lattice) and absent neighbours are all-ones
     tables, which is the same as a zero energy."""
@@ -60,21 +61,27 @@ class Weights:
         le, ph, pv, pd, pa = inst.tables()
         self.shift = 0.0
 
-        def w(T):
+        def lw(T):
+            """-beta (E - eps): the exact logs of the weights."""
             if T.size == 0:
-                return np.ones(T.shape)
+                return np.zeros(T.shape)
             eps = T.reshape(T.shape[: T.ndim - (1 if T is le else 2)] + (-1,)).min(axis=-1)
             self.shift += float(eps.sum())
             if T is le:
-                return np.exp(-b * (T - eps[..., None]))
-            return np.exp(-b * (T - eps[..., None, None]))
+                return -b * (T - eps[..., None])
+            return -b * (T - eps[..., None, None])
 
-        self.loc = w(le)                                    # [R][C][d]
-        self.h = w(ph)                                      # [R][C-1][d][d]
-        self.v = w(pv)                                      # [R-1][C][d][d]
+        self.log_loc = lw(le)                               # [R][C][d]
+        self.log_h = lw(ph)                                 # [R][C-1][d][d]
+        self.log_v = lw(pv)                                 # [R-1][C][d][d]
         if inst.kings:
-            self.dg = w(pd)
-            self.an = w(pa)
+            self.log_dg = lw(pd)
+            self.log_an = lw(pa)
         else:
-            self.dg = np.ones((max(R - 1, 0), max(C - 1, 0), d, d))
-            self.an = np.ones((max(R - 1, 0), max(C - 1, 0), d, d))
+            self.log_dg = np.zeros((max(R - 1, 0), max(C - 1, 0), d, d))
+            self.log_an = np.zeros((max(R - 1, 0), max(C - 1, 0), d, d))
+        self.loc = np.exp(self.log_loc)
+        self.h = np.exp(self.log_h)
+        self.v = np.exp(self.log_v)
+        self.dg = np.exp(self.log_dg)
+        self.an = np.exp(self.log_an)

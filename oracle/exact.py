@@ -6,7 +6,8 @@
   open 1-D chains) in tests/test_oracle_exact.py.
 * ``row_transfer``: exact contraction of the Boltzmann PEPS (Sec. 2, Fig. 1(c))
   one lattice row at a time, with the whole row state as a dense vector of
-  d^cols entries.  Pinned against ``brute_force``.
+  d^cols entries, in the log domain (the workloads' row functions span more
+  than the FP64 range).  Pinned against ``brute_force``.
 * ``exact_conditionals``: p(x_k | x_<k) from the row-transfer vectors, i.e. the
   conditional marginals the branch-and-bound search consumes (Fig. 1(d)).
 
@@ -57,104 +58,101 @@ def prefix_logp(bf: dict, cfg_prefix) -> float:
     return float(bf["prefix_logp"][k - 1][idx])
 
 
-def row_factor(W: Weights, r: int) -> np.ndarray:
-    """F_r(X) = prod_c w_{r,c}(x_c) prod_c W^H_{r,c}(x_c, x_{c+1}) as a dense
-    tensor with one axis per column."""
+def log_row_factor(W: Weights, r: int) -> np.ndarray:
+    """log F_r(X) = sum_c log w_{r,c}(x_c) + sum_c log W^H_{r,c}(x_c, x_{c+1}) as a
+    dense tensor with one axis per column."""
     C, d = W.inst.cols, W.inst.d
-    F = W.loc[r, 0].copy()
+    F = W.log_loc[r, 0].copy()
     for c in range(1, C):
-        F = F[..., :, None] * W.h[r, c - 1][(None,) * (c - 1) + (slice(None), slice(None))]
-        F = F * W.loc[r, c][(None,) * c + (slice(None),)]
+        F = F[..., :, None] + W.log_h[r, c - 1][(None,) * (c - 1) + (slice(None), slice(None))]
+        F = F + W.log_loc[r, c][(None,) * c + (slice(None),)]
     return F.reshape((d,) * C)
 
 
-def apply_couplings(W: Weights, r: int, Y: np.ndarray) -> np.ndarray:
-    """sum_Y G_r(X, Y) Phi(Y), with G_r the product of the V, D and A weights
-    between row r (X) and row r+1 (Y).  The sum over Y is done one column at a
-    time; each y_c is summed once all three of its couplings are applied."""
-    C = W.inst.cols
-    T = Y                                           # axes: y_0..y_{C-1}
+def log_apply_couplings(W: Weights, r: int, LY: np.ndarray) -> np.ndarray:
+    """log sum_Y G_r(X, Y) exp(LY(Y)), with G_r the product of the V, D and A
+    weights between row r (X) and row r+1 (Y); LY holds log Phi(Y).  The sum
+    over Y is done one column at a time (log-sum-exp), each y_c summed once
+    all three of its couplings are applied."""
+    C, d = W.inst.cols, W.inst.d
+    T = LY                                          # axes: y_0..y_{C-1}
     for c in range(C):
         # axes now: x_0..x_{c-1}, [y_{c-1}], y_c..y_{C-1}
-        n_x = c
         if c > 0:
             # introduce x_c through A(x_c, y_{c-1}) and sum y_{c-1}
-            T = np.moveaxis(T, n_x, -1)             # y_{c-1} last
-            T = np.tensordot(T, W.an[r, c - 1].T, axes=([T.ndim - 1], [0]))  # -> x_c last
-            T = np.moveaxis(T, -1, n_x)             # x_c at position c
+            T = np.moveaxis(T, c, -1)                # y_{c-1} last
+            T = logsumexp(T[..., None, :] + W.log_an[r, c - 1], axis=-1)   # -> x_c last
+            T = np.moveaxis(T, -1, c)                # x_c at position c
         else:
-            T = T[None]                             # placeholder axis for x_0
-            T = np.repeat(T, W.inst.d, axis=0)
-        # multiply V(x_c, y_c): x_c at axis c, y_c at axis c+1
+            T = np.repeat(T[None], d, axis=0)        # axis for x_0
         shp = [1] * T.ndim
-        shp[c], shp[c + 1] = W.inst.d, W.inst.d
-        T = T * W.v[r, c].reshape(shp)
+        shp[c], shp[c + 1] = d, d
+        T = T + W.log_v[r, c].reshape(shp)           # V(x_c, y_c)
         if c > 0:
-            # D(x_{c-1}, y_c): x_{c-1} at axis c-1, y_c at axis c+1
             shp = [1] * T.ndim
-            shp[c - 1], shp[c + 1] = W.inst.d, W.inst.d
-            T = T * W.dg[r, c - 1].reshape(shp)
-    # last column: y_{C-1} has no pending coupling
-    return T.sum(axis=C)
+            shp[c - 1], shp[c + 1] = d, d
+            T = T + W.log_dg[r, c - 1].reshape(shp)     # D(x_{c-1}, y_c)
+    return logsumexp(T, axis=C)                      # y_{C-1}: no pending coupling
 
 
 def row_transfer(inst, max_row_states: int = 1 << 16) -> tuple:
-    """Exact boundary vectors E~_r(X) for r = rows-1 .. 0 with log-scales.
-
-    E~_{rows-1} = F_{rows-1};  E~_r = F_r * sum_Y G_r(., Y) E~_{r+1}(Y).
-    Returns (list of (vec, logscale) indexed by r, logZ)."""
+    """Exact boundary functions in the log domain (no under- or overflow at
+    any temperature): log E~_{rows-1} = log F_{rows-1} and
+    log E~_r = log F_r + log sum_Y G_r(., Y) E~_{r+1}(Y).
+    Returns (list of dense log E~_r indexed by r, logZ)."""
     W = Weights(inst)
     R, C, d = inst.rows, inst.cols, inst.d
     if d ** C > max_row_states:
         raise ValueError("row too wide for the exact transfer")
     out = [None] * R
-    v = row_factor(W, R - 1)
-    s = float(np.abs(v).max())
-    out[R - 1] = (v / s, np.log(s))
+    out[R - 1] = log_row_factor(W, R - 1)
     for r in range(R - 2, -1, -1):
-        prev, ls = out[r + 1]
-        v = row_factor(W, r) * apply_couplings(W, r, prev)
-        s = float(np.abs(v).max())
-        out[r] = (v / s, ls + np.log(s))
-    v0, l0 = out[0]
-    logZ = float(np.log(v0.sum()) + l0 - inst.beta * W.shift)
+        out[r] = log_row_factor(W, r) + log_apply_couplings(W, r, out[r + 1])
+    logZ = float(logsumexp(out[0]) - inst.beta * W.shift)
     return out, logZ
 
 
-def fields(W: Weights, r: int, above: np.ndarray) -> np.ndarray:
-    """g_c(x) for c = 0..cols-1: the product of the couplings between x = x_{r,c}
-    and the fixed row above (V from (r-1,c), D from (r-1,c-1), A from (r-1,c+1)).
-    All ones for r = 0."""
+def normalised(L: np.ndarray) -> np.ndarray:
+    """A log row function as a dense function with largest entry 1."""
+    return np.exp(L - L.max())
+
+
+def log_fields(W: Weights, r: int, above: np.ndarray) -> np.ndarray:
+    """log g_c(x) for c = 0..cols-1: the couplings between x = x_{r,c} and the
+    fixed row above (V from (r-1,c), D from (r-1,c-1), A from (r-1,c+1)).
+    All zero for r = 0."""
     C, d = W.inst.cols, W.inst.d
-    g = np.ones((C, d))
+    g = np.zeros((C, d))
     if r == 0:
         return g
     for c in range(C):
-        g[c] *= W.v[r - 1, c][above[c], :]
+        g[c] += W.log_v[r - 1, c][above[c], :]
         if c > 0:
-            g[c] *= W.dg[r - 1, c - 1][above[c - 1], :]
+            g[c] += W.log_dg[r - 1, c - 1][above[c - 1], :]
         if c < C - 1:
-            g[c] *= W.an[r - 1, c][above[c + 1], :]
+            g[c] += W.log_an[r - 1, c][above[c + 1], :]
     return g
 
 
-def exact_conditionals(inst, rows_vec, cfg_prefix) -> np.ndarray:
-    """p(x_k = s | x_<k) for the next site k = len(cfg_prefix), from exact E~_r.
+def exact_conditionals(inst, rows_log, cfg_prefix) -> np.ndarray:
+    """p(x_k = s | x_<k) for the next site k = len(cfg_prefix), from the exact
+    log E~_r of ``row_transfer``.
 
     Given rows 0..r-1 fixed and x_{r,0..c-1} fixed, the unnormalised weight of
-    x_{r,c} = s is sum over x_{r,c+1..} of prod_c' g_c'(x_c') E~_r(X_r)."""
+    x_{r,c} = s is sum over x_{r,c+1..} of prod_c' g_c'(x_c') E~_r(X_r)
+    (log-sum-exp)."""
     W = Weights(inst)
     C, d = inst.cols, inst.d
     k = len(cfg_prefix)
     r, c = divmod(k, C)
     above = np.asarray(cfg_prefix[(r - 1) * C: r * C]) if r > 0 else None
-    g = fields(W, r, above)
-    v = rows_vec[r][0]
+    g = log_fields(W, r, above)
+    v = rows_log[r]
     for cc in range(C):
         shp = [1] * C
         shp[cc] = d
-        v = v * g[cc].reshape(shp)
+        v = v + g[cc].reshape(shp)
     for cc in range(c):
         v = v[cfg_prefix[r * C + cc]]
-    q = v.reshape(d, -1).sum(axis=1)
-    return q / q.sum()
+    lq = logsumexp(v.reshape(d, -1), axis=1)
+    return np.exp(lq - logsumexp(lq))

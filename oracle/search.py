@@ -97,8 +97,20 @@ def select_top(scores: np.ndarray, M: int) -> np.ndarray:
 
 
 def marginals(A_rc, g_c, L, R_next):
-    """q[b, s] = g_c[b, s] * sum_{alpha, alpha'} L[b, alpha] A[alpha, s, alpha'] R[b, alpha']."""
-    return g_c * np.einsum("ba,asz,bz->bs", L, A_rc, R_next)
+    """q[b, s] = g_c[b, s] * sum_{alpha, alpha'} L[b, alpha] A[alpha, s, alpha'] R[b, alpha'],
+    summed over alpha' first (one matrix product for all b), then over alpha."""
+    a, d, z = A_rc.shape
+    U = (R_next @ A_rc.reshape(a * d, z).T).reshape(-1, a, d)      # U[b, alpha, s]
+    return g_c * np.einsum("ba,bas->bs", L, U)
+
+
+def left_step(L, A_rc, s):
+    """L[b] A[:, s[b], :] for every b (grouped by the state s[b])."""
+    out = np.empty((L.shape[0], A_rc.shape[2]))
+    for x in np.unique(s):
+        sel = s == x
+        out[sel] = L[sel] @ A_rc[:, x, :]
+    return out
 
 
 def log_conditionals(q: np.ndarray, dE: np.ndarray, beta: float) -> np.ndarray:
@@ -248,7 +260,7 @@ def beam_search(inst, A, M: int, cut_off_prob: float = 0.0, trace=None, merge=Fa
                                          d, droplets)
                          for j in range(len(keep))]
             # L^child = g^b_c(s) * L^b A_{r,c}[:, s, :]
-            Lb = np.einsum("ba,baz->bz", L[b], np.transpose(A[r][c][:, s, :], (1, 0, 2)))
+            Lb = left_step(L[b], A[r][c], s)
             Lb = Lb * g_anc[anc[b], c, s][:, None]
             m = np.abs(Lb).max(axis=1, keepdims=True)
             L = Lb / np.where(m > 0, m, 1.0)
@@ -277,7 +289,7 @@ def teacher_forced_logp(inst, A, r: int, c: int, cfg: np.ndarray) -> np.ndarray:
     L = np.ones((cfg.shape[0], 1))
     for cc in range(c):
         s = cfg[:, r * C + cc]
-        Lb = np.einsum("ba,baz->bz", L, np.transpose(A[r][cc][:, s, :], (1, 0, 2)))
+        Lb = left_step(L, A[r][cc], s)
         Lb = Lb * g[np.arange(cfg.shape[0]), cc, s][:, None]
         m = np.abs(Lb).max(axis=1, keepdims=True)
         L = Lb / np.where(m > 0, m, 1.0)

@@ -152,7 +152,7 @@ struct BmpsWork {
     f(ident, (size_t)lmax * lmax * sizeof(double));
     f(skws, 16 * mn * lmax * sizeof(double));
     f(tmp, site_sz() * sizeof(double));
-    f(logs, (size_t)(2 * C + 8 + R) * sizeof(double));
+    f(logs, (size_t)(2 * C + 8 + 2 * R) * sizeof(double));
     f(psi0, site_sz() * C * sizeof(double));
   }
   void alloc() {
@@ -241,9 +241,11 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
   fill_sketch(chi * d, w.lmax, w.Om.as<double>(), s);
   double *A = env->A.as<double>();
   double *logs = w.logs.as<double>();
-  // log slots: EL[c] at c, ER[c] at C+1+c, centre at 2C+2, lam[r] at 2C+4+r
-  const int sEL = 0, sER = C + 1, sCen = 2 * C + 2, sLam = 2 * C + 4;
-  fill_zero(logs, (size_t)(2 * C + 8 + R), s);
+  // log slots: EL[c] at c, ER[c] at C+1+c, centre at 2C+2, lam[r] at 2C+4+r,
+  // the rows' site scales at 2C+8+R+r
+  const int sEL = 0, sER = C + 1, sCen = 2 * C + 2, sLam = 2 * C + 4, sRsc = 2 * C + 8 + R;
+  fill_zero(logs, (size_t)(2 * C + 8 + 2 * R), s);
+  copy_d2d(logs + sRsc, pp->row_lsc.as<double>(), sizeof(double) * R, s);
   // E~_rows = 1 through the state y = 0 of a bond-1 product MPS
   fill_zero(w.psi0.as<double>(), site * C, s);
   for (int c = 0; c < C; ++c) set_e0(1, 1, w.psi0.as<double>() + c * site, 1, s);
@@ -269,6 +271,7 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
         normalize_box(phi + c * site, bl, d, br, 1, (long)d * chi, chi, 1, 1, logs, sLam + r,
                       c == 0 ? -1 : sLam + r, w.nscr.as<double>(), s);
       }
+      add_logs(logs, sLam + r, sLam + r, sRsc + r, -1, s);   // + the site scales
       for (int c = 0; c <= C; ++c) env->dims[r * (C + 1) + c] = (c == 0 || c == C) ? 1 : d;
       continue;
     }
@@ -289,6 +292,11 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
              w.Rc.as<double>(), w.qrwork.as<double>(), s);                 // Q column-major
       unpack_right(d, chi, bl, br, w.Qc.as<double>(), (long)d * br, 1, phi + c * site, s);
       lq_fold(d, chi, bl, bl, w.Rc.as<double>(), phi + (c - 1) * site, w.tmp.as<double>(), s);
+      // the folded factor only carries the guess's scale, which no later step
+      // uses (phi_0 and phi_1 are overwritten before they are read): unit norm,
+      // so that it cannot overflow over many columns (its log is discarded)
+      normalize_box(phi + (c - 1) * site, fdims[c - 1], d, bl, 1, (long)d * chi, chi, 1, 1, logs,
+                    sCen, -1, w.nscr.as<double>(), s);
     }
     auto build_ER = [&](int c) {
       env_right(d, chi, fdims[c], fdims[c + 1], pdims[c], pdims[c + 1], phi + c * site,
@@ -399,6 +407,7 @@ static void boundary_mps_fp64(spg_env *env, const spg_mps_params *prm, hipStream
       normalize_box(phi, 1, d, fdims[1], 1, (long)d * chi, chi, 1, 1, logs, sCen, -1,
                     w.nscr.as<double>(), s);
     add_logs(logs, sLam + r, bottom ? -1 : sLam + r + 1, (C > 2) ? sER + 2 : -1, sCen, s);
+    add_logs(logs, sLam + r, sLam + r, sRsc + r, -1, s);     // + the site scales
     for (int c = 0; c <= C; ++c) env->dims[r * (C + 1) + c] = fdims[c];
   }
   copy_d2d(env->lam.as<double>(), logs + sLam, sizeof(double) * R, s);
@@ -524,6 +533,14 @@ int spg_build_peps(const spg_instance_desc *desc, void *stream, spg_peps_t **out
     build_weights((R - 1) * (C - 1), (int)dd, pp->beta, pp->E_a.as<double>(), pp->W_a.as<double>(), mn + off, s); off += (size_t)(R - 1) * (C - 1);
     std::vector<double> hm(ntab);
     if (ntab) SPG_HIP(hipMemcpyAsync(hm.data(), mn, ntab * 8, hipMemcpyDeviceToHost, s));
+    // each column's MPO tensor scaled to a largest entry of 1 (the row logs go
+    // to the boundary MPS's log-scales)
+    DevBuf lsc;
+    lsc.ensure((size_t)R * C * 8);
+    pp->row_lsc.ensure((size_t)R * 8);
+    site_scales(R, C, d, pp->W_loc.as<double>(), pp->W_h.as<double>(), pp->W_v.as<double>(),
+                pp->W_d.as<double>(), pp->W_a.as<double>(), lsc.as<double>(),
+                pp->row_lsc.as<double>(), s);
     // constant helper tables
     std::vector<double> ones(dd, 1.0), e0r(dd, 0.0), e0c(dd, 0.0);
     for (int i = 0; i < d; ++i) { e0r[i] = 1.0; e0c[(size_t)i * d] = 1.0; }
@@ -532,6 +549,7 @@ int spg_build_peps(const spg_instance_desc *desc, void *stream, spg_peps_t **out
     up(pp->e0col, e0c.data(), dd);
     SPG_HIP(hipStreamSynchronize(s));
     mins.release();
+    lsc.release();
     double sh = 0.0;
     for (double v : hm) sh += v;
     pp->shift = sh;
@@ -547,7 +565,8 @@ int spg_build_peps(const spg_instance_desc *desc, void *stream, spg_peps_t **out
 void spg_free_peps(spg_peps_t *pp) {
   if (!pp) return;
   for (DevBuf *b : {&pp->E_loc, &pp->E_h, &pp->E_v, &pp->E_d, &pp->E_a, &pp->W_loc, &pp->W_h,
-                    &pp->W_v, &pp->W_d, &pp->W_a, &pp->ones, &pp->e0row, &pp->e0col, &pp->e0vec})
+                    &pp->W_v, &pp->W_d, &pp->W_a, &pp->ones, &pp->e0row, &pp->e0col, &pp->e0vec,
+                    &pp->row_lsc})
     b->release();
   delete pp;
 }
@@ -1571,10 +1590,12 @@ static size_t build_class(BatchClass &k, const std::vector<const spg_peps *> &sr
   spg_peps *pk = &k.peps;
   const DevBuf *srcb[] = {&p0->E_loc, &p0->E_h, &p0->E_v, &p0->E_d, &p0->E_a, &p0->W_loc,
                           &p0->W_h, &p0->W_v, &p0->W_d, &p0->W_a, &p0->ones, &p0->e0row,
-                          &p0->e0col, &p0->e0vec};
+                          &p0->e0col, &p0->e0vec, &p0->row_lsc};
   DevBuf *dstb[] = {&pk->E_loc, &pk->E_h, &pk->E_v, &pk->E_d, &pk->E_a, &pk->W_loc, &pk->W_h,
-                    &pk->W_v, &pk->W_d, &pk->W_a, &pk->ones, &pk->e0row, &pk->e0col, &pk->e0vec};
-  for (int t = 0; t < 14; ++t) add(*dstb[t], srcb[t]->bytes);
+                    &pk->W_v, &pk->W_d, &pk->W_a, &pk->ones, &pk->e0row, &pk->e0col, &pk->e0vec,
+                    &pk->row_lsc};
+  constexpr int kPepsBufs = 15;
+  for (int t = 0; t < kPepsBufs; ++t) add(*dstb[t], srcb[t]->bytes);
   add(k.env.A, (size_t)R * C * chi * d * chi * sizeof(double));
   add(k.env.lam, (size_t)R * sizeof(double));
   each_search_buffer(&k.env, M, add);
@@ -1603,8 +1624,8 @@ static size_t build_class(BatchClass &k, const std::vector<const spg_peps *> &sr
     const spg_peps *pm = src[k.members[m]];
     const DevBuf *sb[] = {&pm->E_loc, &pm->E_h, &pm->E_v, &pm->E_d, &pm->E_a, &pm->W_loc,
                           &pm->W_h, &pm->W_v, &pm->W_d, &pm->W_a, &pm->ones, &pm->e0row,
-                          &pm->e0col, &pm->e0vec};
-    for (int t = 0; t < 14; ++t)
+                          &pm->e0col, &pm->e0vec, &pm->row_lsc};
+    for (int t = 0; t < kPepsBufs; ++t)
       if (sb[t]->bytes)
         SPG_HIP(hipMemcpy(base + (size_t)m * tot + off[t], sb[t]->p, sb[t]->bytes,
                           hipMemcpyDeviceToDevice));

@@ -80,6 +80,69 @@ __global__ void k_bottom_row(int C, int d, int chi, const double *w, const doubl
   A[e] = v;
 }
 
+// Largest entry of each column's MPO tensor,
+//   max over (a, e, x, y) of w(x) V(x, y) H(a, x) D(a, y) A(x, e)
+//   = max over (x, y) of w(x) V(x, y) max_a [H(a, x) D(a, y)] max_e A(x, e),
+// in logs, one workgroup per site (r, c); the site's w is then divided by it
+// (in place) and the log written to lsc.  The tables are the ones the MPO
+// kernels read: V, D, A are ones on the bottom row; column 0 has no left
+// neighbour (H, D through a = 0 and A through e = 0 only).
+__global__ __launch_bounds__(256) void k_site_scale(int R, int C, int d, double *W_loc,
+                                                    const double *W_h, const double *W_v,
+                                                    const double *W_d, const double *W_a,
+                                                    double *lsc, long ist) {
+  SPG_INST(W_loc);
+  SPG_INST(W_h);
+  SPG_INST(W_v);
+  SPG_INST(W_d);
+  SPG_INST(W_a);
+  SPG_INST(lsc);
+  __shared__ double part[4];
+  const int site = blockIdx.x, r = site / C, c = site % C;
+  const bool bottom = (r == R - 1);
+  const long dd = (long)d * d;
+  double *w = W_loc + (long)site * d;
+  const double *V = bottom ? nullptr : W_v + ((long)r * C + c) * dd;
+  const double *H = c > 0 ? W_h + ((long)r * (C - 1) + c - 1) * dd : nullptr;
+  const double *D = (c > 0 && !bottom) ? W_d + ((long)r * (C - 1) + c - 1) * dd : nullptr;
+  const double *A = (c > 0 && !bottom) ? W_a + ((long)r * (C - 1) + c - 1) * dd : nullptr;
+  const int na = c > 0 ? d : 1;
+  double best = -INFINITY;
+  for (int p = threadIdx.x; p < d * d; p += blockDim.x) {
+    const int x = p / d, y = p - x * d;
+    double m1 = -INFINITY;
+    for (int a = 0; a < na; ++a) {
+      const double h = H ? log(H[(long)a * d + x]) : 0.0;
+      const double g = D ? log(D[(long)a * d + y]) : 0.0;
+      m1 = fmax(m1, h + g);
+    }
+    double m2 = 0.0;
+    if (A) {
+      m2 = -INFINITY;
+      for (int e = 0; e < d; ++e) m2 = fmax(m2, log(A[(long)x * d + e]));
+    }
+    best = fmax(best, log(w[x]) + (V ? log(V[(long)x * d + y]) : 0.0) + m1 + m2);
+  }
+  for (int o = 32; o > 0; o >>= 1) best = fmax(best, __shfl_xor(best, o, 64));
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = best;
+  __syncthreads();
+  double ls = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
+  if (!(ls > -INFINITY) || !(ls < INFINITY)) ls = 0.0;     // an all-zero tensor stays as it is
+  for (int x = threadIdx.x; x < d; x += blockDim.x) w[x] *= exp(-ls);
+  if (threadIdx.x == 0) lsc[site] = ls;
+}
+
+// row_lsc[r] = sum over c of lsc[r * C + c], in column order
+__global__ void k_row_lsc(int R, int C, const double *lsc, double *row_lsc, long ist) {
+  SPG_INST(lsc);
+  SPG_INST(row_lsc);
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double t = 0.0;
+  for (int c = 0; c < C; ++c) t += lsc[(long)r * C + c];
+  row_lsc[r] = t;
+}
+
 // T1[p][a][x][q] = sum_e Al[x][e] EL[p][a][e][q]
 __global__ void k_T1(int d, int chi, int pl, int ql, const double *EL, const double *Al,
                      double *T1, long ist) {
@@ -439,6 +502,22 @@ void build_weights(int ntab, int tsize, double beta, const double *E, double *W,
   SPG_BC(W);
   SPG_BC(mins);
   hipLaunchKernelGGL(k_weights, dim3(ntab, g_bc.n), dim3(256), 0, s, ntab, tsize, beta, E, W, mins, g_bc.ist);
+  SPG_CHECK_LAUNCH();
+}
+
+void site_scales(int R, int C, int d, double *W_loc, const double *W_h, const double *W_v,
+                 const double *W_d, const double *W_a, double *lsc, double *row_lsc,
+                 hipStream_t s) {
+  SPG_BC(W_loc);
+  SPG_BC(W_h);
+  SPG_BC(W_v);
+  SPG_BC(W_d);
+  SPG_BC(W_a);
+  SPG_BC(lsc);
+  SPG_BC(row_lsc);
+  hipLaunchKernelGGL(k_site_scale, dim3(R * C, g_bc.n), dim3(256), 0, s, R, C, d, W_loc, W_h, W_v, W_d, W_a, lsc, g_bc.ist);
+  SPG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_row_lsc, dim3(nblk(R, 64), g_bc.n), dim3(64), 0, s, R, C, lsc, row_lsc, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 

@@ -24,6 +24,38 @@ __device__ double block_sum(double v, double *red) {
   return t;
 }
 
+// Block-wide maximum of non-negative values; every thread receives it.
+__device__ double block_max_nonneg(double v, double *red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = wave_max_nonneg(v);
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t = fmax(t, red[w]);
+  return t;
+}
+
+// Squared tail norms below this lose digits to subnormal squares: the tail is
+// then summed again divided by its largest entry (a column's tail shrinks to
+// the rounding floor of the panel after a few reflections on graded panels).
+constexpr double kTinySq = 1e-280;
+
+// Householder reflector of a column with head al and tail x_i: the tail's
+// squared norm is am^2 sg (sg summed from x_i / am; am = 1 on the plain
+// path).  H = I - tau v v^T with v = 1 at the head and sc x_i below, R = beta.
+__device__ __forceinline__ void householder(double al, double sg, double am, double &tj,
+                                            double &sc, double &beta) {
+  tj = 0.0; sc = 0.0; beta = al;
+  if (sg != 0.0) {
+    const double a = al / am;
+    const double nrm = am * sqrt(a * a + sg);
+    beta = (al >= 0.0) ? -nrm : nrm;
+    tj = (beta - al) / beta;
+    sc = 1.0 / (al - beta);
+  }
+}
+
 // ---------------------------------------------------------------- GEMM
 // TILE x TILE output tile per 256-thread workgroup (TILE = 64 or 32), K staged
 // through LDS in steps of kGemmKs (all of a step's loads are in flight at
@@ -199,18 +231,24 @@ __global__ __launch_bounds__(1024) void k_qr(int m, int n, const double *X, long
     double *col = W + (size_t)j * m;
     double loc = 0.0;
     for (int i = j + 1 + tid; i < m; i += blockDim.x) loc += col[i] * col[i];
-    const double sig = block_sum(loc, red);
+    double sig = block_sum(loc, red), am = 1.0;
+    if (sig < kTinySq) {                         // uniform: every thread holds sig
+      double mx = 0.0;
+      for (int i = j + 1 + tid; i < m; i += blockDim.x) mx = fmax(mx, fabs(col[i]));
+      am = block_max_nonneg(mx, red);
+      loc = 0.0;
+      if (am > 0.0)
+        for (int i = j + 1 + tid; i < m; i += blockDim.x) {
+          const double x = col[i] / am;
+          loc += x * x;
+        }
+      sig = block_sum(loc, red);
+      if (am == 0.0) am = 1.0;
+    }
     if (tid == 0) {
-      const double alpha = col[j];
-      if (sig == 0.0) {
-        sh_tau = 0.0; sh_scale = 0.0; sh_beta = alpha;
-      } else {
-        const double nrm = sqrt(alpha * alpha + sig);
-        const double beta = (alpha >= 0.0) ? -nrm : nrm;
-        sh_tau = (beta - alpha) / beta;
-        sh_scale = 1.0 / (alpha - beta);
-        sh_beta = beta;
-      }
+      double t, sc, b;
+      householder(col[j], sig, am, t, sc, b);
+      sh_tau = t; sh_scale = sc; sh_beta = b;
     }
     __syncthreads();
     const double tj = sh_tau, sc = sh_scale;
@@ -284,6 +322,7 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
   __shared__ double W[kQrLds];
   __shared__ double tau[kMaxSketch + 32];
   __shared__ double sig2[kMaxSketch + 32];   // |column j below the diagonal|^2 before step j
+  __shared__ double sam[kMaxSketch + 32];    // its scale: sig2 sums (x / sam)^2
   __shared__ double red[16];
   const int tid = threadIdx.x;
   const int grp = tid >> 6, l16 = tid & 63, ngrp = blockDim.x >> 6;
@@ -298,21 +337,30 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
   {
     double loc = 0.0;
     for (int i = 1 + tid; i < ld; i += blockDim.x) loc += W[i] * W[i];
-    const double t = block_sum(loc, red);
-    if (tid == 0) sig2[0] = t;
+    double t = block_sum(loc, red), am = 1.0;
+    if (t < kTinySq) {
+      double mx = 0.0;
+      for (int i = 1 + tid; i < ld; i += blockDim.x) mx = fmax(mx, fabs(W[i]));
+      am = block_max_nonneg(mx, red);
+      loc = 0.0;
+      if (am > 0.0)
+        for (int i = 1 + tid; i < ld; i += blockDim.x) {
+          const double x = W[i] / am;
+          loc += x * x;
+        }
+      t = block_sum(loc, red);
+      if (am == 0.0) am = 1.0;
+    }
+    if (tid == 0) {
+      sig2[0] = t;
+      sam[0] = am;
+    }
   }
   __syncthreads();
   // reflector of column j from its raw entries: H_j = I - tau v v^T with
   // v_j = 1, v_i = scale * col[i] (i > j), and R[j][j] = beta
   auto reflector = [&](int j, double &tj, double &sc, double &beta) {
-    const double sg = sig2[j], alpha = W[j * ld + j];
-    tj = 0.0; sc = 0.0; beta = alpha;
-    if (sg != 0.0) {
-      const double nrm = sqrt(alpha * alpha + sg);
-      beta = (alpha >= 0.0) ? -nrm : nrm;
-      tj = (beta - alpha) / beta;
-      sc = 1.0 / (alpha - beta);
-    }
+    householder(W[j * ld + j], sig2[j], sam[j], tj, sc, beta);
   };
   for (int j = 0; j < n; ++j) {
     double tj, sc, beta;
@@ -329,10 +377,26 @@ __global__ __launch_bounds__(1024) void k_qr_lds(int m, int n, int mb, const dou
         for (int i = j + 1 + l16; i < ld; i += 64) ck[i] -= fs * col[i];
       }
       if (k == j + 1) {
-        double a = 0.0;
+        double a = 0.0, am = 1.0;
         for (int i = j + 2 + l16; i < ld; i += 64) a += ck[i] * ck[i];
         a = wave_sum(a);
-        if (l16 == 0) sig2[j + 1] = a;
+        if (a < kTinySq) {
+          double mx = 0.0;
+          for (int i = j + 2 + l16; i < ld; i += 64) mx = fmax(mx, fabs(ck[i]));
+          am = wave_max_nonneg(mx);
+          a = 0.0;
+          if (am > 0.0)
+            for (int i = j + 2 + l16; i < ld; i += 64) {
+              const double x = ck[i] / am;
+              a += x * x;
+            }
+          a = wave_sum(a);
+          if (am == 0.0) am = 1.0;
+        }
+        if (l16 == 0) {
+          sig2[j + 1] = a;
+          sam[j + 1] = am;
+        }
       }
     }
     // finalise column j - 1 (nobody reads it any more)
@@ -546,13 +610,27 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, 
     }
     sg = wave_sum(sg);
     const double al = read_lane(at, jj & 63);
-    double tj = 0.0, sc = 0.0, beta = al;
-    if (sg != 0.0) {
-      const double nrm = sqrt(al * al + sg);
-      beta = (al >= 0.0) ? -nrm : nrm;
-      tj = (beta - al) / beta;
-      sc = 1.0 / (al - beta);
+    double am = 1.0;
+    if (sg < kTinySq) {                          // uniform over the wavefront
+      double mx = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t)
+        if (lane + 64 * t > jj) mx = fmax(mx, fabs(col[t]));
+      am = wave_max_nonneg(mx);
+      sg = 0.0;
+      if (am > 0.0) {
+#pragma unroll
+        for (int t = 0; t < RPL; ++t)
+          if (lane + 64 * t > jj) {
+            const double x = col[t] / am;
+            sg = fma(x, x, sg);
+          }
+      }
+      sg = wave_sum(sg);
+      if (am == 0.0) am = 1.0;
     }
+    double tj, sc, beta;
+    householder(al, sg, am, tj, sc, beta);
     double *vs = buf + (jj % kRegSlots) * (64 * RPL);
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {

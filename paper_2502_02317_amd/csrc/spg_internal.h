@@ -147,6 +147,14 @@ struct RowFactors {         // device d x d tables (row-major) / d vectors of on
   const double *Hl, *Dl, *Al;  // H_{c-1}[a][x], D_{c-1}[a][y], A_{c-1}[x][e]
   const double *ones;          // d x d ones (an epilogue factor of 1 per row)
 };
+// Each column's MPO tensor scaled to a largest entry of 1: W_loc[r][c][.] is
+// divided in place by that entry (its log to lsc[r * C + c]), and row_lsc[r]
+// receives the sum of the row's logs.  Products of tables that are each at
+// most 1 fall far below 1 where the tables peak apart; this keeps the blocks
+// of the contraction from underflowing.
+void site_scales(int R, int C, int d, double *W_loc, const double *W_h, const double *W_v,
+                 const double *W_d, const double *W_a, double *lsc, double *row_lsc,
+                 hipStream_t s);
 // The bottom row's boundary function written exactly (bond d, x_c on the
 // bond): all C padded site tensors of the row at A.  w = W_loc of the row,
 // H = W_h of the row.
@@ -326,6 +334,8 @@ struct spg_peps {
   int device = 0;
   spg::DevBuf E_loc, E_h, E_v, E_d, E_a;   // energies (zero tables for absent classes)
   spg::DevBuf W_loc, W_h, W_v, W_d, W_a;   // Boltzmann weights of the min-shifted tables
+                                           // (W_loc divided by the site scales below)
+  spg::DevBuf row_lsc;                     // [rows] sum of the log site scales of each row
   spg::DevBuf ones, e0row, e0col, e0vec;   // d x d all-ones, first row / column ones; e_0
 };
 

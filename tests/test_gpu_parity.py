@@ -100,8 +100,9 @@ def test_truncated_bmps_matches_oracle(chi, sweeps, p, q):
 
 @pytest.mark.parametrize("shape", [(4, 3, 4, 2.0, ("pm1", 1.0), None, 16),
                                    (8, 3, 4, 2.0, ("pm1", 1.0), None, 16),
-                                   (12, 2, 8, 4.0, ("normal", 1.0), 24, 64)],
-                         ids=["4x3_d16", "8x3_d16", "12x2_d24"])
+                                   (12, 2, 8, 4.0, ("normal", 1.0), 24, 64),
+                                   (8, 3, 8, 4.0, ("normal", 1.0), 24, 64)],
+                         ids=["4x3_d16", "8x3_d16", "12x2_d24", "8x3_d24"])
 def test_strips_exact_rank_vs_row_transfer(shape):
     """King's strips at the workloads' d and beta with chi at the exact rank:
     the GPU keeps the natural basis on every cut (nothing to truncate), so its

@@ -2,7 +2,7 @@
 import numpy as np
 
 from workloads import spin_instance, potts_from_spins, random_potts
-from oracle.exact import row_transfer
+from oracle.exact import row_transfer, normalised
 from oracle.bmps import boundary_mps, mps_full
 
 
@@ -24,7 +24,7 @@ def test_canonical_form_and_normalised():
     assert [a.shape for a in bottom] == [(1, 3, 3)] + [(3, 3, 3)] * 3 + [(3, 3, 1)]
     assert all((a >= 0).all() for a in bottom)
     rows, _ = row_transfer(inst)
-    ex = rows[-1][0]
+    ex = normalised(rows[-1])
     ap = mps_full(bottom)
     np.testing.assert_allclose(ap / ap.max(), ex / ex.max(), rtol=1e-13)
     for row in mp["A"][:-1]:
@@ -48,7 +48,8 @@ def test_truncation_error_falls_with_chi():
         mp = boundary_mps(inst, chi=chi)
         e = 0.0
         for r in range(inst.rows):
-            ex = rows[r][0] / np.linalg.norm(rows[r][0])
+            ex = normalised(rows[r])
+            ex = ex / np.linalg.norm(ex)
             ap = mps_full(mp["A"][r])
             e = max(e, np.linalg.norm(ex - ap / np.linalg.norm(ap) * np.sign(ap.sum())))
         errs.append(e)

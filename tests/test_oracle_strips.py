@@ -1,9 +1,11 @@
 """Exact row transfer against the oracle's boundary MPS on king's strips with
 the workloads' local dimension and temperature (CPU only).
 
-On a strip of cols = 3 and d = 16 every boundary cut has at most d^1 = 16
-states on one side, so chi = 16 is the exact rank; on cols = 2 a single cut
-of d states.  There the boundary MPS represents every row function exactly,
+On a strip of cols = 3 every boundary cut has at most d states on one side,
+so chi >= d is the exact rank (chi = 16 at d = 16, chi = 64 at d = 24); on
+cols = 2 a single cut of d states.  The d = 24, beta = 4 strips (8-spin
+clusters, the 24 lowest states) are the ones whose blocks underflowed before
+each column's MPO tensor was scaled to a largest entry of 1.  There the boundary MPS represents every row function exactly,
 and the branch-and-bound conditionals must equal the exact ones
 p(x_k | x_<k) = P(x_<=k) / P(x_<k) (the paper's marginals, Sec. 2, computed
 from dense row vectors).  Tolerances: log Z to 1e-10 relative, and every
@@ -27,6 +29,7 @@ STRIPS = [
     (6, 3, 4, 2.0, ("pm1", 1.0), None, 16),
     (8, 3, 4, 2.0, ("pm1", 1.0), None, 16),
     (12, 2, 8, 4.0, ("normal", 1.0), 24, 64),
+    (8, 3, 8, 4.0, ("normal", 1.0), 24, 64),
 ]
 
 
