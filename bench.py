@@ -10,10 +10,11 @@ Metric: conditional-marginal evaluations per second, one evaluation being one
 resolved candidate (beam state b, local state s) at one site, so a step does
 sum_k min(M, d^k) * d of them.  ``value`` is evaluations / wall time of the
 whole step (inputs already on the host; the PEPS build copies them over) for
-the mixed path (search contractions in FP32, boundary MPS in FP64); the FP64
-plain path is timed on the same workload and reported beside it, together with
-dlogP, the largest |log p_mixed - log p_fp64| teacher-forced on the FP64
-path's beam over states with p >= 1e-4 of the best at their parent.
+the plain path, every contraction in FP64; the mixed path (search contractions
+in FP32 or with BF16 inputs, boundary MPS in FP64) is timed on the same
+workload and reported beside it, together with dlogP, the largest
+|log p_mixed - log p_fp64| teacher-forced on the FP64 path's beam over states
+with p >= 1e-4 of the best at their parent.
 
 The JSON line also carries the roofline of the dominant kernel class (HIP
 events on its launch stream over the timed region, algorithmic work counted by
@@ -324,6 +325,55 @@ def transforms_leg(spg, torch, inst, wl, M, stream):
             "spread": (max(found) - min(found)) if found else None}
 
 
+def kings12_leg(spg, torch, stream):
+    """The 12x12 king's workload with d = 24 (8-spin clusters, the 24 lowest
+    states), beta = 4, chi = 64, beam 4096: boundary MPS in FP64, then the search
+    in FP64 and with FP32 / BF16-input contractions on that boundary MPS;
+    search-only times, best energies, and the contraction's validity."""
+    import numpy as np
+    from workloads import config_instance
+    inst = config_instance("kings12x12_d24", 0)
+    chi, M = 64, 4096
+    R, C, d = inst.rows, inst.cols, inst.d
+    N = R * C
+    ev = evals_per_step(R, C, d, M)
+    dev = torch.device("cuda:0")
+    st = torch.zeros((M, N), dtype=torch.int32, device=dev)
+    en = torch.zeros(M, dtype=torch.float64, device=dev)
+    lp = torch.zeros(M, dtype=torch.float64, device=dev)
+    peps = spg.build_peps(inst, stream)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    env, _ = spg.boundary_mps(peps, chi, stream=stream, want_logZ=False)
+    torch.cuda.synchronize()
+    bmps_s = time.perf_counter() - a
+    try:
+        _, lz = spg.boundary_mps(peps, chi, stream=stream)
+    except spg.SpgError:
+        lz = None
+    T, _ = spg.env_export(env)
+    sums = row_sums(spg.unpack_mps(T, spg.env_info(env).bond_dims))
+    out = {"workload": "kings12x12_d24 beta=4 chi=64 M=4096 (seed 0)", "evals_per_search": ev,
+           "boundary_mps_s": bmps_s, "logZ": finite_or_none(lz),
+           "rows_with_nonpositive_sum": [r for r, v in enumerate(sums) if not v > 0]}
+    for prec in ("fp64", "fp32", "bf16"):
+        e = env if prec == "fp64" else spg.env_import(
+            peps, chi, spg.env_info(env).bond_dims, T, np.zeros(R), precision=prec,
+            stream=stream)
+        spg.branch_and_bound(e, M, st, en, lp, stream=stream)      # warm
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        n = spg.branch_and_bound(e, M, st, en, lp, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - a) * 1e3
+        out[f"search_ms_{prec}"] = ms
+        out[f"search_evals_per_s_{prec}"] = ev / (ms * 1e-3)
+        out[f"n_states_{prec}"] = n
+        out[f"best_energy_{prec}"] = float(en[0]) if n > 0 else None
+    out["search_speedup_fp32_vs_fp64"] = out["search_ms_fp64"] / out["search_ms_fp32"]
+    return out
+
+
 def merge_leg(spg, torch, inst, wl, M, st, en, lp, stream):
     """Merging branches with equal frontiers: the FP64 search on the same
     boundary MPS with and without it, and with droplets collected while
@@ -437,44 +487,59 @@ def main():
         return (t1 - t0) * 1e3 / args.steps, prof
 
     ev = evals_per_step(R, C, d, M)
-    # the mixed path (the precision form) and the FP64 plain path, same workload,
-    # timed without per-kernel events; then the kernel classes from a separate
+    # the FP64 plain path (the value) and the mixed path (the precision form:
+    # FP32 or BF16-input search contractions), same workload, timed without
+    # per-kernel events; then the kernel classes of each from a separate
     # profiled pass (events on each launch's stream) over the same number of steps
-    ms = timed(args.precision, False)[0]
-    say(f"timed {args.precision}: {ms:.1f} ms/step")
-    ms64 = ms if args.precision == "fp64" else timed("fp64", False)[0]
+    mixed = args.precision != "fp64"
+    ms = timed("fp64", False)[0]
+    say(f"timed fp64: {ms:.1f} ms/step")
+    msmix = timed(args.precision, False)[0] if mixed else ms
     if args.no_kernel_timing:
         prof = {k: (0, 0.0, 0.0) for k in spg.KERNEL_CLASSES}
+        prof_mix = prof
     else:
-        _, prof = timed(args.precision, True)
-        say("profiled pass done")
-    env_last, n_last = step(args.precision)
+        _, prof = timed("fp64", True)
+        prof_mix = timed(args.precision, True)[1] if mixed else prof
+        say("profiled passes done")
+    env_last, n_last = step("fp64")
     dims_last = spg.env_info(env_last).bond_dims.reshape(R, C + 1)
     best_E = float(en[0]) if n_last > 0 else None     # None: the beam ended with no finite state
+    _, n_mix = step(args.precision)
+    best_E_mix = float(en[0]) if n_mix > 0 else None
 
-    # search-only and boundary-MPS-only split (untimed, same work)
+    # search-only and boundary-MPS-only split of the FP64 path (untimed, same work)
     peps = spg.build_peps(inst, stream)
     torch.cuda.synchronize()
     a = time.perf_counter()
-    env, _ = spg.boundary_mps(peps, wl["chi"], num_sweeps=wl["num_sweeps"], precision=args.precision,
-                              oversample=wl["oversample"], power_iters=wl["power_iters"],
-                              stream=stream, want_logZ=False)
+    env64, _ = spg.boundary_mps(peps, wl["chi"], num_sweeps=wl["num_sweeps"], precision="fp64",
+                                oversample=wl["oversample"], power_iters=wl["power_iters"],
+                                stream=stream, want_logZ=False)
     torch.cuda.synchronize()
     b = time.perf_counter()
-    spg.branch_and_bound(env, M, st, en, lp, stream=stream)
+    spg.branch_and_bound(env64, M, st, en, lp, stream=stream)
     torch.cuda.synchronize()
     c = time.perf_counter()
+    env = env64
+    search_ms_mix = None
+    if mixed:
+        env, _ = spg.boundary_mps(peps, wl["chi"], num_sweeps=wl["num_sweeps"],
+                                  precision=args.precision, oversample=wl["oversample"],
+                                  power_iters=wl["power_iters"], stream=stream, want_logZ=False)
+        spg.branch_and_bound(env, M, st, en, lp, stream=stream)
+        torch.cuda.synchronize()
+        a2 = time.perf_counter()
+        spg.branch_and_bound(env, M, st, en, lp, stream=stream)
+        torch.cuda.synchronize()
+        search_ms_mix = (time.perf_counter() - a2) * 1e3
 
     # dlogP: teacher-forced on the FP64 path's beam (the oracle's search on the
     # GPU's FP64 boundary MPS gives that beam), states with p64 >= 1e-4 max
     say("split done")
     dlogp = None
     dlogp_info = None
-    if args.precision != "fp64":
+    if mixed:
         from oracle.search import beam_search, teacher_forced_condition
-        env64, _ = spg.boundary_mps(peps, wl["chi"], num_sweeps=wl["num_sweeps"], precision="fp64",
-                                    oversample=wl["oversample"], power_iters=wl["power_iters"],
-                                    stream=stream, want_logZ=False)
         T, _lam = spg.env_export(env64)
         rows = spg.unpack_mps(T, spg.env_info(env64).bond_dims)
         trace = []
@@ -542,8 +607,8 @@ def main():
     # the matrix-core product of the reduced-precision search (U = R A^T over
     # all ancestors of a row), against the dense MFMA peak of its input type
     mfma = None
-    if args.precision != "fp64" and prof.get("u_mfma", (0, 0.0, 0.0))[1] > 0.0:
-        mc, mt, mw = prof["u_mfma"]
+    if mixed and prof_mix.get("u_mfma", (0, 0.0, 0.0))[1] > 0.0:
+        mc, mt, mw = prof_mix["u_mfma"]
         ach = mw / (mt * 1e-3) / 1e12
         mfma = {"kernel": "k_u_mfma<float>" if args.precision == "fp32"
                 else "k_u_mfma<unsigned short>",
@@ -554,46 +619,55 @@ def main():
                 "avg_launch_us": mt * 1e3 / max(mc, 1)}
 
     # the metric's contraction TFLOP/s: formula flops over summed kernel time
-    # (profiled pass), for the search contractions and for the boundary MPS
+    # (profiled passes), for the search contractions (FP64 path and mixed
+    # path) and for the boundary MPS
     search_cls = ("right_env", "marginals", "beam_update", "u_mfma")
     bmps_cls = ("gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box")
-    s_ms = sum(prof[k][1] for k in search_cls if k in prof) / args.steps
-    b_ms = sum(prof[k][1] for k in bmps_cls if k in prof) / args.steps
     s_fl = search_formula_flops(dims_last, R, C, d, M)
+    b_ms = sum(prof[k][1] for k in bmps_cls if k in prof) / args.steps
     b_fl = (prof["gemm_f64"][2] + prof["qr_f64"][2]) / args.steps
+
+    def search_rate(pr, precision):
+        sm = sum(pr[k][1] for k in search_cls if k in pr) / args.steps
+        return {"formula_flops": s_fl, "kernel_ms": sm,
+                "tflops": s_fl / (sm * 1e-3) / 1e12 if sm > 0 else None, "precision": precision}
+
     contraction = {
-        "search": {"formula_flops": s_fl, "kernel_ms": s_ms,
-                   "tflops": s_fl / (s_ms * 1e-3) / 1e12 if s_ms > 0 else None,
-                   "precision": args.precision},
+        "search": search_rate(prof, "fp64"),
+        "search_mixed": search_rate(prof_mix, args.precision) if mixed else None,
         "boundary_mps": {"gemm_qr_flops": b_fl, "kernel_ms": b_ms,
                          "tflops": b_fl / (b_ms * 1e-3) / 1e12 if b_ms > 0 else None,
                          "precision": "fp64"}}
 
-    dt = {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16"}[args.precision]
     out = {
         "metric": "conditional-marginal evals/s", "value": ev / (ms * 1e-3), "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "kings8x8_d16 beta=2 chi=32 M=1024 (seed 0)", "rows": R, "cols": C,
                    "d": d, "chi": wl["chi"], "max_states": M, "num_sweeps": wl["num_sweeps"],
-                   "evals_per_step": ev, "search_precision": args.precision,
+                   "evals_per_step": ev, "search_precision": "fp64",
                    "boundary_mps_precision": "fp64"},
-        "fp64_plain": {"value": ev / (ms64 * 1e-3), "ms_per_step": ms64},
-        "dlogP": dlogp,
-        "dlogP_coverage": dlogp_info,
+        "mixed": {"value": ev / (msmix * 1e-3), "ms_per_step": msmix,
+                  "dtype": {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16"}[args.precision],
+                  "search_precision": args.precision, "search_ms": search_ms_mix,
+                  "search_speedup_vs_fp64": ((c - b) * 1e3 / search_ms_mix
+                                             if search_ms_mix else None),
+                  "dlogP": dlogp, "dlogP_coverage": dlogp_info, "best_energy": best_E_mix,
+                  "matrix_cores": mfma},
         "best_energy": best_E,
         "split": {"boundary_mps_ms": (b - a) * 1e3, "search_ms": (c - b) * 1e3,
                   "search_evals_per_s": ev / (c - b)},
         "kernels": {k: {"launches": v[0], "ms": v[1], "work": v[2]} for k, v in prof.items()},
         "roofline": roof,
-        "matrix_cores": mfma,
         "contraction_tflops": contraction,
     }
     if not args.no_forms:
         out["forms"] = {"learned_proposal": proposal_leg(spg, torch, inst, wl, M, st, en, lp,
                                                          stream),
                         "batching": batching_leg(spg, torch, stream)}
+        say("kings12x12_d24")
+        out["kings12x12_d24"] = kings12_leg(spg, torch, stream)
         out["extensions"] = {"lattice_transforms": transforms_leg(spg, torch, inst, wl, M,
                                                                   stream),
                              "merge_branches": merge_leg(spg, torch, inst, wl, M, st, en, lp,
