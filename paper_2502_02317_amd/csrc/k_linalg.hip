@@ -523,12 +523,21 @@ __device__ __forceinline__ void wave_sums(const double (&d)[CPW], double (&out)[
 }
 
 template <int RPL, int CPW>
-__global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, const double *X, long xr, long xc,
-                                                double *Qo, long qr, long qc, double *Rs,
+__global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int mb, const double *X, long xr,
+                                                long xc, double *Qo, long qr, long qc, double *Rs,
                                                 int want_q, long ist) {
   SPG_INST(X);
   SPG_INST(Qo);
   SPG_INST(Rs);
+  // workgroup x factorises rows [x mb, min(m, (x+1) mb)) (one TSQR block;
+  // mb = m for a single panel): its Q rows and its own n x n R
+  {
+    const int r0 = blockIdx.x * mb;
+    m = min(mb, m - r0);
+    X += (long)r0 * xr;
+    if (Qo) Qo += (long)r0 * qr;
+    if (Rs) Rs += (long)blockIdx.x * n * n;
+  }
   __shared__ double buf[QrRegLds<RPL, CPW>::kBuf];
   __shared__ double taus[16 * CPW];
   __shared__ double red[16];
@@ -1015,7 +1024,12 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
         }
         __syncthreads();
         const double nv = sh_nv;
-        if (nv > 0.5 || cand >= l - 1) {
+        // after two Gram-Schmidt passes a remainder of norm 1e-3 is orthogonal
+        // to the earlier columns to ~u / 1e-3; below that, try the next unit
+        // vector (the columns at the rounding floor are noise whose
+        // remainders after ~60 projections are ~0.4: a stricter bound sent
+        // most of them to the unit-vector loop)
+        if (nv > 1e-3 || cand >= l - 1) {
           const double inv = (nv > 0.0) ? 1.0 / nv : 0.0;
           for (int r = tid; r < l; r += blockDim.x) V[i * l + r] *= inv;
           __syncthreads();
@@ -1227,13 +1241,13 @@ size_t qr_work_doubles(int m, int n) {
 constexpr int kQrRegRows = 512, kQrRegCols = 80;
 
 template <int RPL>
-static void qr_reg_rows(int cpw, int m, int n, const double *X, long xr, long xc, double *Q,
-                        long qr, long qc, double *R, int want_q, dim3 grid, long ist,
+static void qr_reg_rows(int cpw, int m, int n, int mb, const double *X, long xr, long xc,
+                        double *Q, long qr, long qc, double *R, int want_q, dim3 grid, long ist,
                         hipStream_t s) {
 #define SPG_QR_REG(C)                                                                         \
   case C:                                                                                      \
-    hipLaunchKernelGGL((k_qr_reg<RPL, C>), grid, dim3(1024), 0, s, m, n, X, xr, xc, Q, qr, qc, \
-                       R, want_q, ist);                                                        \
+    hipLaunchKernelGGL((k_qr_reg<RPL, C>), grid, dim3(1024), 0, s, m, n, mb, X, xr, xc, Q, qr, \
+                       qc, R, want_q, ist);                                                    \
     break;
   switch (cpw) {
     SPG_QR_REG(1)
@@ -1249,13 +1263,15 @@ static void qr_reg_rows(int cpw, int m, int n, const double *X, long xr, long xc
   SPG_CHECK_LAUNCH();
 }
 
-static void qr_reg(int m, int n, const double *X, long xr, long xc, double *Q, long qr, long qc,
-                   double *R, int want_q, dim3 grid, long ist, hipStream_t s) {
+// grid.x workgroups, each factorising mb rows of the panel (the last one the
+// rest); the rows per lane are set by mb
+static void qr_reg(int m, int n, int mb, const double *X, long xr, long xc, double *Q, long qr,
+                   long qc, double *R, int want_q, dim3 grid, long ist, hipStream_t s) {
   const int cpw = (n + 15) / 16;
-  if (m <= 64) qr_reg_rows<1>(cpw, m, n, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
-  else if (m <= 128) qr_reg_rows<2>(cpw, m, n, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
-  else if (m <= 256) qr_reg_rows<4>(cpw, m, n, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
-  else qr_reg_rows<8>(cpw, m, n, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
+  if (mb <= 64) qr_reg_rows<1>(cpw, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
+  else if (mb <= 128) qr_reg_rows<2>(cpw, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
+  else if (mb <= 256) qr_reg_rows<4>(cpw, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
+  else qr_reg_rows<8>(cpw, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
 }
 
 // One LDS panel factorisation launch.
@@ -1286,8 +1302,51 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
   const long ist = g_bc.ist;
   if (m <= kQrRegRows && n <= kQrRegCols) {
     KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
-    qr_reg(m, n, X, xr, xc, Q, qr, qc, R, want_q, dim3(1, nI), ist, s);
+    qr_reg(m, n, m, X, xr, xc, Q, qr, qc, R, want_q, dim3(1, nI), ist, s);
     return;
+  }
+  if (n <= kQrRegCols) {
+    // one TSQR level on the register kernel: p blocks of at most 512 rows in
+    // one launch (a workgroup each), the QR of their stacked R factors, and
+    // Q = diag(Q_b) Q_s
+    const int p = (m + kQrRegRows - 1) / kQrRegRows;
+    const int mb = (m + p - 1) / p;
+    if (p * n <= kQrRegRows && m - (p - 1) * mb >= n) {
+      double *Q1 = work;                          // m x n row-major
+      double *S = Q1 + (long)m * n;               // p*n x n row-major (stacked R_b)
+      double *Qs = S + (long)p * n * n;           // p*n x n row-major
+      double *Rt = Qs + (long)p * n * n;          // n x n
+      {
+        KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
+        qr_reg(m, n, mb, X, xr, xc, want_q ? Q1 : nullptr, (long)n, 1L, S, want_q, dim3(p, nI),
+               ist, s);
+      }
+      {
+        KTimer kt_("qr_f64", s, qr_flops(p * n, n, want_q));
+        qr_reg(p * n, n, p * n, S, (long)n, 1L, want_q ? Qs : nullptr, (long)n, 1L, R ? R : Rt,
+               want_q, dim3(1, nI), ist, s);
+      }
+      if (!want_q) return;
+      const int full = m / mb, tail = m - full * mb;
+      GemmDesc g{};
+      g.N = n; g.K = n; g.nb2 = 1; g.alpha = 1.0; g.beta = 0.0;
+      g.a_i = n; g.a_k = 1; g.b_k = n; g.b_j = 1; g.c_i = qr; g.c_j = qc;
+      if (full > 0) {
+        g.M = mb; g.nb1 = full;
+        g.A = Q1; g.a_b1 = (long)mb * n;
+        g.B = Qs; g.b_b1 = (long)n * n;
+        g.C = Q; g.c_b1 = (long)mb * qr;
+        gemm_f64(g, s);
+      }
+      if (tail > 0) {
+        g.M = tail; g.nb1 = 1;
+        g.A = Q1 + (long)full * mb * n; g.a_b1 = 0;
+        g.B = Qs + (long)full * n * n; g.b_b1 = 0;
+        g.C = Q + (long)full * mb * qr; g.c_b1 = 0;
+        gemm_f64(g, s);
+      }
+      return;
+    }
   }
   if ((long)m * n <= kQrLds) {
     // one LDS-resident block; R straight to the caller (or to scratch)

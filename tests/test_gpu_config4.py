@@ -104,3 +104,35 @@ def test_gpu_pipeline_full_size_properties():
     st, en = st.cpu().numpy(), en.cpu().numpy()
     np.testing.assert_allclose(en, potts_energy(inst, st), atol=1e-9)
     assert np.all(np.diff(en) >= -1e-9)
+
+
+@pytest.mark.parametrize("shape,p,q", [((6, 4), 32, 3), ((5, 5), 32, 3)])
+def test_panels_beyond_512_rows_match_oracle(shape, p, q):
+    """Truncated two-site blocks with 24 * 24 = 576 rows: the range finder's
+    panels go through the TSQR of the register QR kernel.  On a
+    well-conditioned lattice (d = 24, beta = 0.3) with a sketch of 96 columns
+    and three power iterations the range finder reaches the truncated SVD's
+    subspace, so log Z and every row function equal the oracle's exact
+    truncated SVD."""
+    from workloads import spin_instance, potts_from_spins
+    from oracle.bmps import boundary_mps as oracle_bmps
+    print(f"panels beyond 512 rows {shape}", flush=True)
+    R, C = shape
+    si = spin_instance(R, C, 8, True, 0, h=("normal", 1.0), j_in=("normal", 1.0),
+                       j_out=("normal", 1.0))
+    inst = potts_from_spins(si, beta=0.3, d_keep=24)
+    env, lz = spg.boundary_mps(spg.build_peps(inst), CHI, oversample=p, power_iters=q)
+    ora = oracle_bmps(inst, CHI)
+    assert abs(lz - ora["logZ"]) <= 1e-9 * abs(ora["logZ"])
+    T, lam = spg.env_export(env)
+    rows = spg.unpack_mps(T, spg.env_info(env).bond_dims)
+    for r in range(R):
+        a, b = rows[r], ora["A"][r]
+        E = np.ones((1, 1))
+        Ea = np.ones((1, 1))
+        Eb = np.ones((1, 1))
+        for x, y in zip(a, b):
+            E = np.einsum("ij,ixk,jxl->kl", E, x, y)
+            Ea = np.einsum("ij,ixk,jxl->kl", Ea, x, x)
+            Eb = np.einsum("ij,ixk,jxl->kl", Eb, y, y)
+        assert 1.0 - E[0, 0] / np.sqrt(Ea[0, 0] * Eb[0, 0]) < 1e-9, r
