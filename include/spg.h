@@ -188,6 +188,20 @@ int spg_branch_and_bound(const spg_env_t *env, const spg_search_params *params,
                          int32_t *states_out, double *energies_out, double *logp_out,
                          int32_t *n_out, void *stream);
 
+/* The pruning step of the branch-and-bound search (Sec. 2: a fixed number of
+ * the most probable configurations is kept at every variable): the indices of
+ * the min(M, n) largest of n scores, ordered by score descending and, among
+ * equal scores, by index ascending; NaN ranks as -inf.
+ *   scores      DEVICE float64 [n]
+ *   sel_out     DEVICE int32   [min(M, n)]
+ *   scores_out  DEVICE float64 [min(M, n)] the selected scores, or NULL
+ * The same selection spg_branch_and_bound applies to each step's d*beam
+ * candidates.  Allocates its work buffers per call (device-synchronous).
+ * Errors: SPG_ERR_INVALID (n < 0, M < 1, null scores/sel_out with n > 0),
+ * SPG_ERR_OOM, SPG_ERR_HIP. */
+int spg_topm(int32_t n, int32_t M, const double *scores, int32_t *sel_out, double *scores_out,
+             void *stream);
+
 void spg_free_peps(spg_peps_t *peps);
 void spg_free_env(spg_env_t *env);
 const char *spg_last_error(void);

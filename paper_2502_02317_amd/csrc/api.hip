@@ -743,7 +743,7 @@ static void each_search_buffer(spg_env *env, int M, F &&f) {
   // reduced-precision search: U_c of every column for the row's ancestors
   if (env->precision != SPG_FP64) f(env->Ulp, (size_t)C * M * chi * d * 4);
   f(env->cand, (size_t)M * d * 8);
-  f(env->selws, (size_t)1280 + 12 * (size_t)M + 256);
+  f(env->selws, select_ws_bytes((long)M * d));
   f(env->sel, (size_t)M * 4);
   f(env->keys, (size_t)p2 * 8);
   f(env->ids, (size_t)p2 * 4);
@@ -841,6 +841,26 @@ int spg_marginals(const spg_env_t *cenv, int32_t site, int32_t n_beam, const int
   MargBufs b{env->cfg32.as<uint8_t>(), env->anc[0].as<int32_t>(), env->Rv.p, env->L[0].p,
              env->L[1].as<double>(), env->Ulp.as<float>()};
   marginals_run(env, site, n_beam, beam_cfg, log_cond_out, (hipStream_t)stream, b);
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_topm(int32_t n, int32_t M, const double *scores, int32_t *sel_out, double *scores_out,
+             void *stream) {
+  SPG_TRY
+  if (n < 0 || M < 1) return fail(SPG_ERR_INVALID, "spg_topm: n >= 0 and M >= 1 required");
+  if (n == 0) return SPG_OK;
+  if (!scores || !sel_out) return fail(SPG_ERR_INVALID, "spg_topm: null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const int Me = std::min(M, (int)n);
+  const int p2 = pow2_at_least(Me);
+  DevBuf keys, ids, ws;
+  keys.ensure((size_t)p2 * 8);
+  ids.ensure((size_t)p2 * 4);
+  ws.ensure(select_ws_bytes(n));
+  select_topm(n, M, scores, sel_out, keys.as<uint64_t>(), ids.as<int32_t>(), s, nullptr, nullptr,
+              scores_out, ws.p, (long)n);
+  SPG_HIP(hipStreamSynchronize(s));                 // before the work buffers are freed
   return SPG_OK;
   SPG_CATCH
 }
@@ -1125,7 +1145,7 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
           apply_cutoff((int)(B * d), log_cut, env->cand.as<double>(), s);
         select_topm((int)(B * d), M, env->cand.as<double>(), env->sel.as<int32_t>(),
                     env->keys.as<uint64_t>(), env->ids.as<int32_t>(), s, nullptr, nullptr,
-                    nullptr, env->selws.p);
+                    nullptr, env->selws.p, (long)M * d);
       }
       const int nx = cur ^ 1;
       if (lp)

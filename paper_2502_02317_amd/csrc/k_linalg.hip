@@ -48,11 +48,12 @@ __device__ __forceinline__ void householder(double al, double sg, double am, dou
                                             double &sc, double &beta) {
   tj = 0.0; sc = 0.0; beta = al;
   if (sg != 0.0) {
-    const double a = al / am;
+    const double a = (am == 1.0) ? al : al / am;   // am = 1 unless the column was rescaled
     const double nrm = am * sqrt(a * a + sg);
     beta = (al >= 0.0) ? -nrm : nrm;
-    tj = (beta - al) / beta;
-    sc = 1.0 / (al - beta);
+    const double x = al - beta;                     // |x| = |al| + nrm: no cancellation
+    tj = -x / beta;                                 // (beta - al) / beta
+    sc = 1.0 / x;                                   // independent of tj: the two overlap
   }
 }
 
@@ -614,7 +615,8 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int mb, const dou
     for (int t = 0; t < RPL; ++t) {
       const int i = lane + 64 * t;
       const double x = col[t];
-      if (i > jj) sg = fma(x, x, sg);
+      const double xm = (i > jj) ? x : 0.0;        // masked operand: the sum stays one chain
+      sg = fma(xm, xm, sg);
       if (t == (jj >> 6)) at = x;
     }
     sg = wave_sum(sg);
@@ -823,7 +825,7 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int mb, const dou
 // rotation test, so only the floor columns (never rotated, last in sorted
 // order) can fail orthonormality: the first of them is the first failing
 // column i0 (without convergence the sorted columns are checked to 1e-13).
-// Then the columns are re-orthonormalised by CGS2 in sorted order, with a
+// Then columns i0.. are re-orthonormalised by CGS2 in sorted order, with a
 // deterministic completion from the unit vectors for columns that lose their
 // norm, so the kk returned vectors are always orthonormal.
 constexpr int kJacRows = kMaxSketch / 16;     // most rows per lane of a pair group
@@ -996,9 +998,11 @@ __global__ __launch_bounds__(1024) void k_jacobi(int l, int kk, const double *Rm
   }
   __syncthreads();
   if (bad) {
-    // CGS2 in sorted order; a column that loses its norm is replaced by the
-    // first unit vector that survives the projection
-    for (int i = 0; i < kk; ++i) {
+    // CGS2 in sorted order from the first failing column (the ones before it
+    // are orthonormal to the rotation test's tolerance and stay as they are);
+    // a column that loses its norm is replaced by the first unit vector that
+    // survives the projection
+    for (int i = first_bad; i < kk; ++i) {
       int cand = -1;
       for (;;) {
         for (int pass = 0; pass < 2; ++pass) {

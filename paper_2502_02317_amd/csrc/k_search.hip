@@ -347,13 +347,24 @@ __global__ __launch_bounds__(256) void k_marginals_lds(SearchTabs t, int r, int 
 // Top-M of n scores by (score desc, id asc), written to sel[0..min(M,n)-1] in
 // that order, with the selected scores in sel_score (may be null).  Candidate
 // i has score cand[i] and id cid[i] (cid null: id = i; ids must be unique and
-// non-negative); n is *n_dev when n_dev is given.  Radix select of the M-th
-// key (8-bit digits), then of the id among keys equal to it, compaction, then
-// a bitonic sort of the survivors.  Up to kSelRegKeys * 1024 candidates are
-// held in registers for all passes, which then start at the highest digit
-// where the keys differ; survivors are sorted in LDS up to kSelLdsSort slots.
+// non-negative); n is *n_dev when n_dev is given.
+//
+// First a histogram of gap_bin(best score, score) over 4096 bins: the bin b*
+// where the running count reaches M bounds the selection, and the m keys in
+// bins <= b* are the first M of the (key, id) order and the rest of bin b*.
+// When m <= kSelLdsSort they are compacted to LDS and ordered without a sort:
+// a second histogram, uniform in the score gap to the best score over the
+// survivors' range, places each in its bin's segment (prefix sums), and its
+// final position is the segment's start plus its rank among the few keys of
+// the same bin.  When a bin still holds more than kSelBucket keys (ties), the
+// survivors are sorted instead (bitonic, in LDS).  When m > kSelLdsSort:
+// radix select of the M-th key (8-bit digits), then of the id among keys equal
+// to it, compaction, then a bitonic sort of the survivors.
+// Up to kSelRegKeys * 1024 candidates are held in registers for all passes,
+// which then start at the highest digit where the keys differ.
 constexpr int kSelRegKeys = 16;
-constexpr int kSelLdsSort = 4096;
+constexpr int kSelLdsSort = 1024 * kSortLdsRegs;     // 8192
+constexpr int kSelBucket = 64;
 
 __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, int M,
                                                 const double *cand, const int32_t *cid,
@@ -367,20 +378,154 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
   SPG_INST(kw);
   SPG_INST(iw);
   __shared__ unsigned hist[256];
+  __shared__ unsigned gh[kGapBins], gs[kGapBins];
   __shared__ uint64_t sh_prefix;
-  __shared__ int sh_need;
+  __shared__ int sh_need, sh_bstar, sh_m;
+  __shared__ unsigned sh_maxc;
+  __shared__ double sh_gap[16];
   __shared__ int wsum[16];
   __shared__ uint64_t wmin[16], wmax[16];
   __shared__ uint64_t skey[kSelLdsSort];
   __shared__ int32_t sid[kSelLdsSort];
   const int tid = threadIdx.x;
   const int n = n_dev ? *n_dev : n_host;
+  if (n <= 0) return;
   const int Me = (M < n) ? M : n;
   int p2 = 1;
   while (p2 < Me) p2 <<= 1;
   const bool lds_sort = p2 <= kSelLdsSort;
   auto key_at = [&](int i) { return desc_key(cand[i]); };
   auto id_at = [&](int i) { return cid ? cid[i] : i; };
+  // from the gap histogram gh: the boundary bin b* and the count m of keys in
+  // bins <= b* (uniform on return)
+  auto gap_bound = [&](int &bstar, int &m) {
+    unsigned hb[4];
+    int own = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      hb[j] = gh[4 * tid + j];
+      own += (int)hb[j];
+    }
+    int tot;
+    const int ex = block_excl_scan_count(own, wsum, &tot);
+    if (ex < Me && ex + own >= Me) {                 // exactly one thread
+      int cum = ex, b = 4 * tid;
+      for (int j = 0; j < 4; ++j) {
+        cum += (int)hb[j];
+        b = 4 * tid + j;
+        if (cum >= Me) break;
+      }
+      sh_bstar = b;
+      sh_m = cum;
+    }
+    __syncthreads();
+    bstar = sh_bstar;
+    m = sh_m;
+  };
+  // sorts the m survivors in skey/sid and writes the first Me
+  auto sort_out = [&](int m) {
+    int p2m = 1;
+    while (p2m < m) p2m <<= 1;
+    for (int i = m + tid; i < p2m; i += 1024) { skey[i] = ~0ull; sid[i] = INT_MAX; }
+    __syncthreads();
+    bitonic_sort_lds(skey, sid, p2m);
+    for (int i = tid; i < Me; i += 1024) {
+      sel[i] = sid[i];
+      if (sel_score) sel_score[i] = key_value(skey[i]);
+    }
+  };
+  // the m survivors (a prefix of the order, m >= Me) sit unordered in
+  // skey/sid: writes the first Me in order.  Bins uniform in the gap
+  // vmax - v over [0, largest gap] (monotone in the score), prefix sums for
+  // the segments, then each survivor's rank within its bin.
+  auto order_out = [&](int m, uint64_t kbest) {
+    const double vmax = key_value(kbest);
+    double gm = 0.0;
+    for (int p = tid; p < m; p += 1024) gm = fmax(gm, vmax - key_value(skey[p]));
+    gm = wave_max_nonneg(gm);
+    if ((tid & 63) == 0) sh_gap[tid >> 6] = gm;
+    for (int b = tid; b < kGapBins; b += 1024) gh[b] = 0u;
+    if (tid == 0) sh_maxc = 0u;
+    __syncthreads();
+    gm = 0.0;
+    for (int w = 0; w < 16; ++w) gm = fmax(gm, sh_gap[w]);
+    if (!(gm > 0.0 && gm <= 1.7e308)) {              // a single score, or -inf among them
+      sort_out(m);
+      return;
+    }
+    const double scale = (double)kGapBins / gm;
+    auto vbin = [&](uint64_t k) {
+      return (int)fmin((vmax - key_value(k)) * scale, (double)(kGapBins - 1));
+    };
+    for (int p = tid; p < m; p += 1024) atomicAdd(&gh[vbin(skey[p])], 1u);
+    __syncthreads();
+    unsigned hb[4];
+    int own = 0;
+    unsigned mc = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      hb[j] = gh[4 * tid + j];
+      own += (int)hb[j];
+      mc = (hb[j] > mc) ? hb[j] : mc;
+    }
+    mc = (unsigned)wave_max_u64(mc);
+    if ((tid & 63) == 0 && mc > 0u) atomicMax(&sh_maxc, mc);
+    int tot;
+    unsigned run = (unsigned)block_excl_scan_count(own, wsum, &tot);
+    if (sh_maxc > (unsigned)kSelBucket) {            // ties: sort instead
+      sort_out(m);
+      return;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      gs[4 * tid + j] = run;
+      gh[4 * tid + j] = run;
+      run += hb[j];
+    }
+    uint64_t kv[kSortLdsRegs];
+    int32_t iv[kSortLdsRegs];
+#pragma unroll
+    for (int r = 0; r < kSortLdsRegs; ++r) {
+      const int p = tid + 1024 * r;
+      kv[r] = (p < m) ? skey[p] : 0ull;
+      iv[r] = (p < m) ? sid[p] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortLdsRegs; ++r) {
+      if (tid + 1024 * r < m) {
+        const unsigned pos = atomicAdd(&gh[vbin(kv[r])], 1u);
+        skey[pos] = kv[r];
+        sid[pos] = iv[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortLdsRegs; ++r) {
+      if (tid + 1024 * r < m) {
+        const uint64_t k = kv[r];
+        const int32_t id = iv[r];
+        const int b = vbin(k);
+        const int s0 = (int)gs[b], e0 = (int)gh[b];
+        int rk = s0;
+        int f = s0;
+        for (; f + 3 < e0; f += 4) {
+          const uint64_t k0 = skey[f], k1 = skey[f + 1], k2 = skey[f + 2], k3 = skey[f + 3];
+          const int32_t i0 = sid[f], i1 = sid[f + 1], i2 = sid[f + 2], i3 = sid[f + 3];
+          rk += (k0 < k || (k0 == k && i0 < id)) + (k1 < k || (k1 == k && i1 < id)) +
+                (k2 < k || (k2 == k && i2 < id)) + (k3 < k || (k3 == k && i3 < id));
+        }
+        for (; f < e0; ++f) {
+          const uint64_t kf = skey[f];
+          rk += (kf < k || (kf == k && sid[f] < id)) ? 1 : 0;
+        }
+        if (rk < Me) {
+          sel[rk] = id;
+          if (sel_score) sel_score[rk] = key_value(k);
+        }
+      }
+    }
+  };
   uint64_t kthr = ~0ull;         // take keys < kthr, and keys == kthr with id <= ithr
   uint64_t ithr = 0;
   bool all_eq = true;
@@ -389,10 +534,20 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
     // or read back for ties and survivors only)
     uint64_t kr[kSelRegKeys];
     uint64_t lo = ~0ull, hi = 0;
+    {
+      // all loads issued before the first use (indices clamped into range)
+      double raw[kSelRegKeys];
+#pragma unroll
+      for (int q = 0; q < kSelRegKeys; ++q) {
+        const int i = tid + 1024 * q;
+        raw[q] = cand[(i < n) ? i : n - 1];
+      }
+#pragma unroll
+      for (int q = 0; q < kSelRegKeys; ++q) kr[q] = (tid + 1024 * q < n) ? desc_key(raw[q]) : 0ull;
+    }
 #pragma unroll
     for (int q = 0; q < kSelRegKeys; ++q) {
       const int i = tid + 1024 * q;
-      kr[q] = (i < n) ? key_at(i) : 0ull;
       if (i < n) {
         lo = (kr[q] < lo) ? kr[q] : lo;
         hi = (kr[q] > hi) ? kr[q] : hi;
@@ -413,6 +568,49 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
       for (int w = 0; w < 16; ++w) {
         lo = (wmin[w] < lo) ? wmin[w] : lo;
         hi = (wmax[w] > hi) ? wmax[w] : hi;
+      }
+      if (lo != hi) {
+        // ---- gap histogram: usually settles the selection in one pass (the
+        // bins stay in registers; -inf, often the most crowded bin, is
+        // counted once per wavefront)
+        for (int b = tid; b < kGapBins; b += 1024) gh[b] = 0u;
+        __syncthreads();
+        const double vmax = key_value(lo);
+        const int binf = gap_bin(vmax, -INFINITY);
+        int kb[kSelRegKeys];
+#pragma unroll
+        for (int q = 0; q < kSelRegKeys; ++q) {
+          const int i = tid + 1024 * q;
+          kb[q] = (i < n) ? gap_bin(vmax, key_value(kr[q])) : kGapBins;
+          const unsigned long long inf_lanes = __ballot(kb[q] == binf);
+          if (kb[q] < kGapBins && kb[q] != binf) atomicAdd(&gh[kb[q]], 1u);
+          if ((tid & 63) == 0 && inf_lanes) atomicAdd(&gh[binf], (unsigned)__popcll(inf_lanes));
+        }
+        __syncthreads();
+        int bstar, m;
+        gap_bound(bstar, m);
+        if (m <= kSelLdsSort) {
+          int cnt = 0;
+          unsigned fl = 0u;
+#pragma unroll
+          for (int q = 0; q < kSelRegKeys; ++q) {
+            const bool f = kb[q] <= bstar;             // kGapBins beyond n
+            fl |= (f ? 1u : 0u) << q;
+            cnt += f;
+          }
+          int tot;
+          int pos = block_excl_scan_count(cnt, wsum, &tot);
+#pragma unroll
+          for (int q = 0; q < kSelRegKeys; ++q) {
+            if ((fl >> q) & 1u) {
+              skey[pos] = kr[q];
+              sid[pos] = id_at(tid + 1024 * q);
+              ++pos;
+            }
+          }
+          order_out(m, lo);
+          return;
+        }
       }
       int need = Me, n_eq = n;
       uint64_t prefix = lo;
@@ -483,6 +681,42 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
   } else {
     // ---- keys read from memory on every pass
     if (Me < n) {
+      // gap histogram first, as above
+      uint64_t lo = ~0ull;
+      for (int i = tid; i < n; i += 1024) {
+        const uint64_t k = key_at(i);
+        lo = (k < lo) ? k : lo;
+      }
+      lo = wave_min_u64(lo);
+      if ((tid & 63) == 0) wmin[tid >> 6] = lo;
+      for (int b = tid; b < kGapBins; b += 1024) gh[b] = 0u;
+      __syncthreads();
+      lo = ~0ull;
+      for (int w = 0; w < 16; ++w) lo = (wmin[w] < lo) ? wmin[w] : lo;
+      const double vmax = key_value(lo);
+      for (int i = tid; i < n; i += 1024) atomicAdd(&gh[gap_bin(vmax, key_value(key_at(i)))], 1u);
+      __syncthreads();
+      int bstar, m;
+      gap_bound(bstar, m);
+      if (m <= kSelLdsSort) {
+        int base = 0;
+        for (int c0 = 0; c0 < n; c0 += 1024) {
+          const int i = c0 + tid;
+          uint64_t k = 0;
+          int f = 0;
+          if (i < n) {
+            k = key_at(i);
+            f = gap_bin(vmax, key_value(k)) <= bstar;
+          }
+          int tot_f;
+          const int pos = block_excl_scan(f, wsum, &tot_f);
+          if (f) { skey[base + pos] = k; sid[base + pos] = id_at(i); }
+          base += tot_f;
+          __syncthreads();
+        }
+        order_out(m, lo);
+        return;
+      }
       uint64_t prefix = 0, pmask = 0;
       int need = Me;
       for (int shift = 56; shift >= 0; shift -= 8) {
@@ -549,103 +783,88 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
 }
 
 // ---- top-M for more candidates than the one-workgroup select holds in
-// registers: the same selection (keys below the M-th key, then the least ids
-// among keys equal to it), with every radix pass a histogram over many
-// workgroups (integer atomics: the totals do not depend on their order) and a
-// one-wavefront step that picks the digit.  The survivors are then sorted by
-// k_select itself (n = M), so sel and sel_score are the ones k_select writes.
-struct SelState {
-  unsigned long long prefix, pmask, kthr;
-  int need, n_eq, count, all_eq;
+// registers: the gap histogram over many workgroups (the least key, then the
+// histogram with integer atomics, whose totals do not depend on their order),
+// then every workgroup finds the same boundary bin b* and appends its keys in
+// bins <= b* to a survivor list (in any order); k_select on the survivors
+// (their scores and original indices) sorts them and writes sel and sel_score.
+struct GselState {
+  unsigned long long kmin;
+  int count;
+  int pad;
 };
 
-__global__ void k_sel_init(SelState *st, unsigned *gh, int Me) {
-  gh[threadIdx.x] = 0u;                              // 256 threads
+__global__ __launch_bounds__(1024) void k_gsel_init(GselState *st, unsigned *gh) {
+  for (int b = threadIdx.x; b < kGapBins; b += 1024) gh[b] = 0u;
   if (threadIdx.x == 0) {
-    st->prefix = 0ull;
-    st->pmask = 0ull;
-    st->kthr = 0ull;
-    st->need = Me;
-    st->n_eq = 0;
+    st->kmin = ~0ull;
     st->count = 0;
-    st->all_eq = 1;
   }
 }
 
-// mode 0: digit of the key; mode 1: digit of the index among keys equal to kthr
-__global__ __launch_bounds__(256) void k_sel_hist(int n, const double *cand, int shift, int mode,
-                                                  const SelState *st, unsigned *gh) {
-  __shared__ unsigned h[256];
-  const int t = threadIdx.x;
-  if (mode && st->all_eq) return;                    // uniform: no id passes needed
-  h[t] = 0u;
-  __syncthreads();
-  const unsigned long long prefix = st->prefix, pmask = st->pmask, kthr = st->kthr;
-  for (int i = blockIdx.x * 256 + t; i < n; i += gridDim.x * 256) {
-    unsigned long long k = desc_key(cand[i]);
-    if (mode) k = (k == kthr) ? (unsigned long long)(unsigned)i : ~0ull;
-    if ((k & pmask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1u);
-  }
-  __syncthreads();
-  if (h[t]) atomicAdd(&gh[t], h[t]);
-}
-
-// one wavefront: the digit holding the need-th smallest key, as radix_find;
-// clears the histogram for the next pass.  mode 2: the last key pass (then
-// kthr is known and the id passes are set up when they are needed).
-__global__ void k_sel_find(SelState *st, unsigned *gh, int shift, int mode) {
-  const int lane = threadIdx.x;                      // 64 threads
-  if (mode == 1 && st->all_eq) return;
-  unsigned h[4], own = 0u;
-  for (int j = 0; j < 4; ++j) { h[j] = gh[4 * lane + j]; own += h[j]; }
-  unsigned inc = own;
-  for (int o = 1; o < 64; o <<= 1) {
-    const unsigned v = __shfl_up(inc, o);
-    if (lane >= o) inc += v;
-  }
-  const unsigned excl = inc - own;
-  const int need = st->need;
-  const unsigned long long hit = __ballot(inc >= (unsigned)need);
-  const int first = hit ? (__ffsll((long long)hit) - 1) : 63;
-  for (int j = 0; j < 4; ++j) gh[4 * lane + j] = 0u;
-  if (lane == first) {
-    unsigned cum = excl;
-    int t = 4 * lane, j = 0;
-    for (; j < 3; ++j, ++t) {
-      if (cum + h[j] >= (unsigned)need) break;
-      cum += h[j];
-    }
-    const unsigned long long prefix = st->prefix | ((unsigned long long)t << shift);
-    const int left = need - (int)cum;
-    if (mode == 2) {
-      // the M-th key is known: keys equal to it are taken whole, or by least index
-      st->kthr = prefix;
-      st->n_eq = (int)h[j];
-      st->all_eq = (left >= (int)h[j]) ? 1 : 0;
-      st->need = left;
-      st->prefix = 0ull;
-      st->pmask = 0xFFFFFFFF00000000ull;          // indices fit in 32 bits
-    } else {
-      st->prefix = prefix;
-      st->pmask |= (255ull << shift);
-      st->need = left;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_sel_compact(int n, const double *cand, SelState *st,
-                                                     double *cs, int32_t *is, int Me) {
-  const unsigned long long kthr = st->kthr, ithr = st->prefix;
-  const int all_eq = st->all_eq;
+__global__ __launch_bounds__(256) void k_gsel_min(int n, const double *cand, GselState *st) {
+  uint64_t lo = ~0ull;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-    const unsigned long long k = desc_key(cand[i]);
-    const bool f = (k < kthr) || (k == kthr && (all_eq || (unsigned long long)(unsigned)i <= ithr));
+    const uint64_t k = desc_key(cand[i]);
+    lo = (k < lo) ? k : lo;
+  }
+  lo = wave_min_u64(lo);
+  if ((threadIdx.x & 63) == 0) atomicMin(&st->kmin, (unsigned long long)lo);
+}
+
+__global__ __launch_bounds__(256) void k_gsel_hist(int n, const double *cand, const GselState *st,
+                                                   unsigned *gh) {
+  __shared__ unsigned h[kGapBins];
+  for (int b = threadIdx.x; b < kGapBins; b += 256) h[b] = 0u;
+  __syncthreads();
+  const double vmax = key_value(st->kmin);
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    atomicAdd(&h[gap_bin(vmax, key_value(desc_key(cand[i])))], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kGapBins; b += 256)
+    if (h[b]) atomicAdd(&gh[b], h[b]);
+}
+
+__global__ __launch_bounds__(256) void k_gsel_compact(int n, int Me, const double *cand,
+                                                      GselState *st, const unsigned *gh,
+                                                      double *cs, int32_t *is) {
+  __shared__ int wsum[4];
+  __shared__ int sh_b;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // boundary bin: thread t owns bins 16t..16t+15
+  unsigned hb[16];
+  int own = 0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    hb[j] = gh[16 * tid + j];
+    own += (int)hb[j];
+  }
+  int tot;
+  const int ex = block_excl_scan_count(own, wsum, &tot);
+  if (ex < Me && ex + own >= Me) {
+    int cum = ex, b = 16 * tid;
+    for (int j = 0; j < 16; ++j) {
+      cum += (int)hb[j];
+      b = 16 * tid + j;
+      if (cum >= Me) break;
+    }
+    sh_b = b;
+  }
+  __syncthreads();
+  const int bstar = sh_b;
+  const double vmax = key_value(st->kmin);
+  // survivors appended a wavefront at a time
+  for (int c0 = blockIdx.x * 256 + (tid & ~63); c0 < n; c0 += gridDim.x * 256) {
+    const int i = c0 + lane;
+    const bool f = (i < n) && gap_bin(vmax, key_value(desc_key(cand[i]))) <= bstar;
+    const unsigned long long bal = __ballot(f);
+    int base = 0;
+    if (lane == 0 && bal) base = atomicAdd(&st->count, __popcll(bal));
+    base = __shfl(base, 0);
     if (f) {
-      const int pos = atomicAdd(&st->count, 1);
-      if (pos < Me) {
-        cs[pos] = cand[i];
-        is[pos] = i;
-      }
+      const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+      cs[pos] = cand[i];
+      is[pos] = i;
     }
   }
 }
@@ -1076,37 +1295,33 @@ void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg
   SPG_CHECK_LAUNCH();
 }
 
+size_t select_ws_bytes(long n_cap) {
+  return 256 + sizeof(unsigned) * (size_t)kGapBins + 12 * (size_t)n_cap;
+}
+
 void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *keys_work,
                  int32_t *ids_work, hipStream_t s, const int *n_dev, const int32_t *cid,
-                 double *sel_score, void *big_ws) {
+                 double *sel_score, void *big_ws, long ws_cap) {
   KTimer kt_("select_topm", s, (cid ? 12.0 : 8.0) * n_cand + 4.0 * (M < n_cand ? M : n_cand));
   const int Me = (M < n_cand) ? M : n_cand;
   if (big_ws && !n_dev && !cid && g_bc.n == 1 && n_cand > kSelRegKeys * 1024 && Me < n_cand &&
-      Me >= 1 && Me <= kSelLdsSort) {
-    // workspace: state (256 B), histogram (1 KiB), survivors' scores [Me] and indices [Me]
-    SelState *st = reinterpret_cast<SelState *>(big_ws);
+      Me >= 1 && n_cand <= ws_cap) {
+    // workspace: state (256 B), histogram, survivors' scores and indices [n_cand]
+    GselState *st = reinterpret_cast<GselState *>(big_ws);
     unsigned *gh = reinterpret_cast<unsigned *>(static_cast<char *>(big_ws) + 256);
-    double *cs = reinterpret_cast<double *>(static_cast<char *>(big_ws) + 1280);
-    int32_t *is = reinterpret_cast<int32_t *>(cs + Me);
+    double *cs = reinterpret_cast<double *>(gh + kGapBins);
+    int32_t *is = reinterpret_cast<int32_t *>(cs + ws_cap);
     const unsigned G = (unsigned)std::min(((long)n_cand + 2047) / 2048, 1024L);
-    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, st, gh, Me);
+    hipLaunchKernelGGL(k_gsel_init, dim3(1), dim3(1024), 0, s, st, gh);
     SPG_CHECK_LAUNCH();
-    for (int shift = 56; shift >= 0; shift -= 8) {
-      hipLaunchKernelGGL(k_sel_hist, dim3(G), dim3(256), 0, s, n_cand, cand, shift, 0, st, gh);
-      SPG_CHECK_LAUNCH();
-      hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(64), 0, s, st, gh, shift, shift == 0 ? 2 : 0);
-      SPG_CHECK_LAUNCH();
-    }
-    for (int shift = 24; shift >= 0; shift -= 8) {
-      hipLaunchKernelGGL(k_sel_hist, dim3(G), dim3(256), 0, s, n_cand, cand, shift, 1, st, gh);
-      SPG_CHECK_LAUNCH();
-      hipLaunchKernelGGL(k_sel_find, dim3(1), dim3(64), 0, s, st, gh, shift, 1);
-      SPG_CHECK_LAUNCH();
-    }
-    hipLaunchKernelGGL(k_sel_compact, dim3(G), dim3(256), 0, s, n_cand, cand, st, cs, is, Me);
+    hipLaunchKernelGGL(k_gsel_min, dim3(G), dim3(256), 0, s, n_cand, cand, st);
     SPG_CHECK_LAUNCH();
-    // the Me survivors sorted by (key, index), as the one-workgroup select does
-    hipLaunchKernelGGL(k_select, dim3(1, 1), dim3(1024), 0, s, Me, (const int *)nullptr, Me,
+    hipLaunchKernelGGL(k_gsel_hist, dim3(G), dim3(256), 0, s, n_cand, cand, st, gh);
+    SPG_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_gsel_compact, dim3(G), dim3(256), 0, s, n_cand, Me, cand, st, gh, cs, is);
+    SPG_CHECK_LAUNCH();
+    // the survivors (at least Me) sorted by (key, original index)
+    hipLaunchKernelGGL(k_select, dim3(1, 1), dim3(1024), 0, s, 0, (const int *)&st->count, Me,
                        (const double *)cs, (const int32_t *)is, sel, sel_score, keys_work,
                        ids_work, 0L);
     SPG_CHECK_LAUNCH();

@@ -127,16 +127,17 @@ __device__ __forceinline__ void bitonic_sort(uint64_t *keys, int32_t *ids, int n
 }
 
 // The same sort for (key, id) pairs held in LDS, blockDim = 1024, n_pow2 <=
-// 4096: thread t keeps elements t + 1024 r in registers; stages whose partner
+// 8192: thread t keeps elements t + 1024 r in registers; stages whose partner
 // lies in the same wavefront (distance < 64) exchange through lane shuffles
 // without barriers, the others go through LDS.  Leaves the sorted pairs in LDS.
+constexpr int kSortLdsRegs = 8;
 __device__ inline void bitonic_sort_lds(uint64_t *keys, int32_t *ids, int n_pow2) {
   const int tid = threadIdx.x;
-  const int R = (n_pow2 + 1023) >> 10;          // 1..4
-  uint64_t kv[4];
-  int32_t iv[4];
+  const int R = (n_pow2 + 1023) >> 10;          // 1..kSortLdsRegs
+  uint64_t kv[kSortLdsRegs];
+  int32_t iv[kSortLdsRegs];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+  for (int r = 0; r < kSortLdsRegs; ++r) {
     const int i = tid + 1024 * r;
     kv[r] = (r < R && i < n_pow2) ? keys[i] : ~0ull;
     iv[r] = (r < R && i < n_pow2) ? ids[i] : INT_MAX;
@@ -146,7 +147,7 @@ __device__ inline void bitonic_sort_lds(uint64_t *keys, int32_t *ids, int n_pow2
     if (j >= 64) {
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < kSortLdsRegs; ++r) {
         const int i = tid + 1024 * r;
         if (r < R && i < n_pow2) { keys[i] = kv[r]; ids[i] = iv[r]; }
       }
@@ -168,14 +169,14 @@ __device__ inline void bitonic_sort_lds(uint64_t *keys, int32_t *ids, int n_pow2
         __syncthreads();
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < kSortLdsRegs; ++r) {
         const int i = tid + 1024 * r;
         if (r < R && i < n_pow2) { kv[r] = keys[i]; iv[r] = ids[i]; }
       }
     }
     for (; j > 0; j >>= 1) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < kSortLdsRegs; ++r) {
         if (r < R) {
           const int i = tid + 1024 * r;
           const uint64_t pk = __shfl_xor(kv[r], j);
@@ -189,11 +190,25 @@ __device__ inline void bitonic_sort_lds(uint64_t *keys, int32_t *ids, int n_pow2
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+  for (int r = 0; r < kSortLdsRegs; ++r) {
     const int i = tid + 1024 * r;
     if (r < R && i < n_pow2) { keys[i] = kv[r]; ids[i] = iv[r]; }
   }
   __syncthreads();
+}
+
+// Log-spaced bins of a score's gap below the best score vmax: 64 bins per
+// octave of g = vmax - v over [2^-32, 2^32) (the exponent and six leading
+// mantissa bits of g), gaps below to bin 0, above it and NaN to the last
+// bin; non-decreasing as the score falls.  All scores in bins up to some b
+// are at least as good as every score beyond it, so they form a prefix of the
+// (score desc, id asc) order.
+constexpr int kGapBins = 4096;
+__device__ __forceinline__ int gap_bin(double vmax, double v) {
+  const double g = vmax - v;                         // >= 0 (vmax is the best)
+  if (!(g == g)) return kGapBins - 1;
+  const int e = (int)((unsigned)__double2hiint(g) >> 14) - ((1023 - 32) << 6);
+  return e < 0 ? 0 : (e > kGapBins - 1 ? kGapBins - 1 : e);
 }
 
 // Inverse of desc_key (NaN came in as -inf).

@@ -63,7 +63,7 @@ class BatchItem(C.Structure):
 
 
 EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals_noalloc",
-           "spg_branch_and_bound",
+           "spg_branch_and_bound", "spg_topm",
            "spg_free_peps", "spg_free_env", "spg_last_error", "spg_env_info", "spg_env_export",
            "spg_env_import", "spg_profile_enable", "spg_profile_reset", "spg_profile_query",
            "spg_proposal_create", "spg_proposal_free", "spg_proposal_params",
@@ -92,6 +92,7 @@ def load() -> C.CDLL:
     lib.spg_boundary_mps.argtypes = [vp, C.POINTER(MpsParams), vp, C.POINTER(vp), f64p]
     lib.spg_marginals.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.spg_marginals_noalloc.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.spg_topm.argtypes = [i32, i32, vp, vp, vp, vp]
     lib.spg_branch_and_bound.argtypes = [vp, C.POINTER(SearchParams), vp, vp, vp, i32p, vp]
     lib.spg_free_peps.argtypes = [vp]
     lib.spg_free_env.argtypes = [vp]
@@ -129,7 +130,7 @@ def load() -> C.CDLL:
     lib.spg_batch_autotune.argtypes = [vp, vp, vp]
     lib.spg_set_tuning.argtypes = [i32]
     for name in ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals_noalloc",
-                 "spg_branch_and_bound",
+                 "spg_branch_and_bound", "spg_topm",
                  "spg_env_info", "spg_env_export", "spg_env_import", "spg_profile_query",
                  "spg_proposal_create", "spg_proposal_params", "spg_proposal_train",
                  "spg_proposal_features", "spg_proposal_forward", "spg_proposal_loss_grad",
@@ -226,6 +227,14 @@ def marginals_noalloc(env: Env, site: int, beam_cfg, out, stream=None):
     _check(load().spg_marginals_noalloc(env.handle, int(site), int(beam_cfg.shape[0]),
                                         _ptr(beam_cfg), _ptr(out), _stream(stream)))
     return out
+
+
+def topm(scores, M: int, sel_out, scores_out=None, stream=None):
+    """spg_topm: scores float64 [n], sel_out int32 [min(M, n)], scores_out
+    float64 [min(M, n)] or None; torch device tensors."""
+    _check(load().spg_topm(int(scores.shape[0]), int(M), _ptr(scores), _ptr(sel_out),
+                           _ptr(scores_out) if scores_out is not None else None, _stream(stream)))
+    return sel_out
 
 
 def branch_and_bound(env: Env, max_states: int, states_out, energies_out, logp_out,
