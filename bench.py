@@ -169,50 +169,80 @@ def cpu_baseline(inst, wl):
             "_oracle_A": mp["A"]}
 
 
-def proposal_leg(spg, torch, inst, wl, M, st, en, lp, stream):
-    """Learned proposal: trained on two other instances of the workload, then
-    the guarded search against the plain FP64 search on this instance (same
-    boundary MPS).  Search-only times; candidates resolved count as evals."""
+def j1_leg(spg, torch, name, chi, M, train_M, epochs, reps, stream):
+    """The mixed-precision + learned-proposal search: FP32 search contractions
+    with the network (trained on the method's own FP64 marginals of two other
+    instances of the workload, seeds 1 and 2) pre-ranking the children and
+    the guard evaluating the rest, against the plain FP64 search and the plain
+    FP32 search on the same boundary MPS.  Search-only times (the boundary MPS
+    is shared); every conditional marginal the search resolves counts as an
+    eval, evaluated exactly or bounded by the guard.  Returns (record, network)."""
+    import numpy as np
     from workloads import config_instance
+    inst = config_instance(name, 0)
+    R, C, d = inst.rows, inst.cols, inst.d
+    N = R * C
+    dev = torch.device("cuda:0")
+    st = torch.zeros((M, N), dtype=torch.int32, device=dev)
+    en = torch.zeros(M, dtype=torch.float64, device=dev)
+    lp = torch.zeros(M, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     prop = spg.Proposal(hidden=32, seed=1)
     for sd in (1, 2):
-        other = config_instance(wl["name"], sd)
-        po = spg.build_peps(other, stream)
-        eo, _ = spg.boundary_mps(po, wl["chi"], num_sweeps=wl["num_sweeps"], precision="fp64",
-                                 oversample=wl["oversample"], power_iters=wl["power_iters"],
-                                 stream=stream, want_logZ=False)
-        prop.train(eo, epochs=4, learning_rate=5e-3, max_states=M, stream=stream)
+        po = spg.build_peps(config_instance(name, sd), stream)
+        eo, _ = spg.boundary_mps(po, chi, stream=stream, want_logZ=False)
+        prop.train(eo, epochs=epochs, learning_rate=5e-3, max_states=train_M, stream=stream)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     peps = spg.build_peps(inst, stream)
-    env, _ = spg.boundary_mps(peps, wl["chi"], num_sweeps=wl["num_sweeps"], precision="fp64",
-                              oversample=wl["oversample"], power_iters=wl["power_iters"],
-                              stream=stream, want_logZ=False)
+    env64, _ = spg.boundary_mps(peps, chi, stream=stream, want_logZ=False)
+    T, _ = spg.env_export(env64)
+    env32 = spg.env_import(peps, chi, spg.env_info(env64).bond_dims, T, np.zeros(R),
+                           precision="fp32", stream=stream)
 
-    def run(**kw):
-        spg.branch_and_bound(env, M, st, en, lp, stream=stream, **kw)   # warm
+    def run(env, **kw):
+        spg.branch_and_bound(env, M, st, en, lp, stream=stream, **kw)      # warm
         torch.cuda.synchronize()
-        reps = 3
         a = time.perf_counter()
         for _ in range(reps):
             n = spg.branch_and_bound(env, M, st, en, lp, stream=stream, **kw)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - a) * 1e3 / reps
-        states = {tuple(x) for x in st[:n].cpu().numpy().tolist()}
-        return ms, states, (float(en[0]) if n > 0 else None), spg.search_stats(env)
+        states = {tuple(x): l for x, l in zip(st[:n].cpu().numpy().tolist(),
+                                              lp[:n].cpu().numpy().tolist())}
+        return {"ms": ms, "states": states, "E": float(en[0]) if n > 0 else None,
+                "stats": spg.search_stats(env)}
 
-    ms_plain, s_plain, e_plain, st_plain = run()
-    ms_g, s_g, e_g, st_g = run(proposal=prop, kappa=2.0)
-    exact, resolved, fb = st_g
-    return {"train_s": train_s, "trained_on": "seeds 1 and 2 of the same workload",
-            "kappa": 2.0, "hidden": 32,
-            "search_ms_plain_fp64": ms_plain, "search_ms_guided": ms_g,
-            "evals_per_s_plain": resolved / (ms_plain * 1e-3),
-            "evals_per_s_guided": resolved / (ms_g * 1e-3),
-            "exact_evals": exact, "resolved": resolved, "exact_fraction": exact / resolved,
-            "fallback_parents": fb, "beam_shared_with_plain": len(s_plain & s_g) / len(s_plain),
-            "best_energy_plain": e_plain, "best_energy_guided": e_g}
+    p64, p32 = run(env64), run(env32)
+    g32 = run(env32, proposal=prop, kappa=2.0)
+    g64 = run(env64, proposal=prop, kappa=2.0)
+    resolved = p64["stats"][1]
+    rate = {k: resolved / (v["ms"] * 1e-3) for k, v in
+            (("plain_fp64", p64), ("plain_fp32", p32), ("guided_fp32", g32), ("guided_fp64", g64))}
+    common = p64["states"].keys() & g32["states"].keys()
+    dl = [abs(p64["states"][k] - g32["states"][k]) for k in common]
+    exact, _, fb = g32["stats"]
+    rec = {"workload": f"{name} chi={chi} M={M} (seed 0)",
+           "trained_on": "FP64 marginals of seeds 1 and 2 of the workload",
+           "train_max_states": train_M, "epochs": epochs, "train_s": train_s,
+           "kappa": 2.0, "hidden": 32, "search_ms": {k: v["ms"] for k, v in
+                                                    (("plain_fp64", p64), ("plain_fp32", p32),
+                                                     ("guided_fp32", g32), ("guided_fp64", g64))},
+           "evals_per_s": rate, "resolved_evals": resolved,
+           "speedup_guided_fp32_vs_plain_fp64": rate["guided_fp32"] / rate["plain_fp64"],
+           "speedup_plain_fp32_vs_plain_fp64": rate["plain_fp32"] / rate["plain_fp64"],
+           "guided_fp32_exact_evals": exact, "guided_fp32_exact_fraction": exact / resolved,
+           "guided_fp32_fallback_parents": fb,
+           "guided_fp64_exact_fraction": g64["stats"][0] / resolved,
+           "best_energy": {"plain_fp64": p64["E"], "plain_fp32": p32["E"],
+                           "guided_fp32": g32["E"], "guided_fp64": g64["E"]},
+           "states_shared_guided_fp32_with_plain_fp64": len(common) / max(len(p64["states"]), 1),
+           "states_shared_guided_fp32_with_plain_fp32":
+               len(p32["states"].keys() & g32["states"].keys()) / max(len(p32["states"]), 1),
+           "logp_shared_states_max_abs_diff_vs_fp64": max(dl) if dl else None,
+           "logp_shared_states_median_abs_diff_vs_fp64": float(np.median(dl)) if dl else None}
+    return rec, prop
 
 
 def batching_leg(spg, torch, stream):
@@ -662,9 +692,12 @@ def main():
         "roofline": roof,
         "contraction_tflops": contraction,
     }
+    prop8 = None
     if not args.no_forms:
-        out["forms"] = {"learned_proposal": proposal_leg(spg, torch, inst, wl, M, st, en, lp,
-                                                         stream),
+        say("mixed precision + learned proposal")
+        j8, prop8 = j1_leg(spg, torch, "kings8x8_d16", wl["chi"], M, M, 4, 3, stream)
+        j12, _ = j1_leg(spg, torch, "kings12x12_d24", 64, 4096, 1024, 2, 1, stream)
+        out["forms"] = {"mixed_learned_proposal": {"kings8x8_d16": j8, "kings12x12_d24": j12},
                         "batching": batching_leg(spg, torch, stream)}
         say("kings12x12_d24")
         out["kings12x12_d24"] = kings12_leg(spg, torch, stream)
@@ -710,6 +743,14 @@ def main():
             "oracle_best_energy": cb["oracle_best_energy"],
             "gpu_search_on_oracle_bmps_best_energy": float(en[0]) if n_o > 0 else None,
             "gpu_search_on_oracle_bmps_n_states": n_o})
+        if prop8 is not None:
+            # the mixed + learned-proposal search on the oracle's boundary MPS
+            env_o32 = spg.env_import(spg.build_peps(inst, stream), wl["chi"], dims_o, T_o,
+                                     np.zeros(R), precision="fp32")
+            n_j = spg.branch_and_bound(env_o32, M, st, en, lp, stream=stream, proposal=prop8,
+                                       kappa=2.0)
+            validity["mixed_proposal_search_on_oracle_bmps_best_energy"] = (
+                float(en[0]) if n_j > 0 else None)
     out["validity"] = validity
     print(json.dumps(out), flush=True)
 

@@ -1080,14 +1080,16 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
       float *Rf = env->Rv.as<float>();
       lp_set_e0(n_anc, chi, Rf + (size_t)C * chi, rstride, s);
       // U_c = A_c R_{c+1} for every ancestor and column: R_c comes from U_c,
-      // and the conditionals of column c read U_c again
+      // and the conditionals of column c read U_c again (the guarded steps
+      // also need R_0 and the scales: Z_b = scale * L^b . R_c)
       for (int c = C - 1; c >= 0; --c) {
         float *Uc = env->Ulp.as<float>() + (size_t)c * M * ldu;
         lp_u_col(t, env->precision, n_anc, Al + ((size_t)r * C + c) * site_sz * eb,
                  Rf + (size_t)(c + 1) * chi, rstride, Uc, ldu, dm[c], dm[c + 1], s);
-        if (c >= 1)
+        if (c >= 1 || guided)
           lp_env_from_u(t, env->precision, r, c, n_anc, env->cfg[cur].as<uint8_t>(), N, Uc, ldu,
-                        Rf + (size_t)c * chi, rstride, dm[c], s);
+                        Rf + (size_t)c * chi, rstride, dm[c], s, guided ? Rsc + c : nullptr,
+                        C + 1);
       }
     } else {
       set_e0(n_anc, chi, Rv + (size_t)C * chi, rstride, s);
@@ -1112,9 +1114,15 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
         // parents are sorted by score: score[0] is the best
         propose(t, r, c, (int)B, cfg, N, score, score, env->sf.as<float>(),
                 prop->prm.as<float>(), prop->H, nullptr, g.bins, g.hist, s);
-        guided_step(t, r, c, (int)B, M, K, cfg, N, Arc, env->L[cur].as<double>(),
-                    env->anc[cur].as<int32_t>(), Rv, rstride, Rsc, score, g, dm[c], dm[c + 1],
-                    s);
+        if (lp)
+          guided_step_lp(t, env->precision, r, c, (int)B, M, K, cfg, N,
+                         env->Ulp.as<float>() + (size_t)c * M * ldu, ldu, env->L[cur].as<float>(),
+                         env->anc[cur].as<int32_t>(), env->Rv.as<float>(), rstride, Rsc, score,
+                         g, dm[c], s);
+        else
+          guided_step(t, r, c, (int)B, M, K, cfg, N, Arc, env->L[cur].as<double>(),
+                      env->anc[cur].as<int32_t>(), Rv, rstride, Rsc, score, g, dm[c], dm[c + 1],
+                      s);
         if (prm->cut_off_prob > 0.0)
           apply_cutoff((int)(B * d), log_cut, g.lkey, s, g.n_list);
         select_topm((int)(B * d), M, g.lkey, env->sel.as<int32_t>(), env->keys.as<uint64_t>(),
@@ -1154,7 +1162,7 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
                        env->anc[cur].as<int32_t>(), env->cand.as<double>(), Alc, c < C - 1,
                        env->cfg[nx].as<uint8_t>(), env->energy[nx].as<double>(),
                        env->score[nx].as<double>(), env->L[nx].as<float>(),
-                       env->anc[nx].as<int32_t>(), dm[c], dm[c + 1], s);
+                       env->anc[nx].as<int32_t>(), dm[c], dm[c + 1], s, sel_score);
       else
         beam_update(t, r, c, (int)Bn, env->sel.as<int32_t>(), N, cfg,
                     env->energy[cur].as<double>(), env->L[cur].as<double>(),
@@ -1216,12 +1224,8 @@ int spg_branch_and_bound(const spg_env_t *cenv, const spg_search_params *prm, in
       return fail(SPG_ERR_INVALID,
                   "spg_branch_and_bound: droplet_energy >= 0 and droplet_hamming >= 0 required");
   }
-  if (prm->proposal) {
-    if (!(prm->kappa > 0.0))
-      return fail(SPG_ERR_INVALID, "spg_branch_and_bound: kappa must be > 0 with a proposal");
-    if (env->precision != SPG_FP64)
-      return fail(SPG_ERR_UNSUPPORTED, "spg_branch_and_bound: the proposal needs an FP64 env");
-  }
+  if (prm->proposal && !(prm->kappa > 0.0))
+    return fail(SPG_ERR_INVALID, "spg_branch_and_bound: kappa must be > 0 with a proposal");
   run_search(env, prm, prm->proposal, nullptr, states_out, energies_out, logp_out, n_out,
              (hipStream_t)stream);
   return SPG_OK;

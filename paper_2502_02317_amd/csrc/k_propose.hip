@@ -10,7 +10,8 @@
 //      children in E, their scores score_b + log(q / Z_b) appended to a
 //      compact list, and the bound score_b + log((max(U_b,0) + eps Z_b) / Z_b)
 //      of every unevaluated child, U_b = Z_b - sum of the evaluated q;
-//   4. k_kth: tau = the M-th best score of the list (-inf if it is shorter);
+//   4. k_tau_bound: tau = a lower bound of the M-th best score of the list
+//      (-inf if it is shorter), the lower edge of the gap bin holding it;
 //   5. k_fallback: parents whose bound reaches tau - margin (or with Z_b <= 0
 //      or a negative evaluated q) get all d children evaluated as in the plain
 //      search (normaliser sum_s max(q, 0)); their list entries are rewritten
@@ -18,10 +19,14 @@
 //   6. the plain search's cut-off and top-M selection run on the list.
 // An unevaluated child of a parent that did not fall back scores below
 // tau - margin, below the true M-th score, so the kept beam is the plain
-// search's.
+// search's.  On a reduced-precision env (k_eval_lp, k_fallback_lp) the exact
+// weights are the plain reduced-precision search's (U products, FP32 L), and
+// Z_b goes through R_c stored in that precision: the relative floor eps and
+// the margin grow to the precision's resolution of Z_b (kEpsLp).
 #include <cfloat>
 #include <climits>
 
+#include "lp_dev.h"
 #include "mlp_dev.h"
 #include "search_dev.h"
 #include "spg_internal.h"
@@ -38,6 +43,9 @@ constexpr int kNBins = 2048;
 constexpr double kBinScale = 64.0;
 constexpr double kEps = 1e-9;      // relative floor of the unevaluated weight
 constexpr double kMargin = 1e-9;   // absolute margin of the bound test (log units)
+// the same two for FP32 and for BF16 envs (R_c rounded to 2^-9), set at the
+// accuracy the reduced-precision search states for its log-marginals
+constexpr double kEpsLp32 = 1e-3, kEpsLpBf16 = 3e-2;
 
 // Per-site features that do not depend on the parent: sf[site][s][0] the
 // look-ahead over the unexplored neighbours, sf[site][s][1] the log one-site
@@ -338,25 +346,98 @@ __global__ __launch_bounds__(256) void k_eval(SearchTabs t, int r, int c, int n_
   }
 }
 
-// tau = the M-th best list score (-inf when the list is shorter than M).
-__global__ __launch_bounds__(1024) void k_kth(const int *n_list, int M, const double *lkey,
-                                              double *tau) {
-  __shared__ unsigned hist[256];
-  __shared__ uint64_t sh_prefix;
-  __shared__ int sh_need;
+// tau = a lower bound of the M-th best list score (-inf when the list is
+// shorter than M): the lower score edge of the gap bin (gap_bin: 64 bins per
+// octave of the gap below the best score) that holds it.  A parent whose
+// bound reaches it falls back, a superset of those whose bound reaches the
+// exact M-th score; one pass over the list.
+__global__ __launch_bounds__(1024) void k_tau_bound(const int *n_list, int M, const double *lkey,
+                                                    double *tau) {
+  __shared__ unsigned gh[kGapBins];
+  __shared__ double wm[16];
+  __shared__ int wsum[16];
+  __shared__ int sh_b;
+  const int tid = threadIdx.x;
   const int n = *n_list;
   if (n < M) {
-    if (threadIdx.x == 0) *tau = -INFINITY;
+    if (tid == 0) *tau = -INFINITY;
     return;
   }
-  auto key_at = [&](int i) { return desc_key(lkey[i]); };
-  uint64_t prefix = 0, pmask = 0;
-  int need = M;
-  for (int shift = 56; shift >= 0; shift -= 8) {
-    radix_digit(n, shift, key_at, pmask, prefix, need, hist, &sh_prefix, &sh_need);
-    pmask |= (255ull << shift);
+  double vmax = -INFINITY;
+  for (int i = tid; i < n; i += 1024) vmax = fmax(vmax, lkey[i]);
+  vmax = wave_max_d(vmax);
+  if ((tid & 63) == 0) wm[tid >> 6] = vmax;
+  for (int b = tid; b < kGapBins; b += 1024) gh[b] = 0u;
+  __syncthreads();
+  vmax = -INFINITY;
+  for (int w = 0; w < 16; ++w) vmax = fmax(vmax, wm[w]);
+  if (!(vmax > -INFINITY)) {
+    if (tid == 0) *tau = -INFINITY;
+    return;
   }
-  if (threadIdx.x == 0) *tau = key_value(prefix);
+  for (int i = tid; i < n; i += 1024) atomicAdd(&gh[gap_bin(vmax, lkey[i])], 1u);
+  __syncthreads();
+  unsigned hb[4];
+  int own = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    hb[j] = gh[4 * tid + j];
+    own += (int)hb[j];
+  }
+  int tot;
+  const int ex = block_excl_scan_count(own, wsum, &tot);
+  if (ex < M && ex + own >= M) {
+    int cum = ex, b = 4 * tid;
+    for (int j = 0; j < 4; ++j) {
+      cum += (int)hb[j];
+      b = 4 * tid + j;
+      if (cum >= M) break;
+    }
+    sh_b = b;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int b = sh_b;
+    // every gap in bins <= b is below the double whose leading bits are bin b + 1
+    const double g_hi = __hiloint2double((int)((unsigned)(b + 1 + ((1023 - 32) << 6)) << 14), 0);
+    *tau = (b >= kGapBins - 1) ? -INFINITY : vmax - g_hi;
+  }
+}
+
+// List entries of a parent evaluated in full: lp[j] = log p(s | b) for s = lane
+// + 64 j; the children of the candidate set overwrite their entries at
+// off[b].., the others are appended.
+__device__ inline void write_full_parent(const SearchTabs &t, int b, double sb,
+                                         const double (&lp)[4], const uint16_t *bins, int js,
+                                         const int32_t *off, const int32_t *cnt, double *lkey,
+                                         int32_t *lid, int *n_list, unsigned long long *stats,
+                                         int lane) {
+  const int d = t.d;
+  const int nb = cnt[b];
+  int extra = 0;
+  if (lane == 0 && d - nb > 0) extra = atomicAdd(n_list, d - nb);
+  extra = __shfl(extra, 0);
+  const int o = off[b];
+  int r_in = 0, r_out = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int s = lane + 64 * j;
+    const bool ok = s < d;
+    const bool ins = ok && in_set(bins, (long)b * d + s, js);
+    const unsigned long long mi = __ballot(ins), mo = __ballot(ok && !ins);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    if (ok) {
+      const int pos = ins ? o + r_in + __popcll(mi & below) : extra + r_out + __popcll(mo & below);
+      lkey[pos] = sb + lp[j];
+      lid[pos] = b * d + s;
+    }
+    r_in += __popcll(mi);
+    r_out += __popcll(mo);
+  }
+  if (lane == 0) {
+    atomicAdd(&stats[0], (unsigned long long)d);
+    atomicAdd(&stats[2], 1ull);
+  }
 }
 
 // Full evaluation of the parents the guard selects, one wavefront per parent.
@@ -423,36 +504,126 @@ __global__ __launch_bounds__(256) void k_fallback(SearchTabs t, int r, int c, in
   const bool dead = !(tot > 0.0);
   double emin = 0.0, lse = 0.0;
   if (dead) local_softmax_norm(t, r, c, cb, lane, emin, lse);
-  const int js = *jstar_p;
-  const int nb = cnt[b];
-  int extra = 0;
-  if (lane == 0 && d - nb > 0) extra = atomicAdd(n_list, d - nb);
-  extra = __shfl(extra, 0);
-  const int o = off[b];
-  int r_in = 0, r_out = 0;
+  double lpv[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int s = lane + 64 * j;
-    const bool ok = s < d;
-    const bool ins = ok && in_set(bins, (long)b * d + s, js);
-    const unsigned long long mi = __ballot(ins), mo = __ballot(ok && !ins);
-    const unsigned long long below = (1ull << lane) - 1ull;
-    if (ok) {
+    double lp = -INFINITY;
+    if (s < d) {
       const double q = myq[j];
-      double lp = (q > 0.0 && tot > 0.0) ? log(q) - ltot : -INFINITY;
+      lp = (q > 0.0 && tot > 0.0) ? log(q) - ltot : -INFINITY;
       if (!(lp == lp)) lp = -INFINITY;
       if (dead) lp = -t.beta * (delta_energy(t, r, c, cb, s) - emin) - lse;
-      const int pos = ins ? o + r_in + __popcll(mi & below) : extra + r_out + __popcll(mo & below);
-      lkey[pos] = sb + lp;
-      lid[pos] = b * d + s;
     }
-    r_in += __popcll(mi);
-    r_out += __popcll(mo);
+    lpv[j] = lp;
+  }
+  write_full_parent(t, b, sb, lpv, bins, *jstar_p, off, cnt, lkey, lid, n_list, stats, lane);
+}
+
+// Exact q(b,s) on the candidate set of a reduced-precision env, one
+// wavefront per parent: q = exp(log g(s) - max_s log g) * (L^b . U^{anc}[:, s])
+// (the couplings relative to their maximum, as in R_c) and
+// Z_b = Rsc * (L^b . R_c); list entries and bounds as k_eval.
+__global__ __launch_bounds__(256) void k_eval_lp(SearchTabs t, int r, int c, int n_beam,
+                                                 const uint8_t *cfg, int N, const float *U,
+                                                 long ldu, const float *L, const int32_t *anc,
+                                                 const float *Rf, long rstride,
+                                                 const double *Rsc, const double *score,
+                                                 const uint16_t *bins, const int *jstar_p,
+                                                 double eps, double *lkey, int32_t *lid,
+                                                 int *n_list, double *bound, int32_t *off,
+                                                 int32_t *cnt, unsigned long long *stats, int cl) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = blockIdx.x * kWaves + w;
+  if (b >= n_beam) return;                 // no barrier below
+  const int chi = t.chi, d = t.d, C = t.cols;
+  const int a = anc[b];
+  const float *Lb = L + (long)b * chi;
+  const float *Ua = U + (long)a * ldu;
+  const float *Rc = Rf + (long)a * rstride + (long)c * chi;
+  float zp = 0.f;
+  for (int al = lane; al < cl; al += 64) zp = fmaf(Lb[al], Rc[al], zp);
+  const double Z = Rsc[(long)a * (C + 1) + c] * (double)wave_sum_f(zp);
+  const uint8_t *cb = cfg + (long)b * N;
+  double lmax = -INFINITY;
+  for (int s = lane; s < d; s += 64) lmax = fmax(lmax, log_field(t, r, c, cb, s));
+  lmax = wave_max_d(lmax);
+  const int js = *jstar_p;
+  unsigned long long mask[4];
+  int nb = 0;
+  for (int j = 0; j < 4; ++j) {
+    const int s = lane + 64 * j;
+    mask[j] = __ballot(s < d && in_set(bins, (long)b * d + s, js));
+    nb += __popcll(mask[j]);
+  }
+  int base = 0;
+  if (lane == 0 && nb > 0) base = atomicAdd(n_list, nb);
+  base = __shfl(base, 0);
+  const double sb = score[b];
+  double sumq = 0.0;
+  bool neg = false;
+  double myq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    unsigned long long m = mask[j];
+    while (m) {
+      const int l = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      const int s = l + 64 * j;
+      float part = 0.f;
+      for (int al = lane; al < cl; al += 64) part = fmaf(Lb[al], Ua[(long)al * d + s], part);
+      const double q = exp(log_field(t, r, c, cb, s) - lmax) * (double)wave_sum_f(part);
+      sumq += q;
+      neg = neg || (q < 0.0);
+      if (lane == l) myq[j] = q;
+    }
+  }
+  const bool mark = !(Z > 0.0) || !isfinite(Z) || neg;
+  const double lz = log(Z);
+  int rank = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const unsigned long long m = mask[j];
+    if ((m >> lane) & 1ull) {
+      const int pos = base + rank + __popcll(m & ((1ull << lane) - 1ull));
+      const double q = myq[j];
+      lkey[pos] = (!mark && q > 0.0) ? sb + (log(q) - lz) : -INFINITY;
+      lid[pos] = b * d + lane + 64 * j;
+    }
+    rank += __popcll(m);
   }
   if (lane == 0) {
-    atomicAdd(&stats[0], (unsigned long long)d);
-    atomicAdd(&stats[2], 1ull);
+    double bd;
+    if (mark) bd = INFINITY;
+    else if (nb == d) bd = -INFINITY;
+    else bd = sb + log((fmax(Z - sumq, 0.0) + eps * Z) / Z);
+    bound[b] = bd;
+    off[b] = base;
+    cnt[b] = nb;
+    atomicAdd(&stats[0], (unsigned long long)nb);
   }
+}
+
+// Full evaluation of the parents the guard selects on a reduced-precision env:
+// the plain reduced-precision conditionals (lp_parent_logp).
+__global__ __launch_bounds__(256) void k_fallback_lp(SearchTabs t, int r, int c, int n_beam,
+                                                     const uint8_t *cfg, int N, const float *U,
+                                                     long ldu, const float *L,
+                                                     const int32_t *anc, const double *score,
+                                                     const uint16_t *bins, const int *jstar_p,
+                                                     const double *tau_p, double margin,
+                                                     const double *bound, const int32_t *off,
+                                                     const int32_t *cnt, double *lkey,
+                                                     int32_t *lid, int *n_list,
+                                                     unsigned long long *stats, int cl) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = blockIdx.x * kWaves + w;
+  if (b >= n_beam) return;                 // no barrier below
+  const double bd = bound[b];
+  if (!((bd == INFINITY) || (cnt[b] < t.d && bd >= *tau_p - margin))) return;
+  double lp[4];
+  lp_parent_logp(t, r, c, b, cfg, N, U, ldu, L, anc, cl, lane, lp);
+  write_full_parent(t, b, score[b], lp, bins, *jstar_p, off, cnt, lkey, lid, n_list, stats, lane);
 }
 
 // Maximum of n doubles (one block) -> *out.
@@ -505,11 +676,34 @@ void guided_step(const SearchTabs &t, int r, int c, int n_beam, int M, int K, co
                        g.n_list, g.bound, g.off, g.cnt, g.stats);
     SPG_CHECK_LAUNCH();
   }
-  hipLaunchKernelGGL(k_kth, dim3(1), dim3(1024), 0, s, g.n_list, M, g.lkey, g.tau);
+  hipLaunchKernelGGL(k_tau_bound, dim3(1), dim3(1024), 0, s, g.n_list, M, g.lkey, g.tau);
   SPG_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_fallback, dim3(nblk(n_beam, kWaves)), dim3(256), 0, s, t, r, c, n_beam,
                      cfg, N, A_rc, L, anc, Rv, rstride, score, g.bins, g.jstar, g.tau, g.bound,
                      g.off, g.cnt, g.lkey, g.lid, g.n_list, g.stats);
+  SPG_CHECK_LAUNCH();
+}
+
+void guided_step_lp(const SearchTabs &t, int precision, int r, int c, int n_beam, int M, int K,
+                    const uint8_t *cfg, int N, const float *U, long ldu, const float *L,
+                    const int32_t *anc, const float *Rf, long rstride, const double *Rsc,
+                    const double *score, GuideWork &g, int cl, hipStream_t s) {
+  bc_single("guided_step_lp");
+  const double eps = (precision == SPG_BF16) ? kEpsLpBf16 : kEpsLp32;
+  hipLaunchKernelGGL(k_tau_pred, dim3(1), dim3(64), 0, s, g.hist, K, g.jstar, g.n_list);
+  SPG_CHECK_LAUNCH();
+  {
+    KTimer kt_("guided_eval", s, 2.0 * n_beam * cl * t.d);
+    hipLaunchKernelGGL(k_eval_lp, dim3(nblk(n_beam, kWaves)), dim3(256), 0, s, t, r, c, n_beam,
+                       cfg, N, U, ldu, L, anc, Rf, rstride, Rsc, score, g.bins, g.jstar, eps,
+                       g.lkey, g.lid, g.n_list, g.bound, g.off, g.cnt, g.stats, cl);
+    SPG_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(k_tau_bound, dim3(1), dim3(1024), 0, s, g.n_list, M, g.lkey, g.tau);
+  SPG_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_fallback_lp, dim3(nblk(n_beam, kWaves)), dim3(256), 0, s, t, r, c, n_beam,
+                     cfg, N, U, ldu, L, anc, score, g.bins, g.jstar, g.tau, eps, g.bound, g.off,
+                     g.cnt, g.lkey, g.lid, g.n_list, g.stats, cl);
   SPG_CHECK_LAUNCH();
 }
 

@@ -5,6 +5,8 @@
 // cannot underflow on them; log-probabilities are added to FP64 scores.
 #include <cfloat>
 
+#include "lp_dev.h"
+#include "mlp_dev.h"
 #include "search_dev.h"
 #include "spg_internal.h"
 
@@ -13,45 +15,6 @@ namespace spg {
 namespace {
 
 inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
-
-__device__ __forceinline__ float wave_sum_f(float v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ float wave_max_f(float v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// round-to-nearest-even FP32 -> BF16 (finite inputs)
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
-template <class T> __device__ __forceinline__ float ld(const T *p, long i);
-template <> __device__ __forceinline__ float ld<float>(const float *p, long i) { return p[i]; }
-template <> __device__ __forceinline__ float ld<uint16_t>(const uint16_t *p, long i) {
-  return bf2f(p[i]);
-}
-
-// vector store with the form's rounding
-__device__ __forceinline__ float vround(float v, int bf16) { return bf16 ? bf2f(f2bf(v)) : v; }
-
-// log g^b_c(s): log of the couplings of x_{r,c} = s to the fixed row above
-__device__ __forceinline__ double log_field(const SearchTabs &t, int r, int c, const uint8_t *cb,
-                                            int s) {
-  if (r == 0) return 0.0;
-  const int C = t.cols, d = t.d;
-  const uint8_t *up = cb + (r - 1) * C;
-  const long dd = (long)d * d;
-  double g = t.W_v[((long)(r - 1) * C + c) * dd + up[c] * d + s];
-  if (c > 0) g *= t.W_d[((long)(r - 1) * (C - 1) + (c - 1)) * dd + up[c - 1] * d + s];
-  if (c < C - 1) g *= t.W_a[((long)(r - 1) * (C - 1) + c) * dd + up[c + 1] * d + s];
-  return log(g);
-}
 
 constexpr int kW = 4;
 
@@ -116,12 +79,14 @@ __global__ __launch_bounds__(256) void k_u_mfma(int n_anc, int npair, int cr, in
   }
 }
 
-// R^a_c[al] = sum_s g^a_c(s) U^a[al][s], normalised by its largest |entry|
-// (one wavefront per ancestor; couplings relative to their maximum over s).
+// R^a_c[al] = sum_s g^a_c(s) U^a[al][s], normalised by its largest |entry| m,
+// which goes to sc[a * sc_stride] when sc is given (one wavefront per
+// ancestor; couplings relative to their maximum over s).
 __global__ __launch_bounds__(256) void k_env_from_u(SearchTabs t, int r, int c, int n_anc,
                                                     const uint8_t *cfg, int N, const float *U,
                                                     long ldu, float *Rout, long rstride,
-                                                    int bf16, int cl) {
+                                                    int bf16, int cl, double *sc,
+                                                    long sc_stride) {
   __shared__ float gs[kW][256];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int a0 = blockIdx.x * kW + w;
@@ -159,12 +124,11 @@ __global__ __launch_bounds__(256) void k_env_from_u(SearchTabs t, int r, int c, 
     const int al = lane + 64 * h;
     if (al < chi) Rout[a * rstride + al] = (al < cl) ? vround(v[h] * inv, bf16) : 0.f;
   }
+  if (sc && lane == 0) sc[(long)a * sc_stride] = (double)m;
 }
 
-// out[b*d+s] = (add_score ? score[b] : 0) + log p(s | b), with
-// q(b, s) = g^b(s) sum_al L^b[al] U^{anc(b)}[al][s] (one wavefront per beam
-// state).  For d <= 64 the lanes form 64 / d groups, group j summing the al
-// = j mod (64 / d) terms, and lane s adds the groups' sums in group order.
+// out[b*d+s] = (add_score ? score[b] : 0) + log p(s | b) (lp_parent_logp, one
+// wavefront per beam state).
 __global__ __launch_bounds__(256) void k_marg_from_u(SearchTabs t, int r, int c, int n_beam,
                                                      const uint8_t *cfg, int N, const float *U,
                                                      long ldu, const float *L,
@@ -173,58 +137,12 @@ __global__ __launch_bounds__(256) void k_marg_from_u(SearchTabs t, int r, int c,
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int b = blockIdx.x * kW + w;
   if (b >= n_beam) return;                    // no barrier below
-  const int chi = t.chi, d = t.d;
-  const float *Ua = U + (long)anc[b] * ldu;
-  const float *Lb = L + (long)b * chi;
-  float q[4] = {0.f, 0.f, 0.f, 0.f};
-  if (d <= 64) {
-    const int G = 64 / d, s = lane % d, j = lane / d;
-    float part = 0.f;
-    if (j < G)
-      for (int al = j; al < cl; al += G) part = fmaf(Lb[al], Ua[(long)al * d + s], part);
-    float tot = 0.f;
-    for (int jj = 0; jj < G; ++jj) tot += __shfl(part, s + jj * d, 64);
-    q[0] = tot;
-  } else {
-    for (int h = 0; h < 4; ++h) {
-      const int s = lane + 64 * h;
-      if (s >= d) continue;
-      float acc = 0.f;
-      for (int al = 0; al < cl; ++al) acc = fmaf(Lb[al], Ua[(long)al * d + s], acc);
-      q[h] = acc;
-    }
-  }
-  const uint8_t *cb = cfg + (long)b * N;
-  float lq[4];
-  float mx = -INFINITY;
-  for (int h = 0; h < 4; ++h) {
-    const int s = lane + 64 * h;
-    lq[h] = -INFINITY;
-    if (s >= d) continue;
-    // negative q (truncation error) = probability 0
-    lq[h] = (q[h] > 0.f) ? (float)log_field(t, r, c, cb, s) + logf(q[h]) : -INFINITY;
-    mx = fmaxf(mx, lq[h]);
-  }
-  mx = wave_max_f(mx);
-  if (!(mx > -INFINITY)) {                 // no child with positive weight
-    double emin, lse;
-    local_softmax_norm(t, r, c, cb, lane, emin, lse);
-    const double base = add_score ? score[b] : 0.0;
-    for (int s = lane; s < d; s += 64)
-      out[(long)b * d + s] = base + (-t.beta * (delta_energy(t, r, c, cb, s) - emin) - lse);
-    return;
-  }
-  float se = 0.f;
-  for (int h = 0; h < 4; ++h)
-    if (lane + 64 * h < d && lq[h] > -INFINITY) se += expf(lq[h] - mx);
-  se = wave_sum_f(se);
-  const float lse = mx + logf(se);
+  double lp[4];
+  lp_parent_logp(t, r, c, b, cfg, N, U, ldu, L, anc, cl, lane, lp);
   const double base = add_score ? score[b] : 0.0;
   for (int h = 0; h < 4; ++h) {
     const int s = lane + 64 * h;
-    if (s >= d) continue;
-    const float lp = (lq[h] > -INFINITY && mx > -INFINITY) ? lq[h] - lse : -INFINITY;
-    out[(long)b * d + s] = base + (double)lp;
+    if (s < t.d) out[(long)b * t.d + s] = base + lp[h];
   }
 }
 
@@ -236,7 +154,8 @@ __global__ __launch_bounds__(256) void k_beam_update_lp(SearchTabs t, int r, int
                                                         const double *cand, const T *A,
                                                         int update_L, uint8_t *cfg_o,
                                                         double *energy_o, double *score_o,
-                                                        float *L_o, int32_t *anc_o, int bf16) {
+                                                        float *L_o, int32_t *anc_o, int bf16,
+                                                        const double *sel_score) {
   __shared__ float Ls[kW][kMaxChi];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j0 = blockIdx.x * kW + w;
@@ -262,7 +181,7 @@ __global__ __launch_bounds__(256) void k_beam_update_lp(SearchTabs t, int r, int
       if (c < C - 1) e += t.E_a[((long)(r - 1) * (C - 1) + c) * dd + up[c + 1] * d + s];
     }
     energy_o[j] = energy[b] + e;
-    score_o[j] = cand[id];
+    score_o[j] = sel_score ? sel_score[j] : cand[id];
     anc_o[j] = anc[b];
   }
   if (!update_L) return;
@@ -376,7 +295,7 @@ void lp_u_col(const SearchTabs &t, int precision, int n_anc, const void *A_rc,
 
 void lp_env_from_u(const SearchTabs &t, int precision, int r, int c, int n_anc,
                    const uint8_t *cfg, int N, const float *U, long ldu, float *Rout, long rstride,
-                   int cl, hipStream_t s) {
+                   int cl, hipStream_t s, double *sc, long sc_stride) {
   bc_single("lp_env_from_u");
   if (n_anc <= 0) return;
   if (t.d > 256 || cl > 128) {
@@ -385,7 +304,7 @@ void lp_env_from_u(const SearchTabs &t, int precision, int r, int c, int n_anc,
   }
   KTimer kt_("right_env", s, 2.0 * n_anc * cl * t.d);
   hipLaunchKernelGGL(k_env_from_u, dim3(nblk(n_anc, kW)), dim3(256), 0, s, t, r, c, n_anc, cfg,
-                     N, U, ldu, Rout, rstride, precision == SPG_BF16 ? 1 : 0, cl);
+                     N, U, ldu, Rout, rstride, precision == SPG_BF16 ? 1 : 0, cl, sc, sc_stride);
   SPG_CHECK_LAUNCH();
 }
 
@@ -408,18 +327,18 @@ void lp_beam_update(const SearchTabs &t, int precision, int r, int c, int n_new,
                     const int32_t *sel, int N, const uint8_t *cfg, const double *energy,
                     const float *L, const int32_t *anc, const double *cand, const void *A_rc,
                     int update_L, uint8_t *cfg_o, double *energy_o, double *score_o, float *L_o,
-                    int32_t *anc_o, int cl, int cr, hipStream_t s) {
+                    int32_t *anc_o, int cl, int cr, hipStream_t s, const double *sel_score) {
   bc_single("lp_beam_update");
   if (n_new <= 0) return;
   KTimer kt_("beam_update", s, 2.0 * n_new * cl * cr);
   if (precision == SPG_FP32)
     hipLaunchKernelGGL(k_beam_update_lp<float>, dim3(nblk(n_new, kW)), dim3(256), 0, s, t, r, c,
                        n_new, sel, N, cfg, energy, L, anc, cand, (const float *)A_rc, update_L,
-                       cfg_o, energy_o, score_o, L_o, anc_o, 0);
+                       cfg_o, energy_o, score_o, L_o, anc_o, 0, sel_score);
   else
     hipLaunchKernelGGL(k_beam_update_lp<uint16_t>, dim3(nblk(n_new, kW)), dim3(256), 0, s, t, r,
                        c, n_new, sel, N, cfg, energy, L, anc, cand, (const uint16_t *)A_rc,
-                       update_L, cfg_o, energy_o, score_o, L_o, anc_o, 1);
+                       update_L, cfg_o, energy_o, score_o, L_o, anc_o, 1, sel_score);
   SPG_CHECK_LAUNCH();
 }
 

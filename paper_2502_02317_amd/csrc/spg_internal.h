@@ -287,6 +287,14 @@ void guided_step(const SearchTabs &t, int r, int c, int n_beam, int M, int K, co
                  int N, const double *A_rc, const double *L, const int32_t *anc, const double *Rv,
                  long rstride, const double *Rsc, const double *score, GuideWork &g, int cl,
                  int cr, hipStream_t s);
+// The same guarded step on a reduced-precision env: exact weights from the
+// column's U products and FP32 L (the plain reduced-precision search's
+// arithmetic), Z_b = Rsc * (L^b . R_c) with R_c in the env's precision; the
+// guard's relative floor and margin are those of that precision.
+void guided_step_lp(const SearchTabs &t, int precision, int r, int c, int n_beam, int M, int K,
+                    const uint8_t *cfg, int N, const float *U, long ldu, const float *L,
+                    const int32_t *anc, const float *Rf, long rstride, const double *Rsc,
+                    const double *score, GuideWork &g, int cl, hipStream_t s);
 void max_of(int n, const double *v, double *out, hipStream_t s);
 // Network evaluation and training (k_mlp.hip); deterministic reductions.
 void mlp_forward(int n_beam, int d, const float *feats, const float *prm, int H, float *logp,
@@ -311,9 +319,10 @@ void lp_u_col(const SearchTabs &t, int precision, int n_anc, const void *A_rc,
               const float *Rnext, long rstride, float *U, long ldu, int cl, int cr,
               hipStream_t s);
 // R^a_c from U and the couplings to the fixed row (normalised per ancestor).
+// sc (optional): the normalisation m of each ancestor's R_c, at sc[a * sc_stride]
 void lp_env_from_u(const SearchTabs &t, int precision, int r, int c, int n_anc,
                    const uint8_t *cfg, int N, const float *U, long ldu, float *Rout, long rstride,
-                   int cl, hipStream_t s);
+                   int cl, hipStream_t s, double *sc = nullptr, long sc_stride = 0);
 // Conditionals of every beam state from U of its ancestor and its L.
 void lp_marginals_u(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
                     const float *U, long ldu, const float *L, const int32_t *anc,
@@ -322,7 +331,8 @@ void lp_beam_update(const SearchTabs &t, int precision, int r, int c, int n_new,
                     const int32_t *sel, int N, const uint8_t *cfg, const double *energy,
                     const float *L, const int32_t *anc, const double *cand, const void *A_rc,
                     int update_L, uint8_t *cfg_o, double *energy_o, double *score_o, float *L_o,
-                    int32_t *anc_o, int cl, int cr, hipStream_t s);
+                    int32_t *anc_o, int cl, int cr, hipStream_t s,
+                    const double *sel_score = nullptr);
 void lp_advance_L(const SearchTabs &t, int precision, int r, int c, int n, const uint8_t *cfg,
                   int N, const void *A_rc, float *L, hipStream_t s);
 

@@ -254,7 +254,47 @@ def test_guided_search_argument_errors():
     with pytest.raises(spg.SpgError) as e:
         spg.branch_and_bound(env, M, st, en, en.clone(), proposal=prop, kappa=0.0)
     assert e.value.code == -1
-    env32, _ = spg.boundary_mps(peps, 8, precision="fp32", want_logZ=False)
-    with pytest.raises(spg.SpgError) as e:
-        spg.branch_and_bound(env32, M, st, en, en.clone(), proposal=prop, kappa=2.0)
-    assert e.value.code == -5
+
+
+
+# relative floor of the unevaluated weight and margin of the guard on
+# reduced-precision envs (the FP32 / BF16 resolution of Z_b)
+LP_TOL = {"fp32": 1e-3, "bf16": 3e-2}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("name,seed,chi,M", [("square4x4_d2", 0, 16, 64),
+                                             ("rand3x5_d4", 0, 8, 50),
+                                             ("rand2x3_d70", 0, 4, 300)])
+def test_guided_search_reduced_precision_keeps_the_plain_beam(precision, name, seed, chi, M):
+    """The proposal on an FP32 or BF16 env (trained on the FP64 env's exact
+    marginals): against the plain search on the same env, the same number of
+    states, the best state's energy, and every shared state's log-probability
+    to the guard's tolerance; states in one beam only sit at the cut (within
+    the tolerance of the last score).  A planted bad network forces fallbacks
+    and keeps the same beam."""
+    inst = _search_inst(name, seed)
+    peps, env64, _ = _env(inst, chi)
+    env, _ = spg.boundary_mps(peps, chi, precision=precision, want_logZ=False)
+    tol = LP_TOL[precision]
+    plain = _run(env, inst, M)
+    trained = spg.Proposal(hidden=32, seed=1)
+    trained.train(env64, epochs=10, learning_rate=1e-2, max_states=M)
+    bad = spg.Proposal(hidden=32, seed=2)
+    bad.set_params(_reversed(bad))
+    for label, prop, kappa in [("trained", trained, 2.0), ("reversed", bad, 2.0),
+                               ("kappa_tiny", trained, 1e-6)]:
+        g = _run(env, inst, M, proposal=prop, kappa=kappa)
+        print(name, precision, label, "exact/resolved/fallback =", g[3])
+        assert len(g[0]) == len(plain[0])
+        assert abs(g[1][0] - plain[1][0]) <= 1e-9
+        ka = {tuple(x): l for x, l in zip(map(tuple, plain[0]), plain[2])}
+        kb = {tuple(x): l for x, l in zip(map(tuple, g[0]), g[2])}
+        last = min(plain[2].min(), g[2].min())
+        for k in ka.keys() ^ kb.keys():
+            l = ka[k] if k in ka else kb[k]
+            assert len(plain[0]) == M and l <= last + 2 * tol, (label, l, last)
+        for k in ka.keys() & kb.keys():
+            assert abs(ka[k] - kb[k]) <= tol, (label, ka[k], kb[k])
+        if label == "kappa_tiny":
+            assert g[3][2] > 0
