@@ -125,8 +125,11 @@ int spg_build_peps(const spg_instance_desc *desc, void *stream, spg_peps_t **out
 /* Boundary-MPS contraction of the PEPS (Sec. 2, Fig. 1(d); Sec. 2.1 names the
  * boundary-MPS approach): for r = rows-1 .. 0 the row's transfer operator is
  * applied to the previous boundary MPS and compressed to bond dimension chi.
- * The result (rows x cols tensors of chi_c x d x chi_{c+1}, right-canonical,
- * plus per-row log-scales) is held in a new env.  When log_Z_out (HOST) is not
+ * The result (rows x cols tensors of chi_c x d x chi_{c+1}, plus per-row
+ * log-scales) is held in a new env.  The bottom row is its exact chain of
+ * nearest-neighbour factors at bond d (chi >= d); every other row has a unit-norm
+ * centre at column 0, or at column 1 when column 0 kept its natural basis (at
+ * most chi states, no rotation), with right isometries beyond it.  When log_Z_out (HOST) is not
  * NULL the call synchronises the stream and writes the estimate of log Z.
  * Errors: SPG_ERR_INVALID, SPG_ERR_UNSUPPORTED (chi, precision), SPG_ERR_OOM,
  * SPG_ERR_HIP, SPG_ERR_NONFINITE (log Z requested and not finite). */
@@ -168,15 +171,17 @@ int spg_marginals_noalloc(const spg_env_t *env, int32_t site, int32_t n_beam,
  * configurations (ties: parent position, then state), and returns the final
  * beam: the states with a finite log-probability first, sorted by energy
  * ascending (ties: beam position), then the beam's other slots.
- * With params->proposal set (FP64 envs only, else SPG_ERR_UNSUPPORTED), each
- * step first ranks the children with the network, evaluates exactly only the
- * best-ranked ones (about kappa * max_states), and bounds every other child
- * of parent b by b's unevaluated weight Z_b - sum of its evaluated q, where
- * Z_b = L^b R_c comes from the right environments at no extra cost; parents
- * whose bound reaches the max_states-th exact score are evaluated in full.
- * The finite part of the result is then the plain search's whatever the
- * network predicts (exact up to rounding while no conditional weight is
- * negative, i.e. outside the truncation-error regime).  Outputs:
+ * With params->proposal set, each step first ranks the children with the
+ * network, evaluates exactly only the best-ranked ones (about kappa *
+ * max_states), and bounds every other child of parent b by b's unevaluated
+ * weight Z_b - sum of its evaluated q (plus a relative floor: 1e-9 of Z_b on
+ * FP64 envs, 1e-3 on FP32 and 3e-2 on BF16 ones, where Z_b is known to that
+ * precision), where Z_b = L^b R_c comes from the right environments at no
+ * extra cost; parents whose bound reaches a lower bound of the
+ * max_states-th exact score are evaluated in full.  The finite part of the
+ * result is then the plain search's whatever the network predicts (exact up
+ * to the floor while no conditional weight is negative, i.e. outside the
+ * truncation-error regime).  Outputs:
  *   states_out   DEVICE int32   [max_states][rows*cols]
  *   energies_out DEVICE float64 [max_states]  (Eq. (1), recomputed in FP64)
  *   logp_out     DEVICE float64 [max_states]  (accumulated log-probability)
