@@ -1153,7 +1153,7 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
           apply_cutoff((int)(B * d), log_cut, env->cand.as<double>(), s);
         select_topm((int)(B * d), M, env->cand.as<double>(), env->sel.as<int32_t>(),
                     env->keys.as<uint64_t>(), env->ids.as<int32_t>(), s, nullptr, nullptr,
-                    nullptr, env->selws.p, (long)M * d);
+                    nullptr, env->selws.p, (long)M * d, score);   // no child above score[0]
       }
       const int nx = cur ^ 1;
       if (lp)

@@ -369,7 +369,8 @@ constexpr int kSelBucket = 64;
 __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, int M,
                                                 const double *cand, const int32_t *cid,
                                                 int32_t *sel, double *sel_score, uint64_t *kw,
-                                                int32_t *iw, long ist) {
+                                                int32_t *iw, long ist, unsigned *gclear,
+                                                int *cclear) {
   SPG_INST(n_dev);
   SPG_INST(cand);
   SPG_INST(cid);
@@ -389,6 +390,13 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
   __shared__ int32_t sid[kSelLdsSort];
   const int tid = threadIdx.x;
   const int n = n_dev ? *n_dev : n_host;
+  if (gclear) {
+    // after the multi-workgroup front end: its histogram and survivor count
+    // (n_dev) start from zero at its next call
+    __syncthreads();                     // every thread has read n
+    for (int b = tid; b < kGapBins; b += 1024) gclear[b] = 0u;
+    if (tid == 0) *cclear = 0;
+  }
   if (n <= 0) return;
   const int Me = (M < n) ? M : n;
   int p2 = 1;
@@ -783,22 +791,29 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
 }
 
 // ---- top-M for more candidates than the one-workgroup select holds in
-// registers: the gap histogram over many workgroups (the least key, then the
-// histogram with integer atomics, whose totals do not depend on their order),
-// then every workgroup finds the same boundary bin b* and appends its keys in
-// bins <= b* to a survivor list (in any order); k_select on the survivors
-// (their scores and original indices) sorts them and writes sel and sel_score.
+// registers: the gap histogram over many workgroups (integer atomics, whose
+// totals do not depend on their order), relative to the best score or to a
+// bound above it that the caller knows (the best parent's score: no child
+// scores above it), and the last workgroup to finish finds the boundary bin
+// b*; then every workgroup appends its scores in bins <= b* to a survivor list
+// (in any order, one atomic per workgroup); k_select on the survivors (their
+// scores and original indices) orders them and writes sel and sel_score, and
+// clears the histogram and the count for the next call.
 struct GselState {
   unsigned long long kmin;
-  int count;
+  int count, bstar;
+  unsigned done;
   int pad;
 };
+
+__device__ __forceinline__ double nan_to_ninf(double v) { return (v == v) ? v : -INFINITY; }
 
 __global__ __launch_bounds__(1024) void k_gsel_init(GselState *st, unsigned *gh) {
   for (int b = threadIdx.x; b < kGapBins; b += 1024) gh[b] = 0u;
   if (threadIdx.x == 0) {
     st->kmin = ~0ull;
     st->count = 0;
+    st->done = 0u;
   }
 }
 
@@ -812,26 +827,28 @@ __global__ __launch_bounds__(256) void k_gsel_min(int n, const double *cand, Gse
   if ((threadIdx.x & 63) == 0) atomicMin(&st->kmin, (unsigned long long)lo);
 }
 
-__global__ __launch_bounds__(256) void k_gsel_hist(int n, const double *cand, const GselState *st,
+__global__ __launch_bounds__(256) void k_gsel_hist(int n, int Me, const double *cand,
+                                                   const double *vref, GselState *st,
                                                    unsigned *gh) {
   __shared__ unsigned h[kGapBins];
-  for (int b = threadIdx.x; b < kGapBins; b += 256) h[b] = 0u;
-  __syncthreads();
-  const double vmax = key_value(st->kmin);
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
-    atomicAdd(&h[gap_bin(vmax, key_value(desc_key(cand[i])))], 1u);
-  __syncthreads();
-  for (int b = threadIdx.x; b < kGapBins; b += 256)
-    if (h[b]) atomicAdd(&gh[b], h[b]);
-}
-
-__global__ __launch_bounds__(256) void k_gsel_compact(int n, int Me, const double *cand,
-                                                      GselState *st, const unsigned *gh,
-                                                      double *cs, int32_t *is) {
   __shared__ int wsum[4];
-  __shared__ int sh_b;
-  const int tid = threadIdx.x, lane = tid & 63;
-  // boundary bin: thread t owns bins 16t..16t+15
+  __shared__ int last;
+  const int tid = threadIdx.x;
+  for (int b = tid; b < kGapBins; b += 256) h[b] = 0u;
+  __syncthreads();
+  const double vmax = vref ? *vref : key_value(st->kmin);
+  for (int i = blockIdx.x * 256 + tid; i < n; i += gridDim.x * 256)
+    atomicAdd(&h[gap_bin(vmax, nan_to_ninf(cand[i]))], 1u);
+  __syncthreads();
+  for (int b = tid; b < kGapBins; b += 256)
+    if (h[b]) atomicAdd(&gh[b], h[b]);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) last = (atomicAdd(&st->done, 1u) == gridDim.x - 1) ? 1 : 0;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // the last workgroup: the boundary bin from the complete histogram
   unsigned hb[16];
   int own = 0;
 #pragma unroll
@@ -848,23 +865,40 @@ __global__ __launch_bounds__(256) void k_gsel_compact(int n, int Me, const doubl
       b = 16 * tid + j;
       if (cum >= Me) break;
     }
-    sh_b = b;
+    st->bstar = b;
   }
+  if (tid == 0) st->done = 0u;
+}
+
+// per = scores per thread; workgroup x covers [x * 256 * per, (x + 1) * 256 * per)
+__global__ __launch_bounds__(256) void k_gsel_compact(int n, int per, const double *cand,
+                                                      const double *vref, GselState *st,
+                                                      double *cs, int32_t *is) {
+  __shared__ int wsum[4];
+  __shared__ int sh_base;
+  const int tid = threadIdx.x;
+  const int bstar = st->bstar;
+  const double vmax = vref ? *vref : key_value(st->kmin);
+  const int i0 = blockIdx.x * 256 * per + tid;
+  int cnt = 0;
+  for (int k = 0; k < per; ++k) {
+    const int i = i0 + 256 * k;
+    if (i < n && gap_bin(vmax, nan_to_ninf(cand[i])) <= bstar) ++cnt;
+  }
+  int tot;
+  int pos = block_excl_scan_count(cnt, wsum, &tot);
+  if (tid == 0) sh_base = (tot > 0) ? atomicAdd(&st->count, tot) : 0;
   __syncthreads();
-  const int bstar = sh_b;
-  const double vmax = key_value(st->kmin);
-  // survivors appended a wavefront at a time
-  for (int c0 = blockIdx.x * 256 + (tid & ~63); c0 < n; c0 += gridDim.x * 256) {
-    const int i = c0 + lane;
-    const bool f = (i < n) && gap_bin(vmax, key_value(desc_key(cand[i]))) <= bstar;
-    const unsigned long long bal = __ballot(f);
-    int base = 0;
-    if (lane == 0 && bal) base = atomicAdd(&st->count, __popcll(bal));
-    base = __shfl(base, 0);
-    if (f) {
-      const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
-      cs[pos] = cand[i];
-      is[pos] = i;
+  pos += sh_base;
+  for (int k = 0; k < per; ++k) {
+    const int i = i0 + 256 * k;
+    if (i < n) {
+      const double v = cand[i];
+      if (gap_bin(vmax, nan_to_ninf(v)) <= bstar) {
+        cs[pos] = v;
+        is[pos] = i;
+        ++pos;
+      }
     }
   }
 }
@@ -1301,29 +1335,35 @@ size_t select_ws_bytes(long n_cap) {
 
 void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *keys_work,
                  int32_t *ids_work, hipStream_t s, const int *n_dev, const int32_t *cid,
-                 double *sel_score, void *big_ws, long ws_cap) {
+                 double *sel_score, void *big_ws, long ws_cap, const double *vref) {
   KTimer kt_("select_topm", s, (cid ? 12.0 : 8.0) * n_cand + 4.0 * (M < n_cand ? M : n_cand));
   const int Me = (M < n_cand) ? M : n_cand;
   if (big_ws && !n_dev && !cid && g_bc.n == 1 && n_cand > kSelRegKeys * 1024 && Me < n_cand &&
       Me >= 1 && n_cand <= ws_cap) {
-    // workspace: state (256 B), histogram, survivors' scores and indices [n_cand]
+    // workspace: state (256 B), histogram, survivors' scores and indices [n_cand];
+    // the histogram and the count are zero at entry (zero-filled allocation, then
+    // cleared by the last k_select of each call)
     GselState *st = reinterpret_cast<GselState *>(big_ws);
     unsigned *gh = reinterpret_cast<unsigned *>(static_cast<char *>(big_ws) + 256);
     double *cs = reinterpret_cast<double *>(gh + kGapBins);
     int32_t *is = reinterpret_cast<int32_t *>(cs + ws_cap);
-    const unsigned G = (unsigned)std::min(((long)n_cand + 2047) / 2048, 1024L);
-    hipLaunchKernelGGL(k_gsel_init, dim3(1), dim3(1024), 0, s, st, gh);
+    constexpr int kPer = 8;
+    const unsigned G = (unsigned)(((long)n_cand + 256 * kPer - 1) / (256 * kPer));
+    if (!vref) {
+      hipLaunchKernelGGL(k_gsel_init, dim3(1), dim3(1024), 0, s, st, gh);
+      SPG_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_gsel_min, dim3(G), dim3(256), 0, s, n_cand, cand, st);
+      SPG_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(k_gsel_hist, dim3(G), dim3(256), 0, s, n_cand, Me, cand, vref, st, gh);
     SPG_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_gsel_min, dim3(G), dim3(256), 0, s, n_cand, cand, st);
+    hipLaunchKernelGGL(k_gsel_compact, dim3(G), dim3(256), 0, s, n_cand, kPer, cand, vref, st,
+                       cs, is);
     SPG_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_gsel_hist, dim3(G), dim3(256), 0, s, n_cand, cand, st, gh);
-    SPG_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_gsel_compact, dim3(G), dim3(256), 0, s, n_cand, Me, cand, st, gh, cs, is);
-    SPG_CHECK_LAUNCH();
-    // the survivors (at least Me) sorted by (key, original index)
+    // the survivors (at least Me) ordered by (score, original index)
     hipLaunchKernelGGL(k_select, dim3(1, 1), dim3(1024), 0, s, 0, (const int *)&st->count, Me,
                        (const double *)cs, (const int32_t *)is, sel, sel_score, keys_work,
-                       ids_work, 0L);
+                       ids_work, 0L, gh, &st->count);
     SPG_CHECK_LAUNCH();
     return;
   }
@@ -1334,7 +1374,9 @@ void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *
   SPG_BC(sel_score);
   SPG_BC(keys_work);
   SPG_BC(ids_work);
-  hipLaunchKernelGGL(k_select, dim3(1, g_bc.n), dim3(1024), 0, s, n_cand, n_dev, M, cand, cid, sel, sel_score, keys_work, ids_work, g_bc.ist);
+  hipLaunchKernelGGL(k_select, dim3(1, g_bc.n), dim3(1024), 0, s, n_cand, n_dev, M, cand, cid,
+                     sel, sel_score, keys_work, ids_work, g_bc.ist, (unsigned *)nullptr,
+                     (int *)nullptr);
   SPG_CHECK_LAUNCH();
 }
 

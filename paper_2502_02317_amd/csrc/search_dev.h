@@ -199,14 +199,15 @@ __device__ inline void bitonic_sort_lds(uint64_t *keys, int32_t *ids, int n_pow2
 
 // Log-spaced bins of a score's gap below the best score vmax: 64 bins per
 // octave of g = vmax - v over [2^-32, 2^32) (the exponent and six leading
-// mantissa bits of g), gaps below to bin 0, above it and NaN to the last
-// bin; non-decreasing as the score falls.  All scores in bins up to some b
+// mantissa bits of g), gaps below (and scores above vmax) to bin 0, above it
+// and NaN to the last bin; non-decreasing as the score falls.  All scores in bins up to some b
 // are at least as good as every score beyond it, so they form a prefix of the
 // (score desc, id asc) order.
 constexpr int kGapBins = 4096;
 __device__ __forceinline__ int gap_bin(double vmax, double v) {
-  const double g = vmax - v;                         // >= 0 (vmax is the best)
+  const double g = vmax - v;           // >= 0 when vmax is the best (a bound above it: < 0)
   if (!(g == g)) return kGapBins - 1;
+  if (!(g > 0.0)) return 0;
   const int e = (int)((unsigned)__double2hiint(g) >> 14) - ((1023 - 32) << 6);
   return e < 0 ? 0 : (e > kGapBins - 1 ? kGapBins - 1 : e);
 }

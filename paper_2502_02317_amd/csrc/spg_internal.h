@@ -217,10 +217,12 @@ void marginals(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg
 void select_topm(int n_cand, int M, const double *cand, int32_t *sel, uint64_t *keys_work,
                  int32_t *ids_work, hipStream_t s, const int *n_dev = nullptr,
                  const int32_t *cid = nullptr, double *sel_score = nullptr,
-                 void *big_ws = nullptr, long ws_cap = 0);
-// big_ws (optional, select_ws_bytes(ws_cap) bytes, ws_cap >= n_cand): more
-// than 16384 candidates of one instance are selected by a gap histogram over
-// many workgroups and a one-workgroup sort of the survivors.
+                 void *big_ws = nullptr, long ws_cap = 0, const double *vref = nullptr);
+// big_ws (optional, select_ws_bytes(ws_cap) bytes, ws_cap >= n_cand, zero-filled
+// when allocated): more than 16384 candidates of one instance are selected by a
+// gap histogram over many workgroups and a one-workgroup ordering of the
+// survivors; vref (optional, device): a score no candidate exceeds, which
+// replaces the pass that finds the best one.
 size_t select_ws_bytes(long n_cap);
 void beam_update(const SearchTabs &t, int r, int c, int n_new, const int32_t *sel, int N,
                  const uint8_t *cfg, const double *energy, const double *L, const int32_t *anc,
