@@ -576,7 +576,7 @@ void spg_free_env(spg_env_t *env) {
   (void)hipDeviceSynchronize();
   for (DevBuf *b : {&env->A, &env->Alp, &env->lam, &env->cfg[0], &env->cfg[1], &env->score[0],
                     &env->score[1], &env->energy[0], &env->energy[1], &env->L[0], &env->L[1],
-                    &env->anc[0], &env->anc[1], &env->Rv, &env->Ulp, &env->selws, &env->cand, &env->sel,
+                    &env->anc[0], &env->anc[1], &env->Rv, &env->Ulp, &env->U64, &env->selws, &env->cand, &env->sel,
                     &env->keys,
                     &env->ids, &env->ework, &env->perm, &env->nvalid, &env->tmp, &env->cfg32})
     b->release();
@@ -742,6 +742,7 @@ static void each_search_buffer(spg_env *env, int M, F &&f) {
   f(env->Rv, (size_t)M * (C + 1) * chi * 8);
   // reduced-precision search: U_c of every column for the row's ancestors
   if (env->precision != SPG_FP64) f(env->Ulp, (size_t)C * M * chi * d * 4);
+  else f(env->U64, (size_t)C * M * chi * d * 8);
   f(env->cand, (size_t)M * d * 8);
   f(env->selws, select_ws_bytes((long)M * d));
   f(env->sel, (size_t)M * 4);
@@ -1052,7 +1053,10 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
   fill_zero(env->energy[0].as<double>(), 1, s);
   const double log_cut = (prm->cut_off_prob > 0.0) ? std::log(prm->cut_off_prob) : 0.0;
   const bool lp = env->precision != SPG_FP64;
-  const long ldu = (long)chi * d;                  // U row stride (reduced precision)
+  // FP64 plain search: conditionals from the per-ancestor products U (the
+  // guarded and the training searches keep the per-state contraction)
+  const bool u64 = !lp && !guided && !td;
+  const long ldu = (long)chi * d;                  // U row stride
   const char *Al = env->Alp.as<char>();
   const size_t eb = lp ? lp_elt(env) : 0;
   int64_t n_resolved = 0;
@@ -1090,6 +1094,18 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
           lp_env_from_u(t, env->precision, r, c, n_anc, env->cfg[cur].as<uint8_t>(), N, Uc, ldu,
                         Rf + (size_t)c * chi, rstride, dm[c], s, guided ? Rsc + c : nullptr,
                         C + 1);
+      }
+    } else if (u64) {
+      // U_c = A_c R_{c+1} for every ancestor and column on the matrix cores;
+      // R_c comes from U_c, and the conditionals of column c read U_c again
+      set_e0(n_anc, chi, Rv + (size_t)C * chi, rstride, s);
+      for (int c = C - 1; c >= 0; --c) {
+        double *Uc = env->U64.as<double>() + (size_t)c * M * ldu;
+        u64_col(n_anc, A + ((size_t)r * C + c) * site_sz, chi, Rv + (size_t)(c + 1) * chi,
+                rstride, Uc, ldu, d, dm[c], dm[c + 1], s);
+        if (c >= 1)
+          env_from_u64(t, r, c, n_anc, env->cfg[cur].as<uint8_t>(), N, Uc, ldu,
+                       Rv + (size_t)c * chi, rstride, dm[c], s);
       }
     } else {
       set_e0(n_anc, chi, Rv + (size_t)C * chi, rstride, s);
@@ -1133,6 +1149,10 @@ static void run_search(spg_env *env, const spg_search_params *prm, const spg_pro
           lp_marginals_u(t, r, c, (int)B, cfg, N, env->Ulp.as<float>() + (size_t)c * M * ldu, ldu,
                          env->L[cur].as<float>(), env->anc[cur].as<int32_t>(), score,
                          env->cand.as<double>(), 1, dm[c], s);
+        else if (u64)
+          marg_from_u64(t, r, c, (int)B, cfg, N, env->U64.as<double>() + (size_t)c * M * ldu,
+                        ldu, env->L[cur].as<double>(), env->anc[cur].as<int32_t>(), score,
+                        env->cand.as<double>(), 1, dm[c], s);
         else
           marginals(t, r, c, (int)B, cfg, N, Arc, env->L[cur].as<double>(),
                     env->anc[cur].as<int32_t>(), Rv, rstride, score, env->cand.as<double>(), 1,

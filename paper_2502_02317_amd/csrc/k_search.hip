@@ -166,6 +166,109 @@ __global__ __launch_bounds__(256) void k_right_env_lds(SearchTabs t, int r, int 
 
 // out[b*d + s] = (add_score ? score[b] : 0) + log p(s | b); a parent with no
 // positive weight takes softmax_s(-beta dE) (local_softmax_norm)
+// ---- the same right environments and conditionals from the column's U
+// products: U^a[al*d + s] = sum_b A[al][s][b] R^a_{c+1}[b], one GEMM over all
+// row-start ancestors on the FP64 matrix cores (u64_col), so the site tensor
+// is read once per output tile instead of once per ancestor or beam state.
+// R^a_c[al] = sum_s g^a(s) U^a[al*d + s] (s order), normalised by its largest
+// |entry| (to scale[a * sstride] when given); q(b, s) = g^b(s) sum_al L^b[al]
+// U^{anc(b)}[al*d + s] (al order); the epilogue is k_marginals'.
+__global__ __launch_bounds__(256) void k_env_from_u64(SearchTabs t, int r, int c, int n_anc,
+                                                      const uint8_t *cfg, int N, const double *U,
+                                                      long ldu, double *Rout, long rstride,
+                                                      int cl, double *scale, int sstride,
+                                                      long ist) {
+  SPG_INST(cfg);
+  SPG_INST(U);
+  SPG_INST(Rout);
+  SPG_INST(scale);
+  shift_tabs(t, ist);
+  __shared__ double gs[kWaves][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int a0 = blockIdx.x * kWaves + w;
+  const bool valid = a0 < n_anc;
+  const int a = valid ? a0 : 0;
+  const int chi = t.chi, d = t.d;
+  const uint8_t *cb = cfg + (long)a * N;
+  if (valid)
+    for (int s = lane; s < d; s += 64) gs[w][s] = field(t, r, c, cb, s);
+  __syncthreads();
+  if (!valid) return;
+  const double *Ua = U + (long)a * ldu;
+  double v[2] = {0.0, 0.0};
+  for (int h = 0; h < 2; ++h) {
+    const int al = lane + 64 * h;
+    if (al >= cl) continue;
+    double acc = 0.0;
+    for (int s = 0; s < d; ++s) acc += gs[w][s] * Ua[(long)al * d + s];
+    v[h] = acc;
+  }
+  const double m = wave_max_nonneg(fmax(fabs(v[0]), fabs(v[1])));
+  const double inv = (m > 0.0) ? 1.0 / m : 1.0;
+  for (int h = 0; h < 2; ++h) {
+    const int al = lane + 64 * h;
+    if (al < chi) Rout[a * rstride + al] = (al < cl) ? v[h] * inv : 0.0;
+  }
+  if (scale && lane == 0) scale[(long)a * sstride] = m;
+}
+
+__global__ __launch_bounds__(256) void k_marg_from_u64(SearchTabs t, int r, int c, int n_beam,
+                                                       const uint8_t *cfg, int N, const double *U,
+                                                       long ldu, const double *L,
+                                                       const int32_t *anc, const double *score,
+                                                       double *out, int add_score, int cl,
+                                                       long ist) {
+  SPG_INST(cfg);
+  SPG_INST(U);
+  SPG_INST(L);
+  SPG_INST(anc);
+  SPG_INST(score);
+  SPG_INST(out);
+  shift_tabs(t, ist);
+  __shared__ double Ls[kWaves][kMaxChi];
+  __shared__ double qs[kWaves][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b0 = blockIdx.x * kWaves + w;
+  const bool valid = b0 < n_beam;
+  const int b = valid ? b0 : 0;
+  const int chi = t.chi, d = t.d;
+  if (valid)
+    for (int i = lane; i < chi; i += 64) Ls[w][i] = L[(long)b * chi + i];
+  __syncthreads();
+  if (!valid) return;
+  const double *Ua = U + (long)anc[b] * ldu;
+  const uint8_t *cb = cfg + (long)b * N;
+  double part = 0.0;
+  for (int s = lane; s < d; s += 64) {
+    double acc = 0.0;
+    for (int al = 0; al < cl; ++al) {
+      const double la = Ls[w][al];
+      if (la == 0.0) continue;
+      acc = fma(la, Ua[(long)al * d + s], acc);
+    }
+    double q = field(t, r, c, cb, s) * acc;
+    q = (q > 0.0) ? q : 0.0;               // negative q (truncation error) = probability 0
+    qs[w][s] = q;
+    part += q;
+  }
+  const double tot = wave_sum(part);
+  const double base = add_score ? score[b] : 0.0;
+  if (!(tot > 0.0)) {                      // no child with positive weight
+    double emin, lse;
+    local_softmax_norm(t, r, c, cb, lane, emin, lse);
+    for (int s = lane; s < d; s += 64)
+      out[(long)b * d + s] = base + (-t.beta * (delta_energy(t, r, c, cb, s) - emin) - lse);
+    return;
+  }
+  const double ltot = log(tot);
+  for (int s = lane; s < d; s += 64) {
+    const double q = qs[w][s];
+    double lp = (q > 0.0 && tot > 0.0) ? log(q) - ltot : -INFINITY;
+    if (!(lp == lp)) lp = -INFINITY;
+    out[(long)b * d + s] = base + lp;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_marginals(SearchTabs t, int r, int c, int n_beam,
                                                    const uint8_t *cfg, int N, const double *A,
                                                    const double *L, const int32_t *anc,
@@ -1285,6 +1388,58 @@ __global__ __launch_bounds__(256) void k_droplet_update(SearchTabs t, int r, int
 }
 
 }  // namespace
+
+void u64_col(int n_anc, const double *A_rc, int chi, const double *Rnext, long rstride,
+             double *U, long ldu, int d, int cl, int cr, hipStream_t s) {
+  if (n_anc <= 0 || cl <= 0 || cr <= 0) return;
+  GemmDesc g{};
+  g.M = n_anc; g.N = cl * d; g.K = cr; g.nb1 = 1; g.nb2 = 1;
+  g.A = Rnext; g.a_i = rstride; g.a_k = 1;
+  g.B = A_rc; g.b_k = 1; g.b_j = chi;
+  g.C = U; g.c_i = ldu; g.c_j = 1;
+  g.alpha = 1.0; g.beta = 0.0;
+  gemm_f64(g, s);
+}
+
+void env_from_u64(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *cfg, int N,
+                  const double *U, long ldu, double *Rout, long rstride, int cl, hipStream_t s,
+                  double *scale, int sstride) {
+  KTimer kt_("right_env", s, 2.0 * n_anc * cl * t.d);
+  if (n_anc <= 0) return;
+  SPG_BC(cfg);
+  SPG_BC(U);
+  SPG_BC(Rout);
+  SPG_BC(scale);
+  bc_check_tabs(t);
+  if (t.d > 256 || cl > 128) {
+    set_error("env_from_u64: d or bond dimension too large");
+    throw Fail{SPG_ERR_UNSUPPORTED};
+  }
+  hipLaunchKernelGGL(k_env_from_u64, dim3(nblk(n_anc, kWaves), g_bc.n), dim3(256), 0, s, t, r, c,
+                     n_anc, cfg, N, U, ldu, Rout, rstride, cl, scale, sstride, g_bc.ist);
+  SPG_CHECK_LAUNCH();
+}
+
+void marg_from_u64(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
+                   const double *U, long ldu, const double *L, const int32_t *anc,
+                   const double *score, double *out, int add_score, int cl, hipStream_t s) {
+  KTimer kt_("marginals", s, 2.0 * n_beam * t.d * cl);
+  if (n_beam <= 0) return;
+  SPG_BC(cfg);
+  SPG_BC(U);
+  SPG_BC(L);
+  SPG_BC(anc);
+  SPG_BC(score);
+  SPG_BC(out);
+  bc_check_tabs(t);
+  if (t.d > 256) {
+    set_error("marg_from_u64: d too large");
+    throw Fail{SPG_ERR_UNSUPPORTED};
+  }
+  hipLaunchKernelGGL(k_marg_from_u64, dim3(nblk(n_beam, kWaves), g_bc.n), dim3(256), 0, s, t, r,
+                     c, n_beam, cfg, N, U, ldu, L, anc, score, out, add_score, cl, g_bc.ist);
+  SPG_CHECK_LAUNCH();
+}
 
 void right_env_col(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *cfg, int N,
                    const double *A_rc, const double *Rnext, double *Rout, long rstride,

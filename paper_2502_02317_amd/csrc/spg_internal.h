@@ -321,6 +321,17 @@ void lp_u_col(const SearchTabs &t, int precision, int n_anc, const void *A_rc,
               const float *Rnext, long rstride, float *U, long ldu, int cl, int cr,
               hipStream_t s);
 // R^a_c from U and the couplings to the fixed row (normalised per ancestor).
+// FP64 search from per-ancestor products (matrix cores): U^a[al*d + s] =
+// sum_b A_c[al][s][b] R^a_{c+1}[b] for every row-start ancestor (one GEMM,
+// row stride ldu), the right environment R_c and the conditionals from U.
+void u64_col(int n_anc, const double *A_rc, int chi, const double *Rnext, long rstride,
+             double *U, long ldu, int d, int cl, int cr, hipStream_t s);
+void env_from_u64(const SearchTabs &t, int r, int c, int n_anc, const uint8_t *cfg, int N,
+                  const double *U, long ldu, double *Rout, long rstride, int cl, hipStream_t s,
+                  double *scale = nullptr, int sstride = 0);
+void marg_from_u64(const SearchTabs &t, int r, int c, int n_beam, const uint8_t *cfg, int N,
+                   const double *U, long ldu, const double *L, const int32_t *anc,
+                   const double *score, double *out, int add_score, int cl, hipStream_t s);
 // sc (optional): the normalisation m of each ancestor's R_c, at sc[a * sc_stride]
 void lp_env_from_u(const SearchTabs &t, int precision, int r, int c, int n_anc,
                    const uint8_t *cfg, int N, const float *U, long ldu, float *Rout, long rstride,
@@ -363,6 +374,7 @@ struct spg_env {
   spg::DevBuf cfg[2], score[2], energy[2], L[2], anc[2], Rv, cand, sel, keys, ids, ework,
       perm, nvalid, tmp, cfg32;
   spg::DevBuf Ulp;               // reduced precision: U_c [cols][M][chi * d] float
+  spg::DevBuf U64;               // FP64 search: U_c [cols][M][chi * d] double
   spg::DevBuf selws;             // multi-workgroup top-M workspace (1280 + 12 M bytes)
   // guarded search with a proposal: right-environment scales, per-site
   // features, step workspace and counters
