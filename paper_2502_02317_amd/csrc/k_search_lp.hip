@@ -25,57 +25,88 @@ typedef short s4v __attribute__((ext_vector_type(4)));
 // (al, s) of the site tensor A[al][s][b] (p = al * d + s, row stride chi):
 // the product shared by the right environments and the conditionals of a
 // column, one GEMM over all ancestors on the matrix cores (M = ancestors,
-// N = cl * d, K = cr).  A wavefront computes a 16 x 16 tile of U: lane l
-// supplies ancestor a0 + l % 16 and pair n0 + l % 16, and the four k of its
-// group l / 16 within each block of 16; FP32 inputs use four
-// v_mfma_f32_16x16x4f32 per block, BF16 inputs one v_mfma_f32_16x16x16bf16
-// (R is rounded to BF16, as it is stored in that form), accumulation in FP32.
-// Out-of-range rows, pairs and k read element 0 and contribute zero.
+// N = cl * d, K = cr).  A workgroup computes a 64 x 64 tile of U, wavefront w
+// the 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 blocks of 16 x 16, so every
+// operand a lane loads feeds two blocks.  Per block: lane l supplies ancestor
+// a0 + l % 16 and pair n0 + l % 16, and the four k of its group l / 16 within
+// each block of 16 k; FP32 inputs use four v_mfma_f32_16x16x4f32 per k block,
+// BF16 inputs one v_mfma_f32_16x16x16bf16 (R is rounded to BF16, as it is
+// stored in that form), accumulation in FP32.  Out-of-range rows, pairs and k
+// read element 0 and contribute zero.
 template <class T>
 __global__ __launch_bounds__(256) void k_u_mfma(int n_anc, int npair, int cr, int chi, const T *A,
                                                 const float *R, long rstride, float *U,
                                                 long ldu) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int a0 = blockIdx.y * 16, n0 = (blockIdx.x * 4 + w) * 16;
-  if (n0 >= npair) return;                    // no barrier below
+  const int a_base = blockIdx.y * 64 + (w >> 1) * 32, n_base = blockIdx.x * 64 + (w & 1) * 32;
+  if (a_base >= n_anc || n_base >= npair) return;   // no barrier below
   const int i = lane & 15, g = lane >> 4;
-  const bool oka = a0 + i < n_anc, okp = n0 + i < npair;
-  const float *Rrow = R + (oka ? (long)(a0 + i) * rstride : 0L);
-  const T *Arow = A + (okp ? (long)(n0 + i) * chi : 0L);
-  f4v acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < cr; k0 += 16) {
-    float rv[4];
-    T av[4];
+  const float *Rrow[2];
+  const T *Arow[2];
+  bool oka[2], okp[2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = k0 + 4 * g + j;
-      const bool ok = k < cr;
-      const float x = Rrow[(ok && oka) ? k : 0];
-      const T y = Arow[(ok && okp) ? k : 0];
-      rv[j] = (ok && oka) ? x : 0.f;
-      av[j] = (ok && okp) ? y : (T)0;
-    }
+  for (int u = 0; u < 2; ++u) {
+    oka[u] = a_base + 16 * u + i < n_anc;
+    okp[u] = n_base + 16 * u + i < npair;
+    Rrow[u] = R + (oka[u] ? (long)(a_base + 16 * u + i) * rstride : 0L);
+    Arow[u] = A + (okp[u] ? (long)(n_base + 16 * u + i) * chi : 0L);
+  }
+  f4v acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = (f4v){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < cr; k0 += 16) {
+    float rv[2][4];
+    T av[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + 4 * g + j;
+        const bool ok = k < cr;
+        const float x = Rrow[u][(ok && oka[u]) ? k : 0];
+        const T y = Arow[u][(ok && okp[u]) ? k : 0];
+        rv[u][j] = (ok && oka[u]) ? x : 0.f;
+        av[u][j] = (ok && okp[u]) ? y : (T)0;
+      }
     if constexpr (sizeof(T) == 4) {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[j], (float)av[j], acc, 0, 0, 0);
-    } else {
-      s4v x, y;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        x[j] = (short)f2bf(rv[j]);
-        y[j] = (short)av[j];
-      }
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, acc, 0, 0, 0);
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v)
+            acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(rv[u][j], (float)av[v][j], acc[u][v],
+                                                             0, 0, 0);
+    } else {
+      s4v x[2], y[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          x[u][j] = (short)f2bf(rv[u][j]);
+          y[u][j] = (short)av[u][j];
+        }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+          acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x[u], y[v], acc[u][v], 0, 0, 0);
     }
   }
-  // lane l holds U[a0 + 4 (l / 16) + q][n0 + l % 16], q = 0..3
-  if (okp) {
+  // block (u, v): lane l holds U[a0 + 4 (l / 16) + q][n0 + l % 16], q = 0..3,
+  // a0 = a_base + 16 u, n0 = n_base + 16 v
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int a = a0 + 4 * g + q;
-      if (a < n_anc) U[(long)a * ldu + n0 + i] = acc[q];
-    }
+  for (int v = 0; v < 2; ++v) {
+    if (!okp[v]) continue;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int a = a_base + 16 * u + 4 * g + q;
+        if (a < n_anc) U[(long)a * ldu + n_base + 16 * v + i] = acc[u][v][q];
+      }
   }
 }
 
@@ -283,7 +314,7 @@ void lp_u_col(const SearchTabs &t, int precision, int n_anc, const void *A_rc,
     throw Fail{SPG_ERR_INVALID};
   }
   KTimer kt_("u_mfma", s, 2.0 * n_anc * npair * cr);
-  dim3 grid(nblk(npair, 64), nblk(n_anc, 16));
+  dim3 grid(nblk(npair, 64), nblk(n_anc, 64));
   if (precision == SPG_FP32)
     hipLaunchKernelGGL(k_u_mfma<float>, grid, dim3(256), 0, s, n_anc, npair, cr, t.chi,
                        (const float *)A_rc, Rnext, rstride, U, ldu);
