@@ -457,6 +457,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (a known-size kernel for "
                          "scaling hardware byte counters)")
+    ap.add_argument("--leg", choices=["kings12x12_d24"], default=None,
+                    help="run only this workload leg and print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the hot path of one instance per GPU); "
@@ -471,6 +473,11 @@ def main():
     def say(msg):
         if args.verbose:
             print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+    if args.leg == "kings12x12_d24":
+        stream = torch.cuda.current_stream()
+        print(json.dumps({"leg": args.leg, args.leg: kings12_leg(spg, torch, stream)}), flush=True)
+        return
 
     wl = WORKLOAD
     inst = config_instance(wl["name"], wl["seed"])
