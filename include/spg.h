@@ -243,6 +243,21 @@ int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items,
 /* Number of units (classes and single instances) and, in unit_of HOST int32
  * [n] (may be NULL), the unit of each instance. */
 int spg_batch_info(const spg_batch_t *batch, int32_t *n_units, int32_t *unit_of);
+/* The plan spg_batch_create would make for instances of these shapes, on the
+ * host only (no device call, nothing allocated; a batch of many instances of
+ * the method, Sec. 3.1, checked before it is built).  shapes HOST int32
+ * [n][4] = (rows, cols, d, kings) of each instance; items, n, flags as for
+ * spg_batch_create.  Outputs, all HOST: unit_of int32 [n], the unit of each
+ * instance; n_units; unit_bytes int64 [n][2] = (members, slice bytes) of each
+ * unit u < n_units (slice 0 for a single instance, whose buffers are its own
+ * allocations); n_buffers int32 [n], the buffers of each class's slice;
+ * layout int64 [n][max_buffers][2] (NULL when max_buffers = 0) = (offset,
+ * bytes) of each buffer in the slice, filled for classes of at most
+ * max_buffers buffers.  A class allocates members x slice bytes, members at
+ * a stride of one slice.  Errors: SPG_ERR_INVALID, SPG_ERR_UNSUPPORTED. */
+int spg_batch_plan(const int32_t *shapes, const spg_batch_item *items, int32_t n, int32_t flags,
+                   int32_t *unit_of, int32_t *n_units, int64_t *unit_bytes, int32_t max_buffers,
+                   int64_t *layout, int32_t *n_buffers);
 void spg_batch_free(spg_batch_t *batch);
 /* Runs every instance (asynchronous on `stream`).  The first run is eager
  * and synchronises once (it sizes the workspaces); with use_graph != 0 the
@@ -263,6 +278,14 @@ int spg_batch_set_tuning(spg_batch_t *batch, int32_t i, int32_t gemm_tile);
 int spg_batch_autotune(spg_batch_t *batch, void *stream, int32_t *tile_out);
 /* Process default GEMM tile (32 or 64) of calls outside batches on this thread. */
 int spg_set_tuning(int32_t gemm_tile);
+/* Process default, on this thread, of how the boundary MPS runs the MPO's
+ * d-index contractions (Sec. 2: the row transfer operator applied to the
+ * boundary MPS).  1 (the default): for d in {8, 16, 24, 32}, one thread per
+ * source column computes the d outputs that share it, each source entry read
+ * once; 0: one thread per output.  Both give bitwise equal results; other d
+ * always take the second.  Batches created afterwards keep the setting.
+ * SPG_ERR_INVALID for any other value. */
+int spg_set_mpo_kernels(int32_t column_forms);
 
 /* ---- learned proposal ---------------------------------------------------
  * Not part of the paper's method: a 2-layer FP32 network that ranks the

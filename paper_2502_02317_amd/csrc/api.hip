@@ -1,6 +1,7 @@
 // C ABI of include/spg.h: argument validation, device buffers and the
 // sequencing of the kernels on the caller's stream.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -479,6 +480,21 @@ int spg_profile_query(const char *name, int64_t *count, double *total_ms, double
   return SPG_OK;
 }
 
+// Bytes of each table of a PEPS of this shape, in the order E_loc, E_h, E_v,
+// E_d, E_a, W_loc, W_h, W_v, W_d, W_a, ones, e0row, e0col, e0vec, row_lsc
+// (what spg_build_peps allocates; e0vec stays empty).
+constexpr int kPepsTables = 15;
+extern "C++" {
+static std::array<size_t, kPepsTables> peps_table_bytes(int R, int C, int d) {
+  const size_t dd = (size_t)d * d;
+  const size_t n_loc = (size_t)R * C * d, n_h = (size_t)R * (C - 1) * dd;
+  const size_t n_v = (size_t)(R - 1) * C * dd, n_x = (size_t)(R - 1) * (C - 1) * dd;
+  auto b = [](size_t n) { return std::max<size_t>(n, 1) * sizeof(double); };
+  return {b(n_loc), b(n_h), b(n_v), b(n_x), b(n_x), b(n_loc), b(n_h), b(n_v), b(n_x), b(n_x),
+          b(dd), b(dd), b(dd), 0, (size_t)R * sizeof(double)};
+}
+}  // extern "C++"
+
 int spg_build_peps(const spg_instance_desc *desc, void *stream, spg_peps_t **out) {
   SPG_TRY
   if (!desc || !out) return fail(SPG_ERR_INVALID, "spg_build_peps: null desc or out");
@@ -553,6 +569,16 @@ int spg_build_peps(const spg_instance_desc *desc, void *stream, spg_peps_t **out
     double sh = 0.0;
     for (double v : hm) sh += v;
     pp->shift = sh;
+    // the tables as peps_table_bytes sizes them (what batch plans lay out)
+    const auto tb = peps_table_bytes(R, C, d);
+    const DevBuf *tabs[] = {&pp->E_loc, &pp->E_h, &pp->E_v, &pp->E_d, &pp->E_a, &pp->W_loc,
+                            &pp->W_h, &pp->W_v, &pp->W_d, &pp->W_a, &pp->ones, &pp->e0row,
+                            &pp->e0col, &pp->e0vec, &pp->row_lsc};
+    for (int t = 0; t < kPepsTables; ++t)
+      if (tabs[t]->bytes != tb[t]) {
+        set_error("spg_build_peps: table sizes differ from peps_table_bytes");
+        throw Fail{SPG_ERR_INVALID};
+      }
   } catch (...) {
     spg_free_peps(pp);
     throw;
@@ -1617,7 +1643,8 @@ constexpr size_t kClassBytes = (size_t)1 << 30;
 // outputs, 256-byte aligned; allocate n slices (unless layout_only) and point
 // the views at slice 0.  Returns the slice size.
 static size_t build_class(BatchClass &k, const std::vector<const spg_peps *> &src,
-                          const spg_batch_item &it, bool layout_only = false) {
+                          const spg_batch_item &it, bool layout_only = false,
+                          std::vector<std::pair<size_t, size_t>> *layout = nullptr) {
   const spg_peps *p0 = src[k.members[0]];
   const int R = p0->rows, C = p0->cols, d = p0->d, chi = it.chi, M = it.max_states;
   k.peps.rows = R; k.peps.cols = C; k.peps.d = d; k.peps.kings = p0->kings;
@@ -1638,7 +1665,7 @@ static size_t build_class(BatchClass &k, const std::vector<const spg_peps *> &sr
   DevBuf *dstb[] = {&pk->E_loc, &pk->E_h, &pk->E_v, &pk->E_d, &pk->E_a, &pk->W_loc, &pk->W_h,
                     &pk->W_v, &pk->W_d, &pk->W_a, &pk->ones, &pk->e0row, &pk->e0col, &pk->e0vec,
                     &pk->row_lsc};
-  constexpr int kPepsBufs = 15;
+  constexpr int kPepsBufs = kPepsTables;
   for (int t = 0; t < kPepsBufs; ++t) add(*dstb[t], srcb[t]->bytes);
   add(k.env.A, (size_t)R * C * chi * d * chi * sizeof(double));
   add(k.env.lam, (size_t)R * sizeof(double));
@@ -1654,6 +1681,8 @@ static size_t build_class(BatchClass &k, const std::vector<const spg_peps *> &sr
     tot += (e.second + 255) / 256 * 256;
   }
   k.slice = tot;
+  if (layout)
+    for (size_t q = 0; q < list.size(); ++q) layout->emplace_back(off[q], list[q].second);
   if (layout_only) return tot;
   const int n = (int)k.members.size();
   if (tot * n > kClassBytes) {
@@ -1733,24 +1762,59 @@ static void enqueue_batch(spg_batch *b, hipStream_t s) {
   }
 }
 
-int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items, int32_t n,
-                     int32_t n_streams, int32_t flags, spg_batch_t **out) {
-  SPG_TRY
-  if (!peps || !items || !out) return fail(SPG_ERR_INVALID, "spg_batch_create: null argument");
-  if (n < 1) return fail(SPG_ERR_INVALID, "spg_batch_create: n must be >= 1");
-  if (n_streams < 1 || n_streams > 64)
-    return fail(SPG_ERR_INVALID, "spg_batch_create: n_streams must be in 1..64");
-  if (flags & ~SPG_BATCH_CLASSES) return fail(SPG_ERR_INVALID, "spg_batch_create: unknown flags");
+// Units of a batch, in order: lists of member instances.  With
+// SPG_BATCH_CLASSES, FP64 instances of equal shape form classes of as many
+// members as fit in kClassBytes; every other instance is a unit of its own.
+extern "C++" {
+static std::vector<std::vector<int>> batch_units(const std::vector<const spg_peps *> &src,
+                                                 const spg_batch_item *items, int n, int flags) {
+  std::vector<std::vector<int>> units;
+  std::vector<int> placed(n, 0);
   for (int i = 0; i < n; ++i) {
-    if (!peps[i]) return fail(SPG_ERR_INVALID, "spg_batch_create: null peps");
+    if (placed[i]) continue;
+    std::vector<int> mem{i};
+    if ((flags & SPG_BATCH_CLASSES) && items[i].precision == SPG_FP64) {
+      BatchClass probe;
+      probe.members = mem;
+      const size_t slice = build_class(probe, src, items[i], true);
+      const size_t cap = std::max<size_t>(1, kClassBytes / slice);
+      for (int j = i + 1; j < n && mem.size() < cap; ++j)
+        if (!placed[j] && same_class(items[i], src[i], items[j], src[j])) mem.push_back(j);
+    }
+    for (int m : mem) placed[m] = 1;
+    units.push_back(mem);
+  }
+  return units;
+}
+}  // extern "C++"
+
+// Argument checks shared by spg_batch_create and spg_batch_plan.
+static int check_batch_items(const spg_batch_item *items, int32_t n, int32_t flags,
+                             const char *who) {
+  if (n < 1) return fail(SPG_ERR_INVALID, std::string(who) + ": n must be >= 1");
+  if (flags & ~SPG_BATCH_CLASSES) return fail(SPG_ERR_INVALID, std::string(who) + ": unknown flags");
+  for (int i = 0; i < n; ++i) {
     const spg_mps_params mp = item_mps(items[i]);
     int rc = check_mps_params(&mp);
     if (rc) return rc;
     if (items[i].max_states < 1 || items[i].max_states > 65536)
-      return fail(SPG_ERR_UNSUPPORTED, "spg_batch_create: max_states must be in 1..65536");
+      return fail(SPG_ERR_UNSUPPORTED, std::string(who) + ": max_states must be in 1..65536");
     if (!(items[i].cut_off_prob >= 0.0) || items[i].cut_off_prob >= 1.0)
-      return fail(SPG_ERR_INVALID, "spg_batch_create: cut_off_prob must be in [0, 1)");
+      return fail(SPG_ERR_INVALID, std::string(who) + ": cut_off_prob must be in [0, 1)");
   }
+  return SPG_OK;
+}
+
+int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items, int32_t n,
+                     int32_t n_streams, int32_t flags, spg_batch_t **out) {
+  SPG_TRY
+  if (!peps || !items || !out) return fail(SPG_ERR_INVALID, "spg_batch_create: null argument");
+  if (n_streams < 1 || n_streams > 64)
+    return fail(SPG_ERR_INVALID, "spg_batch_create: n_streams must be in 1..64");
+  int rc0 = check_batch_items(items, n, flags, "spg_batch_create");
+  if (rc0) return rc0;
+  for (int i = 0; i < n; ++i)
+    if (!peps[i]) return fail(SPG_ERR_INVALID, "spg_batch_create: null peps");
   spg_batch *b = new spg_batch();
   try {
     b->n = n;
@@ -1760,25 +1824,14 @@ int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items,
     b->inst_member.assign(n, 0);
     b->envs.assign(n, nullptr);
     // units: classes of two or more FP64 instances (with SPG_BATCH_CLASSES), else single
-    std::vector<int> placed(n, 0);
-    for (int i = 0; i < n; ++i) {
-      if (placed[i]) continue;
-      std::vector<int> mem{i};
-      if ((flags & SPG_BATCH_CLASSES) && items[i].precision == SPG_FP64) {
-        BatchClass probe;
-        probe.members = mem;
-        const size_t slice = build_class(probe, b->src, items[i], true);
-        const size_t cap = std::max<size_t>(1, kClassBytes / slice);
-        for (int j = i + 1; j < n && mem.size() < cap; ++j)
-          if (!placed[j] && same_class(items[i], peps[i], items[j], peps[j])) mem.push_back(j);
-      }
+    for (const std::vector<int> &mem : batch_units(b->src, items, n, flags)) {
+      const int i = mem[0];
       const int u = (int)b->unit_cls.size();
       if (mem.size() > 1) {
         std::unique_ptr<BatchClass> k(new BatchClass());
         k->members = mem;
         build_class(*k, b->src, items[i]);
         for (size_t m = 0; m < mem.size(); ++m) {
-          placed[mem[m]] = 1;
           b->inst_unit[mem[m]] = u;
           b->inst_member[mem[m]] = (int)m;
         }
@@ -1786,7 +1839,6 @@ int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items,
         b->unit_inst.push_back(-1);
         b->classes.push_back(std::move(k));
       } else {
-        placed[i] = 1;
         b->inst_unit[i] = u;
         b->unit_cls.push_back(-1);
         b->unit_inst.push_back(i);
@@ -1837,6 +1889,58 @@ int spg_batch_create(const spg_peps_t *const *peps, const spg_batch_item *items,
     throw;
   }
   *out = b;
+  return SPG_OK;
+  SPG_CATCH
+}
+
+int spg_batch_plan(const int32_t *shapes, const spg_batch_item *items, int32_t n, int32_t flags,
+                   int32_t *unit_of, int32_t *n_units, int64_t *unit_bytes, int32_t max_buffers,
+                   int64_t *layout, int32_t *n_buffers) {
+  SPG_TRY
+  if (!shapes || !items || !unit_of || !n_units || !unit_bytes || !n_buffers)
+    return fail(SPG_ERR_INVALID, "spg_batch_plan: null argument");
+  if (max_buffers < 0 || (max_buffers > 0 && !layout))
+    return fail(SPG_ERR_INVALID, "spg_batch_plan: layout needs max_buffers >= 1");
+  int rc = check_batch_items(items, n, flags, "spg_batch_plan");
+  if (rc) return rc;
+  // PEPS of the given shapes that only carry their tables' sizes
+  std::vector<std::unique_ptr<spg_peps>> held;
+  std::vector<const spg_peps *> src;
+  for (int i = 0; i < n; ++i) {
+    const int R = shapes[4 * i], C = shapes[4 * i + 1], d = shapes[4 * i + 2];
+    const int kings = shapes[4 * i + 3];
+    if (R < 1 || C < 2 || d < 2 || d > 256 || (long)R * C > 65536 || (kings != 0 && kings != 1))
+      return fail(SPG_ERR_UNSUPPORTED, "spg_batch_plan: shape outside the limits of spg_build_peps");
+    std::unique_ptr<spg_peps> pp(new spg_peps());
+    pp->rows = R; pp->cols = C; pp->d = d; pp->kings = kings;
+    const auto tb = peps_table_bytes(R, C, d);
+    DevBuf *tabs[] = {&pp->E_loc, &pp->E_h, &pp->E_v, &pp->E_d, &pp->E_a, &pp->W_loc, &pp->W_h,
+                      &pp->W_v, &pp->W_d, &pp->W_a, &pp->ones, &pp->e0row, &pp->e0col,
+                      &pp->e0vec, &pp->row_lsc};
+    for (int t = 0; t < kPepsTables; ++t) tabs[t]->view(nullptr, tb[t]);
+    src.push_back(pp.get());
+    held.push_back(std::move(pp));
+  }
+  const std::vector<std::vector<int>> units = batch_units(src, items, n, flags);
+  for (size_t u = 0; u < units.size(); ++u) {
+    const std::vector<int> &mem = units[u];
+    for (int m : mem) unit_of[m] = (int32_t)u;
+    unit_bytes[2 * u] = (int64_t)mem.size();
+    unit_bytes[2 * u + 1] = 0;
+    n_buffers[u] = 0;
+    if (mem.size() < 2) continue;
+    BatchClass k;
+    k.members = mem;
+    std::vector<std::pair<size_t, size_t>> lay;
+    unit_bytes[2 * u + 1] = (int64_t)build_class(k, src, items[mem[0]], true, &lay);
+    n_buffers[u] = (int32_t)lay.size();
+    if ((int)lay.size() > max_buffers) continue;
+    for (size_t q = 0; q < lay.size(); ++q) {
+      layout[((size_t)u * max_buffers + q) * 2] = (int64_t)lay[q].first;
+      layout[((size_t)u * max_buffers + q) * 2 + 1] = (int64_t)lay[q].second;
+    }
+  }
+  *n_units = (int32_t)units.size();
   return SPG_OK;
   SPG_CATCH
 }
@@ -1996,6 +2100,13 @@ int spg_set_tuning(int32_t gemm_tile) {
   if (gemm_tile != 32 && gemm_tile != 64)
     return fail(SPG_ERR_INVALID, "spg_set_tuning: gemm_tile must be 32 or 64");
   g_tune.gemm_tile = gemm_tile;
+  return SPG_OK;
+}
+
+int spg_set_mpo_kernels(int32_t column_forms) {
+  if (column_forms != 0 && column_forms != 1)
+    return fail(SPG_ERR_INVALID, "spg_set_mpo_kernels: column_forms must be 0 or 1");
+  g_tune.mpo_cols = column_forms;
   return SPG_OK;
 }
 

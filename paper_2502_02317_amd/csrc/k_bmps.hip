@@ -241,6 +241,167 @@ __global__ void k_Q2(int d, int chi, int nq, int pr, const double *Qr, const dou
   Q2[(((long)Q * d + x) * d + z) * chi + P] = acc;
 }
 
+// Column forms of the six kernels above for d = D in {8, 16, 24, 32}.  In
+// each, the d outputs that differ only in the output's own d index read the
+// same d-long column of the source; here one thread loads that column once
+// into registers and writes all d outputs, so every source entry is read from
+// memory once (the one-thread-per-output forms re-read each column d times,
+// from workgroups that the dispatcher spreads over XCDs with separate L2
+// caches).  The d x d coefficient table is staged in LDS, laid out so that the
+// terms of one output are contiguous, and read at the same address by the
+// whole wavefront.  Every output keeps its operands and the order of its
+// terms: results are bitwise those of the forms above.
+constexpr int kColThreads = 64;
+
+// cf[i * D + k] = tab[i * d + k] (tr = false) or tab[k * d + i] (tr = true)
+template <int D>
+__device__ __forceinline__ void stage_table(double *cf, const double *tab, bool tr) {
+  for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
+    const int i = e / D, k = e % D;
+    cf[e] = tr ? tab[k * D + i] : tab[e];
+  }
+  __syncthreads();
+}
+
+template <int D>
+__device__ __forceinline__ void load_col(double (&v)[D], const double *src, long stride) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) v[k] = src[k * stride];
+}
+
+// sum over k < D, in order, of row[k] * v[k] as an fma chain
+template <int D>
+__device__ __forceinline__ double dot_row(const double *row, const double (&v)[D]) {
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc = fma(row[k], v[k], acc);
+  return acc;
+}
+
+// the same with row[k] * h[k] as the coefficient
+template <int D>
+__device__ __forceinline__ double dot_row2(const double *row, const double (&h)[D],
+                                           const double (&v)[D]) {
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) acc = fma(h[k] * row[k], v[k], acc);
+  return acc;
+}
+
+// T1[p][a][x][q] = sum_e Al[x][e] EL[p][a][e][q]; thread (p, a, q)
+template <int D>
+__global__ __launch_bounds__(kColThreads) void k_T1c(int chi, int pl, int ql, const double *EL,
+                                                     const double *Al, double *T1, long ist) {
+  SPG_INST(EL);
+  SPG_INST(Al);
+  SPG_INST(T1);
+  __shared__ double cf[D * D];
+  stage_table<D>(cf, Al, false);
+  const unsigned t = flat_id();
+  if (t >= (unsigned)(pl * D * ql)) return;
+  const int q = t % ql, a = (t / ql) % D, p = t / (ql * D);
+  const long base = (((long)p * D + a) * D) * chi + q;
+  double v[D];
+  load_col(v, EL + base, chi);
+  for (int x = 0; x < D; ++x) T1[base + (long)x * chi] = dot_row(cf + x * D, v);
+}
+
+// T2[p][x][y][q] = sum_a Hl[a][x] Dl[a][y] T1[p][a][x][q]; thread (p, x, q)
+template <int D>
+__global__ __launch_bounds__(kColThreads) void k_T2c(int chi, int pl, int ql, const double *T1,
+                                                     const double *Hl, const double *Dl,
+                                                     double *T2, long ist) {
+  SPG_INST(T1);
+  SPG_INST(Hl);
+  SPG_INST(Dl);
+  SPG_INST(T2);
+  __shared__ double cf[D * D];                       // cf[y][a] = Dl[a][y]
+  stage_table<D>(cf, Dl, true);
+  const unsigned t = flat_id();
+  if (t >= (unsigned)(pl * D * ql)) return;
+  const int q = t % ql, x = (t / ql) % D, p = t / (ql * D);
+  double v[D], h[D];
+  load_col(v, T1 + ((long)p * D * D + x) * chi + q, (long)D * chi);
+  load_col(h, Hl + x, D);
+  double *out = T2 + (((long)p * D + x) * D) * chi + q;
+  for (int y = 0; y < D; ++y) out[(long)y * chi] = dot_row2(cf + y * D, h, v);
+}
+
+// G3[p][x][a][q] = sum_y Dl[a][y] G2[p][x][y][q]; thread (p, x, q)
+template <int D>
+__global__ __launch_bounds__(kColThreads) void k_G3c(int chi, int pl, int ql, const double *G2,
+                                                     const double *Dl, double *G3, long ist) {
+  SPG_INST(G2);
+  SPG_INST(Dl);
+  SPG_INST(G3);
+  __shared__ double cf[D * D];
+  stage_table<D>(cf, Dl, false);
+  const unsigned t = flat_id();
+  if (t >= (unsigned)(pl * D * ql)) return;
+  const int q = t % ql, x = (t / ql) % D, p = t / (ql * D);
+  const long base = (((long)p * D + x) * D) * chi + q;
+  double v[D];
+  load_col(v, G2 + base, chi);
+  for (int a = 0; a < D; ++a) G3[base + (long)a * chi] = dot_row(cf + a * D, v);
+}
+
+// ER[p][a][e][q] = sum_x Hl[a][x] Al[x][e] G3[p][x][a][q]; thread (p, a, q)
+template <int D>
+__global__ __launch_bounds__(kColThreads) void k_ERfinc(int chi, int pl, int ql, const double *G3,
+                                                        const double *Hl, const double *Al,
+                                                        double *ER, long ist) {
+  SPG_INST(G3);
+  SPG_INST(Hl);
+  SPG_INST(Al);
+  SPG_INST(ER);
+  __shared__ double cf[D * D];                       // cf[e][x] = Al[x][e]
+  stage_table<D>(cf, Al, true);
+  const unsigned t = flat_id();
+  if (t >= (unsigned)(pl * D * ql)) return;
+  const int q = t % ql, a = (t / ql) % D, p = t / (ql * D);
+  double v[D], h[D];
+  load_col(v, G3 + ((long)p * D * D + a) * chi + q, (long)D * chi);
+  load_col(h, Hl + (long)a * D, 1);
+  double *out = ER + (((long)p * D + a) * D) * chi + q;
+  for (int ee = 0; ee < D; ++ee) out[(long)ee * chi] = dot_row2(cf + ee * D, h, v);
+}
+
+// P2[p][x][z][Q] = sum_y A1[z][y] P[p][x][y][Q]; thread (p, x, Q)
+template <int D>
+__global__ __launch_bounds__(kColThreads) void k_P2c(int chi, int pl, int nq, const double *P,
+                                                     const double *A1, double *P2, long ist) {
+  SPG_INST(P);
+  SPG_INST(A1);
+  SPG_INST(P2);
+  __shared__ double cf[D * D];
+  stage_table<D>(cf, A1, false);
+  const unsigned t = flat_id();
+  if (t >= (unsigned)(pl * D * nq)) return;
+  const int Q = t % nq, x = (t / nq) % D, p = t / (nq * D);
+  const long base = (((long)p * D + x) * D) * chi + Q;
+  double v[D];
+  load_col(v, P + base, chi);
+  for (int z = 0; z < D; ++z) P2[base + (long)z * chi] = dot_row(cf + z * D, v);
+}
+
+// Q2[Q][x][z][P] = sum_v D1[x][v] Qr[Q][z][v][P]; thread (Q, z, P)
+template <int D>
+__global__ __launch_bounds__(kColThreads) void k_Q2c(int chi, int nq, int pr, const double *Qr,
+                                                     const double *D1, double *Q2, long ist) {
+  SPG_INST(Qr);
+  SPG_INST(D1);
+  SPG_INST(Q2);
+  __shared__ double cf[D * D];
+  stage_table<D>(cf, D1, false);
+  const unsigned t = flat_id();
+  if (t >= (unsigned)(nq * D * pr)) return;
+  const int P = t % pr, z = (t / pr) % D, Q = t / (pr * D);
+  double v[D];
+  load_col(v, Qr + (((long)Q * D + z) * D) * chi + P, chi);
+  double *out = Q2 + ((long)Q * D * D + z) * chi + P;
+  for (int x = 0; x < D; ++x) out[(long)x * D * chi] = dot_row(cf + x * D, v);
+}
+
 // The whole padded site dst[chi][d][chi]: entries k < nk, P < pr from src,
 // zero elsewhere.
 __global__ void k_unpack_right(int d, int chi, int nk, int pr, const double *src, long sk,
@@ -349,13 +510,33 @@ void bottom_row(int C, int d, int chi, const double *w, const double *H, double 
   SPG_CHECK_LAUNCH();
 }
 
+// The column forms exist for d in {8, 16, 24, 32}; other d (and calls with
+// the column forms switched off) take the per-output forms.
+inline bool col_form(int d) {
+  return g_tune.mpo_cols && (d == 8 || d == 16 || d == 24 || d == 32);
+}
+
+#define SPG_LAUNCH_COL(KN, nthr, ...)                                            \
+  do {                                                                           \
+    const dim3 g_(nblk((nthr), kColThreads), g_bc.n), b_(kColThreads);           \
+    switch (d) {                                                                 \
+      case 8: hipLaunchKernelGGL(KN<8>, g_, b_, 0, s, __VA_ARGS__); break;       \
+      case 16: hipLaunchKernelGGL(KN<16>, g_, b_, 0, s, __VA_ARGS__); break;     \
+      case 24: hipLaunchKernelGGL(KN<24>, g_, b_, 0, s, __VA_ARGS__); break;     \
+      default: hipLaunchKernelGGL(KN<32>, g_, b_, 0, s, __VA_ARGS__); break;     \
+    }                                                                            \
+  } while (0)
+
 void left_part(int d, int chi, int pl, int ql, int qr, const double *EL, const double *psi,
                const RowFactors &f, double *T1, double *P, hipStream_t s) {
   const long tot = (long)pl * d * d * ql;
   SPG_BC(EL);
   SPG_BC(f.Al);
   SPG_BC(T1);
-  hipLaunchKernelGGL(k_T1, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, EL, f.Al, T1, g_bc.ist);
+  if (col_form(d))
+    SPG_LAUNCH_COL(k_T1c, (long)pl * d * ql, chi, pl, ql, EL, f.Al, T1, g_bc.ist);
+  else
+    hipLaunchKernelGGL(k_T1, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, EL, f.Al, T1, g_bc.ist);
   SPG_CHECK_LAUNCH();
   // T2 written into P (the GEMM below reads T2 and writes P in place would alias),
   // so T2 goes to the second half of T1's buffer.
@@ -364,7 +545,10 @@ void left_part(int d, int chi, int pl, int ql, int qr, const double *EL, const d
   SPG_BC(f.Hl);
   SPG_BC(f.Dl);
   SPG_BC(T2);
-  hipLaunchKernelGGL(k_T2, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, T1, f.Hl, f.Dl, T2, g_bc.ist);
+  if (col_form(d))
+    SPG_LAUNCH_COL(k_T2c, (long)pl * d * ql, chi, pl, ql, T1, f.Hl, f.Dl, T2, g_bc.ist);
+  else
+    hipLaunchKernelGGL(k_T2, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, T1, f.Hl, f.Dl, T2, g_bc.ist);
   SPG_CHECK_LAUNCH();
   // P[p][x][y][Q] = sum_q T2[p][x][y][q] psi[q][y][Q]   (batch y; rows (p,x))
   GemmDesc g{};
@@ -416,13 +600,19 @@ void env_right(int d, int chi, int pl, int pr, int ql, int qr, const double *phi
   SPG_BC(G2);
   SPG_BC(f.Dl);
   SPG_BC(G3);
-  hipLaunchKernelGGL(k_G3, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, G2, f.Dl, G3, g_bc.ist);
+  if (col_form(d))
+    SPG_LAUNCH_COL(k_G3c, (long)pl * d * ql, chi, pl, ql, G2, f.Dl, G3, g_bc.ist);
+  else
+    hipLaunchKernelGGL(k_G3, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, G2, f.Dl, G3, g_bc.ist);
   SPG_CHECK_LAUNCH();
   SPG_BC(G3);
   SPG_BC(f.Hl);
   SPG_BC(f.Al);
   SPG_BC(ERn);
-  hipLaunchKernelGGL(k_ERfin, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, G3, f.Hl, f.Al, ERn, g_bc.ist);
+  if (col_form(d))
+    SPG_LAUNCH_COL(k_ERfinc, (long)pl * d * ql, chi, pl, ql, G3, f.Hl, f.Al, ERn, g_bc.ist);
+  else
+    hipLaunchKernelGGL(k_ERfin, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, G3, f.Hl, f.Al, ERn, g_bc.ist);
   SPG_CHECK_LAUNCH();
 }
 
@@ -446,12 +636,18 @@ void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, cons
   SPG_BC(P);
   SPG_BC(f1.Al);
   SPG_BC(P2);
-  hipLaunchKernelGGL(k_P2, dim3(nblk(totp, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, qm, P, f1.Al, P2, g_bc.ist);
+  if (col_form(d))
+    SPG_LAUNCH_COL(k_P2c, (long)pl * d * qm, chi, pl, qm, P, f1.Al, P2, g_bc.ist);
+  else
+    hipLaunchKernelGGL(k_P2, dim3(nblk(totp, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, qm, P, f1.Al, P2, g_bc.ist);
   SPG_CHECK_LAUNCH();
   SPG_BC(Qr);
   SPG_BC(f1.Dl);
   SPG_BC(Q2);
-  hipLaunchKernelGGL(k_Q2, dim3(nblk(totq, 256), g_bc.n), dim3(256), 0, s, d, chi, qm, pr, Qr, f1.Dl, Q2, g_bc.ist);
+  if (col_form(d))
+    SPG_LAUNCH_COL(k_Q2c, (long)qm * d * pr, chi, qm, pr, Qr, f1.Dl, Q2, g_bc.ist);
+  else
+    hipLaunchKernelGGL(k_Q2, dim3(nblk(totq, 256), g_bc.n), dim3(256), 0, s, d, chi, qm, pr, Qr, f1.Dl, Q2, g_bc.ist);
   SPG_CHECK_LAUNCH();
   // B[p][x][z][P] = sum_Q P2[p][x][z][Q] Q2[Q][x][z][P]   (batch (x,z)), compact output
   GemmDesc h{};

@@ -108,6 +108,7 @@ void gemm_f64(const GemmDesc &g, hipStream_t s);
 struct Tuning {
   int gemm_tile = 32;   // GEMM output tile: 32 or 64
   int splitk = 1;       // deterministic split-K for skinny long-K products
+  int mpo_cols = 1;     // column forms of the MPO d-index contractions (d in {8, 16, 24, 32})
 };
 extern thread_local Tuning g_tune;
 

@@ -70,7 +70,8 @@ EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals
            "spg_proposal_train", "spg_proposal_features", "spg_proposal_forward",
            "spg_proposal_loss_grad", "spg_proposal_adam", "spg_search_stats",
            "spg_batch_create", "spg_batch_free", "spg_batch_run", "spg_batch_result",
-           "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning", "spg_batch_info",
+           "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning", "spg_set_mpo_kernels",
+           "spg_batch_info", "spg_batch_plan",
            "spg_droplets", "spg_ising_to_potts"]
 KERNEL_CLASSES = ["gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box", "right_env",
                   "marginals", "select_topm", "beam_update", "final_sort", "propose",
@@ -129,6 +130,8 @@ def load() -> C.CDLL:
     lib.spg_batch_set_tuning.argtypes = [vp, i32, i32]
     lib.spg_batch_autotune.argtypes = [vp, vp, vp]
     lib.spg_set_tuning.argtypes = [i32]
+    lib.spg_set_mpo_kernels.argtypes = [i32]
+    lib.spg_batch_plan.argtypes = [vp, vp, i32, i32, vp, i32p, vp, i32, vp, vp]
     for name in ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals_noalloc",
                  "spg_branch_and_bound", "spg_topm",
                  "spg_env_info", "spg_env_export", "spg_env_import", "spg_profile_query",
@@ -136,7 +139,9 @@ def load() -> C.CDLL:
                  "spg_proposal_features", "spg_proposal_forward", "spg_proposal_loss_grad",
                  "spg_proposal_adam", "spg_search_stats", "spg_batch_create", "spg_batch_run",
                  "spg_batch_result", "spg_batch_set_tuning", "spg_batch_autotune",
-                 "spg_set_tuning", "spg_batch_info", "spg_droplets", "spg_ising_to_potts"]:
+                 "spg_set_tuning", "spg_set_mpo_kernels", "spg_batch_info", "spg_batch_plan",
+                 "spg_droplets",
+                 "spg_ising_to_potts"]:
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -501,6 +506,44 @@ def search_stats(env: Env):
 def set_tuning(gemm_tile: int) -> None:
     """Default GEMM tile (32 or 64) of calls outside batches on this thread."""
     _check(load().spg_set_tuning(int(gemm_tile)))
+
+
+def set_mpo_kernels(column_forms: bool) -> None:
+    """How the boundary MPS runs the MPO d-index contractions on this thread:
+    True (default) the column forms (d in {8, 16, 24, 32}), False one thread per
+    output.  Results are bitwise equal."""
+    _check(load().spg_set_mpo_kernels(1 if column_forms else 0))
+
+
+def batch_plan(shapes, chi, max_states, num_sweeps=1, precision="fp64", oversample=16,
+               power_iters=1, cut_off_prob=0.0, classes=True, max_buffers=128):
+    """The units spg_batch_create would form for instances of these shapes
+    ((rows, cols, d, kings) each), computed on the host without a device.
+    Returns (unit_of [n], units: list of (members, slice_bytes), layouts: per
+    unit an int64 array [buffers][2] of (offset, bytes) in the slice, empty
+    for single instances)."""
+    n = len(shapes)
+    sh = np.ascontiguousarray(np.asarray(shapes, dtype=np.int32).reshape(n, 4))
+    chis = list(chi) if hasattr(chi, "__len__") else [chi] * n
+    Ms = list(max_states) if hasattr(max_states, "__len__") else [max_states] * n
+    precs = [precision] * n if isinstance(precision, str) else list(precision)
+    items = (BatchItem * n)(*[BatchItem(int(chis[i]), int(num_sweeps), PRECISION[precs[i]],
+                                        int(oversample), int(power_iters), int(Ms[i]),
+                                        float(cut_off_prob)) for i in range(n)])
+    unit_of = np.zeros(n, dtype=np.int32)
+    nu = C.c_int32(0)
+    ub = np.zeros((n, 2), dtype=np.int64)
+    lay = np.zeros((n, max_buffers, 2), dtype=np.int64)
+    nb = np.zeros(n, dtype=np.int32)
+    _check(load().spg_batch_plan(sh.ctypes.data, items, n, BATCH_CLASSES if classes else 0,
+                                 unit_of.ctypes.data, C.byref(nu), ub.ctypes.data,
+                                 int(max_buffers), lay.ctypes.data, nb.ctypes.data))
+    U = nu.value
+    if np.any(nb[:U] > max_buffers):
+        raise ValueError("batch_plan: a class has more buffers than max_buffers")
+    units = [(int(ub[u, 0]), int(ub[u, 1])) for u in range(U)]
+    layouts = [lay[u, :nb[u]].copy() for u in range(U)]
+    return unit_of, units, layouts
 
 
 class Batch:
