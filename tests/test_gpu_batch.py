@@ -141,3 +141,18 @@ def test_batch_argument_errors():
         b.set_tuning(0, 48)
     with pytest.raises(spg.SpgError):
         b.result(1)
+
+
+def test_host_plan_matches_the_batch():
+    # spg_batch_plan (host only) forms the units spg_batch_create forms
+    insts = _class_instances()
+    peps = [spg.build_peps(i) for i, _, _, _ in insts]
+    chis = [c for _, c, _, _ in insts]
+    Ms = [m for _, _, m, _ in insts]
+    precs = [p for _, _, _, p in insts]
+    b = spg.Batch(peps, chi=chis, max_states=Ms, precision=precs, n_streams=3)
+    nu, of = b.units()
+    shapes = [(i.rows, i.cols, i.d, int(i.kings)) for i, _, _, _ in insts]
+    unit_of, units, _ = spg.batch_plan(shapes, chis, Ms, precision=precs)
+    assert nu == len(units)
+    assert np.array_equal(of, unit_of)
