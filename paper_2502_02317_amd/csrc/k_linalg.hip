@@ -1224,7 +1224,7 @@ void gemm_f64(const GemmDesc &g, hipStream_t s) {
     set_error("gemm_f64: batch too large for one launch");
     throw Fail{SPG_ERR_UNSUPPORTED};
   }
-  if (g_tune.gemm_tile == 32)
+  if ((g.tile ? g.tile : g_tune.gemm_tile) == 32)
     gemm_launch<32>(h, s);
   else
     gemm_launch<64>(h, s);

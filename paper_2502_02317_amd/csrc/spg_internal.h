@@ -100,6 +100,7 @@ struct GemmDesc {
   // smode 2: every C(i, j) of batch (b1, b2) times w[b1] V[b1 d + b2]
   const double *sw = nullptr, *sV = nullptr;
   int sd = 0, smode = 0;
+  int tile = 0;           // output tile 32 or 64 for this product (0: the tuning's)
 };
 void gemm_f64(const GemmDesc &g, hipStream_t s);
 
