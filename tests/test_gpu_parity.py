@@ -383,3 +383,30 @@ def test_parent_without_positive_weight_takes_local_conditional():
     res = beam_search(inst, A, M)
     assert n == M == res["n_valid"]
     np.testing.assert_allclose(np.sort(lp), np.sort(res["scores"]), atol=1e-10)
+
+
+@pytest.mark.parametrize("rows", [2, 3])
+def test_panels_wider_than_80_columns_exact(rows):
+    """Sketches of 96 columns (chi = 80 plus 16): the range finder's 256-row
+    panels take the LDS-resident QR with one TSQR level and its 1280-row
+    panels the global-memory Householder QR.  With no couplings between rows
+    every row function has rank <= d = 16 across each cut (only the row's own
+    horizontal table crosses it), so the sketch spans the whole range and the
+    truncation to chi = 80 is exact: log Z equals the exact row transfer and
+    every row function equals the exact one (their overlap is 1), whatever
+    completion the 64 weightless directions take."""
+    from oracle.exact import row_transfer
+    print(f"wide panels rows={rows}", flush=True)
+    inst = random_potts(rows, 5, 16, True, seed=90 + rows, beta=0.5)
+    inst.pair_v[:] = 0.0
+    inst.pair_d[:] = 0.0
+    inst.pair_a[:] = 0.0
+    logs, lz_exact = row_transfer(inst, max_row_states=1 << 21)
+    _, env, lz = _gpu_mps(inst, 80)
+    assert abs(lz - lz_exact) <= 1e-9 * abs(lz_exact), (lz, lz_exact)
+    rows_gpu, _ = _rows_dense(env)
+    for r in range(rows):
+        a = mps_full(rows_gpu[r]).ravel()
+        b = np.exp(logs[r] - logs[r].max()).ravel()
+        ov = abs(a @ b) / (np.linalg.norm(a) * np.linalg.norm(b))
+        assert 1.0 - ov < 1e-10, (r, ov)
