@@ -278,14 +278,18 @@ int spg_batch_set_tuning(spg_batch_t *batch, int32_t i, int32_t gemm_tile);
 int spg_batch_autotune(spg_batch_t *batch, void *stream, int32_t *tile_out);
 /* Process default GEMM tile (32 or 64) of calls outside batches on this thread. */
 int spg_set_tuning(int32_t gemm_tile);
-/* Process default, on this thread, of how the boundary MPS runs the MPO's
- * d-index contractions (Sec. 2: the row transfer operator applied to the
- * boundary MPS).  1 (the default): for d in {8, 16, 24, 32}, one thread per
- * source column computes the d outputs that share it, each source entry read
- * once; 0: one thread per output.  Both give bitwise equal results; other d
- * always take the second.  Batches created afterwards keep the setting.
- * SPG_ERR_INVALID for any other value. */
-int spg_set_mpo_kernels(int32_t column_forms);
+/* Process defaults, on this thread, of two kernel forms of the boundary MPS
+ * (Sec. 2: the row transfer operator applied to the boundary MPS, then
+ * truncated); each pair of forms gives bitwise equal results.  Batches created
+ * afterwards keep the setting.  mpo_columns, the MPO's d-index contractions:
+ * 1 (default) for d in {8, 16, 24, 32} one thread per source column computes
+ * the d outputs that share it, each source entry read once; 0 one thread per
+ * output (other d always take it).  q_split, the orthonormal factor Q of the
+ * truncation's QR factorisations of one panel (at most 512 rows, 32 to 80
+ * columns): 1 (default) the panel kernel stores its reflectors and a second
+ * kernel forms Q with one compute unit per column; 0 the panel kernel forms Q
+ * itself.  SPG_ERR_INVALID for values other than 0 and 1. */
+int spg_set_kernel_forms(int32_t mpo_columns, int32_t q_split);
 
 /* ---- learned proposal ---------------------------------------------------
  * Not part of the paper's method: a 2-layer FP32 network that ranks the

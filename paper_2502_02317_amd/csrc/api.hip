@@ -2103,10 +2103,11 @@ int spg_set_tuning(int32_t gemm_tile) {
   return SPG_OK;
 }
 
-int spg_set_mpo_kernels(int32_t column_forms) {
-  if (column_forms != 0 && column_forms != 1)
-    return fail(SPG_ERR_INVALID, "spg_set_mpo_kernels: column_forms must be 0 or 1");
-  g_tune.mpo_cols = column_forms;
+int spg_set_kernel_forms(int32_t mpo_columns, int32_t q_split) {
+  if ((mpo_columns != 0 && mpo_columns != 1) || (q_split != 0 && q_split != 1))
+    return fail(SPG_ERR_INVALID, "spg_set_kernel_forms: each switch must be 0 or 1");
+  g_tune.mpo_cols = mpo_columns;
+  g_tune.qform_split = q_split;
   return SPG_OK;
 }
 

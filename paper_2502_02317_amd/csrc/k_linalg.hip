@@ -526,10 +526,12 @@ __device__ __forceinline__ void wave_sums(const double (&d)[CPW], double (&out)[
 template <int RPL, int CPW>
 __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int mb, const double *X, long xr,
                                                 long xc, double *Qo, long qr, long qc, double *Rs,
-                                                int want_q, long ist) {
+                                                int want_q, double *Vq, double *Tq, long ist) {
   SPG_INST(X);
   SPG_INST(Qo);
   SPG_INST(Rs);
+  SPG_INST(Vq);
+  SPG_INST(Tq);
   // workgroup x factorises rows [x mb, min(m, (x+1) mb)) (one TSQR block;
   // mb = m for a single panel): its Q rows and its own n x n R
   {
@@ -721,6 +723,19 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int mb, const dou
     }
   }
   if (!want_q) return;
+  if (Vq) {
+    // Q formed by k_qform: the reflectors (column-major m x n, rows below the
+    // diagonal; the rest is not read) and the taus
+#pragma unroll
+    for (int s = 0; s < CPW; ++s)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int i = lane + 64 * t;
+        if (i < m && c0 + s < n) Vq[(long)i + (long)(c0 + s) * m] = a[s][t];
+      }
+    if (tid < n) Tq[tid] = taus[tid];
+    return;
+  }
 
   // ---- Q in place, reflectors published kRegSlots at a time
   for (int lo = ((n - 1) / kRegSlots) * kRegSlots; lo >= 0; lo -= kRegSlots) {
@@ -807,6 +822,101 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int mb, const dou
         if (i < m) Qo[(long)i * qr + (long)j * qc] = buf[j * kStageLd + r];
       }
     }
+  }
+}
+
+// Q of a register-kernel panel from its stored reflectors, one wavefront per
+// column and four columns per workgroup (so the columns' chains run on
+// kQformCols-wide groups of compute units): column c is H_c e_c, then H_j
+// applied for j = c-1 down to 0, each as a dot product with v_j, its total
+// over the wavefront and an update, exactly as the panel kernel's own Q
+// formation does it.  The total is taken in the slot c % CPW of the panel
+// kernel's batched sums (the other slots zero; each slot's total depends on
+// that slot alone), so Q is bitwise the panel kernel's.  The reflectors pass
+// through LDS kRegSlots at a time, the next chunk's loads in flight while the
+// current chunk is applied.  Column-major output, m <= 64 RPL.
+constexpr int kQformCols = 4;
+template <int RPL, int CPW>
+__global__ __launch_bounds__(64 * kQformCols) void k_qform(int m, int n, const double *Vq,
+                                                           const double *Tq, double *Qo, long qc,
+                                                           long ist) {
+  SPG_INST(Vq);
+  SPG_INST(Tq);
+  SPG_INST(Qo);
+  constexpr int kChunk = kRegSlots * 64 * RPL;              // doubles of one chunk
+  constexpr int kPer = kChunk / (64 * kQformCols);          // per thread
+  __shared__ double vbuf[kChunk];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int cw0 = blockIdx.x * kQformCols;
+  const int c = cw0 + w, slot = c % CPW;
+  const int ctop = min(n, cw0 + kQformCols) - 1;            // highest column of the group
+  // raw loads of chunk [lo, lo + kRegSlots): element e = jj * 64 RPL + i of
+  // reflector lo + jj (a valid address where the row is not read)
+  auto fetch = [&](int lo, double (&raw)[kPer]) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = tid + 64 * kQformCols * k;
+      const int jj = e / (64 * RPL), i = e % (64 * RPL), j = lo + jj;
+      raw[k] = Vq[(j <= ctop && i > j && i < m) ? (long)i + (long)j * m : 0L];
+    }
+  };
+  auto publish = [&](int lo, const double (&raw)[kPer]) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = tid + 64 * kQformCols * k;
+      const int jj = e / (64 * RPL), i = e % (64 * RPL), j = lo + jj;
+      vbuf[e] = (i < j) ? 0.0 : (i == j) ? 1.0 : (i < m ? raw[k] : 0.0);
+    }
+  };
+  double q[RPL];
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) q[t] = 0.0;
+  double raw[kPer];
+  int lo = (ctop / kRegSlots) * kRegSlots;
+  fetch(lo, raw);
+  for (; lo >= 0; lo -= kRegSlots) {
+    const int hi = min(ctop + 1, lo + kRegSlots);
+    __syncthreads();
+    publish(lo, raw);
+    __syncthreads();
+    if (lo >= kRegSlots) fetch(lo - kRegSlots, raw);        // next chunk, in flight
+    if (c > ctop) continue;
+    for (int j = hi - 1; j >= lo; --j) {
+      if (j > c) continue;
+      const double tj = Tq[j];
+      const double *vj = vbuf + (j - lo) * (64 * RPL);
+      double v[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) v[t] = vj[lane + 64 * t];
+      if (j == c) {
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int i = lane + 64 * t;
+          q[t] = (i < j) ? 0.0 : (i == j) ? 1.0 - tj : -tj * v[t];
+        }
+      } else if (tj != 0.0) {
+        double dot[CPW], tot[CPW];
+        double dt = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) dt = fma(v[t], q[t], dt);
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) dot[k] = (k == slot) ? dt : 0.0;
+        wave_sums<CPW>(dot, tot);
+        double tk = 0.0;
+#pragma unroll
+        for (int k = 0; k < CPW; ++k)
+          if (k == slot) tk = tot[k];
+        const double f = -tj * tk;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) q[t] = fma(f, v[t], q[t]);
+      }
+    }
+  }
+  if (c > ctop) return;
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int i = lane + 64 * t;
+    if (i < m) Qo[(long)i + (long)c * qc] = q[t];
   }
 }
 
@@ -1247,11 +1357,18 @@ constexpr int kQrRegRows = 512, kQrRegCols = 80;
 template <int RPL>
 static void qr_reg_rows(int cpw, int m, int n, int mb, const double *X, long xr, long xc,
                         double *Q, long qr, long qc, double *R, int want_q, dim3 grid, long ist,
-                        hipStream_t s) {
+                        hipStream_t s, double *Vq = nullptr, double *Tq = nullptr) {
+  // with Vq and Tq (one panel, column-major Q): the panel kernel stores the
+  // reflectors and k_qform forms Q, a compute unit per column
 #define SPG_QR_REG(C)                                                                         \
   case C:                                                                                      \
     hipLaunchKernelGGL((k_qr_reg<RPL, C>), grid, dim3(1024), 0, s, m, n, mb, X, xr, xc, Q, qr, \
-                       qc, R, want_q, ist);                                                    \
+                       qc, R, want_q, Vq, Tq, ist);                                            \
+    if (Vq) {                                                                                  \
+      SPG_CHECK_LAUNCH();                                                                      \
+      hipLaunchKernelGGL((k_qform<RPL, C>), dim3((n + kQformCols - 1) / kQformCols, grid.y),   \
+                         dim3(64 * kQformCols), 0, s, m, n, Vq, Tq, Q, qc, ist);               \
+    }                                                                                          \
     break;
   switch (cpw) {
     SPG_QR_REG(1)
@@ -1270,12 +1387,17 @@ static void qr_reg_rows(int cpw, int m, int n, int mb, const double *X, long xr,
 // grid.x workgroups, each factorising mb rows of the panel (the last one the
 // rest); the rows per lane are set by mb
 static void qr_reg(int m, int n, int mb, const double *X, long xr, long xc, double *Q, long qr,
-                   long qc, double *R, int want_q, dim3 grid, long ist, hipStream_t s) {
+                   long qc, double *R, int want_q, dim3 grid, long ist, hipStream_t s,
+                   double *Vq = nullptr, double *Tq = nullptr) {
   const int cpw = (n + 15) / 16;
-  if (mb <= 64) qr_reg_rows<1>(cpw, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
-  else if (mb <= 128) qr_reg_rows<2>(cpw, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
-  else if (mb <= 256) qr_reg_rows<4>(cpw, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
-  else qr_reg_rows<8>(cpw, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s);
+  if (mb <= 64)
+    qr_reg_rows<1>(cpw, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s, Vq, Tq);
+  else if (mb <= 128)
+    qr_reg_rows<2>(cpw, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s, Vq, Tq);
+  else if (mb <= 256)
+    qr_reg_rows<4>(cpw, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s, Vq, Tq);
+  else
+    qr_reg_rows<8>(cpw, m, n, mb, X, xr, xc, Q, qr, qc, R, want_q, grid, ist, s, Vq, Tq);
 }
 
 // One LDS panel factorisation launch.
@@ -1306,7 +1428,11 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
   const long ist = g_bc.ist;
   if (m <= kQrRegRows && n <= kQrRegCols) {
     KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
-    qr_reg(m, n, m, X, xr, xc, Q, qr, qc, R, want_q, dim3(1, nI), ist, s);
+    // Q of 32 or more columns, column-major: formed by k_qform from the stored
+    // reflectors (work: m x n reflectors, then n taus)
+    const bool split = g_tune.qform_split && want_q && qr == 1 && n >= 32 && work != nullptr;
+    qr_reg(m, n, m, X, xr, xc, Q, qr, qc, R, want_q, dim3(1, nI), ist, s,
+           split ? work : nullptr, split ? work + (long)m * n : nullptr);
     return;
   }
   if (n <= kQrRegCols) {

@@ -110,6 +110,7 @@ struct Tuning {
   int gemm_tile = 32;   // GEMM output tile: 32 or 64
   int splitk = 1;       // deterministic split-K for skinny long-K products
   int mpo_cols = 1;     // column forms of the MPO d-index contractions (d in {8, 16, 24, 32})
+  int qform_split = 1;  // Q of one-panel register QRs by k_qform (a compute unit per column)
 };
 extern thread_local Tuning g_tune;
 

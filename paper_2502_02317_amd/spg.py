@@ -70,7 +70,7 @@ EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals
            "spg_proposal_train", "spg_proposal_features", "spg_proposal_forward",
            "spg_proposal_loss_grad", "spg_proposal_adam", "spg_search_stats",
            "spg_batch_create", "spg_batch_free", "spg_batch_run", "spg_batch_result",
-           "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning", "spg_set_mpo_kernels",
+           "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning", "spg_set_kernel_forms",
            "spg_batch_info", "spg_batch_plan",
            "spg_droplets", "spg_ising_to_potts"]
 KERNEL_CLASSES = ["gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box", "right_env",
@@ -130,7 +130,7 @@ def load() -> C.CDLL:
     lib.spg_batch_set_tuning.argtypes = [vp, i32, i32]
     lib.spg_batch_autotune.argtypes = [vp, vp, vp]
     lib.spg_set_tuning.argtypes = [i32]
-    lib.spg_set_mpo_kernels.argtypes = [i32]
+    lib.spg_set_kernel_forms.argtypes = [i32, i32]
     lib.spg_batch_plan.argtypes = [vp, vp, i32, i32, vp, i32p, vp, i32, vp, vp]
     for name in ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals_noalloc",
                  "spg_branch_and_bound", "spg_topm",
@@ -139,7 +139,7 @@ def load() -> C.CDLL:
                  "spg_proposal_features", "spg_proposal_forward", "spg_proposal_loss_grad",
                  "spg_proposal_adam", "spg_search_stats", "spg_batch_create", "spg_batch_run",
                  "spg_batch_result", "spg_batch_set_tuning", "spg_batch_autotune",
-                 "spg_set_tuning", "spg_set_mpo_kernels", "spg_batch_info", "spg_batch_plan",
+                 "spg_set_tuning", "spg_set_kernel_forms", "spg_batch_info", "spg_batch_plan",
                  "spg_droplets",
                  "spg_ising_to_potts"]:
         getattr(lib, name).restype = C.c_int
@@ -508,11 +508,13 @@ def set_tuning(gemm_tile: int) -> None:
     _check(load().spg_set_tuning(int(gemm_tile)))
 
 
-def set_mpo_kernels(column_forms: bool) -> None:
-    """How the boundary MPS runs the MPO d-index contractions on this thread:
-    True (default) the column forms (d in {8, 16, 24, 32}), False one thread per
-    output.  Results are bitwise equal."""
-    _check(load().spg_set_mpo_kernels(1 if column_forms else 0))
+def set_kernel_forms(mpo_columns: bool = True, q_split: bool = True) -> None:
+    """Kernel forms of the boundary MPS on this thread (each pair gives bitwise
+    equal results): mpo_columns, the column forms of the MPO d-index
+    contractions (d in {8, 16, 24, 32}) rather than one thread per output;
+    q_split, Q of one-panel QR factorisations formed by a second kernel with a
+    compute unit per column rather than by the panel kernel."""
+    _check(load().spg_set_kernel_forms(1 if mpo_columns else 0, 1 if q_split else 0))
 
 
 def batch_plan(shapes, chi, max_states, num_sweeps=1, precision="fp64", oversample=16,
