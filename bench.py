@@ -37,11 +37,13 @@ WORKLOAD = dict(name="kings8x8_d16", seed=0, chi=32, max_states=1024, num_sweeps
                 oversample=16, power_iters=1)
 # MI355X published peaks
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "hbm_GBs": 8000.0}
-FLOP_CLASSES = {"gemm_f64", "qr_f64", "right_env", "marginals", "beam_update", "u_mfma"}
+FLOP_CLASSES = {"gemm_f64", "qr_f64", "qform_f64", "right_env", "marginals", "beam_update",
+                "u_mfma"}
 BYTE_CLASSES = {"normalize_box", "select_topm"}
 
 
-CLASS_KERNEL = {"gemm_f64": "k_gemm<32>", "qr_f64": "k_qr_reg<8, 3>", "jacobi_svd_f64": "k_jacobi<3>",
+CLASS_KERNEL = {"gemm_f64": "k_gemm<32>", "qr_f64": "k_qr_reg<8, 3>", "qform_f64": "k_qform<8, 3>",
+                "jacobi_svd_f64": "k_jacobi<3>",
                 "normalize_box": "k_box_scale", "right_env": "k_right_env",
                 "marginals": "k_marginals", "select_topm": "k_select",
                 "beam_update": "k_beam_update", "final_sort": "k_final_sort",
@@ -287,7 +289,7 @@ def batching_leg(spg, torch, stream):
     torch.cuda.synchronize()
     spg.profile_enable(False)
     rates = {}
-    for k in ("qr_f64", "gemm_f64"):
+    for k in ("qr_f64", "qform_f64", "gemm_f64"):
         cnt, ms, work = spg.profile_query(k)
         if ms > 0.0:
             ach = work / (ms * 1e-3) / 1e12
@@ -622,7 +624,7 @@ def main():
         achieved = work / (tms * 1e-3) / 1e12
         # the QR kernels run on the FP64 vector ALU, the GEMMs on the FP64
         # matrix cores (the two share one peak on this chip)
-        bound = "alu" if dom in ("qr_f64",) else "mfma"
+        bound = "alu" if dom in ("qr_f64", "qform_f64") else "mfma"
         roof = {"bound": bound, "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s"}
     elif dom in BYTE_CLASSES:
         achieved = work / (tms * 1e-3) / 1e9
@@ -635,7 +637,7 @@ def main():
     roof["kernel_class"] = dom
     roof["launches_per_step"] = cnt / args.steps
     roof["avg_launch_us"] = tms * 1e3 / max(cnt, 1)
-    if dom in ("qr_f64", "jacobi_svd_f64") and roof["frac"] is not None:
+    if dom in ("qr_f64", "qform_f64", "jacobi_svd_f64") and roof["frac"] is not None:
         # one workgroup per launch at these panel sizes: the rate against the
         # peak of the one compute unit it occupies (256 on the chip)
         roof["workgroups_per_launch"] = 1
@@ -659,10 +661,10 @@ def main():
     # (profiled passes), for the search contractions (FP64 path and mixed
     # path) and for the boundary MPS
     search_cls = ("right_env", "marginals", "beam_update", "u_mfma")
-    bmps_cls = ("gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box")
+    bmps_cls = ("gemm_f64", "qr_f64", "qform_f64", "jacobi_svd_f64", "normalize_box")
     s_fl = search_formula_flops(dims_last, R, C, d, M)
     b_ms = sum(prof[k][1] for k in bmps_cls if k in prof) / args.steps
-    b_fl = (prof["gemm_f64"][2] + prof["qr_f64"][2]) / args.steps
+    b_fl = (prof["gemm_f64"][2] + prof["qr_f64"][2] + prof["qform_f64"][2]) / args.steps
 
     def search_rate(pr, precision):
         sm = sum(pr[k][1] for k in search_cls if k in pr) / args.steps

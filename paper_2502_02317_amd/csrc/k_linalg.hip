@@ -1362,10 +1362,14 @@ static void qr_reg_rows(int cpw, int m, int n, int mb, const double *X, long xr,
   // reflectors and k_qform forms Q, a compute unit per column
 #define SPG_QR_REG(C)                                                                         \
   case C:                                                                                      \
-    hipLaunchKernelGGL((k_qr_reg<RPL, C>), grid, dim3(1024), 0, s, m, n, mb, X, xr, xc, Q, qr, \
-                       qc, R, want_q, Vq, Tq, ist);                                            \
-    if (Vq) {                                                                                  \
+    {                                                                                          \
+      KTimer kt_("qr_f64", s, qr_flops(m, n, want_q && !Vq));                                  \
+      hipLaunchKernelGGL((k_qr_reg<RPL, C>), grid, dim3(1024), 0, s, m, n, mb, X, xr, xc, Q,   \
+                         qr, qc, R, want_q, Vq, Tq, ist);                                      \
       SPG_CHECK_LAUNCH();                                                                      \
+    }                                                                                          \
+    if (Vq) {                                                                                  \
+      KTimer kt_("qform_f64", s, qr_flops(m, n, 1) - qr_flops(m, n, 0));                        \
       hipLaunchKernelGGL((k_qform<RPL, C>), dim3((n + kQformCols - 1) / kQformCols, grid.y),   \
                          dim3(64 * kQformCols), 0, s, m, n, Vq, Tq, Q, qc, ist);               \
     }                                                                                          \
@@ -1427,7 +1431,7 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
   const unsigned nI = (unsigned)g_bc.n;
   const long ist = g_bc.ist;
   if (m <= kQrRegRows && n <= kQrRegCols) {
-    KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
+    // (timed inside qr_reg_rows: the panel kernel, and k_qform when it runs)
     // Q of 32 or more columns, column-major: formed by k_qform from the stored
     // reflectors (work: m x n reflectors, then n taus)
     const bool split = g_tune.qform_split && want_q && qr == 1 && n >= 32 && work != nullptr;
@@ -1446,16 +1450,11 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
       double *S = Q1 + (long)m * n;               // p*n x n row-major (stacked R_b)
       double *Qs = S + (long)p * n * n;           // p*n x n row-major
       double *Rt = Qs + (long)p * n * n;          // n x n
-      {
-        KTimer kt_("qr_f64", s, qr_flops(m, n, want_q));
-        qr_reg(m, n, mb, X, xr, xc, want_q ? Q1 : nullptr, (long)n, 1L, S, want_q, dim3(p, nI),
-               ist, s);
-      }
-      {
-        KTimer kt_("qr_f64", s, qr_flops(p * n, n, want_q));
-        qr_reg(p * n, n, p * n, S, (long)n, 1L, want_q ? Qs : nullptr, (long)n, 1L, R ? R : Rt,
-               want_q, dim3(1, nI), ist, s);
-      }
+      // (each launch timed inside qr_reg_rows)
+      qr_reg(m, n, mb, X, xr, xc, want_q ? Q1 : nullptr, (long)n, 1L, S, want_q, dim3(p, nI),
+             ist, s);
+      qr_reg(p * n, n, p * n, S, (long)n, 1L, want_q ? Qs : nullptr, (long)n, 1L, R ? R : Rt,
+             want_q, dim3(1, nI), ist, s);
       if (!want_q) return;
       const int full = m / mb, tail = m - full * mb;
       GemmDesc g{};

@@ -73,7 +73,7 @@ EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals
            "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning", "spg_set_kernel_forms",
            "spg_batch_info", "spg_batch_plan",
            "spg_droplets", "spg_ising_to_potts"]
-KERNEL_CLASSES = ["gemm_f64", "qr_f64", "jacobi_svd_f64", "normalize_box", "right_env",
+KERNEL_CLASSES = ["gemm_f64", "qr_f64", "qform_f64", "jacobi_svd_f64", "normalize_box", "right_env",
                   "marginals", "select_topm", "beam_update", "final_sort", "propose",
                   "guided_eval", "mlp_grad", "merge_branches", "droplets", "u_mfma"]
 
