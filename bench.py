@@ -279,6 +279,16 @@ def batching_leg(spg, torch, stream):
     b.run(use_graph=False, stream=stream)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - a
+    # the autotuner's choices (GEMM tile, MPO contraction form, Q formation;
+    # tuning itself untimed), then the batch timed again with them
+    b.autotune(stream=stream)
+    b.run(use_graph=False, stream=stream)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    b.run(use_graph=False, stream=stream)
+    torch.cuda.synchronize()
+    t_tuned = time.perf_counter() - a
+    choices = [b.tuning(i) for i in range(n)]
     # one more batched run with per-launch events: the FP64 kernel classes'
     # rates when a launch covers every member of a shape class (one
     # workgroup per member for the QR and the Jacobi SVD); work over the
@@ -302,6 +312,11 @@ def batching_leg(spg, torch, stream):
             "instances": n, "units": units, "evals": ev,
             "one_by_one_s": t_one, "batched_s": t_batch, "speedup": t_one / t_batch,
             "evals_per_s_one_by_one": ev / t_one, "evals_per_s_batched": ev / t_batch,
+            "batched_autotuned_s": t_tuned, "speedup_autotuned": t_one / t_tuned,
+            "autotuned_choices": {
+                "gemm_tile_64": sum(c["gemm_tile"] == 64 for c in choices),
+                "mpo_columns": sum(c["mpo_columns"] for c in choices),
+                "q_split": sum(c["q_split"] for c in choices), "of_instances": n},
             "kernel_rates_batched": rates}
 
 

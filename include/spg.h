@@ -272,10 +272,18 @@ int spg_batch_result(const spg_batch_t *batch, int32_t i, int32_t *states_out,
                      double *energies_out, double *logp_out, int32_t *n_out, double *log_Z);
 /* GEMM output tile (32 or 64) of instance i's unit; drops a captured graph. */
 int spg_batch_set_tuning(spg_batch_t *batch, int32_t i, int32_t gemm_tile);
-/* Autotuner: times every unit (class or single instance) with each GEMM tile
- * and keeps the fastest; reruns the batch with the choices (synchronous).
- * tile_out HOST int32 [n] (may be NULL): the tile of each instance. */
+/* Autotuner: times every unit (class or single instance) and, one knob after
+ * the other, keeps the fastest GEMM tile (64 or 32), then the faster form of
+ * the MPO d-index contractions and of the Q formation of one-panel QRs (the
+ * two forms of each give bitwise equal results, see spg_set_kernel_forms);
+ * reruns the batch with the choices (synchronous).  tile_out HOST int32 [n]
+ * (may be NULL): the tile of each instance. */
 int spg_batch_autotune(spg_batch_t *batch, void *stream, int32_t *tile_out);
+/* The launch choices of instance i's unit, each output HOST and optional: the
+ * GEMM tile, the MPO contraction form and the Q formation (1 = the column /
+ * split forms, as in spg_set_kernel_forms).  SPG_ERR_INVALID for a bad index. */
+int spg_batch_tuning(const spg_batch_t *batch, int32_t i, int32_t *gemm_tile,
+                     int32_t *mpo_columns, int32_t *q_split);
 /* Process default GEMM tile (32 or 64) of calls outside batches on this thread. */
 int spg_set_tuning(int32_t gemm_tile);
 /* Process defaults, on this thread, of two kernel forms of the boundary MPS

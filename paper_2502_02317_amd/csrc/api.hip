@@ -2043,6 +2043,16 @@ int spg_batch_set_tuning(spg_batch_t *b, int32_t i, int32_t gemm_tile) {
   return SPG_OK;
 }
 
+int spg_batch_tuning(const spg_batch_t *b, int32_t i, int32_t *gemm_tile, int32_t *mpo_columns,
+                     int32_t *q_split) {
+  if (!b || i < 0 || i >= b->n) return fail(SPG_ERR_INVALID, "spg_batch_tuning: bad batch or index");
+  const Tuning &t = b->unit_tune[b->inst_unit[i]];
+  if (gemm_tile) *gemm_tile = t.gemm_tile;
+  if (mpo_columns) *mpo_columns = t.mpo_cols;
+  if (q_split) *q_split = t.qform_split;
+  return SPG_OK;
+}
+
 int spg_batch_autotune(spg_batch_t *b, void *stream, int32_t *tile_out) {
   SPG_TRY
   if (!b) return fail(SPG_ERR_INVALID, "spg_batch_autotune: null batch");
@@ -2052,32 +2062,43 @@ int spg_batch_autotune(spg_batch_t *b, void *stream, int32_t *tile_out) {
     SPG_HIP(hipStreamSynchronize(s));
     b->warm = true;
   }
-  // every unit (a class or a single instance) timed with each GEMM tile,
-  // twice each (the first run only warms); the fastest tile is kept
+  // every unit (a class or a single instance) timed twice per candidate (the
+  // first run only warms); a greedy search over three knobs, each kept at its
+  // fastest value before the next is tried: the GEMM tile (64, 32), then the
+  // MPO d-index contraction form and the Q formation of one-panel QRs (each
+  // form pair gives bitwise equal results)
   hipEvent_t e0, e1;
   SPG_HIP(hipEventCreate(&e0));
   SPG_HIP(hipEventCreate(&e1));
-  const int cand[2] = {64, 32};
   try {
-    for (size_t u = 0; u < b->unit_cls.size(); ++u) {
-      float best = 1e30f;
-      int best_tile = 64;
-      for (int t : cand) {
-        b->unit_tune[u].gemm_tile = t;
-        float ms = 0.0f;
-        for (int rep = 0; rep < 2; ++rep) {
-          SPG_HIP(hipEventRecord(e0, s));
-          enqueue_unit(b, (int)u, s);
-          SPG_HIP(hipEventRecord(e1, s));
-          SPG_HIP(hipEventSynchronize(e1));
-          SPG_HIP(hipEventElapsedTime(&ms, e0, e1));
-        }
-        if (ms < best) {
-          best = ms;
-          best_tile = t;
-        }
+    auto time_unit = [&](size_t u) {
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2; ++rep) {
+        SPG_HIP(hipEventRecord(e0, s));
+        enqueue_unit(b, (int)u, s);
+        SPG_HIP(hipEventRecord(e1, s));
+        SPG_HIP(hipEventSynchronize(e1));
+        SPG_HIP(hipEventElapsedTime(&ms, e0, e1));
       }
-      b->unit_tune[u].gemm_tile = best_tile;
+      return ms;
+    };
+    for (size_t u = 0; u < b->unit_cls.size(); ++u) {
+      Tuning &tu = b->unit_tune[u];
+      int *knob[3] = {&tu.gemm_tile, &tu.mpo_cols, &tu.qform_split};
+      const int cand[3][2] = {{64, 32}, {1, 0}, {1, 0}};
+      for (int k = 0; k < 3; ++k) {
+        float best = 1e30f;
+        int best_v = cand[k][0];
+        for (int v : cand[k]) {
+          *knob[k] = v;
+          const float ms = time_unit(u);
+          if (ms < best) {
+            best = ms;
+            best_v = v;
+          }
+        }
+        *knob[k] = best_v;
+      }
     }
   } catch (...) {
     (void)hipEventDestroy(e0);

@@ -71,7 +71,7 @@ EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals
            "spg_proposal_loss_grad", "spg_proposal_adam", "spg_search_stats",
            "spg_batch_create", "spg_batch_free", "spg_batch_run", "spg_batch_result",
            "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning", "spg_set_kernel_forms",
-           "spg_batch_info", "spg_batch_plan",
+           "spg_batch_info", "spg_batch_plan", "spg_batch_tuning",
            "spg_droplets", "spg_ising_to_potts"]
 KERNEL_CLASSES = ["gemm_f64", "qr_f64", "qform_f64", "jacobi_svd_f64", "normalize_box", "right_env",
                   "marginals", "select_topm", "beam_update", "final_sort", "propose",
@@ -129,6 +129,7 @@ def load() -> C.CDLL:
     lib.spg_batch_result.argtypes = [vp, i32, vp, vp, vp, i32p, f64p]
     lib.spg_batch_set_tuning.argtypes = [vp, i32, i32]
     lib.spg_batch_autotune.argtypes = [vp, vp, vp]
+    lib.spg_batch_tuning.argtypes = [vp, i32, i32p, i32p, i32p]
     lib.spg_set_tuning.argtypes = [i32]
     lib.spg_set_kernel_forms.argtypes = [i32, i32]
     lib.spg_batch_plan.argtypes = [vp, vp, i32, i32, vp, i32p, vp, i32, vp, vp]
@@ -140,6 +141,7 @@ def load() -> C.CDLL:
                  "spg_proposal_adam", "spg_search_stats", "spg_batch_create", "spg_batch_run",
                  "spg_batch_result", "spg_batch_set_tuning", "spg_batch_autotune",
                  "spg_set_tuning", "spg_set_kernel_forms", "spg_batch_info", "spg_batch_plan",
+                 "spg_batch_tuning",
                  "spg_droplets",
                  "spg_ising_to_potts"]:
         getattr(lib, name).restype = C.c_int
@@ -607,6 +609,13 @@ class Batch:
         of = np.zeros(self.n, dtype=np.int32)
         _check(load().spg_batch_info(self.handle, C.byref(nu), of.ctypes.data))
         return nu.value, of
+
+    def tuning(self, i: int) -> dict:
+        """The launch choices of instance i's unit: GEMM tile, MPO contraction
+        form and Q formation (True = the column / split forms)."""
+        t, m, q = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        _check(load().spg_batch_tuning(self.handle, int(i), C.byref(t), C.byref(m), C.byref(q)))
+        return {"gemm_tile": t.value, "mpo_columns": bool(m.value), "q_split": bool(q.value)}
 
     def autotune(self, stream=None) -> np.ndarray:
         out = np.zeros(self.n, dtype=np.int32)

@@ -110,6 +110,12 @@ def test_autotuned_batch_equals_each_instance_alone_with_its_tile():
                   precision=[p for _, _, _, p in insts], n_streams=2)
     tiles = b.autotune()
     assert set(tiles.tolist()) <= {32, 64}
+    # the two kernel forms it also chooses give bitwise equal results, so each
+    # instance equals its run alone with the default forms and its tile
+    for i in range(b.n):
+        t = b.tuning(i)
+        assert t["gemm_tile"] == tiles[i]
+        assert t["mpo_columns"] in (True, False) and t["q_split"] in (True, False)
     for i, (inst, chi, M, prec) in enumerate(insts):
         _same(b.result(i), _alone(inst, chi, M, prec, int(tiles[i])), f"instance {i}")
     b.run(use_graph=True)
