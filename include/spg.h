@@ -15,7 +15,11 @@
  *     Arguments are validated before anything is enqueued, so an error return
  *     leaves outputs untouched unless stated otherwise.
  *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  Work is
- *     enqueued asynchronously; a call blocks only when it writes a HOST output.
+ *     enqueued on it; a call blocks when it writes a HOST output, when it
+ *     allocates device memory (allocation and its zero fill are
+ *     device-synchronous: a new env, a first search on an env, larger beams),
+ *     and spg_boundary_mps blocks until its contraction has finished (its
+ *     workspace lives for the call).
  *   - Ownership: spg_peps_t and spg_env_t are library-owned and freed with
  *     their spg_free_* call.  Every buffer passed in is caller-owned; DEVICE
  *     pointers must stay valid until the enqueued work completes.
@@ -129,8 +133,9 @@ int spg_build_peps(const spg_instance_desc *desc, void *stream, spg_peps_t **out
  * log-scales) is held in a new env.  The bottom row is its exact chain of
  * nearest-neighbour factors at bond d (chi >= d); every other row has a unit-norm
  * centre at column 0, or at column 1 when column 0 kept its natural basis (at
- * most chi states, no rotation), with right isometries beyond it.  When log_Z_out (HOST) is not
- * NULL the call synchronises the stream and writes the estimate of log Z.
+ * most chi states, no rotation), with right isometries beyond it.  The call
+ * returns when the stream has finished the contraction; when log_Z_out (HOST)
+ * is not NULL it also writes the estimate of log Z.
  * Errors: SPG_ERR_INVALID, SPG_ERR_UNSUPPORTED (chi, precision), SPG_ERR_OOM,
  * SPG_ERR_HIP, SPG_ERR_NONFINITE (log Z requested and not finite). */
 int spg_boundary_mps(const spg_peps_t *peps, const spg_mps_params *params, void *stream,
