@@ -652,6 +652,13 @@ def main():
     roof["kernel_class"] = dom
     roof["launches_per_step"] = cnt / args.steps
     roof["avg_launch_us"] = tms * 1e3 / max(cnt, 1)
+    if dom == "qr_f64" and prof.get("qform_f64", (0, 0.0, 0.0))[1] > 0.0:
+        # the factorisation and the Q formation of the same QRs together (the
+        # accounting of a QR with Q in one kernel)
+        qc_, qt_, qw_ = prof["qform_f64"]
+        both = (work + qw_) / ((tms + qt_) * 1e-3) / 1e12
+        roof["qr_with_q_formation"] = {"achieved": both, "frac": both / PEAK["fp64"],
+                                       "kernels": ["k_qr_reg", "k_qform"]}
     if dom in ("qr_f64", "qform_f64", "jacobi_svd_f64") and roof["frac"] is not None:
         # one workgroup per launch at these panel sizes: the rate against the
         # peak of the one compute unit it occupies (256 on the chip)
