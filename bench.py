@@ -421,6 +421,53 @@ def kings12_leg(spg, torch, stream):
     return out
 
 
+def gemm_fp32_leg(spg, torch, stream):
+    """The precision form of the boundary MPS's contractions: every GEMM of the
+    contraction with FP32 operands and FP32 accumulation on the matrix cores
+    (QR, SVD and the MPO d-index contractions FP64), against the FP64 GEMMs on
+    the same instance: time, log Z, the row sums' signs, and the FP64 search
+    on each result (its best energy)."""
+    from workloads import config_instance
+    out = {}
+    for name, chi, M in (("kings8x8_d16", 32, 1024), ("kings12x12_d24", 64, 4096)):
+        inst = config_instance(name, 0)
+        N = inst.rows * inst.cols
+        dev = torch.device("cuda:0")
+        st = torch.zeros((M, N), dtype=torch.int32, device=dev)
+        en = torch.zeros(M, dtype=torch.float64, device=dev)
+        lp = torch.zeros(M, dtype=torch.float64, device=dev)
+        peps = spg.build_peps(inst, stream)
+        rec = {"workload": f"{name} chi={chi} M={M} (seed 0)"}
+        for tag, f32 in (("fp64", False), ("fp32_products", True)):
+            spg.set_gemm_precision(f32)
+            try:
+                spg.boundary_mps(peps, chi, stream=stream, want_logZ=False)     # warm
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                env, _ = spg.boundary_mps(peps, chi, stream=stream, want_logZ=False)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - a) * 1e3
+                try:
+                    _, lz = spg.boundary_mps(peps, chi, stream=stream)
+                except spg.SpgError:
+                    lz = None
+            finally:
+                spg.set_gemm_precision(False)
+            T, _ = spg.env_export(env)
+            sums = row_sums(spg.unpack_mps(T, spg.env_info(env).bond_dims))
+            n = spg.branch_and_bound(env, M, st, en, lp, stream=stream)
+            torch.cuda.synchronize()
+            rec[tag] = {"boundary_mps_ms": ms, "logZ": finite_or_none(lz),
+                        "rows_with_nonpositive_sum": [r for r, v in enumerate(sums)
+                                                      if not v > 0],
+                        "best_energy_fp64_search": float(en[0]) if n > 0 else None}
+        a64, a32 = rec["fp64"]["logZ"], rec["fp32_products"]["logZ"]
+        rec["dlogZ"] = abs(a32 - a64) if (a64 is not None and a32 is not None) else None
+        rec["speedup"] = rec["fp64"]["boundary_mps_ms"] / rec["fp32_products"]["boundary_mps_ms"]
+        out[name] = rec
+    return out
+
+
 def merge_leg(spg, torch, inst, wl, M, st, en, lp, stream):
     """Merging branches with equal frontiers: the FP64 search on the same
     boundary MPS with and without it, and with droplets collected while
@@ -732,6 +779,8 @@ def main():
                         "batching": batching_leg(spg, torch, stream)}
         say("kings12x12_d24")
         out["kings12x12_d24"] = kings12_leg(spg, torch, stream)
+        say("boundary MPS with FP32 products")
+        out["forms"]["boundary_mps_fp32_products"] = gemm_fp32_leg(spg, torch, stream)
         out["extensions"] = {"lattice_transforms": transforms_leg(spg, torch, inst, wl, M,
                                                                   stream),
                              "merge_branches": merge_leg(spg, torch, inst, wl, M, st, en, lp,

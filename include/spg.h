@@ -303,6 +303,16 @@ int spg_set_tuning(int32_t gemm_tile);
  * kernel forms Q with one compute unit per column; 0 the panel kernel forms Q
  * itself.  SPG_ERR_INVALID for values other than 0 and 1. */
 int spg_set_kernel_forms(int32_t mpo_columns, int32_t q_split);
+/* Reduced-precision form of the FP64 GEMMs (the precision form of the
+ * boundary MPS's contractions with the MPO and its environments, Sec. 2; not
+ * the default): with fp32_products = 1 every FP64 GEMM of calls on this thread
+ * rounds its FP64 operands to FP32 and multiplies and accumulates in FP32 on
+ * the matrix cores (v_mfma_f32_16x16x4f32), storing FP64 results; the QR, the
+ * Jacobi SVD, the MPO d-index contractions and every normalisation stay FP64.
+ * It covers the FP64 search's per-ancestor products as well, so set it around
+ * the calls it is meant for.  0 (default) restores FP64 products.
+ * SPG_ERR_INVALID for other values. */
+int spg_set_gemm_precision(int32_t fp32_products);
 
 /* ---- learned proposal ---------------------------------------------------
  * Not part of the paper's method: a 2-layer FP32 network that ranks the

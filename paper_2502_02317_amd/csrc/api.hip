@@ -2124,6 +2124,13 @@ int spg_set_tuning(int32_t gemm_tile) {
   return SPG_OK;
 }
 
+int spg_set_gemm_precision(int32_t fp32_products) {
+  if (fp32_products != 0 && fp32_products != 1)
+    return fail(SPG_ERR_INVALID, "spg_set_gemm_precision: fp32_products must be 0 or 1");
+  g_tune.gemm_f32 = fp32_products;
+  return SPG_OK;
+}
+
 int spg_set_kernel_forms(int32_t mpo_columns, int32_t q_split) {
   if ((mpo_columns != 0 && mpo_columns != 1) || (q_split != 0 && q_split != 1))
     return fail(SPG_ERR_INVALID, "spg_set_kernel_forms: each switch must be 0 or 1");

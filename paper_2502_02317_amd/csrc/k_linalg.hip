@@ -68,9 +68,13 @@ __device__ __forceinline__ void householder(double al, double sg, double am, dou
 // B[k + l / 16][col l % 16], and holds D[l / 16 + 4 q][l % 16], q = 0..3.
 // The tile is picked per launch by the tuning.
 typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v_g __attribute__((ext_vector_type(4)));
 constexpr int kGemmKs = 32;
-template <int TILE>
-__global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
+// F32: the reduced-precision form, the staged FP64 operands rounded to FP32 at
+// the product and accumulated in FP32 (v_mfma_f32_16x16x4f32, same operand
+// layout; lane l holds D[4 (l / 16) + q][l % 16]); epilogue and output in FP64
+template <int TILE, bool F32>
+__device__ __forceinline__ void gemm_body(const GemmDesc &g) {
   constexpr int KS = kGemmKs, NQ = KS * TILE / 256;
   const int nbb = g.nb1 * g.nb2;
   const int inst = blockIdx.z / nbb, bz = blockIdx.z % nbb;   // class-batched instance
@@ -87,10 +91,14 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
   const int Kend = (g.kmax > 0) ? min(g.K, g.kmax - b1 * g.K) : g.K;
   constexpr int NB = TILE / 32;                 // 16 x 16 blocks per quadrant side
   d4v macc[NB][NB];
+  f4v_g macc32[NB][NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) macc[i][j] = (d4v){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NB; ++j) {
+      macc[i][j] = (d4v){0.0, 0.0, 0.0, 0.0};
+      macc32[i][j] = (f4v_g){0.f, 0.f, 0.f, 0.f};
+    }
   const int lane = tid & 63, wq = tid >> 6;
   const int qr0 = (wq >> 1) * (TILE / 2), qc0 = (wq & 1) * (TILE / 2);
   // consecutive threads take consecutive addresses of whichever index has
@@ -151,7 +159,11 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
       for (int i = 0; i < NB; ++i)
 #pragma unroll
         for (int j = 0; j < NB; ++j)
-          macc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], macc[i][j], 0, 0, 0);
+          if constexpr (F32)
+            macc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[i], (float)b[j],
+                                                                macc32[i][j], 0, 0, 0);
+          else
+            macc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], macc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -175,9 +187,23 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
 #pragma unroll
     for (int j = 0; j < NB; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        put(i0 + qr0 + 16 * i + (lane >> 4) + 4 * q, j0 + qc0 + 16 * j + (lane & 15),
-            macc[i][j][q]);
+      for (int q = 0; q < 4; ++q) {
+        if constexpr (F32)
+          put(i0 + qr0 + 16 * i + 4 * (lane >> 4) + q, j0 + qc0 + 16 * j + (lane & 15),
+              (double)macc32[i][j][q]);
+        else
+          put(i0 + qr0 + 16 * i + (lane >> 4) + 4 * q, j0 + qc0 + 16 * j + (lane & 15),
+              macc[i][j][q]);
+      }
+}
+
+template <int TILE>
+__global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
+  gemm_body<TILE, false>(g);
+}
+template <int TILE>
+__global__ __launch_bounds__(256) void k_gemm_f32p(GemmDesc g) {
+  gemm_body<TILE, true>(g);
 }
 
 // Deterministic split-K epilogue: C = alpha * sum_s P[s] + beta * C (P: [S][M][N]).
@@ -1283,7 +1309,7 @@ __global__ void k_fill_zero(double *p, size_t n, long ist) {
 
 thread_local Tuning g_tune;
 
-template <int TILE>
+template <int TILE, bool F32>
 static void gemm_launch(const GemmDesc &g, hipStream_t s) {
   const long tiles = (long)((g.N + TILE - 1) / TILE) * ((g.M + TILE - 1) / TILE) * g.nb1 * g.nb2;
   if (g_tune.splitk && g.ws && tiles < 64 && g.nb1 * g.nb2 == 1 && g.K >= 256) {
@@ -1301,7 +1327,10 @@ static void gemm_launch(const GemmDesc &g, hipStream_t s) {
       h.C = g.ws; h.c_i = g.N; h.c_j = 1; h.c_b1 = (long)g.M * g.N;
       h.alpha = 1.0; h.beta = 0.0; h.kmax = g.K;
       dim3 grid((h.N + TILE - 1) / TILE, (h.M + TILE - 1) / TILE, S * g_bc.n);
-      hipLaunchKernelGGL(k_gemm<TILE>, grid, dim3(256), 0, s, h);
+      if constexpr (F32)
+        hipLaunchKernelGGL(k_gemm_f32p<TILE>, grid, dim3(256), 0, s, h);
+      else
+        hipLaunchKernelGGL(k_gemm<TILE>, grid, dim3(256), 0, s, h);
       SPG_CHECK_LAUNCH();
       const long mn = (long)g.M * g.N;
       hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256), g_bc.n), dim3(256), 0,
@@ -1311,7 +1340,10 @@ static void gemm_launch(const GemmDesc &g, hipStream_t s) {
     }
   }
   dim3 grid((g.N + TILE - 1) / TILE, (g.M + TILE - 1) / TILE, g.nb1 * g.nb2 * g_bc.n);
-  hipLaunchKernelGGL(k_gemm<TILE>, grid, dim3(256), 0, s, g);
+  if constexpr (F32)
+    hipLaunchKernelGGL(k_gemm_f32p<TILE>, grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL(k_gemm<TILE>, grid, dim3(256), 0, s, g);
   SPG_CHECK_LAUNCH();
 }
 
@@ -1334,10 +1366,14 @@ void gemm_f64(const GemmDesc &g, hipStream_t s) {
     set_error("gemm_f64: batch too large for one launch");
     throw Fail{SPG_ERR_UNSUPPORTED};
   }
-  if ((g.tile ? g.tile : g_tune.gemm_tile) == 32)
-    gemm_launch<32>(h, s);
-  else
-    gemm_launch<64>(h, s);
+  const bool t32 = (g.tile ? g.tile : g_tune.gemm_tile) == 32;
+  if (g_tune.gemm_f32) {
+    if (t32) gemm_launch<32, true>(h, s);
+    else gemm_launch<64, true>(h, s);
+  } else {
+    if (t32) gemm_launch<32, false>(h, s);
+    else gemm_launch<64, false>(h, s);
+  }
 }
 
 // Householder QR flops: 2mn^2 - 2n^3/3 for R, the same again to form Q.

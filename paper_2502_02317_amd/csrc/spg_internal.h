@@ -111,6 +111,7 @@ struct Tuning {
   int splitk = 1;       // deterministic split-K for skinny long-K products
   int mpo_cols = 1;     // column forms of the MPO d-index contractions (d in {8, 16, 24, 32})
   int qform_split = 1;  // Q of one-panel register QRs by k_qform (a compute unit per column)
+  int gemm_f32 = 0;     // FP64 GEMMs with FP32 products and accumulation (reduced precision)
 };
 extern thread_local Tuning g_tune;
 

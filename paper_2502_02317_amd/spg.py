@@ -71,7 +71,7 @@ EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals
            "spg_proposal_loss_grad", "spg_proposal_adam", "spg_search_stats",
            "spg_batch_create", "spg_batch_free", "spg_batch_run", "spg_batch_result",
            "spg_batch_set_tuning", "spg_batch_autotune", "spg_set_tuning", "spg_set_kernel_forms",
-           "spg_batch_info", "spg_batch_plan", "spg_batch_tuning",
+           "spg_set_gemm_precision", "spg_batch_info", "spg_batch_plan", "spg_batch_tuning",
            "spg_droplets", "spg_ising_to_potts"]
 KERNEL_CLASSES = ["gemm_f64", "qr_f64", "qform_f64", "jacobi_svd_f64", "normalize_box", "right_env",
                   "marginals", "select_topm", "beam_update", "final_sort", "propose",
@@ -132,6 +132,7 @@ def load() -> C.CDLL:
     lib.spg_batch_tuning.argtypes = [vp, i32, i32p, i32p, i32p]
     lib.spg_set_tuning.argtypes = [i32]
     lib.spg_set_kernel_forms.argtypes = [i32, i32]
+    lib.spg_set_gemm_precision.argtypes = [i32]
     lib.spg_batch_plan.argtypes = [vp, vp, i32, i32, vp, i32p, vp, i32, vp, vp]
     for name in ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals_noalloc",
                  "spg_branch_and_bound", "spg_topm",
@@ -140,7 +141,8 @@ def load() -> C.CDLL:
                  "spg_proposal_features", "spg_proposal_forward", "spg_proposal_loss_grad",
                  "spg_proposal_adam", "spg_search_stats", "spg_batch_create", "spg_batch_run",
                  "spg_batch_result", "spg_batch_set_tuning", "spg_batch_autotune",
-                 "spg_set_tuning", "spg_set_kernel_forms", "spg_batch_info", "spg_batch_plan",
+                 "spg_set_tuning", "spg_set_kernel_forms", "spg_set_gemm_precision",
+                 "spg_batch_info", "spg_batch_plan",
                  "spg_batch_tuning",
                  "spg_droplets",
                  "spg_ising_to_potts"]:
@@ -508,6 +510,13 @@ def search_stats(env: Env):
 def set_tuning(gemm_tile: int) -> None:
     """Default GEMM tile (32 or 64) of calls outside batches on this thread."""
     _check(load().spg_set_tuning(int(gemm_tile)))
+
+
+def set_gemm_precision(fp32_products: bool) -> None:
+    """Reduced-precision FP64 GEMMs on this thread: FP32 operands and FP32
+    accumulation on the matrix cores, FP64 results (QR, SVD and the MPO
+    contractions stay FP64).  False (default) restores FP64 products."""
+    _check(load().spg_set_gemm_precision(1 if fp32_products else 0))
 
 
 def set_kernel_forms(mpo_columns: bool = True, q_split: bool = True) -> None:
