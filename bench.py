@@ -69,6 +69,12 @@ def kernel_source_sha(name):
             continue
         end = src.find("\n}\n", m.start())
         body = src[m.start(): end + 3]
+        # with the device functions of the same file that the kernel calls
+        # (one level: a kernel that is a thin wrapper of a templated body)
+        for callee in sorted(set(re.findall(r"\b(\w+)\s*(?:<[^<>;{}]*>)?\s*\(", body))):
+            d = re.search(r"__device__[^{;]*?\b" + re.escape(callee) + r"\(", src)
+            if d and callee != name:
+                body += src[d.start(): src.find("\n}\n", d.start()) + 3]
         return "paper_2502_02317_amd/csrc/" + f, hashlib.sha256(body.encode()).hexdigest()
     return None, None
 
