@@ -125,3 +125,28 @@ def test_plan_rejects_bad_shapes():
         spg.batch_plan([(4, 4, 300, 1)], 16, M)          # d above 256
     with pytest.raises(spg.SpgError):
         spg.batch_plan([(4, 4, 16, 2)], 16, M)           # kings must be 0 or 1
+
+
+def test_plan_without_classes_or_with_reduced_precision():
+    shapes = [(6, 6, D, 1)] * 4 + [(7, 7, D, 1)] * 2
+    # classes off: every instance its own unit
+    unit_of, units, _ = spg.batch_plan(shapes, 16, M, classes=False)
+    assert unit_of.tolist() == list(range(6)) and all(m == 1 for m, _ in units)
+    # FP32 instances never join a class; the FP64 ones of equal shape do
+    precs = ["fp64", "fp32", "fp64", "fp64", "fp32", "fp64"]
+    unit_of, units, _ = spg.batch_plan(shapes, 16, M, precision=precs)
+    assert unit_of[0] == unit_of[2] == unit_of[3]
+    assert len({unit_of[1], unit_of[4], unit_of[0], unit_of[5]}) == 4
+    assert [m for m, _ in units] == [3, 1, 1, 1]
+    # different chi or beam: different classes
+    unit_of, _, _ = spg.batch_plan([(6, 6, D, 1)] * 3, [16, 32, 16], [M, M, M // 2])
+    assert len(set(unit_of.tolist())) == 3
+
+
+def test_kernel_switches_reject_other_values():
+    lib = spg.load()
+    assert lib.spg_set_kernel_forms(2, 1) != 0
+    assert lib.spg_set_kernel_forms(1, -1) != 0
+    assert lib.spg_set_gemm_precision(3) != 0
+    assert lib.spg_set_kernel_forms(1, 1) == 0           # the defaults
+    assert lib.spg_set_gemm_precision(0) == 0
