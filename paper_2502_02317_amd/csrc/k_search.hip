@@ -546,7 +546,7 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
     }
   };
   // the m survivors (a prefix of the order, m >= Me) sit unordered in
-  // skey/sid: writes the first Me in order.  Bins uniform in the gap
+  // skey/sid (written before a barrier): writes the first Me in order.  Bins uniform in the gap
   // vmax - v over [0, largest gap] (monotone in the score), prefix sums for
   // the segments, then each survivor's rank within its bin.
   auto order_out = [&](int m, uint64_t kbest) {
@@ -646,13 +646,17 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
     uint64_t kr[kSelRegKeys];
     uint64_t lo = ~0ull, hi = 0;
     {
-      // all loads issued before the first use (indices clamped into range)
+      // all loads issued before the first use (indices clamped into range);
+      // the gap histogram is cleared while they are in flight (the barrier
+      // after the min/max orders the clearing before its counts)
       double raw[kSelRegKeys];
 #pragma unroll
       for (int q = 0; q < kSelRegKeys; ++q) {
         const int i = tid + 1024 * q;
         raw[q] = cand[(i < n) ? i : n - 1];
       }
+      if (Me < n)
+        for (int b = tid; b < kGapBins; b += 1024) gh[b] = 0u;
 #pragma unroll
       for (int q = 0; q < kSelRegKeys; ++q) kr[q] = (tid + 1024 * q < n) ? desc_key(raw[q]) : 0ull;
     }
@@ -684,8 +688,6 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
         // ---- gap histogram: usually settles the selection in one pass (the
         // bins stay in registers; -inf, often the most crowded bin, is
         // counted once per wavefront)
-        for (int b = tid; b < kGapBins; b += 1024) gh[b] = 0u;
-        __syncthreads();
         const double vmax = key_value(lo);
         const int binf = gap_bin(vmax, -INFINITY);
         int kb[kSelRegKeys];
@@ -719,6 +721,7 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
               ++pos;
             }
           }
+          __syncthreads();                     // every survivor in skey/sid
           order_out(m, lo);
           return;
         }
