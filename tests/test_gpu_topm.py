@@ -3,8 +3,10 @@
 The order is score descending, then index ascending, with NaN ranked as -inf
 and the float total order (so -0.0 ranks below +0.0).  Sizes cover the
 one-workgroup register path (n <= 16384), the multi-workgroup path beyond it,
-survivor sets above the LDS sort's 8192 slots, and the degenerate cases where
-one histogram bin holds most keys (ties, a single value, -inf)."""
+survivor sets above the LDS sort's 8192 slots (down to M = n - 1, where every
+key but one survives and the multi-workgroup front end hands on all of them),
+and the degenerate cases where one histogram bin holds most keys (ties, a
+single value, -inf)."""
 import numpy as np
 import pytest
 import torch
@@ -64,7 +66,8 @@ def _scores(kind: str, n: int, seed: int) -> np.ndarray:
 @pytest.mark.parametrize("kind", ["normal", "logp", "ties", "constant", "special", "tiny_gaps"])
 @pytest.mark.parametrize("n,M", [(1, 1), (5, 3), (1000, 1000), (1000, 1007), (16384, 1024),
                                  (16384, 1), (16385, 1024), (65536, 4096), (98304, 4096),
-                                 (98304, 9000), (200000, 512)])
+                                 (98304, 9000), (200000, 512), (5000, 4999), (16384, 16383),
+                                 (16385, 16384), (40000, 39999)])
 def test_topm_matches_reference_order(kind, n, M):
     s = _scores(kind, n, seed=n + M)
     sel, sc = _run(s, M)
