@@ -427,6 +427,53 @@ def kings12_leg(spg, torch, stream):
     return out
 
 
+def kings16_leg(spg, torch, stream):
+    """The search at the full-stack lattice shape: 16x16 king's, d = 256
+    (8-spin clusters), beta = 4, chi = 64, beam 10000, on a seeded synthetic
+    environment with the workload's bond dimensions (its boundary MPS is not
+    built here); FP64 and FP32-input searches, search-only times, device memory
+    the library holds for each."""
+    import numpy as np
+    from workloads import config_instance, synthetic_env
+    inst = config_instance("kings16x16_d256", 0)
+    chi, M = 64, 10000
+    R, C, d = inst.rows, inst.cols, inst.d
+    N = R * C
+    ev = evals_per_step(R, C, d, M)
+    dev = torch.device("cuda:0")
+    st = torch.zeros((M, N), dtype=torch.int32, device=dev)
+    en = torch.zeros(M, dtype=torch.float64, device=dev)
+    lp = torch.zeros(M, dtype=torch.float64, device=dev)
+    peps = spg.build_peps(inst, stream)
+    A = synthetic_env(R, C, d, chi, 11)
+    T, dims = spg.pack_oracle_mps(A, chi, d)
+    del A
+    out = {"workload": "kings16x16_d256 beta=4 chi=64 M=10000 (seed 0), synthetic environment "
+                       "(seed 11)", "evals_per_search": ev}
+    for prec in ("fp64", "fp32"):
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        e = spg.env_import(peps, chi, dims, T, np.zeros(R), precision=prec, stream=stream)
+        spg.branch_and_bound(e, M, st, en, lp, stream=stream)      # warm (allocates)
+        torch.cuda.synchronize()
+        held = free0 - torch.cuda.mem_get_info()[0]
+        times = []
+        for _ in range(3):
+            a = time.perf_counter()
+            n = spg.branch_and_bound(e, M, st, en, lp, stream=stream)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - a) * 1e3)
+        ms = float(np.median(times))
+        out[f"search_ms_{prec}"] = ms
+        out[f"search_evals_per_s_{prec}"] = ev / (ms * 1e-3)
+        out[f"n_states_{prec}"] = n
+        out[f"best_energy_{prec}"] = float(en[0]) if n > 0 else None
+        out[f"device_gib_{prec}"] = held / 2 ** 30
+        del e
+    out["search_speedup_fp32_vs_fp64"] = out["search_ms_fp64"] / out["search_ms_fp32"]
+    return out
+
+
 def gemm_fp32_leg(spg, torch, stream):
     """The precision form of the boundary MPS's contractions: every GEMM of the
     contraction with FP32 operands and FP32 accumulation on the matrix cores
@@ -527,7 +574,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (a known-size kernel for "
                          "scaling hardware byte counters)")
-    ap.add_argument("--leg", choices=["kings12x12_d24"], default=None,
+    ap.add_argument("--leg", choices=["kings12x12_d24", "kings16x16_d256"], default=None,
                     help="run only this workload leg and print its record (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -544,9 +591,10 @@ def main():
         if args.verbose:
             print(f"bench: {msg}", file=sys.stderr, flush=True)
 
-    if args.leg == "kings12x12_d24":
+    if args.leg is not None:
         stream = torch.cuda.current_stream()
-        print(json.dumps({"leg": args.leg, args.leg: kings12_leg(spg, torch, stream)}), flush=True)
+        leg = kings12_leg if args.leg == "kings12x12_d24" else kings16_leg
+        print(json.dumps({"leg": args.leg, args.leg: leg(spg, torch, stream)}), flush=True)
         return
 
     wl = WORKLOAD

@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "PottsInstance", "SpinInstance", "spin_instance", "potts_from_spins",
-    "random_potts", "config_instance", "CONFIGS", "ConfigSpec",
+    "random_potts", "config_instance", "CONFIGS", "ConfigSpec", "synthetic_env",
 ]
 
 
@@ -235,3 +235,14 @@ CONFIGS = {
 
 def config_instance(name: str, seed: int) -> PottsInstance:
     return CONFIGS[name].make(seed)
+
+
+def synthetic_env(rows: int, cols: int, d: int, chi: int, seed: int):
+    """A seeded stand-in for a boundary-MPS environment: for each row, ``cols``
+    tensors [D_c][d][D_{c+1}] with entries uniform in [0, 1) and the bond
+    dimensions a contraction at bond cap ``chi`` has, D_c = min(chi, d**c,
+    d**(cols-c)).  Positive entries make every conditional a sum of positive
+    terms.  Drawn row by row, column by column, from PCG64(seed)."""
+    rng = np.random.default_rng(seed)
+    dims = [min(chi, d ** c, d ** (cols - c)) for c in range(cols + 1)]
+    return [[rng.random((dims[c], d, dims[c + 1])) for c in range(cols)] for _ in range(rows)]
