@@ -510,10 +510,35 @@ void bottom_row(int C, int d, int chi, const double *w, const double *H, double 
   SPG_CHECK_LAUNCH();
 }
 
-// The column forms exist for d in {8, 16, 24, 32}; other d (and calls with
-// the column forms switched off) take the per-output forms.
+// The column forms exist for d in {8, 16, 24, 32}; other d up to 32 (and
+// calls with the column forms switched off) take the per-output forms.  Above
+// d = 32 the d-index contractions are batched GEMMs on the matrix cores (K =
+// d, 2d flops per output: above the FP64 ridge from d of about 40), with the
+// horizontal table H applied in the producing GEMM's epilogue where its
+// factor depends on both indices.
+inline bool gemm_form(int d) { return d > 32; }
 inline bool col_form(int d) {
   return g_tune.mpo_cols && (d == 8 || d == 16 || d == 24 || d == 32);
+}
+
+// C[b1][b2](i, j) = sum_k A(i, k) B[b1][b2](k, j) for i < d, j < n, k < d, with
+// the d x d coefficient table A shared by all batches (element (i, k) at
+// A[i * ai + k * ak]), every batch's B and C rows chi apart and their
+// columns adjacent; smode 3 / 4 scale the outputs by the table H (see GemmDesc).
+static void mpo_gemm(int d, int chi, int nb1, int n, const double *A, long ai, long ak,
+                     const double *B, long bk, long bb1, long bb2, double *C, long ci, long cb1,
+                     long cb2, int smode, const double *ones, const double *H, hipStream_t s) {
+  GemmDesc g{};
+  g.M = d; g.N = n; g.K = d; g.nb1 = nb1; g.nb2 = d;
+  g.A = A; g.a_i = ai; g.a_k = ak; g.a_b1 = 0; g.a_b2 = 0;
+  g.B = B; g.b_k = bk; g.b_j = 1; g.b_b1 = bb1; g.b_b2 = bb2;
+  g.C = C; g.c_i = ci; g.c_j = 1; g.c_b1 = cb1; g.c_b2 = cb2;
+  g.alpha = 1.0; g.beta = 0.0;
+  if (smode) {
+    g.sw = ones; g.sV = H; g.sd = d; g.smode = smode;
+  }
+  (void)chi;
+  gemm_f64(g, s);
 }
 
 #define SPG_LAUNCH_COL(KN, nthr, ...)                                            \
@@ -530,6 +555,15 @@ inline bool col_form(int d) {
 void left_part(int d, int chi, int pl, int ql, int qr, const double *EL, const double *psi,
                const RowFactors &f, double *T1, double *P, hipStream_t s) {
   const long tot = (long)pl * d * d * ql;
+  double *T2 = T1 + (long)chi * d * d * chi;
+  const long dc = (long)d * chi, ddc = (long)d * d * chi;
+  if (gemm_form(d)) {
+    // T1'[p][a][x][q] = H(a, x) sum_e Al[x][e] EL[p][a][e][q]   (batch (p, a); rows x)
+    mpo_gemm(d, chi, pl, ql, f.Al, d, 1, EL, chi, ddc, dc, T1, chi, ddc, dc, 3, f.ones, f.Hl, s);
+    // T2[p][x][y][q] = sum_a Dl[a][y] T1'[p][a][x][q]   (batch (p, x); rows y)
+    mpo_gemm(d, chi, pl, ql, f.Dl, 1, d, T1, dc, ddc, chi, T2, chi, ddc, dc, 0, nullptr, nullptr,
+             s);
+  } else {
   SPG_BC(EL);
   SPG_BC(f.Al);
   SPG_BC(T1);
@@ -540,7 +574,6 @@ void left_part(int d, int chi, int pl, int ql, int qr, const double *EL, const d
   SPG_CHECK_LAUNCH();
   // T2 written into P (the GEMM below reads T2 and writes P in place would alias),
   // so T2 goes to the second half of T1's buffer.
-  double *T2 = T1 + (long)chi * d * d * chi;
   SPG_BC(T1);
   SPG_BC(f.Hl);
   SPG_BC(f.Dl);
@@ -550,6 +583,7 @@ void left_part(int d, int chi, int pl, int ql, int qr, const double *EL, const d
   else
     hipLaunchKernelGGL(k_T2, dim3(nblk(tot, 256), g_bc.n), dim3(256), 0, s, d, chi, pl, ql, T1, f.Hl, f.Dl, T2, g_bc.ist);
   SPG_CHECK_LAUNCH();
+  }
   // P[p][x][y][Q] = sum_q T2[p][x][y][q] psi[q][y][Q]   (batch y; rows (p,x))
   GemmDesc g{};
   g.M = pl * d; g.N = qr; g.K = ql; g.nb1 = d; g.nb2 = 1;
@@ -597,6 +631,15 @@ void env_right(int d, int chi, int pl, int pr, int ql, int qr, const double *phi
   gemm_f64(h, s);
   const long tot = (long)pl * d * d * ql;
   double *G3 = G1;  // G1 no longer needed
+  if (gemm_form(d)) {
+    const long dc = (long)d * chi, ddc = (long)d * d * chi;
+    // G3'[p][x][a][q] = H(a, x) sum_y Dl[a][y] G2[p][x][y][q]   (batch (p, x); rows a)
+    mpo_gemm(d, chi, pl, ql, f.Dl, d, 1, G2, chi, ddc, dc, G3, chi, ddc, dc, 4, f.ones, f.Hl, s);
+    // ER[p][a][e][q] = sum_x Al[x][e] G3'[p][x][a][q]   (batch (p, a); rows e)
+    mpo_gemm(d, chi, pl, ql, f.Al, 1, d, G3, dc, ddc, chi, ERn, chi, ddc, dc, 0, nullptr, nullptr,
+             s);
+    return;
+  }
   SPG_BC(G2);
   SPG_BC(f.Dl);
   SPG_BC(G3);
@@ -633,6 +676,15 @@ void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, cons
   gemm_f64(g, s);
   const long totq = (long)qm * d * d * pr;
   const long totp = (long)pl * d * d * qm;
+  const long dc = (long)d * chi, ddc = (long)d * d * chi;
+  if (gemm_form(d)) {
+    // P2[p][x][z][Q] = sum_y A1[z][y] P[p][x][y][Q]   (batch (p, x); rows z)
+    mpo_gemm(d, chi, pl, qm, f1.Al, d, 1, P, chi, ddc, dc, P2, chi, ddc, dc, 0, nullptr, nullptr,
+             s);
+    // Q2[Q][x][z][P] = sum_v D1[x][v] Qr[Q][z][v][P]   (batch (Q, z); rows x)
+    mpo_gemm(d, chi, qm, pr, f1.Dl, d, 1, Qr, chi, ddc, dc, Q2, dc, ddc, chi, 0, nullptr, nullptr,
+             s);
+  } else {
   SPG_BC(P);
   SPG_BC(f1.Al);
   SPG_BC(P2);
@@ -649,6 +701,7 @@ void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, cons
   else
     hipLaunchKernelGGL(k_Q2, dim3(nblk(totq, 256), g_bc.n), dim3(256), 0, s, d, chi, qm, pr, Qr, f1.Dl, Q2, g_bc.ist);
   SPG_CHECK_LAUNCH();
+  }
   // B[p][x][z][P] = sum_Q P2[p][x][z][Q] Q2[Q][x][z][P]   (batch (x,z)), compact output
   GemmDesc h{};
   h.M = pl; h.N = pr; h.K = qm; h.nb1 = d; h.nb2 = d;

@@ -169,13 +169,18 @@ __device__ __forceinline__ void gemm_body(const GemmDesc &g) {
   }
   const double *sw = g.sw ? (const double *)((const char *)g.sw + io) : nullptr;
   const double *sV = g.sV ? (const double *)((const char *)g.sV + io) : nullptr;
-  const double fb = (g.smode == 2) ? sw[b1] * sV[b1 * g.sd + b2] : 1.0;
+  const int b1g = b1 + g.b1_base;               // the batch index over all launches
+  const double fb = (g.smode == 2) ? sw[b1g] * sV[b1g * g.sd + b2] : 1.0;
   auto put = [&](int gi, int gj, double a) {
     if (gi >= g.M || gj >= g.N) return;
     double f = fb;
     if (g.smode == 1) {
       const int x = gi % g.sd;
-      f = sw[x] * sV[x * g.sd + b1];
+      f = sw[x] * sV[x * g.sd + b1g];
+    } else if (g.smode == 3) {
+      f = sV[b2 * g.sd + gi % g.sd];
+    } else if (g.smode == 4) {
+      f = sV[(gi % g.sd) * g.sd + b2];
     }
     double *cp = C + gi * g.c_i + gj * g.c_j;
     double v = g.alpha * a;
@@ -1362,17 +1367,38 @@ void gemm_f64(const GemmDesc &g, hipStream_t s) {
   }
   GemmDesc h = g;
   h.ist = g_bc.ist;
-  if ((long)h.nb1 * h.nb2 * g_bc.n > 65535) {
+  const bool t32 = (g.tile ? g.tile : g_tune.gemm_tile) == 32;
+  auto launch = [&](const GemmDesc &k) {
+    if (g_tune.gemm_f32) {
+      if (t32) gemm_launch<32, true>(k, s);
+      else gemm_launch<64, true>(k, s);
+    } else {
+      if (t32) gemm_launch<32, false>(k, s);
+      else gemm_launch<64, false>(k, s);
+    }
+  };
+  const long per_b1 = (long)h.nb2 * g_bc.n;      // grid z entries per first batch index
+  if ((long)h.nb1 * per_b1 <= 65535) {
+    launch(h);
+    return;
+  }
+  // more batches than one launch's grid holds: launches over runs of the first
+  // batch index (each batch's tiles are computed as in one launch)
+  const long run = 65535 / per_b1;
+  if (run < 1 || g.kmax != 0) {
     set_error("gemm_f64: batch too large for one launch");
     throw Fail{SPG_ERR_UNSUPPORTED};
   }
-  const bool t32 = (g.tile ? g.tile : g_tune.gemm_tile) == 32;
-  if (g_tune.gemm_f32) {
-    if (t32) gemm_launch<32, true>(h, s);
-    else gemm_launch<64, true>(h, s);
-  } else {
-    if (t32) gemm_launch<32, false>(h, s);
-    else gemm_launch<64, false>(h, s);
+  for (long c0 = 0; c0 < g.nb1; c0 += run) {
+    GemmDesc k = h;
+    k.nb1 = (int)std::min<long>(run, g.nb1 - c0);
+    k.A = g.A + c0 * g.a_b1;
+    k.B = g.B + c0 * g.b_b1;
+    k.C = g.C + c0 * g.c_b1;
+    k.b1_base = (int)c0;
+    k.ws = nullptr;                               // no split-K: every batch as in one launch
+    k.ws_len = 0;
+    launch(k);
   }
 }
 
@@ -1476,12 +1502,13 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
     return;
   }
   if (n <= kQrRegCols) {
-    // one TSQR level on the register kernel: p blocks of at most 512 rows in
-    // one launch (a workgroup each), the QR of their stacked R factors, and
-    // Q = diag(Q_b) Q_s
+    // TSQR on the register kernel: p blocks of at most 512 rows in one launch
+    // (a workgroup each), the QR of their stacked R factors (the register
+    // kernel again, or TSQR of the p*n stacked rows when they exceed 512, with
+    // the rest of the workspace), and Q = diag(Q_b) Q_s
     const int p = (m + kQrRegRows - 1) / kQrRegRows;
     const int mb = (m + p - 1) / p;
-    if (p * n <= kQrRegRows && m - (p - 1) * mb >= n) {
+    if (m - (p - 1) * mb >= n) {
       double *Q1 = work;                          // m x n row-major
       double *S = Q1 + (long)m * n;               // p*n x n row-major (stacked R_b)
       double *Qs = S + (long)p * n * n;           // p*n x n row-major
@@ -1489,8 +1516,12 @@ void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr,
       // (each launch timed inside qr_reg_rows)
       qr_reg(m, n, mb, X, xr, xc, want_q ? Q1 : nullptr, (long)n, 1L, S, want_q, dim3(p, nI),
              ist, s);
-      qr_reg(p * n, n, p * n, S, (long)n, 1L, want_q ? Qs : nullptr, (long)n, 1L, R ? R : Rt,
-             want_q, dim3(1, nI), ist, s);
+      if (p * n <= kQrRegRows)
+        qr_reg(p * n, n, p * n, S, (long)n, 1L, want_q ? Qs : nullptr, (long)n, 1L, R ? R : Rt,
+               want_q, dim3(1, nI), ist, s);
+      else
+        qr_f64(p * n, n, S, (long)n, 1L, want_q ? Qs : nullptr, (long)n, 1L, R ? R : Rt,
+               Rt + (long)n * n, s);
       if (!want_q) return;
       const int full = m / mb, tail = m - full * mb;
       GemmDesc g{};

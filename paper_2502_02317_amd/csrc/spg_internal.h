@@ -97,10 +97,13 @@ struct GemmDesc {
   long ist = 0;           // internal: class-batched instance stride (bytes)
   // optional epilogue factor (the MPO site weights w(x) V(x, y)), d = sd:
   // smode 1: C(i, j) of batch b1 times w[i % d] V[(i % d) d + b1];
-  // smode 2: every C(i, j) of batch (b1, b2) times w[b1] V[b1 d + b2]
+  // smode 2: every C(i, j) of batch (b1, b2) times w[b1] V[b1 d + b2];
+  // smode 3: C(i, j) of batch (b1, b2) times V[b2 d + i % d];
+  // smode 4: C(i, j) of batch (b1, b2) times V[(i % d) d + b2] (w unused)
   const double *sw = nullptr, *sV = nullptr;
   int sd = 0, smode = 0;
   int tile = 0;           // output tile 32 or 64 for this product (0: the tuning's)
+  int b1_base = 0;        // internal: first batch index b1 of a launch (the epilogue's)
 };
 void gemm_f64(const GemmDesc &g, hipStream_t s);
 
@@ -118,8 +121,10 @@ extern thread_local Tuning g_tune;
 // Householder QR of an m x n matrix (m >= n, n <= kMaxSketch), element (i,j) at
 // X[i*xr + j*xc].  Writes Q (m x n, orthonormal columns) to Q[i*qr + j*qc]
 // unless Q == nullptr and, if R != nullptr, the n x n upper-triangular factor
-// to R[i*n + j] (row-major).  Panels that fit in LDS are factored there (one
-// level of TSQR above that size); `work` holds qr_work_doubles(m, n) doubles.
+// to R[i*n + j] (row-major).  Panels of at most 80 columns are factored in
+// registers, by TSQR over blocks of 512 rows beyond that (recursing on the
+// stacked R factors); wider ones in LDS (one level of TSQR beyond it) or in
+// global memory.  `work` holds qr_work_doubles(m, n) doubles.
 size_t qr_work_doubles(int m, int n);
 void qr_f64(int m, int n, const double *X, long xr, long xc, double *Q, long qr, long qc,
             double *R, double *work, hipStream_t s);
