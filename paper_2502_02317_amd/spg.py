@@ -211,8 +211,11 @@ def build_peps(inst, stream=None) -> Peps:
 
 
 def boundary_mps(peps: Peps, chi: int, num_sweeps: int = 1, precision: str = "fp64",
-                 oversample: int = 16, power_iters: int = 1, stream=None, want_logZ=True):
-    """spg_boundary_mps; returns (Env, log Z or None)."""
+                 oversample: int = 16, power_iters: int = 1, stream=None, want_logZ=True,
+                 nonfinite_ok=False):
+    """spg_boundary_mps; returns (Env, log Z or None).  With nonfinite_ok a
+    non-finite log Z (SPG_ERR_NONFINITE, the env is still returned) comes back
+    as the value instead of raising."""
     lib = load()
     prm = MpsParams(chi, num_sweeps, PRECISION[precision], oversample, power_iters)
     h = C.c_void_p()
@@ -220,7 +223,8 @@ def boundary_mps(peps: Peps, chi: int, num_sweeps: int = 1, precision: str = "fp
     rc = lib.spg_boundary_mps(peps.handle, C.byref(prm), _stream(stream), C.byref(h),
                               C.byref(lz) if want_logZ else None)
     env = Env(h, peps) if h.value else None
-    _check(rc)
+    if not (nonfinite_ok and want_logZ and rc == -4 and env is not None):
+        _check(rc)
     return env, (lz.value if want_logZ else None)
 
 
