@@ -446,16 +446,28 @@ def kings16_leg(spg, torch, stream):
     lp = torch.zeros(M, dtype=torch.float64, device=dev)
     peps = spg.build_peps(inst, stream)
     torch.cuda.synchronize()
+    spg.profile_reset()
+    spg.profile_enable(True)                  # per-launch events on the MPO GEMMs' class
     a = time.perf_counter()
     env, lz = spg.boundary_mps(peps, chi, stream=stream, nonfinite_ok=True)
     torch.cuda.synchronize()
     bmps_s = time.perf_counter() - a
+    spg.profile_enable(False)
+    g_n, g_ms, g_work = spg.profile_query("mpo_gemm_f64")
+    spg.profile_reset()
     T, _ = spg.env_export(env)
     dims = spg.env_info(env).bond_dims
     sums = row_sums(spg.unpack_mps(T, dims))
     out = {"workload": "kings16x16_d256 beta=4 chi=64 M=10000 (seed 0), one instance",
            "evals_per_search": ev, "boundary_mps_s": bmps_s, "logZ": finite_or_none(lz),
-           "rows_with_nonpositive_sum": [r for r, v in enumerate(sums) if not v > 0]}
+           "rows_with_nonpositive_sum": [r for r, v in enumerate(sums) if not v > 0],
+           # the MPO d-index contractions as FP64 GEMMs on the matrix cores: flops by
+           # formula (2 M N K per batch) over the summed launch durations
+           "mpo_gemm_matrix_cores": {
+               "instruction": "v_mfma_f64_16x16x4f64", "launches": g_n, "ms": g_ms,
+               "achieved": g_work / (g_ms * 1e-3) / 1e12 if g_ms > 0 else None,
+               "peak": PEAK["fp64"], "unit": "TFLOP/s",
+               "frac": g_work / (g_ms * 1e-3) / 1e12 / PEAK["fp64"] if g_ms > 0 else None}}
     for prec in ("fp64", "fp32"):
         e = env if prec == "fp64" else spg.env_import(peps, chi, dims, T, np.zeros(R),
                                                       precision=prec, stream=stream)

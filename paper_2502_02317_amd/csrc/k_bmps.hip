@@ -538,6 +538,7 @@ static void mpo_gemm(int d, int chi, int nb1, int n, const double *A, long ai, l
     g.sw = ones; g.sV = H; g.sd = d; g.smode = smode;
   }
   if (d >= 64) g.tile = 64;           // d x n outputs per batch: 64 x 64 tiles fill them
+  g.cls = "mpo_gemm_f64";
   (void)chi;
   gemm_f64(g, s);
 }

@@ -1353,7 +1353,7 @@ static void gemm_launch(const GemmDesc &g, hipStream_t s) {
 }
 
 void gemm_f64(const GemmDesc &g, hipStream_t s) {
-  KTimer kt_("gemm_f64", s, 2.0 * g.M * g.N * g.K * g.nb1 * g.nb2);
+  KTimer kt_(g.cls ? g.cls : "gemm_f64", s, 2.0 * g.M * g.N * g.K * g.nb1 * g.nb2);
   if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
   SPG_BC(g.A);
   SPG_BC(g.B);

@@ -104,6 +104,7 @@ struct GemmDesc {
   int sd = 0, smode = 0;
   int tile = 0;           // output tile 32 or 64 for this product (0: the tuning's)
   int b1_base = 0;        // internal: first batch index b1 of a launch (the epilogue's)
+  const char *cls = nullptr;   // kernel class of the launch's timer (null: gemm_f64)
 };
 void gemm_f64(const GemmDesc &g, hipStream_t s);
 

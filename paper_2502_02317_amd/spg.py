@@ -75,7 +75,8 @@ EXPORTS = ["spg_build_peps", "spg_boundary_mps", "spg_marginals", "spg_marginals
            "spg_droplets", "spg_ising_to_potts"]
 KERNEL_CLASSES = ["gemm_f64", "qr_f64", "qform_f64", "jacobi_svd_f64", "normalize_box", "right_env",
                   "marginals", "select_topm", "beam_update", "final_sort", "propose",
-                  "guided_eval", "mlp_grad", "merge_branches", "droplets", "u_mfma"]
+                  "guided_eval", "mlp_grad", "merge_branches", "droplets", "u_mfma",
+                  "mpo_gemm_f64"]
 
 _lib = None
 
