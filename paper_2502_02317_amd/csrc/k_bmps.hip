@@ -521,6 +521,13 @@ inline bool col_form(int d) {
   return g_tune.mpo_cols && (d == 8 || d == 16 || d == 24 || d == 32);
 }
 
+// Above d = 32 the products of the contraction are large (K and the batch
+// counts grow with d): 64 x 64 tiles from d = 64 (the tile does not change
+// any output's order of terms).
+inline void large_d_tile(GemmDesc &g, int d) {
+  if (d >= 64) g.tile = 64;
+}
+
 // C[b1][b2](i, j) = sum_k A(i, k) B[b1][b2](k, j) for i < d, j < n, k < d, with
 // the d x d coefficient table A shared by all batches (element (i, k) at
 // A[i * ai + k * ak]), every batch's B and C rows chi apart and their
@@ -537,7 +544,7 @@ static void mpo_gemm(int d, int chi, int nb1, int n, const double *A, long ai, l
   if (smode) {
     g.sw = ones; g.sV = H; g.sd = d; g.smode = smode;
   }
-  if (d >= 64) g.tile = 64;           // d x n outputs per batch: 64 x 64 tiles fill them
+  large_d_tile(g, d);
   g.cls = "mpo_gemm_f64";
   (void)chi;
   gemm_f64(g, s);
@@ -594,6 +601,7 @@ void left_part(int d, int chi, int pl, int ql, int qr, const double *EL, const d
   g.C = P; g.c_i = (long)d * chi; g.c_j = 1; g.c_b1 = chi; g.c_b2 = 0;
   g.alpha = 1.0; g.beta = 0.0;
   g.sw = f.w; g.sV = f.V; g.sd = d; g.smode = 1;        // P[p][x][y][Q] *= w(x) V(x, y)
+  large_d_tile(g, d);
   gemm_f64(g, s);
 }
 
@@ -607,6 +615,7 @@ void env_left(int d, int chi, int pl, int pr, int qr, const double *phi, const d
   g.C = ELn; g.c_i = (long)d * d * chi; g.c_j = 1; g.c_b1 = (long)d * chi; g.c_b2 = 0;
   g.alpha = 1.0; g.beta = 0.0;
   (void)qr;
+  large_d_tile(g, d);
   gemm_f64(g, s);
 }
 
@@ -620,6 +629,7 @@ void env_right(int d, int chi, int pl, int pr, int ql, int qr, const double *phi
   g.B = ER; g.b_k = (long)d * d * chi; g.b_j = 1; g.b_b1 = (long)d * chi; g.b_b2 = 0;
   g.C = G1; g.c_i = (long)d * d * chi; g.c_j = 1; g.c_b1 = (long)d * chi; g.c_b2 = 0;
   g.alpha = 1.0; g.beta = 0.0;
+  large_d_tile(g, d);
   gemm_f64(g, s);
   (void)qr;
   // G2[p][x][y][q] = sum_Q G1[p][x][y][Q] psi[q][y][Q]   (batch y; rows (p,x))
@@ -630,6 +640,7 @@ void env_right(int d, int chi, int pl, int pr, int ql, int qr, const double *phi
   h.C = G2; h.c_i = (long)d * chi; h.c_j = 1; h.c_b1 = chi; h.c_b2 = 0;
   h.alpha = 1.0; h.beta = 0.0;
   h.sw = f.w; h.sV = f.V; h.sd = d; h.smode = 1;        // G2[p][x][y][q] *= w(x) V(x, y)
+  large_d_tile(h, d);
   gemm_f64(h, s);
   const long tot = (long)pl * d * d * ql;
   double *G3 = G1;  // G1 no longer needed
@@ -675,6 +686,7 @@ void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, cons
   g.C = Qr; g.c_i = (long)d * d * chi; g.c_j = 1; g.c_b1 = (long)d * chi; g.c_b2 = chi;
   g.alpha = 1.0; g.beta = 0.0;
   g.sw = f1.w; g.sV = f1.V; g.sd = d; g.smode = 2;      // Qr[q][x][y][P] *= w1(x) V1(x, y)
+  large_d_tile(g, d);
   gemm_f64(g, s);
   const long totq = (long)qm * d * d * pr;
   const long totp = (long)pl * d * d * qm;
@@ -712,6 +724,7 @@ void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, cons
   h.C = B; h.c_i = (long)d * d * pr; h.c_j = 1; h.c_b1 = (long)d * pr; h.c_b2 = pr;
   h.alpha = 1.0; h.beta = 0.0;
   h.sw = f1.ones; h.sV = f1.Hl; h.sd = d; h.smode = 2;  // B[p][x][z][P] *= 1 * H1(x, z)
+  large_d_tile(h, d);
   gemm_f64(h, s);
 }
 
