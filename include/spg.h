@@ -297,9 +297,10 @@ int spg_set_tuning(int32_t gemm_tile);
  * afterwards keep the setting.  mpo_columns, the MPO's d-index contractions:
  * 1 (default) for d in {8, 16, 24, 32} one thread per source column computes
  * the d outputs that share it, each source entry read once; 0 one thread per
- * output (other d always take it).  q_split, the orthonormal factor Q of the
- * truncation's QR factorisations of one panel (at most 512 rows, 32 to 80
- * columns): 1 (default) the panel kernel stores its reflectors and a second
+ * output (other d up to 32 always take it; above d = 32 these contractions
+ * are batched GEMMs on the matrix cores whatever the setting).  q_split, the
+ * orthonormal factor Q of the truncation's QR factorisations of one panel (at
+ * most 512 rows, 32 to 80 columns): 1 (default) the panel kernel stores its reflectors and a second
  * kernel forms Q with one compute unit per column; 0 the panel kernel forms Q
  * itself.  SPG_ERR_INVALID for values other than 0 and 1. */
 int spg_set_kernel_forms(int32_t mpo_columns, int32_t q_split);

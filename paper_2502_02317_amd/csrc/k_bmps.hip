@@ -532,7 +532,7 @@ inline void large_d_tile(GemmDesc &g, int d) {
 // the d x d coefficient table A shared by all batches (element (i, k) at
 // A[i * ai + k * ak]), every batch's B and C rows chi apart and their
 // columns adjacent; smode 3 / 4 scale the outputs by the table H (see GemmDesc).
-static void mpo_gemm(int d, int chi, int nb1, int n, const double *A, long ai, long ak,
+static void mpo_gemm(int d, int nb1, int n, const double *A, long ai, long ak,
                      const double *B, long bk, long bb1, long bb2, double *C, long ci, long cb1,
                      long cb2, int smode, const double *ones, const double *H, hipStream_t s) {
   GemmDesc g{};
@@ -546,7 +546,6 @@ static void mpo_gemm(int d, int chi, int nb1, int n, const double *A, long ai, l
   }
   large_d_tile(g, d);
   g.cls = "mpo_gemm_f64";
-  (void)chi;
   gemm_f64(g, s);
 }
 
@@ -568,9 +567,9 @@ void left_part(int d, int chi, int pl, int ql, int qr, const double *EL, const d
   const long dc = (long)d * chi, ddc = (long)d * d * chi;
   if (gemm_form(d)) {
     // T1'[p][a][x][q] = H(a, x) sum_e Al[x][e] EL[p][a][e][q]   (batch (p, a); rows x)
-    mpo_gemm(d, chi, pl, ql, f.Al, d, 1, EL, chi, ddc, dc, T1, chi, ddc, dc, 3, f.ones, f.Hl, s);
+    mpo_gemm(d, pl, ql, f.Al, d, 1, EL, chi, ddc, dc, T1, chi, ddc, dc, 3, f.ones, f.Hl, s);
     // T2[p][x][y][q] = sum_a Dl[a][y] T1'[p][a][x][q]   (batch (p, x); rows y)
-    mpo_gemm(d, chi, pl, ql, f.Dl, 1, d, T1, dc, ddc, chi, T2, chi, ddc, dc, 0, nullptr, nullptr,
+    mpo_gemm(d, pl, ql, f.Dl, 1, d, T1, dc, ddc, chi, T2, chi, ddc, dc, 0, nullptr, nullptr,
              s);
   } else {
   SPG_BC(EL);
@@ -647,9 +646,9 @@ void env_right(int d, int chi, int pl, int pr, int ql, int qr, const double *phi
   if (gemm_form(d)) {
     const long dc = (long)d * chi, ddc = (long)d * d * chi;
     // G3'[p][x][a][q] = H(a, x) sum_y Dl[a][y] G2[p][x][y][q]   (batch (p, x); rows a)
-    mpo_gemm(d, chi, pl, ql, f.Dl, d, 1, G2, chi, ddc, dc, G3, chi, ddc, dc, 4, f.ones, f.Hl, s);
+    mpo_gemm(d, pl, ql, f.Dl, d, 1, G2, chi, ddc, dc, G3, chi, ddc, dc, 4, f.ones, f.Hl, s);
     // ER[p][a][e][q] = sum_x Al[x][e] G3'[p][x][a][q]   (batch (p, a); rows e)
-    mpo_gemm(d, chi, pl, ql, f.Al, 1, d, G3, dc, ddc, chi, ERn, chi, ddc, dc, 0, nullptr, nullptr,
+    mpo_gemm(d, pl, ql, f.Al, 1, d, G3, dc, ddc, chi, ERn, chi, ddc, dc, 0, nullptr, nullptr,
              s);
     return;
   }
@@ -693,10 +692,10 @@ void two_site_block(int d, int chi, int pl, int ql, int qm, int qr, int pr, cons
   const long dc = (long)d * chi, ddc = (long)d * d * chi;
   if (gemm_form(d)) {
     // P2[p][x][z][Q] = sum_y A1[z][y] P[p][x][y][Q]   (batch (p, x); rows z)
-    mpo_gemm(d, chi, pl, qm, f1.Al, d, 1, P, chi, ddc, dc, P2, chi, ddc, dc, 0, nullptr, nullptr,
+    mpo_gemm(d, pl, qm, f1.Al, d, 1, P, chi, ddc, dc, P2, chi, ddc, dc, 0, nullptr, nullptr,
              s);
     // Q2[Q][x][z][P] = sum_v D1[x][v] Qr[Q][z][v][P]   (batch (Q, z); rows x)
-    mpo_gemm(d, chi, qm, pr, f1.Dl, d, 1, Qr, chi, ddc, dc, Q2, dc, ddc, chi, 0, nullptr, nullptr,
+    mpo_gemm(d, qm, pr, f1.Dl, d, 1, Qr, chi, ddc, dc, Q2, dc, ddc, chi, 0, nullptr, nullptr,
              s);
   } else {
   SPG_BC(P);
