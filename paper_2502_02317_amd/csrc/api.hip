@@ -180,6 +180,7 @@ static int tsvd_left(BmpsWork &w, const double *B, long br, long bc, int m, int 
     g.C = Cp; g.c_i = ci; g.c_j = cj;
     g.alpha = 1.0; g.beta = 0.0;
     g.ws = w.skws.as<double>(); g.ws_len = w.skws.bytes / sizeof(double);
+    if ((long)M * N >= (1L << 20)) g.tile = 64;   // the large products at many states per site
     gemm_f64(g, s);
   };
   double *qw = w.qrwork.as<double>();
