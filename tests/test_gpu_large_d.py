@@ -12,7 +12,8 @@ levels.
   chains: log Z is the sum over rows of log sum_x exp(-beta E_r(x)), with
   E_r the row's own local and horizontal energies (enumerated densely), and
   each row's boundary function is proportional to exp(-beta E_r) (the sum over
-  the rows below is a constant), so its overlap with the GPU's is 1.  At
+  the rows below is a constant), so its overlap with the GPU's is 1 (the closed
+  form is pinned against brute force in test_decoupled_rows.py).  At
   d = 72 and chi = 80 the panels have 72 * 72 = 5184 rows (11 blocks, then 792
   stacked rows: two TSQR levels).
 * d = 256 (8-spin clusters, 4x4 king's, beta = 4, chi = 64, panels of 16384
@@ -26,6 +27,7 @@ import pytest
 from workloads import random_potts, spin_instance, potts_from_spins
 from oracle.bmps import mps_full
 from oracle.energy import potts_energy
+from test_decoupled_rows import decoupled_log_z
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -43,21 +45,6 @@ def _rows(env):
     return spg.unpack_mps(T, spg.env_info(env).bond_dims), lam
 
 
-def _row_energy(inst, r):
-    """E_r(x_0, ..., x_{C-1}) of row r alone (local and horizontal terms), dense."""
-    C, d = inst.cols, inst.d
-    E = np.zeros((d,) * C)
-    for c in range(C):
-        shp = [1] * C
-        shp[c] = d
-        E = E + inst.local_E[r, c].reshape(shp)
-    for c in range(C - 1):
-        shp = [1] * C
-        shp[c] = shp[c + 1] = d
-        E = E + inst.pair_h[r, c].reshape(shp)
-    return E.ravel()
-
-
 @pytest.mark.parametrize("d,chi", [(40, 48), (72, 80)])
 def test_decoupled_rows_exact(d, chi):
     print(f"large d exact: d={d} chi={chi}", flush=True)
@@ -65,11 +52,7 @@ def test_decoupled_rows_exact(d, chi):
     inst.pair_v[:] = 0.0
     inst.pair_d[:] = 0.0
     inst.pair_a[:] = 0.0
-    lw = [-inst.beta * _row_energy(inst, r) for r in range(inst.rows)]
-    lz_exact = 0.0
-    for v in lw:
-        m = v.max()
-        lz_exact += m + np.log(np.exp(v - m).sum())
+    lz_exact, lw = decoupled_log_z(inst)
     env, lz = spg.boundary_mps(spg.build_peps(inst), chi)
     assert abs(lz - lz_exact) <= 1e-9 * abs(lz_exact), (lz, lz_exact)
     rows, _ = _rows(env)
