@@ -637,6 +637,101 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
       }
     }
   };
+  // the m survivors of a selection of more than kSelLdsSort (every one of
+  // them selected, m <= kSelRegKeys * 1024) sit unordered in kw/iw (written
+  // before a barrier): placed in order in kw/iw by the gap bins of order_out,
+  // each one's position its bin's start plus its rank among the bin's keys,
+  // and written to sel.  Returns false, having written nothing, when the gaps
+  // are not finite or a bin holds more than kSelBucket keys (the caller then
+  // sorts).
+  auto order_global = [&](int m) -> bool {
+    uint64_t kv[kSelRegKeys];
+    int32_t iv[kSelRegKeys];
+    uint64_t klo = ~0ull, khi = 0;
+#pragma unroll
+    for (int r = 0; r < kSelRegKeys; ++r) {
+      const int p = tid + 1024 * r;
+      kv[r] = (p < m) ? kw[p] : 0ull;
+      iv[r] = (p < m) ? iw[p] : 0;
+      if (p < m) {
+        klo = (kv[r] < klo) ? kv[r] : klo;
+        khi = (kv[r] > khi) ? kv[r] : khi;
+      }
+    }
+    klo = wave_min_u64(klo);
+    khi = wave_max_u64(khi);
+    if ((tid & 63) == 0) {
+      wmin[tid >> 6] = klo;
+      wmax[tid >> 6] = khi;
+    }
+    for (int b = tid; b < kGapBins; b += 1024) gh[b] = 0u;
+    if (tid == 0) sh_maxc = 0u;
+    __syncthreads();
+    klo = ~0ull;
+    khi = 0;
+    for (int w = 0; w < 16; ++w) {
+      klo = (wmin[w] < klo) ? wmin[w] : klo;
+      khi = (wmax[w] > khi) ? wmax[w] : khi;
+    }
+    const double vmax = key_value(klo);
+    const double gm = vmax - key_value(khi);
+    if (!(gm > 0.0 && gm <= 1.7e308)) return false;  // one score, or -inf among them
+    const double scale = (double)kGapBins / gm;
+    auto vbin = [&](uint64_t k) {
+      return (int)fmax(0.0, fmin((vmax - key_value(k)) * scale, (double)(kGapBins - 1)));
+    };
+#pragma unroll
+    for (int r = 0; r < kSelRegKeys; ++r)
+      if (tid + 1024 * r < m) atomicAdd(&gh[vbin(kv[r])], 1u);
+    __syncthreads();
+    unsigned hb[4];
+    int own = 0;
+    unsigned mc = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      hb[j] = gh[4 * tid + j];
+      own += (int)hb[j];
+      mc = (hb[j] > mc) ? hb[j] : mc;
+    }
+    mc = (unsigned)wave_max_u64(mc);
+    if ((tid & 63) == 0 && mc > 0u) atomicMax(&sh_maxc, mc);
+    int tot;
+    unsigned run = (unsigned)block_excl_scan_count(own, wsum, &tot);
+    if (sh_maxc > (unsigned)kSelBucket) return false;   // ties: sort instead
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      gs[4 * tid + j] = run;
+      gh[4 * tid + j] = run;
+      run += hb[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSelRegKeys; ++r) {
+      if (tid + 1024 * r < m) {
+        const unsigned pos = atomicAdd(&gh[vbin(kv[r])], 1u);
+        kw[pos] = kv[r];
+        iw[pos] = iv[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSelRegKeys; ++r) {
+      if (tid + 1024 * r < m) {
+        const uint64_t k = kv[r];
+        const int32_t id = iv[r];
+        const int b = vbin(k);
+        const int s0 = (int)gs[b], e0 = (int)gh[b];
+        int rk = s0;
+        for (int f = s0; f < e0; ++f) {
+          const uint64_t kf = kw[f];
+          rk += (kf < k || (kf == k && iw[f] < id)) ? 1 : 0;
+        }
+        sel[rk] = id;
+        if (sel_score) sel_score[rk] = key_value(k);
+      }
+    }
+    return true;
+  };
   uint64_t kthr = ~0ull;         // take keys < kthr, and keys == kthr with id <= ithr
   uint64_t ithr = 0;
   bool all_eq = true;
@@ -886,6 +981,8 @@ __global__ __launch_bounds__(1024) void k_select(int n_host, const int *n_dev, i
       if (sel_score) sel_score[i] = key_value(skey[i]);
     }
   } else {
+    __syncthreads();                             // every survivor in kw/iw
+    if (Me <= kSelRegKeys * 1024 && order_global(Me)) return;
     for (int i = Me + tid; i < p2; i += blockDim.x) { kw[i] = ~0ull; iw[i] = INT_MAX; }
     __syncthreads();
     bitonic_sort(kw, iw, p2);
