@@ -432,7 +432,8 @@ def kings16_leg(spg, torch, stream):
     clusters with dense 256 x 256 pair tables), beta = 4, chi = 64, beam 10000.
     The FP64 boundary MPS (MPO contractions as matrix-core GEMMs at this d),
     its validity (log Z, the sign of every row function's sum), then the FP64
-    and FP32-input searches on it: search-only times, states, best energies."""
+    and FP32-input searches on it: search-only times, states, best energies; and
+    the contraction with FP32 products in its GEMMs, with the FP64 search on it."""
     import numpy as np
     from workloads import config_instance
     inst = config_instance("kings16x16_d256", 0)
@@ -484,6 +485,26 @@ def kings16_leg(spg, torch, stream):
         del e
     del env
     out["search_speedup_fp32_vs_fp64"] = out["search_ms_fp64"] / out["search_ms_fp32"]
+    # the precision form of the contraction: every GEMM with FP32 products and
+    # accumulation on the matrix cores (QR and SVD FP64), then the FP64 search on it
+    spg.set_gemm_precision(True)
+    try:
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        env32, lz32 = spg.boundary_mps(peps, chi, stream=stream, nonfinite_ok=True)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - a
+    finally:
+        spg.set_gemm_precision(False)
+    T32, _ = spg.env_export(env32)
+    sums32 = row_sums(spg.unpack_mps(T32, spg.env_info(env32).bond_dims))
+    n = spg.branch_and_bound(env32, M, st, en, lp, stream=stream)
+    torch.cuda.synchronize()
+    out["boundary_mps_fp32_products"] = {
+        "boundary_mps_s": t32, "speedup_vs_fp64": bmps_s / t32, "logZ": finite_or_none(lz32),
+        "rows_with_nonpositive_sum": [r for r, v in enumerate(sums32) if not v > 0],
+        "n_states_fp64_search": n, "best_energy_fp64_search": float(en[0]) if n > 0 else None}
+    del env32
     return out
 
 
